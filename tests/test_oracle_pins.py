@@ -1,0 +1,453 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: every expected value comes from
+a high-precision evaluation of the plain definitions, a closed form, a
+textbook theorem evaluated by an independent library routine (Hopcroft-Karp,
+HiGHS), or brute force over all subsets.
+"""
+import itertools
+import math
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.optimize import linprog
+from scipy.sparse.csgraph import maximum_bipartite_matching
+
+import graphgen as gg
+
+getcontext().prec = 60
+EPS = 0.1
+
+
+# ------------------------------------------------------------- definitions
+
+def d_smax(y, eta):
+    """smax_eta(y) = (1/eta) ln sum exp(eta y_i), Section 2.2, in 60 digits."""
+    eta = Decimal(repr(eta))
+    return sum((eta * Decimal(repr(float(v)))).exp() for v in y).ln() / eta
+
+
+def d_smin(z, eta):
+    eta = Decimal(repr(eta))
+    return -sum((-eta * Decimal(repr(float(v)))).exp() for v in z).ln() / eta
+
+
+def test_smax_smin_match_definition(oracle_mod):
+    rng = np.random.default_rng(0)
+    for m in (1, 2, 3, 7, 40):
+        for eta in (2.5, 30.0, 800.0):
+            y = rng.uniform(0, 1.5, m)
+            v, w = oracle_mod.smax(y, eta)
+            assert abs(Decimal(repr(float(v))) - d_smax(y, eta)) < Decimal("1e-14")
+            v2, u = oracle_mod.smin(y, eta)
+            assert abs(Decimal(repr(float(v2))) - d_smin(y, eta)) < Decimal("1e-14")
+            # gradients are the softmax / softmin probability vectors
+            ed = [(Decimal(repr(eta)) * Decimal(repr(float(t)))).exp() for t in y]
+            s = sum(ed)
+            for i in range(m):
+                assert abs(Decimal(repr(float(w[i]))) - ed[i] / s) < Decimal("1e-14")
+            assert abs(u.sum() - 1.0) < 1e-13 and np.all(u >= 0)
+            # smooth max/min are within ln(m)/eta of max/min (Section 2.2, eta choice)
+            assert y.max() - 1e-12 <= v <= y.max() + math.log(m) / eta + 1e-12
+            assert y.min() - math.log(m) / eta - 1e-12 <= v2 <= y.min() + 1e-12
+
+
+def test_single_entry_is_exact(oracle_mod):
+    # smax and smin of one entry are the entry (end of Section 2.2)
+    for val in (0.0, 0.37, 5.0):
+        assert oracle_mod.smax([val], 900.0)[0] == pytest.approx(val, abs=1e-15)
+        assert oracle_mod.smin([val], 900.0)[0] == pytest.approx(val, abs=1e-15)
+
+
+def _phi_psi_decimal(y, dy, z, dz, eta, alpha):
+    yp = [float(a) + alpha * float(b) for a, b in zip(y, dy)]
+    zp = [float(a) + alpha * float(b) for a, b in zip(z, dz)]
+    psi = d_smax(yp, eta) - d_smax(y, eta)
+    phi = d_smin(zp, eta) - d_smin(z, eta)
+    return float(psi), float(phi)
+
+
+@pytest.mark.parametrize("alpha", [1e-3, 0.5, 1.0, 7.0, 300.0, 5e4])
+def test_phi_psi_forms_match_definition(oracle_mod, alpha):
+    """Section 4.1: Psi, Phi are differences of smax/smin; the oracle's
+    cancellation-free evaluation must agree with a 60-digit evaluation of the
+    plain differences, over alpha ranges hitting every branch."""
+    rng = np.random.default_rng(int(alpha * 1000) % 997)
+    eta = 200.0
+    m = 9
+    y = rng.uniform(0.2, 0.9, m)
+    dy = rng.uniform(0, 2e-3, m)
+    z = rng.uniform(0.1, 0.8, m)
+    dz = rng.uniform(0, 4e-3, m)
+    LP, w = oracle_mod.smax(y, eta)
+    LC, u = oracle_mod.smin(z, eta)
+    psi = oracle_mod.psi(y, dy, w, eta, LP, alpha)
+    phi, zmn = oracle_mod.phi(z, dz, u, eta, LC, alpha)
+    e_psi, e_phi = _phi_psi_decimal(y, dy, z, dz, eta, alpha)
+    assert psi == pytest.approx(e_psi, rel=1e-10, abs=1e-300)
+    assert phi == pytest.approx(e_phi, rel=1e-10, abs=1e-300)
+    assert zmn == pytest.approx(float(np.min(z + alpha * dz)), rel=1e-15)
+
+
+def test_bang_for_buck_is_monotone(oracle_mod):
+    """Proposition 1 (Section 4.1): f = Phi/Psi decreases in alpha."""
+    rng = np.random.default_rng(7)
+    eta = 150.0
+    for trial in range(5):
+        y = rng.uniform(0, 1, 12)
+        dy = rng.uniform(0, 1e-2, 12)
+        z = rng.uniform(0, 1, 15)
+        dz = rng.uniform(0, 1e-2, 15)
+        LP, w = oracle_mod.smax(y, eta)
+        LC, u = oracle_mod.smin(z, eta)
+        alphas = np.geomspace(1e-3, 1e3, 60)
+        f = [oracle_mod.phi(z, dz, u, eta, LC, a)[0] / oracle_mod.psi(y, dy, w, eta, LP, a)
+             for a in alphas]
+        assert np.all(np.diff(f) <= 1e-9 * np.abs(f[:-1]))
+
+
+def _scan(oracle_mod, y, dy, z, dz, eta):
+    LP, w = oracle_mod.smax(y, eta)
+    LC, u = oracle_mod.smin(z, eta)
+    T = lambda a: oracle_mod.phi(z, dz, u, eta, LC, a)[0] >= oracle_mod.psi(y, dy, w, eta, LP, a)
+    return LP, w, LC, u, T
+
+
+def test_algorithm3_brackets_the_largest_step(oracle_mod):
+    """Algorithm 3 returns lb with T(lb) true and T(ub) false, ub-lb <= eps*lb,
+    so by monotonicity the largest admissible step lies in [lb, (1+eps) lb]."""
+    rng = np.random.default_rng(11)
+    eta = 300.0
+    hits = 0
+    for trial in range(12):
+        y = rng.uniform(0, 0.5, 20)
+        dy = rng.uniform(0, 1e-3, 20)
+        z = rng.uniform(0, 0.3, 25)
+        dz = rng.uniform(1e-4, 2e-3, 25) * rng.uniform(0.5, 4)
+        LP, w, LC, u, T = _scan(oracle_mod, y, dy, z, dz, eta)
+        a, ev = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS)
+        if not T(1.0):
+            assert a < 1.0
+            continue
+        assert a >= 1.0 and T(a)
+        if np.min(z + a * dz) >= 1.0:
+            continue  # early return
+        hits += 1
+        assert not T(a * (1 + EPS) * 1.0000001) or not T(2 * a)
+        # fine scan: the true crossing is within [a, (1+eps) a]
+        grid = a * np.linspace(1.0, 2.0, 401)
+        ok = np.array([T(b) for b in grid])
+        cross = grid[np.argmin(ok)] if not ok.all() else 2 * a
+        assert a <= cross <= a * (1 + EPS) * (1 + 1e-9)
+    assert hits > 3
+
+
+def test_algorithm3_early_return(oracle_mod):
+    """If T(alpha) holds and min(z + alpha dz) >= 1 the search returns alpha
+    immediately (Algorithm 3, early return)."""
+    eta = 50.0
+    y = np.array([0.1, 0.2])
+    dy = np.array([1e-6, 1e-6])
+    z = np.array([0.9, 0.95])
+    dz = np.array([0.06, 0.06])
+    LP, w = oracle_mod.smax(y, eta)
+    LC, u = oracle_mod.smin(z, eta)
+    a, ev = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS)
+    # alpha = 1 already makes z >= 0.96 < 1; alpha = 2 gives >= 1.02
+    assert a == 2.0 and ev == 2
+
+
+# --------------------------------------------------------- whole iterations
+
+def _bmatch_problem(g):
+    import oracle
+    P = oracle.incidence(g)
+    return P
+
+
+def test_iteration_invariants(oracle_mod):
+    """Algorithm 1/2 facts: P x0 <= eps; d >= 0 with d_i <= s x_i/eta; every
+    accepted step keeps T; the potential smax(Px) - smin(Cx) never grows."""
+    g = gg.bipartite_uniform(40, 40, 200, seed=3)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    ones = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    M = 30.0
+    x0 = np.zeros(n)
+    import ctypes
+    oracle_mod.lib().orc_initial_point(P.c, 1.0, EPS, x0.ctypes.data)
+    assert (P.dense() @ x0).max() <= EPS * (1 + 1e-12)
+    x = x0.copy()
+    eta = oracle_mod.eta(P.rows + 1, EPS)
+    pot_prev = None
+    for it in range(25):
+        t = oracle_mod.iteration_terms(P, 1.0, ones, 1.0 / M, EPS, x, alphas=[1.0])
+        assert np.all(t["d"] >= 0)
+        assert np.all(t["d"] <= (1.0 / eta) * x * (1 + 1e-12))   # s = 1: one covering row
+        pot = t["LP"] - t["LC"]
+        if pot_prev is not None:
+            assert pot <= pot_prev + 1e-12
+        pot_prev = pot
+        if t["z"].min() >= 1:
+            break
+        a, _ = oracle_mod.step_search(t["y"], t["dy"], t["w"], t["LP"], t["z"], t["dz"], t["u"],
+                                      t["LC"], eta, EPS)
+        assert a >= 1.0
+        tt = oracle_mod.iteration_terms(P, 1.0, ones, 1.0 / M, EPS, x, alphas=[a])
+        assert tt["phi"][0] >= tt["psi"][0]
+        x = x + a * t["d"]
+
+
+def test_probe_trajectory_matches_forced_replay(oracle_mod):
+    """Decision replay: forcing the probe to its own step sequence reproduces
+    its iterate bit for bit (the replay hook used against the GPU)."""
+    g = gg.bipartite_uniform(50, 60, 300, seed=4)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    ones = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    r1 = oracle_mod.probe(P, 1.0, ones, 1.0 / 40.0)
+    r2 = oracle_mod.probe(P, 1.0, ones, 1.0 / 40.0, forced_alpha=r1.alphas)
+    assert r1.status == r2.status and r1.iterations == r2.iterations
+    assert np.array_equal(r1.x, r2.x)
+
+
+# ------------------------------------------------------------ graph LP pins
+
+def hopcroft_karp(g):
+    B = sp.csr_matrix((np.ones(g.num_edges), (g.u, g.v - g.n_left)),
+                      shape=(g.n_left, g.num_vertices - g.n_left))
+    return int((maximum_bipartite_matching(B, perm_type="column") >= 0).sum())
+
+
+def _check_packing(g, r, opt):
+    import oracle
+    M = oracle.incidence(g).dense()
+    assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+    assert (M @ r.x).max() <= 1 + 1e-9 and r.x.min() >= 0
+    assert r.x.sum() == pytest.approx(r.objective, rel=1e-9)
+    assert opt / r.objective <= 1 + EPS + 1e-9
+
+
+@pytest.mark.parametrize("seed,nl,nr,ne", [(1, 30, 30, 90), (2, 50, 40, 160), (3, 80, 80, 400),
+                                            (4, 200, 150, 900)])
+def test_bmatch_equals_maximum_matching(oracle_mod, seed, nl, nr, ne):
+    """No integrality gap for bipartite matching (Section 3): LP optimum =
+    maximum matching size, computed by Hopcroft-Karp."""
+    g = gg.bipartite_uniform(nl, nr, ne, seed=seed)
+    r = oracle_mod.solve_bmatch(g)
+    assert r.certified
+    _check_packing(g, r, hopcroft_karp(g))
+
+
+@pytest.mark.parametrize("a,b", [(3, 3), (4, 7), (9, 2)])
+def test_bmatch_complete_bipartite(oracle_mod, a, b):
+    g = gg.complete_bipartite(a, b)
+    r = oracle_mod.solve_bmatch(g)
+    _check_packing(g, r, min(a, b))
+
+
+def test_bmatch_config_size(oracle_mod):
+    """The 2000+2000 vertex, 20000 edge bipartite matching workload: within
+    (1+eps) of the Hopcroft-Karp optimum."""
+    g = gg.bipartite_uniform(2000, 2000, 20000, seed=1)
+    r = oracle_mod.solve_bmatch(g)
+    assert r.certified
+    _check_packing(g, r, hopcroft_karp(g))
+
+
+def _check_covering(C_dense, r, opt):
+    assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+    assert (C_dense @ r.x).min() >= 1 - 1e-9 and r.x.min() >= 0
+    assert r.x.sum() == pytest.approx(r.objective, rel=1e-9)
+    assert r.objective / opt <= 1 + EPS + 1e-9
+
+
+def _double_cover_matching(g):
+    """nu(G x K2): maximum matching of the bipartite double cover."""
+    n = g.num_vertices
+    r = np.concatenate([g.u, g.v])
+    c = np.concatenate([g.v, g.u])
+    B = sp.csr_matrix((np.ones(r.shape[0]), (r, c)), shape=(n, n))
+    return int((maximum_bipartite_matching(B, perm_type="column") >= 0).sum())
+
+
+@pytest.mark.parametrize("seed,n,m", [(1, 30, 60), (2, 60, 200), (3, 120, 300)])
+def test_vcover_lp_equals_half_double_cover_matching(oracle_mod, seed, n, m):
+    """Vertex cover LP optimum = fractional matching number = nu(G x K2)/2
+    (LP duality plus half-integrality); cross-checked with HiGHS."""
+    g = gg.gnm_random(n, m, seed=seed)
+    r = oracle_mod.solve_vcover(g)
+    opt = _double_cover_matching(g) / 2.0
+    C, keep = oracle_mod.vertex_cover_matrix(g)
+    A = C.dense()
+    lp = linprog(np.ones(A.shape[1]), A_ub=-A, b_ub=-np.ones(A.shape[0]), bounds=(0, None))
+    assert lp.fun == pytest.approx(opt, abs=1e-7)
+    full = oracle_mod.incidence(g, drop_isolated=False).dense().T
+    _check_covering(full, r, opt)
+
+
+def test_vcover_bipartite_koenig(oracle_mod):
+    """Koenig: on bipartite graphs the vertex cover LP equals the maximum matching."""
+    g = gg.bipartite_uniform(60, 50, 250, seed=9)
+    r = oracle_mod.solve_vcover(g)
+    full = oracle_mod.incidence(g, drop_isolated=False).dense().T
+    _check_covering(full, r, hopcroft_karp(g))
+
+
+@pytest.mark.parametrize("make,opt", [
+    (lambda: gg.regular_circulant(30, 4), 30 / 5),
+    (lambda: gg.regular_circulant(24, 6), 24 / 7),
+    (lambda: gg.complete_graph(9), 1.0),
+    (lambda: gg.star_graph(12), 1.0),
+    (lambda: gg.cycle_graph(21), 7.0),
+])
+def test_domset_closed_forms(oracle_mod, make, opt):
+    """Dominating set LP: k-regular -> n/(k+1); K_n and stars -> 1; cycles -> n/3."""
+    g = make()
+    r = oracle_mod.solve_domset(g)
+    _check_covering(oracle_mod.dominating_set_matrix(g).dense(), r, opt)
+
+
+def test_domset_matches_highs(oracle_mod):
+    g = gg.chung_lu(300, 2.3, 6.0, seed=4)
+    D = oracle_mod.dominating_set_matrix(g).dense()
+    lp = linprog(np.ones(D.shape[1]), A_ub=-D, b_ub=-np.ones(D.shape[0]), bounds=(0, None))
+    r = oracle_mod.solve_domset(g)
+    _check_covering(D, r, lp.fun)
+
+
+def brute_force_density(g):
+    best = 0.0
+    n = g.num_vertices
+    for mask in range(1, 1 << n):
+        inS = np.array([(mask >> i) & 1 for i in range(n)], dtype=bool)
+        e = int(np.sum(inS[g.u] & inS[g.v]))
+        best = max(best, e / inS.sum())
+    return best
+
+
+def _check_densest(oracle_mod, g, r, opt):
+    assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+    O, W, keep = oracle_mod.densest_matrices(g)
+    z = r.x
+    assert (W.dense() @ z).min() >= 1 - 1e-9 and z.min() >= 0
+    assert (O.dense() @ z).max() == pytest.approx(r.objective, rel=1e-9)
+    assert r.objective / opt <= 1 + EPS + 1e-9
+
+
+@pytest.mark.parametrize("seed,n,m", [(5, 14, 30), (6, 12, 40), (7, 16, 25)])
+def test_densest_brute_force(oracle_mod, seed, n, m):
+    """Densest subgraph LP = max over subsets of |E(S)|/|S| (Charikar)."""
+    g = gg.gnm_random(n, m, seed=seed)
+    r = oracle_mod.solve_densest(g)
+    _check_densest(oracle_mod, g, r, brute_force_density(g))
+
+
+@pytest.mark.parametrize("make,opt", [
+    (lambda: gg.complete_graph(8), 3.5),
+    (lambda: gg.cycle_graph(15), 1.0),
+    (lambda: gg.path_graph(10), 0.9),
+    (lambda: gg.random_tree(25, seed=3), 24 / 25),
+])
+def test_densest_closed_forms(oracle_mod, make, opt):
+    """K_n -> (n-1)/2; cycles -> 1; trees (and paths) -> (n-1)/n."""
+    g = make()
+    r = oracle_mod.solve_densest(g)
+    _check_densest(oracle_mod, g, r, opt)
+
+
+def test_level_set_density_brute_force(oracle_mod):
+    """The level-set rounding returns the best prefix density, which is the
+    true maximum when scored by the indicator of a densest set."""
+    g = gg.gnm_random(12, 30, seed=21)
+    best = brute_force_density(g)
+    n = g.num_vertices
+    found = None
+    for mask in range(1, 1 << n):
+        inS = np.array([(mask >> i) & 1 for i in range(n)], dtype=bool)
+        if np.sum(inS[g.u] & inS[g.v]) / inS.sum() == best:
+            found = inS
+            break
+    v = oracle_mod.level_set_density(n, g.u, g.v, found.astype(float))
+    assert v == pytest.approx(best, rel=1e-12)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        s = rng.random(n)
+        order = np.argsort(-s, kind="stable")
+        want = 0.0
+        for k in range(1, n + 1):
+            S = np.zeros(n, bool)
+            S[order[:k]] = True
+            want = max(want, np.sum(S[g.u] & S[g.v]) / k)
+        assert oracle_mod.level_set_density(n, g.u, g.v, s) == pytest.approx(want, rel=1e-12)
+
+
+def test_weak_duality_bounds(oracle_mod):
+    """Every iteration's 1/min(P^T w) bounds the packing optimum from above and
+    1/max(C^T u) bounds the covering optimum from below."""
+    g = gg.bipartite_uniform(40, 40, 150, seed=12)
+    opt = hopcroft_karp(g)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    ones = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    for M in (0.6 * opt, 0.95 * opt, 1.3 * opt):
+        pr = oracle_mod.probe(P, 1.0, ones, 1.0 / M)
+        assert pr.pack_bound >= opt * (1 - 1e-12)
+    C, keep = oracle_mod.vertex_cover_matrix(g)
+    onesC = oracle_mod.CSR(1, C.cols, np.array([0, C.cols]), np.arange(C.cols), np.ones(C.cols))
+    for M in (0.6 * opt, 1.3 * opt):
+        pr = oracle_mod.probe(onesC, 1.0 / M, C, 1.0)
+        assert pr.cover_bound <= opt * (1 + 1e-12)
+
+
+def test_infeasible_probe_reports_infeasible(oracle_mod):
+    """A probe with M well above the optimum cannot be feasible; the theorem of
+    Section 4.1 says MWU then reports INFEASIBLE (and never FEASIBLE)."""
+    g = gg.bipartite_uniform(40, 40, 150, seed=12)
+    opt = hopcroft_karp(g)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    ones = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    pr = oracle_mod.probe(P, 1.0, ones, 1.0 / (1.5 * opt))
+    assert pr.status == oracle_mod.INFEASIBLE
+    pr = oracle_mod.probe(P, 1.0, ones, 1.0 / (0.7 * opt))
+    assert pr.status == oracle_mod.FEASIBLE
+    # (1+eps)-relative point (Theorem, Section 4.1).  The early return of
+    # Algorithm 3 may overshoot the covering side, so the statement is checked
+    # on x / min(Cx), which keeps Cx >= 1: max(Px) / min(Cx) <= 1 + eps.
+    Px = P.dense() @ pr.x
+    z = pr.x.sum() / (0.7 * opt)
+    assert z >= 1.0 and Px.max() / z <= 1 + EPS + 1e-12
+
+
+def test_step_rule_effect(oracle_mod):
+    """Table 2: the standard step needs orders of magnitude more iterations than
+    the searched step on the same probe."""
+    g = gg.bipartite_uniform(60, 60, 300, seed=2)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    ones = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    M = 0.8 * hopcroft_karp(g)
+    bin_ = oracle_mod.probe(P, 1.0, ones, 1.0 / M, step_rule=oracle_mod.STEP_BIN)
+    std = oracle_mod.probe(P, 1.0, ones, 1.0 / M, step_rule=oracle_mod.STEP_STD, max_iter=200000)
+    assert bin_.status == std.status == oracle_mod.FEASIBLE
+    assert std.iterations >= 30 * bin_.iterations
+
+
+def test_general_lp_normalization(oracle_mod):
+    """Weighted packing max c^T x s.t. A x <= b via P = A/(b c^T) (Section 2.1),
+    against HiGHS."""
+    rng = np.random.default_rng(5)
+    A = (rng.random((15, 25)) < 0.3) * rng.uniform(0.5, 3.0, (15, 25))
+    A[0, :] += 0.1  # every column covered
+    b = rng.uniform(1, 4, 15)
+    c = rng.uniform(0.5, 2, 25)
+    lp = linprog(-c, A_ub=A, b_ub=b, bounds=(0, None))
+    P = oracle_mod.normalize_packing(oracle_mod.CSR.from_dense(A), b, c)
+    r = oracle_mod.solve_packing(P)
+    x = r.x / c
+    assert (A @ x <= b * (1 + 1e-9)).all()
+    assert -lp.fun / (c @ x) <= 1 + EPS + 1e-9
+    assert r.lower <= -lp.fun * (1 + 1e-9) <= r.upper * (1 + 1e-9) * (1 + 1e-9)
