@@ -1,0 +1,245 @@
+/*
+ * mwu.h -- C ABI of the MI355X (gfx950) multiplicative-weight-update solver
+ * for positive linear programs.
+ *
+ * Method: Ju, Yesil, Sun, Chekuri, Solomonik, "Efficient Parallel
+ * Implementation of the Multiplicative Weight Update Method for Graph-based
+ * Linear Programs" (arXiv 2307.03307):
+ *   - problem forms: general LP (eq. LPDef, Section 1), normalized mixed
+ *     packing/covering feasibility (eq. NormFeasibleLP, Section 2.2), pure
+ *     packing and pure covering with the objective embedded as one extra row
+ *     and M searched (end of Section 2.2);
+ *   - graph LPs: matching / bipartite matching, dominating set, vertex cover,
+ *     densest subgraph with D searched (Section 3);
+ *   - iteration: Algorithm 2 with the step-size search of Algorithm 3
+ *     (Section 4), or the standard step alpha = 1 (Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an mwu_status: 0 (MWU_OK) or a negative error.
+ *     Solve outcomes (feasible, infeasible, iteration cap) are not errors;
+ *     they are reported in mwu_result_info.status.
+ *   - Host pointers are plain host memory unless stated otherwise.  Inputs are
+ *     deep-copied by mwu_create*; the caller may free them on return.
+ *   - A handle owns all device memory until mwu_destroy.  A handle is not
+ *     thread-safe; distinct handles are independent.
+ *   - All indices are 0-based.  Device-side indices are 32-bit: every count
+ *     (rows, columns, nonzeros, vertices, edges) must be below 2^31 - 1,
+ *     otherwise MWU_ERR_TOO_LARGE.
+ */
+#ifndef MWU_H
+#define MWU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mwu_status;
+
+/* error codes (negative) */
+#define MWU_OK                 0
+#define MWU_ERR_INVALID_ARG   -1  /* NULL where not allowed, eps outside (0,1), size mismatch */
+#define MWU_ERR_NEGATIVE_ENTRY -2 /* a matrix value < 0 */
+#define MWU_ERR_NONFINITE     -3  /* NaN or infinity in values, b or c */
+#define MWU_ERR_BAD_RHS       -4  /* some b_i <= 0 or c_j <= 0 */
+#define MWU_ERR_GRAPH         -5  /* self-loop, duplicate edge or vertex id out of range */
+#define MWU_ERR_TOO_LARGE     -6  /* a count does not fit the 32-bit device indices */
+#define MWU_ERR_OOM           -7  /* device or host allocation failed */
+#define MWU_ERR_DEVICE        -8  /* HIP runtime error, or no gfx950 device */
+#define MWU_ERR_UNBOUNDED     -9  /* packing column with no nonzero: the LP is unbounded */
+#define MWU_ERR_STATE        -10  /* call not valid for this handle (e.g. probe API before a probe) */
+
+/* solve outcome, mwu_result_info.status */
+#define MWU_CERTIFIED            0  /* returned x is feasible and within (1+eps) of OPT */
+#define MWU_FEASIBLE_UNCERTIFIED 1  /* feasible x, bracket not closed (probe cap or iteration cap) */
+#define MWU_INFEASIBLE           2  /* single-probe mode: the feasibility LP is infeasible */
+#define MWU_MAX_ITER             3  /* single-probe mode: iteration cap reached */
+
+/* probe outcome (mwu_probe_info.status) */
+#define MWU_PROBE_RUNNING    0
+#define MWU_PROBE_FEASIBLE   1  /* min(Cx) >= 1 reached (Algorithm 2 stop) */
+#define MWU_PROBE_INFEASIBLE 2  /* max(d) = 0, or the step search found alpha < 1 */
+#define MWU_PROBE_MAX_ITER   3
+
+typedef enum {
+    MWU_PACKING = 0,   /* max c^T x  s.t. A x <= b, x >= 0        (eq. LPDef; pure packing, Sec. 2.2) */
+    MWU_COVERING = 1,  /* min c^T x  s.t. A x >= b, x >= 0        (pure covering, Sec. 2.2)          */
+    MWU_MIXED = 2      /* min lambda s.t. P x <= lambda b_P, C x >= b_C, x >= 0: the densest
+                          subgraph "min D" form (Section 3); with opts.mixed_fixed_lambda > 0 a
+                          single feasibility probe P x <= lambda b_P, C x >= b_C (eq. NormFeasibleLP) */
+} mwu_form;
+
+typedef enum {
+    MWU_MAT_CSR = 0,          /* explicit CSR: row_ptr (int64, rows+1), col_idx (int32, nnz),
+                                 values (double, nnz; NULL = every stored entry is 1)           */
+    MWU_MAT_INCIDENCE = 1,    /* M (num_vertices x num_edges) from an edge list: M[u,e] = 1 iff
+                                 u is an endpoint of e (eq. incidence, Section 3)                */
+    MWU_MAT_INCIDENCE_T = 2,  /* M^T (num_edges x num_vertices): row e reads x_u + x_v (vertex
+                                 cover, Section 3)                                               */
+    MWU_MAT_EDGE_PAIR = 3,    /* O (num_vertices x 2 num_edges): O[u,2e] = 1 for e = (u,.),
+                                 O[v,2e+1] = 1 for e = (.,v) (eq. oddshifted, Section 3)        */
+    MWU_MAT_INTERWEAVE = 4    /* W (num_edges x 2 num_edges): W[e,2e] = W[e,2e+1] = 1
+                                 (eq. interweaved, Section 3)                                    */
+} mwu_matrix_kind;
+
+/* A constraint matrix.  CSR fields are used for MWU_MAT_CSR, edge-list fields
+ * for the implicit graph kinds.  Edge lists: vertices 0..num_vertices-1, no
+ * self-loops, no duplicate undirected edge (MWU_ERR_GRAPH otherwise); any
+ * order and orientation.  Edge e of the caller's list is variable e (and the
+ * pair variables 2e, 2e+1) in the caller's order. */
+typedef struct {
+    mwu_matrix_kind kind;
+    int64_t rows, cols;            /* CSR only */
+    const int64_t *row_ptr;        /* CSR only */
+    const int32_t *col_idx;        /* CSR only */
+    const double *values;          /* CSR only, nullable */
+    int64_t num_vertices, num_edges;
+    const int32_t *edge_u;         /* edge kinds only */
+    const int32_t *edge_v;
+} mwu_matrix;
+
+/* The LP.  PACKING uses P only, COVERING uses C only, MIXED uses both.
+ * b_P (rows of P), b_C (rows of C) and c (columns) are nullable (all ones).
+ * Implicit graph kinds are pattern-only 0/1 matrices; passing b or c with
+ * them is allowed and materializes the scaled matrix as CSR. */
+typedef struct {
+    mwu_form form;
+    mwu_matrix P, C;
+    const double *b_P;
+    const double *b_C;
+    const double *c;
+} mwu_problem;
+
+#define MWU_STEP_STD 0   /* alpha = 1 (Algorithm 1) */
+#define MWU_STEP_BIN 1   /* exponential + binary search (Algorithm 3) */
+
+#define MWU_FP64 0               /* plain: every vector and sum in double */
+#define MWU_MIXED_FP32_FP64 1    /* vectors and per-element terms in float; LSE totals, search sums,
+                                    step decisions and certificates in double */
+
+#define MWU_FLAG_NO_FACTOR2   1u  /* do not double the step when one side is a single row */
+#define MWU_FLAG_GENERIC      2u  /* force the generic CSR engine (no fused graph program) */
+
+typedef struct {
+    double eps;                 /* accuracy, default 0.1 (Section 6.2) */
+    int32_t max_iter;           /* iterations per probe, default 5000 (Section 6.2) */
+    int32_t max_probes;         /* outer search cap, default 64 */
+    int32_t step_rule;          /* MWU_STEP_BIN (default) or MWU_STEP_STD */
+    int32_t precision;          /* MWU_MIXED_FP32_FP64 (default) or MWU_FP64 */
+    int32_t iters_per_launch;   /* iterations captured per graph launch; 0 = default (8) */
+    int32_t device;             /* HIP device ordinal, default 0 */
+    void *hip_stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
+    double mixed_fixed_lambda;  /* MWU_MIXED: > 0 runs one feasibility probe at this lambda */
+    uint64_t flags;
+} mwu_options;
+
+typedef struct {
+    int32_t status;             /* MWU_CERTIFIED ... MWU_MAX_ITER */
+    double objective;           /* c^T x of the returned x (MIXED: lambda of the returned x) */
+    double lower_bound;         /* final bracket on OPT */
+    double upper_bound;
+    int64_t total_iterations;   /* MWU iterations over all probes */
+    int64_t final_probe_iterations;
+    int64_t search_passes;      /* K-candidate step-search passes over the rows */
+    int64_t probes;
+    double max_violation;       /* max{0, max(Px)-1, 1-min(Cx)} of the last probe's x (Sec. 6.3) */
+    double seconds_solve;       /* wall time of mwu_solve */
+} mwu_result_info;
+
+/* Fill *opt with the defaults listed above. */
+void mwu_default_options(mwu_options *opt);
+
+/* Validate, normalize (P_ij = A_ij / (b_i c_j), Section 2.1), drop empty rows
+ * and (covering) empty columns, canonicalize edge lists, upload to the device
+ * and build the transpose plans.  opt is nullable (defaults).  On success
+ * *out receives a handle; on error *out is set to NULL. */
+mwu_status mwu_create(const mwu_problem *prob, const mwu_options *opt, void **out);
+
+/* Many independent problems solved together (every problem must be a
+ * MWU_PACKING problem with P of kind MWU_MAT_INCIDENCE, e.g. bipartite
+ * matchings).  Variables and results are concatenated in problem order. */
+mwu_status mwu_create_batch(const mwu_problem *probs, int32_t count, const mwu_options *opt,
+                            void **out);
+
+/* Run the outer search (or the single fixed-lambda probe).
+ * x_out: nullable, host, length = number of variables of the problem (batch:
+ * the concatenation); receives x in the caller's variable order and scale.
+ * objective_out, iterations_out: nullable, host (batch: length count).
+ * info: nullable (batch: length count). */
+mwu_status mwu_solve(void *s, double *x_out, double *objective_out, int64_t *iterations_out,
+                     mwu_result_info *info);
+
+/* Release every resource of the handle.  NULL is accepted. */
+void mwu_destroy(void *s);
+
+/* Static text for a status or error code. */
+const char *mwu_status_string(mwu_status st);
+
+/* Number of variables (columns) the handle exposes to the caller. */
+int64_t mwu_num_variables(void *s);
+
+/* ---------------------------------------------------------------------------
+ * Probe-level access, used for per-pass comparisons and by the autograd
+ * potential.  "param" is M for pure problems (the embedded objective row is
+ * (1/M) 1^T), D (lambda) for MWU_MIXED.  Vectors are in the internal
+ * (normalized, compacted) variable space of length mwu_probe_sizes().n.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t n;        /* internal variables */
+    int64_t m_P;      /* internal packing rows (1 for the embedded objective row) */
+    int64_t m_C;      /* internal covering rows */
+    double eta;       /* 10 ln(m_P + m_C) / eps (Algorithm 1) */
+} mwu_sizes;
+
+typedef struct {
+    int32_t status;            /* MWU_PROBE_* */
+    int64_t iterations;
+    int64_t search_passes;
+    double alpha;              /* last accepted step */
+    double L_P, L_C;           /* smax(Px), smin(Cx) (Section 2.2) */
+    double pack_bound, cover_bound;   /* weak-duality bounds seen so far */
+} mwu_probe_info;
+
+mwu_status mwu_probe_sizes(void *s, mwu_sizes *out);
+
+/* Start a probe at the given param.  x0 (host, nullable, length n): starting
+ * point; NULL = the Algorithm 1 initial point eps / (n max_j P_ji). */
+mwu_status mwu_probe_begin(void *s, double param, const double *x0);
+
+/* Run up to max_iters iterations of Algorithm 2 (stops early on any outcome).
+ * forced_alpha (host, nullable, n_forced entries): use these steps instead
+ * of the search for the next n_forced iterations (decision replay). */
+mwu_status mwu_probe_run(void *s, int32_t max_iters, const double *forced_alpha, int32_t n_forced,
+                         mwu_probe_info *info);
+
+/* Compute g, h, d, P d, C d at the current x without stepping. */
+mwu_status mwu_probe_direction(void *s);
+
+/* Copy an internal vector to the host (double).  which: 0 x, 1 d, 2 g, 3 h,
+ * 4 y = Px (m_P), 5 z = Cx (m_C), 6 dy = Pd (m_P), 7 dz = Cd (m_C).  len must
+ * equal the vector's length. */
+mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
+
+/* Evaluate Psi(alpha_k), Phi(alpha_k) (Section 4.1) and min(Cx + alpha_k Cd)
+ * at the current x and direction, for k < count (count <= 16).  Outputs are
+ * host arrays of length count; zmin_new is nullable. */
+mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, double *psi,
+                                double *phi, double *zmin_new);
+
+/* ---------------------------------------------------------------------------
+ * Smoothed potential for automatic differentiation: Phi(x) = smax_eta(P x) -
+ * smin_eta(C x) at the handle's current param (Section 4.1) and its gradient
+ * P^T grad smax(Px) - C^T grad smin(Cx) (the g - h of Algorithm 2).
+ * x_dev, grad_dev: DEVICE pointers to double arrays of length n in the
+ * internal variable space; stream: hipStream_t or NULL (handle stream).
+ * ------------------------------------------------------------------------- */
+mwu_status mwu_potential_forward(void *s, const double *x_dev, double *value_out, void *stream);
+mwu_status mwu_potential_backward(void *s, const double *x_dev, double grad_scale, double *grad_dev,
+                                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MWU_H */

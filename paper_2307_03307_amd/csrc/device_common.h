@@ -1,0 +1,495 @@
+// Device building blocks shared by the gfx950 programs: deterministic
+// block/grid reductions, nnz-balanced segment tiles, and the step-search
+// replay that runs on the device after each search pass.
+#pragma once
+
+#include "engine.h"
+
+namespace mwu {
+
+#define MWU_DEV __device__ __forceinline__
+
+// ------------------------------------------------------------------ math
+
+MWU_DEV float expm1_t(float v) { return expm1f(v); }
+MWU_DEV double expm1_t(double v) { return expm1(v); }
+MWU_DEV float exp_t(float v) { return expf(v); }
+MWU_DEV double exp_t(double v) { return exp(v); }
+
+// ------------------------------------------------------------ reductions
+// A reduction record holds ns sums, then nmn minima, then nmx maxima.
+
+struct Red {
+    int ns, nmn, nmx;
+    MWU_DEV int q() const { return ns + nmn + nmx; }
+};
+
+MWU_DEV double red_op(double a, double b, int q, Red r)
+{
+    if (q < r.ns) return a + b;
+    if (q < r.ns + r.nmn) return fmin(a, b);
+    return fmax(a, b);
+}
+
+MWU_DEV double red_id(int q, Red r)
+{
+    if (q < r.ns) return 0.0;
+    if (q < r.ns + r.nmn) return INFINITY;
+    return -INFINITY;
+}
+
+// Combine per-thread values v[0..Q) over the block into out[0..Q) (LDS).
+// Butterfly inside each wave64, then the four wave results in a fixed order:
+// the result does not depend on timing.
+template <int Q>
+MWU_DEV void block_combine(const double (&v)[Q], Red r, int qoff, double *s_wave, double *out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double a = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a = red_op(a, __shfl_xor(a, o), q + qoff, r);
+        if (lane == 0) s_wave[wv * Q + q] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < Q) {
+        const int q = threadIdx.x;
+        double a = s_wave[q];
+        for (int w = 1; w < BLOCK / 64; ++w) a = red_op(a, s_wave[w * Q + q], q + qoff, r);
+        out[q] = a;
+    }
+    __syncthreads();
+}
+
+MWU_DEV void st_agent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+MWU_DEV double ld_agent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int RGROUP = 32;   // blocks per first-level reduction group
+
+// Grid-wide reduction of the block records s_rec[0..Q) (LDS).  Every block
+// publishes its record; the last block of each group of RGROUP folds the
+// group in block order; the last group folds the groups in order.  Returns
+// true in exactly one block, with the grid result in s_rec.  Counters are
+// reset by their last user, so the kernel can be replayed (graphs) without
+// any clearing.  tick: 1 + ceil(gridDim/RGROUP) counters.
+MWU_DEV bool grid_reduce(double *s_rec, Red r, double *partials, double *gpart, unsigned *tick)
+{
+    __shared__ int s_last;
+    const int Q = r.q();
+    const int G = gridDim.x, b = blockIdx.x;
+    const int grp = b / RGROUP, ng = (G + RGROUP - 1) / RGROUP;
+    const int gsz = min(RGROUP, G - grp * RGROUP);
+    if (threadIdx.x < Q) st_agent(&partials[(size_t)b * QMAX + threadIdx.x], s_rec[threadIdx.x]);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(&tick[1 + grp], 1u);
+        s_last = (t == (unsigned)(gsz - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    if (threadIdx.x < Q) {
+        const int q = threadIdx.x;
+        double a = red_id(q, r);
+        for (int i = 0; i < gsz; ++i)
+            a = red_op(a, ld_agent(&partials[(size_t)(grp * RGROUP + i) * QMAX + q]), q, r);
+        st_agent(&gpart[(size_t)grp * QMAX + q], a);
+    }
+    if (threadIdx.x == 0) atomicExch(&tick[1 + grp], 0u);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(&tick[0], 1u);
+        s_last = (t == (unsigned)(ng - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    if (threadIdx.x < Q) {
+        const int q = threadIdx.x;
+        double a = red_id(q, r);
+        for (int i = 0; i < ng; ++i) a = red_op(a, ld_agent(&gpart[(size_t)i * QMAX + q]), q, r);
+        s_rec[q] = a;
+    }
+    if (threadIdx.x == 0) atomicExch(&tick[0], 0u);
+    __syncthreads();
+    return true;
+}
+
+// ------------------------------------------------------------ accumulators
+
+template <class T>
+struct Pair {
+    T g, h;
+    MWU_DEV Pair &operator+=(const Pair &o) { g += o.g; h += o.h; return *this; }
+};
+
+template <class T> MWU_DEV T acc_zero() { return T{}; }
+
+// Loads and stores of partial sums published by other workgroups (possibly on
+// another XCD): agent-scope atomics, so no stale cache line is read.
+MWU_DEV void st_acc(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MWU_DEV void st_acc(double *p, double v) { st_agent(p, v); }
+template <class T> MWU_DEV void st_acc(Pair<T> *p, Pair<T> v) { st_acc(&p->g, v.g); st_acc(&p->h, v.h); }
+MWU_DEV float ld_acc(const float *p) { return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MWU_DEV double ld_acc(const double *p) { return ld_agent(p); }
+template <class T> MWU_DEV Pair<T> ld_acc(const Pair<T> *p) { Pair<T> v; v.g = ld_acc(&p->g); v.h = ld_acc(&p->h); return v; }
+
+// ------------------------------------------------------------ segment tiles
+
+MWU_DEV int pad_idx(int k) { return k + (k >> 3); }   // one spare slot per 8: no LDS bank conflicts
+constexpr int TILE_LDS = TILE_NZ + TILE_NZ / 8 + 8;
+
+// Sum the nonzeros of every segment of a multi-segment tile and call
+// epi(segment, sum) once per segment (empty segments get a zero sum).
+// elem(k) returns the term of global nonzero k.  Nonzeros are staged through
+// LDS with coalesced loads; each thread then walks ITEMS consecutive terms and
+// segments crossing thread boundaries are completed by their owner (the
+// thread holding their last term) in a fixed order.
+template <class Acc, class ElemF, class EpiF>
+MWU_DEV void seg_tile(const Tile &tl, const int32_t *__restrict__ ptr, ElemF &elem, EpiF &epi,
+                      Acc *s_acc, int32_t *s_ptr, int32_t *s_tseg, Acc *s_tacc)
+{
+    const int tid = threadIdx.x;
+    const int S = tl.s1 - tl.s0;
+    const int base = tl.k0;
+    const int N = tl.k1 - tl.k0;
+    for (int i = tid; i <= S; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int k = j * BLOCK + tid;
+        if (k < N) s_acc[pad_idx(k)] = elem(base + k);
+    }
+    __syncthreads();
+    const int a = tid * ITEMS;
+    const int b = min(a + ITEMS, N);
+    int pend = -1, tseg = -1;
+    Acc pacc = acc_zero<Acc>(), tacc = acc_zero<Acc>();
+    if (a < N) {
+        int lo = 0, hi = S;   // s_ptr[lo] <= a < s_ptr[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_ptr[mid] <= a) lo = mid; else hi = mid;
+        }
+        int s = lo;
+        bool started = (s_ptr[s] == a);
+        int end = s_ptr[s + 1];
+        Acc acc = acc_zero<Acc>();
+        for (int k = a; k < b; ++k) {
+            while (k >= end) {
+                if (s_ptr[s] < end) {
+                    if (started) epi(tl.s0 + s, acc);
+                    else { pend = s; pacc = acc; }
+                }
+                ++s;
+                started = true;
+                acc = acc_zero<Acc>();
+                end = s_ptr[s + 1];
+            }
+            acc += s_acc[pad_idx(k)];
+        }
+        if (end <= b) {
+            if (started) epi(tl.s0 + s, acc);
+            else { pend = s; pacc = acc; }
+        } else {
+            tseg = s;
+            tacc = acc;
+        }
+    }
+    s_tseg[tid] = tseg;
+    s_tacc[tid] = tacc;
+    __syncthreads();
+    if (pend >= 0) {
+        Acc tot = pacc;
+        for (int t = tid - 1; t >= 0 && s_tseg[t] == pend; --t) tot += s_tacc[t];
+        epi(tl.s0 + pend, tot);
+    }
+    for (int s = tid; s < S; s += BLOCK)
+        if (s_ptr[s] == s_ptr[s + 1]) epi(tl.s0 + s, acc_zero<Acc>());
+    __syncthreads();
+}
+
+// Chunk tile of a long segment: reduce the chunk, publish it, and let the
+// last chunk of the segment (ticket) fold all chunks in order and call epi
+// from thread 0.
+template <class Acc, class ElemF, class EpiF>
+MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, EpiF &epi, Acc *s_tacc, Acc *lpart,
+                        const int32_t *lfirst, const int32_t *lcount, unsigned *ltick)
+{
+    __shared__ int s_lastc;
+    const int tid = threadIdx.x;
+    Acc acc = acc_zero<Acc>();
+    for (int k = tl.k0 + tid; k < tl.k1; k += BLOCK) acc += elem(k);
+    s_tacc[tid] = acc;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (tid < w) s_tacc[tid] += s_tacc[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        st_acc(&lpart[lfirst[tl.lid] + tl.cidx], s_tacc[0]);
+        __threadfence();
+        unsigned t = atomicAdd(&ltick[tl.lid], 1u);
+        s_lastc = (t == (unsigned)(lcount[tl.lid] - 1));
+        if (s_lastc) {
+            __threadfence();
+            Acc tot = acc_zero<Acc>();
+            const int f = lfirst[tl.lid], c = lcount[tl.lid];
+            for (int i = 0; i < c; ++i) tot += ld_acc(lpart + f + i);
+            atomicExch(&ltick[tl.lid], 0u);
+            epi(tl.s0, tot);
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------ step-search replay
+//
+// The search kernels evaluate up to KC candidate steps per pass.  After a
+// pass the last block replays Algorithm 3 sequentially over the evaluated
+// values; when the sequential algorithm needs a value that the pass did not
+// produce, the next pass is set up and the replay resumes from its state.
+
+struct Eval { double psi, phi, zmin; int ok; };
+
+MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
+{
+    Eval e;
+    e.ok = 1;
+    if (c->onesP) {
+        e.psi = alpha * c->dy1;
+    } else {
+        const double s1 = c->rS1P[k] * c->invSw;
+        if (c->eta * alpha * c->dymax > c->psi_lim || !isfinite(s1)) { e.ok = 0; e.psi = 0; }
+        else e.psi = log1p(s1) / c->eta;
+    }
+    if (c->onesC) {
+        e.phi = alpha * c->dz1;
+        e.zmin = c->z1 + alpha * c->dz1;
+    } else {
+        const double s1 = c->rS1C[k] * c->invSu;
+        e.zmin = c->rZmin[k];
+        if (1.0 + s1 >= 0.5) {
+            e.phi = -log1p(s1) / c->eta;
+        } else {
+            const double s2 = c->rS2C[k] * c->invSu;
+            if (s2 >= c->s2_min && isfinite(s2)) e.phi = -log(s2) / c->eta;
+            else { e.ok = 0; e.phi = 0; }
+        }
+    }
+    return e;
+}
+
+MWU_DEV void setup_exp(Ctl *c, double a0)
+{
+    c->skind = SK_EXP;
+    c->ncand = KC;
+    double a = a0;
+    for (int k = 0; k < KC; ++k) { c->cand[k] = a; a *= 2.0; }
+    c->ga0 = a0;
+    c->gdelta = 0.0;
+}
+
+// Candidates of the bisection of [lb, ub] to depth 4, computed with exactly
+// the midpoint arithmetic of the sequential search, in ascending order.
+MWU_DEV void setup_grid(Ctl *c, double lb, double ub)
+{
+    double v[15];
+    // in-order positions of a complete binary tree of depth 4
+    double lo1 = lb, hi1 = ub;
+    double m1 = (lo1 + hi1) / 2.0;
+    double m2a = (lo1 + m1) / 2.0, m2b = (m1 + hi1) / 2.0;
+    double m3a = (lo1 + m2a) / 2.0, m3b = (m2a + m1) / 2.0, m3c = (m1 + m2b) / 2.0,
+           m3d = (m2b + hi1) / 2.0;
+    v[0] = (lo1 + m3a) / 2.0;  v[1] = m3a; v[2] = (m3a + m2a) / 2.0; v[3] = m2a;
+    v[4] = (m2a + m3b) / 2.0;  v[5] = m3b; v[6] = (m3b + m1) / 2.0;  v[7] = m1;
+    v[8] = (m1 + m3c) / 2.0;   v[9] = m3c; v[10] = (m3c + m2b) / 2.0; v[11] = m2b;
+    v[12] = (m2b + m3d) / 2.0; v[13] = m3d; v[14] = (m3d + hi1) / 2.0;
+    c->skind = SK_GRID;
+    c->ncand = 15;
+    for (int k = 0; k < 15; ++k) c->cand[k] = v[k];
+    c->ga0 = v[0];
+    c->gdelta = (ub - lb) / 16.0;
+}
+
+MWU_DEV void setup_refine(Ctl *c, double a)
+{
+    c->skind = SK_REFINE;
+    c->ref_alpha = a;
+    c->ref_valid = 0;
+}
+
+MWU_DEV void accept_step(Ctl *c, double a, double psi, double phi)
+{
+    c->alpha = a;
+    c->LP += psi;
+    c->LC += phi;
+    c->iter += 1;
+    c->last_alpha = a;
+    c->amode = AM_EXP;
+    c->have_cur = 0;
+    c->ref_valid = 0;
+    c->phase = PH_ROW;
+}
+
+MWU_DEV void stop_infeasible(Ctl *c)
+{
+    c->status = ST_INFEASIBLE;
+    c->phase = PH_DONE;
+}
+
+// Find the evaluation of step a: a refined value, or a grid candidate.
+// Returns 0 = found (e filled), 1 = not in the grid, 2 = needs refinement.
+MWU_DEV int lookup(const Ctl *c, double a, Eval *e)
+{
+    if (c->ref_valid == 1 && c->ref_alpha == a) {
+        e->psi = c->ref_psi; e->phi = c->ref_phi; e->zmin = c->ref_zmin; e->ok = 1;
+        return 0;
+    }
+    for (int k = 0; k < c->ncand; ++k)
+        if (c->cand[k] == a) {
+            *e = eval_cand(c, k, a);
+            return e->ok ? 0 : 2;
+        }
+    return 1;
+}
+
+constexpr double ALPHA_CAP = 1125899906842624.0;   // 2^50
+
+MWU_DEV void replay(Ctl *c)
+{
+    for (int guard = 0; guard < 256; ++guard) {
+        if (c->amode == AM_FORCED) {
+            const double a = c->cur_alpha;
+            Eval e;
+            int r = lookup(c, a, &e);
+            if (r == 1) { c->skind = SK_LIST; c->ncand = 1; c->cand[0] = a; return; }
+            if (r == 2) { setup_refine(c, a); return; }
+            c->evaluations += 1;
+            if (a < 1.0) { stop_infeasible(c); return; }
+            accept_step(c, a, e.psi, e.phi);
+            return;
+        }
+        if (c->amode == AM_EXP) {
+            const double a = c->exp_next;
+            Eval e;
+            int r = lookup(c, a, &e);
+            if (r == 1) { setup_exp(c, a); return; }
+            if (r == 2) { setup_refine(c, a); return; }
+            c->evaluations += 1;
+            if (!(e.phi >= e.psi)) {
+                if (!c->have_cur) { stop_infeasible(c); return; }   // T(1) fails: alpha < 1
+                c->lb = c->cur_alpha; c->ub = a;
+                c->lb_psi = c->cur_psi; c->lb_phi = c->cur_phi;
+                c->amode = AM_BIS;
+                continue;
+            }
+            c->have_cur = 1;
+            c->cur_alpha = a; c->cur_psi = e.psi; c->cur_phi = e.phi;
+            if (e.zmin >= 1.0 || a >= ALPHA_CAP) { accept_step(c, a, e.psi, e.phi); return; }
+            c->exp_next = 2.0 * a;
+            continue;
+        }
+        // AM_BIS
+        if (!(c->ub - c->lb > c->eps * c->lb)) { accept_step(c, c->lb, c->lb_psi, c->lb_phi); return; }
+        const double beta = (c->lb + c->ub) / 2.0;
+        Eval e;
+        int r = lookup(c, beta, &e);
+        if (r == 1) { setup_grid(c, c->lb, c->ub); return; }
+        if (r == 2) { setup_refine(c, beta); return; }
+        c->evaluations += 1;
+        if (e.phi >= e.psi) { c->lb = beta; c->lb_psi = e.psi; c->lb_phi = e.phi; }
+        else c->ub = beta;
+    }
+    c->status = ST_NUMERIC;
+    c->phase = PH_DONE;
+}
+
+// Called after the forward product: start the step decision of this iteration.
+MWU_DEV void begin_search(Ctl *c, const double *forced)
+{
+    c->ref_valid = 0;
+    if (c->eval_mode) { c->phase = PH_IDLE; return; }
+    if (forced && c->forced_pos < c->n_forced) {
+        c->amode = AM_FORCED;
+        c->cur_alpha = forced[c->forced_pos++];
+        c->skind = SK_LIST;
+        c->ncand = 1;
+        c->cand[0] = c->cur_alpha;
+        c->phase = PH_SEARCH;
+        return;
+    }
+    if (c->step_rule == 0) {   // standard step alpha = 1; predicted LSE moves are safe bounds
+        accept_step(c, 1.0, c->onesP ? 0.0 : c->dymax, 0.0);
+        return;
+    }
+    c->amode = AM_EXP;
+    c->exp_next = 1.0;
+    c->have_cur = 0;
+    setup_exp(c, 1.0);
+    c->phase = PH_SEARCH;
+}
+
+// Store the reduced record of a search pass and advance the state machine.
+// rec layout: grid passes [s1P(KC) | s1C(KC) | s2C(KC) | zmin'(KC)];
+// refine pass 1 [min z' | max eta*y']; refine pass 2 [sumP | sumC].
+MWU_DEV void finish_search(Ctl *c, const double *rec)
+{
+    c->search_passes += 1;
+    if (c->skind == SK_REFINE) {
+        if (c->ref_valid == 0) {        // pass 1 produced the shifts
+            c->rfZmin = rec[0];
+            c->rfPm = rec[1];
+            c->ref_valid = -1;          // pass 2 pending
+            return;
+        }
+        const double a = c->ref_alpha;
+        double psi, phi, zmn;
+        if (c->onesP) psi = a * c->dy1;
+        else psi = (c->rfPm + log(rec[0])) / c->eta - c->LP;
+        if (c->onesC) { phi = a * c->dz1; zmn = c->z1 + a * c->dz1; }
+        else { zmn = c->rfZmin; phi = zmn - c->LC - log(rec[1]) / c->eta; }
+        c->ref_psi = psi; c->ref_phi = phi; c->ref_zmin = zmn;
+        c->ref_valid = 1;
+        if (c->eval_mode) {
+            const int k = c->ev_cur;
+            c->ev_psi[k] = psi; c->ev_phi[k] = phi; c->ev_zmin[k] = zmn; c->ev_ok[k] = 1;
+        }
+    } else {
+        for (int k = 0; k < KC; ++k) {
+            c->rS1P[k] = rec[k];
+            c->rS1C[k] = rec[KC + k];
+            c->rS2C[k] = rec[2 * KC + k];
+            c->rZmin[k] = rec[3 * KC + k];
+        }
+        if (c->eval_mode) {
+            for (int k = 0; k < c->ncand; ++k) {
+                Eval e = eval_cand(c, k, c->cand[k]);
+                c->ev_psi[k] = e.psi; c->ev_phi[k] = e.phi; c->ev_zmin[k] = e.zmin; c->ev_ok[k] = e.ok;
+            }
+        }
+    }
+    if (c->eval_mode) {
+        // refine, one at a time, every candidate the grid pass could not resolve
+        for (int k = 0; k < c->ncand; ++k)
+            if (!c->ev_ok[k]) {
+                c->ev_cur = k;
+                setup_refine(c, c->cand[k]);
+                c->phase = PH_SEARCH;
+                return;
+            }
+        c->phase = PH_IDLE;
+        return;
+    }
+    replay(c);
+}
+
+}  // namespace mwu

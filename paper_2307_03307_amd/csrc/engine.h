@@ -1,0 +1,157 @@
+// Internal definitions shared by the host driver (solver.cpp) and the gfx950
+// kernels (kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mwu {
+
+constexpr int BLOCK = 256;               // threads per workgroup (4 wave64)
+constexpr int ITEMS = 8;                 // nonzeros per thread in a segment tile
+constexpr int TILE_NZ = BLOCK * ITEMS;   // nonzeros per tile
+constexpr int KC = 16;                   // step candidates per search pass
+constexpr int QMAX = 4 * KC + 8;         // doubles per block in a reduction record
+
+// Phase of the per-probe state machine.  Every kernel of the iteration graph
+// runs only in its own phase and returns at once otherwise, so a graph that
+// captures a fixed launch sequence can follow a data-dependent number of
+// search passes.
+enum Phase : int32_t {
+    PH_IDLE = 0,
+    PH_ROW = 1,      // apply pending step to the rows, weights and LSE totals
+    PH_COL = 2,      // apply pending step to x, transpose product, direction
+    PH_FWD = 3,      // forward product of the direction
+    PH_SEARCH = 4,   // K-candidate step search passes
+    PH_COMMIT = 5,   // apply pending step to x only, then stop
+    PH_DONE = 6
+};
+
+enum Status : int32_t { ST_RUNNING = 0, ST_FEASIBLE = 1, ST_INFEASIBLE = 2, ST_MAX_ITER = 3,
+                        ST_NUMERIC = 4 };
+
+// Kind of candidate set evaluated by one search pass.
+enum SKind : int32_t {
+    SK_EXP = 0,      // cand[k] = a0 * 2^k           (exponential phase of Algorithm 3)
+    SK_GRID = 1,     // cand[j] ~ a0 + j * delta      (bisection tree of depth 4)
+    SK_LIST = 2,     // arbitrary values, direct evaluation
+    SK_REFINE = 3    // one value, max-shifted evaluation of both LSE differences
+};
+
+enum AMode : int32_t { AM_EXP = 0, AM_BIS = 1, AM_FORCED = 2, AM_EVAL = 3 };
+
+// A contiguous piece of a CSR-like structure handled by one workgroup:
+// segments [s0, s1) with nonzeros [k0, k1).  A segment longer than TILE_NZ is
+// split into chunk tiles (lid >= 0): chunk cidx of long segment lid.
+struct Tile {
+    int32_t s0, s1, k0, k1, lid, cidx;
+};
+
+// Device-resident control block of one probe (one per handle).
+struct Ctl {
+    // ---- configuration (set by the host at probe start)
+    double eta, eps, step;      // step = s / eta of the direction formula
+    double sP, sC;              // uniform scale of P and C (1/M, 1/D or 1)
+    double psi_lim;             // largest eta*alpha*max(dy) for the expm1 form
+    double s2_min;              // smallest trusted direct sum of the C-side LSE
+    int32_t onesP, onesC;       // side is the implicit objective row (1 row, all ones)
+    int32_t step_rule, max_iter;
+    int32_t n_forced, forced_pos;
+    int32_t eval_mode, ev_cur;
+    // ---- status
+    int32_t status, phase, iter, pad1;
+    int64_t search_passes, evaluations;
+    // ---- point state
+    double alpha;               // pending step (applied by the next row/column pass)
+    double LP, LC;              // LSE totals; predicted before a row pass, exact after
+    double invSw, invSu;        // 1 / sum of the stored (unnormalized) weights
+    double y1, z1, dy1, dz1;    // value of an implicit objective row and of its product with d
+    double dymax;               // max over packing rows of P d
+    double dmax, dsum;
+    double ymax, zmin;
+    double gmin, hmax;          // of the last direction (certificates)
+    double pack_bound, cover_bound;
+    double last_alpha;
+    double sumx;                // sum of x (init / final statistics)
+    // ---- search state (replay of Algorithm 3)
+    int32_t skind, ncand, amode, have_cur;
+    double cand[KC];
+    double ga0, gdelta;
+    double exp_next, cur_alpha, cur_psi, cur_phi;
+    double lb, ub, lb_psi, lb_phi;
+    int32_t ref_valid, pad2;
+    double ref_alpha, ref_psi, ref_phi, ref_zmin;
+    // results of the last grid pass (raw sums, before normalization)
+    double rS1P[KC], rS1C[KC], rS2C[KC], rZmin[KC];
+    // results of the last refine pass (max-shifted pairs)
+    double rfPm, rfPs, rfCm, rfCs, rfZmin;
+    // evaluation outputs (probe API)
+    double ev_psi[KC], ev_phi[KC], ev_zmin[KC];
+    int32_t ev_ok[KC];
+};
+
+// Generic engine over explicit CSR sides.  Rows of P (if not the implicit
+// objective row) come first in the concatenated row space, then rows of C.
+template <class T>
+struct GenericDev {
+    int32_t n, mPc, mR;                 // variables, explicit P rows, all explicit rows
+    // row structure (forward products)
+    const int32_t *rptr, *rcol;
+    const T *rval;                      // nullable: all ones
+    const Tile *rtiles; int32_t nrtiles;
+    // column structure (transpose products); crow indexes the row space
+    const int32_t *cptr, *crow;
+    const T *cval;                      // nullable
+    const Tile *ctiles; int32_t nctiles;
+    const double *colmaxP;              // max_j P_ji (unscaled) per column, nullable if onesP
+    // long segments
+    const int32_t *rlfirst, *clfirst;   // first partial slot per long segment
+    const int32_t *rlcount, *clcount;
+    unsigned *rltick, *cltick;
+    void *rlpart, *clpart;              // partial sums of chunk tiles
+    // vectors
+    T *x, *d, *yz, *dyz, *wu;
+    double *g_dbg, *h_dbg;              // nullable: debug copies of g, h
+    const double *forced;               // forced steps (host-provided), nullable
+};
+
+// Launch helpers implemented in kernels.hip.
+struct Launch {
+    int grid_elem_rows;  // persistent grid for element-wise passes over rows
+    int grid_elem_cols;  // persistent grid for element-wise passes over columns
+    int grid_rtile;      // persistent grid for row tiles
+    int grid_ctile;      // persistent grid for column tiles
+    double *partials;    // GRID_MAX * QMAX doubles: one record per block
+    double *gpart;       // ceil(GRID_MAX / 32) * QMAX doubles: one record per group
+    unsigned *tickets;   // 1 + ceil(GRID_MAX / 32) counters, all zero between kernels
+};
+
+constexpr int GRID_MAX = 2048;
+
+// Probe start: x0 (Algorithm 1 point unless have_x0), y = Px, z = Cx and the
+// max/min used as the first LSE shift.  Leaves the state machine in PH_ROW.
+template <class T> void generic_init(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
+                                     hipStream_t st, bool have_x0);
+// One iteration slot of the graph: row pass, column pass, forward pass and
+// two search passes (each a no-op outside its phase).
+template <class T> void generic_iteration(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
+                                          hipStream_t st);
+// Individual passes (probe API).
+template <class T> void generic_row(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st);
+template <class T> void generic_col(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st);
+template <class T> void generic_fwd(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st);
+template <class T> void generic_search(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
+                                       hipStream_t st);
+// Copy a double device vector into x (T) and compute sum(x) into the control block.
+template <class T> void generic_load_x(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
+                                       hipStream_t st, const double *x_dev);
+// out[i] = scale * (g_dbg[i] - h_dbg[i]); val (nullable) = LP - LC.
+void potential_finish(const double *g_dbg, const double *h_dbg, int n, double scale, double *out,
+                      const Ctl *ctl, double *val, hipStream_t st);
+// Copy a device vector of T to a double device vector.
+template <class T> void widen(const T *src, double *dst, int64_t n, hipStream_t st);
+template <class T> void narrow(const double *src, T *dst, int64_t n, hipStream_t st);
+// Set ctl->phase (single thread).
+void set_phase(Ctl *ctl, int phase, hipStream_t st);
+
+}  // namespace mwu

@@ -1,0 +1,119 @@
+// Host-side internal structures of the solver library.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mwu.h"
+#include "engine.h"
+
+namespace mwu {
+
+#define HIP_OK(expr)                                                    \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess) throw DeviceError(e_, #expr);             \
+    } while (0)
+
+struct DeviceError {
+    hipError_t code;
+    const char *what;
+    DeviceError(hipError_t c, const char *w) : code(c), what(w) {}
+};
+
+struct ApiError {
+    mwu_status code;
+    std::string msg;
+};
+
+// Explicit CSR on the host (normalized values).
+struct HostCSR {
+    int64_t rows = 0, cols = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> idx;
+    std::vector<double> val;   // empty = every entry is 1
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+    double v(int64_t k) const { return val.empty() ? 1.0 : val[k]; }
+};
+
+// Edge list after validation (caller order) for the graph programs.
+struct EdgeList {
+    int64_t nv = 0, ne = 0;
+    std::vector<int32_t> u, v;
+};
+
+// Owning device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    void alloc(size_t b) {
+        if (p) { (void)hipFree(p); p = nullptr; }
+        bytes = b;
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) { p = nullptr; throw ApiError{MWU_ERR_OOM, "device allocation failed"}; }
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Interface of a device program (the generic CSR engine, the fused graph
+// programs).  All launches go to the solver stream.
+struct Program {
+    virtual ~Program() {}
+    virtual int64_t n() const = 0;
+    virtual int64_t mP() const = 0;     // packing rows as the method sees them
+    virtual int64_t mC() const = 0;
+    virtual void probe_init(bool have_x0) = 0;
+    virtual void upload_x(const double *host_x) = 0;   // host double -> device x
+    virtual void iterations(int slots) = 0;            // enqueue iteration slots
+    virtual void final_stats() = 0;                    // fresh Px, Cx statistics into ctl
+    virtual void save_best() = 0;
+    virtual void best_to_host(double *out) = 0;        // internal variable space
+    virtual void read(int which, double *out, int64_t len) = 0;
+    virtual void row_pass() = 0;
+    virtual void col_pass() = 0;
+    virtual void fwd_pass() = 0;
+    virtual void search_pass() = 0;
+    virtual void potential(const double *x_dev, double *val_dev, double scale, double *grad_dev,
+                           hipStream_t st) = 0;
+    virtual void set_debug(bool on) = 0;
+    virtual void set_forced(const double *host, int count) = 0;
+};
+
+struct Solver {
+    mwu_options opt{};
+    mwu_form form = MWU_PACKING;
+    int onesP = 0, onesC = 0;
+    bool fp32 = true;
+    int64_t n_user = 0;
+    std::vector<int64_t> col_user;   // internal column -> caller variable
+    std::vector<double> col_c;       // c_j of the internal column (x_user = x'/c)
+    // outer-search starting bracket and trivially feasible points
+    double lo0 = 0, hi0 = 0;
+    std::vector<double> x_start;     // rescaled feasible start (internal space)
+    // densest subgraph level-set rounding (mixed problems built from an edge list)
+    bool level_sets = false;
+    EdgeList dens_graph;             // non-isolated vertex ids, canonical
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    DevBuf ctl_buf;
+    Ctl *ctl_host = nullptr;         // pinned mirror
+    std::unique_ptr<Program> prog;
+    hipGraphExec_t graph = nullptr;
+    int graph_slots = 0;
+    bool in_probe = false;
+    double probe_param = 0.0;
+    ~Solver();
+};
+
+// Builders (solver.cpp).
+std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C);
+
+}  // namespace mwu

@@ -1,0 +1,313 @@
+// Host side of the generic CSR engine: device layout of the concatenated row
+// structure and its transpose, nnz-balanced tiles, and the Program interface.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+
+namespace mwu {
+
+// Split segments [0, nseg) of a CSR-like pointer array into tiles of at most
+// TILE_NZ nonzeros and TILE_NZ segments; longer segments become chunk tiles.
+struct TilePlan {
+    std::vector<Tile> tiles;
+    std::vector<int32_t> lfirst, lcount;
+    int32_t nslots = 0;
+};
+
+static TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg)
+{
+    TilePlan tp;
+    int64_t s = 0;
+    while (s < nseg) {
+        const int64_t len = (int64_t)ptr[s + 1] - ptr[s];
+        if (len > TILE_NZ) {
+            const int32_t lid = (int32_t)tp.lfirst.size();
+            const int32_t nch = (int32_t)((len + TILE_NZ - 1) / TILE_NZ);
+            tp.lfirst.push_back(tp.nslots);
+            tp.lcount.push_back(nch);
+            tp.nslots += nch;
+            for (int32_t c = 0; c < nch; ++c) {
+                Tile t;
+                t.s0 = (int32_t)s; t.s1 = (int32_t)(s + 1);
+                t.k0 = ptr[s] + c * TILE_NZ;
+                t.k1 = std::min<int64_t>((int64_t)ptr[s] + (int64_t)(c + 1) * TILE_NZ, ptr[s + 1]);
+                t.lid = lid; t.cidx = c;
+                tp.tiles.push_back(t);
+            }
+            ++s;
+            continue;
+        }
+        const int64_t s0 = s;
+        const int64_t k0 = ptr[s];
+        while (s < nseg && (int64_t)ptr[s + 1] - k0 <= TILE_NZ && s - s0 < TILE_NZ) ++s;
+        Tile t;
+        t.s0 = (int32_t)s0; t.s1 = (int32_t)s; t.k0 = (int32_t)k0; t.k1 = ptr[s];
+        t.lid = -1; t.cidx = 0;
+        tp.tiles.push_back(t);
+    }
+    return tp;
+}
+
+template <class T>
+class GenericProgram : public Program {
+  public:
+    GenericProgram(Solver &s, const HostCSR *P, const HostCSR *C) : s_(s)
+    {
+        const int64_t mPc = s.onesP ? 0 : P->rows;
+        const int64_t mCc = s.onesC ? 0 : C->rows;
+        n_ = s.onesP ? C->cols : P->cols;
+        mPc_ = mPc;
+        mR_ = mPc + mCc;
+        if (mR_ < 1) throw ApiError{MWU_ERR_INVALID_ARG, "no explicit constraint rows"};
+        const bool vals = (!s.onesP && !P->val.empty()) || (!s.onesC && !C->val.empty());
+        const int64_t nnz = (s.onesP ? 0 : P->nnz()) + (s.onesC ? 0 : C->nnz());
+        if (nnz >= INT32_MAX || mR_ >= INT32_MAX || n_ >= INT32_MAX)
+            throw ApiError{MWU_ERR_TOO_LARGE, "structure exceeds 32-bit device indices"};
+        // concatenated row structure
+        std::vector<int32_t> rptr(mR_ + 1), rcol(nnz);
+        std::vector<T> rval(vals ? nnz : 0);
+        int64_t k = 0, r = 0;
+        auto add_side = [&](const HostCSR &A) {
+            for (int64_t i = 0; i < A.rows; ++i, ++r) {
+                rptr[r] = (int32_t)k;
+                for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q, ++k) {
+                    rcol[k] = A.idx[q];
+                    if (vals) rval[k] = (T)A.v(q);
+                }
+            }
+        };
+        if (!s.onesP) add_side(*P);
+        if (!s.onesC) add_side(*C);
+        rptr[mR_] = (int32_t)k;
+        // column structure (transpose); rows visited in order keep each column sorted
+        std::vector<int32_t> cptr(n_ + 1, 0), crow(nnz);
+        std::vector<T> cval(vals ? nnz : 0);
+        for (int64_t q = 0; q < nnz; ++q) cptr[rcol[q] + 1]++;
+        for (int64_t i = 0; i < n_; ++i) cptr[i + 1] += cptr[i];
+        {
+            std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+            for (int64_t rr = 0; rr < mR_; ++rr)
+                for (int32_t q = rptr[rr]; q < rptr[rr + 1]; ++q) {
+                    const int32_t pos = fill[rcol[q]]++;
+                    crow[pos] = (int32_t)rr;
+                    if (vals) cval[pos] = rval[q];
+                }
+        }
+        // max_j P_ji per column (Algorithm 1 initial point)
+        std::vector<double> colmax;
+        if (!s.onesP) {
+            colmax.assign(n_, 0.0);
+            for (int64_t q = 0; q < P->nnz(); ++q)
+                colmax[P->idx[q]] = std::max(colmax[P->idx[q]], P->v(q));
+        }
+        TilePlan rt = build_tiles(rptr, mR_);
+        TilePlan ct = build_tiles(cptr, n_);
+
+        auto up = [&](DevBuf &b, const void *src, size_t bytes) {
+            b.alloc(bytes);
+            if (bytes) HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        up(rptr_, rptr.data(), rptr.size() * 4);
+        up(rcol_, rcol.data(), rcol.size() * 4);
+        up(rval_, rval.data(), rval.size() * sizeof(T));
+        up(cptr_, cptr.data(), cptr.size() * 4);
+        up(crow_, crow.data(), crow.size() * 4);
+        up(cval_, cval.data(), cval.size() * sizeof(T));
+        up(colmax_, colmax.data(), colmax.size() * 8);
+        up(rtiles_, rt.tiles.data(), rt.tiles.size() * sizeof(Tile));
+        up(ctiles_, ct.tiles.data(), ct.tiles.size() * sizeof(Tile));
+        up(rlfirst_, rt.lfirst.data(), rt.lfirst.size() * 4);
+        up(rlcount_, rt.lcount.data(), rt.lcount.size() * 4);
+        up(clfirst_, ct.lfirst.data(), ct.lfirst.size() * 4);
+        up(clcount_, ct.lcount.data(), ct.lcount.size() * 4);
+        rltick_.alloc(std::max<size_t>(rt.lfirst.size(), 1) * 4);
+        cltick_.alloc(std::max<size_t>(ct.lfirst.size(), 1) * 4);
+        HIP_OK(hipMemset(rltick_.p, 0, rltick_.bytes));
+        HIP_OK(hipMemset(cltick_.p, 0, cltick_.bytes));
+        rlpart_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(T));
+        clpart_.alloc(std::max<int32_t>(ct.nslots, 1) * 2 * sizeof(T));
+        x_.alloc(n_ * sizeof(T));
+        d_.alloc(n_ * sizeof(T));
+        xbest_.alloc(n_ * sizeof(T));
+        yz_.alloc(mR_ * sizeof(T));
+        dyz_.alloc(mR_ * sizeof(T));
+        wu_.alloc(mR_ * sizeof(T));
+        HIP_OK(hipMemset(d_.p, 0, d_.bytes));
+        HIP_OK(hipMemset(dyz_.p, 0, dyz_.bytes));
+        partials_.alloc((size_t)GRID_MAX * QMAX * 8);
+        gpart_.alloc((size_t)(GRID_MAX / 32 + 1) * QMAX * 8);
+        tickets_.alloc((size_t)(GRID_MAX / 32 + 2) * 4);
+        HIP_OK(hipMemset(tickets_.p, 0, tickets_.bytes));
+
+        gd_ = GenericDev<T>{};
+        gd_.n = (int32_t)n_; gd_.mPc = (int32_t)mPc_; gd_.mR = (int32_t)mR_;
+        gd_.rptr = rptr_.as<int32_t>(); gd_.rcol = rcol_.as<int32_t>(); gd_.rval = vals ? rval_.as<T>() : nullptr;
+        gd_.rtiles = rtiles_.as<Tile>(); gd_.nrtiles = (int32_t)rt.tiles.size();
+        gd_.cptr = cptr_.as<int32_t>(); gd_.crow = crow_.as<int32_t>(); gd_.cval = vals ? cval_.as<T>() : nullptr;
+        gd_.ctiles = ctiles_.as<Tile>(); gd_.nctiles = (int32_t)ct.tiles.size();
+        gd_.colmaxP = s.onesP ? nullptr : colmax_.as<double>();
+        gd_.rlfirst = rlfirst_.as<int32_t>(); gd_.clfirst = clfirst_.as<int32_t>();
+        gd_.rlcount = rlcount_.as<int32_t>(); gd_.clcount = clcount_.as<int32_t>();
+        gd_.rltick = rltick_.as<unsigned>(); gd_.cltick = cltick_.as<unsigned>();
+        gd_.rlpart = rlpart_.p; gd_.clpart = clpart_.p;
+        gd_.x = x_.as<T>(); gd_.d = d_.as<T>(); gd_.yz = yz_.as<T>(); gd_.dyz = dyz_.as<T>();
+        gd_.wu = wu_.as<T>();
+        gd_.g_dbg = nullptr; gd_.h_dbg = nullptr; gd_.forced = nullptr;
+
+        auto clampg = [](int64_t items, int64_t per) {
+            int64_t g = (items + per - 1) / per;
+            return (int)std::max<int64_t>(1, std::min<int64_t>(g, GRID_MAX));
+        };
+        L_.grid_elem_rows = clampg(mR_, BLOCK * 2);
+        L_.grid_elem_cols = clampg(n_, BLOCK * 2);
+        L_.grid_rtile = clampg((int64_t)rt.tiles.size(), 1);
+        L_.grid_ctile = clampg((int64_t)ct.tiles.size(), 1);
+        L_.partials = partials_.as<double>();
+        L_.gpart = gpart_.as<double>();
+        L_.tickets = tickets_.as<unsigned>();
+    }
+
+    int64_t n() const override { return n_; }
+    int64_t mP() const override { return s_.onesP ? 1 : mPc_; }
+    int64_t mC() const override { return s_.onesC ? 1 : mR_ - mPc_; }
+
+    Ctl *ctl() const { return s_.ctl_buf.as<Ctl>(); }
+
+    void probe_init(bool have_x0) override { generic_init<T>(gd_, ctl(), L_, s_.stream, have_x0); }
+
+    void upload_x(const double *host_x) override
+    {
+        DevBuf tmp;
+        tmp.alloc(n_ * 8);
+        HIP_OK(hipMemcpyAsync(tmp.p, host_x, n_ * 8, hipMemcpyHostToDevice, s_.stream));
+        narrow<T>(tmp.as<double>(), gd_.x, n_, s_.stream);
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    void iterations(int slots) override
+    {
+        for (int i = 0; i < slots; ++i) generic_iteration<T>(gd_, ctl(), L_, s_.stream);
+    }
+
+    void final_stats() override { generic_init<T>(gd_, ctl(), L_, s_.stream, true); }
+
+    void save_best() override
+    {
+        HIP_OK(hipMemcpyAsync(xbest_.p, x_.p, n_ * sizeof(T), hipMemcpyDeviceToDevice, s_.stream));
+    }
+
+    void best_to_host(double *out) override { to_host(xbest_.as<T>(), n_, out); }
+
+    void read(int which, double *out, int64_t len) override
+    {
+        const int64_t mCc = mR_ - mPc_;
+        switch (which) {
+        case 0: need(len, n_); to_host(gd_.x, n_, out); return;
+        case 1: need(len, n_); to_host(gd_.d, n_, out); return;
+        case 2:
+        case 3:
+            need(len, n_);
+            if (!dbg_g_.p) throw ApiError{MWU_ERR_STATE, "g/h are recorded by mwu_probe_direction"};
+            HIP_OK(hipMemcpyAsync(out, which == 2 ? dbg_g_.p : dbg_h_.p, n_ * 8, hipMemcpyDeviceToHost,
+                                  s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            return;
+        case 4:
+        case 6:
+            if (s_.onesP) { need(len, 1); out[0] = scalar(which == 4 ? 0 : 2); return; }
+            need(len, mPc_);
+            to_host((which == 4 ? gd_.yz : gd_.dyz), mPc_, out);
+            return;
+        case 5:
+        case 7:
+            if (s_.onesC) { need(len, 1); out[0] = scalar(which == 5 ? 1 : 3); return; }
+            need(len, mCc);
+            to_host((which == 5 ? gd_.yz : gd_.dyz) + mPc_, mCc, out);
+            return;
+        }
+        throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
+    }
+
+    void row_pass() override { generic_row<T>(dbg_gd(), ctl(), L_, s_.stream); }
+    void col_pass() override { generic_col<T>(dbg_gd(), ctl(), L_, s_.stream); }
+    void fwd_pass() override { generic_fwd<T>(dbg_gd(), ctl(), L_, s_.stream); }
+    void search_pass() override { generic_search<T>(dbg_gd(), ctl(), L_, s_.stream); }
+
+    void set_debug(bool on) override
+    {
+        if (on && !dbg_g_.p) { dbg_g_.alloc(n_ * 8); dbg_h_.alloc(n_ * 8); }
+        debug_ = on;
+    }
+
+    void set_forced(const double *host, int count) override
+    {
+        if (count > 0) {
+            forced_.alloc((size_t)count * 8);
+            HIP_OK(hipMemcpy(forced_.p, host, (size_t)count * 8, hipMemcpyHostToDevice));
+            gd_.forced = forced_.as<double>();
+        } else {
+            gd_.forced = nullptr;
+        }
+        s_.graph_slots = -1;   // graph holds the old parameters: recapture
+    }
+
+    void potential(const double *x_dev, double *val_dev, double scale, double *grad_dev,
+                   hipStream_t st) override
+    {
+        set_debug(true);
+        GenericDev<T> g = dbg_gd();
+        generic_load_x<T>(g, ctl(), L_, st, x_dev);
+        generic_row<T>(g, ctl(), L_, st);
+        generic_col<T>(g, ctl(), L_, st);
+        if (grad_dev || val_dev)
+            potential_finish(dbg_g_.as<double>(), dbg_h_.as<double>(), grad_dev ? (int)n_ : 0, scale,
+                             grad_dev, ctl(), val_dev, st);
+    }
+
+  private:
+    GenericDev<T> dbg_gd() const
+    {
+        GenericDev<T> g = gd_;
+        if (debug_) { g.g_dbg = dbg_g_.as<double>(); g.h_dbg = dbg_h_.as<double>(); }
+        return g;
+    }
+    static void need(int64_t len, int64_t want)
+    {
+        if (len != want) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
+    }
+    double scalar(int which)
+    {
+        Ctl c;
+        HIP_OK(hipMemcpyAsync(&c, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        return which == 0 ? c.y1 : which == 1 ? c.z1 : which == 2 ? c.dy1 : c.dz1;
+    }
+    void to_host(const T *src, int64_t len, double *out)
+    {
+        if (len == 0) return;
+        DevBuf tmp;
+        tmp.alloc(len * 8);
+        widen<T>(src, tmp.as<double>(), len, s_.stream);
+        HIP_OK(hipMemcpyAsync(out, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    Solver &s_;
+    int64_t n_ = 0, mPc_ = 0, mR_ = 0;
+    bool debug_ = false;
+    GenericDev<T> gd_{};
+    Launch L_{};
+    DevBuf rptr_, rcol_, rval_, cptr_, crow_, cval_, colmax_, rtiles_, ctiles_;
+    DevBuf rlfirst_, rlcount_, clfirst_, clcount_, rltick_, cltick_, rlpart_, clpart_;
+    DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, gpart_, tickets_, forced_, dbg_g_, dbg_h_;
+};
+
+std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C)
+{
+    if (s.fp32) return std::unique_ptr<Program>(new GenericProgram<float>(s, P, C));
+    return std::unique_ptr<Program>(new GenericProgram<double>(s, P, C));
+}
+
+}  // namespace mwu
