@@ -218,8 +218,10 @@ mwu_status mwu_probe_run(void *s, int32_t max_iters, const double *forced_alpha,
 mwu_status mwu_probe_direction(void *s);
 
 /* Copy an internal vector to the host (double).  which: 0 x, 1 d, 2 g, 3 h,
- * 4 y = Px (m_P), 5 z = Cx (m_C), 6 dy = Pd (m_P), 7 dz = Cd (m_C).  len must
- * equal the vector's length. */
+ * 4 y = Px (m_P), 5 z = Cx (m_C), 6 dy = Pd (m_P), 7 dz = Cd (m_C), 8 the
+ * accepted steps of the current probe (length = its iteration count).  len
+ * must equal the vector's length.  g and h are those of the last
+ * mwu_probe_direction call. */
 mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
 
 /* Evaluate Psi(alpha_k), Phi(alpha_k) (Section 4.1) and min(Cx + alpha_k Cd)
@@ -227,6 +229,19 @@ mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
  * host arrays of length count; zmin_new is nullable. */
 mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new);
+
+/* Time one pass of the iteration: which = 0 row / transpose pass (the
+ * weights, their LSE totals and C^T u, P^T w), 1 column / direction pass,
+ * 2 forward pass (P d, C d; a no-op in fused programs that form it inside
+ * the search), 3 step-search pass over a 16-candidate exponential grid.
+ * The pass is launched reps times on the handle's stream with the probe state
+ * frozen (after one direction at the current point), timed with HIP events;
+ * the probe state is restored afterwards.  Outputs (host): average duration
+ * in microseconds, algorithmic HBM bytes of one launch (every index, dense
+ * vector and output counted once; nullable) and the nonzeros the pass visits
+ * (nullable).  Needs a probe at an iteration start (mwu_probe_begin). */
+mwu_status mwu_time_pass(void *s, int32_t which, int32_t reps, double *avg_us, double *bytes,
+                         double *nnz);
 
 /* ---------------------------------------------------------------------------
  * Smoothed potential for automatic differentiation: Phi(x) = smax_eta(P x) -

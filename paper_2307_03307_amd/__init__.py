@@ -25,7 +25,7 @@ __all__ = ["Solver", "Result", "csr_matrix", "incidence", "incidence_t", "edge_p
            "MwuError", "PACKING", "COVERING", "MIXED", "FP64", "MIXED_FP32_FP64", "STEP_BIN",
            "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER"]
 
-VEC = {"x": 0, "d": 1, "g": 2, "h": 3, "y": 4, "z": 5, "dy": 6, "dz": 7}
+VEC = {"x": 0, "d": 1, "g": 2, "h": 3, "y": 4, "z": 5, "dy": 6, "dz": 7, "alpha": 8}
 
 
 @dataclasses.dataclass
@@ -194,6 +194,13 @@ class Solver:
                                                 phi.ctypes.data, zm.ctypes.data),
                    "mwu_probe_eval_steps")
         return psi, phi, zm
+
+    def time_pass(self, which: int, reps: int = 20):
+        """(average microseconds, algorithmic bytes, nonzeros) of one pass launch."""
+        us, by, nz = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(self._L.mwu_time_pass(self._h, int(which), int(reps), ctypes.addressof(us),
+                                         ctypes.addressof(by), ctypes.addressof(nz)), "mwu_time_pass")
+        return us.value, by.value, nz.value
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -251,6 +251,66 @@ MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, EpiF &epi, Acc *s_tacc, Acc
     __syncthreads();
 }
 
+// ------------------------------------------------- search terms of one row
+//
+// Covering row with weight u (unnormalized, u = exp(-eta (z - L))), value z
+// and direction dz; adds, for every candidate step a_k of the pass,
+//   acc[k]        += u expm1(-eta a_k dz)      (cancellation-free Phi sum)
+//   acc[KC + k]   += u exp(-eta a_k dz)        (direct Phi sum)
+//   acc[2KC + k]   = min(acc[2KC + k], z + a_k dz)
+// Exponential grids use expm1(2x) = expm1(x)(expm1(x) + 2) and squaring,
+// bisection grids the addition rule expm1(x+y) = expm1(x) + expm1(y) +
+// expm1(x) expm1(y); float re-seeds the squared term every 4 candidates.
+template <class T>
+MWU_DEV void cov_row_terms(int kind, int nc, const double *cd, double gdel, double eta, T u, T z,
+                           T dz, double *acc)
+{
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (k < nc) acc[2 * KC + k] = fmin(acc[2 * KC + k], (double)(z + (T)cd[k] * dz));
+    if (!(u > T(0))) return;
+    if (!(dz > T(0))) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[KC + k] += (double)u;
+        return;
+    }
+    if (kind == SK_EXP) {
+        const T b0 = (T)(eta * cd[0] * (double)dz);
+        T m = expm1_t(-b0);
+        T t = exp_t(-b0);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            acc[k] += (double)(u * m);
+            acc[KC + k] += (double)(u * t);
+            m = m * (m + T(2));
+            if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KC)
+                t = exp_t((T)(-eta * cd[k + 1] * (double)dz));
+            else
+                t = t * t;
+        }
+    } else if (kind == SK_GRID) {
+        const T b0 = (T)(eta * cd[0] * (double)dz);
+        const T bd = (T)(eta * gdel * (double)dz);
+        T m = expm1_t(-b0);
+        T t = exp_t(-b0);
+        const T mr = expm1_t(-bd);
+        const T tr = exp_t(-bd);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            acc[k] += (double)(u * m);
+            acc[KC + k] += (double)(u * t);
+            m = m + mr + m * mr;
+            t = t * tr;
+        }
+    } else {
+        for (int k = 0; k < nc; ++k) {
+            const T b = (T)(eta * cd[k] * (double)dz);
+            acc[k] += (double)(u * expm1_t(-b));
+            acc[KC + k] += (double)(u * exp_t(-b));
+        }
+    }
+}
+
 // ------------------------------------------------------ step-search replay
 //
 // The search kernels evaluate up to KC candidate steps per pass.  After a
@@ -286,6 +346,14 @@ MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
         }
     }
     return e;
+}
+
+// Timing mode: a pass can be replayed with the state frozen.
+MWU_DEV bool held(Ctl *c)
+{
+    if (!c->hold) return false;
+    c->phase = c->hold;
+    return true;
 }
 
 MWU_DEV void setup_exp(Ctl *c, double a0)
@@ -329,6 +397,7 @@ MWU_DEV void setup_refine(Ctl *c, double a)
 
 MWU_DEV void accept_step(Ctl *c, double a, double psi, double phi)
 {
+    if (c->trace && c->iter < c->trace_cap) c->trace[c->iter] = a;
     c->alpha = a;
     c->LP += psi;
     c->LC += phi;
@@ -443,6 +512,7 @@ MWU_DEV void begin_search(Ctl *c, const double *forced)
 // refine pass 1 [min z' | max eta*y']; refine pass 2 [sumP | sumC].
 MWU_DEV void finish_search(Ctl *c, const double *rec)
 {
+    if (held(c)) return;
     c->search_passes += 1;
     if (c->skind == SK_REFINE) {
         if (c->ref_valid == 0) {        // pass 1 produced the shifts

@@ -58,12 +58,14 @@ struct Ctl {
     int32_t step_rule, max_iter;
     int32_t n_forced, forced_pos;
     int32_t eval_mode, ev_cur;
+    int32_t hold, pad4;         // nonzero: finishers keep this phase and change nothing (timing)
     // ---- status
     int32_t status, phase, iter, pad1;
     int64_t search_passes, evaluations;
     // ---- point state
     double alpha;               // pending step (applied by the next row/column pass)
     double LP, LC;              // LSE totals; predicted before a row pass, exact after
+    double LCw;                 // shift the stored/recomputed covering weights were formed with
     double invSw, invSu;        // 1 / sum of the stored (unnormalized) weights
     double y1, z1, dy1, dz1;    // value of an implicit objective row and of its product with d
     double dymax;               // max over packing rows of P d
@@ -73,6 +75,8 @@ struct Ctl {
     double pack_bound, cover_bound;
     double last_alpha;
     double sumx;                // sum of x (init / final statistics)
+    double *trace;              // nullable device array: accepted step of each iteration
+    int32_t trace_cap, pad3;
     // ---- search state (replay of Algorithm 3)
     int32_t skind, ncand, amode, have_cur;
     double cand[KC];
@@ -109,13 +113,36 @@ struct GenericDev {
     const int32_t *rlcount, *clcount;
     unsigned *rltick, *cltick;
     void *rlpart, *clpart;              // partial sums of chunk tiles
+    void *rlpart64;                     // double partial sums of row chunk tiles (statistics)
     // vectors
     T *x, *d, *yz, *dyz, *wu;
     double *g_dbg, *h_dbg;              // nullable: debug copies of g, h
     const double *forced;               // forced steps (host-provided), nullable
 };
 
-// Launch helpers implemented in kernels.hip.
+// Fused vertex-cover program: C = M^T read from the edge list, P = the
+// objective row.  Edge-indexed vectors (z = x_u + x_v, dz, u) are never
+// stored; every pass recomputes them from the vertex vectors.
+template <class T>
+struct XD { T x, d; };
+
+template <class T>
+struct VcDev {
+    int32_t nv, ne;
+    const int32_t *uptr, *ucol;         // upper adjacency: edges (u, w) with u < w, canonical order
+    const Tile *utiles; int32_t nutiles;
+    const int32_t *fptr, *fcol;         // full adjacency (both directions)
+    const Tile *ftiles; int32_t nftiles;
+    const int32_t *flfirst, *flcount;
+    unsigned *fltick;
+    T *flpart;
+    XD<T> *xd;                          // x and d interleaved (one 2T gather per neighbor)
+    T *h;                               // unnormalized C^T u per vertex
+    double *h_dbg;                      // nullable
+    const double *forced;
+};
+
+// Launch helpers implemented in the .hip files.
 struct Launch {
     int grid_elem_rows;  // persistent grid for element-wise passes over rows
     int grid_elem_cols;  // persistent grid for element-wise passes over columns
@@ -136,6 +163,9 @@ template <class T> void generic_init(const GenericDev<T> &g, Ctl *ctl, const Lau
 // two search passes (each a no-op outside its phase).
 template <class T> void generic_iteration(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
                                           hipStream_t st);
+// FP64 statistics of x: sum x, max over packing rows, min over covering rows.
+template <class T> void generic_stats(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
+                                      hipStream_t st, const double *rval64);
 // Individual passes (probe API).
 template <class T> void generic_row(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st);
 template <class T> void generic_col(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st);
@@ -153,5 +183,22 @@ template <class T> void widen(const T *src, double *dst, int64_t n, hipStream_t 
 template <class T> void narrow(const double *src, T *dst, int64_t n, hipStream_t st);
 // Set ctl->phase (single thread).
 void set_phase(Ctl *ctl, int phase, hipStream_t st);
+
+struct VcLaunch {
+    int grid_v;        // element-wise over vertices
+    int grid_ftile;    // full-adjacency tiles
+    int grid_utile;    // upper-adjacency tiles
+    double *partials, *gpart;
+    unsigned *tickets;
+};
+template <class T> void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,
+                                bool have_x0);
+template <class T> void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
+template <class T> void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
+template <class T> void vc_passB(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
+template <class T> void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
+// which: 0 = x, 1 = d (vertex vectors, double out); 2 = z, 3 = dz (edge vectors, canonical order)
+template <class T> void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st);
+template <class T> void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st);
 
 }  // namespace mwu

@@ -21,6 +21,7 @@ namespace mwu {
 MWU_DEV void finish_row(Ctl *c, const double *rec)
 {
     // rec: [sum w | sum u | min z | max y]
+    if (held(c)) return;
     const double a = c->alpha;
     bool bad = false;
     if (c->onesP) {
@@ -57,6 +58,7 @@ MWU_DEV void finish_row(Ctl *c, const double *rec)
 MWU_DEV void finish_col(Ctl *c, const double *rec)
 {
     // rec: [sum d | min g | max d | max h]
+    if (held(c)) return;
     c->alpha = 0.0;
     c->dsum = rec[0];
     c->gmin = rec[1];
@@ -280,10 +282,45 @@ __global__ __launch_bounds__(BLOCK) void k_fwd(GenericDev<T> gd, Ctl *ctl, const
     if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
         if (INIT) {
             finish_init_fwd(ctl, s_rec);
-        } else {
+        } else if (!held(ctl)) {
             ctl->dymax = s_rec[1];
             begin_search(ctl, gd.forced);
         }
+    }
+}
+
+// Certificate statistics of the current x in FP64 whatever the storage type:
+// max over packing rows and min over covering rows of (scaled) A x, formed from
+// the double coefficients (rval64, nullable = all ones).
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_stats(GenericDev<T> gd, Ctl *ctl, const double *rval64,
+                                                  double *part, double *gpart, unsigned *tick)
+{
+    __shared__ double s_acc[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ int32_t s_tseg[BLOCK];
+    __shared__ double s_tacc[BLOCK];
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    const double sP = ctl->sP, sC = ctl->sC;
+    const int mPc = gd.mPc;
+    double v[2] = {INFINITY, -INFINITY};
+    auto elem = [&](int k) -> double { return (rval64 ? rval64[k] : 1.0) * (double)gd.x[gd.rcol[k]]; };
+    auto epi = [&](int r, double acc) {
+        if (r < mPc) v[1] = fmax(v[1], sP * acc);
+        else v[0] = fmin(v[0], sC * acc);
+    };
+    for (int t = blockIdx.x; t < gd.nrtiles; t += gridDim.x) {
+        const Tile tl = gd.rtiles[t];
+        if (tl.lid < 0) seg_tile<double>(tl, gd.rptr, elem, epi, s_acc, s_ptr, s_tseg, s_tacc);
+        else chunk_tile<double>(tl, elem, epi, s_tacc, (double *)gd.rlpart64, gd.rlfirst, gd.rlcount,
+                                gd.rltick);
+    }
+    const Red red{0, 1, 1};
+    block_combine<2>(v, red, 0, s_wave, s_rec);
+    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+        ctl->zmin = ctl->onesC ? ctl->sC * ctl->sumx : s_rec[0];
+        ctl->ymax = ctl->onesP ? ctl->sP * ctl->sumx : s_rec[1];
     }
 }
 
@@ -371,53 +408,8 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
         double acc[3 * KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) { acc[k] = 0.0; acc[KC + k] = 0.0; acc[2 * KC + k] = INFINITY; }
-        for (int r = mPc + r0; r < mR; r += stride) {
-            const T u = gd.wu[r], z = gd.yz[r], dz = gd.dyz[r];
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < nc) acc[2 * KC + k] = fmin(acc[2 * KC + k], (double)(z + (T)cd[k] * dz));
-            if (!(u > T(0))) continue;
-            if (!(dz > T(0))) {
-#pragma unroll
-                for (int k = 0; k < KC; ++k) acc[KC + k] += (double)u;
-                continue;
-            }
-            if (kind == SK_EXP) {
-                const T b0 = (T)(eta * cd[0] * (double)dz);
-                T m = expm1_t(-b0);
-                T t = exp_t(-b0);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    acc[k] += (double)(u * m);
-                    acc[KC + k] += (double)(u * t);
-                    m = m * (m + T(2));
-                    if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KC)
-                        t = exp_t((T)(-eta * cd[k + 1] * (double)dz));   // float: re-seed every 4
-                    else
-                        t = t * t;
-                }
-            } else if (kind == SK_GRID) {
-                const T b0 = (T)(eta * cd[0] * (double)dz);
-                const T bd = (T)(eta * gdel * (double)dz);
-                T m = expm1_t(-b0);
-                T t = exp_t(-b0);
-                const T mr = expm1_t(-bd);
-                const T tr = exp_t(-bd);
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    acc[k] += (double)(u * m);
-                    acc[KC + k] += (double)(u * t);
-                    m = m + mr + m * mr;
-                    t = t * tr;
-                }
-            } else {
-                for (int k = 0; k < nc; ++k) {
-                    const T b = (T)(eta * cd[k] * (double)dz);
-                    acc[k] += (double)(u * expm1_t(-b));
-                    acc[KC + k] += (double)(u * exp_t(-b));
-                }
-            }
-        }
+        for (int r = mPc + r0; r < mR; r += stride)
+            cov_row_terms<T>(kind, nc, cd, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], acc);
         const Red redc{3 * KC, KC, 0};
         block_combine<3 * KC>(acc, redc, KC, s_wave, s_rec + KC);
     }
@@ -476,6 +468,16 @@ void generic_load_x(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream
                        L.partials, L.gpart, L.tickets);
     hipLaunchKernelGGL((k_fwd<T, true>), dim3(L.grid_rtile), dim3(BLOCK), 0, st, g, ctl,
                        (const T *)g.x, g.yz, L.partials, L.gpart, L.tickets);
+}
+
+template <class T>
+void generic_stats(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st,
+                   const double *rval64)
+{
+    hipLaunchKernelGGL(k_init_x<T>, dim3(L.grid_elem_cols), dim3(BLOCK), 0, st, g, ctl, 1,
+                       L.partials, L.gpart, L.tickets);
+    hipLaunchKernelGGL(k_stats<T>, dim3(L.grid_rtile), dim3(BLOCK), 0, st, g, ctl, rval64,
+                       L.partials, L.gpart, L.tickets);
 }
 
 template <class T>
@@ -546,6 +548,8 @@ void set_phase(Ctl *ctl, int phase, hipStream_t st)
     template void generic_load_x<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t,  \
                                     const double *);                                            \
     template void generic_row<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t);    \
+    template void generic_stats<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t,   \
+                                   const double *);                                             \
     template void generic_col<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t);    \
     template void generic_fwd<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t);    \
     template void generic_search<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t); \

@@ -84,6 +84,10 @@ struct Program {
                            hipStream_t st) = 0;
     virtual void set_debug(bool on) = 0;
     virtual void set_forced(const double *host, int count) = 0;
+    // Algorithmic HBM bytes of one launch of a pass (0 row/transpose, 1 column/direction,
+    // 2 forward, 3 search): every index once, every dense vector once, every output once.
+    virtual double algo_bytes(int which) const = 0;
+    virtual double pass_nnz(int which) const = 0;
 };
 
 struct Solver {
@@ -104,6 +108,7 @@ struct Solver {
     bool own_stream = false;
     int device = 0;
     DevBuf ctl_buf;
+    DevBuf trace_buf;                // accepted steps of the current probe (max_iter doubles)
     Ctl *ctl_host = nullptr;         // pinned mirror
     std::unique_ptr<Program> prog;
     hipGraphExec_t graph = nullptr;
@@ -113,7 +118,17 @@ struct Solver {
     ~Solver();
 };
 
-// Builders (solver.cpp).
+struct TilePlan {
+    std::vector<Tile> tiles;
+    std::vector<int32_t> lfirst, lcount;
+    int32_t nslots = 0;
+};
+TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg);
+
+// Program builders.
 std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C);
+// Vertex cover from a validated edge list; newid maps vertices to compact ids (-1 = isolated).
+std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,
+                                             const std::vector<int64_t> &newid, int64_t nv);
 
 }  // namespace mwu

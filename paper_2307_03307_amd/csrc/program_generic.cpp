@@ -10,13 +10,7 @@ namespace mwu {
 
 // Split segments [0, nseg) of a CSR-like pointer array into tiles of at most
 // TILE_NZ nonzeros and TILE_NZ segments; longer segments become chunk tiles.
-struct TilePlan {
-    std::vector<Tile> tiles;
-    std::vector<int32_t> lfirst, lcount;
-    int32_t nslots = 0;
-};
-
-static TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg)
+TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg)
 {
     TilePlan tp;
     int64_t s = 0;
@@ -102,6 +96,8 @@ class GenericProgram : public Program {
             for (int64_t q = 0; q < P->nnz(); ++q)
                 colmax[P->idx[q]] = std::max(colmax[P->idx[q]], P->v(q));
         }
+        nnz_ = nnz;
+        vals_ = vals;
         TilePlan rt = build_tiles(rptr, mR_);
         TilePlan ct = build_tiles(cptr, n_);
 
@@ -127,6 +123,14 @@ class GenericProgram : public Program {
         HIP_OK(hipMemset(rltick_.p, 0, rltick_.bytes));
         HIP_OK(hipMemset(cltick_.p, 0, cltick_.bytes));
         rlpart_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(T));
+        rlpart64_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(double));
+        if (vals) {   // exact coefficients for the FP64 certificate statistics
+            std::vector<double> r64(nnz);
+            int64_t q = 0;
+            for (const HostCSR *A : {s.onesP ? nullptr : P, s.onesC ? nullptr : C})
+                if (A) for (int64_t kk = 0; kk < A->nnz(); ++kk) r64[q++] = A->v(kk);
+            up(rval64_, r64.data(), r64.size() * 8);
+        }
         clpart_.alloc(std::max<int32_t>(ct.nslots, 1) * 2 * sizeof(T));
         x_.alloc(n_ * sizeof(T));
         d_.alloc(n_ * sizeof(T));
@@ -151,7 +155,7 @@ class GenericProgram : public Program {
         gd_.rlfirst = rlfirst_.as<int32_t>(); gd_.clfirst = clfirst_.as<int32_t>();
         gd_.rlcount = rlcount_.as<int32_t>(); gd_.clcount = clcount_.as<int32_t>();
         gd_.rltick = rltick_.as<unsigned>(); gd_.cltick = cltick_.as<unsigned>();
-        gd_.rlpart = rlpart_.p; gd_.clpart = clpart_.p;
+        gd_.rlpart = rlpart_.p; gd_.clpart = clpart_.p; gd_.rlpart64 = rlpart64_.p;
         gd_.x = x_.as<T>(); gd_.d = d_.as<T>(); gd_.yz = yz_.as<T>(); gd_.dyz = dyz_.as<T>();
         gd_.wu = wu_.as<T>();
         gd_.g_dbg = nullptr; gd_.h_dbg = nullptr; gd_.forced = nullptr;
@@ -191,7 +195,10 @@ class GenericProgram : public Program {
         for (int i = 0; i < slots; ++i) generic_iteration<T>(gd_, ctl(), L_, s_.stream);
     }
 
-    void final_stats() override { generic_init<T>(gd_, ctl(), L_, s_.stream, true); }
+    void final_stats() override
+    {
+        generic_stats<T>(gd_, ctl(), L_, s_.stream, rval64_.p ? rval64_.as<double>() : nullptr);
+    }
 
     void save_best() override
     {
@@ -266,6 +273,19 @@ class GenericProgram : public Program {
                              grad_dev, ctl(), val_dev, st);
     }
 
+    double algo_bytes(int which) const override
+    {
+        const double t = sizeof(T), nnz = (double)nnz_, vb = vals_ ? t : 0.0;
+        switch (which) {
+        case 0: return 4.0 * t * mR_;
+        case 1: return 4.0 * (n_ + 1) + (4.0 + vb) * nnz + t * mR_ + 4.0 * t * n_;
+        case 2: return 4.0 * (mR_ + 1) + (4.0 + vb) * nnz + t * n_ + t * mR_;
+        case 3: return 3.0 * t * mR_;
+        }
+        return 0.0;
+    }
+    double pass_nnz(int which) const override { return (which == 1 || which == 2) ? (double)nnz_ : 0.0; }
+
   private:
     GenericDev<T> dbg_gd() const
     {
@@ -295,12 +315,13 @@ class GenericProgram : public Program {
     }
 
     Solver &s_;
-    int64_t n_ = 0, mPc_ = 0, mR_ = 0;
+    int64_t n_ = 0, mPc_ = 0, mR_ = 0, nnz_ = 0;
+    bool vals_ = false;
     bool debug_ = false;
     GenericDev<T> gd_{};
     Launch L_{};
     DevBuf rptr_, rcol_, rval_, cptr_, crow_, cval_, colmax_, rtiles_, ctiles_;
-    DevBuf rlfirst_, rlcount_, clfirst_, clcount_, rltick_, cltick_, rlpart_, clpart_;
+    DevBuf rlfirst_, rlcount_, clfirst_, clcount_, rltick_, cltick_, rlpart_, clpart_, rlpart64_, rval64_;
     DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, gpart_, tickets_, forced_, dbg_g_, dbg_h_;
 };
 

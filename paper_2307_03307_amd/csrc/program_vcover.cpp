@@ -1,0 +1,243 @@
+// Host side of the fused vertex-cover program: canonical upper and full
+// adjacency of the non-isolated vertices, their tiles, and the Program
+// interface.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+
+namespace mwu {
+
+template <class T>
+class VcoverProgram : public Program {
+  public:
+    VcoverProgram(Solver &s, const EdgeList &el, const std::vector<int64_t> &newid, int64_t nv) : s_(s)
+    {
+        nv_ = nv;
+        // canonical edges (min, max) of compact ids, sorted: edge e = position
+        std::vector<uint64_t> key(el.ne);
+        for (int64_t e = 0; e < el.ne; ++e) {
+            const int64_t a = newid[el.u[e]], b = newid[el.v[e]];
+            key[e] = (uint64_t)std::min(a, b) * (uint64_t)nv + (uint64_t)std::max(a, b);
+        }
+        std::sort(key.begin(), key.end());
+        ne_ = el.ne;
+        if (2 * ne_ >= INT32_MAX) throw ApiError{MWU_ERR_TOO_LARGE, "too many edges"};
+        std::vector<int32_t> uptr(nv + 1, 0), ucol(ne_), fptr(nv + 1, 0), fcol(2 * ne_);
+        for (int64_t e = 0; e < ne_; ++e) {
+            const int64_t a = key[e] / nv, b = key[e] % nv;
+            uptr[a + 1]++;
+            fptr[a + 1]++;
+            fptr[b + 1]++;
+            ucol[e] = (int32_t)b;
+        }
+        for (int64_t v = 0; v < nv; ++v) { uptr[v + 1] += uptr[v]; fptr[v + 1] += fptr[v]; }
+        {
+            std::vector<int32_t> fill(fptr.begin(), fptr.end() - 1);
+            for (int64_t e = 0; e < ne_; ++e) {   // sorted keys keep every row sorted
+                const int64_t a = key[e] / nv, b = key[e] % nv;
+                fcol[fill[b]++] = (int32_t)a;
+            }
+            for (int64_t e = 0; e < ne_; ++e) {
+                const int64_t a = key[e] / nv, b = key[e] % nv;
+                fcol[fill[a]++] = (int32_t)b;
+            }
+        }
+        key.clear();
+        key.shrink_to_fit();
+        TilePlan ut = build_tiles(uptr, nv);
+        TilePlan ft = build_tiles(fptr, nv);
+        auto up = [&](DevBuf &b, const void *src, size_t bytes) {
+            b.alloc(bytes);
+            if (bytes) HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        up(uptr_, uptr.data(), uptr.size() * 4);
+        up(ucol_, ucol.data(), ucol.size() * 4);
+        up(fptr_, fptr.data(), fptr.size() * 4);
+        up(fcol_, fcol.data(), fcol.size() * 4);
+        up(utiles_, ut.tiles.data(), ut.tiles.size() * sizeof(Tile));
+        up(ftiles_, ft.tiles.data(), ft.tiles.size() * sizeof(Tile));
+        up(flfirst_, ft.lfirst.data(), ft.lfirst.size() * 4);
+        up(flcount_, ft.lcount.data(), ft.lcount.size() * 4);
+        fltick_.alloc(std::max<size_t>(ft.lfirst.size(), 1) * 4);
+        HIP_OK(hipMemset(fltick_.p, 0, fltick_.bytes));
+        flpart_.alloc(std::max<int32_t>(ft.nslots, 1) * sizeof(T));
+        xd_.alloc(nv * sizeof(XD<T>));
+        xbest_.alloc(nv * sizeof(XD<T>));
+        h_.alloc(nv * sizeof(T));
+        HIP_OK(hipMemset(xd_.p, 0, xd_.bytes));
+        partials_.alloc((size_t)GRID_MAX * QMAX * 8);
+        gpart_.alloc((size_t)(GRID_MAX / 32 + 1) * QMAX * 8);
+        tickets_.alloc((size_t)(GRID_MAX / 32 + 2) * 4);
+        HIP_OK(hipMemset(tickets_.p, 0, tickets_.bytes));
+
+        vd_ = VcDev<T>{};
+        vd_.nv = (int32_t)nv; vd_.ne = (int32_t)ne_;
+        vd_.uptr = uptr_.as<int32_t>(); vd_.ucol = ucol_.as<int32_t>();
+        vd_.utiles = utiles_.as<Tile>(); vd_.nutiles = (int32_t)ut.tiles.size();
+        vd_.fptr = fptr_.as<int32_t>(); vd_.fcol = fcol_.as<int32_t>();
+        vd_.ftiles = ftiles_.as<Tile>(); vd_.nftiles = (int32_t)ft.tiles.size();
+        vd_.flfirst = flfirst_.as<int32_t>(); vd_.flcount = flcount_.as<int32_t>();
+        vd_.fltick = fltick_.as<unsigned>(); vd_.flpart = flpart_.as<T>();
+        vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>();
+        vd_.h_dbg = nullptr; vd_.forced = nullptr;
+        auto clampg = [](int64_t items, int64_t per) {
+            int64_t g = (items + per - 1) / per;
+            return (int)std::max<int64_t>(1, std::min<int64_t>(g, GRID_MAX));
+        };
+        L_.grid_v = clampg(nv, BLOCK * 2);
+        L_.grid_ftile = clampg((int64_t)ft.tiles.size(), 1);
+        L_.grid_utile = clampg((int64_t)ut.tiles.size(), 1);
+        L_.partials = partials_.as<double>();
+        L_.gpart = gpart_.as<double>();
+        L_.tickets = tickets_.as<unsigned>();
+    }
+
+    int64_t n() const override { return nv_; }
+    int64_t mP() const override { return 1; }
+    int64_t mC() const override { return ne_; }
+    Ctl *ctl() const { return s_.ctl_buf.as<Ctl>(); }
+
+    void probe_init(bool have_x0) override { vc_init<T>(vd_, ctl(), L_, s_.stream, have_x0); }
+
+    void upload_x(const double *host_x) override
+    {
+        DevBuf tmp;
+        tmp.alloc(nv_ * 8);
+        HIP_OK(hipMemcpyAsync(tmp.p, host_x, nv_ * 8, hipMemcpyHostToDevice, s_.stream));
+        vc_import_x<T>(vd_, tmp.as<double>(), s_.stream);
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    void iterations(int slots) override
+    {
+        for (int i = 0; i < slots; ++i) vc_iteration<T>(vd_, ctl(), L_, s_.stream);
+    }
+
+    void final_stats() override { vc_init<T>(vd_, ctl(), L_, s_.stream, true); }
+
+    void save_best() override
+    {
+        HIP_OK(hipMemcpyAsync(xbest_.p, xd_.p, xd_.bytes, hipMemcpyDeviceToDevice, s_.stream));
+    }
+
+    void best_to_host(double *out) override
+    {
+        VcDev<T> b = vd_;
+        b.xd = xbest_.as<XD<T>>();
+        export_to_host(b, 0, nv_, out);
+    }
+
+    void read(int which, double *out, int64_t len) override
+    {
+        switch (which) {
+        case 0: need(len, nv_); export_to_host(vd_, 0, nv_, out); return;
+        case 1: need(len, nv_); export_to_host(vd_, 1, nv_, out); return;
+        case 2: {
+            need(len, nv_);
+            Ctl c = pull();
+            std::fill(out, out + nv_, c.sP);
+            return;
+        }
+        case 3:
+            need(len, nv_);
+            if (!hdbg_.p) throw ApiError{MWU_ERR_STATE, "h is recorded by mwu_probe_direction"};
+            HIP_OK(hipMemcpyAsync(out, hdbg_.p, nv_ * 8, hipMemcpyDeviceToHost, s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            return;
+        case 4: need(len, 1); out[0] = pull().y1; return;
+        case 6: need(len, 1); out[0] = pull().dy1; return;
+        case 5: need(len, ne_); export_to_host(vd_, 2, ne_, out); return;
+        case 7: need(len, ne_); export_to_host(vd_, 3, ne_, out); return;
+        }
+        throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
+    }
+
+    void row_pass() override { vc_passA<T>(dbg(), ctl(), L_, s_.stream); }
+    void col_pass() override { vc_passB<T>(dbg(), ctl(), L_, s_.stream); }
+    void fwd_pass() override {}
+    void search_pass() override { vc_search<T>(dbg(), ctl(), L_, s_.stream); }
+
+    void set_debug(bool on) override
+    {
+        if (on && !hdbg_.p) hdbg_.alloc(nv_ * 8);
+        debug_ = on;
+    }
+
+    void set_forced(const double *host, int count) override
+    {
+        if (count > 0) {
+            forced_.alloc((size_t)count * 8);
+            HIP_OK(hipMemcpy(forced_.p, host, (size_t)count * 8, hipMemcpyHostToDevice));
+            vd_.forced = forced_.as<double>();
+        } else {
+            vd_.forced = nullptr;
+        }
+        s_.graph_slots = -1;
+    }
+
+    void potential(const double *, double *, double, double *, hipStream_t) override
+    {
+        throw ApiError{MWU_ERR_STATE, "potential is provided by the generic engine (MWU_FLAG_GENERIC)"};
+    }
+
+    double algo_bytes(int which) const override
+    {
+        const double t = sizeof(T), V = (double)nv_, E = (double)ne_;
+        switch (which) {
+        case 0: return 4.0 * (V + 1) + 8.0 * E + 2.0 * t * V + t * V;   // fptr, fcol, xd, h
+        case 1: return 4.0 * t * V + t * V;                           // xd read+write, h
+        case 3: return 4.0 * (V + 1) + 4.0 * E + 2.0 * t * V;           // uptr, ucol, xd
+        }
+        return 0.0;
+    }
+    double pass_nnz(int which) const override
+    {
+        return which == 0 ? 2.0 * (double)ne_ : which == 3 ? (double)ne_ : 0.0;
+    }
+
+  private:
+    VcDev<T> dbg() const
+    {
+        VcDev<T> v = vd_;
+        if (debug_) v.h_dbg = hdbg_.as<double>();
+        return v;
+    }
+    static void need(int64_t len, int64_t want)
+    {
+        if (len != want) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
+    }
+    Ctl pull()
+    {
+        Ctl c;
+        HIP_OK(hipMemcpyAsync(&c, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        return c;
+    }
+    void export_to_host(const VcDev<T> &v, int which, int64_t len, double *out)
+    {
+        DevBuf tmp;
+        tmp.alloc(len * 8);
+        vc_export<T>(v, which, tmp.as<double>(), s_.stream);
+        HIP_OK(hipMemcpyAsync(out, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    Solver &s_;
+    int64_t nv_ = 0, ne_ = 0;
+    bool debug_ = false;
+    VcDev<T> vd_{};
+    VcLaunch L_{};
+    DevBuf uptr_, ucol_, fptr_, fcol_, utiles_, ftiles_, flfirst_, flcount_, fltick_, flpart_;
+    DevBuf xd_, xbest_, h_, partials_, gpart_, tickets_, forced_, hdbg_;
+};
+
+std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,
+                                             const std::vector<int64_t> &newid, int64_t nv)
+{
+    if (s.fp32) return std::unique_ptr<Program>(new VcoverProgram<float>(s, el, newid, nv));
+    return std::unique_ptr<Program>(new VcoverProgram<double>(s, el, newid, nv));
+}
+
+}  // namespace mwu

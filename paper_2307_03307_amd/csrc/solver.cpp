@@ -374,7 +374,14 @@ static void build(Solver &s, const mwu_problem &p)
         }
     }
     setup_device(s);
-    s.prog = make_generic_program(s, s.onesP ? nullptr : &P, s.onesC ? nullptr : &C);
+    const bool fused_vc = p.form == MWU_COVERING && p.C.kind == MWU_MAT_INCIDENCE_T && !p.b_C && !p.c &&
+                          !(s.opt.flags & MWU_FLAG_GENERIC);
+    if (fused_vc) {
+        C = HostCSR();
+        s.prog = make_vcover_program(s, elC, newid, kept);
+    } else {
+        s.prog = make_generic_program(s, s.onesP ? nullptr : &P, s.onesC ? nullptr : &C);
+    }
 }
 
 // ------------------------------------------------------------ probes
@@ -419,6 +426,9 @@ static void begin_probe(Solver &s, double param, const double *x0)
     c.max_iter = s.opt.max_iter;
     c.pack_bound = INFINITY;
     c.cover_bound = 0.0;
+    if (!s.trace_buf.p) s.trace_buf.alloc((size_t)s.opt.max_iter * 8);
+    c.trace = s.trace_buf.as<double>();
+    c.trace_cap = s.opt.max_iter;
     c.status = ST_RUNNING;
     c.phase = PH_IDLE;
     push_ctl(s);
@@ -776,7 +786,18 @@ mwu_status mwu_probe_read(void *h, int32_t which, double *out, int64_t len)
 {
     if (!h || !out) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
-    return run_guarded([&] { s.prog->read(which, out, len); });
+    return run_guarded([&] {
+        if (which == 8) {   // accepted steps of the current probe
+            pull_ctl(s);
+            if (len != s.ctl_host->iter) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
+            if (len > 0) {
+                HIP_OK(hipMemcpyAsync(out, s.trace_buf.p, (size_t)len * 8, hipMemcpyDeviceToHost, s.stream));
+                HIP_OK(hipStreamSynchronize(s.stream));
+            }
+            return;
+        }
+        s.prog->read(which, out, len);
+    });
 }
 
 mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, double *psi,
@@ -819,6 +840,62 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
         }
         s.ctl_host->eval_mode = 0;
         s.ctl_host->phase = PH_IDLE;
+        push_ctl(s);
+        HIP_OK(hipStreamSynchronize(s.stream));
+    });
+}
+
+mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, double *bytes,
+                         double *nnz)
+{
+    if (!h || which < 0 || which > 3 || reps < 1 || !avg_us) return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (!s.in_probe) return MWU_ERR_STATE;
+    return run_guarded([&] {
+        HIP_OK(hipSetDevice(s.opt.device));
+        pull_ctl(s);
+        if (s.ctl_host->phase != PH_ROW) throw ApiError{MWU_ERR_STATE, "probe is not at an iteration start"};
+        const Ctl saved = *s.ctl_host;
+        // one direction so that d, Pd, Cd are those of a real iteration
+        s.ctl_host->eval_mode = 1;
+        push_ctl(s);
+        s.prog->row_pass();
+        s.prog->col_pass();
+        s.prog->fwd_pass();
+        pull_ctl(s);
+        Ctl &c = *s.ctl_host;
+        c.eval_mode = 0;
+        static const int phase_of[4] = {PH_ROW, PH_COL, PH_FWD, PH_SEARCH};
+        c.hold = phase_of[which];
+        c.phase = phase_of[which];
+        c.alpha = 0.0;
+        c.skind = SK_EXP;
+        c.ncand = KC;
+        for (int k = 0; k < KC; ++k) c.cand[k] = std::ldexp(1.0, k);
+        c.ga0 = 1.0;
+        push_ctl(s);
+        auto launch = [&] {
+            if (which == 0) s.prog->row_pass();
+            else if (which == 1) s.prog->col_pass();
+            else if (which == 2) s.prog->fwd_pass();
+            else s.prog->search_pass();
+        };
+        launch();   // warm caches
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        HIP_OK(hipEventRecord(e0, s.stream));
+        for (int r = 0; r < reps; ++r) launch();
+        HIP_OK(hipEventRecord(e1, s.stream));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_us = 1000.0 * ms / reps;
+        if (bytes) *bytes = s.prog->algo_bytes(which);
+        if (nnz) *nnz = s.prog->pass_nnz(which);
+        *s.ctl_host = saved;   // the probe continues from where it was
         push_ctl(s);
         HIP_OK(hipStreamSynchronize(s.stream));
     });

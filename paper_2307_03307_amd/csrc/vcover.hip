@@ -1,0 +1,481 @@
+// Fused vertex-cover program (gfx950): min 1^T x s.t. M^T x >= 1 (Section 3),
+// run as the mixed problem with the objective row (1/M) 1^T x <= 1 (end of
+// Section 2.2) and Algorithm 2 / Algorithm 3 (Section 4).
+//
+// The covering rows are the edges: z_e = x_u + x_v, dz_e = d_u + d_v and the
+// weights u_e = exp(-eta (z_e - L)) are recomputed from the vertex vectors in
+// every pass instead of being stored, so a pass reads only the adjacency
+// indices from HBM (the vertex vectors stay in the caches).  Per iteration:
+//   pass A  (full adjacency, one segment per vertex) h_v = sum_{w ~ v} u_vw
+//           at x + a d, min z, sum u: the transpose product C^T u fused with
+//           the weights and the LSE totals;
+//   pass B  (vertices) commit x += a d, direction d_v = (1/eta) max(0, 1 -
+//           g/h_v) x_v with g = 1/M, sum d (= M * Pd);
+//   search  (upper adjacency, one visit per edge) the K-candidate sums of
+//           Phi, with the forward product C d formed on the fly.
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace mwu {
+
+// Multi-segment tile where each term depends on its segment: stage(k) is
+// staged through LDS with coalesced loads, then term(seg_value, staged)
+// is accumulated per segment and epi(seg, sum) called once per segment.
+template <class S, class Acc, class StageF, class SegF, class TermF, class EpiF>
+MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, StageF &stage, SegF &segval,
+                           TermF &term, EpiF &epi, S *s_val, int32_t *s_ptr, int32_t *s_tseg,
+                           Acc *s_tacc)
+{
+    const int tid = threadIdx.x;
+    const int S_ = tl.s1 - tl.s0;
+    const int base = tl.k0;
+    const int N = tl.k1 - tl.k0;
+    for (int i = tid; i <= S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int k = j * BLOCK + tid;
+        if (k < N) s_val[pad_idx(k)] = stage(base + k);
+    }
+    __syncthreads();
+    const int a = tid * ITEMS;
+    const int b = min(a + ITEMS, N);
+    int pend = -1, tseg = -1;
+    Acc pacc = acc_zero<Acc>(), tacc = acc_zero<Acc>();
+    if (a < N) {
+        int lo = 0, hi = S_;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_ptr[mid] <= a) lo = mid; else hi = mid;
+        }
+        int s = lo;
+        bool started = (s_ptr[s] == a);
+        int end = s_ptr[s + 1];
+        auto sv = segval(tl.s0 + s);
+        Acc acc = acc_zero<Acc>();
+        for (int k = a; k < b; ++k) {
+            if (k >= end) {
+                if (started) epi(tl.s0 + s, acc);
+                else { pend = s; pacc = acc; }
+                do { ++s; end = s_ptr[s + 1]; } while (k >= end);   // empty segments: separate pass
+                started = true;
+                acc = acc_zero<Acc>();
+                sv = segval(tl.s0 + s);
+            }
+            acc += term(sv, s_val[pad_idx(k)]);
+        }
+        if (end <= b) {
+            if (started) epi(tl.s0 + s, acc);
+            else { pend = s; pacc = acc; }
+        } else {
+            tseg = s;
+            tacc = acc;
+        }
+    }
+    s_tseg[tid] = tseg;
+    s_tacc[tid] = tacc;
+    __syncthreads();
+    if (pend >= 0) {
+        Acc tot = pacc;
+        for (int t = tid - 1; t >= 0 && s_tseg[t] == pend; --t) tot += s_tacc[t];
+        epi(tl.s0 + pend, tot);
+    }
+    for (int s = tid; s < S_; s += BLOCK)
+        if (s_ptr[s] == s_ptr[s + 1]) epi(tl.s0 + s, acc_zero<Acc>());
+    __syncthreads();
+}
+
+// Visit every nonzero of a tile with its segment: visit(seg_value, staged).
+template <class S, class StageF, class SegF, class VisitF>
+MWU_DEV void walk_tile(const Tile &tl, const int32_t *__restrict__ ptr, StageF &stage, SegF &segval,
+                       VisitF &visit, S *s_val, int32_t *s_ptr)
+{
+    const int tid = threadIdx.x;
+    if (tl.lid >= 0) {   // chunk of one long segment
+        auto sv = segval(tl.s0);
+        for (int k = tl.k0 + tid; k < tl.k1; k += BLOCK) visit(sv, stage(k), k);
+        return;
+    }
+    const int S_ = tl.s1 - tl.s0;
+    const int base = tl.k0;
+    const int N = tl.k1 - tl.k0;
+    for (int i = tid; i <= S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int k = j * BLOCK + tid;
+        if (k < N) s_val[pad_idx(k)] = stage(base + k);
+    }
+    __syncthreads();
+    const int a = tid * ITEMS;
+    const int b = min(a + ITEMS, N);
+    if (a < N) {
+        int lo = 0, hi = S_;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_ptr[mid] <= a) lo = mid; else hi = mid;
+        }
+        int s = lo;
+        int end = s_ptr[s + 1];
+        auto sv = segval(tl.s0 + s);
+        for (int k = a; k < b; ++k) {
+            if (k >= end) {
+                do { ++s; end = s_ptr[s + 1]; } while (k >= end);
+                sv = segval(tl.s0 + s);
+            }
+            visit(sv, s_val[pad_idx(k)], base + k);
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ finishers
+
+MWU_DEV void finish_vc_start(Ctl *c, const double *rec)
+{
+    // rec: [- | min z]
+    c->zmin = rec[1];
+    c->ymax = c->y1;
+    c->LP = c->y1;
+    c->LC = c->zmin;        // first shift; pass A makes it the exact smin
+    c->alpha = 0.0;
+    c->status = ST_RUNNING;
+    c->phase = PH_ROW;
+}
+
+MWU_DEV void finish_vcA(Ctl *c, const double *rec)
+{
+    // rec: [sum_v h_v (= 2 sum_e u_e) | min z]
+    if (held(c)) return;
+    const double a = c->alpha;
+    c->y1 += a * c->dy1;
+    c->LP = c->y1;
+    c->ymax = c->y1;
+    c->invSw = 1.0;
+    const double su = 0.5 * rec[0];
+    const bool bad = !(su > 0.0) || !isfinite(su);
+    c->LCw = c->LC;
+    c->LC = c->LCw - log(su) / c->eta;
+    c->invSu = 1.0 / su;
+    c->zmin = rec[1];
+    if (c->eval_mode) { c->phase = PH_COL; return; }
+    if (bad) { c->status = ST_NUMERIC; c->phase = PH_COMMIT; return; }
+    if (c->zmin >= 1.0) { c->status = ST_FEASIBLE; c->phase = PH_COMMIT; }
+    else if (c->iter >= c->max_iter) { c->status = ST_MAX_ITER; c->phase = PH_COMMIT; }
+    else c->phase = PH_COL;
+}
+
+MWU_DEV void finish_vcB(Ctl *c, const double *rec, const double *forced)
+{
+    // rec: [sum d | max d | max h]
+    if (held(c)) return;
+    c->alpha = 0.0;
+    c->dsum = rec[0];
+    c->dmax = rec[1];
+    c->hmax = rec[2];
+    c->gmin = c->sP;
+    if (c->hmax > 0.0 && 1.0 / c->hmax > c->cover_bound) c->cover_bound = 1.0 / c->hmax;
+    if (1.0 / c->sP < c->pack_bound) c->pack_bound = 1.0 / c->sP;
+    c->dy1 = c->sP * c->dsum;
+    c->dz1 = 0.0;
+    c->dymax = 0.0;
+    if (!c->eval_mode && !(c->dmax > 0.0)) { c->status = ST_INFEASIBLE; c->phase = PH_DONE; return; }
+    begin_search(c, forced);
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_init_x(VcDev<T> vd, Ctl *ctl, int have_x0, double *part,
+                                                    double *gpart, unsigned *tick)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const double eps = ctl->eps, sP = ctl->sP;
+    double v[1] = {0.0};
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
+        XD<T> p = vd.xd[i];
+        if (!have_x0) p.x = (T)(eps / ((double)vd.nv * sP));   // Algorithm 1 with P = (1/M) 1^T
+        p.d = T(0);
+        vd.xd[i] = p;
+        v[0] += (double)p.x;
+    }
+    const Red red{1, 0, 0};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+        ctl->sumx = s_rec[0];
+        ctl->y1 = ctl->sP * s_rec[0];
+        ctl->dy1 = 0.0;
+    }
+}
+
+// min over edges of x_u + x_w: the first LSE shift of a probe, and the final
+// min(Cx) of the outer search.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_minz(VcDev<T> vd, Ctl *ctl, double *part, double *gpart,
+                                                  unsigned *tick)
+{
+    __shared__ T s_val[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    double v[2] = {0.0, INFINITY};
+    auto stage = [&](int k) -> T { return vd.xd[vd.ucol[k]].x; };
+    auto segval = [&](int u) -> T { return vd.xd[u].x; };
+    auto visit = [&](T xu, T xw, int) { v[1] = fmin(v[1], (double)xu + (double)xw); };   // FP64 certificate
+    for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
+        const Tile tl = vd.utiles[t];
+        walk_tile<T>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
+    }
+    const Red red{1, 1, 0};
+    block_combine<2>(v, red, 0, s_wave, s_rec);
+    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_vc_start(ctl, s_rec);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, double *part, double *gpart,
+                                                     unsigned *tick)
+{
+    __shared__ T s_val[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ int32_t s_tseg[BLOCK];
+    __shared__ T s_tacc[BLOCK];
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_ROW) return;
+    const T a = (T)ctl->alpha;
+    const double eta = ctl->eta, Lw = ctl->LC;
+    double v[2] = {0.0, INFINITY};   // sum h | min z
+    auto stage = [&](int k) -> T {
+        const XD<T> p = vd.xd[vd.fcol[k]];
+        return p.x + a * p.d;
+    };
+    auto segval = [&](int u) -> T {
+        const XD<T> p = vd.xd[u];
+        return p.x + a * p.d;
+    };
+    auto term = [&](T xu, T xw) -> T {
+        const T z = xu + xw;
+        v[1] = fmin(v[1], (double)z);
+        return exp_t((T)(-eta * ((double)z - Lw)));
+    };
+    auto epi = [&](int u, T acc) {
+        vd.h[u] = acc;
+        v[0] += (double)acc;
+    };
+    for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
+        const Tile tl = vd.ftiles[t];
+        if (tl.lid < 0) {
+            seg_tile_rows<T, T>(tl, vd.fptr, stage, segval, term, epi, s_val, s_ptr, s_tseg, s_tacc);
+        } else {
+            const T xu = segval(tl.s0);
+            auto elem = [&](int k) -> T { return term(xu, stage(k)); };
+            chunk_tile<T>(tl, elem, epi, s_tacc, vd.flpart, vd.flfirst, vd.flcount, vd.fltick);
+        }
+    }
+    const Red red{1, 1, 0};
+    block_combine<2>(v, red, 0, s_wave, s_rec);
+    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_vcA(ctl, s_rec);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, double *part, double *gpart,
+                                                     unsigned *tick)
+{
+    __shared__ double s_wave[4 * 3];
+    __shared__ double s_rec[QMAX];
+    const int ph = ctl->phase;
+    if (ph != PH_COL && ph != PH_COMMIT) return;
+    const T a = (T)ctl->alpha;
+    const double invSu = ctl->invSu, g = ctl->sP, step = ctl->step;
+    const bool commit = ph == PH_COMMIT;
+    double v[3] = {0.0, -INFINITY, -INFINITY};   // sum d | max d | max h
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
+        XD<T> p = vd.xd[i];
+        p.x = p.x + a * p.d;
+        if (!commit) {
+            const double h = (double)vd.h[i] * invSu;
+            double di = 0.0;
+            if (h > 0.0) {
+                const double q = 1.0 - g / h;
+                if (q > 0.0) di = step * q * (double)p.x;
+            }
+            p.d = (T)di;
+            v[0] += (double)p.d;
+            v[1] = fmax(v[1], (double)p.d);
+            v[2] = fmax(v[2], h);
+            if (vd.h_dbg) vd.h_dbg[i] = h;
+        }
+        vd.xd[i] = p;
+    }
+    const Red red{1, 0, 2};
+    block_combine<3>(v, red, 0, s_wave, s_rec);
+    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+        if (commit) { ctl->alpha = 0.0; ctl->phase = PH_DONE; }
+        else finish_vcB(ctl, s_rec, vd.forced);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part,
+                                                      double *gpart, unsigned *tick)
+{
+    __shared__ XD<T> s_val[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ double s_wave[4 * 3 * KC];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_SEARCH) return;
+    const int kind = ctl->skind;
+    const double eta = ctl->eta;
+    auto stage = [&](int k) -> XD<T> { return vd.xd[vd.ucol[k]]; };
+    auto segval = [&](int u) -> XD<T> { return vd.xd[u]; };
+    if (kind == SK_REFINE) {
+        const double a = ctl->ref_alpha;
+        const bool second = ctl->ref_valid != 0;
+        const double zm = ctl->rfZmin;
+        double v[2] = {0.0, INFINITY};   // pass 2: [- | sum]; pass 1: [- | min z']
+        auto visit = [&](XD<T> pu, XD<T> pw, int) {
+            const double zp = (double)(pu.x + pw.x) + a * (double)(pu.d + pw.d);
+            if (second) v[0] += exp(-eta * (zp - zm));
+            else v[1] = fmin(v[1], zp);
+        };
+        for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
+            const Tile tl = vd.utiles[t];
+            walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
+        }
+        const Red red{1, 1, 0};
+        block_combine<2>(v, red, 0, s_wave, s_rec);
+        if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+            // records expected by finish_search: pass 1 [min z' | max eta*y'], pass 2 [sumP | sumC]
+            double r[2];
+            if (!second) { r[0] = s_rec[1]; r[1] = -INFINITY; }
+            else { r[0] = 1.0; r[1] = s_rec[0]; }
+            finish_search(ctl, r);
+        }
+        return;
+    }
+    const int nc = ctl->ncand;
+    double cd[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) cd[k] = ctl->cand[k];
+    const double gdel = ctl->gdelta, Lw = ctl->LCw;
+    double acc[3 * KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) { acc[k] = 0.0; acc[KC + k] = 0.0; acc[2 * KC + k] = INFINITY; }
+    auto visit = [&](XD<T> pu, XD<T> pw, int) {
+        const T z = pu.x + pw.x;
+        const T dz = pu.d + pw.d;
+        const T u = exp_t((T)(-eta * ((double)z - Lw)));
+        cov_row_terms<T>(kind, nc, cd, gdel, eta, u, z, dz, acc);
+    };
+    for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
+        const Tile tl = vd.utiles[t];
+        walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
+    }
+    if (threadIdx.x < KC) s_rec[threadIdx.x] = 0.0;   // no packing rows
+    const Red redc{3 * KC, KC, 0};
+    block_combine<3 * KC>(acc, redc, KC, s_wave, s_rec + KC);
+    const Red red{3 * KC, KC, 0};
+    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_search(ctl, s_rec);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_export_k(VcDev<T> vd, int which, double *out)
+{
+    __shared__ XD<T> s_val[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    if (which < 2) {
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK)
+            out[i] = (double)(which == 0 ? vd.xd[i].x : vd.xd[i].d);
+        return;
+    }
+    auto stage = [&](int k) -> XD<T> { return vd.xd[vd.ucol[k]]; };
+    auto segval = [&](int u) -> XD<T> { return vd.xd[u]; };
+    auto visit = [&](XD<T> pu, XD<T> pw, int k) {
+        out[k] = which == 2 ? (double)(pu.x + pw.x) : (double)(pu.d + pw.d);
+    };
+    for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
+        const Tile tl = vd.utiles[t];
+        walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
+    }
+}
+
+template <class T>
+__global__ void vc_import_k(VcDev<T> vd, const double *src)
+{
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
+        XD<T> p;
+        p.x = (T)src[i];
+        p.d = T(0);
+        vd.xd[i] = p;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <class T>
+void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, bool have_x0)
+{
+    hipLaunchKernelGGL(vc_init_x<T>, dim3(L.grid_v), dim3(BLOCK), 0, st, v, ctl, have_x0 ? 1 : 0,
+                       L.partials, L.gpart, L.tickets);
+    hipLaunchKernelGGL(vc_minz<T>, dim3(L.grid_utile), dim3(BLOCK), 0, st, v, ctl, L.partials, L.gpart,
+                       L.tickets);
+}
+
+template <class T>
+void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(vc_passA_k<T>, dim3(L.grid_ftile), dim3(BLOCK), 0, st, v, ctl, L.partials,
+                       L.gpart, L.tickets);
+}
+
+template <class T>
+void vc_passB(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(vc_passB_k<T>, dim3(L.grid_v), dim3(BLOCK), 0, st, v, ctl, L.partials, L.gpart,
+                       L.tickets);
+}
+
+template <class T>
+void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(vc_search_k<T>, dim3(L.grid_utile), dim3(BLOCK), 0, st, v, ctl, L.partials,
+                       L.gpart, L.tickets);
+}
+
+template <class T>
+void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
+{
+    vc_passA(v, ctl, L, st);
+    vc_passB(v, ctl, L, st);
+    vc_search(v, ctl, L, st);
+    vc_search(v, ctl, L, st);
+}
+
+template <class T>
+void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st)
+{
+    const int g = which < 2 ? std::max(1, std::min(GRID_MAX, (v.nv + BLOCK - 1) / BLOCK))
+                            : std::max(1, std::min(GRID_MAX, v.nutiles));
+    hipLaunchKernelGGL(vc_export_k<T>, dim3(g), dim3(BLOCK), 0, st, v, which, out);
+}
+
+template <class T>
+void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st)
+{
+    const int g = std::max(1, std::min(GRID_MAX, (v.nv + BLOCK - 1) / BLOCK));
+    hipLaunchKernelGGL(vc_import_k<T>, dim3(g), dim3(BLOCK), 0, st, v, src);
+}
+
+#define MWU_VC_INSTANTIATE(T)                                                                    \
+    template void vc_init<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t, bool);      \
+    template void vc_iteration<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);       \
+    template void vc_passA<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);           \
+    template void vc_passB<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);           \
+    template void vc_search<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);          \
+    template void vc_export<T>(const VcDev<T> &, int, double *, hipStream_t);                    \
+    template void vc_import_x<T>(const VcDev<T> &, const double *, hipStream_t);
+
+MWU_VC_INSTANTIATE(float)
+MWU_VC_INSTANTIATE(double)
+
+}  // namespace mwu

@@ -1,0 +1,88 @@
+"""CPU checks of the C ABI: every declared symbol is exported, and invalid
+inputs are rejected with the documented error codes before any device work.
+A valid problem on a machine without a GPU fails loudly (MWU_ERR_DEVICE)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2307_03307_amd as mwu
+from paper_2307_03307_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mwu.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mwu_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_status_strings():
+    L = _lib.load()
+    assert L.mwu_status_string(0) == b"MWU_OK"
+    for code, name in _lib.ERRORS.items():
+        assert L.mwu_status_string(code).decode() == name
+
+
+def _code(fn):
+    with pytest.raises(mwu.MwuError) as e:
+        fn()
+    return e.value.code
+
+
+def test_invalid_graphs_rejected():
+    u = np.array([0, 1, 2], np.int32)
+    v = np.array([1, 2, 0], np.int32)
+    assert _code(lambda: mwu.bmatch(3, [0, 1], [1, 1])) == -5          # self-loop
+    assert _code(lambda: mwu.bmatch(3, [0, 1, 0], [1, 2, 1])) == -5    # duplicate edge
+    assert _code(lambda: mwu.bmatch(3, [0, 1, 2], [1, 2, 3])) == -5    # out of range
+    assert _code(lambda: mwu.vertex_cover(0, [], [])) == -1             # empty graph
+    assert _code(lambda: mwu.bmatch(3, u, v, eps=0.0)) == -1            # eps outside (0,1)
+    assert _code(lambda: mwu.bmatch(3, u, v, eps=1.5)) == -1
+
+
+def test_invalid_csr_rejected():
+    ptr = np.array([0, 2, 3], np.int64)
+    col = np.array([0, 1, 1], np.int32)
+    neg = mwu.csr_matrix(ptr, col, [1.0, -1.0, 2.0], shape=(2, 2))
+    nan = mwu.csr_matrix(ptr, col, [1.0, np.nan, 2.0], shape=(2, 2))
+    ok = mwu.csr_matrix(ptr, col, [1.0, 1.0, 2.0], shape=(2, 2))
+    assert _code(lambda: mwu.Solver(mwu.PACKING, P=neg)) == -2
+    assert _code(lambda: mwu.Solver(mwu.PACKING, P=nan)) == -3
+    assert _code(lambda: mwu.Solver(mwu.PACKING, P=ok, b_P=[1.0, 0.0])) == -4
+    assert _code(lambda: mwu.Solver(mwu.PACKING, P=ok, c=[1.0, -2.0])) == -4
+    bad_col = mwu.csr_matrix(ptr, np.array([0, 5, 1], np.int32), shape=(2, 2))
+    assert _code(lambda: mwu.Solver(mwu.PACKING, P=bad_col)) == -1
+    # a packing column with no nonzero makes the LP unbounded
+    empty_col = mwu.csr_matrix(np.array([0, 1, 2], np.int64), np.array([0, 0], np.int32), shape=(2, 3))
+    assert _code(lambda: mwu.Solver(mwu.PACKING, P=empty_col)) == -9
+    # a covering row with no nonzero can never be satisfied
+    empty_row = mwu.csr_matrix(np.array([0, 2, 2], np.int64), np.array([0, 1], np.int32), shape=(2, 2))
+    assert _code(lambda: mwu.Solver(mwu.COVERING, C=empty_row)) == -1
+
+
+def test_null_arguments():
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.mwu_create(None, None, ctypes.byref(h)) == -1
+    assert L.mwu_solve(None, None, None, None, None) == -1
+    L.mwu_destroy(None)   # NULL-safe
+
+
+def test_valid_problem_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _code(lambda: mwu.bmatch(4, [0, 1], [2, 3])) == -8

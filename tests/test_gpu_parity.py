@@ -1,0 +1,288 @@
+"""GPU parity against the CPU oracle, through the C ABI.
+
+Modes (oracle vs gfx950 library):
+  per-pass      identical x fed to both: y = Px, z = Cx, g, h, d, Pd, Cd and
+                Psi, Phi, min(z + a Cd) at candidate steps.  FP64 form: max
+                relative error <= 1e-9.  Mixed FP32/FP64 form: <= 5e-3 (the
+                weights carry eta * 2^-24 ~ 1e-4 relative error).
+  replay        the oracle is forced to the GPU's step sequence: FP64 final x
+                objective within 1e-9 (final x within 1e-6), mixed form final
+                objective within 1e-5.
+  free run      both solve; both certified within (1+eps) of the exact optimum
+                and within eps of each other.  Exact agreement is not a
+                property of the method: with steps of 1e3-1e4 the MWU map
+                amplifies last-bit differences about tenfold per iteration, so
+                two correct FP64 runs drift apart late in a long probe (the
+                replay tests bound this) and may then take different
+                decisions and probes.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2307_03307_amd as mwu
+
+from gpu_common import (EPS, bmatch_case, densest_case, domset_case, rel_err, start_point,
+                        vcover_case, weighted_packing_case)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+FP32_TOL = 5e-3
+EXP_ALPHAS = [float(2 ** k) for k in range(16)]
+LIST_ALPHAS = [0.37, 1.0, 3.5, 11.0, 70.0]
+
+
+def _cases():
+    bip = gg.bipartite_uniform(700, 650, 9000, seed=21)          # several tiles, ragged tail
+    gnm = gg.gnm_random(900, 7000, seed=22)
+    star = gg.star_graph(5000)
+    pl = gg.chung_lu(3000, 2.3, 8.0, seed=23)                     # power-law rows
+    return {
+        "bmatch": lambda: bmatch_case(bip),
+        "vcover": lambda: vcover_case(gnm),
+        "vcover-generic": lambda: vcover_case(gnm, generic=True),
+        "vcover-star": lambda: vcover_case(star, param=2.0),       # a row of 5000 > one tile
+        "domset": lambda: domset_case(pl),
+        "domset-star": lambda: domset_case(gg.star_graph(6000), param=3.0),
+        "densest": lambda: densest_case(gg.gnm_random(400, 3000, seed=24)),
+        "weighted": lambda: weighted_packing_case(),
+    }
+
+
+CASES = _cases()
+
+
+def _per_pass(case, precision, tol, seed=0, direction=True):
+    x0 = start_point(case, seed)
+    sP, sC = case.sP(case.param), case.sC(case.param)
+    ref = oracle.iteration_terms(case.P, sP, case.C, sC, EPS, x0,
+                                 alphas=EXP_ALPHAS)
+    ref_list = oracle.iteration_terms(case.P, sP, case.C, sC, EPS, x0, alphas=LIST_ALPHAS)
+    with case.make_gpu(precision=precision) as s:
+        sz = s.sizes()
+        assert sz.n == case.P.cols
+        assert sz.eta == pytest.approx(ref["eta"], rel=1e-15)
+        s.probe_begin(case.param, x0)
+        s.probe_direction()
+        got = {k: s.probe_read(k, n) for k, n in
+               (("x", sz.n), ("d", sz.n), ("g", sz.n), ("h", sz.n), ("y", sz.m_P),
+                ("z", sz.m_C), ("dy", sz.m_P), ("dz", sz.m_C))}
+        errs = {k: rel_err(got[k], ref[k]) for k in ("d", "g", "h", "y", "z", "dy", "dz")}
+        errs["x"] = rel_err(got["x"], x0)
+        psi, phi, zm = s.probe_eval_steps(EXP_ALPHAS)
+        psi2, phi2, zm2 = s.probe_eval_steps(LIST_ALPHAS)
+    for name, (a, b) in {"psi": (psi, ref["psi"]), "phi": (phi, ref["phi"]),
+                         "psi_list": (psi2, ref_list["psi"]), "phi_list": (phi2, ref_list["phi"])}.items():
+        errs[name] = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+    errs["zmin"] = rel_err(zm, ref["zmin_new"])
+    errs["zmin_list"] = rel_err(zm2, ref_list["zmin_new"])
+    if not direction:
+        # d, Pd, Cd and the step sums depend on coordinates whose weights lie
+        # below float range; their error is reported, not bounded
+        for k in ("d", "dy", "dz", "psi", "phi", "psi_list", "phi_list", "zmin", "zmin_list"):
+            errs.pop(k)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (case.name, bad)
+    return errs
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_per_pass_fp64(name):
+    _per_pass(CASES[name](), mwu.FP64, FP64_TOL)
+
+
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "vcover-star", "domset", "weighted"])
+def test_per_pass_mixed(name):
+    _per_pass(CASES[name](), mwu.MIXED_FP32_FP64, FP32_TOL)
+
+
+def test_per_pass_mixed_densest_weights():
+    """Generic engine on the densest-subgraph LP in the mixed form: both sides
+    are exponential weights, so coordinates whose weights underflow float get
+    d = 0; the weights, g and h themselves still match to float accuracy."""
+    _per_pass(CASES["densest"](), mwu.MIXED_FP32_FP64, FP32_TOL, direction=False)
+
+
+def _replay(case, precision):
+    sP, sC = case.sP(case.param), case.sC(case.param)
+    with case.make_gpu(precision=precision) as s:
+        s.probe_begin(case.param)
+        info = s.probe_run(5000)
+        alphas = s.probe_read("alpha", info.iterations)
+        xg = s.probe_read("x", s.sizes().n)
+    r = oracle.probe(case.P, sP, case.C, sC, EPS, forced_alpha=alphas)
+    return info, alphas, xg, r
+
+
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "domset", "densest", "weighted"])
+def test_decision_replay_fp64(name):
+    case = CASES[name]()
+    info, alphas, xg, r = _replay(case, mwu.FP64)
+    assert info.status == r.status
+    assert info.iterations == r.iterations
+    # per-iteration quantities agree to 1e-9 (per-pass tests); over a whole
+    # probe, steps of up to 1e5 amplify last-bit differences of coordinates
+    # with g_i/h_i near 1, so the iterate is held to 1e-6 and its objective to 1e-9
+    assert abs(xg.sum() - r.x.sum()) <= FP64_TOL * r.x.sum()
+    assert rel_err(xg, r.x) <= 1e-6
+    # free-running oracle takes the same decisions in FP64
+    sP, sC = case.sP(case.param), case.sC(case.param)
+    free = oracle.probe(case.P, sP, case.C, sC, EPS)
+    assert free.iterations == info.iterations and np.array_equal(free.alphas, alphas)
+
+
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "domset"])
+def test_decision_replay_mixed(name):
+    case = CASES[name]()
+    info, alphas, xg, r = _replay(case, mwu.MIXED_FP32_FP64)
+    assert info.status == r.status
+    assert abs(xg.sum() - r.x.sum()) <= 1e-5 * r.x.sum()
+
+
+def _opt_bmatch(g):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import maximum_bipartite_matching
+    B = sp.csr_matrix((np.ones(g.num_edges), (g.u, g.v - g.n_left)),
+                      shape=(g.n_left, g.num_vertices - g.n_left))
+    return int((maximum_bipartite_matching(B, perm_type="column") >= 0).sum())
+
+
+def _opt_vcover(g):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import maximum_bipartite_matching
+    n = g.num_vertices
+    r = np.concatenate([g.u, g.v])
+    c = np.concatenate([g.v, g.u])
+    B = sp.csr_matrix((np.ones(r.shape[0]), (r, c)), shape=(n, n))
+    return int((maximum_bipartite_matching(B, perm_type="column") >= 0).sum()) / 2.0
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+def test_solve_bmatch(precision):
+    g = gg.bipartite_uniform(2000, 2000, 20000, seed=1)   # the 2000+2000 / 20000 workload
+    opt = _opt_bmatch(g)
+    with mwu.bmatch(g.num_vertices, g.u, g.v, precision=precision) as s:
+        r = s.solve()
+    assert r.certified
+    assert r.lower <= opt <= r.upper * (1 + 1e-12)
+    assert opt / r.objective <= 1 + EPS
+    load = np.bincount(g.u, weights=r.x, minlength=g.num_vertices) + \
+        np.bincount(g.v, weights=r.x, minlength=g.num_vertices)
+    assert load.max() <= 1 + 1e-9 and r.x.min() >= 0
+    assert r.x.sum() == pytest.approx(r.objective, rel=1e-9)
+    if precision == mwu.FP64:
+        ro = oracle.solve_bmatch(g)
+        assert ro.certified and r.objective == pytest.approx(ro.objective, rel=EPS)
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+@pytest.mark.parametrize("generic", [False, True])
+def test_solve_vcover(precision, generic):
+    g = gg.rmat(13, 16, seed=2)                       # power-law, isolated vertices
+    opt = _opt_vcover(g)
+    flags = mwu._lib.FLAG_GENERIC if generic else 0
+    with mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, flags=flags) as s:
+        r = s.solve()
+    assert r.certified
+    assert r.lower <= opt * (1 + 1e-12) and opt <= r.upper * (1 + 1e-12)
+    assert r.objective / opt <= 1 + EPS
+    assert (r.x[g.u] + r.x[g.v]).min() >= 1 - 1e-9 and r.x.min() >= 0
+    deg = g.degrees()
+    assert np.all(r.x[deg == 0] == 0)
+    if precision == mwu.FP64:
+        ro = oracle.solve_vcover(g)
+        assert ro.certified and r.objective == pytest.approx(ro.objective, rel=EPS)
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+def test_solve_domset(precision):
+    from scipy.optimize import linprog
+    g = gg.chung_lu(400, 2.3, 6.0, seed=4)
+    ptr, col = gg.adjacency_csr(g, with_identity=True)
+    D = oracle.dominating_set_matrix(g).dense()
+    opt = linprog(np.ones(D.shape[1]), A_ub=-D, b_ub=-np.ones(D.shape[0]), bounds=(0, None)).fun
+    with mwu.dominating_set(ptr, col, g.num_vertices, precision=precision) as s:
+        r = s.solve()
+    assert r.certified
+    assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+    assert (D @ r.x).min() >= 1 - 1e-9
+    if precision == mwu.FP64:
+        ro = oracle.solve_domset(g)
+        assert ro.certified and r.objective == pytest.approx(ro.objective, rel=EPS)
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+def test_solve_densest(precision):
+    g = gg.gnm_random(16, 34, seed=5)
+    best = 0.0
+    for mask in range(1, 1 << 16):
+        S = np.array([(mask >> i) & 1 for i in range(16)], bool)
+        best = max(best, np.sum(S[g.u] & S[g.v]) / S.sum())
+    with mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision) as s:
+        r = s.solve()
+    assert r.certified
+    assert r.lower <= best * (1 + 1e-9) and best <= r.upper * (1 + 1e-9)
+    assert r.objective / best <= 1 + EPS
+    z = r.x
+    assert (z[0::2] + z[1::2]).min() >= 1 - 1e-9
+    load = np.bincount(g.u, weights=z[0::2], minlength=16) + np.bincount(g.v, weights=z[1::2], minlength=16)
+    assert load.max() == pytest.approx(r.objective, rel=1e-9)
+
+
+def test_solve_weighted_packing():
+    case = weighted_packing_case()
+    from scipy.optimize import linprog
+    lp = linprog(-case.c, A_ub=case.A, b_ub=case.b, bounds=(0, None))
+    with case.make_gpu(precision=mwu.FP64) as s:
+        r = s.solve()
+    assert r.certified
+    assert (case.A @ r.x <= case.b * (1 + 1e-9)).all()
+    assert -lp.fun / (case.c @ r.x) <= 1 + EPS + 1e-9
+    ro = oracle.solve_packing(case.P)
+    assert ro.certified and r.objective == pytest.approx(ro.objective, rel=EPS)
+
+
+def test_tiny_and_degenerate():
+    # one edge: matching 1, vertex cover 1
+    with mwu.bmatch(2, [0], [1], precision=mwu.FP64) as s:
+        r = s.solve()
+    assert r.certified and r.objective == pytest.approx(1.0, rel=0.1)
+    with mwu.vertex_cover(5, [3], [1], precision=mwu.FP64) as s:
+        r = s.solve()
+    assert r.certified and 1.0 <= r.objective <= 1.1
+    assert r.x[0] == r.x[2] == r.x[4] == 0.0
+    # an infeasible fixed-lambda probe reports INFEASIBLE
+    g = gg.complete_graph(6)
+    with mwu.densest_subgraph(6, g.u, g.v, precision=mwu.FP64, fixed_lambda=1.0) as s:
+        r = s.solve()
+    assert r.status == mwu.INFEASIBLE
+    with mwu.densest_subgraph(6, g.u, g.v, precision=mwu.FP64, fixed_lambda=4.0) as s:
+        r = s.solve()
+    assert r.status == mwu.CERTIFIED and r.objective <= 4.0 * (1 + EPS)
+
+
+def test_deterministic_rerun():
+    g = gg.rmat(12, 8, seed=6)
+    out = []
+    for _ in range(2):
+        with mwu.vertex_cover(g.num_vertices, g.u, g.v) as s:
+            out.append(s.solve())
+    assert out[0].objective == out[1].objective
+    assert np.array_equal(out[0].x, out[1].x)
+    assert out[0].total_iterations == out[1].total_iterations
+
+
+def test_max_iter_and_standard_step():
+    g = gg.bipartite_uniform(100, 100, 600, seed=7)
+    with mwu.bmatch(g.num_vertices, g.u, g.v, precision=mwu.FP64, max_iter=1, max_probes=3) as s:
+        r = s.solve()
+    assert r.status == mwu.FEASIBLE_UNCERTIFIED
+    case = bmatch_case(g, param=0.8 * _opt_bmatch(g))
+    with case.make_gpu(precision=mwu.FP64, step_rule=mwu.STEP_STD, max_iter=100000) as s:
+        s.probe_begin(case.param)
+        info = s.probe_run(100000)
+    ref = oracle.probe(case.P, 1.0, case.C, 1.0 / case.param, EPS, step_rule=oracle.STEP_STD,
+                       max_iter=100000)
+    assert info.status == ref.status and info.iterations == ref.iterations
