@@ -36,6 +36,14 @@
  *   R7  natural logarithm in eta = 10 ln(m) / eps.
  *   R8  Phi and Psi are evaluated in cancellation-free forms (below) that are
  *       exact identities of the Section 4.1 definitions.
+ *   R9  outer search over M (or D): geometric bisection of a search bracket
+ *       that moves to every probed value (feasible: upper end, infeasible:
+ *       lower end), kept apart from the certified bracket on OPT, which only
+ *       certificates move.  It stops when the certified bracket is within
+ *       1+eps, when the search bracket is within 1+eps/16, or at the probe cap.
+ *       Only an infeasible verdict (a dual certificate) moves the certified
+ *       bracket; a probe that hits the iteration cap moves the search bracket
+ *       and leaves the result uncertified.
  */
 #include <math.h>
 #include <stdint.h>
@@ -486,8 +494,9 @@ int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t ma
     double lo = sx / ymax;
     for (int64_t i = 0; i < n; ++i) x_best[i] = x[i] / ymax;
     int uncertified = 0;
-    while (r->probes < max_probes && hi > (1.0 + eps) * lo) {
-        double M = sqrt(lo * hi);
+    double slo = lo, shi = hi;   /* search bracket for M (R9) */
+    while (r->probes < max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+        double M = sqrt(slo * shi);
         orc_probe_result pr;
         rc = orc_probe(P, 1.0, &one.m, 1.0 / M, eps, max_iter, step_rule, 0, x,
                        NULL, 0, NULL, 0, &pr);
@@ -506,10 +515,14 @@ int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t ma
                 lo = sx / ymax;
                 for (int64_t i = 0; i < n; ++i) x_best[i] = x[i] / ymax;
             }
+            slo = M;
         } else {
-            if (M < hi) hi = M;
+            if (pr.status == ORC_INFEASIBLE && M < hi) hi = M;
+            shi = M;
             if (pr.status == ORC_MAX_ITER) uncertified = 1;
         }
+        if (lo > slo) slo = lo;
+        if (hi < shi) shi = hi;
     }
     r->lower = lo; r->upper = hi; r->objective = lo;
     r->status = (hi <= (1.0 + eps) * lo && !uncertified) ? 0 : 1;
@@ -559,8 +572,9 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
     double hi = 0.0;
     for (int64_t i = 0; i < n; ++i) { hi += x[i]; x_best[i] = x[i]; }
     int uncertified = 0;
-    while (r->probes < max_probes && hi > (1.0 + eps) * lo) {
-        double M = sqrt(lo * hi);
+    double slo = lo, shi = hi;   /* search bracket for M (R9) */
+    while (r->probes < max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+        double M = sqrt(slo * shi);
         orc_probe_result pr;
         rc = orc_probe(&one.m, 1.0 / M, C, 1.0, eps, max_iter, step_rule, 0, x,
                        NULL, 0, NULL, 0, &pr);
@@ -579,10 +593,14 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
                 hi = sx / zmin;
                 for (int64_t i = 0; i < n; ++i) x_best[i] = x[i] / zmin;
             }
+            shi = M;
         } else {
-            if (M > lo) lo = M;
+            if (pr.status == ORC_INFEASIBLE && M > lo) lo = M;
+            slo = M;
             if (pr.status == ORC_MAX_ITER) uncertified = 1;
         }
+        if (lo > slo) slo = lo;
+        if (hi < shi) shi = hi;
     }
     r->lower = lo; r->upper = hi; r->objective = hi;
     r->status = (hi <= (1.0 + eps) * lo && !uncertified) ? 0 : 1;
@@ -658,8 +676,9 @@ int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, con
     for (int64_t v = 0; v < nv; ++v) if (load[v] > hi) hi = load[v];
     double lo = (double)ne / (double)nv;
     int uncertified = 0;
-    while (r->probes < max_probes && hi > (1.0 + eps) * lo) {
-        double D = sqrt(lo * hi);
+    double slo = lo, shi = hi;   /* search bracket for D (R9) */
+    while (r->probes < max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+        double D = sqrt(slo * shi);
         orc_probe_result pr;
         rc = orc_probe(O, 1.0 / D, W, 1.0, eps, max_iter, step_rule, 0, z,
                        NULL, 0, NULL, 0, &pr);
@@ -680,10 +699,14 @@ int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, con
                 hi = lmax / cmin;
                 for (int64_t i = 0; i < n; ++i) z_best[i] = z[i] / cmin;
             }
+            shi = D;
         } else {
-            if (D > lo) lo = D;
+            if (pr.status == ORC_INFEASIBLE && D > lo) lo = D;
+            slo = D;
             if (pr.status == ORC_MAX_ITER) uncertified = 1;
         }
+        if (lo > slo) slo = lo;
+        if (hi < shi) shi = hi;
     }
     r->lower = lo; r->upper = hi; r->objective = hi;
     r->status = (hi <= (1.0 + eps) * lo && !uncertified) ? 0 : 1;

@@ -62,66 +62,32 @@ MWU_DEV void block_combine(const double (&v)[Q], Red r, int qoff, double *s_wave
     __syncthreads();
 }
 
-MWU_DEV void st_agent(double *p, double v)
+// Cross-workgroup reduction without fences or atomics.  Every workgroup of a
+// pass stores its record (plain stores) in partials[blockIdx.x]; the one-
+// workgroup finisher kernel launched right after the pass folds the records
+// in block order.  The kernel boundary makes the stores visible, so the hot
+// kernels never write back or invalidate the L2 (an agent-scope fence on
+// gfx950 does both, and throws away the cached vertex vectors).
+MWU_DEV void store_record(const double *s_rec, int Q, double *partials)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-MWU_DEV double ld_agent(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < Q) partials[(size_t)blockIdx.x * QMAX + threadIdx.x] = s_rec[threadIdx.x];
 }
 
-constexpr int RGROUP = 32;   // blocks per first-level reduction group
-
-// Grid-wide reduction of the block records s_rec[0..Q) (LDS).  Every block
-// publishes its record; the last block of each group of RGROUP folds the
-// group in block order; the last group folds the groups in order.  Returns
-// true in exactly one block, with the grid result in s_rec.  Counters are
-// reset by their last user, so the kernel can be replayed (graphs) without
-// any clearing.  tick: 1 + ceil(gridDim/RGROUP) counters.
-MWU_DEV bool grid_reduce(double *s_rec, Red r, double *partials, double *gpart, unsigned *tick)
+// Fold the G records of a pass (finisher kernel, one workgroup): thread t
+// folds records t, t + BLOCK, ... in order, then the block combines.  Record
+// entry q is reduced with the operation of layout position q + qoff.
+template <int Q>
+MWU_DEV void fold_records(const double *partials, int G, Red r, int qoff, double *s_wave, double *out)
 {
-    __shared__ int s_last;
-    const int Q = r.q();
-    const int G = gridDim.x, b = blockIdx.x;
-    const int grp = b / RGROUP, ng = (G + RGROUP - 1) / RGROUP;
-    const int gsz = min(RGROUP, G - grp * RGROUP);
-    if (threadIdx.x < Q) st_agent(&partials[(size_t)b * QMAX + threadIdx.x], s_rec[threadIdx.x]);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&tick[1 + grp], 1u);
-        s_last = (t == (unsigned)(gsz - 1));
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = red_id(q + qoff, r);
+    for (int b = threadIdx.x; b < G; b += BLOCK) {
+        const double *rec = partials + (size_t)b * QMAX;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], rec[q], q + qoff, r);
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    if (threadIdx.x < Q) {
-        const int q = threadIdx.x;
-        double a = red_id(q, r);
-        for (int i = 0; i < gsz; ++i)
-            a = red_op(a, ld_agent(&partials[(size_t)(grp * RGROUP + i) * QMAX + q]), q, r);
-        st_agent(&gpart[(size_t)grp * QMAX + q], a);
-    }
-    if (threadIdx.x == 0) atomicExch(&tick[1 + grp], 0u);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&tick[0], 1u);
-        s_last = (t == (unsigned)(ng - 1));
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    if (threadIdx.x < Q) {
-        const int q = threadIdx.x;
-        double a = red_id(q, r);
-        for (int i = 0; i < ng; ++i) a = red_op(a, ld_agent(&gpart[(size_t)i * QMAX + q]), q, r);
-        s_rec[q] = a;
-    }
-    if (threadIdx.x == 0) atomicExch(&tick[0], 0u);
-    __syncthreads();
-    return true;
+    block_combine<Q>(v, r, qoff, s_wave, out);
 }
 
 // ------------------------------------------------------------ accumulators
@@ -133,15 +99,6 @@ struct Pair {
 };
 
 template <class T> MWU_DEV T acc_zero() { return T{}; }
-
-// Loads and stores of partial sums published by other workgroups (possibly on
-// another XCD): agent-scope atomics, so no stale cache line is read.
-MWU_DEV void st_acc(float *p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-MWU_DEV void st_acc(double *p, double v) { st_agent(p, v); }
-template <class T> MWU_DEV void st_acc(Pair<T> *p, Pair<T> v) { st_acc(&p->g, v.g); st_acc(&p->h, v.h); }
-MWU_DEV float ld_acc(const float *p) { return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-MWU_DEV double ld_acc(const double *p) { return ld_agent(p); }
-template <class T> MWU_DEV Pair<T> ld_acc(const Pair<T> *p) { Pair<T> v; v.g = ld_acc(&p->g); v.h = ld_acc(&p->h); return v; }
 
 // ------------------------------------------------------------ segment tiles
 
@@ -217,14 +174,11 @@ MWU_DEV void seg_tile(const Tile &tl, const int32_t *__restrict__ ptr, ElemF &el
     __syncthreads();
 }
 
-// Chunk tile of a long segment: reduce the chunk, publish it, and let the
-// last chunk of the segment (ticket) fold all chunks in order and call epi
-// from thread 0.
-template <class Acc, class ElemF, class EpiF>
-MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, EpiF &epi, Acc *s_tacc, Acc *lpart,
-                        const int32_t *lfirst, const int32_t *lcount, unsigned *ltick)
+// Chunk tile of a long segment: reduce the chunk and store its partial sum;
+// the finisher kernel of the pass completes the segment.
+template <class Acc, class ElemF>
+MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, Acc *s_tacc, Acc *lpart, const int32_t *lfirst)
 {
-    __shared__ int s_lastc;
     const int tid = threadIdx.x;
     Acc acc = acc_zero<Acc>();
     for (int k = tl.k0 + tid; k < tl.k1; k += BLOCK) acc += elem(k);
@@ -234,82 +188,121 @@ MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, EpiF &epi, Acc *s_tacc, Acc
         if (tid < w) s_tacc[tid] += s_tacc[tid + w];
         __syncthreads();
     }
-    if (tid == 0) {
-        st_acc(&lpart[lfirst[tl.lid] + tl.cidx], s_tacc[0]);
-        __threadfence();
-        unsigned t = atomicAdd(&ltick[tl.lid], 1u);
-        s_lastc = (t == (unsigned)(lcount[tl.lid] - 1));
-        if (s_lastc) {
-            __threadfence();
-            Acc tot = acc_zero<Acc>();
-            const int f = lfirst[tl.lid], c = lcount[tl.lid];
-            for (int i = 0; i < c; ++i) tot += ld_acc(lpart + f + i);
-            atomicExch(&ltick[tl.lid], 0u);
-            epi(tl.s0, tot);
-        }
-    }
+    if (tid == 0) lpart[lfirst[tl.lid] + tl.cidx] = s_tacc[0];
     __syncthreads();
+}
+
+// Sum of the chunk partials of long segment lid, in chunk order.
+template <class Acc>
+MWU_DEV Acc long_sum(int lid, const Acc *lpart, const int32_t *lfirst, const int32_t *lcount)
+{
+    Acc tot = acc_zero<Acc>();
+    const int f = lfirst[lid], c = lcount[lid];
+    for (int i = 0; i < c; ++i) tot += lpart[f + i];
+    return tot;
 }
 
 // ------------------------------------------------- search terms of one row
 //
 // Covering row with weight u (unnormalized, u = exp(-eta (z - L))), value z
 // and direction dz; adds, for every candidate step a_k of the pass,
-//   acc[k]        += u expm1(-eta a_k dz)      (cancellation-free Phi sum)
-//   acc[KC + k]   += u exp(-eta a_k dz)        (direct Phi sum)
-//   acc[2KC + k]   = min(acc[2KC + k], z + a_k dz)
-// Exponential grids use expm1(2x) = expm1(x)(expm1(x) + 2) and squaring,
+//   acc[k]      += u expm1(-eta a_k dz)      (cancellation-free Phi sum)
+//   acc[KC + k] += u exp(-eta a_k dz)        (direct Phi sum)
+//   zmn[k]       = min(zmn[k], z + a_k dz)   (early return of Algorithm 3)
+// The sums are double; the minima stay in the storage type (z is stored in
+// it).  Exponential grids use expm1(2x) = expm1(x)(expm1(x) + 2) and squaring,
 // bisection grids the addition rule expm1(x+y) = expm1(x) + expm1(y) +
 // expm1(x) expm1(y); float re-seeds the squared term every 4 candidates.
 template <class T>
-MWU_DEV void cov_row_terms(int kind, int nc, const double *cd, double gdel, double eta, T u, T z,
-                           T dz, double *acc)
+MWU_DEV void cov_row_terms(int kind, int nc, const double *cand, double a0, double gdel, double eta,
+                           T u, T z, T dz, T *acc, T *zmn)
 {
+    if (kind == SK_LIST) {   // arbitrary candidates, direct evaluation (forced steps, probes)
 #pragma unroll
-    for (int k = 0; k < KC; ++k)
-        if (k < nc) acc[2 * KC + k] = fmin(acc[2 * KC + k], (double)(z + (T)cd[k] * dz));
+        for (int k = 0; k < KC; ++k)
+            if (k < nc) {
+                const double a = cand[k];
+                zmn[k] = fmin(zmn[k], z + (T)a * dz);
+                if (u > T(0)) {
+                    const T b = (T)(eta * a * (double)dz);
+                    acc[k] += u * expm1_t(-b);
+                    acc[KC + k] += u * exp_t(-b);
+                }
+            }
+        return;
+    }
+    {   // candidate k: a0 * 2^k (exponential grid, exact) or a0 + k * gdel (bisection grid)
+        T ak = (T)a0;
+        const T step = (T)gdel;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            zmn[k] = fmin(zmn[k], z + ak * dz);
+            ak = kind == SK_EXP ? ak + ak : ak + step;
+        }
+    }
     if (!(u > T(0))) return;
     if (!(dz > T(0))) {
 #pragma unroll
-        for (int k = 0; k < KC; ++k) acc[KC + k] += (double)u;
+        for (int k = 0; k < KC; ++k) acc[KC + k] += u;
         return;
     }
+    const T b0 = (T)(eta * a0 * (double)dz);
+    T m = expm1_t(-b0);
+    T t = exp_t(-b0);
     if (kind == SK_EXP) {
-        const T b0 = (T)(eta * cd[0] * (double)dz);
-        T m = expm1_t(-b0);
-        T t = exp_t(-b0);
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            acc[k] += (double)(u * m);
-            acc[KC + k] += (double)(u * t);
+            acc[k] += u * m;
+            acc[KC + k] += u * t;
             m = m * (m + T(2));
             if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KC)
-                t = exp_t((T)(-eta * cd[k + 1] * (double)dz));
+                t = exp_t((T)(-eta * a0 * (double)(1 << (k + 1)) * (double)dz));
             else
                 t = t * t;
         }
-    } else if (kind == SK_GRID) {
-        const T b0 = (T)(eta * cd[0] * (double)dz);
+    } else {
         const T bd = (T)(eta * gdel * (double)dz);
-        T m = expm1_t(-b0);
-        T t = exp_t(-b0);
         const T mr = expm1_t(-bd);
         const T tr = exp_t(-bd);
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-            acc[k] += (double)(u * m);
-            acc[KC + k] += (double)(u * t);
+            acc[k] += u * m;
+            acc[KC + k] += u * t;
             m = m + mr + m * mr;
             t = t * tr;
         }
-    } else {
-        for (int k = 0; k < nc; ++k) {
-            const T b = (T)(eta * cd[k] * (double)dz);
-            acc[k] += (double)(u * expm1_t(-b));
-            acc[KC + k] += (double)(u * exp_t(-b));
-        }
     }
 }
+
+// Per-thread accumulators of the covering side of a search pass.  The
+// per-thread partial sums (same-sign terms, a few dozen per thread) are kept
+// in the storage type; block and grid totals are double.
+template <class T>
+struct CovAcc {
+    T acc[2 * KC];
+    T zmn[KC];
+    MWU_DEV void init()
+    {
+#pragma unroll
+        for (int k = 0; k < 2 * KC; ++k) acc[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) zmn[k] = T(INFINITY);
+    }
+    // block-combine into out[0..3KC): [s1C | s2C | zmin]
+    MWU_DEV void combine(double *s_wave, double *out)
+    {
+        double ad[2 * KC];
+#pragma unroll
+        for (int k = 0; k < 2 * KC; ++k) ad[k] = (double)acc[k];
+        const Red rs{2 * KC, 0, 0};
+        block_combine<2 * KC>(ad, rs, 0, s_wave, out);
+        double zd[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) zd[k] = (double)zmn[k];
+        const Red rm{0, KC, 0};
+        block_combine<KC>(zd, rm, 0, s_wave, out + 2 * KC);
+    }
+};
 
 // ------------------------------------------------------ step-search replay
 //

@@ -54,6 +54,7 @@ struct Ctl {
     double sP, sC;              // uniform scale of P and C (1/M, 1/D or 1)
     double psi_lim;             // largest eta*alpha*max(dy) for the expm1 form
     double s2_min;              // smallest trusted direct sum of the C-side LSE
+    double qmin;                // d_i = 0 unless 1 - g_i/h_i exceeds this (0 in FP64)
     int32_t onesP, onesC;       // side is the implicit objective row (1 row, all ones)
     int32_t step_rule, max_iter;
     int32_t n_forced, forced_pos;
@@ -94,6 +95,14 @@ struct Ctl {
     int32_t ev_ok[KC];
 };
 
+// Long segments (longer than one tile) are split into chunk tiles whose
+// partial sums the finisher kernel of the pass folds: lseg[l] is the segment,
+// its chunks are partial slots lfirst[l] .. lfirst[l] + lcount[l] - 1.
+struct LongSegs {
+    const int32_t *lseg, *lfirst, *lcount;
+    int32_t nlong;
+};
+
 // Generic engine over explicit CSR sides.  Rows of P (if not the implicit
 // objective row) come first in the concatenated row space, then rows of C.
 template <class T>
@@ -103,17 +112,16 @@ struct GenericDev {
     const int32_t *rptr, *rcol;
     const T *rval;                      // nullable: all ones
     const Tile *rtiles; int32_t nrtiles;
+    LongSegs rlong;
+    T *rlpart;                          // chunk partials of the forward products
+    double *rlpart64;                   // chunk partials of the FP64 statistics
     // column structure (transpose products); crow indexes the row space
     const int32_t *cptr, *crow;
     const T *cval;                      // nullable
     const Tile *ctiles; int32_t nctiles;
+    LongSegs clong;
+    void *clpart;                       // chunk partials (g, h pairs) of the transpose products
     const double *colmaxP;              // max_j P_ji (unscaled) per column, nullable if onesP
-    // long segments
-    const int32_t *rlfirst, *clfirst;   // first partial slot per long segment
-    const int32_t *rlcount, *clcount;
-    unsigned *rltick, *cltick;
-    void *rlpart, *clpart;              // partial sums of chunk tiles
-    void *rlpart64;                     // double partial sums of row chunk tiles (statistics)
     // vectors
     T *x, *d, *yz, *dyz, *wu;
     double *g_dbg, *h_dbg;              // nullable: debug copies of g, h
@@ -133,8 +141,7 @@ struct VcDev {
     const Tile *utiles; int32_t nutiles;
     const int32_t *fptr, *fcol;         // full adjacency (both directions)
     const Tile *ftiles; int32_t nftiles;
-    const int32_t *flfirst, *flcount;
-    unsigned *fltick;
+    LongSegs flong;
     T *flpart;
     XD<T> *xd;                          // x and d interleaved (one 2T gather per neighbor)
     T *h;                               // unnormalized C^T u per vertex
@@ -148,9 +155,7 @@ struct Launch {
     int grid_elem_cols;  // persistent grid for element-wise passes over columns
     int grid_rtile;      // persistent grid for row tiles
     int grid_ctile;      // persistent grid for column tiles
-    double *partials;    // GRID_MAX * QMAX doubles: one record per block
-    double *gpart;       // ceil(GRID_MAX / 32) * QMAX doubles: one record per group
-    unsigned *tickets;   // 1 + ceil(GRID_MAX / 32) counters, all zero between kernels
+    double *partials;    // GRID_MAX * QMAX doubles: one reduction record per workgroup
 };
 
 constexpr int GRID_MAX = 2048;
@@ -188,8 +193,7 @@ struct VcLaunch {
     int grid_v;        // element-wise over vertices
     int grid_ftile;    // full-adjacency tiles
     int grid_utile;    // upper-adjacency tiles
-    double *partials, *gpart;
-    unsigned *tickets;
+    double *partials;
 };
 template <class T> void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,
                                 bool have_x0);

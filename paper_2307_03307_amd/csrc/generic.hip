@@ -9,9 +9,11 @@
 //   forward pass dy = P d, dz = C d.
 //   search pass  Psi/Phi of up to KC candidate steps (Section 4.1) and the
 //                device-side replay of Algorithm 3.
-// Rows of P come first in the concatenated row space, then rows of C.  A side
-// equal to the single objective row (1/M) 1^T (end of Section 2.2) is kept as
-// a scalar in the control block.
+// Each pass is a wide kernel that stores one reduction record per workgroup
+// plus a one-workgroup finisher that folds the records, completes segments
+// longer than a tile, and advances the state machine.  Rows of P come first
+// in the concatenated row space, then rows of C.  A side equal to the single
+// objective row (1/M) 1^T (end of Section 2.2) is kept as a scalar.
 #include "device_common.h"
 
 namespace mwu {
@@ -64,8 +66,9 @@ MWU_DEV void finish_col(Ctl *c, const double *rec)
     c->gmin = rec[1];
     c->dmax = rec[2];
     c->hmax = rec[3];
-    if (c->gmin > 0.0 && 1.0 / c->gmin < c->pack_bound) c->pack_bound = 1.0 / c->gmin;
-    if (c->hmax > 0.0 && 1.0 / c->hmax > c->cover_bound) c->cover_bound = 1.0 / c->hmax;
+    const double cf = 1.0 - c->qmin;   // margin for the rounding of g and h
+    if (c->gmin > 0.0 && 1.0 / (cf * c->gmin) < c->pack_bound) c->pack_bound = 1.0 / (cf * c->gmin);
+    if (c->hmax > 0.0 && cf / c->hmax > c->cover_bound) c->cover_bound = cf / c->hmax;
     c->dy1 = c->onesP ? c->sP * c->dsum : 0.0;
     c->dz1 = c->onesC ? c->sC * c->dsum : 0.0;
     if (c->eval_mode) { c->phase = PH_FWD; return; }
@@ -85,11 +88,83 @@ MWU_DEV void finish_init_fwd(Ctl *c, const double *rec)
     c->phase = PH_ROW;
 }
 
+MWU_DEV void finish_sumx(Ctl *c, double sumx)
+{
+    c->sumx = sumx;
+    c->y1 = c->sP * sumx;
+    c->z1 = c->sC * sumx;
+    c->dy1 = 0.0;
+    c->dz1 = 0.0;
+}
+
+// ------------------------------------------------------------------ epilogues
+
+// Column epilogue: commit the pending step, form g, h and the direction.
+template <class T>
+struct ColEpi {
+    GenericDev<T> gd;
+    double sP, sC, invSw, invSu, step, qmin;
+    int onesP, onesC;
+    T a;
+    MWU_DEV void load(const Ctl *c)
+    {
+        sP = c->sP; sC = c->sC; invSw = c->invSw; invSu = c->invSu; step = c->step; qmin = c->qmin;
+        onesP = c->onesP; onesC = c->onesC; a = (T)c->alpha;
+    }
+    // v: [sum d | min g | max d | max h]
+    MWU_DEV void operator()(int i, Pair<T> acc, double *v) const
+    {
+        const double g = onesP ? sP : sP * (double)acc.g * invSw;
+        const double h = onesC ? sC : sC * (double)acc.h * invSu;
+        const T x = gd.x[i] + a * gd.d[i];
+        gd.x[i] = x;
+        double di = 0.0;
+        if (h > 0.0) {
+            const double q = 1.0 - g / h;
+            if (q > qmin) di = step * q * (double)x;
+        }
+        const T dt = (T)di;
+        gd.d[i] = dt;
+        v[0] += (double)dt;
+        v[1] = fmin(v[1], g);
+        v[2] = fmax(v[2], (double)dt);
+        v[3] = fmax(v[3], h);
+        if (gd.g_dbg) { gd.g_dbg[i] = g; gd.h_dbg[i] = h; }
+    }
+};
+
+// Row epilogue of a forward product: vout[r] = s * acc; v: [min C rows | max P rows].
+template <class T>
+struct FwdEpi {
+    T *vout;
+    double sP, sC;
+    int mPc;
+    MWU_DEV void operator()(int r, T acc, double *v) const
+    {
+        const double s = r < mPc ? sP : sC;
+        const T o = (T)(s * (double)acc);
+        vout[r] = o;
+        if (r < mPc) v[1] = fmax(v[1], (double)o);
+        else v[0] = fmin(v[0], (double)o);
+    }
+};
+
+// Row epilogue of the FP64 statistics: v: [min C rows | max P rows].
+struct StatEpi {
+    double sP, sC;
+    int mPc;
+    MWU_DEV void operator()(int r, double acc, double *v) const
+    {
+        if (r < mPc) v[1] = fmax(v[1], sP * acc);
+        else v[0] = fmin(v[0], sC * acc);
+    }
+};
+
 // ------------------------------------------------------------------ kernels
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_init_x(GenericDev<T> gd, Ctl *ctl, int have_x0,
-                                                   double *part, double *gpart, unsigned *tick)
+                                                   const double *src, double *part)
 {
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
@@ -99,7 +174,10 @@ __global__ __launch_bounds__(BLOCK) void k_init_x(GenericDev<T> gd, Ctl *ctl, in
     const int stride = gridDim.x * BLOCK;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < gd.n; i += stride) {
         T x;
-        if (!have_x0) {
+        if (src) {
+            x = (T)src[i];
+            gd.x[i] = x;
+        } else if (!have_x0) {
             // Algorithm 1: x_i = eps / (n max_j P_ji)
             const double cm = onesP ? sP : sP * gd.colmaxP[i];
             x = (T)(eps / ((double)gd.n * cm));
@@ -111,46 +189,22 @@ __global__ __launch_bounds__(BLOCK) void k_init_x(GenericDev<T> gd, Ctl *ctl, in
         v[0] += (double)x;
     }
     for (int r = blockIdx.x * BLOCK + threadIdx.x; r < gd.mR; r += stride) gd.dyz[r] = T(0);
-    Red red{1, 0, 0};
+    const Red red{1, 0, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
-        ctl->sumx = s_rec[0];
-        ctl->y1 = ctl->sP * s_rec[0];
-        ctl->z1 = ctl->sC * s_rec[0];
-        ctl->dy1 = 0.0;
-        ctl->dz1 = 0.0;
-    }
+    store_record(s_rec, 1, part);
 }
 
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_load_x(GenericDev<T> gd, Ctl *ctl, const double *src,
-                                                   double *part, double *gpart, unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void k_init_x_fin(Ctl *ctl, const double *part, int G)
 {
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
-    double v[1] = {0.0};
-    const int stride = gridDim.x * BLOCK;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < gd.n; i += stride) {
-        const T x = (T)src[i];
-        gd.x[i] = x;
-        gd.d[i] = T(0);
-        v[0] += (double)x;
-    }
-    for (int r = blockIdx.x * BLOCK + threadIdx.x; r < gd.mR; r += stride) gd.dyz[r] = T(0);
-    Red red{1, 0, 0};
-    block_combine<1>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
-        ctl->sumx = s_rec[0];
-        ctl->y1 = ctl->sP * s_rec[0];
-        ctl->z1 = ctl->sC * s_rec[0];
-        ctl->dy1 = 0.0;
-        ctl->dz1 = 0.0;
-    }
+    const Red red{1, 0, 0};
+    fold_records<1>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) finish_sumx(ctl, s_rec[0]);
 }
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_row(GenericDev<T> gd, Ctl *ctl, double *part,
-                                                double *gpart, unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void k_row(GenericDev<T> gd, Ctl *ctl, double *part)
 {
     __shared__ double s_wave[4 * 4];
     __shared__ double s_rec[QMAX];
@@ -176,12 +230,21 @@ __global__ __launch_bounds__(BLOCK) void k_row(GenericDev<T> gd, Ctl *ctl, doubl
     }
     const Red red{2, 1, 1};
     block_combine<4>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_row(ctl, s_rec);
+    store_record(s_rec, 4, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_row_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_ROW) return;
+    const Red red{2, 1, 1};
+    fold_records<4>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) finish_row(ctl, s_rec);
 }
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_col(GenericDev<T> gd, Ctl *ctl, double *part,
-                                                double *gpart, unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void k_col(GenericDev<T> gd, Ctl *ctl, double *part)
 {
     __shared__ Pair<T> s_acc[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
@@ -191,24 +254,15 @@ __global__ __launch_bounds__(BLOCK) void k_col(GenericDev<T> gd, Ctl *ctl, doubl
     __shared__ double s_rec[QMAX];
     const int ph = ctl->phase;
     if (ph != PH_COL && ph != PH_COMMIT) return;
-    const double alpha = ctl->alpha;
-    const T a = (T)alpha;
-    const int stride = gridDim.x * BLOCK;
     if (ph == PH_COMMIT) {
-        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < gd.n; i += stride)
+        const T a = (T)ctl->alpha;
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < gd.n; i += gridDim.x * BLOCK)
             gd.x[i] = gd.x[i] + a * gd.d[i];
-        double v[1] = {0.0};
-        const Red red{1, 0, 0};
-        block_combine<1>(v, red, 0, s_wave, s_rec);
-        if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
-            ctl->alpha = 0.0;
-            ctl->phase = PH_DONE;
-        }
         return;
     }
-    const double sP = ctl->sP, sC = ctl->sC, invSw = ctl->invSw, invSu = ctl->invSu;
-    const double step = ctl->step;
-    const int onesP = ctl->onesP, onesC = ctl->onesC;
+    ColEpi<T> ep;
+    ep.gd = gd;
+    ep.load(ctl);
     const int mPc = gd.mPc;
     double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};   // sum d | min g | max d | max h
     auto elem = [&](int k) -> Pair<T> {
@@ -219,40 +273,50 @@ __global__ __launch_bounds__(BLOCK) void k_col(GenericDev<T> gd, Ctl *ctl, doubl
         p.h = r < mPc ? T(0) : val;
         return p;
     };
-    auto epi = [&](int i, Pair<T> acc) {
-        const double g = onesP ? sP : sP * (double)acc.g * invSw;
-        const double h = onesC ? sC : sC * (double)acc.h * invSu;
-        const T x = gd.x[i] + a * gd.d[i];
-        gd.x[i] = x;
-        double di = 0.0;
-        if (h > 0.0) {
-            const double q = 1.0 - g / h;
-            if (q > 0.0) di = step * q * (double)x;
-        }
-        const T dt = (T)di;
-        gd.d[i] = dt;
-        v[0] += (double)dt;
-        v[1] = fmin(v[1], g);
-        v[2] = fmax(v[2], (double)dt);
-        v[3] = fmax(v[3], h);
-        if (gd.g_dbg) { gd.g_dbg[i] = g; gd.h_dbg[i] = h; }
-    };
+    auto epi = [&](int i, Pair<T> acc) { ep(i, acc, v); };
     for (int t = blockIdx.x; t < gd.nctiles; t += gridDim.x) {
         const Tile tl = gd.ctiles[t];
         if (tl.lid < 0) seg_tile<Pair<T>>(tl, gd.cptr, elem, epi, s_acc, s_ptr, s_tseg, s_tacc);
-        else chunk_tile<Pair<T>>(tl, elem, epi, s_tacc, (Pair<T> *)gd.clpart, gd.clfirst,
-                                 gd.clcount, gd.cltick);
+        else chunk_tile<Pair<T>>(tl, elem, s_tacc, (Pair<T> *)gd.clpart, gd.clong.lfirst);
     }
     const Red red{1, 1, 2};
     block_combine<4>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_col(ctl, s_rec);
+    store_record(s_rec, 4, part);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_col_fin(GenericDev<T> gd, Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    __shared__ double s_lng[QMAX];
+    const int ph = ctl->phase;
+    if (ph != PH_COL && ph != PH_COMMIT) return;
+    if (ph == PH_COMMIT) {
+        if (threadIdx.x == 0 && !held(ctl)) { ctl->alpha = 0.0; ctl->phase = PH_DONE; }
+        return;
+    }
+    ColEpi<T> ep;
+    ep.gd = gd;
+    ep.load(ctl);
+    const Red red{1, 1, 2};
+    double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
+    for (int l = threadIdx.x; l < gd.clong.nlong; l += BLOCK)
+        ep(gd.clong.lseg[l], long_sum<Pair<T>>(l, (const Pair<T> *)gd.clpart, gd.clong.lfirst,
+                                               gd.clong.lcount), v);
+    block_combine<4>(v, red, 0, s_wave, s_lng);
+    fold_records<4>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 4; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
+        finish_col(ctl, s_rec);
+    }
 }
 
 // Forward product vout = (scaled rows) * vin.  INIT: y = Px, z = Cx at the
-// probe start (no phase check); otherwise dy = Pd, dz = Cd and the search setup.
+// probe start (no phase check); otherwise dy = Pd, dz = Cd.
 template <class T, bool INIT>
 __global__ __launch_bounds__(BLOCK) void k_fwd(GenericDev<T> gd, Ctl *ctl, const T *vin, T *vout,
-                                                double *part, double *gpart, unsigned *tick)
+                                                double *part)
 {
     __shared__ T s_acc[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
@@ -261,25 +325,37 @@ __global__ __launch_bounds__(BLOCK) void k_fwd(GenericDev<T> gd, Ctl *ctl, const
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
     if (!INIT && ctl->phase != PH_FWD) return;
-    const double sP = ctl->sP, sC = ctl->sC;
-    const int mPc = gd.mPc;
+    FwdEpi<T> ep{vout, ctl->sP, ctl->sC, gd.mPc};
     double v[2] = {INFINITY, -INFINITY};   // min over C rows | max over P rows
     auto elem = [&](int k) -> T { return (gd.rval ? gd.rval[k] : T(1)) * vin[gd.rcol[k]]; };
-    auto epi = [&](int r, T acc) {
-        const double s = r < mPc ? sP : sC;
-        const T o = (T)(s * (double)acc);
-        vout[r] = o;
-        if (r < mPc) v[1] = fmax(v[1], (double)o);
-        else v[0] = fmin(v[0], (double)o);
-    };
+    auto epi = [&](int r, T acc) { ep(r, acc, v); };
     for (int t = blockIdx.x; t < gd.nrtiles; t += gridDim.x) {
         const Tile tl = gd.rtiles[t];
         if (tl.lid < 0) seg_tile<T>(tl, gd.rptr, elem, epi, s_acc, s_ptr, s_tseg, s_tacc);
-        else chunk_tile<T>(tl, elem, epi, s_tacc, (T *)gd.rlpart, gd.rlfirst, gd.rlcount, gd.rltick);
+        else chunk_tile<T>(tl, elem, s_tacc, gd.rlpart, gd.rlong.lfirst);
     }
     const Red red{0, 1, 1};
     block_combine<2>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+    store_record(s_rec, 2, part);
+}
+
+template <class T, bool INIT>
+__global__ __launch_bounds__(BLOCK) void k_fwd_fin(GenericDev<T> gd, Ctl *ctl, T *vout,
+                                                    const double *part, int G)
+{
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    __shared__ double s_lng[QMAX];
+    if (!INIT && ctl->phase != PH_FWD) return;
+    FwdEpi<T> ep{vout, ctl->sP, ctl->sC, gd.mPc};
+    const Red red{0, 1, 1};
+    double v[2] = {INFINITY, -INFINITY};
+    for (int l = threadIdx.x; l < gd.rlong.nlong; l += BLOCK)
+        ep(gd.rlong.lseg[l], long_sum<T>(l, gd.rlpart, gd.rlong.lfirst, gd.rlong.lcount), v);
+    block_combine<2>(v, red, 0, s_wave, s_lng);
+    fold_records<2>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
         if (INIT) {
             finish_init_fwd(ctl, s_rec);
         } else if (!held(ctl)) {
@@ -294,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd(GenericDev<T> gd, Ctl *ctl, const
 // the double coefficients (rval64, nullable = all ones).
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_stats(GenericDev<T> gd, Ctl *ctl, const double *rval64,
-                                                  double *part, double *gpart, unsigned *tick)
+                                                  double *part)
 {
     __shared__ double s_acc[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
@@ -302,23 +378,35 @@ __global__ __launch_bounds__(BLOCK) void k_stats(GenericDev<T> gd, Ctl *ctl, con
     __shared__ double s_tacc[BLOCK];
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
-    const double sP = ctl->sP, sC = ctl->sC;
-    const int mPc = gd.mPc;
+    StatEpi ep{ctl->sP, ctl->sC, gd.mPc};
     double v[2] = {INFINITY, -INFINITY};
     auto elem = [&](int k) -> double { return (rval64 ? rval64[k] : 1.0) * (double)gd.x[gd.rcol[k]]; };
-    auto epi = [&](int r, double acc) {
-        if (r < mPc) v[1] = fmax(v[1], sP * acc);
-        else v[0] = fmin(v[0], sC * acc);
-    };
+    auto epi = [&](int r, double acc) { ep(r, acc, v); };
     for (int t = blockIdx.x; t < gd.nrtiles; t += gridDim.x) {
         const Tile tl = gd.rtiles[t];
         if (tl.lid < 0) seg_tile<double>(tl, gd.rptr, elem, epi, s_acc, s_ptr, s_tseg, s_tacc);
-        else chunk_tile<double>(tl, elem, epi, s_tacc, (double *)gd.rlpart64, gd.rlfirst, gd.rlcount,
-                                gd.rltick);
+        else chunk_tile<double>(tl, elem, s_tacc, gd.rlpart64, gd.rlong.lfirst);
     }
     const Red red{0, 1, 1};
     block_combine<2>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+    store_record(s_rec, 2, part);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_stats_fin(GenericDev<T> gd, Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    __shared__ double s_lng[QMAX];
+    StatEpi ep{ctl->sP, ctl->sC, gd.mPc};
+    const Red red{0, 1, 1};
+    double v[2] = {INFINITY, -INFINITY};
+    for (int l = threadIdx.x; l < gd.rlong.nlong; l += BLOCK)
+        ep(gd.rlong.lseg[l], long_sum<double>(l, gd.rlpart64, gd.rlong.lfirst, gd.rlong.lcount), v);
+    block_combine<2>(v, red, 0, s_wave, s_lng);
+    fold_records<2>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
         ctl->zmin = ctl->onesC ? ctl->sC * ctl->sumx : s_rec[0];
         ctl->ymax = ctl->onesP ? ctl->sP * ctl->sumx : s_rec[1];
     }
@@ -327,8 +415,7 @@ __global__ __launch_bounds__(BLOCK) void k_stats(GenericDev<T> gd, Ctl *ctl, con
 // Search pass over the stored rows: for each candidate step, the sums that
 // give Psi and Phi (Section 4.1) plus min(z + a dz) (Algorithm 3 early return).
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, double *part,
-                                                   double *gpart, unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, double *part)
 {
     __shared__ double s_wave[4 * 3 * KC];
     __shared__ double s_rec[QMAX];
@@ -349,8 +436,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             }
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
-            if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0)
-                finish_search(ctl, s_rec);
+            store_record(s_rec, 2, part);
         } else {
             const double pm = ctl->rfPm, zm = ctl->rfZmin;
             double v[2] = {0.0, 0.0};
@@ -361,15 +447,13 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             }
             const Red red{2, 0, 0};
             block_combine<2>(v, red, 0, s_wave, s_rec);
-            if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0)
-                finish_search(ctl, s_rec);
+            store_record(s_rec, 2, part);
         }
         return;
     }
     const int nc = ctl->ncand;
-    double cd[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) cd[k] = ctl->cand[k];
+    const double *cand = ctl->cand;
+    const double a0 = ctl->cand[0];
     const double gdel = ctl->gdelta;
     // ---- packing rows: s1P[k] = sum_i w_i expm1(eta a_k dy_i)
     {
@@ -380,14 +464,14 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             const T w = gd.wu[r], dy = gd.dyz[r];
             if (!(w > T(0)) || !(dy > T(0))) continue;
             if (kind == SK_EXP) {
-                T m = expm1_t((T)(eta * cd[0] * (double)dy));
+                T m = expm1_t((T)(eta * a0 * (double)dy));
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     s1[k] += (double)(w * m);
                     m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
                 }
             } else if (kind == SK_GRID) {
-                T m = expm1_t((T)(eta * cd[0] * (double)dy));
+                T m = expm1_t((T)(eta * a0 * (double)dy));
                 const T mr = expm1_t((T)(eta * gdel * (double)dy));
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
@@ -395,8 +479,9 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
                     m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
                 }
             } else {
-                for (int k = 0; k < nc; ++k)
-                    s1[k] += (double)(w * expm1_t((T)(eta * cd[k] * (double)dy)));
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+                    if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
             }
         }
         const Red redp{KC, 0, 0};
@@ -405,16 +490,28 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
     // ---- covering rows: s1C[k] = sum_j u_j expm1(-b_jk), s2C[k] = sum_j u_j e^{-b_jk},
     //      zmin[k] = min_j z_j + a_k dz_j, with b_jk = eta a_k dz_j
     {
-        double acc[3 * KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) { acc[k] = 0.0; acc[KC + k] = 0.0; acc[2 * KC + k] = INFINITY; }
+        CovAcc<T> ca;
+        ca.init();
         for (int r = mPc + r0; r < mR; r += stride)
-            cov_row_terms<T>(kind, nc, cd, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], acc);
-        const Red redc{3 * KC, KC, 0};
-        block_combine<3 * KC>(acc, redc, KC, s_wave, s_rec + KC);
+            cov_row_terms<T>(kind, nc, cand, a0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
+        ca.combine(s_wave, s_rec + KC);
     }
-    const Red red{3 * KC, KC, 0};
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_search(ctl, s_rec);
+    store_record(s_rec, 4 * KC, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_search_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 4 * KC];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_SEARCH) return;
+    if (ctl->skind == SK_REFINE) {
+        const Red red = ctl->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
+        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+    } else {
+        const Red red{3 * KC, KC, 0};
+        fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
+    }
+    if (threadIdx.x == 0) finish_search(ctl, s_rec);
 }
 
 template <class T>
@@ -451,61 +548,73 @@ static inline int grid_for(int64_t items)
     return (int)g;
 }
 
+#define LAUNCH(kernel, grid, ...) hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, st, __VA_ARGS__)
+
+template <class T>
+static void init_sum(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st, int have_x0,
+                     const double *src)
+{
+    LAUNCH(k_init_x<T>, L.grid_elem_cols, g, ctl, have_x0, src, L.partials);
+    LAUNCH(k_init_x_fin, 1, ctl, (const double *)L.partials, L.grid_elem_cols);
+}
+
+template <class T>
+static void fwd_init(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
+{
+    LAUNCH((k_fwd<T, true>), L.grid_rtile, g, ctl, (const T *)g.x, g.yz, L.partials);
+    LAUNCH((k_fwd_fin<T, true>), 1, g, ctl, g.yz, (const double *)L.partials, L.grid_rtile);
+}
+
 template <class T>
 void generic_init(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st, bool have_x0)
 {
-    hipLaunchKernelGGL(k_init_x<T>, dim3(L.grid_elem_cols), dim3(BLOCK), 0, st, g, ctl,
-                       have_x0 ? 1 : 0, L.partials, L.gpart, L.tickets);
-    hipLaunchKernelGGL((k_fwd<T, true>), dim3(L.grid_rtile), dim3(BLOCK), 0, st, g, ctl,
-                       (const T *)g.x, g.yz, L.partials, L.gpart, L.tickets);
+    init_sum(g, ctl, L, st, have_x0 ? 1 : 0, nullptr);
+    fwd_init(g, ctl, L, st);
 }
 
 template <class T>
 void generic_load_x(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st,
                     const double *x_dev)
 {
-    hipLaunchKernelGGL(k_load_x<T>, dim3(L.grid_elem_cols), dim3(BLOCK), 0, st, g, ctl, x_dev,
-                       L.partials, L.gpart, L.tickets);
-    hipLaunchKernelGGL((k_fwd<T, true>), dim3(L.grid_rtile), dim3(BLOCK), 0, st, g, ctl,
-                       (const T *)g.x, g.yz, L.partials, L.gpart, L.tickets);
+    init_sum(g, ctl, L, st, 1, x_dev);
+    fwd_init(g, ctl, L, st);
 }
 
 template <class T>
 void generic_stats(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st,
                    const double *rval64)
 {
-    hipLaunchKernelGGL(k_init_x<T>, dim3(L.grid_elem_cols), dim3(BLOCK), 0, st, g, ctl, 1,
-                       L.partials, L.gpart, L.tickets);
-    hipLaunchKernelGGL(k_stats<T>, dim3(L.grid_rtile), dim3(BLOCK), 0, st, g, ctl, rval64,
-                       L.partials, L.gpart, L.tickets);
+    init_sum(g, ctl, L, st, 1, nullptr);
+    LAUNCH(k_stats<T>, L.grid_rtile, g, ctl, rval64, L.partials);
+    LAUNCH(k_stats_fin<T>, 1, g, ctl, (const double *)L.partials, L.grid_rtile);
 }
 
 template <class T>
 void generic_row(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_row<T>, dim3(L.grid_elem_rows), dim3(BLOCK), 0, st, g, ctl, L.partials,
-                       L.gpart, L.tickets);
+    LAUNCH(k_row<T>, L.grid_elem_rows, g, ctl, L.partials);
+    LAUNCH(k_row_fin, 1, ctl, (const double *)L.partials, L.grid_elem_rows);
 }
 
 template <class T>
 void generic_col(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_col<T>, dim3(L.grid_ctile), dim3(BLOCK), 0, st, g, ctl, L.partials,
-                       L.gpart, L.tickets);
+    LAUNCH(k_col<T>, L.grid_ctile, g, ctl, L.partials);
+    LAUNCH(k_col_fin<T>, 1, g, ctl, (const double *)L.partials, L.grid_ctile);
 }
 
 template <class T>
 void generic_fwd(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fwd<T, false>), dim3(L.grid_rtile), dim3(BLOCK), 0, st, g, ctl,
-                       (const T *)g.d, g.dyz, L.partials, L.gpart, L.tickets);
+    LAUNCH((k_fwd<T, false>), L.grid_rtile, g, ctl, (const T *)g.d, g.dyz, L.partials);
+    LAUNCH((k_fwd_fin<T, false>), 1, g, ctl, g.dyz, (const double *)L.partials, L.grid_rtile);
 }
 
 template <class T>
 void generic_search(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_search<T>, dim3(L.grid_elem_rows), dim3(BLOCK), 0, st, g, ctl, L.partials,
-                       L.gpart, L.tickets);
+    LAUNCH(k_search<T>, L.grid_elem_rows, g, ctl, L.partials);
+    LAUNCH(k_search_fin, 1, ctl, (const double *)L.partials, L.grid_elem_rows);
 }
 
 template <class T>
@@ -521,20 +630,19 @@ void generic_iteration(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStr
 void potential_finish(const double *g_dbg, const double *h_dbg, int n, double scale, double *out,
                       const Ctl *ctl, double *val, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_potential_finish, dim3(grid_for(n)), dim3(BLOCK), 0, st, g_dbg, h_dbg, n,
-                       scale, out, ctl, val);
+    LAUNCH(k_potential_finish, grid_for(n), g_dbg, h_dbg, n, scale, out, ctl, val);
 }
 
 template <class T>
 void widen(const T *src, double *dst, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_widen<T>, dim3(grid_for(n)), dim3(BLOCK), 0, st, src, dst, n);
+    LAUNCH(k_widen<T>, grid_for(n), src, dst, n);
 }
 
 template <class T>
 void narrow(const double *src, T *dst, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_narrow<T>, dim3(grid_for(n)), dim3(BLOCK), 0, st, src, dst, n);
+    LAUNCH(k_narrow<T>, grid_for(n), src, dst, n);
 }
 
 void set_phase(Ctl *ctl, int phase, hipStream_t st)

@@ -120,7 +120,7 @@ struct Solver {
 
 struct TilePlan {
     std::vector<Tile> tiles;
-    std::vector<int32_t> lfirst, lcount;
+    std::vector<int32_t> lseg, lfirst, lcount;   // long segments and their chunk slots
     int32_t nslots = 0;
 };
 TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg);

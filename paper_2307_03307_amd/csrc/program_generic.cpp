@@ -19,6 +19,7 @@ TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg)
         if (len > TILE_NZ) {
             const int32_t lid = (int32_t)tp.lfirst.size();
             const int32_t nch = (int32_t)((len + TILE_NZ - 1) / TILE_NZ);
+            tp.lseg.push_back((int32_t)s);
             tp.lfirst.push_back(tp.nslots);
             tp.lcount.push_back(nch);
             tp.nslots += nch;
@@ -114,14 +115,12 @@ class GenericProgram : public Program {
         up(colmax_, colmax.data(), colmax.size() * 8);
         up(rtiles_, rt.tiles.data(), rt.tiles.size() * sizeof(Tile));
         up(ctiles_, ct.tiles.data(), ct.tiles.size() * sizeof(Tile));
+        up(rlseg_, rt.lseg.data(), rt.lseg.size() * 4);
         up(rlfirst_, rt.lfirst.data(), rt.lfirst.size() * 4);
         up(rlcount_, rt.lcount.data(), rt.lcount.size() * 4);
+        up(clseg_, ct.lseg.data(), ct.lseg.size() * 4);
         up(clfirst_, ct.lfirst.data(), ct.lfirst.size() * 4);
         up(clcount_, ct.lcount.data(), ct.lcount.size() * 4);
-        rltick_.alloc(std::max<size_t>(rt.lfirst.size(), 1) * 4);
-        cltick_.alloc(std::max<size_t>(ct.lfirst.size(), 1) * 4);
-        HIP_OK(hipMemset(rltick_.p, 0, rltick_.bytes));
-        HIP_OK(hipMemset(cltick_.p, 0, cltick_.bytes));
         rlpart_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(T));
         rlpart64_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(double));
         if (vals) {   // exact coefficients for the FP64 certificate statistics
@@ -141,9 +140,6 @@ class GenericProgram : public Program {
         HIP_OK(hipMemset(d_.p, 0, d_.bytes));
         HIP_OK(hipMemset(dyz_.p, 0, dyz_.bytes));
         partials_.alloc((size_t)GRID_MAX * QMAX * 8);
-        gpart_.alloc((size_t)(GRID_MAX / 32 + 1) * QMAX * 8);
-        tickets_.alloc((size_t)(GRID_MAX / 32 + 2) * 4);
-        HIP_OK(hipMemset(tickets_.p, 0, tickets_.bytes));
 
         gd_ = GenericDev<T>{};
         gd_.n = (int32_t)n_; gd_.mPc = (int32_t)mPc_; gd_.mR = (int32_t)mR_;
@@ -152,10 +148,11 @@ class GenericProgram : public Program {
         gd_.cptr = cptr_.as<int32_t>(); gd_.crow = crow_.as<int32_t>(); gd_.cval = vals ? cval_.as<T>() : nullptr;
         gd_.ctiles = ctiles_.as<Tile>(); gd_.nctiles = (int32_t)ct.tiles.size();
         gd_.colmaxP = s.onesP ? nullptr : colmax_.as<double>();
-        gd_.rlfirst = rlfirst_.as<int32_t>(); gd_.clfirst = clfirst_.as<int32_t>();
-        gd_.rlcount = rlcount_.as<int32_t>(); gd_.clcount = clcount_.as<int32_t>();
-        gd_.rltick = rltick_.as<unsigned>(); gd_.cltick = cltick_.as<unsigned>();
-        gd_.rlpart = rlpart_.p; gd_.clpart = clpart_.p; gd_.rlpart64 = rlpart64_.p;
+        gd_.rlong = LongSegs{rlseg_.as<int32_t>(), rlfirst_.as<int32_t>(), rlcount_.as<int32_t>(),
+                             (int32_t)rt.lseg.size()};
+        gd_.clong = LongSegs{clseg_.as<int32_t>(), clfirst_.as<int32_t>(), clcount_.as<int32_t>(),
+                             (int32_t)ct.lseg.size()};
+        gd_.rlpart = rlpart_.as<T>(); gd_.clpart = clpart_.p; gd_.rlpart64 = rlpart64_.as<double>();
         gd_.x = x_.as<T>(); gd_.d = d_.as<T>(); gd_.yz = yz_.as<T>(); gd_.dyz = dyz_.as<T>();
         gd_.wu = wu_.as<T>();
         gd_.g_dbg = nullptr; gd_.h_dbg = nullptr; gd_.forced = nullptr;
@@ -169,8 +166,6 @@ class GenericProgram : public Program {
         L_.grid_rtile = clampg((int64_t)rt.tiles.size(), 1);
         L_.grid_ctile = clampg((int64_t)ct.tiles.size(), 1);
         L_.partials = partials_.as<double>();
-        L_.gpart = gpart_.as<double>();
-        L_.tickets = tickets_.as<unsigned>();
     }
 
     int64_t n() const override { return n_; }
@@ -321,8 +316,8 @@ class GenericProgram : public Program {
     GenericDev<T> gd_{};
     Launch L_{};
     DevBuf rptr_, rcol_, rval_, cptr_, crow_, cval_, colmax_, rtiles_, ctiles_;
-    DevBuf rlfirst_, rlcount_, clfirst_, clcount_, rltick_, cltick_, rlpart_, clpart_, rlpart64_, rval64_;
-    DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, gpart_, tickets_, forced_, dbg_g_, dbg_h_;
+    DevBuf rlseg_, rlfirst_, rlcount_, clseg_, clfirst_, clcount_, rlpart_, clpart_, rlpart64_, rval64_;
+    DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, forced_, dbg_g_, dbg_h_;
 };
 
 std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C)

@@ -58,19 +58,15 @@ class VcoverProgram : public Program {
         up(fcol_, fcol.data(), fcol.size() * 4);
         up(utiles_, ut.tiles.data(), ut.tiles.size() * sizeof(Tile));
         up(ftiles_, ft.tiles.data(), ft.tiles.size() * sizeof(Tile));
+        up(flseg_, ft.lseg.data(), ft.lseg.size() * 4);
         up(flfirst_, ft.lfirst.data(), ft.lfirst.size() * 4);
         up(flcount_, ft.lcount.data(), ft.lcount.size() * 4);
-        fltick_.alloc(std::max<size_t>(ft.lfirst.size(), 1) * 4);
-        HIP_OK(hipMemset(fltick_.p, 0, fltick_.bytes));
         flpart_.alloc(std::max<int32_t>(ft.nslots, 1) * sizeof(T));
         xd_.alloc(nv * sizeof(XD<T>));
         xbest_.alloc(nv * sizeof(XD<T>));
         h_.alloc(nv * sizeof(T));
         HIP_OK(hipMemset(xd_.p, 0, xd_.bytes));
         partials_.alloc((size_t)GRID_MAX * QMAX * 8);
-        gpart_.alloc((size_t)(GRID_MAX / 32 + 1) * QMAX * 8);
-        tickets_.alloc((size_t)(GRID_MAX / 32 + 2) * 4);
-        HIP_OK(hipMemset(tickets_.p, 0, tickets_.bytes));
 
         vd_ = VcDev<T>{};
         vd_.nv = (int32_t)nv; vd_.ne = (int32_t)ne_;
@@ -78,8 +74,9 @@ class VcoverProgram : public Program {
         vd_.utiles = utiles_.as<Tile>(); vd_.nutiles = (int32_t)ut.tiles.size();
         vd_.fptr = fptr_.as<int32_t>(); vd_.fcol = fcol_.as<int32_t>();
         vd_.ftiles = ftiles_.as<Tile>(); vd_.nftiles = (int32_t)ft.tiles.size();
-        vd_.flfirst = flfirst_.as<int32_t>(); vd_.flcount = flcount_.as<int32_t>();
-        vd_.fltick = fltick_.as<unsigned>(); vd_.flpart = flpart_.as<T>();
+        vd_.flong = LongSegs{flseg_.as<int32_t>(), flfirst_.as<int32_t>(), flcount_.as<int32_t>(),
+                             (int32_t)ft.lseg.size()};
+        vd_.flpart = flpart_.as<T>();
         vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>();
         vd_.h_dbg = nullptr; vd_.forced = nullptr;
         auto clampg = [](int64_t items, int64_t per) {
@@ -90,8 +87,6 @@ class VcoverProgram : public Program {
         L_.grid_ftile = clampg((int64_t)ft.tiles.size(), 1);
         L_.grid_utile = clampg((int64_t)ut.tiles.size(), 1);
         L_.partials = partials_.as<double>();
-        L_.gpart = gpart_.as<double>();
-        L_.tickets = tickets_.as<unsigned>();
     }
 
     int64_t n() const override { return nv_; }
@@ -229,8 +224,8 @@ class VcoverProgram : public Program {
     bool debug_ = false;
     VcDev<T> vd_{};
     VcLaunch L_{};
-    DevBuf uptr_, ucol_, fptr_, fcol_, utiles_, ftiles_, flfirst_, flcount_, fltick_, flpart_;
-    DevBuf xd_, xbest_, h_, partials_, gpart_, tickets_, forced_, hdbg_;
+    DevBuf uptr_, ucol_, fptr_, fcol_, utiles_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
+    DevBuf xd_, xbest_, h_, partials_, forced_, hdbg_;
 };
 
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,

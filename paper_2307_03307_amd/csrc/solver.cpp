@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <new>
@@ -406,6 +408,11 @@ static void push_ctl(Solver &s)
     HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, s.stream));
 }
 
+// Direction threshold of the mixed form: the relative rounding of g_i and h_i
+// (FP32 weights and per-thread partials) stays well below this, so a
+// coordinate is moved only when g_i < h_i holds beyond that rounding.
+static constexpr double kMixedQmin = 1.0 / 65536.0;
+
 static void begin_probe(Solver &s, double param, const double *x0)
 {
     Ctl &c = *s.ctl_host;
@@ -420,6 +427,7 @@ static void begin_probe(Solver &s, double param, const double *x0)
     c.sC = probe_scale_C(s, param);
     c.psi_lim = s.fp32 ? 80.0 : 700.0;
     c.s2_min = s.fp32 ? 1e-25 : 1e-280;
+    c.qmin = s.fp32 ? kMixedQmin : 0.0;
     c.onesP = s.onesP;
     c.onesC = s.onesC;
     c.step_rule = s.opt.step_rule;
@@ -515,7 +523,9 @@ static SolveOut solve_impl(Solver &s)
         begin_probe(s, param, nullptr);
         run_probe(s, s.opt.max_iter);
         pull_ctl(s);
-        const Ctl c = *s.ctl_host;
+        Ctl c = *s.ctl_host;
+        // the iteration cap was reached before the device could flag it
+        if (c.status == ST_RUNNING) c.status = ST_MAX_ITER;
         o.probes++;
         o.total_iters += c.iter;
         o.final_iters = c.iter;
@@ -538,45 +548,55 @@ static SolveOut solve_impl(Solver &s)
         o.max_violation = std::max({0.0, f.ymax - 1.0, 1.0 - f.zmin});
         return o;
     }
-    while (o.probes < s.opt.max_probes && hi > (1.0 + eps) * lo) {
-        const double param = std::sqrt(lo * hi);
+    const bool trace = std::getenv("MWU_TRACE") != nullptr;
+    // An infeasible verdict proves OPT < param (packing) or OPT > param
+    // (covering, densest) up to the direction threshold qmin.
+    const double cf = s.fp32 ? 1.0 - kMixedQmin : 1.0;
+    // search bracket for the parameter: moves to every probed value, while
+    // lo/hi (the certified bracket on OPT) move only with certificates
+    double slo = lo, shi = hi;
+    while (o.probes < s.opt.max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+        const double param = std::sqrt(slo * shi);
         const Ctl c = probe_done(param);
         finish_probe_stats(s);
         const Ctl f = *s.ctl_host;
+        if (trace)
+            std::fprintf(stderr, "[mwu] probe %lld param %.10g status %d iters %d passes %lld alpha %.6g "
+                         "sumx %.10g ymax %.10g zmin %.10g bounds %.10g %.10g bracket %.10g %.10g\n",
+                         (long long)o.probes, param, c.status, c.iter, (long long)c.search_passes,
+                         c.last_alpha, f.sumx, f.ymax, f.zmin, c.pack_bound, c.cover_bound, lo, hi);
         o.max_violation = std::max({0.0, f.ymax - 1.0, 1.0 - f.zmin});
         if (c.status == ST_NUMERIC) throw ApiError{MWU_ERR_DEVICE, "numerical failure in a probe"};
+        const bool feasible = c.status == ST_FEASIBLE;
+        if (c.status == ST_MAX_ITER) uncertified = true;
         if (s.form == MWU_PACKING) {
             if (c.pack_bound < hi) hi = c.pack_bound;
-            if (c.status == ST_FEASIBLE) {
+            if (feasible) {
                 const double val = f.sumx / f.ymax;
                 if (val > lo) { lo = val; s.prog->save_best(); o.have_best_dev = true; o.best_scale = 1.0 / f.ymax; }
+                slo = param;
             } else {
-                hi = std::min(hi, param);
-                if (c.status == ST_MAX_ITER) uncertified = true;
-            }
-        } else if (s.form == MWU_COVERING) {
-            if (c.cover_bound > lo) lo = c.cover_bound;
-            if (c.status == ST_FEASIBLE) {
-                const double val = f.sumx / f.zmin;
-                if (val < hi) { hi = val; s.prog->save_best(); o.have_best_dev = true; o.best_scale = 1.0 / f.zmin; }
-            } else {
-                lo = std::max(lo, param);
-                if (c.status == ST_MAX_ITER) uncertified = true;
+                if (c.status == ST_INFEASIBLE) hi = std::min(hi, param / cf);
+                shi = param;
             }
         } else {
+            if (s.form == MWU_COVERING && c.cover_bound > lo) lo = c.cover_bound;
             if (s.level_sets) {
                 std::vector<double> load(s.prog->mP());
                 s.prog->read(4, load.data(), (int64_t)load.size());
                 lo = std::max(lo, level_set_density(s.dens_graph, load));
             }
-            if (c.status == ST_FEASIBLE) {
-                const double val = (f.ymax / f.sP) / f.zmin;
+            if (feasible) {
+                const double val = s.form == MWU_COVERING ? f.sumx / f.zmin : (f.ymax / f.sP) / f.zmin;
                 if (val < hi) { hi = val; s.prog->save_best(); o.have_best_dev = true; o.best_scale = 1.0 / f.zmin; }
+                shi = param;
             } else {
-                lo = std::max(lo, param);
-                if (c.status == ST_MAX_ITER) uncertified = true;
+                if (c.status == ST_INFEASIBLE) lo = std::max(lo, param * cf);
+                slo = param;
             }
         }
+        slo = std::max(slo, lo);
+        shi = std::min(shi, hi);
     }
     o.lower = lo;
     o.upper = hi;

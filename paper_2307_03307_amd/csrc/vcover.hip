@@ -173,7 +173,8 @@ MWU_DEV void finish_vcB(Ctl *c, const double *rec, const double *forced)
     c->dmax = rec[1];
     c->hmax = rec[2];
     c->gmin = c->sP;
-    if (c->hmax > 0.0 && 1.0 / c->hmax > c->cover_bound) c->cover_bound = 1.0 / c->hmax;
+    const double cf = 1.0 - c->qmin;   // margin for the rounding of h
+    if (c->hmax > 0.0 && cf / c->hmax > c->cover_bound) c->cover_bound = cf / c->hmax;
     if (1.0 / c->sP < c->pack_bound) c->pack_bound = 1.0 / c->sP;
     c->dy1 = c->sP * c->dsum;
     c->dz1 = 0.0;
@@ -185,8 +186,7 @@ MWU_DEV void finish_vcB(Ctl *c, const double *rec, const double *forced)
 // ------------------------------------------------------------------ kernels
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_init_x(VcDev<T> vd, Ctl *ctl, int have_x0, double *part,
-                                                    double *gpart, unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void vc_init_x(VcDev<T> vd, Ctl *ctl, int have_x0, double *part)
 {
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
@@ -201,39 +201,58 @@ __global__ __launch_bounds__(BLOCK) void vc_init_x(VcDev<T> vd, Ctl *ctl, int ha
     }
     const Red red{1, 0, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
+    store_record(s_rec, 1, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void vc_init_x_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const Red red{1, 0, 0};
+    fold_records<1>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
         ctl->sumx = s_rec[0];
         ctl->y1 = ctl->sP * s_rec[0];
         ctl->dy1 = 0.0;
     }
 }
 
-// min over edges of x_u + x_w: the first LSE shift of a probe, and the final
-// min(Cx) of the outer search.
+// min over edges of x_u + x_w in FP64: the first LSE shift of a probe, and the
+// min(Cx) certificate of the outer search.
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_minz(VcDev<T> vd, Ctl *ctl, double *part, double *gpart,
-                                                  unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void vc_minz(VcDev<T> vd, Ctl *ctl, double *part)
 {
     __shared__ T s_val[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
-    __shared__ double s_wave[4 * 2];
+    __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
-    double v[2] = {0.0, INFINITY};
+    double v[1] = {INFINITY};
     auto stage = [&](int k) -> T { return vd.xd[vd.ucol[k]].x; };
     auto segval = [&](int u) -> T { return vd.xd[u].x; };
-    auto visit = [&](T xu, T xw, int) { v[1] = fmin(v[1], (double)xu + (double)xw); };   // FP64 certificate
+    auto visit = [&](T xu, T xw, int) { v[0] = fmin(v[0], (double)xu + (double)xw); };
     for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
         const Tile tl = vd.utiles[t];
         walk_tile<T>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
     }
-    const Red red{1, 1, 0};
-    block_combine<2>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_vc_start(ctl, s_rec);
+    const Red red{0, 1, 0};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 1, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void vc_minz_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const Red red{0, 1, 0};
+    fold_records<1>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        double r[2] = {0.0, s_rec[0]};
+        finish_vc_start(ctl, r);
+    }
 }
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, double *part, double *gpart,
-                                                     unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, double *part)
 {
     __shared__ T s_val[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
@@ -269,24 +288,45 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
         } else {
             const T xu = segval(tl.s0);
             auto elem = [&](int k) -> T { return term(xu, stage(k)); };
-            chunk_tile<T>(tl, elem, epi, s_tacc, vd.flpart, vd.flfirst, vd.flcount, vd.fltick);
+            chunk_tile<T>(tl, elem, s_tacc, vd.flpart, vd.flong.lfirst);
         }
     }
     const Red red{1, 1, 0};
     block_combine<2>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_vcA(ctl, s_rec);
+    store_record(s_rec, 2, part);
 }
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, double *part, double *gpart,
-                                                     unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    __shared__ double s_lng[QMAX];
+    if (ctl->phase != PH_ROW) return;
+    const Red red{1, 1, 0};
+    double v[2] = {0.0, INFINITY};
+    for (int l = threadIdx.x; l < vd.flong.nlong; l += BLOCK) {
+        const T acc = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
+        vd.h[vd.flong.lseg[l]] = acc;
+        v[0] += (double)acc;
+    }
+    block_combine<2>(v, red, 0, s_wave, s_lng);
+    fold_records<2>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
+        finish_vcA(ctl, s_rec);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, double *part)
 {
     __shared__ double s_wave[4 * 3];
     __shared__ double s_rec[QMAX];
     const int ph = ctl->phase;
     if (ph != PH_COL && ph != PH_COMMIT) return;
     const T a = (T)ctl->alpha;
-    const double invSu = ctl->invSu, g = ctl->sP, step = ctl->step;
+    const double invSu = ctl->invSu, g = ctl->sP, step = ctl->step, qmin = ctl->qmin;
     const bool commit = ph == PH_COMMIT;
     double v[3] = {0.0, -INFINITY, -INFINITY};   // sum d | max d | max h
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
@@ -297,7 +337,7 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, doubl
             double di = 0.0;
             if (h > 0.0) {
                 const double q = 1.0 - g / h;
-                if (q > 0.0) di = step * q * (double)p.x;
+                if (q > qmin) di = step * q * (double)p.x;
             }
             p.d = (T)di;
             v[0] += (double)p.d;
@@ -307,17 +347,30 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, doubl
         }
         vd.xd[i] = p;
     }
+    if (commit) return;
     const Red red{1, 0, 2};
     block_combine<3>(v, red, 0, s_wave, s_rec);
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
-        if (commit) { ctl->alpha = 0.0; ctl->phase = PH_DONE; }
-        else finish_vcB(ctl, s_rec, vd.forced);
-    }
+    store_record(s_rec, 3, part);
 }
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part,
-                                                      double *gpart, unsigned *tick)
+__global__ __launch_bounds__(BLOCK) void vc_passB_fin(VcDev<T> vd, Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 3];
+    __shared__ double s_rec[QMAX];
+    const int ph = ctl->phase;
+    if (ph != PH_COL && ph != PH_COMMIT) return;
+    if (ph == PH_COMMIT) {
+        if (threadIdx.x == 0 && !held(ctl)) { ctl->alpha = 0.0; ctl->phase = PH_DONE; }
+        return;
+    }
+    const Red red{1, 0, 2};
+    fold_records<3>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) finish_vcB(ctl, s_rec, vd.forced);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part)
 {
     __shared__ XD<T> s_val[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
@@ -332,9 +385,9 @@ __global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, doub
         const double a = ctl->ref_alpha;
         const bool second = ctl->ref_valid != 0;
         const double zm = ctl->rfZmin;
-        double v[2] = {0.0, INFINITY};   // pass 2: [- | sum]; pass 1: [- | min z']
+        double v[2] = {0.0, INFINITY};   // pass 2: [sum | -]; pass 1: [- | min z']
         auto visit = [&](XD<T> pu, XD<T> pw, int) {
-            const double zp = (double)(pu.x + pw.x) + a * (double)(pu.d + pw.d);
+            const double zp = ((double)pu.x + (double)pw.x) + a * ((double)pu.d + (double)pw.d);
             if (second) v[0] += exp(-eta * (zp - zm));
             else v[1] = fmin(v[1], zp);
         };
@@ -344,38 +397,52 @@ __global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, doub
         }
         const Red red{1, 1, 0};
         block_combine<2>(v, red, 0, s_wave, s_rec);
-        if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) {
-            // records expected by finish_search: pass 1 [min z' | max eta*y'], pass 2 [sumP | sumC]
-            double r[2];
-            if (!second) { r[0] = s_rec[1]; r[1] = -INFINITY; }
-            else { r[0] = 1.0; r[1] = s_rec[0]; }
-            finish_search(ctl, r);
-        }
+        store_record(s_rec, 2, part);
         return;
     }
     const int nc = ctl->ncand;
-    double cd[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) cd[k] = ctl->cand[k];
+    const double *cand = ctl->cand;
+    const double a0 = ctl->cand[0];
     const double gdel = ctl->gdelta, Lw = ctl->LCw;
-    double acc[3 * KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) { acc[k] = 0.0; acc[KC + k] = 0.0; acc[2 * KC + k] = INFINITY; }
+    CovAcc<T> ca;
+    ca.init();
     auto visit = [&](XD<T> pu, XD<T> pw, int) {
         const T z = pu.x + pw.x;
         const T dz = pu.d + pw.d;
         const T u = exp_t((T)(-eta * ((double)z - Lw)));
-        cov_row_terms<T>(kind, nc, cd, gdel, eta, u, z, dz, acc);
+        cov_row_terms<T>(kind, nc, cand, a0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
     };
     for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
         const Tile tl = vd.utiles[t];
         walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
     }
-    if (threadIdx.x < KC) s_rec[threadIdx.x] = 0.0;   // no packing rows
+    ca.combine(s_wave, s_rec + KC);
+    store_record(s_rec + KC, 3 * KC, part);   // records hold the covering sums only
+}
+
+__global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 3 * KC];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_SEARCH) return;
+    if (ctl->skind == SK_REFINE) {
+        const Red red{1, 1, 0};
+        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+        if (threadIdx.x == 0) {
+            // finish_search expects pass 1 [min z' | max eta*y'], pass 2 [sumP | sumC]
+            double r[2];
+            if (ctl->ref_valid == 0) { r[0] = s_rec[1]; r[1] = -INFINITY; }
+            else { r[0] = 1.0; r[1] = s_rec[0]; }
+            finish_search(ctl, r);
+        }
+        return;
+    }
     const Red redc{3 * KC, KC, 0};
-    block_combine<3 * KC>(acc, redc, KC, s_wave, s_rec + KC);
-    const Red red{3 * KC, KC, 0};
-    if (grid_reduce(s_rec, red, part, gpart, tick) && threadIdx.x == 0) finish_search(ctl, s_rec);
+    fold_records<3 * KC>(part, G, redc, KC, s_wave, s_rec + KC);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < KC; ++k) s_rec[k] = 0.0;   // no packing rows: Psi = a * dy1
+        finish_search(ctl, s_rec);
+    }
 }
 
 template <class T>
@@ -412,34 +479,36 @@ __global__ void vc_import_k(VcDev<T> vd, const double *src)
 
 // ------------------------------------------------------------------ launchers
 
+#define VLAUNCH(kernel, grid, ...) hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, st, __VA_ARGS__)
+
 template <class T>
 void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, bool have_x0)
 {
-    hipLaunchKernelGGL(vc_init_x<T>, dim3(L.grid_v), dim3(BLOCK), 0, st, v, ctl, have_x0 ? 1 : 0,
-                       L.partials, L.gpart, L.tickets);
-    hipLaunchKernelGGL(vc_minz<T>, dim3(L.grid_utile), dim3(BLOCK), 0, st, v, ctl, L.partials, L.gpart,
-                       L.tickets);
+    VLAUNCH(vc_init_x<T>, L.grid_v, v, ctl, have_x0 ? 1 : 0, L.partials);
+    VLAUNCH(vc_init_x_fin, 1, ctl, (const double *)L.partials, L.grid_v);
+    VLAUNCH(vc_minz<T>, L.grid_utile, v, ctl, L.partials);
+    VLAUNCH(vc_minz_fin, 1, ctl, (const double *)L.partials, L.grid_utile);
 }
 
 template <class T>
 void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL(vc_passA_k<T>, dim3(L.grid_ftile), dim3(BLOCK), 0, st, v, ctl, L.partials,
-                       L.gpart, L.tickets);
+    VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials);
+    VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile);
 }
 
 template <class T>
 void vc_passB(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL(vc_passB_k<T>, dim3(L.grid_v), dim3(BLOCK), 0, st, v, ctl, L.partials, L.gpart,
-                       L.tickets);
+    VLAUNCH(vc_passB_k<T>, L.grid_v, v, ctl, L.partials);
+    VLAUNCH(vc_passB_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_v);
 }
 
 template <class T>
 void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL(vc_search_k<T>, dim3(L.grid_utile), dim3(BLOCK), 0, st, v, ctl, L.partials,
-                       L.gpart, L.tickets);
+    VLAUNCH(vc_search_k<T>, L.grid_utile, v, ctl, L.partials);
+    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_utile);
 }
 
 template <class T>
@@ -456,14 +525,14 @@ void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st)
 {
     const int g = which < 2 ? std::max(1, std::min(GRID_MAX, (v.nv + BLOCK - 1) / BLOCK))
                             : std::max(1, std::min(GRID_MAX, v.nutiles));
-    hipLaunchKernelGGL(vc_export_k<T>, dim3(g), dim3(BLOCK), 0, st, v, which, out);
+    VLAUNCH(vc_export_k<T>, g, v, which, out);
 }
 
 template <class T>
 void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st)
 {
     const int g = std::max(1, std::min(GRID_MAX, (v.nv + BLOCK - 1) / BLOCK));
-    hipLaunchKernelGGL(vc_import_k<T>, dim3(g), dim3(BLOCK), 0, st, v, src);
+    VLAUNCH(vc_import_k<T>, g, v, src);
 }
 
 #define MWU_VC_INSTANTIATE(T)                                                                    \
