@@ -62,7 +62,20 @@ def pass_times(s, reps, param):
     return out
 
 
-def cpu_baseline(g, gpu_iters, iters=4):
+def copy_calibration(mib):
+    """A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
+    readings give the scale between counter units and bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {mib} MiB")
+
+
+def cpu_baseline(g, gpu_iters, iters=8):
     """The plain FP64 oracle on this host: a bounded number of iterations of the
     first probe, scaled to the GPU's iteration count."""
     import numpy as np
@@ -99,6 +112,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=50)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -114,6 +129,8 @@ def main():
     log(f"graph: {g.num_vertices} vertices, {g.num_edges} edges, max degree {int(g.degrees().max())} "
         f"({time.perf_counter() - t:.1f}s)")
 
+    if args.copy_calib_mib:
+        copy_calibration(args.copy_calib_mib)
     torch.cuda.synchronize()
     s32, create32, r32 = run_solves(mwu, g, mwu.MIXED_FP32_FP64, args.steps, args.warmup)
     torch.cuda.synchronize()

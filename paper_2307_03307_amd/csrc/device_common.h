@@ -38,25 +38,65 @@ MWU_DEV double red_id(int q, Red r)
     return -INFINITY;
 }
 
-// Combine per-thread values v[0..Q) over the block into out[0..Q) (LDS).
-// Butterfly inside each wave64, then the four wave results in a fixed order:
-// the result does not depend on timing.
+// Reduce-scatter inside a wave64.  The Q values of every lane are halved at
+// each exchange while Q stays even: a lane keeps one half (chosen by its bit
+// of the exchange mask), sends the other half to its partner and folds the
+// half it receives, so the cost is about Q exchanges instead of 6 Q.  When
+// the count is odd the remaining exchanges are a full butterfly.  Afterwards
+// lane l holds the wave totals of quantities qb .. qb + N - 1 (N = rs_count),
+// and lanes that differ only in the butterfly bits hold identical values.
+constexpr int rs_count(int n, int m) { return m == 0 ? n : (n % 2 == 0 ? rs_count(n / 2, m / 2) : n); }
+constexpr int rs_full(int n, int m) { return m == 0 ? 0 : (n % 2 == 0 ? rs_full(n / 2, m / 2) : m); }
+
+template <int N, int M>
+struct WaveRS {
+    static MWU_DEV void run(double *v, int lane, int &qb, Red r, int qoff)
+    {
+        if constexpr (M == 0) {
+            return;
+        } else if constexpr (N % 2 == 0) {
+            constexpr int H = N / 2;
+            const bool up = (lane & M) != 0;
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const double keep = up ? v[i + H] : v[i];
+                const double send = up ? v[i] : v[i + H];
+                const double recv = __shfl_xor(send, M);
+                v[i] = red_op(keep, recv, qb + i + (up ? H : 0) + qoff, r);
+            }
+            qb += up ? H : 0;
+            WaveRS<H, M / 2>::run(v, lane, qb, r, qoff);
+        } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = red_op(v[i], __shfl_xor(v[i], M), qb + i + qoff, r);
+            WaveRS<N, M / 2>::run(v, lane, qb, r, qoff);
+        }
+    }
+};
+
+// Combine per-thread values v[0..Q) over the block into out[0..Q) (LDS):
+// reduce-scatter inside each wave, then the four wave results in a fixed
+// order.  The result does not depend on timing.
 template <int Q>
 MWU_DEV void block_combine(const double (&v)[Q], Red r, int qoff, double *s_wave, double *out)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int N = rs_count(Q, 32);
+    constexpr int F = rs_full(Q, 32);
+    double w[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        double a = v[q];
+    for (int q = 0; q < Q; ++q) w[q] = v[q];
+    int qb = 0;
+    WaveRS<Q, 32>::run(w, lane, qb, r, qoff);
+    if (F == 0 || (lane & (2 * F - 1)) == 0) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) a = red_op(a, __shfl_xor(a, o), q + qoff, r);
-        if (lane == 0) s_wave[wv * Q + q] = a;
+        for (int i = 0; i < N; ++i) s_wave[wv * Q + qb + i] = w[i];
     }
     __syncthreads();
     if (threadIdx.x < Q) {
         const int q = threadIdx.x;
         double a = s_wave[q];
-        for (int w = 1; w < BLOCK / 64; ++w) a = red_op(a, s_wave[w * Q + q], q + qoff, r);
+        for (int k = 1; k < BLOCK / 64; ++k) a = red_op(a, s_wave[k * Q + q], q + qoff, r);
         out[q] = a;
     }
     __syncthreads();
@@ -73,21 +113,31 @@ MWU_DEV void store_record(const double *s_rec, int Q, double *partials)
     if (threadIdx.x < Q) partials[(size_t)blockIdx.x * QMAX + threadIdx.x] = s_rec[threadIdx.x];
 }
 
-// Fold the G records of a pass (finisher kernel, one workgroup): thread t
-// folds records t, t + BLOCK, ... in order, then the block combines.  Record
+// Fold the G records of a pass (finisher kernel, one workgroup).  BLOCK / Q
+// threads share each quantity: thread (q, j) folds records j, j + BLOCK/Q,
+// ... in order, then thread q folds the BLOCK/Q partials in order.  Record
 // entry q is reduced with the operation of layout position q + qoff.
 template <int Q>
 MWU_DEV void fold_records(const double *partials, int G, Red r, int qoff, double *s_wave, double *out)
 {
-    double v[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = red_id(q + qoff, r);
-    for (int b = threadIdx.x; b < G; b += BLOCK) {
-        const double *rec = partials + (size_t)b * QMAX;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], rec[q], q + qoff, r);
+    static_assert(Q <= BLOCK, "record too wide");
+    __shared__ double s_fold[BLOCK];
+    constexpr int NT = BLOCK / Q;
+    const int t = threadIdx.x;
+    if (t < NT * Q) {
+        const int q = t % Q, j = t / Q;
+        double a = red_id(q + qoff, r);
+        for (int b = j; b < G; b += NT) a = red_op(a, partials[(size_t)b * QMAX + q], q + qoff, r);
+        s_fold[j * Q + q] = a;
     }
-    block_combine<Q>(v, r, qoff, s_wave, out);
+    __syncthreads();
+    if (t < Q) {
+        double a = s_fold[t];
+        for (int j = 1; j < NT; ++j) a = red_op(a, s_fold[j * Q + t], t + qoff, r);
+        out[t] = a;
+    }
+    __syncthreads();
+    (void)s_wave;
 }
 
 // ------------------------------------------------------------ accumulators
@@ -99,6 +149,77 @@ struct Pair {
 };
 
 template <class T> MWU_DEV T acc_zero() { return T{}; }
+
+// Lane exchanges of an accumulator (a scalar or a Pair).
+template <class T> MWU_DEV T shfl_up_acc(T v, int d) { return __shfl_up(v, d); }
+template <class T> MWU_DEV Pair<T> shfl_up_acc(Pair<T> v, int d)
+{
+    return Pair<T>{__shfl_up(v.g, d), __shfl_up(v.h, d)};
+}
+template <class T> MWU_DEV T shfl_xor_acc(T v, int m) { return __shfl_xor(v, m); }
+template <class T> MWU_DEV Pair<T> shfl_xor_acc(Pair<T> v, int m)
+{
+    return Pair<T>{__shfl_xor(v.g, m), __shfl_xor(v.h, m)};
+}
+
+// Completion of segments that cross thread boundaries inside a tile.
+// Thread t holds the partial tacc of its last segment tseg when that segment
+// continues past its items (else tseg = -1), and pend >= 0 when its first
+// segment began in an earlier thread and ends in its items.  Threads whose
+// tail partials belong to one segment form a contiguous run, so a segmented
+// inclusive scan (in-wave shuffles, then a fixed-order carry across the four
+// waves) gives every owner the sum of the run right before it.  Returns that
+// sum for owners and zero for every other thread.  All threads must call.
+template <class Acc>
+MWU_DEV Acc seg_carry(int tseg, Acc tacc, int pend)
+{
+    __shared__ int32_t s_kf[BLOCK / 64], s_kl[BLOCK / 64];
+    __shared__ Acc s_vl[BLOCK / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    Acc v = tacc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const Acc o = shfl_up_acc(v, d);
+        const int ko = __shfl_up(tseg, d);
+        if (lane >= d && tseg >= 0 && ko == tseg) v += o;
+    }
+    const Acc pv = shfl_up_acc(v, 1);
+    const int pk = __shfl_up(tseg, 1);
+    const int kf = __shfl(tseg, 0);
+    if (lane == 0) s_kf[w] = tseg;
+    if (lane == 63) { s_kl[w] = tseg; s_vl[w] = v; }
+    __syncthreads();
+    // inclusive run value at the last thread of each wave, waves in order
+    Acc incl[BLOCK / 64];
+    incl[0] = s_vl[0];
+#pragma unroll
+    for (int i = 1; i < BLOCK / 64; ++i) {
+        incl[i] = s_vl[i];
+        if (s_kl[i] >= 0 && s_kf[i] == s_kl[i] && s_kl[i - 1] == s_kl[i]) incl[i] += incl[i - 1];
+    }
+    Acc carry = acc_zero<Acc>();
+    if (pend >= 0) {
+        if (lane > 0) {
+            if (pk == pend) {
+                carry = pv;
+                if (w > 0 && kf == pend && s_kl[w - 1] == pend) {
+                    Acc c = incl[0];
+#pragma unroll
+                    for (int i = 1; i < BLOCK / 64; ++i)
+                        if (i == w - 1) c = incl[i];
+                    Acc t = c;
+                    t += carry;
+                    carry = t;
+                }
+            }
+        } else if (w > 0 && s_kl[w - 1] == pend) {
+#pragma unroll
+            for (int i = 0; i < BLOCK / 64; ++i)
+                if (i == w - 1) carry = incl[i];
+        }
+    }
+    return carry;
+}
 
 // ------------------------------------------------------------ segment tiles
 
@@ -161,12 +282,9 @@ MWU_DEV void seg_tile(const Tile &tl, const int32_t *__restrict__ ptr, ElemF &el
             tacc = acc;
         }
     }
-    s_tseg[tid] = tseg;
-    s_tacc[tid] = tacc;
-    __syncthreads();
+    Acc tot = seg_carry<Acc>(tseg, tacc, pend);
     if (pend >= 0) {
-        Acc tot = pacc;
-        for (int t = tid - 1; t >= 0 && s_tseg[t] == pend; --t) tot += s_tacc[t];
+        tot += pacc;
         epi(tl.s0 + pend, tot);
     }
     for (int s = tid; s < S; s += BLOCK)
@@ -182,13 +300,15 @@ MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, Acc *s_tacc, Acc *lpart, co
     const int tid = threadIdx.x;
     Acc acc = acc_zero<Acc>();
     for (int k = tl.k0 + tid; k < tl.k1; k += BLOCK) acc += elem(k);
-    s_tacc[tid] = acc;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_acc(acc, m);
+    if ((tid & 63) == 0) s_tacc[tid >> 6] = acc;
     __syncthreads();
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if (tid < w) s_tacc[tid] += s_tacc[tid + w];
-        __syncthreads();
+    if (tid == 0) {
+        Acc tot = s_tacc[0];
+        for (int w = 1; w < BLOCK / 64; ++w) tot += s_tacc[w];
+        lpart[lfirst[tl.lid] + tl.cidx] = tot;
     }
-    if (tid == 0) lpart[lfirst[tl.lid] + tl.cidx] = s_tacc[0];
     __syncthreads();
 }
 
@@ -202,74 +322,61 @@ MWU_DEV Acc long_sum(int lid, const Acc *lpart, const int32_t *lfirst, const int
     return tot;
 }
 
-// ------------------------------------------------- search terms of one row
-//
-// Covering row with weight u (unnormalized, u = exp(-eta (z - L))), value z
-// and direction dz; adds, for every candidate step a_k of the pass,
-//   acc[k]      += u expm1(-eta a_k dz)      (cancellation-free Phi sum)
-//   acc[KC + k] += u exp(-eta a_k dz)        (direct Phi sum)
-//   zmn[k]       = min(zmn[k], z + a_k dz)   (early return of Algorithm 3)
-// The sums are double; the minima stay in the storage type (z is stored in
-// it).  Exponential grids use expm1(2x) = expm1(x)(expm1(x) + 2) and squaring,
-// bisection grids the addition rule expm1(x+y) = expm1(x) + expm1(y) +
-// expm1(x) expm1(y); float re-seeds the squared term every 4 candidates.
-template <class T>
-MWU_DEV void cov_row_terms(int kind, int nc, const double *cand, double a0, double gdel, double eta,
-                           T u, T z, T dz, T *acc, T *zmn)
+// Covering-row terms of one search pass for candidate k (KIND fixed per
+// launch, no data-dependent branches): acc[k] += u expm1(-b_k), acc[KC+k] +=
+// u e^{-b_k}, zmn[k] = min(zmn[k], z + a_k dz) with b_k = eta a_k dz.  On the
+// exponential grid a_k = a0 2^k, so expm1(-b_k) follows from expm1(2x) =
+// expm1(x)(expm1(x) + 2) and e^{-b_k} from squaring (float re-seeds the
+// squared term from exp every 4 candidates); on the bisection grid a_k = a0 +
+// k gdel and expm1(x + y) = expm1(x) + expm1(y) + expm1(x) expm1(y).  A zero
+// weight or a zero dz needs no special case: the terms come out as 0 and u.
+template <class T, int KIND>
+MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, double eta, T u, T z, T dz,
+                       T *acc, T *zmn)
 {
-    if (kind == SK_LIST) {   // arbitrary candidates, direct evaluation (forced steps, probes)
+    if constexpr (KIND == SK_LIST) {   // arbitrary candidates, direct evaluation
 #pragma unroll
         for (int k = 0; k < KC; ++k)
             if (k < nc) {
                 const double a = cand[k];
                 zmn[k] = fmin(zmn[k], z + (T)a * dz);
-                if (u > T(0)) {
-                    const T b = (T)(eta * a * (double)dz);
-                    acc[k] += u * expm1_t(-b);
-                    acc[KC + k] += u * exp_t(-b);
-                }
+                const T b = (T)(eta * a * (double)dz);
+                acc[k] += u * expm1_t(-b);
+                acc[KC + k] += u * exp_t(-b);
             }
-        return;
-    }
-    {   // candidate k: a0 * 2^k (exponential grid, exact) or a0 + k * gdel (bisection grid)
+    } else {
         T ak = (T)a0;
         const T step = (T)gdel;
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
             zmn[k] = fmin(zmn[k], z + ak * dz);
-            ak = kind == SK_EXP ? ak + ak : ak + step;
+            ak = KIND == SK_EXP ? ak + ak : ak + step;
         }
-    }
-    if (!(u > T(0))) return;
-    if (!(dz > T(0))) {
+        const T b0 = (T)(eta * a0 * (double)dz);
+        T m = expm1_t(-b0);
+        T t = exp_t(-b0);
+        if constexpr (KIND == SK_EXP) {
 #pragma unroll
-        for (int k = 0; k < KC; ++k) acc[KC + k] += u;
-        return;
-    }
-    const T b0 = (T)(eta * a0 * (double)dz);
-    T m = expm1_t(-b0);
-    T t = exp_t(-b0);
-    if (kind == SK_EXP) {
+            for (int k = 0; k < KC; ++k) {
+                acc[k] += u * m;
+                acc[KC + k] += u * t;
+                m = m * (m + T(2));
+                if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KC)
+                    t = exp_t((T)(-eta * a0 * (double)(1 << (k + 1)) * (double)dz));
+                else
+                    t = t * t;
+            }
+        } else {
+            const T bd = (T)(eta * gdel * (double)dz);
+            const T mr = expm1_t(-bd);
+            const T tr = exp_t(-bd);
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            acc[k] += u * m;
-            acc[KC + k] += u * t;
-            m = m * (m + T(2));
-            if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KC)
-                t = exp_t((T)(-eta * a0 * (double)(1 << (k + 1)) * (double)dz));
-            else
-                t = t * t;
-        }
-    } else {
-        const T bd = (T)(eta * gdel * (double)dz);
-        const T mr = expm1_t(-bd);
-        const T tr = exp_t(-bd);
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            acc[k] += u * m;
-            acc[KC + k] += u * t;
-            m = m + mr + m * mr;
-            t = t * tr;
+            for (int k = 0; k < KC; ++k) {
+                acc[k] += u * m;
+                acc[KC + k] += u * t;
+                m = m + mr + m * mr;
+                t = t * tr;
+            }
         }
     }
 }

@@ -137,8 +137,7 @@ struct XD { T x, d; };
 template <class T>
 struct VcDev {
     int32_t nv, ne;
-    const int32_t *uptr, *ucol;         // upper adjacency: edges (u, w) with u < w, canonical order
-    const Tile *utiles; int32_t nutiles;
+    const int32_t *eu, *ew;             // edges (u, w), u < w, sorted: one visit per covering row
     const int32_t *fptr, *fcol;         // full adjacency (both directions)
     const Tile *ftiles; int32_t nftiles;
     LongSegs flong;
@@ -192,7 +191,7 @@ void set_phase(Ctl *ctl, int phase, hipStream_t st);
 struct VcLaunch {
     int grid_v;        // element-wise over vertices
     int grid_ftile;    // full-adjacency tiles
-    int grid_utile;    // upper-adjacency tiles
+    int grid_e;        // edge passes (search, min z, export)
     double *partials;
 };
 template <class T> void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,

@@ -412,6 +412,59 @@ __global__ __launch_bounds__(BLOCK) void k_stats_fin(GenericDev<T> gd, Ctl *ctl,
     }
 }
 
+// Candidate sums of one search pass over the stored rows (KIND fixed per
+// launch): packing s1P[k] = sum_i w_i expm1(eta a_k dy_i); covering sums and
+// minima as in cov_terms.  Leaves [s1P | s1C | s2C | zmin] in s_rec.
+template <class T, int KIND>
+__device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_wave, double *s_rec)
+{
+    const double eta = ctl->eta;
+    const int stride = gridDim.x * BLOCK;
+    const int r0 = blockIdx.x * BLOCK + threadIdx.x;
+    const int mPc = gd.mPc, mR = gd.mR;
+    const int nc = ctl->ncand;
+    const double *cand = ctl->cand;
+    const double a0 = ctl->cand[0];
+    const double gdel = ctl->gdelta;
+    {
+        double s1[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) s1[k] = 0.0;
+        for (int r = r0; r < mPc; r += stride) {
+            const T w = gd.wu[r], dy = gd.dyz[r];
+            if constexpr (KIND == SK_EXP) {
+                T m = expm1_t((T)(eta * a0 * (double)dy));
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    s1[k] += (double)(w * m);
+                    m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
+                }
+            } else if constexpr (KIND == SK_GRID) {
+                T m = expm1_t((T)(eta * a0 * (double)dy));
+                const T mr = expm1_t((T)(eta * gdel * (double)dy));
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    s1[k] += (double)(w * m);
+                    m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+                    if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
+            }
+        }
+        const Red redp{KC, 0, 0};
+        block_combine<KC>(s1, redp, 0, s_wave, s_rec);
+    }
+    {
+        CovAcc<T> ca;
+        ca.init();
+        for (int r = mPc + r0; r < mR; r += stride)
+            cov_terms<T, KIND>(nc, cand, a0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
+        ca.combine(s_wave, s_rec + KC);
+    }
+}
+
 // Search pass over the stored rows: for each candidate step, the sums that
 // give Psi and Phi (Section 4.1) plus min(z + a dz) (Algorithm 3 early return).
 template <class T>
@@ -451,50 +504,10 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
         }
         return;
     }
-    const int nc = ctl->ncand;
-    const double *cand = ctl->cand;
-    const double a0 = ctl->cand[0];
-    const double gdel = ctl->gdelta;
-    // ---- packing rows: s1P[k] = sum_i w_i expm1(eta a_k dy_i)
-    {
-        double s1[KC];
-#pragma unroll
-        for (int k = 0; k < KC; ++k) s1[k] = 0.0;
-        for (int r = r0; r < mPc; r += stride) {
-            const T w = gd.wu[r], dy = gd.dyz[r];
-            if (!(w > T(0)) || !(dy > T(0))) continue;
-            if (kind == SK_EXP) {
-                T m = expm1_t((T)(eta * a0 * (double)dy));
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    s1[k] += (double)(w * m);
-                    m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
-                }
-            } else if (kind == SK_GRID) {
-                T m = expm1_t((T)(eta * a0 * (double)dy));
-                const T mr = expm1_t((T)(eta * gdel * (double)dy));
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    s1[k] += (double)(w * m);
-                    m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < KC; ++k)
-                    if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
-            }
-        }
-        const Red redp{KC, 0, 0};
-        block_combine<KC>(s1, redp, 0, s_wave, s_rec);
-    }
-    // ---- covering rows: s1C[k] = sum_j u_j expm1(-b_jk), s2C[k] = sum_j u_j e^{-b_jk},
-    //      zmin[k] = min_j z_j + a_k dz_j, with b_jk = eta a_k dz_j
-    {
-        CovAcc<T> ca;
-        ca.init();
-        for (int r = mPc + r0; r < mR; r += stride)
-            cov_row_terms<T>(kind, nc, cand, a0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
-        ca.combine(s_wave, s_rec + KC);
+    switch (kind) {
+    case SK_EXP: search_rows<T, SK_EXP>(gd, ctl, s_wave, s_rec); break;
+    case SK_GRID: search_rows<T, SK_GRID>(gd, ctl, s_wave, s_rec); break;
+    default: search_rows<T, SK_LIST>(gd, ctl, s_wave, s_rec); break;
     }
     store_record(s_rec, 4 * KC, part);
 }

@@ -106,6 +106,7 @@ struct Solver {
     EdgeList dens_graph;             // non-isolated vertex ids, canonical
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int num_cus = 256;
     int device = 0;
     DevBuf ctl_buf;
     DevBuf trace_buf;                // accepted steps of the current probe (max_iter doubles)

@@ -15,48 +15,49 @@ class VcoverProgram : public Program {
     VcoverProgram(Solver &s, const EdgeList &el, const std::vector<int64_t> &newid, int64_t nv) : s_(s)
     {
         nv_ = nv;
-        // canonical edges (min, max) of compact ids, sorted: edge e = position
+        ne_ = el.ne;
+        if (2 * ne_ >= INT32_MAX) throw ApiError{MWU_ERR_TOO_LARGE, "too many edges"};
+        // device vertex order: degree descending, ties by compact id, so the
+        // neighbours gathered most often share cache lines
+        std::vector<int64_t> deg(nv, 0);
+        for (int64_t e = 0; e < el.ne; ++e) { deg[newid[el.u[e]]]++; deg[newid[el.v[e]]]++; }
+        std::vector<int32_t> order(nv);
+        for (int64_t i = 0; i < nv; ++i) order[i] = (int32_t)i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+        dev_.assign(nv, 0);
+        for (int64_t r = 0; r < nv; ++r) dev_[order[r]] = (int32_t)r;
+        // edges (u, w), u < w in device ids, sorted
         std::vector<uint64_t> key(el.ne);
         for (int64_t e = 0; e < el.ne; ++e) {
-            const int64_t a = newid[el.u[e]], b = newid[el.v[e]];
+            const int64_t a = dev_[newid[el.u[e]]], b = dev_[newid[el.v[e]]];
             key[e] = (uint64_t)std::min(a, b) * (uint64_t)nv + (uint64_t)std::max(a, b);
         }
         std::sort(key.begin(), key.end());
-        ne_ = el.ne;
-        if (2 * ne_ >= INT32_MAX) throw ApiError{MWU_ERR_TOO_LARGE, "too many edges"};
-        std::vector<int32_t> uptr(nv + 1, 0), ucol(ne_), fptr(nv + 1, 0), fcol(2 * ne_);
+        std::vector<int32_t> eu(ne_), ew(ne_), fptr(nv + 1, 0), fcol(2 * ne_);
         for (int64_t e = 0; e < ne_; ++e) {
             const int64_t a = key[e] / nv, b = key[e] % nv;
-            uptr[a + 1]++;
+            eu[e] = (int32_t)a;
+            ew[e] = (int32_t)b;
             fptr[a + 1]++;
             fptr[b + 1]++;
-            ucol[e] = (int32_t)b;
-        }
-        for (int64_t v = 0; v < nv; ++v) { uptr[v + 1] += uptr[v]; fptr[v + 1] += fptr[v]; }
-        {
-            std::vector<int32_t> fill(fptr.begin(), fptr.end() - 1);
-            for (int64_t e = 0; e < ne_; ++e) {   // sorted keys keep every row sorted
-                const int64_t a = key[e] / nv, b = key[e] % nv;
-                fcol[fill[b]++] = (int32_t)a;
-            }
-            for (int64_t e = 0; e < ne_; ++e) {
-                const int64_t a = key[e] / nv, b = key[e] % nv;
-                fcol[fill[a]++] = (int32_t)b;
-            }
         }
         key.clear();
         key.shrink_to_fit();
-        TilePlan ut = build_tiles(uptr, nv);
+        for (int64_t v = 0; v < nv; ++v) fptr[v + 1] += fptr[v];
+        {
+            std::vector<int32_t> fill(fptr.begin(), fptr.end() - 1);
+            for (int64_t e = 0; e < ne_; ++e) fcol[fill[ew[e]]++] = eu[e];   // sorted rows
+            for (int64_t e = 0; e < ne_; ++e) fcol[fill[eu[e]]++] = ew[e];
+        }
         TilePlan ft = build_tiles(fptr, nv);
         auto up = [&](DevBuf &b, const void *src, size_t bytes) {
             b.alloc(bytes);
             if (bytes) HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
         };
-        up(uptr_, uptr.data(), uptr.size() * 4);
-        up(ucol_, ucol.data(), ucol.size() * 4);
+        up(eu_, eu.data(), eu.size() * 4);
+        up(ew_, ew.data(), ew.size() * 4);
         up(fptr_, fptr.data(), fptr.size() * 4);
         up(fcol_, fcol.data(), fcol.size() * 4);
-        up(utiles_, ut.tiles.data(), ut.tiles.size() * sizeof(Tile));
         up(ftiles_, ft.tiles.data(), ft.tiles.size() * sizeof(Tile));
         up(flseg_, ft.lseg.data(), ft.lseg.size() * 4);
         up(flfirst_, ft.lfirst.data(), ft.lfirst.size() * 4);
@@ -70,8 +71,7 @@ class VcoverProgram : public Program {
 
         vd_ = VcDev<T>{};
         vd_.nv = (int32_t)nv; vd_.ne = (int32_t)ne_;
-        vd_.uptr = uptr_.as<int32_t>(); vd_.ucol = ucol_.as<int32_t>();
-        vd_.utiles = utiles_.as<Tile>(); vd_.nutiles = (int32_t)ut.tiles.size();
+        vd_.eu = eu_.as<int32_t>(); vd_.ew = ew_.as<int32_t>();
         vd_.fptr = fptr_.as<int32_t>(); vd_.fcol = fcol_.as<int32_t>();
         vd_.ftiles = ftiles_.as<Tile>(); vd_.nftiles = (int32_t)ft.tiles.size();
         vd_.flong = LongSegs{flseg_.as<int32_t>(), flfirst_.as<int32_t>(), flcount_.as<int32_t>(),
@@ -79,13 +79,14 @@ class VcoverProgram : public Program {
         vd_.flpart = flpart_.as<T>();
         vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>();
         vd_.h_dbg = nullptr; vd_.forced = nullptr;
-        auto clampg = [](int64_t items, int64_t per) {
+        auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
-            return (int)std::max<int64_t>(1, std::min<int64_t>(g, GRID_MAX));
+            return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
         };
-        L_.grid_v = clampg(nv, BLOCK * 2);
-        L_.grid_ftile = clampg((int64_t)ft.tiles.size(), 1);
-        L_.grid_utile = clampg((int64_t)ut.tiles.size(), 1);
+        L_.grid_v = clampg(nv, BLOCK * 2, GRID_MAX);
+        L_.grid_ftile = clampg((int64_t)ft.tiles.size(), 1, GRID_MAX);
+        // edge passes: a few resident workgroups per CU, each over many edges
+        L_.grid_e = clampg(ne_, BLOCK * 8, 4 * s.num_cus);
         L_.partials = partials_.as<double>();
     }
 
@@ -98,9 +99,11 @@ class VcoverProgram : public Program {
 
     void upload_x(const double *host_x) override
     {
+        std::vector<double> xv(nv_);
+        for (int64_t c = 0; c < nv_; ++c) xv[dev_[c]] = host_x[c];
         DevBuf tmp;
         tmp.alloc(nv_ * 8);
-        HIP_OK(hipMemcpyAsync(tmp.p, host_x, nv_ * 8, hipMemcpyHostToDevice, s_.stream));
+        HIP_OK(hipMemcpyAsync(tmp.p, xv.data(), nv_ * 8, hipMemcpyHostToDevice, s_.stream));
         vc_import_x<T>(vd_, tmp.as<double>(), s_.stream);
         HIP_OK(hipStreamSynchronize(s_.stream));
     }
@@ -135,12 +138,15 @@ class VcoverProgram : public Program {
             std::fill(out, out + nv_, c.sP);
             return;
         }
-        case 3:
+        case 3: {
             need(len, nv_);
             if (!hdbg_.p) throw ApiError{MWU_ERR_STATE, "h is recorded by mwu_probe_direction"};
-            HIP_OK(hipMemcpyAsync(out, hdbg_.p, nv_ * 8, hipMemcpyDeviceToHost, s_.stream));
+            std::vector<double> t(nv_);
+            HIP_OK(hipMemcpyAsync(t.data(), hdbg_.p, nv_ * 8, hipMemcpyDeviceToHost, s_.stream));
             HIP_OK(hipStreamSynchronize(s_.stream));
+            for (int64_t c = 0; c < nv_; ++c) out[c] = t[dev_[c]];
             return;
+        }
         case 4: need(len, 1); out[0] = pull().y1; return;
         case 6: need(len, 1); out[0] = pull().dy1; return;
         case 5: need(len, ne_); export_to_host(vd_, 2, ne_, out); return;
@@ -183,7 +189,7 @@ class VcoverProgram : public Program {
         switch (which) {
         case 0: return 4.0 * (V + 1) + 8.0 * E + 2.0 * t * V + t * V;   // fptr, fcol, xd, h
         case 1: return 4.0 * t * V + t * V;                           // xd read+write, h
-        case 3: return 4.0 * (V + 1) + 4.0 * E + 2.0 * t * V;           // uptr, ucol, xd
+        case 3: return 8.0 * E + 2.0 * t * V;                           // eu, ew, xd
         }
         return 0.0;
     }
@@ -210,13 +216,41 @@ class VcoverProgram : public Program {
         HIP_OK(hipStreamSynchronize(s_.stream));
         return c;
     }
+    // Export a vector in the caller's order: vertices by compact id, edges in
+    // the canonical order (sorted (min, max) of compact ids).
     void export_to_host(const VcDev<T> &v, int which, int64_t len, double *out)
     {
         DevBuf tmp;
         tmp.alloc(len * 8);
         vc_export<T>(v, which, tmp.as<double>(), s_.stream);
-        HIP_OK(hipMemcpyAsync(out, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
+        std::vector<double> t(len);
+        HIP_OK(hipMemcpyAsync(t.data(), tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
         HIP_OK(hipStreamSynchronize(s_.stream));
+        if (which < 2) {
+            for (int64_t c = 0; c < nv_; ++c) out[c] = t[dev_[c]];
+            return;
+        }
+        const std::vector<int64_t> &pos = canonical_edges();
+        for (int64_t e = 0; e < ne_; ++e) out[e] = t[pos[e]];
+    }
+
+    // canonical edge e -> position in the device edge list (built on first use)
+    const std::vector<int64_t> &canonical_edges()
+    {
+        if ((int64_t)canon_.size() == ne_) return canon_;
+        std::vector<int32_t> eu(ne_), ew(ne_), cid(nv_);
+        HIP_OK(hipMemcpy(eu.data(), eu_.p, ne_ * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(ew.data(), ew_.p, ne_ * 4, hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < nv_; ++c) cid[dev_[c]] = (int32_t)c;
+        std::vector<std::pair<uint64_t, int64_t>> k(ne_);
+        for (int64_t e = 0; e < ne_; ++e) {
+            const uint64_t a = cid[eu[e]], b = cid[ew[e]];
+            k[e] = {std::min(a, b) * (uint64_t)nv_ + std::max(a, b), e};
+        }
+        std::sort(k.begin(), k.end());
+        canon_.resize(ne_);
+        for (int64_t e = 0; e < ne_; ++e) canon_[e] = k[e].second;
+        return canon_;
     }
 
     Solver &s_;
@@ -224,7 +258,9 @@ class VcoverProgram : public Program {
     bool debug_ = false;
     VcDev<T> vd_{};
     VcLaunch L_{};
-    DevBuf uptr_, ucol_, fptr_, fcol_, utiles_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
+    std::vector<int32_t> dev_;     // compact vertex id -> device vertex id
+    std::vector<int64_t> canon_;
+    DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
     DevBuf xd_, xbest_, h_, partials_, forced_, hdbg_;
 };
 

@@ -208,6 +208,7 @@ static void setup_device(Solver &s)
     HIP_OK(hipGetDeviceProperties(&prop, s.opt.device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         throw ApiError{MWU_ERR_DEVICE, "device is not gfx950"};
+    s.num_cus = std::max(1, prop.multiProcessorCount);
     if (s.opt.hip_stream) {
         s.stream = (hipStream_t)s.opt.hip_stream;
     } else {

@@ -11,27 +11,30 @@
 //           the weights and the LSE totals;
 //   pass B  (vertices) commit x += a d, direction d_v = (1/eta) max(0, 1 -
 //           g/h_v) x_v with g = 1/M, sum d (= M * Pd);
-//   search  (upper adjacency, one visit per edge) the K-candidate sums of
-//           Phi, with the forward product C d formed on the fly.
+//   search  (edge list, one visit per edge) the K-candidate sums of Phi,
+//           with the forward product C d formed on the fly.
 #include <algorithm>
 
 #include "device_common.h"
 
 namespace mwu {
 
-// Multi-segment tile where each term depends on its segment: stage(k) is
-// staged through LDS with coalesced loads, then term(seg_value, staged)
-// is accumulated per segment and epi(seg, sum) called once per segment.
+// Multi-segment tile where each term depends on its segment: stage(k) and
+// the segment values segval(s) are staged through LDS with coalesced loads
+// (all gathers of the tile in flight at once), then each thread walks ITEMS
+// consecutive nonzeros, accumulating term(segment value, staged value), and
+// epi(seg, sum) is called once per segment.  Segments crossing thread
+// boundaries are completed through seg_carry.
 template <class S, class Acc, class StageF, class SegF, class TermF, class EpiF>
 MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, StageF &stage, SegF &segval,
-                           TermF &term, EpiF &epi, S *s_val, int32_t *s_ptr, int32_t *s_tseg,
-                           Acc *s_tacc)
+                           TermF &term, EpiF &epi, S *s_val, S *s_seg, int32_t *s_ptr)
 {
     const int tid = threadIdx.x;
     const int S_ = tl.s1 - tl.s0;
     const int base = tl.k0;
     const int N = tl.k1 - tl.k0;
     for (int i = tid; i <= S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+    for (int i = tid; i < S_; i += BLOCK) s_seg[i] = segval(tl.s0 + i);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int k = j * BLOCK + tid;
@@ -43,7 +46,7 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
     int pend = -1, tseg = -1;
     Acc pacc = acc_zero<Acc>(), tacc = acc_zero<Acc>();
     if (a < N) {
-        int lo = 0, hi = S_;
+        int lo = 0, hi = S_;   // s_ptr[lo] <= a < s_ptr[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (s_ptr[mid] <= a) lo = mid; else hi = mid;
@@ -51,7 +54,7 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
         int s = lo;
         bool started = (s_ptr[s] == a);
         int end = s_ptr[s + 1];
-        auto sv = segval(tl.s0 + s);
+        S sv = s_seg[s];
         Acc acc = acc_zero<Acc>();
         for (int k = a; k < b; ++k) {
             if (k >= end) {
@@ -60,7 +63,7 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
                 do { ++s; end = s_ptr[s + 1]; } while (k >= end);   // empty segments: separate pass
                 started = true;
                 acc = acc_zero<Acc>();
-                sv = segval(tl.s0 + s);
+                sv = s_seg[s];
             }
             acc += term(sv, s_val[pad_idx(k)]);
         }
@@ -72,12 +75,9 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
             tacc = acc;
         }
     }
-    s_tseg[tid] = tseg;
-    s_tacc[tid] = tacc;
-    __syncthreads();
+    Acc tot = seg_carry<Acc>(tseg, tacc, pend);
     if (pend >= 0) {
-        Acc tot = pacc;
-        for (int t = tid - 1; t >= 0 && s_tseg[t] == pend; --t) tot += s_tacc[t];
+        tot += pacc;
         epi(tl.s0 + pend, tot);
     }
     for (int s = tid; s < S_; s += BLOCK)
@@ -85,47 +85,27 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
     __syncthreads();
 }
 
-// Visit every nonzero of a tile with its segment: visit(seg_value, staged).
-template <class S, class StageF, class SegF, class VisitF>
-MWU_DEV void walk_tile(const Tile &tl, const int32_t *__restrict__ ptr, StageF &stage, SegF &segval,
-                       VisitF &visit, S *s_val, int32_t *s_ptr)
+// Visit every edge once: visit(x_d of u, x_d of w, e).  Grid-stride over the
+// edge list, U edges per step so that their gathers are in flight together
+// (fewer in FP64, where the search accumulators take twice the registers).
+template <class T, class VisitF>
+MWU_DEV void for_edges(const VcDev<T> &vd, VisitF &visit)
 {
-    const int tid = threadIdx.x;
-    if (tl.lid >= 0) {   // chunk of one long segment
-        auto sv = segval(tl.s0);
-        for (int k = tl.k0 + tid; k < tl.k1; k += BLOCK) visit(sv, stage(k), k);
-        return;
-    }
-    const int S_ = tl.s1 - tl.s0;
-    const int base = tl.k0;
-    const int N = tl.k1 - tl.k0;
-    for (int i = tid; i <= S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+    constexpr int U = sizeof(T) == 4 ? 4 : 2;
+    const int stride = gridDim.x * BLOCK;
+    int e = blockIdx.x * BLOCK + threadIdx.x;
+    const int ne = vd.ne;
+    for (; e + (U - 1) * stride < ne; e += U * stride) {
+        int iu[U], iw[U];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = j * BLOCK + tid;
-        if (k < N) s_val[pad_idx(k)] = stage(base + k);
+        for (int j = 0; j < U; ++j) { iu[j] = vd.eu[e + j * stride]; iw[j] = vd.ew[e + j * stride]; }
+        XD<T> pu[U], pw[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) { pu[j] = vd.xd[iu[j]]; pw[j] = vd.xd[iw[j]]; }
+#pragma unroll
+        for (int j = 0; j < U; ++j) visit(pu[j], pw[j], e + j * stride);
     }
-    __syncthreads();
-    const int a = tid * ITEMS;
-    const int b = min(a + ITEMS, N);
-    if (a < N) {
-        int lo = 0, hi = S_;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_ptr[mid] <= a) lo = mid; else hi = mid;
-        }
-        int s = lo;
-        int end = s_ptr[s + 1];
-        auto sv = segval(tl.s0 + s);
-        for (int k = a; k < b; ++k) {
-            if (k >= end) {
-                do { ++s; end = s_ptr[s + 1]; } while (k >= end);
-                sv = segval(tl.s0 + s);
-            }
-            visit(sv, s_val[pad_idx(k)], base + k);
-        }
-    }
-    __syncthreads();
+    for (; e < ne; e += stride) visit(vd.xd[vd.eu[e]], vd.xd[vd.ew[e]], e);
 }
 
 // ------------------------------------------------------------------ finishers
@@ -222,18 +202,11 @@ __global__ __launch_bounds__(BLOCK) void vc_init_x_fin(Ctl *ctl, const double *p
 template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_minz(VcDev<T> vd, Ctl *ctl, double *part)
 {
-    __shared__ T s_val[TILE_LDS];
-    __shared__ int32_t s_ptr[TILE_NZ + 1];
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
     double v[1] = {INFINITY};
-    auto stage = [&](int k) -> T { return vd.xd[vd.ucol[k]].x; };
-    auto segval = [&](int u) -> T { return vd.xd[u].x; };
-    auto visit = [&](T xu, T xw, int) { v[0] = fmin(v[0], (double)xu + (double)xw); };
-    for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
-        const Tile tl = vd.utiles[t];
-        walk_tile<T>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
-    }
+    auto visit = [&](XD<T> pu, XD<T> pw, int) { v[0] = fmin(v[0], (double)pu.x + (double)pw.x); };
+    for_edges<T>(vd, visit);
     const Red red{0, 1, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
     store_record(s_rec, 1, part);
@@ -255,9 +228,9 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, double *part)
 {
     __shared__ T s_val[TILE_LDS];
+    __shared__ T s_seg[TILE_NZ];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
-    __shared__ int32_t s_tseg[BLOCK];
-    __shared__ T s_tacc[BLOCK];
+    __shared__ T s_tacc[BLOCK / 64];
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_ROW) return;
@@ -273,9 +246,9 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
         return p.x + a * p.d;
     };
     auto term = [&](T xu, T xw) -> T {
-        const T z = xu + xw;
-        v[1] = fmin(v[1], (double)z);
-        return exp_t((T)(-eta * ((double)z - Lw)));
+        const double z = (double)xu + (double)xw;
+        v[1] = fmin(v[1], z);
+        return exp_t((T)(-eta * (z - Lw)));
     };
     auto epi = [&](int u, T acc) {
         vd.h[u] = acc;
@@ -284,7 +257,7 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
         const Tile tl = vd.ftiles[t];
         if (tl.lid < 0) {
-            seg_tile_rows<T, T>(tl, vd.fptr, stage, segval, term, epi, s_val, s_ptr, s_tseg, s_tacc);
+            seg_tile_rows<T, T>(tl, vd.fptr, stage, segval, term, epi, s_val, s_seg, s_ptr);
         } else {
             const T xu = segval(tl.s0);
             auto elem = [&](int k) -> T { return term(xu, stage(k)); };
@@ -369,19 +342,37 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_fin(VcDev<T> vd, Ctl *ctl, con
     if (threadIdx.x == 0) finish_vcB(ctl, s_rec, vd.forced);
 }
 
+// K-candidate covering sums of one search pass over the edge list (KIND fixed
+// per launch): [s1C | s2C | zmin] in s_rec.
+template <class T, int KIND>
+__device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wave, double *s_rec)
+{
+    const int nc = ctl->ncand;
+    const double *cand = ctl->cand;
+    const double eta = ctl->eta, a0 = ctl->cand[0];
+    const double gdel = ctl->gdelta, Lw = ctl->LCw;
+    CovAcc<T> ca;
+    ca.init();
+    auto visit = [&](XD<T> pu, XD<T> pw, int) {
+        const double zd = (double)pu.x + (double)pw.x;
+        const T z = (T)zd;
+        const T dz = pu.d + pw.d;
+        const T u = exp_t((T)(-eta * (zd - Lw)));
+        cov_terms<T, KIND>(nc, cand, a0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
+    };
+    for_edges<T>(vd, visit);
+    ca.combine(s_wave, s_rec);
+}
+
 template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part)
 {
-    __shared__ XD<T> s_val[TILE_LDS];
-    __shared__ int32_t s_ptr[TILE_NZ + 1];
     __shared__ double s_wave[4 * 3 * KC];
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_SEARCH) return;
     const int kind = ctl->skind;
-    const double eta = ctl->eta;
-    auto stage = [&](int k) -> XD<T> { return vd.xd[vd.ucol[k]]; };
-    auto segval = [&](int u) -> XD<T> { return vd.xd[u]; };
     if (kind == SK_REFINE) {
+        const double eta = ctl->eta;
         const double a = ctl->ref_alpha;
         const bool second = ctl->ref_valid != 0;
         const double zm = ctl->rfZmin;
@@ -391,33 +382,18 @@ __global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, doub
             if (second) v[0] += exp(-eta * (zp - zm));
             else v[1] = fmin(v[1], zp);
         };
-        for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
-            const Tile tl = vd.utiles[t];
-            walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
-        }
+        for_edges<T>(vd, visit);
         const Red red{1, 1, 0};
         block_combine<2>(v, red, 0, s_wave, s_rec);
         store_record(s_rec, 2, part);
         return;
     }
-    const int nc = ctl->ncand;
-    const double *cand = ctl->cand;
-    const double a0 = ctl->cand[0];
-    const double gdel = ctl->gdelta, Lw = ctl->LCw;
-    CovAcc<T> ca;
-    ca.init();
-    auto visit = [&](XD<T> pu, XD<T> pw, int) {
-        const T z = pu.x + pw.x;
-        const T dz = pu.d + pw.d;
-        const T u = exp_t((T)(-eta * ((double)z - Lw)));
-        cov_row_terms<T>(kind, nc, cand, a0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
-    };
-    for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
-        const Tile tl = vd.utiles[t];
-        walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
+    switch (kind) {
+    case SK_EXP: vc_search_edges<T, SK_EXP>(vd, ctl, s_wave, s_rec); break;
+    case SK_GRID: vc_search_edges<T, SK_GRID>(vd, ctl, s_wave, s_rec); break;
+    default: vc_search_edges<T, SK_LIST>(vd, ctl, s_wave, s_rec); break;
     }
-    ca.combine(s_wave, s_rec + KC);
-    store_record(s_rec + KC, 3 * KC, part);   // records hold the covering sums only
+    store_record(s_rec, 3 * KC, part);   // records hold the covering sums only
 }
 
 __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G)
@@ -437,8 +413,8 @@ __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *p
         }
         return;
     }
-    const Red redc{3 * KC, KC, 0};
-    fold_records<3 * KC>(part, G, redc, KC, s_wave, s_rec + KC);
+    const Red redc{2 * KC, KC, 0};
+    fold_records<3 * KC>(part, G, redc, 0, s_wave, s_rec + KC);
     if (threadIdx.x == 0) {
         for (int k = 0; k < KC; ++k) s_rec[k] = 0.0;   // no packing rows: Psi = a * dy1
         finish_search(ctl, s_rec);
@@ -448,22 +424,15 @@ __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *p
 template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_export_k(VcDev<T> vd, int which, double *out)
 {
-    __shared__ XD<T> s_val[TILE_LDS];
-    __shared__ int32_t s_ptr[TILE_NZ + 1];
     if (which < 2) {
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK)
             out[i] = (double)(which == 0 ? vd.xd[i].x : vd.xd[i].d);
         return;
     }
-    auto stage = [&](int k) -> XD<T> { return vd.xd[vd.ucol[k]]; };
-    auto segval = [&](int u) -> XD<T> { return vd.xd[u]; };
-    auto visit = [&](XD<T> pu, XD<T> pw, int k) {
-        out[k] = which == 2 ? (double)(pu.x + pw.x) : (double)(pu.d + pw.d);
+    auto visit = [&](XD<T> pu, XD<T> pw, int e) {
+        out[e] = which == 2 ? (double)(pu.x + pw.x) : (double)(pu.d + pw.d);
     };
-    for (int t = blockIdx.x; t < vd.nutiles; t += gridDim.x) {
-        const Tile tl = vd.utiles[t];
-        walk_tile<XD<T>>(tl, vd.uptr, stage, segval, visit, s_val, s_ptr);
-    }
+    for_edges<T>(vd, visit);
 }
 
 template <class T>
@@ -486,8 +455,8 @@ void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, boo
 {
     VLAUNCH(vc_init_x<T>, L.grid_v, v, ctl, have_x0 ? 1 : 0, L.partials);
     VLAUNCH(vc_init_x_fin, 1, ctl, (const double *)L.partials, L.grid_v);
-    VLAUNCH(vc_minz<T>, L.grid_utile, v, ctl, L.partials);
-    VLAUNCH(vc_minz_fin, 1, ctl, (const double *)L.partials, L.grid_utile);
+    VLAUNCH(vc_minz<T>, L.grid_e, v, ctl, L.partials);
+    VLAUNCH(vc_minz_fin, 1, ctl, (const double *)L.partials, L.grid_e);
 }
 
 template <class T>
@@ -507,8 +476,8 @@ void vc_passB(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 template <class T>
 void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
-    VLAUNCH(vc_search_k<T>, L.grid_utile, v, ctl, L.partials);
-    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_utile);
+    VLAUNCH(vc_search_k<T>, L.grid_e, v, ctl, L.partials);
+    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_e);
 }
 
 template <class T>
@@ -524,7 +493,7 @@ template <class T>
 void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st)
 {
     const int g = which < 2 ? std::max(1, std::min(GRID_MAX, (v.nv + BLOCK - 1) / BLOCK))
-                            : std::max(1, std::min(GRID_MAX, v.nutiles));
+                            : std::max(1, std::min(GRID_MAX, (v.ne + BLOCK - 1) / BLOCK));
     VLAUNCH(vc_export_k<T>, g, v, which, out);
 }
 
