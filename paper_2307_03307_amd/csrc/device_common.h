@@ -16,6 +16,19 @@ MWU_DEV double expm1_t(double v) { return expm1(v); }
 MWU_DEV float exp_t(float v) { return expf(v); }
 MWU_DEV double exp_t(double v) { return exp(v); }
 
+// e^v for a double argument, returned in T.  Float: the argument is split
+// in base 2 in double, v log2(e) = n + f with |f| <= 1/2, so the hardware
+// 2^f (v_exp_f32, about 1 ulp) sees a small reduced argument and ldexp adds
+// n exactly; the result carries no error from rounding a large argument to
+// float.  Double: the library exp.
+MWU_DEV float exp_arg(double v, float)
+{
+    const double a = v * 1.4426950408889634;
+    const double n = rint(a);
+    return ldexpf(__builtin_amdgcn_exp2f((float)(a - n)), (int)fmax(n, -300.0));
+}
+MWU_DEV double exp_arg(double v, double) { return exp(v); }
+
 // ------------------------------------------------------------ reductions
 // A reduction record holds ns sums, then nmn minima, then nmx maxima.
 
@@ -334,6 +347,7 @@ template <class T, int KIND>
 MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, double eta, T u, T z, T dz,
                        T *acc, T *zmn)
 {
+    constexpr int NK = KIND == SK_EXP ? KE : KC;
     if constexpr (KIND == SK_LIST) {   // arbitrary candidates, direct evaluation
 #pragma unroll
         for (int k = 0; k < KC; ++k)
@@ -345,31 +359,34 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, doubl
                 acc[KC + k] += u * exp_t(-b);
             }
     } else {
-        T ak = (T)a0;
-        const T step = (T)gdel;
+        if constexpr (KIND == SK_EXP) {   // the bisection replay never reads the minima
+            T ak = (T)a0;
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            zmn[k] = fmin(zmn[k], z + ak * dz);
-            ak = KIND == SK_EXP ? ak + ak : ak + step;
+            for (int k = 0; k < NK; ++k) {
+                zmn[k] = fmin(zmn[k], z + ak * dz);
+                ak = ak + ak;
+            }
         }
-        const T b0 = (T)(eta * a0 * (double)dz);
+        const double b0d = eta * a0 * (double)dz;
+        const T b0 = (T)b0d;
         T m = expm1_t(-b0);
-        T t = exp_t(-b0);
+        T t = exp_arg(-b0d, T(0));
         if constexpr (KIND == SK_EXP) {
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
+            for (int k = 0; k < NK; ++k) {
                 acc[k] += u * m;
                 acc[KC + k] += u * t;
                 m = m * (m + T(2));
-                if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KC)
-                    t = exp_t((T)(-eta * a0 * (double)(1 << (k + 1)) * (double)dz));
+                if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < NK)
+                    t = exp_arg(-b0d * (double)(1 << (k + 1)), T(0));
                 else
                     t = t * t;
             }
         } else {
-            const T bd = (T)(eta * gdel * (double)dz);
+            const double bdd = eta * gdel * (double)dz;
+            const T bd = (T)bdd;
             const T mr = expm1_t(-bd);
-            const T tr = exp_t(-bd);
+            const T tr = exp_arg(-bdd, T(0));
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 acc[k] += u * m;
@@ -388,12 +405,14 @@ template <class T>
 struct CovAcc {
     T acc[2 * KC];
     T zmn[KC];
-    MWU_DEV void init()
+    // Bisection passes leave the minima at -inf: the replay never reads them,
+    // and -inf can never pass for an early return.
+    MWU_DEV void init(bool minima = true)
     {
 #pragma unroll
         for (int k = 0; k < 2 * KC; ++k) acc[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < KC; ++k) zmn[k] = T(INFINITY);
+        for (int k = 0; k < KC; ++k) zmn[k] = minima ? T(INFINITY) : T(-INFINITY);
     }
     // block-combine into out[0..3KC): [s1C | s2C | zmin]
     MWU_DEV void combine(double *s_wave, double *out)
@@ -459,9 +478,9 @@ MWU_DEV bool held(Ctl *c)
 MWU_DEV void setup_exp(Ctl *c, double a0)
 {
     c->skind = SK_EXP;
-    c->ncand = KC;
+    c->ncand = KE;
     double a = a0;
-    for (int k = 0; k < KC; ++k) { c->cand[k] = a; a *= 2.0; }
+    for (int k = 0; k < KE; ++k) { c->cand[k] = a; a *= 2.0; }
     c->ga0 = a0;
     c->gdelta = 0.0;
 }

@@ -11,6 +11,7 @@ constexpr int BLOCK = 256;               // threads per workgroup (4 wave64)
 constexpr int ITEMS = 8;                 // nonzeros per thread in a segment tile
 constexpr int TILE_NZ = BLOCK * ITEMS;   // nonzeros per tile
 constexpr int KC = 16;                   // step candidates per search pass
+constexpr int KE = 8;            // candidates of an exponential-grid pass (1 .. 128 from a0 = 1)
 constexpr int QMAX = 4 * KC + 8;         // doubles per block in a reduction record
 
 // Phase of the per-probe state machine.  Every kernel of the iteration graph
@@ -142,7 +143,8 @@ struct VcDev {
     const Tile *ftiles; int32_t nftiles;
     LongSegs flong;
     T *flpart;
-    XD<T> *xd;                          // x and d interleaved (one 2T gather per neighbor)
+    XD<T> *xd;                          // x and d interleaved (one 2T gather per edge endpoint)
+    T *xs;                              // copy of x for the transpose pass (half the footprint)
     T *h;                               // unnormalized C^T u per vertex
     double *h_dbg;                      // nullable
     const double *forced;

@@ -217,12 +217,12 @@ __global__ __launch_bounds__(BLOCK) void k_row(GenericDev<T> gd, Ctl *ctl, doubl
         const T y = gd.yz[r] + a * gd.dyz[r];
         gd.yz[r] = y;
         if (r < gd.mPc) {
-            const T w = exp_t((T)(eta * ((double)y - LP)));
+            const T w = exp_arg(eta * ((double)y - LP), T(0));
             gd.wu[r] = w;
             v[0] += (double)w;
             v[3] = fmax(v[3], (double)y);
         } else {
-            const T u = exp_t((T)(-eta * ((double)y - LC)));
+            const T u = exp_arg(-eta * ((double)y - LC), T(0));
             gd.wu[r] = u;
             v[1] += (double)u;
             v[2] = fmin(v[2], (double)y);
@@ -435,7 +435,7 @@ __device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_w
             if constexpr (KIND == SK_EXP) {
                 T m = expm1_t((T)(eta * a0 * (double)dy));
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
+                for (int k = 0; k < KE; ++k) {
                     s1[k] += (double)(w * m);
                     m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
                 }
@@ -458,7 +458,7 @@ __device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_w
     }
     {
         CovAcc<T> ca;
-        ca.init();
+        ca.init(KIND != SK_GRID);
         for (int r = mPc + r0; r < mR; r += stride)
             cov_terms<T, KIND>(nc, cand, a0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
         ca.combine(s_wave, s_rec + KC);

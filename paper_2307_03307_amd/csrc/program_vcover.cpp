@@ -9,6 +9,21 @@
 
 namespace mwu {
 
+// Interleave the bits of a (even positions) and b (odd positions).
+static uint64_t morton2(uint32_t a, uint32_t b)
+{
+    auto spread = [](uint64_t x) {
+        x &= 0xffffffffull;
+        x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+        x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+        x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+        x = (x | (x << 2)) & 0x3333333333333333ull;
+        x = (x | (x << 1)) & 0x5555555555555555ull;
+        return x;
+    };
+    return spread(a) | (spread(b) << 1);
+}
+
 template <class T>
 class VcoverProgram : public Program {
   public:
@@ -26,7 +41,7 @@ class VcoverProgram : public Program {
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
         dev_.assign(nv, 0);
         for (int64_t r = 0; r < nv; ++r) dev_[order[r]] = (int32_t)r;
-        // edges (u, w), u < w in device ids, sorted
+        // edges (u, w), u < w in device ids, sorted: rows of the full adjacency
         std::vector<uint64_t> key(el.ne);
         for (int64_t e = 0; e < el.ne; ++e) {
             const int64_t a = dev_[newid[el.u[e]]], b = dev_[newid[el.v[e]]];
@@ -41,14 +56,29 @@ class VcoverProgram : public Program {
             fptr[a + 1]++;
             fptr[b + 1]++;
         }
-        key.clear();
-        key.shrink_to_fit();
         for (int64_t v = 0; v < nv; ++v) fptr[v + 1] += fptr[v];
         {
             std::vector<int32_t> fill(fptr.begin(), fptr.end() - 1);
             for (int64_t e = 0; e < ne_; ++e) fcol[fill[ew[e]]++] = eu[e];   // sorted rows
             for (int64_t e = 0; e < ne_; ++e) fcol[fill[eu[e]]++] = ew[e];
         }
+        // The edge passes are plain sums over edges, so the edge list is kept
+        // in Z-order of (u, w): neighbouring lanes then gather from nearby
+        // vertices on both endpoints (about half the cache lines per wave of
+        // a row-sorted list on power-law graphs).
+        for (int64_t e = 0; e < ne_; ++e) key[e] = morton2((uint32_t)eu[e], (uint32_t)ew[e]);
+        std::vector<int64_t> zp(ne_);
+        for (int64_t e = 0; e < ne_; ++e) zp[e] = e;
+        std::sort(zp.begin(), zp.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        {
+            std::vector<int32_t> t(ne_);
+            for (int64_t e = 0; e < ne_; ++e) t[e] = eu[zp[e]];
+            eu.swap(t);
+            for (int64_t e = 0; e < ne_; ++e) t[e] = ew[zp[e]];
+            ew.swap(t);
+        }
+        key.clear();
+        key.shrink_to_fit();
         TilePlan ft = build_tiles(fptr, nv);
         auto up = [&](DevBuf &b, const void *src, size_t bytes) {
             b.alloc(bytes);
@@ -66,6 +96,7 @@ class VcoverProgram : public Program {
         xd_.alloc(nv * sizeof(XD<T>));
         xbest_.alloc(nv * sizeof(XD<T>));
         h_.alloc(nv * sizeof(T));
+        xs_.alloc(nv * sizeof(T));
         HIP_OK(hipMemset(xd_.p, 0, xd_.bytes));
         partials_.alloc((size_t)GRID_MAX * QMAX * 8);
 
@@ -77,7 +108,7 @@ class VcoverProgram : public Program {
         vd_.flong = LongSegs{flseg_.as<int32_t>(), flfirst_.as<int32_t>(), flcount_.as<int32_t>(),
                              (int32_t)ft.lseg.size()};
         vd_.flpart = flpart_.as<T>();
-        vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>();
+        vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>(); vd_.xs = xs_.as<T>();
         vd_.h_dbg = nullptr; vd_.forced = nullptr;
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
@@ -187,7 +218,7 @@ class VcoverProgram : public Program {
     {
         const double t = sizeof(T), V = (double)nv_, E = (double)ne_;
         switch (which) {
-        case 0: return 4.0 * (V + 1) + 8.0 * E + 2.0 * t * V + t * V;   // fptr, fcol, xd, h
+        case 0: return 4.0 * (V + 1) + 8.0 * E + t * V + t * V;       // fptr, fcol, x, h
         case 1: return 4.0 * t * V + t * V;                           // xd read+write, h
         case 3: return 8.0 * E + 2.0 * t * V;                           // eu, ew, xd
         }
@@ -261,7 +292,7 @@ class VcoverProgram : public Program {
     std::vector<int32_t> dev_;     // compact vertex id -> device vertex id
     std::vector<int64_t> canon_;
     DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
-    DevBuf xd_, xbest_, h_, partials_, forced_, hdbg_;
+    DevBuf xd_, xs_, xbest_, h_, partials_, forced_, hdbg_;
 };
 
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,

@@ -831,7 +831,7 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
         pull_ctl(s);
         Ctl &c = *s.ctl_host;
         // the direction must have been computed (mwu_probe_direction)
-        bool dbl = count == KC, ari = count == 15;
+        bool dbl = count == KE, ari = count == 15;
         for (int k = 1; k < count; ++k) {
             if (alphas[k] != 2.0 * alphas[k - 1]) dbl = false;
         }

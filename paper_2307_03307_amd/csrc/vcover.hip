@@ -6,11 +6,12 @@
 // weights u_e = exp(-eta (z_e - L)) are recomputed from the vertex vectors in
 // every pass instead of being stored, so a pass reads only the adjacency
 // indices from HBM (the vertex vectors stay in the caches).  Per iteration:
-//   pass A  (full adjacency, one segment per vertex) h_v = sum_{w ~ v} u_vw
-//           at x + a d, min z, sum u: the transpose product C^T u fused with
-//           the weights and the LSE totals;
-//   pass B  (vertices) commit x += a d, direction d_v = (1/eta) max(0, 1 -
-//           g/h_v) x_v with g = 1/M, sum d (= M * Pd);
+//   commit  (vertices) x += a d for the step accepted last;
+//   pass A  (full adjacency, one segment per vertex) h_v = sum_{w ~ v} u_vw,
+//           min z, sum u: the transpose product C^T u fused with the weights
+//           and the LSE totals;
+//   pass B  (vertices) direction d_v = (1/eta) max(0, 1 - g/h_v) x_v with
+//           g = 1/M, sum d (= M * Pd);
 //   search  (edge list, one visit per edge) the K-candidate sums of Phi,
 //           with the forward product C d formed on the fly.
 #include <algorithm>
@@ -91,7 +92,7 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
 template <class T, class VisitF>
 MWU_DEV void for_edges(const VcDev<T> &vd, VisitF &visit)
 {
-    constexpr int U = sizeof(T) == 4 ? 4 : 2;
+    constexpr int U = sizeof(T) == 4 ? 3 : 2;
     const int stride = gridDim.x * BLOCK;
     int e = blockIdx.x * BLOCK + threadIdx.x;
     const int ne = vd.ne;
@@ -177,6 +178,7 @@ __global__ __launch_bounds__(BLOCK) void vc_init_x(VcDev<T> vd, Ctl *ctl, int ha
         if (!have_x0) p.x = (T)(eps / ((double)vd.nv * sP));   // Algorithm 1 with P = (1/M) 1^T
         p.d = T(0);
         vd.xd[i] = p;
+        vd.xs[i] = p.x;
         v[0] += (double)p.x;
     }
     const Red red{1, 0, 0};
@@ -224,6 +226,20 @@ __global__ __launch_bounds__(BLOCK) void vc_minz_fin(Ctl *ctl, const double *par
     }
 }
 
+// x += a d for the step accepted by the last search (a no-op outside PH_ROW).
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_commit_k(VcDev<T> vd, Ctl *ctl)
+{
+    if (ctl->phase != PH_ROW) return;
+    const T a = (T)ctl->alpha;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
+        XD<T> p = vd.xd[i];
+        p.x = p.x + a * p.d;
+        vd.xd[i] = p;
+        vd.xs[i] = p.x;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, double *part)
 {
@@ -234,21 +250,14 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_ROW) return;
-    const T a = (T)ctl->alpha;
     const double eta = ctl->eta, Lw = ctl->LC;
     double v[2] = {0.0, INFINITY};   // sum h | min z
-    auto stage = [&](int k) -> T {
-        const XD<T> p = vd.xd[vd.fcol[k]];
-        return p.x + a * p.d;
-    };
-    auto segval = [&](int u) -> T {
-        const XD<T> p = vd.xd[u];
-        return p.x + a * p.d;
-    };
+    auto stage = [&](int k) -> T { return vd.xs[vd.fcol[k]]; };
+    auto segval = [&](int u) -> T { return vd.xs[u]; };
     auto term = [&](T xu, T xw) -> T {
         const double z = (double)xu + (double)xw;
         v[1] = fmin(v[1], z);
-        return exp_t((T)(-eta * (z - Lw)));
+        return exp_arg(-eta * (z - Lw), T(0));
     };
     auto epi = [&](int u, T acc) {
         vd.h[u] = acc;
@@ -298,29 +307,24 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, doubl
     __shared__ double s_rec[QMAX];
     const int ph = ctl->phase;
     if (ph != PH_COL && ph != PH_COMMIT) return;
-    const T a = (T)ctl->alpha;
+    if (ph == PH_COMMIT) return;   // x was committed before pass A
     const double invSu = ctl->invSu, g = ctl->sP, step = ctl->step, qmin = ctl->qmin;
-    const bool commit = ph == PH_COMMIT;
     double v[3] = {0.0, -INFINITY, -INFINITY};   // sum d | max d | max h
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
         XD<T> p = vd.xd[i];
-        p.x = p.x + a * p.d;
-        if (!commit) {
-            const double h = (double)vd.h[i] * invSu;
-            double di = 0.0;
-            if (h > 0.0) {
-                const double q = 1.0 - g / h;
-                if (q > qmin) di = step * q * (double)p.x;
-            }
-            p.d = (T)di;
-            v[0] += (double)p.d;
-            v[1] = fmax(v[1], (double)p.d);
-            v[2] = fmax(v[2], h);
-            if (vd.h_dbg) vd.h_dbg[i] = h;
+        const double h = (double)vd.h[i] * invSu;
+        double di = 0.0;
+        if (h > 0.0) {
+            const double q = 1.0 - g / h;
+            if (q > qmin) di = step * q * (double)p.x;
         }
+        p.d = (T)di;
+        v[0] += (double)p.d;
+        v[1] = fmax(v[1], (double)p.d);
+        v[2] = fmax(v[2], h);
+        if (vd.h_dbg) vd.h_dbg[i] = h;
         vd.xd[i] = p;
     }
-    if (commit) return;
     const Red red{1, 0, 2};
     block_combine<3>(v, red, 0, s_wave, s_rec);
     store_record(s_rec, 3, part);
@@ -352,12 +356,12 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
     const double eta = ctl->eta, a0 = ctl->cand[0];
     const double gdel = ctl->gdelta, Lw = ctl->LCw;
     CovAcc<T> ca;
-    ca.init();
+    ca.init(KIND != SK_GRID);
     auto visit = [&](XD<T> pu, XD<T> pw, int) {
         const double zd = (double)pu.x + (double)pw.x;
         const T z = (T)zd;
         const T dz = pu.d + pw.d;
-        const T u = exp_t((T)(-eta * (zd - Lw)));
+        const T u = exp_arg(-eta * (zd - Lw), T(0));
         cov_terms<T, KIND>(nc, cand, a0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
     };
     for_edges<T>(vd, visit);
@@ -365,7 +369,7 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
 }
 
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part)
+__device__ __forceinline__ void vc_search_body(const VcDev<T> &vd, Ctl *ctl, double *part)
 {
     __shared__ double s_wave[4 * 3 * KC];
     __shared__ double s_rec[QMAX];
@@ -395,6 +399,15 @@ __global__ __launch_bounds__(BLOCK) void vc_search_k(VcDev<T> vd, Ctl *ctl, doub
     }
     store_record(s_rec, 3 * KC, part);   // records hold the covering sums only
 }
+
+// The FP32 search fits five waves per SIMD; ask the compiler to keep it there.
+template <class T> __global__ void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part);
+template <>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
+void vc_search_k<float>(VcDev<float> vd, Ctl *ctl, double *part) { vc_search_body<float>(vd, ctl, part); }
+template <>
+__global__ __launch_bounds__(BLOCK)
+void vc_search_k<double>(VcDev<double> vd, Ctl *ctl, double *part) { vc_search_body<double>(vd, ctl, part); }
 
 __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G)
 {
@@ -443,6 +456,7 @@ __global__ void vc_import_k(VcDev<T> vd, const double *src)
         p.x = (T)src[i];
         p.d = T(0);
         vd.xd[i] = p;
+        vd.xs[i] = p.x;
     }
 }
 
@@ -462,6 +476,7 @@ void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, boo
 template <class T>
 void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
+    VLAUNCH(vc_commit_k<T>, L.grid_v, v, ctl);
     VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials);
     VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile);
 }
