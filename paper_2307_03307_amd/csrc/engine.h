@@ -156,6 +156,7 @@ struct Launch {
     int grid_elem_cols;  // persistent grid for element-wise passes over columns
     int grid_rtile;      // persistent grid for row tiles
     int grid_ctile;      // persistent grid for column tiles
+    int grid_search;     // persistent grid of the search pass
     double *partials;    // GRID_MAX * QMAX doubles: one reduction record per workgroup
 };
 
@@ -205,5 +206,7 @@ template <class T> void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L
 // which: 0 = x, 1 = d (vertex vectors, double out); 2 = z, 3 = dz (edge vectors, canonical order)
 template <class T> void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st);
 template <class T> void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st);
+template <class T> void vc_occupancy(int *per_cu_ftile, int *per_cu_edge);
+template <class T> void generic_occupancy(int *per_cu_fwd, int *per_cu_col, int *per_cu_search);
 
 }  // namespace mwu

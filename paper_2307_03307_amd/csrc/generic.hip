@@ -626,8 +626,8 @@ void generic_fwd(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t 
 template <class T>
 void generic_search(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
 {
-    LAUNCH(k_search<T>, L.grid_elem_rows, g, ctl, L.partials);
-    LAUNCH(k_search_fin, 1, ctl, (const double *)L.partials, L.grid_elem_rows);
+    LAUNCH(k_search<T>, L.grid_search, g, ctl, L.partials);
+    LAUNCH(k_search_fin, 1, ctl, (const double *)L.partials, L.grid_search);
 }
 
 template <class T>
@@ -663,7 +663,21 @@ void set_phase(Ctl *ctl, int phase, hipStream_t st)
     hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(1), 0, st, ctl, phase);
 }
 
+// Workgroups per CU of the persistent tile kernels and the search kernel.
+template <class T>
+void generic_occupancy(int *per_cu_fwd, int *per_cu_col, int *per_cu_search)
+{
+    int a = 0, b = 0, c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_fwd<T, false>, BLOCK, 0) != hipSuccess) a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_col<T>, BLOCK, 0) != hipSuccess) b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_search<T>, BLOCK, 0) != hipSuccess) c = 0;
+    *per_cu_fwd = a > 0 ? a : 1;
+    *per_cu_col = b > 0 ? b : 1;
+    *per_cu_search = c > 0 ? c : 1;
+}
+
 #define MWU_INSTANTIATE(T)                                                                      \
+    template void generic_occupancy<T>(int *, int *, int *);                                   \
     template void generic_init<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t,    \
                                   bool);                                                        \
     template void generic_load_x<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t,  \

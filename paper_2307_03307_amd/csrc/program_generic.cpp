@@ -163,8 +163,15 @@ class GenericProgram : public Program {
         };
         L_.grid_elem_rows = clampg(mR_, BLOCK * 2);
         L_.grid_elem_cols = clampg(n_, BLOCK * 2);
-        L_.grid_rtile = clampg((int64_t)rt.tiles.size(), 1);
-        L_.grid_ctile = clampg((int64_t)ct.tiles.size(), 1);
+        int occ_f = 1, occ_c = 1, occ_s = 1;
+        generic_occupancy<T>(&occ_f, &occ_c, &occ_s);
+        auto round1 = [&](int64_t items, int64_t per, int occ) {   // one full round of workgroups
+            return (int)std::max<int64_t>(1, std::min<int64_t>({(items + per - 1) / per, (int64_t)GRID_MAX,
+                                                               (int64_t)occ * s.num_cus}));
+        };
+        L_.grid_rtile = round1((int64_t)rt.tiles.size(), 1, occ_f);
+        L_.grid_ctile = round1((int64_t)ct.tiles.size(), 1, occ_c);
+        L_.grid_search = round1(mR_, BLOCK * 4, occ_s);
         L_.partials = partials_.as<double>();
     }
 

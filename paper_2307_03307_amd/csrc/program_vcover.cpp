@@ -114,10 +114,14 @@ class VcoverProgram : public Program {
             int64_t g = (items + per - 1) / per;
             return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
         };
+        int occ_f = 1, occ_e = 1;
+        vc_occupancy<T>(&occ_f, &occ_e);
         L_.grid_v = clampg(nv, BLOCK * 2, GRID_MAX);
-        L_.grid_ftile = clampg((int64_t)ft.tiles.size(), 1, GRID_MAX);
-        // edge passes: a few resident workgroups per CU, each over many edges
-        L_.grid_e = clampg(ne_, BLOCK * 8, 4 * s.num_cus);
+        // persistent tile and edge grids: one full round of resident workgroups
+        L_.grid_ftile = clampg((int64_t)ft.tiles.size(), 1, std::min<int64_t>(GRID_MAX, (int64_t)occ_f * s.num_cus));
+        // (at most 4 per CU: measured faster than 5 for the FP32 search, whose
+        // per-workgroup combine is then amortized over more edges)
+        L_.grid_e = clampg(ne_, BLOCK * 8, std::min<int64_t>(GRID_MAX, (int64_t)std::min(occ_e, 4) * s.num_cus));
         L_.partials = partials_.as<double>();
     }
 

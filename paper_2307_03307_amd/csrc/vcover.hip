@@ -18,6 +18,8 @@
 
 #include "device_common.h"
 
+#define HIP_CHECK_OCC(call) do { if ((call) != hipSuccess) { a = b = 0; } } while (0)
+
 namespace mwu {
 
 // Multi-segment tile where each term depends on its segment: stage(k) and
@@ -519,6 +521,18 @@ void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st)
     VLAUNCH(vc_import_k<T>, g, v, src);
 }
 
+// Workgroups of the tile and edge kernels that fit on one CU at once: the
+// persistent grids are sized to exactly fill the chip in one round.
+template <class T>
+void vc_occupancy(int *per_cu_ftile, int *per_cu_edge)
+{
+    int a = 0, b = 0;
+    HIP_CHECK_OCC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, vc_passA_k<T>, BLOCK, 0));
+    HIP_CHECK_OCC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, vc_search_k<T>, BLOCK, 0));
+    *per_cu_ftile = a > 0 ? a : 1;
+    *per_cu_edge = b > 0 ? b : 1;
+}
+
 #define MWU_VC_INSTANTIATE(T)                                                                    \
     template void vc_init<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t, bool);      \
     template void vc_iteration<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);       \
@@ -526,7 +540,8 @@ void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st)
     template void vc_passB<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);           \
     template void vc_search<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);          \
     template void vc_export<T>(const VcDev<T> &, int, double *, hipStream_t);                    \
-    template void vc_import_x<T>(const VcDev<T> &, const double *, hipStream_t);
+    template void vc_import_x<T>(const VcDev<T> &, const double *, hipStream_t);                 \
+    template void vc_occupancy<T>(int *, int *);
 
 MWU_VC_INSTANTIATE(float)
 MWU_VC_INSTANTIATE(double)
