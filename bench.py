@@ -22,8 +22,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-(1+eps) at eps=0.1 + A/A^T nnz/s (HBM GB/s), chosen vs plain FP64"
 HBM_PEAK_GBPS = 8000.0
-PASS_NAMES = {0: "transpose_pass", 1: "direction_pass", 2: "forward_pass", 3: "search_pass"}
+PASS_NAMES = {0: "transpose_pass", 1: "direction_pass", 2: "forward_pass", 3: "search_pass_exp",
+              4: "search_pass_bisect"}
 KERNEL_NAMES = {0: "vc_passA_k", 1: "vc_passB_k", 3: "vc_search_k"}
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
@@ -53,9 +55,11 @@ def run_solves(mwu, g, precision, steps, warmup):
 
 
 def pass_times(s, reps, param):
+    """Average duration of each pass's main kernel (HIP events on the solver
+    stream, state held), its algorithmic bytes and nonzeros."""
     out = {}
     s.probe_begin(param)
-    for which in (0, 1, 3):
+    for which in (0, 1, 3, 4):
         us, by, nz = s.time_pass(which, reps)
         out[which] = {"us": us, "bytes": by, "nnz": nz, "GBps": by / us / 1e3,
                       "nnz_per_s": nz / (us * 1e-6) if nz else None}
@@ -150,15 +154,24 @@ def main():
         passes64 = pass_times(s64, args.pass_reps, param=0.5 * (last64.lower + last64.upper))
         s64.close()
 
-    # dominant kernel: the pass with the largest share of one iteration
-    # (one transpose pass, one direction pass, search passes per iteration)
+    # dominant kernel: the pass with the largest share of one iteration (one
+    # transpose pass, one direction pass, about one exponential-grid and one
+    # bisection search pass per iteration, both launches of vc_search_k)
     spi = last32.search_passes / max(1, last32.total_iterations)
-    share = {0: passes32[0]["us"], 1: passes32[1]["us"], 3: spi * passes32[3]["us"]}
+    search_us = 0.5 * (passes32[3]["us"] + passes32[4]["us"])
+    share = {0: passes32[0]["us"], 1: passes32[1]["us"], 3: spi * search_us}
     dom = max(share, key=share.get)
-    dp = passes32[dom]
-    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": dp["GBps"],
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": dp["GBps"] / HBM_PEAK_GBPS,
-                "traffic": None, "avg_launch_us": dp["us"], "algorithmic_bytes": dp["bytes"]}
+    dom_us = search_us if dom == 3 else passes32[dom]["us"]
+    dom_bytes = passes32[dom]["bytes"]
+    kernel = KERNEL_NAMES[dom]
+    from paper_2307_03307_amd import profiling
+    traffic = profiling.load_traffic(
+        os.path.join(PROFILES, f"{kernel}_rmat{args.scale}_f32_traffic.txt"), f"{kernel}<float>")
+    achieved = dom_bytes / dom_us / 1e3
+    roofline = {"bound": "hbm", "kernel": kernel + "<float>", "achieved": achieved,
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": traffic, "avg_launch_us": dom_us, "algorithmic_bytes": dom_bytes,
+                "share_of_iteration": share[dom] / sum(share.values())}
 
     out = {
         "metric": METRIC,
@@ -191,7 +204,7 @@ def main():
         "fp64_iterations": last64.total_iterations if last64 else None,
         "passes": {PASS_NAMES[k]: v for k, v in passes32.items()},
         "passes_fp64": {PASS_NAMES[k]: v for k, v in passes64.items()} if passes64 else None,
-        "A_nnz_per_s": passes32[3]["nnz_per_s"],
+        "A_nnz_per_s": (passes32[3]["nnz"] / (search_us * 1e-6)),
         "AT_nnz_per_s": passes32[0]["nnz_per_s"],
         "roofline": roofline,
     }

@@ -230,12 +230,15 @@ mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
 mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new);
 
-/* Time one pass of the iteration: which = 0 row / transpose pass (the
- * weights, their LSE totals and C^T u, P^T w), 1 column / direction pass,
- * 2 forward pass (P d, C d; a no-op in fused programs that form it inside
- * the search), 3 step-search pass over a 16-candidate exponential grid.
- * The pass is launched reps times on the handle's stream with the probe state
- * frozen (after one direction at the current point), timed with HIP events;
+/* Time the main kernel of one pass of the iteration: which = 0 row /
+ * transpose pass (the weights, their LSE totals and C^T u, P^T w), 1 column /
+ * direction pass, 2 forward pass (P d, C d; a no-op in fused programs that
+ * form it inside the search), 3 step-search pass over the exponential grid
+ * (8 candidates from 1), 4 step-search pass over a bisection grid (15
+ * candidates in [1, 2]).  The kernel is launched reps times on the handle's
+ * stream with the probe state frozen (after one direction at the current
+ * point; the finisher kernel of the pass is not launched), timed with HIP
+ * events;
  * the probe state is restored afterwards.  Outputs (host): average duration
  * in microseconds, algorithmic HBM bytes of one launch (every index, dense
  * vector and output counted once; nullable) and the nonzeros the pass visits

@@ -108,6 +108,9 @@ def lib():
                                             vp, vp, vp, ctypes.c_int64, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, vp]
         L.orc_step_search_terms.restype = ctypes.c_double
+        L.orc_potential.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double,
+                                    ctypes.c_double, vp, vp]
+        L.orc_potential.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -334,6 +337,15 @@ def solve_densest(g, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 6
     if rc != 0:
         raise RuntimeError(f"orc_solve_densest failed: {rc}")
     return _solve_result(r, z)
+
+
+def potential(P: CSR, sP: float, C: CSR, sC: float, eta_: float, x):
+    """(smax(sP P x) - smin(sC C x), its gradient): the smoothed potential of
+    Section 4.1 and g - h of Algorithm 2."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    gr = np.zeros(P.cols)
+    v = lib().orc_potential(P.c, sP, C.c, sC, eta_, x.ctypes.data, gr.ctypes.data)
+    return v, gr
 
 
 def smax(y, eta_):

@@ -41,9 +41,13 @@
  *       lower end), kept apart from the certified bracket on OPT, which only
  *       certificates move.  It stops when the certified bracket is within
  *       1+eps, when the search bracket is within 1+eps/16, or at the probe cap.
- *       Only an infeasible verdict (a dual certificate) moves the certified
- *       bracket; a probe that hits the iteration cap moves the search bracket
- *       and leaves the result uncertified.
+ *       Only certificates move the certified bracket (rescaled feasible
+ *       points, weak-duality bounds, infeasible verdicts); a probe that hits
+ *       the iteration cap moves only the search bracket (as if infeasible).
+ *       The result is certified exactly when the final bracket is within
+ *       1+eps.  When the search bracket closes first, the probes continue at
+ *       half the tolerance (a feasible probe then overshoots its M by about
+ *       eps/2 instead of eps) from the certified bracket, at most twice.
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,6 +70,9 @@ enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_UNBOUNDED = -2, ORC_ERR_OOM = -3 };
 #define ORC_PHI_LOG1P_MIN 0.5
 /* Largest eta*alpha*dy for which the expm1 form of Psi is used (R8). */
 #define ORC_PSI_EXPM1_MAX 700.0
+/* Times the probe tolerance may be halved when the search bracket closes
+ * without a certified (1+eps) bracket (R9). */
+#define ORC_MAX_HALVINGS 2
 /* Cap of the exponential phase of Algorithm 3. */
 #define ORC_ALPHA_CAP 1125899906842624.0 /* 2^50 */
 
@@ -113,6 +120,35 @@ double orc_smin(const double *z, int64_t m, double eta, double *grad)
     for (int64_t j = 0; j < m; ++j) sum += exp(-eta * (z[j] - zmin));
     if (grad) for (int64_t j = 0; j < m; ++j) grad[j] = exp(-eta * (z[j] - zmin)) / sum;
     return zmin - log(sum) / eta;
+}
+
+/* Smoothed potential of Section 4.1 at x: smax_eta(sP P x) - smin_eta(sC C x),
+ * the quantity whose decrease the step test of Algorithm 3 certifies.  grad
+ * (nullable, length P->cols) receives its gradient
+ * sP P^T grad smax(sP P x) - sC C^T grad smin(sC C x), the g - h of
+ * Algorithm 2 (chain rule through the two linear maps). */
+double orc_potential(const orc_mat *P, double sP, const orc_mat *C, double sC, double eta,
+                     const double *x, double *grad)
+{
+    int64_t n = P->cols;
+    double *y = malloc((size_t)P->rows * sizeof(double));
+    double *z = malloc((size_t)C->rows * sizeof(double));
+    double *w = malloc((size_t)P->rows * sizeof(double));
+    double *u = malloc((size_t)C->rows * sizeof(double));
+    double *gh = malloc((size_t)n * sizeof(double));
+    double val = NAN;
+    if (!y || !z || !w || !u || !gh) goto out;
+    orc_matvec(P, sP, x, y);
+    orc_matvec(C, sC, x, z);
+    val = orc_smax(y, P->rows, eta, w) - orc_smin(z, C->rows, eta, u);
+    if (grad) {
+        orc_matvec_t(P, sP, w, grad);
+        orc_matvec_t(C, sC, u, gh);
+        for (int64_t i = 0; i < n; ++i) grad[i] -= gh[i];
+    }
+out:
+    free(y); free(z); free(w); free(u); free(gh);
+    return val;
 }
 
 /* Psi(alpha) = smax(y + alpha*dy) - smax(y)   (Section 4.1).
@@ -493,12 +529,21 @@ int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t ma
     for (int64_t i = 0; i < n; ++i) sx += x[i];
     double lo = sx / ymax;
     for (int64_t i = 0; i < n; ++i) x_best[i] = x[i] / ymax;
-    int uncertified = 0;
     double slo = lo, shi = hi;   /* search bracket for M (R9) */
-    while (r->probes < max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+    double ep = eps;             /* probe tolerance (R9) */
+    int halvings = 0;
+    while (r->probes < max_probes && hi > (1.0 + eps) * lo) {
+        if (!(shi > (1.0 + eps / 16.0) * slo)) {
+            if (halvings == ORC_MAX_HALVINGS) break;
+            halvings++;
+            ep *= 0.5;
+            slo = lo;
+            shi = hi;
+            continue;
+        }
         double M = sqrt(slo * shi);
         orc_probe_result pr;
-        rc = orc_probe(P, 1.0, &one.m, 1.0 / M, eps, max_iter, step_rule, 0, x,
+        rc = orc_probe(P, 1.0, &one.m, 1.0 / M, ep, max_iter, step_rule, 0, x,
                        NULL, 0, NULL, 0, &pr);
         if (rc) goto done;
         r->probes++;
@@ -519,13 +564,12 @@ int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t ma
         } else {
             if (pr.status == ORC_INFEASIBLE && M < hi) hi = M;
             shi = M;
-            if (pr.status == ORC_MAX_ITER) uncertified = 1;
         }
         if (lo > slo) slo = lo;
         if (hi < shi) shi = hi;
     }
     r->lower = lo; r->upper = hi; r->objective = lo;
-    r->status = (hi <= (1.0 + eps) * lo && !uncertified) ? 0 : 1;
+    r->status = (hi <= (1.0 + eps) * lo) ? 0 : 1;
 done:
     free(x); free(y); free(cm);
     ones_row_free(&one);
@@ -571,12 +615,21 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
     }
     double hi = 0.0;
     for (int64_t i = 0; i < n; ++i) { hi += x[i]; x_best[i] = x[i]; }
-    int uncertified = 0;
     double slo = lo, shi = hi;   /* search bracket for M (R9) */
-    while (r->probes < max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+    double ep = eps;             /* probe tolerance (R9) */
+    int halvings = 0;
+    while (r->probes < max_probes && hi > (1.0 + eps) * lo) {
+        if (!(shi > (1.0 + eps / 16.0) * slo)) {
+            if (halvings == ORC_MAX_HALVINGS) break;
+            halvings++;
+            ep *= 0.5;
+            slo = lo;
+            shi = hi;
+            continue;
+        }
         double M = sqrt(slo * shi);
         orc_probe_result pr;
-        rc = orc_probe(&one.m, 1.0 / M, C, 1.0, eps, max_iter, step_rule, 0, x,
+        rc = orc_probe(&one.m, 1.0 / M, C, 1.0, ep, max_iter, step_rule, 0, x,
                        NULL, 0, NULL, 0, &pr);
         if (rc) goto done;
         r->probes++;
@@ -597,13 +650,12 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
         } else {
             if (pr.status == ORC_INFEASIBLE && M > lo) lo = M;
             slo = M;
-            if (pr.status == ORC_MAX_ITER) uncertified = 1;
         }
         if (lo > slo) slo = lo;
         if (hi < shi) shi = hi;
     }
     r->lower = lo; r->upper = hi; r->objective = hi;
-    r->status = (hi <= (1.0 + eps) * lo && !uncertified) ? 0 : 1;
+    r->status = (hi <= (1.0 + eps) * lo) ? 0 : 1;
 done:
     free(x); free(z); free(cs);
     ones_row_free(&one);
@@ -675,12 +727,21 @@ int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, con
     double hi = 0.0;
     for (int64_t v = 0; v < nv; ++v) if (load[v] > hi) hi = load[v];
     double lo = (double)ne / (double)nv;
-    int uncertified = 0;
     double slo = lo, shi = hi;   /* search bracket for D (R9) */
-    while (r->probes < max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+    double ep = eps;             /* probe tolerance (R9) */
+    int halvings = 0;
+    while (r->probes < max_probes && hi > (1.0 + eps) * lo) {
+        if (!(shi > (1.0 + eps / 16.0) * slo)) {
+            if (halvings == ORC_MAX_HALVINGS) break;
+            halvings++;
+            ep *= 0.5;
+            slo = lo;
+            shi = hi;
+            continue;
+        }
         double D = sqrt(slo * shi);
         orc_probe_result pr;
-        rc = orc_probe(O, 1.0 / D, W, 1.0, eps, max_iter, step_rule, 0, z,
+        rc = orc_probe(O, 1.0 / D, W, 1.0, ep, max_iter, step_rule, 0, z,
                        NULL, 0, NULL, 0, &pr);
         if (rc) goto done;
         r->probes++;
@@ -703,13 +764,12 @@ int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, con
         } else {
             if (pr.status == ORC_INFEASIBLE && D > lo) lo = D;
             slo = D;
-            if (pr.status == ORC_MAX_ITER) uncertified = 1;
         }
         if (lo > slo) slo = lo;
         if (hi < shi) shi = hi;
     }
     r->lower = lo; r->upper = hi; r->objective = hi;
-    r->status = (hi <= (1.0 + eps) * lo && !uncertified) ? 0 : 1;
+    r->status = (hi <= (1.0 + eps) * lo) ? 0 : 1;
 done:
     free(z); free(load); free(cov);
     return rc;

@@ -202,6 +202,24 @@ class Solver:
                                          ctypes.addressof(by), ctypes.addressof(nz)), "mwu_time_pass")
         return us.value, by.value, nz.value
 
+    # ---- smoothed potential (device pointers) ---------------------------------
+    def potential_forward(self, x_dev_ptr: int, stream: Optional[int] = None) -> float:
+        """smax(Px) - smin(Cx) at the current probe's param; x_dev_ptr is the
+        device address of n doubles (internal variable order)."""
+        v = ctypes.c_double()
+        _lib.check(self._L.mwu_potential_forward(self._h, ctypes.c_void_p(x_dev_ptr),
+                                                 ctypes.addressof(v), ctypes.c_void_p(stream or 0)),
+                   "mwu_potential_forward")
+        return v.value
+
+    def potential_backward(self, x_dev_ptr: int, grad_scale: float, grad_dev_ptr: int,
+                           stream: Optional[int] = None) -> None:
+        """grad_dev <- grad_scale * (P^T grad smax(Px) - C^T grad smin(Cx))."""
+        _lib.check(self._L.mwu_potential_backward(self._h, ctypes.c_void_p(x_dev_ptr),
+                                                  float(grad_scale), ctypes.c_void_p(grad_dev_ptr),
+                                                  ctypes.c_void_p(stream or 0)),
+                   "mwu_potential_backward")
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.mwu_destroy(self._h)

@@ -126,31 +126,25 @@ MWU_DEV void store_record(const double *s_rec, int Q, double *partials)
     if (threadIdx.x < Q) partials[(size_t)blockIdx.x * QMAX + threadIdx.x] = s_rec[threadIdx.x];
 }
 
-// Fold the G records of a pass (finisher kernel, one workgroup).  BLOCK / Q
-// threads share each quantity: thread (q, j) folds records j, j + BLOCK/Q,
-// ... in order, then thread q folds the BLOCK/Q partials in order.  Record
-// entry q is reduced with the operation of layout position q + qoff.
+// Fold the G records of a pass (finisher kernel, one workgroup): thread t
+// folds whole records t, t + BLOCK, ... in order (all Q loads of a record in
+// flight at once), then the block combines.  Record entry q is reduced with
+// the operation of layout position q + qoff.
 template <int Q>
 MWU_DEV void fold_records(const double *partials, int G, Red r, int qoff, double *s_wave, double *out)
 {
-    static_assert(Q <= BLOCK, "record too wide");
-    __shared__ double s_fold[BLOCK];
-    constexpr int NT = BLOCK / Q;
-    const int t = threadIdx.x;
-    if (t < NT * Q) {
-        const int q = t % Q, j = t / Q;
-        double a = red_id(q + qoff, r);
-        for (int b = j; b < G; b += NT) a = red_op(a, partials[(size_t)b * QMAX + q], q + qoff, r);
-        s_fold[j * Q + q] = a;
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = red_id(q + qoff, r);
+    for (int b = threadIdx.x; b < G; b += BLOCK) {
+        const double *rec = partials + (size_t)b * QMAX;
+        double t[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) t[q] = rec[q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], t[q], q + qoff, r);
     }
-    __syncthreads();
-    if (t < Q) {
-        double a = s_fold[t];
-        for (int j = 1; j < NT; ++j) a = red_op(a, s_fold[j * Q + t], t + qoff, r);
-        out[t] = a;
-    }
-    __syncthreads();
-    (void)s_wave;
+    block_combine<Q>(v, r, qoff, s_wave, out);
 }
 
 // ------------------------------------------------------------ accumulators
@@ -306,9 +300,10 @@ MWU_DEV void seg_tile(const Tile &tl, const int32_t *__restrict__ ptr, ElemF &el
 }
 
 // Chunk tile of a long segment: reduce the chunk and store its partial sum;
-// the finisher kernel of the pass completes the segment.
+// a later kernel completes the segment.  Returns the chunk's sum in thread 0
+// (zero in the other threads).
 template <class Acc, class ElemF>
-MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, Acc *s_tacc, Acc *lpart, const int32_t *lfirst)
+MWU_DEV Acc chunk_tile(const Tile &tl, ElemF &elem, Acc *s_tacc, Acc *lpart, const int32_t *lfirst)
 {
     const int tid = threadIdx.x;
     Acc acc = acc_zero<Acc>();
@@ -317,12 +312,14 @@ MWU_DEV void chunk_tile(const Tile &tl, ElemF &elem, Acc *s_tacc, Acc *lpart, co
     for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_acc(acc, m);
     if ((tid & 63) == 0) s_tacc[tid >> 6] = acc;
     __syncthreads();
+    Acc tot = acc_zero<Acc>();
     if (tid == 0) {
-        Acc tot = s_tacc[0];
+        tot = s_tacc[0];
         for (int w = 1; w < BLOCK / 64; ++w) tot += s_tacc[w];
         lpart[lfirst[tl.lid] + tl.cidx] = tot;
     }
     __syncthreads();
+    return tot;
 }
 
 // Sum of the chunk partials of long segment lid, in chunk order.

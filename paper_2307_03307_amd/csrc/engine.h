@@ -208,5 +208,9 @@ template <class T> void vc_export(const VcDev<T> &v, int which, double *out, hip
 template <class T> void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st);
 template <class T> void vc_occupancy(int *per_cu_ftile, int *per_cu_edge);
 template <class T> void generic_occupancy(int *per_cu_fwd, int *per_cu_col, int *per_cu_search);
+// Main kernel of pass `which` (0 row, 1 column, 2 forward, 3 search) alone.
+template <class T> void generic_main(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st,
+                                     int which);
+template <class T> void vc_main(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, int which);
 
 }  // namespace mwu

@@ -663,6 +663,18 @@ void set_phase(Ctl *ctl, int phase, hipStream_t st)
     hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(1), 0, st, ctl, phase);
 }
 
+// The main kernel of one pass alone (no finisher): timing of held passes.
+template <class T>
+void generic_main(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st, int which)
+{
+    switch (which) {
+    case 0: LAUNCH(k_row<T>, L.grid_elem_rows, g, ctl, L.partials); break;
+    case 1: LAUNCH(k_col<T>, L.grid_ctile, g, ctl, L.partials); break;
+    case 2: LAUNCH((k_fwd<T, false>), L.grid_rtile, g, ctl, (const T *)g.d, g.dyz, L.partials); break;
+    default: LAUNCH(k_search<T>, L.grid_search, g, ctl, L.partials); break;
+    }
+}
+
 // Workgroups per CU of the persistent tile kernels and the search kernel.
 template <class T>
 void generic_occupancy(int *per_cu_fwd, int *per_cu_col, int *per_cu_search)
@@ -678,6 +690,7 @@ void generic_occupancy(int *per_cu_fwd, int *per_cu_col, int *per_cu_search)
 
 #define MWU_INSTANTIATE(T)                                                                      \
     template void generic_occupancy<T>(int *, int *, int *);                                   \
+    template void generic_main<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t, int); \
     template void generic_init<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t,    \
                                   bool);                                                        \
     template void generic_load_x<T>(const GenericDev<T> &, Ctl *, const Launch &, hipStream_t,  \

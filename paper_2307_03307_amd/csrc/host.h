@@ -80,6 +80,7 @@ struct Program {
     virtual void col_pass() = 0;
     virtual void fwd_pass() = 0;
     virtual void search_pass() = 0;
+    virtual void main_kernel(int which) = 0;          // a pass's main kernel alone (timing)
     virtual void potential(const double *x_dev, double *val_dev, double scale, double *grad_dev,
                            hipStream_t st) = 0;
     virtual void set_debug(bool on) = 0;

@@ -243,6 +243,7 @@ class GenericProgram : public Program {
     void col_pass() override { generic_col<T>(dbg_gd(), ctl(), L_, s_.stream); }
     void fwd_pass() override { generic_fwd<T>(dbg_gd(), ctl(), L_, s_.stream); }
     void search_pass() override { generic_search<T>(dbg_gd(), ctl(), L_, s_.stream); }
+    void main_kernel(int which) override { generic_main<T>(gd_, ctl(), L_, s_.stream, which); }
 
     void set_debug(bool on) override
     {

@@ -194,6 +194,7 @@ class VcoverProgram : public Program {
     void col_pass() override { vc_passB<T>(dbg(), ctl(), L_, s_.stream); }
     void fwd_pass() override {}
     void search_pass() override { vc_search<T>(dbg(), ctl(), L_, s_.stream); }
+    void main_kernel(int which) override { vc_main<T>(vd_, ctl(), L_, s_.stream, which); }
 
     void set_debug(bool on) override
     {

@@ -413,14 +413,18 @@ static void push_ctl(Solver &s)
 // (FP32 weights and per-thread partials) stays well below this, so a
 // coordinate is moved only when g_i < h_i holds beyond that rounding.
 static constexpr double kMixedQmin = 1.0 / 65536.0;
+// Times the probe tolerance may be halved when the search bracket closes
+// without a certified (1 + eps) bracket.
+static constexpr int kMaxHalvings = 2;
 
-static void begin_probe(Solver &s, double param, const double *x0)
+static void begin_probe(Solver &s, double param, const double *x0, double eps_probe = 0.0)
 {
     Ctl &c = *s.ctl_host;
     std::memset(&c, 0, sizeof(Ctl));
     const int64_t m = s.prog->mP() + s.prog->mC();
-    c.eta = 10.0 * std::log((double)m) / s.opt.eps;          // Algorithm 1, natural log
-    c.eps = s.opt.eps;
+    const double eps = eps_probe > 0.0 ? eps_probe : s.opt.eps;
+    c.eta = 10.0 * std::log((double)m) / eps;                // Algorithm 1, natural log
+    c.eps = eps;
     const bool single = s.prog->mP() == 1 || s.prog->mC() == 1;
     const double sfac = (single && !(s.opt.flags & MWU_FLAG_NO_FACTOR2)) ? 1.0 : 0.5;
     c.step = sfac / c.eta;
@@ -517,11 +521,11 @@ static SolveOut solve_impl(Solver &s)
     SolveOut o{};
     const double eps = s.opt.eps;
     double lo = s.lo0, hi = s.hi0;
-    bool uncertified = false;
     o.have_best_dev = false;
     o.best_scale = 1.0;
+    double eps_probe = eps;
     auto probe_done = [&](double param) {
-        begin_probe(s, param, nullptr);
+        begin_probe(s, param, nullptr, eps_probe);
         run_probe(s, s.opt.max_iter);
         pull_ctl(s);
         Ctl c = *s.ctl_host;
@@ -556,20 +560,30 @@ static SolveOut solve_impl(Solver &s)
     // search bracket for the parameter: moves to every probed value, while
     // lo/hi (the certified bracket on OPT) move only with certificates
     double slo = lo, shi = hi;
-    while (o.probes < s.opt.max_probes && hi > (1.0 + eps) * lo && shi > (1.0 + eps / 16.0) * slo) {
+    int halvings = 0;
+    while (o.probes < s.opt.max_probes && hi > (1.0 + eps) * lo) {
+        if (!(shi > (1.0 + eps / 16.0) * slo)) {
+            // the search bracket closed without a certified bracket: continue
+            // at half the probe tolerance from the certified bracket
+            if (halvings == kMaxHalvings) break;
+            ++halvings;
+            eps_probe *= 0.5;
+            slo = lo;
+            shi = hi;
+            continue;
+        }
         const double param = std::sqrt(slo * shi);
         const Ctl c = probe_done(param);
         finish_probe_stats(s);
         const Ctl f = *s.ctl_host;
         if (trace)
-            std::fprintf(stderr, "[mwu] probe %lld param %.10g status %d iters %d passes %lld alpha %.6g "
+            std::fprintf(stderr, "[mwu] probe %lld eps %.4g param %.10g status %d iters %d passes %lld alpha %.6g "
                          "sumx %.10g ymax %.10g zmin %.10g bounds %.10g %.10g bracket %.10g %.10g\n",
-                         (long long)o.probes, param, c.status, c.iter, (long long)c.search_passes,
+                         (long long)o.probes, eps_probe, param, c.status, c.iter, (long long)c.search_passes,
                          c.last_alpha, f.sumx, f.ymax, f.zmin, c.pack_bound, c.cover_bound, lo, hi);
         o.max_violation = std::max({0.0, f.ymax - 1.0, 1.0 - f.zmin});
         if (c.status == ST_NUMERIC) throw ApiError{MWU_ERR_DEVICE, "numerical failure in a probe"};
         const bool feasible = c.status == ST_FEASIBLE;
-        if (c.status == ST_MAX_ITER) uncertified = true;
         if (s.form == MWU_PACKING) {
             if (c.pack_bound < hi) hi = c.pack_bound;
             if (feasible) {
@@ -602,7 +616,7 @@ static SolveOut solve_impl(Solver &s)
     o.lower = lo;
     o.upper = hi;
     o.objective = s.form == MWU_PACKING ? lo : hi;
-    o.status = (hi <= (1.0 + eps) * lo && !uncertified) ? MWU_CERTIFIED : MWU_FEASIBLE_UNCERTIFIED;
+    o.status = hi <= (1.0 + eps) * lo ? MWU_CERTIFIED : MWU_FEASIBLE_UNCERTIFIED;
     return o;
 }
 
@@ -869,7 +883,7 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
 mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, double *bytes,
                          double *nnz)
 {
-    if (!h || which < 0 || which > 3 || reps < 1 || !avg_us) return MWU_ERR_INVALID_ARG;
+    if (!h || which < 0 || which > 4 || reps < 1 || !avg_us) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
@@ -886,21 +900,26 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         pull_ctl(s);
         Ctl &c = *s.ctl_host;
         c.eval_mode = 0;
-        static const int phase_of[4] = {PH_ROW, PH_COL, PH_FWD, PH_SEARCH};
+        static const int phase_of[5] = {PH_ROW, PH_COL, PH_FWD, PH_SEARCH, PH_SEARCH};
         c.hold = phase_of[which];
         c.phase = phase_of[which];
         c.alpha = 0.0;
-        c.skind = SK_EXP;
-        c.ncand = KC;
-        for (int k = 0; k < KC; ++k) c.cand[k] = std::ldexp(1.0, k);
-        c.ga0 = 1.0;
+        if (which == 4) {   // bisection grid of [1, 2] to depth 4
+            c.skind = SK_GRID;
+            c.ncand = 15;
+            for (int k = 0; k < KC; ++k) c.cand[k] = 1.0 + (k + 1) / 16.0;
+            c.ga0 = 1.0 + 1.0 / 16.0;
+            c.gdelta = 1.0 / 16.0;
+        } else {            // exponential grid from 1
+            c.skind = SK_EXP;
+            c.ncand = KE;
+            for (int k = 0; k < KC; ++k) c.cand[k] = std::ldexp(1.0, k);
+            c.ga0 = 1.0;
+            c.gdelta = 0.0;
+        }
         push_ctl(s);
-        auto launch = [&] {
-            if (which == 0) s.prog->row_pass();
-            else if (which == 1) s.prog->col_pass();
-            else if (which == 2) s.prog->fwd_pass();
-            else s.prog->search_pass();
-        };
+        // the pass's main kernel only (its finisher leaves a held state alone)
+        auto launch = [&] { s.prog->main_kernel(which == 4 ? 3 : which); };
         launch();   // warm caches
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
@@ -914,8 +933,8 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *avg_us = 1000.0 * ms / reps;
-        if (bytes) *bytes = s.prog->algo_bytes(which);
-        if (nnz) *nnz = s.prog->pass_nnz(which);
+        if (bytes) *bytes = s.prog->algo_bytes(which == 4 ? 3 : which);
+        if (nnz) *nnz = s.prog->pass_nnz(which == 4 ? 3 : which);
         *s.ctl_host = saved;   // the probe continues from where it was
         push_ctl(s);
         HIP_OK(hipStreamSynchronize(s.stream));

@@ -272,7 +272,8 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
         } else {
             const T xu = segval(tl.s0);
             auto elem = [&](int k) -> T { return term(xu, stage(k)); };
-            chunk_tile<T>(tl, elem, s_tacc, vd.flpart, vd.flong.lfirst);
+            const T tot = chunk_tile<T>(tl, elem, s_tacc, vd.flpart, vd.flong.lfirst);
+            v[0] += (double)tot;   // nonzero in thread 0 only
         }
     }
     const Red red{1, 1, 0};
@@ -280,26 +281,25 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     store_record(s_rec, 2, part);
 }
 
+// h of the vertices whose rows were split into chunks: the chunk partials in
+// chunk order (one thread per long row, many workgroups).
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_long_k(VcDev<T> vd, const Ctl *ctl)
+{
+    if (ctl->phase != PH_ROW) return;
+    const int l = blockIdx.x * BLOCK + threadIdx.x;
+    if (l < vd.flong.nlong) vd.h[vd.flong.lseg[l]] = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
+}
+
 template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, const double *part, int G)
 {
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
-    __shared__ double s_lng[QMAX];
     if (ctl->phase != PH_ROW) return;
     const Red red{1, 1, 0};
-    double v[2] = {0.0, INFINITY};
-    for (int l = threadIdx.x; l < vd.flong.nlong; l += BLOCK) {
-        const T acc = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
-        vd.h[vd.flong.lseg[l]] = acc;
-        v[0] += (double)acc;
-    }
-    block_combine<2>(v, red, 0, s_wave, s_lng);
     fold_records<2>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
-        finish_vcA(ctl, s_rec);
-    }
+    if (threadIdx.x == 0) finish_vcA(ctl, s_rec);
 }
 
 template <class T>
@@ -480,6 +480,7 @@ void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
     VLAUNCH(vc_commit_k<T>, L.grid_v, v, ctl);
     VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials);
+    if (v.flong.nlong > 0) VLAUNCH(vc_long_k<T>, (v.flong.nlong + BLOCK - 1) / BLOCK, v, ctl);
     VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile);
 }
 
@@ -521,6 +522,18 @@ void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st)
     VLAUNCH(vc_import_k<T>, g, v, src);
 }
 
+// The main kernel of one pass alone (no finisher): timing of held passes.
+template <class T>
+void vc_main(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, int which)
+{
+    switch (which) {
+    case 0: VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials); break;
+    case 1: VLAUNCH(vc_passB_k<T>, L.grid_v, v, ctl, L.partials); break;
+    case 2: break;
+    default: VLAUNCH(vc_search_k<T>, L.grid_e, v, ctl, L.partials); break;
+    }
+}
+
 // Workgroups of the tile and edge kernels that fit on one CU at once: the
 // persistent grids are sized to exactly fill the chip in one round.
 template <class T>
@@ -541,7 +554,8 @@ void vc_occupancy(int *per_cu_ftile, int *per_cu_edge)
     template void vc_search<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);          \
     template void vc_export<T>(const VcDev<T> &, int, double *, hipStream_t);                    \
     template void vc_import_x<T>(const VcDev<T> &, const double *, hipStream_t);                 \
-    template void vc_occupancy<T>(int *, int *);
+    template void vc_occupancy<T>(int *, int *);                                                  \
+    template void vc_main<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t, int);
 
 MWU_VC_INSTANTIATE(float)
 MWU_VC_INSTANTIATE(double)

@@ -1,0 +1,108 @@
+"""Counter bookkeeping for the roofline report.
+
+``rocprofv3 --pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` (two separate runs of
+``bench.py --copy-calib-mib N``) give, per dispatch, the HBM-side read and
+write volume in KiB.  The same runs include a plain device copy of N MiB,
+whose readings fix the scale between counter units and bytes on this chip.
+``summarize`` turns the two counter CSVs into a small text record (kept under
+``profiles/``) holding the bytes per launch of one kernel and a hash of the
+kernel sources; ``load_traffic`` returns those bytes only while the sources
+still hash the same, so a stale measurement is never reported.
+
+Usage:
+    python -m paper_2307_03307_amd.profiling FETCH_DIR WRITE_DIR KERNEL COPY_MIB OUT [LAST]
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["device_common.h", "engine.h", "vcover.hip", "generic.hip"]
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(d: str, counter: str):
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def _kernel_values(rows, kernel: str, last: int):
+    vals = [v for _, k, v in rows if kernel in k]
+    return vals[-last:] if last else vals
+
+
+def summarize(fetch_dir: str, write_dir: str, kernel: str, copy_mib: int, last: int = 10) -> dict:
+    """Bytes per launch of `kernel` (mean over its last `last` dispatches, the
+    timed repetitions of bench.py) scaled by the copy calibration."""
+    copy_bytes = copy_mib * float(1 << 20)
+    rec = {"kernel": kernel, "source_sha": source_hash(), "copy_mib": copy_mib}
+    for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _rows(d, counter)
+        copies = [v for _, k, v in rows if COPY_KERNEL in k]
+        big = max(copies) if copies else 0.0
+        factor = copy_bytes / (big * 1024.0) if big > 0 else float("nan")
+        vals = _kernel_values(rows, kernel, last)
+        kib = statistics.mean(vals) if vals else float("nan")
+        rec[f"{name}_kib_raw"] = kib
+        rec[f"{name}_copy_kib_raw"] = big
+        rec[f"{name}_factor"] = factor
+        rec[f"{name}_bytes"] = kib * 1024.0 * factor
+        rec[f"{name}_dispatches"] = len(vals)
+    rec["traffic_bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+    return rec
+
+
+def write_record(rec: dict, path: str, command: str) -> None:
+    with open(path, "w") as f:
+        f.write(f"# HBM traffic per launch of {rec['kernel']} (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n")
+        f.write(f"# command: {command}\n")
+        for k, v in rec.items():
+            f.write(f"{k}: {v}\n")
+
+
+def load_traffic(path: str, kernel: str):
+    """traffic_bytes of the record at `path` if it covers `kernel` and the
+    kernel sources have not changed since it was taken, else None."""
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel") != kernel or rec.get("source_sha") != source_hash():
+        return None
+    try:
+        return float(rec["traffic_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
+if __name__ == "__main__":
+    fetch_dir, write_dir, kernel, copy_mib, out = sys.argv[1:6]
+    last = int(sys.argv[6]) if len(sys.argv) > 6 else 10
+    r = summarize(fetch_dir, write_dir, kernel, int(copy_mib), last)
+    cmd = os.environ.get("PMC_COMMAND", "bench.py --copy-calib-mib " + copy_mib)
+    write_record(r, out, cmd)
+    print(r)

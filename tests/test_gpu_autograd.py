@@ -1,0 +1,103 @@
+"""The smoothed potential as a torch.autograd.Function (Section 4.1): forward
+and hand-written backward through the C ABI, against the FP64 oracle and
+against central finite differences of the GPU forward itself.
+
+Workload: the dominating-set LP (C = I + A) of the induced subgraph on the
+first 10,000 vertices of a BFS from the maximum-degree vertex of the seeded
+Chung-Lu graph (2M vertices, exponent 2.3, mean degree 10).
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+EPS = 0.1
+
+
+@pytest.fixture(scope="module")
+def subgraph():
+    g = gg.cached("chunglu2m_g23_d10_s4", lambda: gg.chung_lu(2_000_000, 2.3, 10.0, seed=4))
+    return gg.cached("chunglu2m_g23_d10_s4_bfs10k", lambda: gg.bfs_induced_subgraph(g, 10_000))
+
+
+def _setup(sub, precision):
+    import torch
+    import paper_2307_03307_amd as mwu
+    from paper_2307_03307_amd.autograd import MwuPotential
+    ptr, col = gg.adjacency_csr(sub, with_identity=True)
+    n = sub.num_vertices
+    s = mwu.dominating_set(ptr, col, n, precision=precision)
+    M = 0.05 * n
+    pot = MwuPotential(s, M)
+    C = oracle.dominating_set_matrix(sub)
+    P = oracle.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    eta = oracle.lib().orc_eta(1 + n, EPS)
+    rng = np.random.default_rng(7)
+    # a point with covering rows around 1 and the objective row around 0.6
+    x = rng.uniform(0.02, 0.12, n)
+    x *= 0.6 * M / x.sum()
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda", requires_grad=True)
+    return s, pot, P, C, 1.0 / M, eta, x, xt
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_potential_matches_oracle(subgraph, precision):
+    import torch
+    s, pot, P, C, sP, eta, x, xt = _setup(subgraph, precision)
+    with s:
+        val = pot(xt)
+        val.backward()
+        torch.cuda.synchronize()
+        v_ref, g_ref = oracle.potential(P, sP, C, 1.0, eta, x)
+        got = xt.grad.detach().cpu().numpy()
+        scale = max(1.0, abs(float(val)), abs(v_ref))
+        err_v = abs(float(val) - v_ref) / scale
+        err_g = float(np.max(np.abs(got - g_ref)) / np.max(np.abs(g_ref)))
+        print(f"precision {precision}: potential rel err {err_v:.3e}, gradient rel err {err_g:.3e}")
+        if precision == 0:
+            assert err_v <= 1e-9 and err_g <= 1e-9
+        else:   # FP32 weights and terms, FP64 totals
+            assert err_v <= 1e-5 and err_g <= 2e-3
+
+
+def test_backward_scales_with_grad_output(subgraph):
+    import torch
+    s, pot, P, C, sP, eta, x, xt = _setup(subgraph, 0)
+    with s:
+        (3.0 * pot(xt)).backward()
+        g3 = xt.grad.detach().clone()
+        xt.grad = None
+        pot(xt).backward()
+        torch.cuda.synchronize()
+        assert torch.allclose(g3, 3.0 * xt.grad, rtol=1e-14, atol=0.0)
+
+
+def test_gradient_matches_central_differences(subgraph):
+    """(Phi(x + h v) - Phi(x - h v)) / 2h against <grad, v> along random
+    directions and single coordinates, FP64, h = 1e-3/eta."""
+    import torch
+    s, pot, P, C, sP, eta, x, xt = _setup(subgraph, 0)
+    with s:
+        pot(xt).backward()
+        grad = xt.grad.detach().cpu().numpy()
+        rng = np.random.default_rng(11)
+        h = 1e-3 / eta
+        n = x.shape[0]
+        dirs = [rng.standard_normal(n) for _ in range(3)]
+        for i in rng.choice(n, 8, replace=False):
+            e = np.zeros(n)
+            e[i] = 1.0
+            dirs.append(e)
+        for v in dirs:
+            v = v / np.max(np.abs(v))
+            xp = torch.tensor(x + h * v, dtype=torch.float64, device="cuda")
+            xm = torch.tensor(x - h * v, dtype=torch.float64, device="cuda")
+            fd = (float(pot(xp)) - float(pot(xm))) / (2 * h)
+            an = float(grad @ v)
+            # truncation ~ (eta h)^2 ~ 1e-6 relative; rounding of two FP64
+            # potentials over 2h ~ 1e-14 / 1e-6
+            tol = 1e-4 * abs(an) + 1e-7
+            assert abs(fd - an) <= tol, (fd, an)

@@ -451,3 +451,52 @@ def test_general_lp_normalization(oracle_mod):
     assert (A @ x <= b * (1 + 1e-9)).all()
     assert -lp.fun / (c @ x) <= 1 + EPS + 1e-9
     assert r.lower <= -lp.fun * (1 + 1e-9) <= r.upper * (1 + 1e-9) * (1 + 1e-9)
+
+
+# ------------------------------------------------------------- potential (autograd)
+
+def _d_potential(Pd, sP, Cd, sC, eta, x):
+    """smax(sP P x) - smin(sC C x) from the definitions, in 60 digits."""
+    D = lambda v: Decimal(repr(float(v)))
+    xd = [D(t) for t in x]
+    y = [D(sP) * sum(D(Pd[r, c]) * xd[c] for c in range(len(x))) for r in range(Pd.shape[0])]
+    z = [D(sC) * sum(D(Cd[r, c]) * xd[c] for c in range(len(x))) for r in range(Cd.shape[0])]
+    e = D(eta)
+    smax = sum((e * t).exp() for t in y).ln() / e
+    smin = -sum((-e * t).exp() for t in z).ln() / e
+    return smax - smin
+
+
+@pytest.mark.parametrize("eta", [3.0, 60.0, 900.0])
+def test_potential_value_and_gradient(oracle_mod, eta):
+    """Section 4.1 potential and its gradient g - h: the value against the
+    definitions in 60 digits, every gradient coordinate against a 60-digit
+    central difference of the definitions (step 1e-25, truncation ~1e-45)."""
+    rng = np.random.default_rng(int(eta))
+    n, mP, mC = 6, 3, 4
+    Pd = (rng.random((mP, n)) < 0.6) * rng.uniform(0.3, 2.0, (mP, n))
+    Cd = (rng.random((mC, n)) < 0.6) * rng.uniform(0.3, 2.0, (mC, n))
+    Pd[0, :] += 0.1
+    Cd[0, :] += 0.1
+    P, C = oracle_mod.CSR.from_dense(Pd), oracle_mod.CSR.from_dense(Cd)
+    sP, sC = 0.7, 1.3
+    x = rng.uniform(0.05, 0.6, n)
+    v, gr = oracle_mod.potential(P, sP, C, sC, eta, x)
+    ref = _d_potential(Pd, sP, Cd, sC, eta, x)
+    assert abs(Decimal(repr(float(v))) - ref) < Decimal("1e-13") * max(Decimal(1), abs(ref))
+    h = Decimal("1e-25")
+    for i in range(n):
+        xp = [Decimal(repr(float(t))) for t in x]
+        xm = list(xp)
+        xp[i] += h
+        xm[i] -= h
+        # _d_potential takes floats; evaluate the perturbed points in decimal directly
+        def pot(xs):
+            e = Decimal(repr(eta))
+            y = [Decimal(repr(sP)) * sum(Decimal(repr(float(Pd[r, c]))) * xs[c] for c in range(n))
+                 for r in range(mP)]
+            z = [Decimal(repr(sC)) * sum(Decimal(repr(float(Cd[r, c]))) * xs[c] for c in range(n))
+                 for r in range(mC)]
+            return sum((e * t).exp() for t in y).ln() / e + sum((-e * t).exp() for t in z).ln() / e
+        fd = (pot(xp) - pot(xm)) / (2 * h)
+        assert abs(Decimal(repr(float(gr[i]))) - fd) < Decimal("1e-12") * max(Decimal(1), abs(fd))
