@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (CERTIFIED, COVERING, FEASIBLE_UNCERTIFIED, FP64, INFEASIBLE, MAX_ITER,
                    MIXED, MIXED_FP32_FP64, PACKING, STEP_BIN, STEP_STD, MwuError)
 
-__all__ = ["Solver", "Result", "csr_matrix", "incidence", "incidence_t", "edge_pair",
+__all__ = ["Solver", "BatchSolver", "Result", "csr_matrix", "incidence", "incidence_t", "edge_pair",
            "interweave", "bmatch", "vertex_cover", "dominating_set", "densest_subgraph",
            "MwuError", "PACKING", "COVERING", "MIXED", "FP64", "MIXED_FP32_FP64", "STEP_BIN",
            "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER"]
@@ -219,6 +219,73 @@ class Solver:
                                                   float(grad_scale), ctypes.c_void_p(grad_dev_ptr),
                                                   ctypes.c_void_p(stream or 0)),
                    "mwu_potential_backward")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.mwu_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class BatchSolver:
+    """Many independent bipartite-matching LPs solved together in the same
+    kernels (``mwu_create_batch``): every instance keeps its own probe state
+    and outer search, and all of them advance in one captured launch
+    sequence.  ``graphs`` is a sequence of (num_vertices, u, v)."""
+
+    def __init__(self, graphs, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
+                 step_rule: int = STEP_BIN, precision: int = MIXED_FP32_FP64, device: int = 0,
+                 flags: int = 0):
+        L = _lib.load()
+        self._L = L
+        mats = [incidence(nv, u, v) for (nv, u, v) in graphs]
+        empty = _Mat(_lib.MAT_CSR)
+        arr = (_lib.Problem * len(mats))()
+        for k, m in enumerate(mats):
+            arr[k] = _lib.Problem(PACKING, m.c(), empty.c(), None, None, None)
+        self._mats = mats
+        self._sizes = [int(m.num_edges) for m in mats]
+        opt = _lib.Options()
+        L.mwu_default_options(ctypes.byref(opt))
+        opt.eps, opt.max_iter, opt.max_probes = eps, max_iter, max_probes
+        opt.step_rule, opt.precision, opt.device, opt.flags = step_rule, precision, device, flags
+        h = ctypes.c_void_p()
+        _lib.check(L.mwu_create_batch(arr, len(mats), ctypes.byref(opt), ctypes.byref(h)),
+                   "mwu_create_batch")
+        self._h = h
+
+    @property
+    def count(self) -> int:
+        return len(self._sizes)
+
+    def solve(self):
+        """List of per-instance Results (x per instance, in edge order)."""
+        n = sum(self._sizes)
+        x = np.zeros(n)
+        obj = np.zeros(self.count)
+        it = ctypes.c_int64()
+        info = (_lib.ResultInfo * self.count)()
+        _lib.check(self._L.mwu_solve(self._h, x.ctypes.data, obj.ctypes.data, ctypes.addressof(it),
+                                     ctypes.addressof(info)), "mwu_solve")
+        out, off = [], 0
+        for k, ne in enumerate(self._sizes):
+            r = info[k]
+            out.append(Result(x[off:off + ne].copy(), r.objective, r.status, r.lower_bound,
+                              r.upper_bound, r.total_iterations, r.final_probe_iterations,
+                              r.search_passes, r.probes, r.max_violation, r.seconds_solve))
+            off += ne
+        return out
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -1,0 +1,448 @@
+// Batched program (gfx950): many independent bipartite-matching packing LPs,
+// max 1^T x s.t. M_k x <= 1 (Section 3), each run as the mixed problem with
+// the objective row (1/M_k) 1^T x >= 1 (end of Section 2.2) through Algorithm
+// 2 with the step search of Algorithm 3 (Section 4), all in the same kernels.
+//
+// Every instance keeps its own control block, so instances sit in different
+// phases of their own probes at the same time; each kernel visits the tiles
+// of the instances that are in its phase and skips the others.  The iteration
+// slot launched (and captured in a hipGraph) is
+//   init-x, init-y (probe start), row, column, forward, search, search,
+//   statistics (probe end)
+// with one finisher per pass that runs one workgroup per instance.  The host
+// drives only the outer search over M_k from a compact status array.
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace mwu {
+
+template <class T>
+MWU_DEV void write_stat(const BatchDev<T> &b, int k)
+{
+    const Ctl *c = b.ctl + k;
+    b.stat[4 * k + 0] = c->phase;
+    b.stat[4 * k + 1] = c->status;
+    b.stat[4 * k + 2] = c->iter;
+}
+
+// ------------------------------------------------------------------ probe start
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_initx(BatchDev<T> b)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.net; t += gridDim.x) {
+        const BTile tl = b.et[t];
+        const Ctl *c = b.ctl + tl.inst;
+        if (c->phase != PH_INIT) continue;
+        // Algorithm 1: x_i = eps / (n max_j P_ji) with P_ji = 1 on incident rows
+        const T x0 = (T)(c->eps / (double)b.nedge[tl.inst]);
+        double v[1] = {0.0};
+        for (int e = tl.i0 + threadIdx.x; e < tl.i1; e += BLOCK) {
+            b.x[e] = x0;
+            b.d[e] = T(0);
+            v[0] += (double)x0;
+        }
+        const Red red{1, 0, 0};
+        block_combine<1>(v, red, 0, s_wave, s_rec);
+        if (threadIdx.x == 0) b.epart[(size_t)t * QMAX] = s_rec[0];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_initx_fin(BatchDev<T> b)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const int k = blockIdx.x;
+    Ctl *c = b.ctl + k;
+    if (c->phase != PH_INIT) return;
+    const Red red{1, 0, 0};
+    fold_records<1>(b.epart + (size_t)b.erec0[k] * QMAX, b.erecn[k], red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        finish_sumx(c, s_rec[0]);
+        c->phase = PH_INIT_Y;
+        write_stat(b, k);
+    }
+}
+
+// Vertex sums over incident edges: INIT_Y gives y = P x0 (and clears dy),
+// FWD gives dy = P d.  Record [min over covering rows (none) | max over rows].
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_vfwd(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
+        const BTile tl = b.vt[t];
+        const Ctl *c = b.ctl + tl.inst;
+        const int ph = c->phase;
+        if (ph != PH_INIT_Y && ph != PH_FWD) continue;
+        const bool init = ph == PH_INIT_Y;
+        const T *src = init ? b.x : b.d;
+        const T sP = (T)c->sP;
+        double v[2] = {INFINITY, -INFINITY};
+        for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
+            T acc = T(0);
+            for (int q = b.vptr[i]; q < b.vptr[i + 1]; ++q) acc += src[b.vedge[q]];
+            acc = sP * acc;
+            if (init) { b.y[i] = acc; b.dy[i] = T(0); }
+            else b.dy[i] = acc;
+            v[1] = fmax(v[1], (double)acc);
+        }
+        const Red red{0, 1, 1};
+        block_combine<2>(v, red, 0, s_wave, s_rec);
+        if (threadIdx.x < 2) b.vpart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_vfwd_fin(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    const int k = blockIdx.x;
+    Ctl *c = b.ctl + k;
+    const int ph = c->phase;
+    if (ph != PH_INIT_Y && ph != PH_FWD) return;
+    const Red red{0, 1, 1};
+    fold_records<2>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        if (ph == PH_INIT_Y) {
+            finish_init_fwd(c, s_rec);
+        } else {
+            c->dymax = s_rec[1];
+            begin_search(c, nullptr);
+        }
+        write_stat(b, k);
+    }
+}
+
+// ------------------------------------------------------------------ iteration
+
+// Row pass: y += a dy, w = exp(eta (y - L_P)).  Record [sum w | - | - | max y].
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_row(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
+        const BTile tl = b.vt[t];
+        const Ctl *c = b.ctl + tl.inst;
+        if (c->phase != PH_ROW) continue;
+        const T a = (T)c->alpha;
+        const double eta = c->eta, LP = c->LP;
+        double v[4] = {0.0, 0.0, INFINITY, -INFINITY};
+        for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
+            const T y = b.y[i] + a * b.dy[i];
+            b.y[i] = y;
+            const T w = exp_arg(eta * ((double)y - LP), T(0));
+            b.w[i] = w;
+            v[0] += (double)w;
+            v[3] = fmax(v[3], (double)y);
+        }
+        const Red red{2, 1, 1};
+        block_combine<4>(v, red, 0, s_wave, s_rec);
+        if (threadIdx.x < 4) b.vpart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_row_fin(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    const int k = blockIdx.x;
+    Ctl *c = b.ctl + k;
+    if (c->phase != PH_ROW) return;
+    const Red red{2, 1, 1};
+    fold_records<4>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        finish_row(c, s_rec);
+        write_stat(b, k);
+    }
+}
+
+// Column pass over edges: commit x += a d, then g = (w_u + w_v) / sum w,
+// h = 1/M (the objective row) and the direction.  Record [sum d | min g |
+// max d | max h].  In PH_COMMIT only the commit.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_col(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.net; t += gridDim.x) {
+        const BTile tl = b.et[t];
+        const Ctl *c = b.ctl + tl.inst;
+        const int ph = c->phase;
+        if (ph != PH_COL && ph != PH_COMMIT) continue;
+        const T a = (T)c->alpha;
+        if (ph == PH_COMMIT) {
+            for (int e = tl.i0 + threadIdx.x; e < tl.i1; e += BLOCK) b.x[e] = b.x[e] + a * b.d[e];
+            continue;
+        }
+        const double sP = c->sP, sC = c->sC, invSw = c->invSw, step = c->step, qmin = c->qmin;
+        double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
+        for (int e = tl.i0 + threadIdx.x; e < tl.i1; e += BLOCK) {
+            const T x = b.x[e] + a * b.d[e];
+            b.x[e] = x;
+            const double g = sP * (double)(b.w[b.eu[e]] + b.w[b.ev[e]]) * invSw;
+            const double h = sC;
+            double di = 0.0;
+            const double q = 1.0 - g / h;
+            if (q > qmin) di = step * q * (double)x;
+            const T dt = (T)di;
+            b.d[e] = dt;
+            v[0] += (double)dt;
+            v[1] = fmin(v[1], g);
+            v[2] = fmax(v[2], (double)dt);
+            v[3] = fmax(v[3], h);
+        }
+        const Red red{1, 1, 2};
+        block_combine<4>(v, red, 0, s_wave, s_rec);
+        if (threadIdx.x < 4) b.epart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_col_fin(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    const int k = blockIdx.x;
+    Ctl *c = b.ctl + k;
+    const int ph = c->phase;
+    if (ph != PH_COL && ph != PH_COMMIT) return;
+    if (ph == PH_COMMIT) {
+        if (threadIdx.x == 0) {
+            c->alpha = 0.0;
+            c->phase = PH_STATS;
+            write_stat(b, k);
+        }
+        return;
+    }
+    const Red red{1, 1, 2};
+    fold_records<4>(b.epart + (size_t)b.erec0[k] * QMAX, b.erecn[k], red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        finish_col(c, s_rec);
+        if (c->phase == PH_DONE) c->phase = PH_STATS;
+        write_stat(b, k);
+    }
+}
+
+// ------------------------------------------------------------------ step search
+
+// Packing sums of one search pass over the vertex rows of a tile (KIND fixed
+// per pass): s1P[k] = sum_v w_v expm1(eta a_k dy_v).
+template <class T, int KIND>
+MWU_DEV void kb_search_rows(const BatchDev<T> &b, const BTile &tl, const Ctl *c, double *s_wave,
+                            double *s_rec)
+{
+    const double eta = c->eta, a0 = c->cand[0], gdel = c->gdelta;
+    const int nc = c->ncand;
+    double s1[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) s1[k] = 0.0;
+    for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
+        const T w = b.w[i], dy = b.dy[i];
+        if constexpr (KIND == SK_EXP) {
+            T m = expm1_t((T)(eta * a0 * (double)dy));
+#pragma unroll
+            for (int k = 0; k < KE; ++k) {
+                s1[k] += (double)(w * m);
+                m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
+            }
+        } else if constexpr (KIND == SK_GRID) {
+            T m = expm1_t((T)(eta * a0 * (double)dy));
+            const T mr = expm1_t((T)(eta * gdel * (double)dy));
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                s1[k] += (double)(w * m);
+                m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+                if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * c->cand[k] * (double)dy)));
+        }
+    }
+    const Red redp{KC, 0, 0};
+    block_combine<KC>(s1, redp, 0, s_wave, s_rec);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * KC];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
+        const BTile tl = b.vt[t];
+        const Ctl *c = b.ctl + tl.inst;
+        if (c->phase != PH_SEARCH) continue;
+        double *rec = b.vpart + (size_t)t * QMAX;
+        if (c->skind == SK_REFINE) {
+            const double a = c->ref_alpha, eta = c->eta;
+            double v[2];
+            if (c->ref_valid == 0) {          // pass 1: [min z' (no covering rows) | max eta y']
+                v[0] = INFINITY;
+                v[1] = -INFINITY;
+                for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
+                    v[1] = fmax(v[1], eta * ((double)b.y[i] + a * (double)b.dy[i]));
+                const Red red{0, 1, 1};
+                block_combine<2>(v, red, 0, s_wave, s_rec);
+            } else {                          // pass 2: [sum exp(eta y' - pm) | -]
+                const double pm = c->rfPm;
+                v[0] = 0.0;
+                v[1] = 0.0;
+                for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
+                    v[0] += exp(eta * ((double)b.y[i] + a * (double)b.dy[i]) - pm);
+                const Red red{2, 0, 0};
+                block_combine<2>(v, red, 0, s_wave, s_rec);
+            }
+            if (threadIdx.x < 2) rec[threadIdx.x] = s_rec[threadIdx.x];
+            continue;
+        }
+        switch (c->skind) {
+        case SK_EXP: kb_search_rows<T, SK_EXP>(b, tl, c, s_wave, s_rec); break;
+        case SK_GRID: kb_search_rows<T, SK_GRID>(b, tl, c, s_wave, s_rec); break;
+        default: kb_search_rows<T, SK_LIST>(b, tl, c, s_wave, s_rec); break;
+        }
+        if (threadIdx.x < KC) rec[threadIdx.x] = s_rec[threadIdx.x];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_search_fin(BatchDev<T> b)
+{
+    __shared__ double s_wave[4 * KC];
+    __shared__ double s_rec[QMAX];
+    const int k = blockIdx.x;
+    Ctl *c = b.ctl + k;
+    if (c->phase != PH_SEARCH) return;
+    const double *part = b.vpart + (size_t)b.vrec0[k] * QMAX;
+    const int G = b.vrecn[k];
+    if (c->skind == SK_REFINE) {
+        const Red red = c->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
+        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+    } else {
+        const Red red{KC, 0, 0};
+        fold_records<KC>(part, G, red, 0, s_wave, s_rec);
+        // no explicit covering rows: their sums are unused (the objective row
+        // is evaluated in closed form)
+        for (int q = KC + threadIdx.x; q < 4 * KC; q += BLOCK) s_rec[q] = 0.0;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        finish_search(c, s_rec);
+        if (c->phase == PH_DONE) c->phase = PH_STATS;
+        write_stat(b, k);
+    }
+}
+
+// ------------------------------------------------------------------ probe end
+
+// FP64 statistics of the final x: max over vertices of sum_{e ~ v} x_e, and
+// sum x (the objective row before scaling).
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_stats_v(BatchDev<T> b)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
+        const BTile tl = b.vt[t];
+        if (b.ctl[tl.inst].phase != PH_STATS) continue;
+        double v[1] = {-INFINITY};
+        for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
+            double acc = 0.0;
+            for (int q = b.vptr[i]; q < b.vptr[i + 1]; ++q) acc += (double)b.x[b.vedge[q]];
+            v[0] = fmax(v[0], acc);
+        }
+        const Red red{0, 0, 1};
+        block_combine<1>(v, red, 0, s_wave, s_rec);
+        if (threadIdx.x == 0) b.vpart[(size_t)t * QMAX] = s_rec[0];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_stats_e(BatchDev<T> b)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    for (int t = blockIdx.x; t < b.net; t += gridDim.x) {
+        const BTile tl = b.et[t];
+        if (b.ctl[tl.inst].phase != PH_STATS) continue;
+        double v[1] = {0.0};
+        for (int e = tl.i0 + threadIdx.x; e < tl.i1; e += BLOCK) v[0] += (double)b.x[e];
+        const Red red{1, 0, 0};
+        block_combine<1>(v, red, 0, s_wave, s_rec);
+        if (threadIdx.x == 0) b.epart[(size_t)t * QMAX] = s_rec[0];
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void kb_stats_fin(BatchDev<T> b)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    __shared__ double s_rec2[QMAX];
+    const int k = blockIdx.x;
+    Ctl *c = b.ctl + k;
+    if (c->phase != PH_STATS) return;
+    const Red rmax{0, 0, 1}, rsum{1, 0, 0};
+    fold_records<1>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], rmax, 0, s_wave, s_rec);
+    fold_records<1>(b.epart + (size_t)b.erec0[k] * QMAX, b.erecn[k], rsum, 0, s_wave, s_rec2);
+    if (threadIdx.x == 0) {
+        c->sumx = s_rec2[0];
+        c->ymax = c->sP * s_rec[0];
+        c->zmin = c->sC * s_rec2[0];
+        c->phase = PH_IDLE;
+        write_stat(b, k);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define BLAUNCH(kernel, grid) hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, st, b)
+
+template <class T>
+void batch_slots(const BatchDev<T> &b, const BLaunch &L, int slots, hipStream_t st)
+{
+    for (int s = 0; s < slots; ++s) {
+        BLAUNCH(kb_initx<T>, L.grid_e);
+        BLAUNCH(kb_initx_fin<T>, b.nb);
+        BLAUNCH(kb_vfwd<T>, L.grid_v);       // INIT_Y instances
+        BLAUNCH(kb_vfwd_fin<T>, b.nb);
+        BLAUNCH(kb_row<T>, L.grid_v);
+        BLAUNCH(kb_row_fin<T>, b.nb);
+        BLAUNCH(kb_col<T>, L.grid_e);
+        BLAUNCH(kb_col_fin<T>, b.nb);
+        BLAUNCH(kb_vfwd<T>, L.grid_v);       // FWD instances
+        BLAUNCH(kb_vfwd_fin<T>, b.nb);
+        BLAUNCH(kb_search<T>, L.grid_v);
+        BLAUNCH(kb_search_fin<T>, b.nb);
+        BLAUNCH(kb_search<T>, L.grid_v);
+        BLAUNCH(kb_search_fin<T>, b.nb);
+        BLAUNCH(kb_stats_v<T>, L.grid_v);
+        BLAUNCH(kb_stats_e<T>, L.grid_e);
+        BLAUNCH(kb_stats_fin<T>, b.nb);
+    }
+}
+
+template <class T>
+void batch_occupancy(int *per_cu_v, int *per_cu_e)
+{
+    int a = 0, c = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_search<T>, BLOCK, 0) != hipSuccess) a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, kb_col<T>, BLOCK, 0) != hipSuccess) c = 0;
+    *per_cu_v = a > 0 ? a : 1;
+    *per_cu_e = c > 0 ? c : 1;
+}
+
+template void batch_slots<float>(const BatchDev<float> &, const BLaunch &, int, hipStream_t);
+template void batch_slots<double>(const BatchDev<double> &, const BLaunch &, int, hipStream_t);
+template void batch_occupancy<float>(int *, int *);
+template void batch_occupancy<double>(int *, int *);
+
+}  // namespace mwu

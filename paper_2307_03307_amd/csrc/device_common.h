@@ -678,4 +678,85 @@ MWU_DEV void finish_search(Ctl *c, const double *rec)
     replay(c);
 }
 
+// ------------------------------------------------- finishers of the CSR passes
+// Shared by the generic engine and the batched program: they turn the reduced
+// record of a pass into the next state of the probe (Algorithm 2).
+
+MWU_DEV void finish_row(Ctl *c, const double *rec)
+{
+    // rec: [sum w | sum u | min z | max y]
+    if (held(c)) return;
+    const double a = c->alpha;
+    bool bad = false;
+    if (c->onesP) {
+        c->y1 += a * c->dy1;
+        c->LP = c->y1;
+        c->invSw = 1.0;
+        c->ymax = c->y1;
+    } else {
+        const double sw = rec[0];
+        bad |= !(sw > 0.0) || !isfinite(sw);
+        c->LP += log(sw) / c->eta;
+        c->invSw = 1.0 / sw;
+        c->ymax = rec[3];
+    }
+    if (c->onesC) {
+        c->z1 += a * c->dz1;
+        c->LC = c->z1;
+        c->invSu = 1.0;
+        c->zmin = c->z1;
+    } else {
+        const double su = rec[1];
+        bad |= !(su > 0.0) || !isfinite(su);
+        c->LC -= log(su) / c->eta;
+        c->invSu = 1.0 / su;
+        c->zmin = rec[2];
+    }
+    if (c->eval_mode) { c->phase = PH_COL; return; }
+    if (bad) { c->status = ST_NUMERIC; c->phase = PH_COMMIT; return; }
+    if (c->zmin >= 1.0) { c->status = ST_FEASIBLE; c->phase = PH_COMMIT; }
+    else if (c->iter >= c->max_iter) { c->status = ST_MAX_ITER; c->phase = PH_COMMIT; }
+    else c->phase = PH_COL;
+}
+
+MWU_DEV void finish_col(Ctl *c, const double *rec)
+{
+    // rec: [sum d | min g | max d | max h]
+    if (held(c)) return;
+    c->alpha = 0.0;
+    c->dsum = rec[0];
+    c->gmin = rec[1];
+    c->dmax = rec[2];
+    c->hmax = rec[3];
+    const double cf = 1.0 - c->qmin;   // margin for the rounding of g and h
+    if (c->gmin > 0.0 && 1.0 / (cf * c->gmin) < c->pack_bound) c->pack_bound = 1.0 / (cf * c->gmin);
+    if (c->hmax > 0.0 && cf / c->hmax > c->cover_bound) c->cover_bound = cf / c->hmax;
+    c->dy1 = c->onesP ? c->sP * c->dsum : 0.0;
+    c->dz1 = c->onesC ? c->sC * c->dsum : 0.0;
+    if (c->eval_mode) { c->phase = PH_FWD; return; }
+    if (!(c->dmax > 0.0)) { c->status = ST_INFEASIBLE; c->phase = PH_DONE; return; }
+    c->phase = PH_FWD;
+}
+
+MWU_DEV void finish_init_fwd(Ctl *c, const double *rec)
+{
+    // rec: [min z | max y]
+    c->zmin = c->onesC ? c->z1 : rec[0];
+    c->ymax = c->onesP ? c->y1 : rec[1];
+    c->LP = c->ymax;        // first shifts; the row pass turns them into exact LSE totals
+    c->LC = c->zmin;
+    c->alpha = 0.0;
+    c->status = ST_RUNNING;
+    c->phase = PH_ROW;
+}
+
+MWU_DEV void finish_sumx(Ctl *c, double sumx)
+{
+    c->sumx = sumx;
+    c->y1 = c->sP * sumx;
+    c->z1 = c->sC * sumx;
+    c->dy1 = 0.0;
+    c->dz1 = 0.0;
+}
+
 }  // namespace mwu

@@ -25,7 +25,11 @@ enum Phase : int32_t {
     PH_FWD = 3,      // forward product of the direction
     PH_SEARCH = 4,   // K-candidate step search passes
     PH_COMMIT = 5,   // apply pending step to x only, then stop
-    PH_DONE = 6
+    PH_DONE = 6,
+    // batched program only
+    PH_INIT = 7,     // probe start: x = x0
+    PH_INIT_Y = 8,   // probe start: y = P x0 and the first LSE shift
+    PH_STATS = 9     // probe ended: FP64 statistics of x, then PH_IDLE
 };
 
 enum Status : int32_t { ST_RUNNING = 0, ST_FEASIBLE = 1, ST_INFEASIBLE = 2, ST_MAX_ITER = 3,
@@ -149,6 +153,38 @@ struct VcDev {
     double *h_dbg;                      // nullable
     const double *forced;
 };
+
+// Batched matching program: many independent packing LPs max 1^T x s.t.
+// M_k x <= 1 (bipartite matching, Section 3) in concatenated arrays.  Tiles
+// never cross instances; every tile of a pass writes one record, and the
+// finisher of instance k folds its contiguous range of tile records.
+struct BTile {
+    int32_t inst, i0, i1, pad;
+};
+
+template <class T>
+struct BatchDev {
+    int32_t nb, nv, ne;
+    const int32_t *vptr, *vedge;          // incident edges of each vertex (global edge ids)
+    const int32_t *eu, *ev;               // endpoints of each edge (global vertex ids)
+    T *x, *d;                             // per edge (variables)
+    T *y, *dy, *w;                        // per vertex (packing rows)
+    const BTile *vt, *et;                 // vertex tiles, edge tiles (grouped by instance)
+    int32_t nvt, net;
+    const int32_t *vrec0, *vrecn;         // per instance: first vertex tile, count
+    const int32_t *erec0, *erecn;         // per instance: first edge tile, count
+    const int32_t *nedge;                 // per instance: number of edges (variables)
+    Ctl *ctl;                             // one control block per instance
+    int32_t *stat;                        // per instance: phase, status, iter, serial
+    double *vpart, *epart;                // one record (QMAX doubles) per tile
+};
+
+struct BLaunch {
+    int grid_v, grid_e;                   // persistent grids over vertex / edge tiles
+};
+
+template <class T> void batch_slots(const BatchDev<T> &b, const BLaunch &L, int slots, hipStream_t st);
+template <class T> void batch_occupancy(int *per_cu_v, int *per_cu_e);
 
 // Launch helpers implemented in the .hip files.
 struct Launch {

@@ -91,6 +91,16 @@ struct Program {
     virtual double pass_nnz(int which) const = 0;
 };
 
+// Many independent problems solved together (the batched programs).
+struct BatchProgram {
+    virtual ~BatchProgram() {}
+    virtual int32_t count() const = 0;
+    virtual int64_t total_variables() const = 0;
+    // x_out: concatenated variables of all instances (nullable); obj_out and
+    // info: one entry per instance (nullable); iters_out: total iterations.
+    virtual void solve(double *x_out, double *obj_out, int64_t *iters_out, mwu_result_info *info) = 0;
+};
+
 struct Solver {
     mwu_options opt{};
     mwu_form form = MWU_PACKING;
@@ -113,6 +123,7 @@ struct Solver {
     DevBuf trace_buf;                // accepted steps of the current probe (max_iter doubles)
     Ctl *ctl_host = nullptr;         // pinned mirror
     std::unique_ptr<Program> prog;
+    std::unique_ptr<BatchProgram> batch;
     hipGraphExec_t graph = nullptr;
     int graph_slots = 0;
     bool in_probe = false;
@@ -130,6 +141,7 @@ TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg);
 // Program builders.
 std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C);
 // Vertex cover from a validated edge list; newid maps vertices to compact ids (-1 = isolated).
+std::unique_ptr<BatchProgram> make_batch_matching(Solver &s, const mwu_problem *probs, int32_t count);
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,
                                              const std::vector<int64_t> &newid, int64_t nv);
 

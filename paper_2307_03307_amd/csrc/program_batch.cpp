@@ -1,0 +1,374 @@
+// Host side of the batched matching program: layout of many instances in
+// concatenated arrays, the captured iteration slots, and the outer search
+// over M_k of every instance (the same rules as the single-instance driver,
+// run per instance while all probes advance together on the device).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+
+namespace mwu {
+
+namespace {
+
+constexpr int kTileV = BLOCK * 4;    // vertices per vertex tile
+constexpr int kTileE = BLOCK * 8;    // edges per edge tile
+constexpr double kMixedQminB = 1.0 / 65536.0;
+constexpr int kMaxHalvingsB = 2;
+
+struct Inst {
+    int64_t v0 = 0, nv = 0, e0 = 0, ne = 0;   // ranges in the concatenated arrays
+    int64_t user_v = 0;                       // vertices as given (before dropping isolated ones)
+    double lo = 0, hi = 0, slo = 0, shi = 0, eps_probe = 0, param = 0;
+    int halvings = 0, probes = 0, serial = 0;
+    int64_t iters = 0, passes = 0, final_iters = 0;
+    bool done = false, have_best = false, failed = false;
+    double best_scale = 1.0, x_start_scale = 1.0, max_violation = 0.0;
+};
+
+}  // namespace
+
+template <class T>
+class BatchMatching : public BatchProgram {
+  public:
+    BatchMatching(Solver &s, const mwu_problem *probs, int32_t count) : s_(s)
+    {
+        nb_ = count;
+        inst_.resize(count);
+        std::vector<int32_t> eu, ev, vptr(1, 0), vedge;
+        std::vector<BTile> vt, et;
+        std::vector<int32_t> vrec0(count), vrecn(count), erec0(count), erecn(count), nedge(count);
+        int64_t V = 0, E = 0;
+        for (int32_t k = 0; k < count; ++k) {
+            const mwu_problem &p = probs[k];
+            if (p.form != MWU_PACKING || p.P.kind != MWU_MAT_INCIDENCE || p.b_P || p.c)
+                throw ApiError{MWU_ERR_INVALID_ARG,
+                               "batched solve supports matching LPs (PACKING, INCIDENCE, b = c = 1)"};
+            const mwu_matrix &m = p.P;
+            if (!(m.num_vertices > 0 && m.num_edges > 0 && m.edge_u && m.edge_v))
+                throw ApiError{MWU_ERR_INVALID_ARG, "empty or NULL edge list"};
+            const int64_t nv = m.num_vertices, ne = m.num_edges;
+            // validate: range, self-loops, duplicates
+            std::vector<uint64_t> key(ne);
+            for (int64_t e = 0; e < ne; ++e) {
+                const int64_t a = m.edge_u[e], b = m.edge_v[e];
+                if (a < 0 || a >= nv || b < 0 || b >= nv) throw ApiError{MWU_ERR_GRAPH, "vertex id out of range"};
+                if (a == b) throw ApiError{MWU_ERR_GRAPH, "self-loop"};
+                key[e] = (uint64_t)std::min(a, b) * (uint64_t)nv + (uint64_t)std::max(a, b);
+            }
+            std::sort(key.begin(), key.end());
+            for (int64_t e = 1; e < ne; ++e)
+                if (key[e] == key[e - 1]) throw ApiError{MWU_ERR_GRAPH, "duplicate edge"};
+            // compact the non-isolated vertices (empty rows never bind)
+            std::vector<int64_t> deg(nv, 0), id(nv, -1);
+            for (int64_t e = 0; e < ne; ++e) { deg[m.edge_u[e]]++; deg[m.edge_v[e]]++; }
+            int64_t kept = 0, maxdeg = 0;
+            for (int64_t v = 0; v < nv; ++v)
+                if (deg[v] > 0) { id[v] = kept++; maxdeg = std::max(maxdeg, deg[v]); }
+            if (V + kept >= INT32_MAX || 2 * (E + ne) >= INT32_MAX)
+                throw ApiError{MWU_ERR_TOO_LARGE, "batch exceeds 32-bit device indices"};
+            Inst &I = inst_[k];
+            I.v0 = V; I.nv = kept; I.e0 = E; I.ne = ne; I.user_v = nv;
+            nedge[k] = (int32_t)ne;
+            for (int64_t e = 0; e < ne; ++e) {
+                eu.push_back((int32_t)(V + id[m.edge_u[e]]));
+                ev.push_back((int32_t)(V + id[m.edge_v[e]]));
+            }
+            // incidence rows: for every vertex its edges (in edge order)
+            std::vector<int64_t> cnt(kept + 1, 0);
+            for (int64_t e = 0; e < ne; ++e) { cnt[id[m.edge_u[e]] + 1]++; cnt[id[m.edge_v[e]] + 1]++; }
+            for (int64_t v = 0; v < kept; ++v) cnt[v + 1] += cnt[v];
+            std::vector<int32_t> inc(2 * ne);
+            std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+            for (int64_t e = 0; e < ne; ++e) {
+                inc[fill[id[m.edge_u[e]]]++] = (int32_t)(E + e);
+                inc[fill[id[m.edge_v[e]]]++] = (int32_t)(E + e);
+            }
+            const int64_t base = vedge.size();
+            for (int64_t v = 0; v < kept; ++v) vptr.push_back((int32_t)(base + cnt[v + 1]));
+            vedge.insert(vedge.end(), inc.begin(), inc.end());
+            // tiles (never across instances)
+            vrec0[k] = (int32_t)vt.size();
+            for (int64_t i = 0; i < kept; i += kTileV)
+                vt.push_back(BTile{k, (int32_t)(V + i), (int32_t)(V + std::min<int64_t>(i + kTileV, kept)), 0});
+            vrecn[k] = (int32_t)vt.size() - vrec0[k];
+            erec0[k] = (int32_t)et.size();
+            for (int64_t i = 0; i < ne; i += kTileE)
+                et.push_back(BTile{k, (int32_t)(E + i), (int32_t)(E + std::min<int64_t>(i + kTileE, ne)), 0});
+            erecn[k] = (int32_t)et.size() - erec0[k];
+            // outer-search bracket (as for any packing LP with unit entries):
+            // hi = sum_i 1 / min_j P_ji = |E|; lo from the rescaled Algorithm 1 point
+            I.hi = (double)ne;
+            I.lo = (double)ne / (double)maxdeg;
+            I.x_start_scale = 1.0 / (double)maxdeg;   // x_start = 1/maxdeg on every edge
+            V += kept;
+            E += ne;
+        }
+        nv_ = V;
+        ne_ = E;
+        auto up = [&](DevBuf &b, const void *src, size_t bytes) {
+            b.alloc(std::max<size_t>(bytes, 8));
+            if (bytes) HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        up(eu_, eu.data(), eu.size() * 4);
+        up(ev_, ev.data(), ev.size() * 4);
+        up(vptr_, vptr.data(), vptr.size() * 4);
+        up(vedge_, vedge.data(), vedge.size() * 4);
+        up(vt_, vt.data(), vt.size() * sizeof(BTile));
+        up(et_, et.data(), et.size() * sizeof(BTile));
+        up(vrec0_, vrec0.data(), count * 4);
+        up(vrecn_, vrecn.data(), count * 4);
+        up(erec0_, erec0.data(), count * 4);
+        up(erecn_, erecn.data(), count * 4);
+        up(nedge_, nedge.data(), count * 4);
+        x_.alloc(E * sizeof(T));
+        d_.alloc(E * sizeof(T));
+        xbest_.alloc(E * sizeof(T));
+        y_.alloc(V * sizeof(T));
+        dy_.alloc(V * sizeof(T));
+        w_.alloc(V * sizeof(T));
+        vpart_.alloc(vt.size() * QMAX * 8);
+        epart_.alloc(et.size() * QMAX * 8);
+        ctl_.alloc((size_t)count * sizeof(Ctl));
+        stat_.alloc((size_t)count * 16);
+        HIP_OK(hipMemset(ctl_.p, 0, ctl_.bytes));
+        HIP_OK(hipMemset(stat_.p, 0, stat_.bytes));
+        HIP_OK(hipHostMalloc((void **)&ctl_host_, (size_t)count * sizeof(Ctl), hipHostMallocDefault));
+        HIP_OK(hipHostMalloc((void **)&stat_host_, (size_t)count * 16, hipHostMallocDefault));
+        std::memset(ctl_host_, 0, (size_t)count * sizeof(Ctl));
+        std::memset(stat_host_, 0, (size_t)count * 16);
+
+        bd_ = BatchDev<T>{};
+        bd_.nb = count; bd_.nv = (int32_t)V; bd_.ne = (int32_t)E;
+        bd_.vptr = vptr_.as<int32_t>(); bd_.vedge = vedge_.as<int32_t>();
+        bd_.eu = eu_.as<int32_t>(); bd_.ev = ev_.as<int32_t>();
+        bd_.x = x_.as<T>(); bd_.d = d_.as<T>();
+        bd_.y = y_.as<T>(); bd_.dy = dy_.as<T>(); bd_.w = w_.as<T>();
+        bd_.vt = vt_.as<BTile>(); bd_.et = et_.as<BTile>();
+        bd_.nvt = (int32_t)vt.size(); bd_.net = (int32_t)et.size();
+        bd_.vrec0 = vrec0_.as<int32_t>(); bd_.vrecn = vrecn_.as<int32_t>();
+        bd_.erec0 = erec0_.as<int32_t>(); bd_.erecn = erecn_.as<int32_t>();
+        bd_.nedge = nedge_.as<int32_t>();
+        bd_.ctl = ctl_.as<Ctl>();
+        bd_.stat = stat_.as<int32_t>();
+        bd_.vpart = vpart_.as<double>(); bd_.epart = epart_.as<double>();
+        int occ_v = 1, occ_e = 1;
+        batch_occupancy<T>(&occ_v, &occ_e);
+        auto grid = [&](int64_t tiles, int occ) {
+            return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, (int64_t)occ * s.num_cus, (int64_t)65535}));
+        };
+        L_.grid_v = grid(bd_.nvt, occ_v);
+        L_.grid_e = grid(bd_.net, occ_e);
+    }
+
+    ~BatchMatching() override
+    {
+        if (graph_) (void)hipGraphExecDestroy(graph_);
+        if (ctl_host_) (void)hipHostFree(ctl_host_);
+        if (stat_host_) (void)hipHostFree(stat_host_);
+    }
+
+    int32_t count() const override { return nb_; }
+    int64_t total_variables() const override { return ne_; }
+
+    void solve(double *x_out, double *obj_out, int64_t *iters_out, mwu_result_info *info) override
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        const double eps = s_.opt.eps;
+        for (int32_t k = 0; k < nb_; ++k) {
+            Inst &I = inst_[k];
+            I.slo = I.lo; I.shi = I.hi; I.eps_probe = eps; I.halvings = 0; I.probes = 0;
+            I.iters = I.passes = I.final_iters = 0;
+            I.done = false; I.have_best = false; I.failed = false; I.best_scale = 1.0;
+            I.max_violation = 0.0;
+            if (!next_probe(k)) I.done = true;
+        }
+        push_state();
+        ensure_graph();
+        int64_t launches = 0;
+        const int64_t cap = ((int64_t)s_.opt.max_probes * (s_.opt.max_iter + 8) * 4) / std::max(1, slots_) + 64;
+        std::vector<int32_t> finished;
+        std::vector<int32_t> last((size_t)nb_ * 4, -1);
+        int stalled = 0;
+        while (true) {
+            int active = 0;
+            for (const Inst &I : inst_) active += !I.done;
+            if (!active) break;
+            if (launches++ > cap) throw ApiError{MWU_ERR_DEVICE, "batched solve did not finish"};
+            HIP_OK(hipGraphLaunch(graph_, s_.stream));
+            HIP_OK(hipMemcpyAsync(stat_host_, stat_.p, (size_t)nb_ * 16, hipMemcpyDeviceToHost, s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            // every running instance advances its phase or iteration in a launch
+            if (std::equal(last.begin(), last.end(), stat_host_)) {
+                if (++stalled > 64) throw ApiError{MWU_ERR_DEVICE, "batched solve makes no progress"};
+            } else {
+                stalled = 0;
+                std::copy(stat_host_, stat_host_ + (size_t)nb_ * 4, last.begin());
+            }
+            finished.clear();
+            for (int32_t k = 0; k < nb_; ++k) {
+                const Inst &I = inst_[k];
+                if (I.done) continue;
+                if (stat_host_[4 * k] == PH_IDLE && stat_host_[4 * k + 3] == I.serial) finished.push_back(k);
+            }
+            if (finished.empty()) continue;
+            HIP_OK(hipMemcpyAsync(ctl_host_, ctl_.p, (size_t)nb_ * sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            for (int32_t k : finished) {
+                probe_outcome(k);
+                if (!inst_[k].done && !next_probe(k)) inst_[k].done = true;
+            }
+            // nothing runs between the pull above and this push (one stream), so
+            // the blocks of running instances go back unchanged
+            push_state();
+        }
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        // outputs
+        std::vector<T> xb;
+        if (x_out) {
+            xb.resize(ne_);
+            HIP_OK(hipMemcpy(xb.data(), xbest_.p, ne_ * sizeof(T), hipMemcpyDeviceToHost));
+        }
+        int64_t total = 0;
+        for (int32_t k = 0; k < nb_; ++k) {
+            const Inst &I = inst_[k];
+            total += I.iters;
+            const bool cert = !I.failed && I.hi <= (1.0 + eps) * I.lo;
+            if (x_out)
+                for (int64_t e = 0; e < I.ne; ++e)
+                    x_out[I.e0 + e] = I.have_best ? (double)xb[I.e0 + e] * I.best_scale : I.x_start_scale;
+            if (obj_out) obj_out[k] = I.lo;
+            if (info) {
+                mwu_result_info &r = info[k];
+                r.status = cert ? MWU_CERTIFIED : MWU_FEASIBLE_UNCERTIFIED;
+                r.objective = I.lo;
+                r.lower_bound = I.lo;
+                r.upper_bound = I.hi;
+                r.total_iterations = I.iters;
+                r.final_probe_iterations = I.final_iters;
+                r.search_passes = I.passes;
+                r.probes = I.probes;
+                r.max_violation = I.max_violation;
+                r.seconds_solve = secs;
+            }
+        }
+        if (iters_out) *iters_out = total;
+    }
+
+  private:
+    // Configure instance k's next probe in the host copy of its control block
+    // (phase PH_INIT); false when its search is over.
+    bool next_probe(int32_t k)
+    {
+        Inst &I = inst_[k];
+        const double eps = s_.opt.eps;
+        while (true) {
+            if (I.probes >= s_.opt.max_probes || I.hi <= (1.0 + eps) * I.lo) return false;
+            if (I.shi > (1.0 + eps / 16.0) * I.slo) break;
+            if (I.halvings == kMaxHalvingsB) return false;
+            ++I.halvings;
+            I.eps_probe *= 0.5;
+            I.slo = I.lo;
+            I.shi = I.hi;
+        }
+        I.param = std::sqrt(I.slo * I.shi);
+        Ctl &c = ctl_host_[k];
+        std::memset(&c, 0, sizeof(Ctl));
+        const int64_t m = I.nv + 1;                              // vertex rows + objective row
+        c.eta = 10.0 * std::log((double)m) / I.eps_probe;        // Algorithm 1, natural log
+        c.eps = I.eps_probe;
+        const double sfac = (s_.opt.flags & MWU_FLAG_NO_FACTOR2) ? 0.5 : 1.0;   // one covering row
+        c.step = sfac / c.eta;
+        c.sP = 1.0;
+        c.sC = 1.0 / I.param;
+        c.psi_lim = s_.fp32 ? 80.0 : 700.0;
+        c.s2_min = s_.fp32 ? 1e-25 : 1e-280;
+        c.qmin = s_.fp32 ? kMixedQminB : 0.0;
+        c.onesP = 0;
+        c.onesC = 1;
+        c.step_rule = s_.opt.step_rule;
+        c.max_iter = s_.opt.max_iter;
+        c.pack_bound = INFINITY;
+        c.cover_bound = 0.0;
+        c.trace = nullptr;
+        c.status = ST_RUNNING;
+        c.phase = PH_INIT;
+        ++I.serial;
+        stat_host_[4 * k + 0] = PH_INIT;      // pushed with the control blocks
+        stat_host_[4 * k + 3] = I.serial;
+        return true;
+    }
+
+    // Apply the finished probe of instance k to its brackets (the packing
+    // rules of the single-instance driver).
+    void probe_outcome(int32_t k)
+    {
+        Inst &I = inst_[k];
+        const Ctl &c = ctl_host_[k];
+        const double cf = s_.fp32 ? 1.0 - kMixedQminB : 1.0;
+        I.probes++;
+        I.iters += c.iter;
+        I.final_iters = c.iter;
+        I.passes += c.search_passes;
+        I.max_violation = std::max({0.0, c.ymax - 1.0, 1.0 - c.zmin});
+        if (c.status == ST_NUMERIC) { I.failed = true; I.done = true; return; }
+        if (c.pack_bound < I.hi) I.hi = c.pack_bound;
+        if (c.status == ST_FEASIBLE) {
+            const double val = c.sumx / c.ymax;
+            if (val > I.lo) {
+                I.lo = val;
+                HIP_OK(hipMemcpyAsync(xbest_.as<T>() + I.e0, x_.as<T>() + I.e0, I.ne * sizeof(T),
+                                      hipMemcpyDeviceToDevice, s_.stream));
+                I.have_best = true;
+                I.best_scale = 1.0 / c.ymax;
+            }
+            I.slo = I.param;
+        } else {
+            if (c.status == ST_INFEASIBLE) I.hi = std::min(I.hi, I.param / cf);
+            I.shi = I.param;
+        }
+        I.slo = std::max(I.slo, I.lo);
+        I.shi = std::min(I.shi, I.hi);
+    }
+
+    void push_state()
+    {
+        HIP_OK(hipMemcpyAsync(ctl_.p, ctl_host_, (size_t)nb_ * sizeof(Ctl), hipMemcpyHostToDevice, s_.stream));
+        HIP_OK(hipMemcpyAsync(stat_.p, stat_host_, (size_t)nb_ * 16, hipMemcpyHostToDevice, s_.stream));
+    }
+
+    void ensure_graph()
+    {
+        if (graph_) return;
+        hipGraph_t g;
+        HIP_OK(hipStreamBeginCapture(s_.stream, hipStreamCaptureModeThreadLocal));
+        batch_slots<T>(bd_, L_, slots_, s_.stream);
+        HIP_OK(hipStreamEndCapture(s_.stream, &g));
+        HIP_OK(hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+    }
+
+    Solver &s_;
+    int32_t nb_ = 0;
+    int64_t nv_ = 0, ne_ = 0;
+    int slots_ = 8;
+    std::vector<Inst> inst_;
+    BatchDev<T> bd_{};
+    BLaunch L_{};
+    Ctl *ctl_host_ = nullptr;
+    int32_t *stat_host_ = nullptr;
+    hipGraphExec_t graph_ = nullptr;
+    DevBuf eu_, ev_, vptr_, vedge_, vt_, et_, vrec0_, vrecn_, erec0_, erecn_, nedge_;
+    DevBuf x_, d_, xbest_, y_, dy_, w_, vpart_, epart_, ctl_, stat_;
+};
+
+std::unique_ptr<BatchProgram> make_batch_matching(Solver &s, const mwu_problem *probs, int32_t count)
+{
+    if (s.fp32) return std::unique_ptr<BatchProgram>(new BatchMatching<float>(s, probs, count));
+    return std::unique_ptr<BatchProgram>(new BatchMatching<double>(s, probs, count));
+}
+
+}  // namespace mwu

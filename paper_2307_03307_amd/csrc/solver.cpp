@@ -24,6 +24,7 @@ Solver::~Solver()
 {
     if (graph) (void)hipGraphExecDestroy(graph);
     prog.reset();
+    batch.reset();
     if (ctl_host) (void)hipHostFree(ctl_host);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
@@ -681,9 +682,31 @@ mwu_status mwu_create(const mwu_problem *prob, const mwu_options *opt, void **ou
 
 mwu_status mwu_create_batch(const mwu_problem *probs, int32_t count, const mwu_options *opt, void **out)
 {
-    (void)probs; (void)count; (void)opt;
-    if (out) *out = nullptr;
-    return MWU_ERR_STATE;
+    if (!out) return MWU_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!probs || count < 1) return MWU_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < count; ++k)   // the batched program solves matching LPs
+        if (probs[k].form != MWU_PACKING || probs[k].P.kind != MWU_MAT_INCIDENCE || probs[k].b_P || probs[k].c)
+            return MWU_ERR_INVALID_ARG;
+    Solver *s = new (std::nothrow) Solver();
+    if (!s) return MWU_ERR_OOM;
+    if (opt) s->opt = *opt; else fill_defaults(&s->opt);
+    mwu_status st = run_guarded([&] {
+        check(s->opt.eps > 0.0 && s->opt.eps < 1.0, MWU_ERR_INVALID_ARG, "eps must be in (0,1)");
+        check(s->opt.max_iter >= 1 && s->opt.max_probes >= 1, MWU_ERR_INVALID_ARG, "bad iteration caps");
+        check(s->opt.step_rule == MWU_STEP_STD || s->opt.step_rule == MWU_STEP_BIN, MWU_ERR_INVALID_ARG,
+              "bad step rule");
+        check(s->opt.precision == MWU_FP64 || s->opt.precision == MWU_MIXED_FP32_FP64, MWU_ERR_INVALID_ARG,
+              "bad precision");
+        s->fp32 = s->opt.precision == MWU_MIXED_FP32_FP64;
+        s->form = MWU_PACKING;
+        setup_device(*s);
+        s->batch = make_batch_matching(*s, probs, count);
+        s->n_user = s->batch->total_variables();
+    });
+    if (st != MWU_OK) { delete s; return st; }
+    *out = s;
+    return MWU_OK;
 }
 
 void mwu_destroy(void *h)
@@ -701,6 +724,12 @@ mwu_status mwu_solve(void *h, double *x_out, double *objective_out, int64_t *ite
 {
     if (!h) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) {
+        return run_guarded([&] {
+            HIP_OK(hipSetDevice(s.opt.device));
+            s.batch->solve(x_out, objective_out, iterations_out, info);
+        });
+    }
     return run_guarded([&] {
         HIP_OK(hipSetDevice(s.opt.device));
         const auto t0 = std::chrono::steady_clock::now();
@@ -738,6 +767,7 @@ mwu_status mwu_probe_sizes(void *h, mwu_sizes *out)
 {
     if (!h || !out) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     out->n = s.prog->n();
     out->m_P = s.prog->mP();
     out->m_C = s.prog->mC();
@@ -749,6 +779,7 @@ mwu_status mwu_probe_begin(void *h, double param, const double *x0)
 {
     if (!h || !(param > 0.0)) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     return run_guarded([&] {
         HIP_OK(hipSetDevice(s.opt.device));
         s.prog->set_forced(nullptr, 0);
@@ -775,6 +806,7 @@ mwu_status mwu_probe_run(void *h, int32_t max_iters, const double *forced_alpha,
 {
     if (!h || max_iters < 0 || n_forced < 0) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         HIP_OK(hipSetDevice(s.opt.device));
@@ -799,6 +831,7 @@ mwu_status mwu_probe_direction(void *h)
 {
     if (!h) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         pull_ctl(s);
@@ -821,6 +854,7 @@ mwu_status mwu_probe_read(void *h, int32_t which, double *out, int64_t len)
 {
     if (!h || !out) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     return run_guarded([&] {
         if (which == 8) {   // accepted steps of the current probe
             pull_ctl(s);
@@ -840,6 +874,7 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
 {
     if (!h || !alphas || count < 1 || count > KC || !psi || !phi) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         pull_ctl(s);
@@ -885,6 +920,7 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
 {
     if (!h || which < 0 || which > 4 || reps < 1 || !avg_us) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         HIP_OK(hipSetDevice(s.opt.device));
@@ -945,6 +981,7 @@ mwu_status mwu_potential_forward(void *h, const double *x_dev, double *value_out
 {
     if (!h || !x_dev || !value_out) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         hipStream_t st = stream ? (hipStream_t)stream : s.stream;
@@ -965,6 +1002,7 @@ mwu_status mwu_potential_backward(void *h, const double *x_dev, double grad_scal
 {
     if (!h || !x_dev || !grad_dev) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         hipStream_t st = stream ? (hipStream_t)stream : s.stream;

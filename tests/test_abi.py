@@ -86,3 +86,32 @@ def test_valid_problem_without_gpu_fails_loudly():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _code(lambda: mwu.bmatch(4, [0, 1], [2, 3])) == -8
+
+
+def test_create_batch_rejects_unsupported_problems():
+    """The batched program solves matching LPs only; anything else, an empty
+    batch or a NULL output handle is rejected before device work."""
+    L = _lib.load()
+    u = np.array([0, 1], np.int32)
+    v = np.array([2, 3], np.int32)
+    inc = mwu.incidence(4, u, v)
+    empty = mwu._Mat(_lib.MAT_CSR)
+    ok = _lib.Problem(_lib.PACKING, inc.c(), empty.c(), None, None, None)
+    cov = _lib.Problem(_lib.COVERING, empty.c(), mwu.incidence_t(4, u, v).c(), None, None, None)
+    h = ctypes.c_void_p()
+    arr = (_lib.Problem * 2)(ok, cov)
+    assert L.mwu_create_batch(arr, 2, None, ctypes.byref(h)) == -1
+    assert L.mwu_create_batch(arr, 0, None, ctypes.byref(h)) == -1
+    assert L.mwu_create_batch(arr, 1, None, None) == -1
+    # a valid batch on a machine without a GPU: device error, no handle
+    if not _has_gpu():
+        assert L.mwu_create_batch(arr, 1, None, ctypes.byref(h)) == -8
+        assert not h.value
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False

@@ -1,0 +1,76 @@
+"""Batched execution (many uneven matching LPs in the same kernels): every
+instance is checked on its own against facts that do not come from the
+library -- the exact LP optimum (maximum matching size by Hopcroft-Karp, for
+bipartite graphs the matching LP is integral, Section 3), feasibility of the
+returned x and the (1 + eps) bracket -- and against the single-instance
+solver on the same graph."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import maximum_bipartite_matching
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+EPS = 0.1
+
+
+def _nu(g):
+    nl = g.n_left
+    A = sp.csr_matrix((np.ones(g.num_edges), (g.u, g.v - nl)), shape=(nl, g.num_vertices - nl))
+    return int((maximum_bipartite_matching(A, perm_type="column") >= 0).sum())
+
+
+def _instances():
+    gs = gg.batch_bipartite(14, scale_div=64)            # sides 16 .. 1024, uneven
+    gs.append(gg.complete_bipartite(3, 5))                # OPT = 3
+    gs.append(gg.complete_bipartite(1, 6))                # star: OPT = 1
+    gs.append(gg.Graph(2, np.array([0], np.int32), np.array([1], np.int32), n_left=1))   # one edge
+    gs.append(gg.bipartite_uniform(300, 40, 900, seed=9))  # lopsided
+    return gs
+
+
+def _check(g, r, nu):
+    assert r.certified, (r.lower, r.upper)
+    assert r.lower - 1e-9 * nu <= nu <= r.upper * (1 + 1e-12)
+    assert r.objective * (1 + EPS) >= nu * (1 - 1e-12)
+    load = np.bincount(g.u, weights=r.x, minlength=g.num_vertices) + \
+        np.bincount(g.v, weights=r.x, minlength=g.num_vertices)
+    assert load.max() <= 1.0 + 1e-9 and r.x.min() >= 0.0
+    assert abs(r.x.sum() - r.objective) <= 1e-9 * max(1.0, r.objective)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_exact_optimum(precision):
+    import paper_2307_03307_amd as mwu
+    gs = _instances()
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs], precision=precision) as b:
+        res = b.solve()
+    assert len(res) == len(gs)
+    for g, r in zip(gs, res):
+        _check(g, r, _nu(g))
+
+
+def test_batch_agrees_with_single_instance_solver():
+    import paper_2307_03307_amd as mwu
+    gs = _instances()[:6]
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs], precision=0) as b:
+        res = b.solve()
+    for g, r in zip(gs, res):
+        with mwu.bmatch(g.num_vertices, g.u, g.v, precision=0) as s:
+            r1 = s.solve()
+        assert r1.certified and r.certified
+        # both are certified (1 + eps) answers of the same LP
+        assert max(r.objective, r1.objective) <= (1 + EPS) * min(r.objective, r1.objective)
+        assert max(r.lower, r1.lower) <= min(r.upper, r1.upper) * (1 + 1e-12)
+
+
+def test_batch_medium_uneven():
+    """64 instances, sides 128 .. 8192, mean degree 4 .. 16, mixed form."""
+    import paper_2307_03307_amd as mwu
+    gs = gg.batch_bipartite(64, scale_div=8)
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs]) as b:
+        res = b.solve()
+    for g, r in zip(gs, res):
+        _check(g, r, _nu(g))
