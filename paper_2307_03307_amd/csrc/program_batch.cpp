@@ -21,6 +21,7 @@ constexpr int kMaxHalvingsB = 2;
 struct Inst {
     int64_t v0 = 0, nv = 0, e0 = 0, ne = 0;   // ranges in the concatenated arrays
     int64_t user_v = 0;                       // vertices as given (before dropping isolated ones)
+    double lo0 = 0, hi0 = 0;                  // starting bracket
     double lo = 0, hi = 0, slo = 0, shi = 0, eps_probe = 0, param = 0;
     int halvings = 0, probes = 0, serial = 0;
     int64_t iters = 0, passes = 0, final_iters = 0;
@@ -100,8 +101,8 @@ class BatchMatching : public BatchProgram {
             erecn[k] = (int32_t)et.size() - erec0[k];
             // outer-search bracket (as for any packing LP with unit entries):
             // hi = sum_i 1 / min_j P_ji = |E|; lo from the rescaled Algorithm 1 point
-            I.hi = (double)ne;
-            I.lo = (double)ne / (double)maxdeg;
+            I.hi0 = (double)ne;
+            I.lo0 = (double)ne / (double)maxdeg;
             I.x_start_scale = 1.0 / (double)maxdeg;   // x_start = 1/maxdeg on every edge
             V += kept;
             E += ne;
@@ -179,6 +180,7 @@ class BatchMatching : public BatchProgram {
         const double eps = s_.opt.eps;
         for (int32_t k = 0; k < nb_; ++k) {
             Inst &I = inst_[k];
+            I.lo = I.lo0; I.hi = I.hi0;
             I.slo = I.lo; I.shi = I.hi; I.eps_probe = eps; I.halvings = 0; I.probes = 0;
             I.iters = I.passes = I.final_iters = 0;
             I.done = false; I.have_best = false; I.failed = false; I.best_scale = 1.0;

@@ -74,3 +74,17 @@ def test_batch_medium_uneven():
         res = b.solve()
     for g, r in zip(gs, res):
         _check(g, r, _nu(g))
+
+
+def test_batch_solve_twice_is_identical():
+    """A second solve on the same handle starts again from the initial brackets
+    and reproduces the first bit for bit (fixed-order reductions)."""
+    import paper_2307_03307_amd as mwu
+    gs = _instances()[:5]
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs]) as b:
+        r1 = b.solve()
+        r2 = b.solve()
+    for a, c in zip(r1, r2):
+        assert a.total_iterations == c.total_iterations > 0
+        assert a.objective == c.objective and a.lower == c.lower and a.upper == c.upper
+        assert np.array_equal(a.x, c.x)
