@@ -26,6 +26,43 @@ MWU_DEV void write_stat(const BatchDev<T> &b, int k)
     b.stat[4 * k + 2] = c->iter;
 }
 
+// Visit this workgroup's tiles (t = blockIdx.x + j gridDim.x, ascending)
+// whose instance is in one of two phases.  The phases of up to BLOCK tiles are
+// read in parallel from the compact status array and the matching tiles are
+// compacted through LDS in ascending order (wave ballots, no atomics), so a
+// pass that most instances sit out costs one parallel read per BLOCK tiles
+// instead of one dependent read per tile.  body(t) runs with the whole
+// workgroup.
+template <class T, class Body>
+MWU_DEV void for_phase_tiles(const BatchDev<T> &b, const BTile *tiles, int ntiles, int ph1, int ph2,
+                             Body &body)
+{
+    __shared__ int32_t s_list[BLOCK];
+    __shared__ int32_t s_cnt[BLOCK / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int G = gridDim.x;
+    for (int base = blockIdx.x; base < ntiles; base += G * BLOCK) {
+        const int t = base + threadIdx.x * G;
+        bool hit = false;
+        if (t < ntiles) {
+            const int ph = b.stat[4 * tiles[t].inst];
+            hit = ph == ph1 || ph == ph2;
+        }
+        const unsigned long long m = __ballot(hit);
+        if (lane == 0) s_cnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = 0, total = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            if (w < wv) off += s_cnt[w];
+            total += s_cnt[w];
+        }
+        if (hit) s_list[off + __popcll(m & ((1ull << lane) - 1ull))] = t;
+        __syncthreads();
+        for (int i = 0; i < total; ++i) body(s_list[i]);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ probe start
 
 template <class T>
@@ -33,10 +70,9 @@ __global__ __launch_bounds__(BLOCK) void kb_initx(BatchDev<T> b)
 {
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.net; t += gridDim.x) {
+    auto body = [&](int t) {
         const BTile tl = b.et[t];
         const Ctl *c = b.ctl + tl.inst;
-        if (c->phase != PH_INIT) continue;
         // Algorithm 1: x_i = eps / (n max_j P_ji) with P_ji = 1 on incident rows
         const T x0 = (T)(c->eps / (double)b.nedge[tl.inst]);
         double v[1] = {0.0};
@@ -48,7 +84,8 @@ __global__ __launch_bounds__(BLOCK) void kb_initx(BatchDev<T> b)
         const Red red{1, 0, 0};
         block_combine<1>(v, red, 0, s_wave, s_rec);
         if (threadIdx.x == 0) b.epart[(size_t)t * QMAX] = s_rec[0];
-    }
+    };
+    for_phase_tiles(b, b.et, b.net, PH_INIT, PH_INIT, body);
 }
 
 template <class T>
@@ -68,34 +105,49 @@ __global__ __launch_bounds__(BLOCK) void kb_initx_fin(BatchDev<T> b)
     }
 }
 
-// Vertex sums over incident edges: INIT_Y gives y = P x0 (and clears dy),
-// FWD gives dy = P d.  Record [min over covering rows (none) | max over rows].
+// Tile of vertex tiles as a plain segment tile.
+MWU_DEV Tile as_tile(const BTile &b)
+{
+    Tile t;
+    t.s0 = b.i0; t.s1 = b.i1; t.k0 = b.k0; t.k1 = b.k1; t.lid = b.lid; t.cidx = b.cidx;
+    return t;
+}
+
+// Vertex sums over incident edges, nnz-balanced: INIT_Y gives y = P x0 (and
+// clears dy), FWD gives dy = P d.  Incidence indices are staged through LDS
+// with coalesced loads; vertices longer than a tile are summed in chunks and
+// completed by the finisher.  Record [min over covering rows (none) | max].
 template <class T>
 __global__ __launch_bounds__(BLOCK) void kb_vfwd(BatchDev<T> b)
 {
+    __shared__ T s_acc[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ T s_tacc[BLOCK / 64];
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
-        const BTile tl = b.vt[t];
-        const Ctl *c = b.ctl + tl.inst;
+    auto body = [&](int t) {
+        const BTile bt = b.vt[t];
+        const Ctl *c = b.ctl + bt.inst;
         const int ph = c->phase;
-        if (ph != PH_INIT_Y && ph != PH_FWD) continue;
         const bool init = ph == PH_INIT_Y;
         const T *src = init ? b.x : b.d;
         const T sP = (T)c->sP;
         double v[2] = {INFINITY, -INFINITY};
-        for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
-            T acc = T(0);
-            for (int q = b.vptr[i]; q < b.vptr[i + 1]; ++q) acc += src[b.vedge[q]];
+        auto elem = [&](int k) -> T { return src[b.vedge[k]]; };
+        auto epi = [&](int i, T acc) {
             acc = sP * acc;
             if (init) { b.y[i] = acc; b.dy[i] = T(0); }
             else b.dy[i] = acc;
             v[1] = fmax(v[1], (double)acc);
-        }
+        };
+        const Tile tl = as_tile(bt);
+        if (tl.lid < 0) seg_tile<T>(tl, b.vptr, elem, epi, s_acc, s_ptr, nullptr, nullptr);
+        else chunk_tile<T>(tl, elem, s_tacc, b.lpart, b.vlong.lfirst);
         const Red red{0, 1, 1};
         block_combine<2>(v, red, 0, s_wave, s_rec);
         if (threadIdx.x < 2) b.vpart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
-    }
+    };
+    for_phase_tiles(b, b.vt, b.nvt, PH_INIT_Y, PH_FWD, body);
 }
 
 template <class T>
@@ -103,14 +155,27 @@ __global__ __launch_bounds__(BLOCK) void kb_vfwd_fin(BatchDev<T> b)
 {
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
+    __shared__ double s_lng[QMAX];
     const int k = blockIdx.x;
     Ctl *c = b.ctl + k;
     const int ph = c->phase;
     if (ph != PH_INIT_Y && ph != PH_FWD) return;
+    const bool init = ph == PH_INIT_Y;
+    const T sP = (T)c->sP;
     const Red red{0, 1, 1};
+    double v[2] = {INFINITY, -INFINITY};
+    for (int l = b.lrec0[k] + threadIdx.x; l < b.lrec0[k] + b.lrecn[k]; l += BLOCK) {
+        const T acc = sP * long_sum<T>(l, b.lpart, b.vlong.lfirst, b.vlong.lcount);
+        const int i = b.vlong.lseg[l];
+        if (init) { b.y[i] = acc; b.dy[i] = T(0); }
+        else b.dy[i] = acc;
+        v[1] = fmax(v[1], (double)acc);
+    }
+    block_combine<2>(v, red, 0, s_wave, s_lng);
     fold_records<2>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], red, 0, s_wave, s_rec);
     if (threadIdx.x == 0) {
-        if (ph == PH_INIT_Y) {
+        for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
+        if (init) {
             finish_init_fwd(c, s_rec);
         } else {
             c->dymax = s_rec[1];
@@ -128,10 +193,9 @@ __global__ __launch_bounds__(BLOCK) void kb_row(BatchDev<T> b)
 {
     __shared__ double s_wave[4 * 4];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
-        const BTile tl = b.vt[t];
+    auto body = [&](int t) {
+        const BTile tl = b.wt[t];
         const Ctl *c = b.ctl + tl.inst;
-        if (c->phase != PH_ROW) continue;
         const T a = (T)c->alpha;
         const double eta = c->eta, LP = c->LP;
         double v[4] = {0.0, 0.0, INFINITY, -INFINITY};
@@ -145,8 +209,9 @@ __global__ __launch_bounds__(BLOCK) void kb_row(BatchDev<T> b)
         }
         const Red red{2, 1, 1};
         block_combine<4>(v, red, 0, s_wave, s_rec);
-        if (threadIdx.x < 4) b.vpart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
-    }
+        if (threadIdx.x < 4) b.wpart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
+    };
+    for_phase_tiles(b, b.wt, b.nwt, PH_ROW, PH_ROW, body);
 }
 
 template <class T>
@@ -158,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void kb_row_fin(BatchDev<T> b)
     Ctl *c = b.ctl + k;
     if (c->phase != PH_ROW) return;
     const Red red{2, 1, 1};
-    fold_records<4>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], red, 0, s_wave, s_rec);
+    fold_records<4>(b.wpart + (size_t)b.wrec0[k] * QMAX, b.wrecn[k], red, 0, s_wave, s_rec);
     if (threadIdx.x == 0) {
         finish_row(c, s_rec);
         write_stat(b, k);
@@ -173,15 +238,14 @@ __global__ __launch_bounds__(BLOCK) void kb_col(BatchDev<T> b)
 {
     __shared__ double s_wave[4 * 4];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.net; t += gridDim.x) {
+    auto body = [&](int t) {
         const BTile tl = b.et[t];
         const Ctl *c = b.ctl + tl.inst;
         const int ph = c->phase;
-        if (ph != PH_COL && ph != PH_COMMIT) continue;
         const T a = (T)c->alpha;
         if (ph == PH_COMMIT) {
             for (int e = tl.i0 + threadIdx.x; e < tl.i1; e += BLOCK) b.x[e] = b.x[e] + a * b.d[e];
-            continue;
+            return;
         }
         const double sP = c->sP, sC = c->sC, invSw = c->invSw, step = c->step, qmin = c->qmin;
         double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
@@ -203,7 +267,8 @@ __global__ __launch_bounds__(BLOCK) void kb_col(BatchDev<T> b)
         const Red red{1, 1, 2};
         block_combine<4>(v, red, 0, s_wave, s_rec);
         if (threadIdx.x < 4) b.epart[(size_t)t * QMAX + threadIdx.x] = s_rec[threadIdx.x];
-    }
+    };
+    for_phase_tiles(b, b.et, b.net, PH_COL, PH_COMMIT, body);
 }
 
 template <class T>
@@ -277,18 +342,18 @@ __global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
 {
     __shared__ double s_wave[4 * KC];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
-        const BTile tl = b.vt[t];
+    auto body = [&](int t) {
+        const BTile tl = b.wt[t];
         const Ctl *c = b.ctl + tl.inst;
-        if (c->phase != PH_SEARCH) continue;
-        double *rec = b.vpart + (size_t)t * QMAX;
+        double *rec = b.wpart + (size_t)t * QMAX;
         if (c->skind == SK_REFINE) {
             const double a = c->ref_alpha, eta = c->eta;
             double v[2];
+            const int i1 = tl.i1;
             if (c->ref_valid == 0) {          // pass 1: [min z' (no covering rows) | max eta y']
                 v[0] = INFINITY;
                 v[1] = -INFINITY;
-                for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
+                for (int i = tl.i0 + threadIdx.x; i < i1; i += BLOCK)
                     v[1] = fmax(v[1], eta * ((double)b.y[i] + a * (double)b.dy[i]));
                 const Red red{0, 1, 1};
                 block_combine<2>(v, red, 0, s_wave, s_rec);
@@ -296,13 +361,13 @@ __global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
                 const double pm = c->rfPm;
                 v[0] = 0.0;
                 v[1] = 0.0;
-                for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
+                for (int i = tl.i0 + threadIdx.x; i < i1; i += BLOCK)
                     v[0] += exp(eta * ((double)b.y[i] + a * (double)b.dy[i]) - pm);
                 const Red red{2, 0, 0};
                 block_combine<2>(v, red, 0, s_wave, s_rec);
             }
             if (threadIdx.x < 2) rec[threadIdx.x] = s_rec[threadIdx.x];
-            continue;
+            return;
         }
         switch (c->skind) {
         case SK_EXP: kb_search_rows<T, SK_EXP>(b, tl, c, s_wave, s_rec); break;
@@ -310,7 +375,8 @@ __global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
         default: kb_search_rows<T, SK_LIST>(b, tl, c, s_wave, s_rec); break;
         }
         if (threadIdx.x < KC) rec[threadIdx.x] = s_rec[threadIdx.x];
-    }
+    };
+    for_phase_tiles(b, b.wt, b.nwt, PH_SEARCH, PH_SEARCH, body);
 }
 
 template <class T>
@@ -321,8 +387,8 @@ __global__ __launch_bounds__(BLOCK) void kb_search_fin(BatchDev<T> b)
     const int k = blockIdx.x;
     Ctl *c = b.ctl + k;
     if (c->phase != PH_SEARCH) return;
-    const double *part = b.vpart + (size_t)b.vrec0[k] * QMAX;
-    const int G = b.vrecn[k];
+    const double *part = b.wpart + (size_t)b.wrec0[k] * QMAX;
+    const int G = b.wrecn[k];
     if (c->skind == SK_REFINE) {
         const Red red = c->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
         fold_records<2>(part, G, red, 0, s_wave, s_rec);
@@ -348,21 +414,24 @@ __global__ __launch_bounds__(BLOCK) void kb_search_fin(BatchDev<T> b)
 template <class T>
 __global__ __launch_bounds__(BLOCK) void kb_stats_v(BatchDev<T> b)
 {
+    __shared__ double s_acc[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ double s_tacc[BLOCK / 64];
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.nvt; t += gridDim.x) {
-        const BTile tl = b.vt[t];
-        if (b.ctl[tl.inst].phase != PH_STATS) continue;
+    auto body = [&](int t) {
+        const BTile bt = b.vt[t];
         double v[1] = {-INFINITY};
-        for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
-            double acc = 0.0;
-            for (int q = b.vptr[i]; q < b.vptr[i + 1]; ++q) acc += (double)b.x[b.vedge[q]];
-            v[0] = fmax(v[0], acc);
-        }
+        auto elem = [&](int k) -> double { return (double)b.x[b.vedge[k]]; };
+        auto epi = [&](int, double acc) { v[0] = fmax(v[0], acc); };
+        const Tile tl = as_tile(bt);
+        if (tl.lid < 0) seg_tile<double>(tl, b.vptr, elem, epi, s_acc, s_ptr, nullptr, nullptr);
+        else chunk_tile<double>(tl, elem, s_tacc, b.lpart64, b.vlong.lfirst);
         const Red red{0, 0, 1};
         block_combine<1>(v, red, 0, s_wave, s_rec);
         if (threadIdx.x == 0) b.vpart[(size_t)t * QMAX] = s_rec[0];
-    }
+    };
+    for_phase_tiles(b, b.vt, b.nvt, PH_STATS, PH_STATS, body);
 }
 
 template <class T>
@@ -370,15 +439,15 @@ __global__ __launch_bounds__(BLOCK) void kb_stats_e(BatchDev<T> b)
 {
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
-    for (int t = blockIdx.x; t < b.net; t += gridDim.x) {
+    auto body = [&](int t) {
         const BTile tl = b.et[t];
-        if (b.ctl[tl.inst].phase != PH_STATS) continue;
         double v[1] = {0.0};
         for (int e = tl.i0 + threadIdx.x; e < tl.i1; e += BLOCK) v[0] += (double)b.x[e];
         const Red red{1, 0, 0};
         block_combine<1>(v, red, 0, s_wave, s_rec);
         if (threadIdx.x == 0) b.epart[(size_t)t * QMAX] = s_rec[0];
-    }
+    };
+    for_phase_tiles(b, b.et, b.net, PH_STATS, PH_STATS, body);
 }
 
 template <class T>
@@ -391,11 +460,17 @@ __global__ __launch_bounds__(BLOCK) void kb_stats_fin(BatchDev<T> b)
     Ctl *c = b.ctl + k;
     if (c->phase != PH_STATS) return;
     const Red rmax{0, 0, 1}, rsum{1, 0, 0};
+    double lv[1] = {-INFINITY};
+    for (int l = b.lrec0[k] + threadIdx.x; l < b.lrec0[k] + b.lrecn[k]; l += BLOCK)
+        lv[0] = fmax(lv[0], long_sum<double>(l, b.lpart64, b.vlong.lfirst, b.vlong.lcount));
+    block_combine<1>(lv, rmax, 0, s_wave, s_rec2);
+    const double lmax = s_rec2[0];
+    __syncthreads();
     fold_records<1>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], rmax, 0, s_wave, s_rec);
     fold_records<1>(b.epart + (size_t)b.erec0[k] * QMAX, b.erecn[k], rsum, 0, s_wave, s_rec2);
     if (threadIdx.x == 0) {
         c->sumx = s_rec2[0];
-        c->ymax = c->sP * s_rec[0];
+        c->ymax = c->sP * fmax(s_rec[0], lmax);
         c->zmin = c->sC * s_rec2[0];
         c->phase = PH_IDLE;
         write_stat(b, k);
@@ -414,15 +489,15 @@ void batch_slots(const BatchDev<T> &b, const BLaunch &L, int slots, hipStream_t 
         BLAUNCH(kb_initx_fin<T>, b.nb);
         BLAUNCH(kb_vfwd<T>, L.grid_v);       // INIT_Y instances
         BLAUNCH(kb_vfwd_fin<T>, b.nb);
-        BLAUNCH(kb_row<T>, L.grid_v);
+        BLAUNCH(kb_row<T>, L.grid_w);
         BLAUNCH(kb_row_fin<T>, b.nb);
         BLAUNCH(kb_col<T>, L.grid_e);
         BLAUNCH(kb_col_fin<T>, b.nb);
         BLAUNCH(kb_vfwd<T>, L.grid_v);       // FWD instances
         BLAUNCH(kb_vfwd_fin<T>, b.nb);
-        BLAUNCH(kb_search<T>, L.grid_v);
+        BLAUNCH(kb_search<T>, L.grid_w);
         BLAUNCH(kb_search_fin<T>, b.nb);
-        BLAUNCH(kb_search<T>, L.grid_v);
+        BLAUNCH(kb_search<T>, L.grid_w);
         BLAUNCH(kb_search_fin<T>, b.nb);
         BLAUNCH(kb_stats_v<T>, L.grid_v);
         BLAUNCH(kb_stats_e<T>, L.grid_e);
@@ -434,7 +509,7 @@ template <class T>
 void batch_occupancy(int *per_cu_v, int *per_cu_e)
 {
     int a = 0, c = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_search<T>, BLOCK, 0) != hipSuccess) a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kb_vfwd<T>, BLOCK, 0) != hipSuccess) a = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, kb_col<T>, BLOCK, 0) != hipSuccess) c = 0;
     *per_cu_v = a > 0 ? a : 1;
     *per_cu_e = c > 0 ? c : 1;

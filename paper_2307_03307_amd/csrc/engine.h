@@ -159,7 +159,10 @@ struct VcDev {
 // never cross instances; every tile of a pass writes one record, and the
 // finisher of instance k folds its contiguous range of tile records.
 struct BTile {
-    int32_t inst, i0, i1, pad;
+    int32_t inst, i0, i1;   // instance; item range (vertices or edges)
+    int32_t k0, k1;         // vertex tiles: incidence nonzeros [k0, k1) (nnz-balanced)
+    int32_t lid, cidx;      // vertex tiles: chunk cidx of long vertex lid (lid < 0: whole vertices)
+    int32_t pad;
 };
 
 template <class T>
@@ -172,15 +175,23 @@ struct BatchDev {
     const BTile *vt, *et;                 // vertex tiles, edge tiles (grouped by instance)
     int32_t nvt, net;
     const int32_t *vrec0, *vrecn;         // per instance: first vertex tile, count
+    const BTile *wt;                      // element tiles over vertices (row and search passes)
+    int32_t nwt;
+    const int32_t *wrec0, *wrecn;         // per instance: first element tile, count
+    double *wpart;                        // one record per element tile
     const int32_t *erec0, *erecn;         // per instance: first edge tile, count
     const int32_t *nedge;                 // per instance: number of edges (variables)
+    LongSegs vlong;                       // vertices longer than one tile (global long ids)
+    const int32_t *lrec0, *lrecn;         // per instance: first long vertex, count
+    T *lpart;                             // chunk partials (storage type)
+    double *lpart64;                      // chunk partials of the FP64 statistics
     Ctl *ctl;                             // one control block per instance
     int32_t *stat;                        // per instance: phase, status, iter, serial
     double *vpart, *epart;                // one record (QMAX doubles) per tile
 };
 
 struct BLaunch {
-    int grid_v, grid_e;                   // persistent grids over vertex / edge tiles
+    int grid_v, grid_e, grid_w;           // persistent grids over vertex / edge / element tiles
 };
 
 template <class T> void batch_slots(const BatchDev<T> &b, const BLaunch &L, int slots, hipStream_t st);

@@ -13,8 +13,8 @@ namespace mwu {
 
 namespace {
 
-constexpr int kTileV = BLOCK * 4;    // vertices per vertex tile
 constexpr int kTileE = BLOCK * 8;    // edges per edge tile
+constexpr int kTileW = BLOCK * 16;   // vertices per element tile (row and search passes)
 constexpr double kMixedQminB = 1.0 / 65536.0;
 constexpr int kMaxHalvingsB = 2;
 
@@ -41,6 +41,9 @@ class BatchMatching : public BatchProgram {
         std::vector<int32_t> eu, ev, vptr(1, 0), vedge;
         std::vector<BTile> vt, et;
         std::vector<int32_t> vrec0(count), vrecn(count), erec0(count), erecn(count), nedge(count);
+        std::vector<int32_t> lrec0(count), lrecn(count), lseg, lfirst, lcount, wrec0(count), wrecn(count);
+        std::vector<BTile> wt;
+        int32_t nslots = 0;
         int64_t V = 0, E = 0;
         for (int32_t k = 0; k < count; ++k) {
             const mwu_problem &p = probs[k];
@@ -78,7 +81,7 @@ class BatchMatching : public BatchProgram {
                 ev.push_back((int32_t)(V + id[m.edge_v[e]]));
             }
             // incidence rows: for every vertex its edges (in edge order)
-            std::vector<int64_t> cnt(kept + 1, 0);
+            std::vector<int32_t> cnt(kept + 1, 0);
             for (int64_t e = 0; e < ne; ++e) { cnt[id[m.edge_u[e]] + 1]++; cnt[id[m.edge_v[e]] + 1]++; }
             for (int64_t v = 0; v < kept; ++v) cnt[v + 1] += cnt[v];
             std::vector<int32_t> inc(2 * ne);
@@ -90,14 +93,33 @@ class BatchMatching : public BatchProgram {
             const int64_t base = vedge.size();
             for (int64_t v = 0; v < kept; ++v) vptr.push_back((int32_t)(base + cnt[v + 1]));
             vedge.insert(vedge.end(), inc.begin(), inc.end());
-            // tiles (never across instances)
+            // nnz-balanced vertex tiles of this instance (never across instances)
             vrec0[k] = (int32_t)vt.size();
-            for (int64_t i = 0; i < kept; i += kTileV)
-                vt.push_back(BTile{k, (int32_t)(V + i), (int32_t)(V + std::min<int64_t>(i + kTileV, kept)), 0});
+            lrec0[k] = (int32_t)lseg.size();
+            {
+                const TilePlan tp = build_tiles(cnt, kept);
+                const int32_t lbase = (int32_t)lseg.size();
+                for (const Tile &t : tp.tiles)
+                    vt.push_back(BTile{k, (int32_t)(V + t.s0), (int32_t)(V + t.s1), (int32_t)(base + t.k0),
+                                       (int32_t)(base + t.k1), t.lid < 0 ? -1 : lbase + t.lid, t.cidx, 0});
+                for (size_t l = 0; l < tp.lseg.size(); ++l) {
+                    lseg.push_back((int32_t)(V + tp.lseg[l]));
+                    lfirst.push_back(nslots + tp.lfirst[l]);
+                    lcount.push_back(tp.lcount[l]);
+                }
+                nslots += tp.nslots;
+            }
             vrecn[k] = (int32_t)vt.size() - vrec0[k];
+            lrecn[k] = (int32_t)lseg.size() - lrec0[k];
+            wrec0[k] = (int32_t)wt.size();
+            for (int64_t i = 0; i < kept; i += kTileW)
+                wt.push_back(BTile{k, (int32_t)(V + i), (int32_t)(V + std::min<int64_t>(i + kTileW, kept)),
+                                   0, 0, -1, 0, 0});
+            wrecn[k] = (int32_t)wt.size() - wrec0[k];
             erec0[k] = (int32_t)et.size();
             for (int64_t i = 0; i < ne; i += kTileE)
-                et.push_back(BTile{k, (int32_t)(E + i), (int32_t)(E + std::min<int64_t>(i + kTileE, ne)), 0});
+                et.push_back(BTile{k, (int32_t)(E + i), (int32_t)(E + std::min<int64_t>(i + kTileE, ne)),
+                                   0, 0, -1, 0, 0});
             erecn[k] = (int32_t)et.size() - erec0[k];
             // outer-search bracket (as for any packing LP with unit entries):
             // hi = sum_i 1 / min_j P_ji = |E|; lo from the rescaled Algorithm 1 point
@@ -124,6 +146,17 @@ class BatchMatching : public BatchProgram {
         up(erec0_, erec0.data(), count * 4);
         up(erecn_, erecn.data(), count * 4);
         up(nedge_, nedge.data(), count * 4);
+        up(lrec0_, lrec0.data(), count * 4);
+        up(wt_, wt.data(), wt.size() * sizeof(BTile));
+        up(wrec0_, wrec0.data(), count * 4);
+        up(wrecn_, wrecn.data(), count * 4);
+        wpart_.alloc(wt.size() * QMAX * 8);
+        up(lrecn_, lrecn.data(), count * 4);
+        up(lseg_, lseg.data(), lseg.size() * 4);
+        up(lfirst_, lfirst.data(), lfirst.size() * 4);
+        up(lcount_, lcount.data(), lcount.size() * 4);
+        lpart_.alloc(std::max<size_t>((size_t)nslots, 1) * sizeof(T));
+        lpart64_.alloc(std::max<size_t>((size_t)nslots, 1) * 8);
         x_.alloc(E * sizeof(T));
         d_.alloc(E * sizeof(T));
         xbest_.alloc(E * sizeof(T));
@@ -152,6 +185,13 @@ class BatchMatching : public BatchProgram {
         bd_.vrec0 = vrec0_.as<int32_t>(); bd_.vrecn = vrecn_.as<int32_t>();
         bd_.erec0 = erec0_.as<int32_t>(); bd_.erecn = erecn_.as<int32_t>();
         bd_.nedge = nedge_.as<int32_t>();
+        bd_.vlong = LongSegs{lseg_.as<int32_t>(), lfirst_.as<int32_t>(), lcount_.as<int32_t>(),
+                             (int32_t)lseg.size()};
+        bd_.lrec0 = lrec0_.as<int32_t>(); bd_.lrecn = lrecn_.as<int32_t>();
+        bd_.wt = wt_.as<BTile>(); bd_.nwt = (int32_t)wt.size();
+        bd_.wrec0 = wrec0_.as<int32_t>(); bd_.wrecn = wrecn_.as<int32_t>();
+        bd_.wpart = wpart_.as<double>();
+        bd_.lpart = lpart_.as<T>(); bd_.lpart64 = lpart64_.as<double>();
         bd_.ctl = ctl_.as<Ctl>();
         bd_.stat = stat_.as<int32_t>();
         bd_.vpart = vpart_.as<double>(); bd_.epart = epart_.as<double>();
@@ -161,6 +201,7 @@ class BatchMatching : public BatchProgram {
             return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, (int64_t)occ * s.num_cus, (int64_t)65535}));
         };
         L_.grid_v = grid(bd_.nvt, occ_v);
+        L_.grid_w = grid(bd_.nwt, occ_e);
         L_.grid_e = grid(bd_.net, occ_e);
     }
 
@@ -364,6 +405,7 @@ class BatchMatching : public BatchProgram {
     int32_t *stat_host_ = nullptr;
     hipGraphExec_t graph_ = nullptr;
     DevBuf eu_, ev_, vptr_, vedge_, vt_, et_, vrec0_, vrecn_, erec0_, erecn_, nedge_;
+    DevBuf lrec0_, lrecn_, lseg_, lfirst_, lcount_, lpart_, lpart64_, wt_, wrec0_, wrecn_, wpart_;
     DevBuf x_, d_, xbest_, y_, dy_, w_, vpart_, epart_, ctl_, stat_;
 };
 
