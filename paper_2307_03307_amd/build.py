@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmwu.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["generic.hip", "vcover.hip", "batch.hip", "program_generic.cpp", "program_vcover.cpp",
-           "program_batch.cpp", "solver.cpp"]
+SOURCES = ["generic.hip", "vcover.hip", "batch.hip", "densest.hip", "program_generic.cpp",
+           "program_vcover.cpp", "program_batch.cpp", "program_densest.cpp", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,0 +1,525 @@
+// Fused densest-subgraph program (gfx950): the dual of Charikar's LP with D
+// fixed (Section 3), W z >= 1, (1/D) O z <= 1, z >= 0, run through Algorithm 2
+// with the step search of Algorithm 3 (Section 4).
+//
+// Variables are the edge ends: z_{2e} on the first endpoint of edge e and
+// z_{2e+1} on the second.  Every variable lies in exactly one packing row (its
+// vertex) and one covering row (its edge), so the transpose products need no
+// index structure: g_i = w_{v(i)} / (D sum w), h_i = u_{e(i)} / sum u.  The
+// vertex rows are segmented sums over each vertex's variables (nnz-balanced
+// tiles with LDS staging); the edge rows are pairs.
+//
+// The direction compares g_i with h_i.  In FP32 both weights of a variable
+// whose edge is well covered and whose vertex is lightly loaded underflow, so
+// the ratio is formed in the log domain from y_v and z_e in FP64:
+// g_i / h_i = exp(eta (y_v - L_P) + eta (z_e - L_C) + ln(sP / sC)), with L_P and
+// L_C the LSE totals of the current point.
+// FP64 keeps the plain ratio of the stored weights, as the definition reads.
+#include "device_common.h"
+
+namespace mwu {
+
+#define DLAUNCH(kernel, grid, ...) hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLOCK), 0, st, __VA_ARGS__)
+
+// ------------------------------------------------------------------ init
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_init_x(DnDev<T> dd, Ctl *ctl, int have_x0, const double *src,
+                                                    double *part)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const double eps = ctl->eps, sP = ctl->sP;
+    double v[1] = {0.0};
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += gridDim.x * BLOCK) {
+        T x;
+        if (src) {
+            x = (T)src[i];
+            dd.x[i] = x;
+        } else if (!have_x0) {
+            x = (T)(eps / ((double)dd.n * sP));   // Algorithm 1: eps / (n max_j P_ji), P_ji = sP
+            dd.x[i] = x;
+        } else {
+            x = dd.x[i];
+        }
+        dd.d[i] = T(0);
+        v[0] += (double)x;
+    }
+    const Red red{1, 0, 0};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 1, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void dn_init_x_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const Red red{1, 0, 0};
+    fold_records<1>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) finish_sumx(ctl, s_rec[0]);
+}
+
+// ------------------------------------------------------------------ forward products
+
+// Vertex rows: INIT y = sP O x (clears dy), else dy = sP O d.  Record [max].
+template <class T, bool INIT>
+__global__ __launch_bounds__(BLOCK) void dn_fwd_v(DnDev<T> dd, Ctl *ctl, double *part)
+{
+    __shared__ T s_acc[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ T s_tacc[BLOCK / 64];
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    if (!INIT && ctl->phase != PH_FWD) return;
+    const T *src = INIT ? dd.x : dd.d;
+    const T sP = (T)ctl->sP;
+    double v[1] = {-INFINITY};
+    auto elem = [&](int k) -> T { return src[dd.vvar[k]]; };
+    auto epi = [&](int r, T acc) {
+        acc = sP * acc;
+        if (INIT) { dd.y[r] = (double)acc; dd.dy[r] = T(0); }
+        else dd.dy[r] = acc;
+        v[0] = fmax(v[0], (double)acc);
+    };
+    for (int t = blockIdx.x; t < dd.nvtiles; t += gridDim.x) {
+        const Tile tl = dd.vtiles[t];
+        if (tl.lid < 0) seg_tile<T>(tl, dd.vptr, elem, epi, s_acc, s_ptr, nullptr, nullptr);
+        else chunk_tile<T>(tl, elem, s_tacc, dd.lpart, dd.vlong.lfirst);
+    }
+    const Red red{0, 0, 1};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 1, part);
+}
+
+// Edge rows: INIT z = sC (x_2e + x_2e+1) (clears dz), else dz.  Record [min].
+template <class T, bool INIT>
+__global__ __launch_bounds__(BLOCK) void dn_fwd_e(DnDev<T> dd, Ctl *ctl, double *part)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    if (!INIT && ctl->phase != PH_FWD) return;
+    const T *src = INIT ? dd.x : dd.d;
+    const T sC = (T)ctl->sC;
+    double v[1] = {INFINITY};
+    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK) {
+        if (INIT) {
+            const double val = (double)sC * ((double)src[2 * e] + (double)src[2 * e + 1]);
+            dd.z[e] = val;
+            dd.dz[e] = T(0);
+            v[0] = fmin(v[0], val);
+        } else {
+            const T val = sC * (src[2 * e] + src[2 * e + 1]);
+            dd.dz[e] = val;
+            v[0] = fmin(v[0], (double)val);
+        }
+    }
+    const Red red{0, 1, 0};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 1, part);
+}
+
+template <class T, bool INIT>
+__global__ __launch_bounds__(BLOCK) void dn_fwd_fin(DnDev<T> dd, Ctl *ctl, const double *pv, int Gv,
+                                                     const double *pe, int Ge)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_a[QMAX], s_b[QMAX], s_l[QMAX];
+    if (!INIT && ctl->phase != PH_FWD) return;
+    const T sP = (T)ctl->sP;
+    double lv[1] = {-INFINITY};
+    for (int l = threadIdx.x; l < dd.vlong.nlong; l += BLOCK) {
+        const T acc = sP * long_sum<T>(l, dd.lpart, dd.vlong.lfirst, dd.vlong.lcount);
+        const int r = dd.vlong.lseg[l];
+        if (INIT) { dd.y[r] = (double)acc; dd.dy[r] = T(0); }
+        else dd.dy[r] = acc;
+        lv[0] = fmax(lv[0], (double)acc);
+    }
+    const Red rmax{0, 0, 1}, rmin{0, 1, 0};
+    block_combine<1>(lv, rmax, 0, s_wave, s_l);
+    fold_records<1>(pv, Gv, rmax, 0, s_wave, s_a);
+    fold_records<1>(pe, Ge, rmin, 0, s_wave, s_b);
+    if (threadIdx.x == 0) {
+        double rec[2] = {s_b[0], fmax(s_a[0], s_l[0])};   // [min over C rows | max over P rows]
+        if (INIT) {
+            finish_init_fwd(ctl, rec);
+        } else if (!held(ctl)) {
+            ctl->dymax = rec[1];
+            begin_search(ctl, dd.forced);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ row pass
+
+// y += a dy, w = exp(eta (y - L_P)) over vertices; z += a dz, u = exp(-eta (z
+// - L_C)) over edges.  Record [sum w | sum u | min z | max y].
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_row(DnDev<T> dd, Ctl *ctl, double *part)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_ROW) return;
+    const double a = ctl->alpha;
+    const double eta = ctl->eta, LP = ctl->LP, LC = ctl->LC;
+    double v[4] = {0.0, 0.0, INFINITY, -INFINITY};
+    const int stride = gridDim.x * BLOCK;
+    for (int r = blockIdx.x * BLOCK + threadIdx.x; r < dd.nv; r += stride) {
+        const double y = dd.y[r] + a * (double)dd.dy[r];
+        dd.y[r] = y;
+        const T w = exp_arg(eta * (y - LP), T(0));
+        dd.w[r] = w;
+        v[0] += (double)w;
+        v[3] = fmax(v[3], y);
+    }
+    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
+        const double z = dd.z[e] + a * (double)dd.dz[e];
+        dd.z[e] = z;
+        const T u = exp_arg(-eta * (z - LC), T(0));
+        dd.u[e] = u;
+        v[1] += (double)u;
+        v[2] = fmin(v[2], z);
+    }
+    const Red red{2, 1, 1};
+    block_combine<4>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 4, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void dn_row_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_ROW) return;
+    const Red red{2, 1, 1};
+    fold_records<4>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) finish_row(ctl, s_rec);
+}
+
+// ------------------------------------------------------------------ column pass
+
+// Commit x += a d, then g, h and the direction of every variable.  Record
+// [sum d | min g | max d | max h].  In PH_COMMIT only the commit.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *part)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    const int ph = ctl->phase;
+    if (ph != PH_COL && ph != PH_COMMIT) return;
+    const T a = (T)ctl->alpha;
+    const int stride = gridDim.x * BLOCK;
+    if (ph == PH_COMMIT) {
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += stride) dd.x[i] = dd.x[i] + a * dd.d[i];
+        return;
+    }
+    const double sP = ctl->sP, sC = ctl->sC, invSw = ctl->invSw, invSu = ctl->invSu;
+    const double step = ctl->step, qmin = ctl->qmin, eta = ctl->eta, LP = ctl->LP, LC = ctl->LC;
+    // after the row pass L_P and L_C are the exact LSE totals: the normalized
+    // weights are exp(eta (y - L_P)) and exp(-eta (z - L_C))
+    const double lnK = log(sP / sC);
+    double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += stride) {
+        const int e = i >> 1;
+        const int r = (i & 1) ? dd.ev[e] : dd.eu[e];
+        const T x = dd.x[i] + a * dd.d[i];
+        dd.x[i] = x;
+        const double g = sP * (double)dd.w[r] * invSw;
+        const double h = sC * (double)dd.u[e] * invSu;
+        double q;
+        if (sizeof(T) == 4) {
+            // log-domain ratio: no underflow of the FP32 weights, and
+            // q = 1 - g/h = -expm1(ln(g/h)) without cancellation near g = h
+            const double lr = eta * (dd.y[r] - LP) + eta * (dd.z[e] - LC) + lnK;
+            q = -expm1(lr);
+        } else {
+            q = h > 0.0 ? 1.0 - g / h : 0.0;
+        }
+        double di = 0.0;
+        if (q > qmin) di = step * q * (double)x;
+        const T dt = (T)di;
+        dd.d[i] = dt;
+        v[0] += (double)dt;
+        v[1] = fmin(v[1], g);
+        v[2] = fmax(v[2], (double)dt);
+        v[3] = fmax(v[3], h);
+        if (dd.g_dbg) { dd.g_dbg[i] = g; dd.h_dbg[i] = h; }
+    }
+    const Red red{1, 1, 2};
+    block_combine<4>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 4, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void dn_col_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 4];
+    __shared__ double s_rec[QMAX];
+    const int ph = ctl->phase;
+    if (ph != PH_COL && ph != PH_COMMIT) return;
+    if (ph == PH_COMMIT) {
+        if (threadIdx.x == 0 && !held(ctl)) { ctl->alpha = 0.0; ctl->phase = PH_DONE; }
+        return;
+    }
+    const Red red{1, 1, 2};
+    fold_records<4>(part, G, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) finish_col(ctl, s_rec);
+}
+
+// ------------------------------------------------------------------ step search
+
+template <class T, int KIND>
+__device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wave, double *s_rec)
+{
+    const double eta = ctl->eta;
+    const int stride = gridDim.x * BLOCK;
+    const int r0 = blockIdx.x * BLOCK + threadIdx.x;
+    const int nc = ctl->ncand;
+    const double *cand = ctl->cand;
+    const double a0 = ctl->cand[0], gdel = ctl->gdelta;
+    {
+        double s1[KC];
+#pragma unroll
+        for (int k = 0; k < KC; ++k) s1[k] = 0.0;
+        for (int r = r0; r < dd.nv; r += stride) {
+            const T w = dd.w[r], dy = dd.dy[r];
+            if constexpr (KIND == SK_EXP) {
+                T m = expm1_t((T)(eta * a0 * (double)dy));
+#pragma unroll
+                for (int k = 0; k < KE; ++k) {
+                    s1[k] += (double)(w * m);
+                    m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
+                }
+            } else if constexpr (KIND == SK_GRID) {
+                T m = expm1_t((T)(eta * a0 * (double)dy));
+                const T mr = expm1_t((T)(eta * gdel * (double)dy));
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    s1[k] += (double)(w * m);
+                    m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < KC; ++k)
+                    if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
+            }
+        }
+        const Red redp{KC, 0, 0};
+        block_combine<KC>(s1, redp, 0, s_wave, s_rec);
+    }
+    {
+        CovAcc<T, double> ca;
+        ca.init(KIND != SK_GRID);
+        for (int e = r0; e < dd.ne; e += stride)
+            cov_terms<T, KIND, double>(nc, cand, a0, gdel, eta, dd.u[e], dd.z[e], dd.dz[e], ca.acc, ca.zmn);
+        ca.combine(s_wave, s_rec + KC);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double *part)
+{
+    __shared__ double s_wave[4 * 3 * KC];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_SEARCH) return;
+    const int kind = ctl->skind;
+    if (kind == SK_REFINE) {
+        const double a = ctl->ref_alpha, eta = ctl->eta;
+        const int stride = gridDim.x * BLOCK;
+        const int r0 = blockIdx.x * BLOCK + threadIdx.x;
+        double v[2];
+        if (ctl->ref_valid == 0) {   // [min z' | max eta y']
+            v[0] = INFINITY;
+            v[1] = -INFINITY;
+            for (int r = r0; r < dd.nv; r += stride) v[1] = fmax(v[1], eta * (dd.y[r] + a * (double)dd.dy[r]));
+            for (int e = r0; e < dd.ne; e += stride) v[0] = fmin(v[0], dd.z[e] + a * (double)dd.dz[e]);
+            const Red red{0, 1, 1};
+            block_combine<2>(v, red, 0, s_wave, s_rec);
+        } else {                     // [sum over packing rows | sum over covering rows]
+            const double pm = ctl->rfPm, zm = ctl->rfZmin;
+            v[0] = 0.0;
+            v[1] = 0.0;
+            for (int r = r0; r < dd.nv; r += stride) v[0] += exp(eta * (dd.y[r] + a * (double)dd.dy[r]) - pm);
+            for (int e = r0; e < dd.ne; e += stride)
+                v[1] += exp(-eta * ((dd.z[e] + a * (double)dd.dz[e]) - zm));
+            const Red red{2, 0, 0};
+            block_combine<2>(v, red, 0, s_wave, s_rec);
+        }
+        store_record(s_rec, 2, part);
+        return;
+    }
+    switch (kind) {
+    case SK_EXP: dn_search_rows<T, SK_EXP>(dd, ctl, s_wave, s_rec); break;
+    case SK_GRID: dn_search_rows<T, SK_GRID>(dd, ctl, s_wave, s_rec); break;
+    default: dn_search_rows<T, SK_LIST>(dd, ctl, s_wave, s_rec); break;
+    }
+    store_record(s_rec, 4 * KC, part);
+}
+
+__global__ __launch_bounds__(BLOCK) void dn_search_fin(Ctl *ctl, const double *part, int G)
+{
+    __shared__ double s_wave[4 * 4 * KC];
+    __shared__ double s_rec[QMAX];
+    if (ctl->phase != PH_SEARCH) return;
+    if (ctl->skind == SK_REFINE) {
+        const Red red = ctl->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
+        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+    } else {
+        const Red red{3 * KC, KC, 0};
+        fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
+    }
+    if (threadIdx.x == 0) finish_search(ctl, s_rec);
+}
+
+// ------------------------------------------------------------------ FP64 statistics
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_stats_v(DnDev<T> dd, double *part)
+{
+    __shared__ double s_acc[TILE_LDS];
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ double s_tacc[BLOCK / 64];
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    double v[1] = {-INFINITY};
+    auto elem = [&](int k) -> double { return (double)dd.x[dd.vvar[k]]; };
+    auto epi = [&](int, double acc) { v[0] = fmax(v[0], acc); };
+    for (int t = blockIdx.x; t < dd.nvtiles; t += gridDim.x) {
+        const Tile tl = dd.vtiles[t];
+        if (tl.lid < 0) seg_tile<double>(tl, dd.vptr, elem, epi, s_acc, s_ptr, nullptr, nullptr);
+        else chunk_tile<double>(tl, elem, s_tacc, dd.lpart64, dd.vlong.lfirst);
+    }
+    const Red red{0, 0, 1};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 1, part);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_stats_e(DnDev<T> dd, double *part)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    double v[1] = {INFINITY};
+    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK)
+        v[0] = fmin(v[0], (double)dd.x[2 * e] + (double)dd.x[2 * e + 1]);
+    const Red red{0, 1, 0};
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    store_record(s_rec, 1, part);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_stats_fin(DnDev<T> dd, Ctl *ctl, const double *pv, int Gv,
+                                                       const double *pe, int Ge)
+{
+    __shared__ double s_wave[4];
+    __shared__ double s_a[QMAX], s_b[QMAX], s_l[QMAX];
+    double lv[1] = {-INFINITY};
+    for (int l = threadIdx.x; l < dd.vlong.nlong; l += BLOCK)
+        lv[0] = fmax(lv[0], long_sum<double>(l, dd.lpart64, dd.vlong.lfirst, dd.vlong.lcount));
+    const Red rmax{0, 0, 1}, rmin{0, 1, 0};
+    block_combine<1>(lv, rmax, 0, s_wave, s_l);
+    fold_records<1>(pv, Gv, rmax, 0, s_wave, s_a);
+    fold_records<1>(pe, Ge, rmin, 0, s_wave, s_b);
+    if (threadIdx.x == 0) {
+        ctl->ymax = ctl->sP * fmax(s_a[0], s_l[0]);
+        ctl->zmin = ctl->sC * s_b[0];
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <class T>
+void dn_init(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st, bool have_x0, const double *src)
+{
+    DLAUNCH(dn_init_x<T>, L.grid_n, dd, ctl, have_x0 ? 1 : 0, src, L.partials);
+    DLAUNCH(dn_init_x_fin, 1, ctl, (const double *)L.partials, L.grid_n);
+    DLAUNCH((dn_fwd_v<T, true>), L.grid_vt, dd, ctl, L.partials);
+    DLAUNCH((dn_fwd_e<T, true>), L.grid_e, dd, ctl, L.partials2);
+    DLAUNCH((dn_fwd_fin<T, true>), 1, dd, ctl, (const double *)L.partials, L.grid_vt,
+            (const double *)L.partials2, L.grid_e);
+}
+
+template <class T>
+void dn_row_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
+{
+    DLAUNCH(dn_row<T>, L.grid_r, dd, ctl, L.partials);
+    DLAUNCH(dn_row_fin, 1, ctl, (const double *)L.partials, L.grid_r);
+}
+
+template <class T>
+void dn_col_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
+{
+    DLAUNCH(dn_col<T>, L.grid_n, dd, ctl, L.partials);
+    DLAUNCH(dn_col_fin, 1, ctl, (const double *)L.partials, L.grid_n);
+}
+
+template <class T>
+void dn_fwd_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
+{
+    DLAUNCH((dn_fwd_v<T, false>), L.grid_vt, dd, ctl, L.partials);
+    DLAUNCH((dn_fwd_e<T, false>), L.grid_e, dd, ctl, L.partials2);
+    DLAUNCH((dn_fwd_fin<T, false>), 1, dd, ctl, (const double *)L.partials, L.grid_vt,
+            (const double *)L.partials2, L.grid_e);
+}
+
+template <class T>
+void dn_search_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
+{
+    DLAUNCH(dn_search<T>, L.grid_s, dd, ctl, L.partials);
+    DLAUNCH(dn_search_fin, 1, ctl, (const double *)L.partials, L.grid_s);
+}
+
+template <class T>
+void dn_iteration(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
+{
+    dn_row_pass<T>(dd, ctl, L, st);
+    dn_col_pass<T>(dd, ctl, L, st);
+    dn_fwd_pass<T>(dd, ctl, L, st);
+    dn_search_pass<T>(dd, ctl, L, st);
+    dn_search_pass<T>(dd, ctl, L, st);
+}
+
+template <class T>
+void dn_stats(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
+{
+    DLAUNCH(dn_init_x<T>, L.grid_n, dd, ctl, 1, (const double *)nullptr, L.partials);
+    DLAUNCH(dn_init_x_fin, 1, ctl, (const double *)L.partials, L.grid_n);
+    DLAUNCH(dn_stats_v<T>, L.grid_vt, dd, L.partials);
+    DLAUNCH(dn_stats_e<T>, L.grid_e, dd, L.partials2);
+    DLAUNCH(dn_stats_fin<T>, 1, dd, ctl, (const double *)L.partials, L.grid_vt, (const double *)L.partials2,
+            L.grid_e);
+}
+
+template <class T>
+void dn_main(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st, int which)
+{
+    switch (which) {
+    case 0: DLAUNCH(dn_row<T>, L.grid_r, dd, ctl, L.partials); break;
+    case 1: DLAUNCH(dn_col<T>, L.grid_n, dd, ctl, L.partials); break;
+    case 2: DLAUNCH((dn_fwd_v<T, false>), L.grid_vt, dd, ctl, L.partials); break;
+    default: DLAUNCH(dn_search<T>, L.grid_s, dd, ctl, L.partials); break;
+    }
+}
+
+template <class T>
+void dn_occupancy(int *per_cu_vt, int *per_cu_search)
+{
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, dn_fwd_v<T, false>, BLOCK, 0) != hipSuccess) a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, dn_search<T>, BLOCK, 0) != hipSuccess) b = 0;
+    *per_cu_vt = a > 0 ? a : 1;
+    *per_cu_search = b > 0 ? b : 1;
+}
+
+#define MWU_DN_INSTANTIATE(T)                                                                          \
+    template void dn_init<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t, bool, const double *); \
+    template void dn_row_pass<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);              \
+    template void dn_col_pass<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);              \
+    template void dn_fwd_pass<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);              \
+    template void dn_search_pass<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);           \
+    template void dn_iteration<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);             \
+    template void dn_stats<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);                 \
+    template void dn_main<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t, int);             \
+    template void dn_occupancy<T>(int *, int *);
+
+MWU_DN_INSTANTIATE(float)
+MWU_DN_INSTANTIATE(double)
+
+}  // namespace mwu

@@ -340,9 +340,9 @@ MWU_DEV Acc long_sum(int lid, const Acc *lpart, const int32_t *lfirst, const int
 // squared term from exp every 4 candidates); on the bisection grid a_k = a0 +
 // k gdel and expm1(x + y) = expm1(x) + expm1(y) + expm1(x) expm1(y).  A zero
 // weight or a zero dz needs no special case: the terms come out as 0 and u.
-template <class T, int KIND>
-MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, double eta, T u, T z, T dz,
-                       T *acc, T *zmn)
+template <class T, int KIND, class Z = T>
+MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, double eta, T u, Z z, T dz,
+                       T *acc, Z *zmn)
 {
     constexpr int NK = KIND == SK_EXP ? KE : KC;
     if constexpr (KIND == SK_LIST) {   // arbitrary candidates, direct evaluation
@@ -350,17 +350,17 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, doubl
         for (int k = 0; k < KC; ++k)
             if (k < nc) {
                 const double a = cand[k];
-                zmn[k] = fmin(zmn[k], z + (T)a * dz);
+                zmn[k] = fmin(zmn[k], z + (Z)a * (Z)dz);
                 const T b = (T)(eta * a * (double)dz);
                 acc[k] += u * expm1_t(-b);
                 acc[KC + k] += u * exp_t(-b);
             }
     } else {
         if constexpr (KIND == SK_EXP) {   // the bisection replay never reads the minima
-            T ak = (T)a0;
+            Z ak = (Z)a0;
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
-                zmn[k] = fmin(zmn[k], z + ak * dz);
+                zmn[k] = fmin(zmn[k], z + ak * (Z)dz);
                 ak = ak + ak;
             }
         }
@@ -398,10 +398,10 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, doubl
 // Per-thread accumulators of the covering side of a search pass.  The
 // per-thread partial sums (same-sign terms, a few dozen per thread) are kept
 // in the storage type; block and grid totals are double.
-template <class T>
+template <class T, class Z = T>
 struct CovAcc {
     T acc[2 * KC];
-    T zmn[KC];
+    Z zmn[KC];
     // Bisection passes leave the minima at -inf: the replay never reads them,
     // and -inf can never pass for an early return.
     MWU_DEV void init(bool minima = true)
@@ -409,7 +409,7 @@ struct CovAcc {
 #pragma unroll
         for (int k = 0; k < 2 * KC; ++k) acc[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < KC; ++k) zmn[k] = minima ? T(INFINITY) : T(-INFINITY);
+        for (int k = 0; k < KC; ++k) zmn[k] = minima ? Z(INFINITY) : Z(-INFINITY);
     }
     // block-combine into out[0..3KC): [s1C | s2C | zmin]
     MWU_DEV void combine(double *s_wave, double *out)

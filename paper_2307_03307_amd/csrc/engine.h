@@ -154,6 +154,46 @@ struct VcDev {
     const double *forced;
 };
 
+// Fused densest-subgraph program: variables z_{2e}, z_{2e+1} are the two ends
+// of edge e; vertex rows (packing, scaled by 1/D) are segmented sums over
+// vptr/vvar, edge rows (covering) are pairs.  The row values y, z are kept in
+// FP64 in both forms: every variable sees one weight on each side, so the
+// exponents eta (y - L) must not carry storage rounding.
+template <class T>
+struct DnDev {
+    int32_t nv, ne, n;                    // non-isolated vertices, edges, variables (2 ne)
+    const int32_t *vptr, *vvar;           // variables of each vertex row
+    const Tile *vtiles;
+    int32_t nvtiles;
+    LongSegs vlong;
+    T *lpart;
+    double *lpart64;
+    const int32_t *eu, *ev;               // vertex rows of variables 2e and 2e+1
+    T *x, *d;                             // variables
+    double *y;                            // vertex rows (scaled by sP), FP64 in both forms
+    T *dy, *w;
+    double *z;                            // edge rows, FP64 in both forms
+    T *dz, *u;
+    double *g_dbg, *h_dbg;                // nullable
+    const double *forced;
+};
+
+struct DnLaunch {
+    int grid_vt, grid_e, grid_n, grid_r, grid_s;
+    double *partials, *partials2;
+};
+
+template <class T> void dn_init(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st, bool have_x0,
+                                const double *src);
+template <class T> void dn_row_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
+template <class T> void dn_col_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
+template <class T> void dn_fwd_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
+template <class T> void dn_search_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
+template <class T> void dn_iteration(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
+template <class T> void dn_stats(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
+template <class T> void dn_main(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st, int which);
+template <class T> void dn_occupancy(int *per_cu_vt, int *per_cu_search);
+
 // Batched matching program: many independent packing LPs max 1^T x s.t.
 // M_k x <= 1 (bipartite matching, Section 3) in concatenated arrays.  Tiles
 // never cross instances; every tile of a pass writes one record, and the

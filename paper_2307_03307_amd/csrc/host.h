@@ -141,6 +141,10 @@ TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg);
 // Program builders.
 std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C);
 // Vertex cover from a validated edge list; newid maps vertices to compact ids (-1 = isolated).
+// Densest subgraph from the edge list of an (O/D, W) problem; vid maps vertices
+// to compact ids (-1 isolated), in vertex order.
+std::unique_ptr<Program> make_densest_program(Solver &s, const EdgeList &el, const std::vector<int64_t> &vid,
+                                              int64_t nv);
 std::unique_ptr<BatchProgram> make_batch_matching(Solver &s, const mwu_problem *probs, int32_t count);
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,
                                              const std::vector<int64_t> &newid, int64_t nv);

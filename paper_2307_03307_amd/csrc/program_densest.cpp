@@ -1,0 +1,230 @@
+// Host side of the fused densest-subgraph program: vertex rows of the
+// non-isolated vertices (in vertex order, as the level-set rounding expects),
+// edge rows in the caller's edge order, variables 2e / 2e+1 on the two ends.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+
+namespace mwu {
+
+template <class T>
+class DensestProgram : public Program {
+  public:
+    // el: validated edge list; vid: compact id of every vertex (-1 isolated)
+    DensestProgram(Solver &s, const EdgeList &el, const std::vector<int64_t> &vid, int64_t nv) : s_(s)
+    {
+        nv_ = nv;
+        ne_ = el.ne;
+        n_ = 2 * ne_;
+        if (n_ >= INT32_MAX) throw ApiError{MWU_ERR_TOO_LARGE, "too many edges"};
+        std::vector<int32_t> eu(ne_), ev(ne_), vptr(nv + 1, 0), vvar(n_);
+        for (int64_t e = 0; e < ne_; ++e) {
+            eu[e] = (int32_t)vid[el.u[e]];
+            ev[e] = (int32_t)vid[el.v[e]];
+            vptr[eu[e] + 1]++;
+            vptr[ev[e] + 1]++;
+        }
+        for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+        {
+            std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
+            for (int64_t e = 0; e < ne_; ++e) {   // variables of a vertex in increasing order
+                vvar[fill[eu[e]]++] = (int32_t)(2 * e);
+                vvar[fill[ev[e]]++] = (int32_t)(2 * e + 1);
+            }
+        }
+        TilePlan vt = build_tiles(vptr, nv);
+        auto up = [&](DevBuf &b, const void *src, size_t bytes) {
+            b.alloc(std::max<size_t>(bytes, 8));
+            if (bytes) HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        up(eu_, eu.data(), ne_ * 4);
+        up(ev_, ev.data(), ne_ * 4);
+        up(vptr_, vptr.data(), vptr.size() * 4);
+        up(vvar_, vvar.data(), vvar.size() * 4);
+        up(vtiles_, vt.tiles.data(), vt.tiles.size() * sizeof(Tile));
+        up(lseg_, vt.lseg.data(), vt.lseg.size() * 4);
+        up(lfirst_, vt.lfirst.data(), vt.lfirst.size() * 4);
+        up(lcount_, vt.lcount.data(), vt.lcount.size() * 4);
+        lpart_.alloc(std::max<int32_t>(vt.nslots, 1) * sizeof(T));
+        lpart64_.alloc(std::max<int32_t>(vt.nslots, 1) * 8);
+        x_.alloc(n_ * sizeof(T)); d_.alloc(n_ * sizeof(T)); xbest_.alloc(n_ * sizeof(T));
+        y_.alloc(nv * 8); dy_.alloc(nv * sizeof(T)); w_.alloc(nv * sizeof(T));
+        z_.alloc(ne_ * 8); dz_.alloc(ne_ * sizeof(T)); u_.alloc(ne_ * sizeof(T));
+        HIP_OK(hipMemset(x_.p, 0, x_.bytes));
+        HIP_OK(hipMemset(d_.p, 0, d_.bytes));
+        partials_.alloc((size_t)GRID_MAX * QMAX * 8);
+        partials2_.alloc((size_t)GRID_MAX * QMAX * 8);
+
+        dd_ = DnDev<T>{};
+        dd_.nv = (int32_t)nv; dd_.ne = (int32_t)ne_; dd_.n = (int32_t)n_;
+        dd_.vptr = vptr_.as<int32_t>(); dd_.vvar = vvar_.as<int32_t>();
+        dd_.vtiles = vtiles_.as<Tile>(); dd_.nvtiles = (int32_t)vt.tiles.size();
+        dd_.vlong = LongSegs{lseg_.as<int32_t>(), lfirst_.as<int32_t>(), lcount_.as<int32_t>(),
+                             (int32_t)vt.lseg.size()};
+        dd_.lpart = lpart_.as<T>(); dd_.lpart64 = lpart64_.as<double>();
+        dd_.eu = eu_.as<int32_t>(); dd_.ev = ev_.as<int32_t>();
+        dd_.x = x_.as<T>(); dd_.d = d_.as<T>();
+        dd_.y = y_.as<double>(); dd_.dy = dy_.as<T>(); dd_.w = w_.as<T>();
+        dd_.z = z_.as<double>(); dd_.dz = dz_.as<T>(); dd_.u = u_.as<T>();
+        dd_.g_dbg = nullptr; dd_.h_dbg = nullptr; dd_.forced = nullptr;
+        int occ_v = 1, occ_s = 1;
+        dn_occupancy<T>(&occ_v, &occ_s);
+        auto clampg = [](int64_t items, int64_t per, int64_t cap) {
+            return (int)std::max<int64_t>(1, std::min<int64_t>((items + per - 1) / per, cap));
+        };
+        L_.grid_vt = clampg((int64_t)vt.tiles.size(), 1, std::min<int64_t>(GRID_MAX, (int64_t)occ_v * s.num_cus));
+        L_.grid_e = clampg(ne_, BLOCK * 4, GRID_MAX);
+        L_.grid_n = clampg(n_, BLOCK * 4, GRID_MAX);
+        L_.grid_r = clampg(std::max<int64_t>(nv, ne_), BLOCK * 4, GRID_MAX);
+        L_.grid_s = clampg(std::max<int64_t>(nv, ne_), BLOCK * 4,
+                           std::min<int64_t>(GRID_MAX, (int64_t)occ_s * s.num_cus));
+        L_.partials = partials_.as<double>();
+        L_.partials2 = partials2_.as<double>();
+    }
+
+    int64_t n() const override { return n_; }
+    int64_t mP() const override { return nv_; }
+    int64_t mC() const override { return ne_; }
+    Ctl *ctl() const { return s_.ctl_buf.as<Ctl>(); }
+
+    void probe_init(bool have_x0) override { dn_init<T>(dd_, ctl(), L_, s_.stream, have_x0, nullptr); }
+
+    void upload_x(const double *host_x) override
+    {
+        DevBuf tmp;
+        tmp.alloc(n_ * 8);
+        HIP_OK(hipMemcpyAsync(tmp.p, host_x, n_ * 8, hipMemcpyHostToDevice, s_.stream));
+        narrow<T>(tmp.as<double>(), dd_.x, n_, s_.stream);
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    void iterations(int slots) override
+    {
+        for (int i = 0; i < slots; ++i) dn_iteration<T>(dd_, ctl(), L_, s_.stream);
+    }
+
+    void final_stats() override { dn_stats<T>(dd_, ctl(), L_, s_.stream); }
+
+    void save_best() override
+    {
+        HIP_OK(hipMemcpyAsync(xbest_.p, x_.p, n_ * sizeof(T), hipMemcpyDeviceToDevice, s_.stream));
+    }
+
+    void best_to_host(double *out) override { to_host(xbest_.as<T>(), n_, out); }
+
+    void read(int which, double *out, int64_t len) override
+    {
+        switch (which) {
+        case 0: need(len, n_); to_host(dd_.x, n_, out); return;
+        case 1: need(len, n_); to_host(dd_.d, n_, out); return;
+        case 2:
+        case 3:
+            need(len, n_);
+            if (!dbg_g_.p) throw ApiError{MWU_ERR_STATE, "g/h are recorded by mwu_probe_direction"};
+            HIP_OK(hipMemcpyAsync(out, which == 2 ? dbg_g_.p : dbg_h_.p, n_ * 8, hipMemcpyDeviceToHost,
+                                  s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            return;
+        case 4: need(len, nv_); copy_host(dd_.y, nv_, out); return;
+        case 6: need(len, nv_); to_host(dd_.dy, nv_, out); return;
+        case 5: need(len, ne_); copy_host(dd_.z, ne_, out); return;
+        case 7: need(len, ne_); to_host(dd_.dz, ne_, out); return;
+        }
+        throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
+    }
+
+    void row_pass() override { dn_row_pass<T>(dbg(), ctl(), L_, s_.stream); }
+    void col_pass() override { dn_col_pass<T>(dbg(), ctl(), L_, s_.stream); }
+    void fwd_pass() override { dn_fwd_pass<T>(dbg(), ctl(), L_, s_.stream); }
+    void search_pass() override { dn_search_pass<T>(dbg(), ctl(), L_, s_.stream); }
+    void main_kernel(int which) override { dn_main<T>(dd_, ctl(), L_, s_.stream, which); }
+
+    void set_debug(bool on) override
+    {
+        if (on && !dbg_g_.p) { dbg_g_.alloc(n_ * 8); dbg_h_.alloc(n_ * 8); }
+        debug_ = on;
+    }
+
+    void set_forced(const double *host, int count) override
+    {
+        if (count > 0) {
+            forced_.alloc((size_t)count * 8);
+            HIP_OK(hipMemcpy(forced_.p, host, (size_t)count * 8, hipMemcpyHostToDevice));
+            dd_.forced = forced_.as<double>();
+        } else {
+            dd_.forced = nullptr;
+        }
+        s_.graph_slots = -1;
+    }
+
+    void potential(const double *x_dev, double *val_dev, double scale, double *grad_dev,
+                   hipStream_t st) override
+    {
+        set_debug(true);
+        DnDev<T> g = dbg();
+        dn_init<T>(g, ctl(), L_, st, true, x_dev);
+        dn_row_pass<T>(g, ctl(), L_, st);
+        dn_col_pass<T>(g, ctl(), L_, st);
+        if (grad_dev || val_dev)
+            potential_finish(dbg_g_.as<double>(), dbg_h_.as<double>(), grad_dev ? (int)n_ : 0, scale,
+                             grad_dev, ctl(), val_dev, st);
+    }
+
+    double algo_bytes(int which) const override
+    {
+        const double t = sizeof(T), V = (double)nv_, E = (double)ne_;
+        switch (which) {
+        case 0: return (16.0 + 2.0 * t) * (V + E);                     // y rw, dy, w; z rw, dz, u
+        case 1: return 8.0 * E + 4.0 * t * 2.0 * E + 3.0 * t * V + 2.0 * t * E;   // eu, ev; x, d rw; w, y; u, z
+        case 2: return 4.0 * (V + 1) + 4.0 * 2.0 * E + 2.0 * t * 2.0 * E + t * V + t * E;
+        case 3: return 2.0 * t * V + 3.0 * t * E;
+        }
+        return 0.0;
+    }
+    double pass_nnz(int which) const override { return which == 2 ? 2.0 * (double)ne_ : 0.0; }
+
+  private:
+    DnDev<T> dbg() const
+    {
+        DnDev<T> g = dd_;
+        if (debug_) { g.g_dbg = dbg_g_.as<double>(); g.h_dbg = dbg_h_.as<double>(); }
+        return g;
+    }
+    static void need(int64_t len, int64_t want)
+    {
+        if (len != want) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
+    }
+    void to_host(const T *src, int64_t len, double *out)
+    {
+        DevBuf tmp;
+        tmp.alloc(std::max<int64_t>(len, 1) * 8);
+        widen<T>(src, tmp.as<double>(), len, s_.stream);
+        HIP_OK(hipMemcpyAsync(out, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    void copy_host(const double *src, int64_t len, double *out)
+    {
+        HIP_OK(hipMemcpyAsync(out, src, len * 8, hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+    }
+
+    Solver &s_;
+    int64_t nv_ = 0, ne_ = 0, n_ = 0;
+    bool debug_ = false;
+    DnDev<T> dd_{};
+    DnLaunch L_{};
+    DevBuf eu_, ev_, vptr_, vvar_, vtiles_, lseg_, lfirst_, lcount_, lpart_, lpart64_;
+    DevBuf x_, d_, xbest_, y_, dy_, w_, z_, dz_, u_, partials_, partials2_, forced_, dbg_g_, dbg_h_;
+};
+
+std::unique_ptr<Program> make_densest_program(Solver &s, const EdgeList &el, const std::vector<int64_t> &vid,
+                                              int64_t nv)
+{
+    if (s.fp32) return std::unique_ptr<Program>(new DensestProgram<float>(s, el, vid, nv));
+    return std::unique_ptr<Program>(new DensestProgram<double>(s, el, vid, nv));
+}
+
+}  // namespace mwu

@@ -358,10 +358,11 @@ static void build(Solver &s, const mwu_problem &p)
             s.x_start = xt;
         }
     }
+    std::vector<int64_t> vid;
+    int64_t nv = 0;
     if (s.level_sets) {
         // non-isolated vertex ids of the densest-subgraph graph
-        std::vector<int64_t> vid(elP.nv, -1);
-        int64_t nv = 0;
+        vid.assign(elP.nv, -1);
         for (int64_t e = 0; e < elP.ne; ++e) {
             if (vid[elP.u[e]] < 0) vid[elP.u[e]] = 0;
             if (vid[elP.v[e]] < 0) vid[elP.v[e]] = 0;
@@ -380,9 +381,14 @@ static void build(Solver &s, const mwu_problem &p)
     setup_device(s);
     const bool fused_vc = p.form == MWU_COVERING && p.C.kind == MWU_MAT_INCIDENCE_T && !p.b_C && !p.c &&
                           !(s.opt.flags & MWU_FLAG_GENERIC);
+    const bool fused_dn = s.level_sets && !p.b_P && !p.b_C && !(s.opt.flags & MWU_FLAG_GENERIC);
     if (fused_vc) {
         C = HostCSR();
         s.prog = make_vcover_program(s, elC, newid, kept);
+    } else if (fused_dn) {
+        P = HostCSR();
+        C = HostCSR();
+        s.prog = make_densest_program(s, elP, vid, nv);
     } else {
         s.prog = make_generic_program(s, s.onesP ? nullptr : &P, s.onesC ? nullptr : &C);
     }

@@ -22,13 +22,19 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["device_common.h", "engine.h", "vcover.hip", "generic.hip"]
+# sources whose text defines each kernel family (shared helpers + the program)
+KERNEL_SOURCES = {"vc_": ["device_common.h", "vcover.hip"],
+                  "k_": ["device_common.h", "generic.hip"],
+                  "kb_": ["device_common.h", "batch.hip"],
+                  "dn_": ["device_common.h", "densest.hip"]}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-def source_hash() -> str:
+def source_hash(kernel: str) -> str:
+    """Hash of the sources of `kernel`'s family (by name prefix)."""
+    files = next(v for k, v in KERNEL_SOURCES.items() if kernel.startswith(k))
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in files:
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -54,7 +60,7 @@ def summarize(fetch_dir: str, write_dir: str, kernel: str, copy_mib: int, last: 
     """Bytes per launch of `kernel` (mean over its last `last` dispatches, the
     timed repetitions of bench.py) scaled by the copy calibration."""
     copy_bytes = copy_mib * float(1 << 20)
-    rec = {"kernel": kernel, "source_sha": source_hash(), "copy_mib": copy_mib}
+    rec = {"kernel": kernel, "source_sha": source_hash(kernel), "copy_mib": copy_mib}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _rows(d, counter)
         copies = [v for _, k, v in rows if COPY_KERNEL in k]
@@ -91,7 +97,7 @@ def load_traffic(path: str, kernel: str):
                 continue
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("kernel") != kernel or rec.get("source_sha") != source_hash():
+    if rec.get("kernel") != kernel or rec.get("source_sha") != source_hash(kernel):
         return None
     try:
         return float(rec["traffic_bytes"])

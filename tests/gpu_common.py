@@ -56,10 +56,12 @@ def domset_case(g, param=None):
                 lambda p: 1.0 / p, lambda p: 1.0, param)
 
 
-def densest_case(g, param=None):
+def densest_case(g, param=None, generic=False):
     O, W, keep = oracle.densest_matrices(g)
     param = param or 1.2 * g.num_edges / keep.shape[0]
-    return Case("densest", lambda **kw: mwu.densest_subgraph(g.num_vertices, g.u, g.v, **kw), O, W,
+    flags = mwu._lib.FLAG_GENERIC if generic else 0
+    return Case("densest" + ("-generic" if generic else ""),
+                lambda **kw: mwu.densest_subgraph(g.num_vertices, g.u, g.v, flags=flags, **kw), O, W,
                 lambda p: 1.0 / p, lambda p: 1.0, param)
 
 

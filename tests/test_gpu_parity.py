@@ -47,6 +47,8 @@ def _cases():
         "domset": lambda: domset_case(pl),
         "domset-star": lambda: domset_case(gg.star_graph(6000), param=3.0),
         "densest": lambda: densest_case(gg.gnm_random(400, 3000, seed=24)),
+        "densest-generic": lambda: densest_case(gg.gnm_random(400, 3000, seed=24), generic=True),
+        "densest-powerlaw": lambda: densest_case(gg.chung_lu(3000, 2.1, 8.0, seed=25)),   # long vertex rows
         "weighted": lambda: weighted_packing_case(),
     }
 
@@ -73,9 +75,16 @@ def _per_pass(case, precision, tol, seed=0, direction=True):
         errs["x"] = rel_err(got["x"], x0)
         psi, phi, zm = s.probe_eval_steps(EXP_ALPHAS)
         psi2, phi2, zm2 = s.probe_eval_steps(LIST_ALPHAS)
-    for name, (a, b) in {"psi": (psi, ref["psi"]), "phi": (phi, ref["phi"]),
-                         "psi_list": (psi2, ref_list["psi"]), "phi_list": (phi2, ref_list["phi"])}.items():
-        errs[name] = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+    for name, (a, b, other) in {"psi": (psi, ref["psi"], ref["phi"]), "phi": (phi, ref["phi"], ref["psi"]),
+                                "psi_list": (psi2, ref_list["psi"], ref_list["phi"]),
+                                "phi_list": (phi2, ref_list["phi"], ref_list["psi"])}.items():
+        if precision == mwu.FP64:
+            scale = np.abs(b)
+        else:
+            # the mixed form is held to the scale of the test Phi >= Psi that the
+            # values feed: a Psi far below Phi may underflow in FP32 per term
+            scale = np.maximum(np.abs(b), np.abs(other))
+        errs[name] = float(np.max(np.abs(a - b) / np.maximum(scale, 1e-300)))
     errs["zmin"] = rel_err(zm, ref["zmin_new"])
     errs["zmin_list"] = rel_err(zm2, ref_list["zmin_new"])
     if not direction:
@@ -93,16 +102,19 @@ def test_per_pass_fp64(name):
     _per_pass(CASES[name](), mwu.FP64, FP64_TOL)
 
 
-@pytest.mark.parametrize("name", ["bmatch", "vcover", "vcover-star", "domset", "weighted"])
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "vcover-star", "domset", "weighted", "densest",
+                                  "densest-powerlaw"])
 def test_per_pass_mixed(name):
+    """The fused densest program forms g_i / h_i in the log domain, so its FP32
+    direction matches even where both FP32 weights underflow."""
     _per_pass(CASES[name](), mwu.MIXED_FP32_FP64, FP32_TOL)
 
 
-def test_per_pass_mixed_densest_weights():
+def test_per_pass_mixed_densest_generic_weights():
     """Generic engine on the densest-subgraph LP in the mixed form: both sides
     are exponential weights, so coordinates whose weights underflow float get
     d = 0; the weights, g and h themselves still match to float accuracy."""
-    _per_pass(CASES["densest"](), mwu.MIXED_FP32_FP64, FP32_TOL, direction=False)
+    _per_pass(CASES["densest-generic"](), mwu.MIXED_FP32_FP64, FP32_TOL, direction=False)
 
 
 def _replay(case, precision):
@@ -116,7 +128,7 @@ def _replay(case, precision):
     return info, alphas, xg, r
 
 
-@pytest.mark.parametrize("name", ["bmatch", "vcover", "domset", "densest", "weighted"])
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "domset", "densest", "densest-generic", "weighted"])
 def test_decision_replay_fp64(name):
     case = CASES[name]()
     info, alphas, xg, r = _replay(case, mwu.FP64)
@@ -133,12 +145,22 @@ def test_decision_replay_fp64(name):
     assert free.iterations == info.iterations and np.array_equal(free.alphas, alphas)
 
 
-@pytest.mark.parametrize("name", ["bmatch", "vcover", "domset"])
+# FP32 storage of x and d rounds every step by ~6e-8; with eta ~ 900 and steps
+# up to 3e5 that is ~5e-5 in the exponents of the next weights.  Rows of one
+# weight each (densest: every g_i and h_i is a single weight) carry it
+# undamped through a probe, rows that sum many weights (matching, covers)
+# average it out.
+MIXED_REPLAY_TOL = {"bmatch": 1e-5, "vcover": 1e-5, "domset": 1e-5, "densest": 2e-3}
+
+
+@pytest.mark.parametrize("name", list(MIXED_REPLAY_TOL))
 def test_decision_replay_mixed(name):
     case = CASES[name]()
     info, alphas, xg, r = _replay(case, mwu.MIXED_FP32_FP64)
     assert info.status == r.status
-    assert abs(xg.sum() - r.x.sum()) <= 1e-5 * r.x.sum()
+    err = abs(xg.sum() - r.x.sum()) / r.x.sum()
+    print(f"{name}: mixed replay objective rel err {err:.2e}")
+    assert err <= MIXED_REPLAY_TOL[name]
 
 
 def _opt_bmatch(g):
@@ -214,13 +236,15 @@ def test_solve_domset(precision):
 
 
 @pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
-def test_solve_densest(precision):
+@pytest.mark.parametrize("generic", [False, True])
+def test_solve_densest(precision, generic):
     g = gg.gnm_random(16, 34, seed=5)
     best = 0.0
     for mask in range(1, 1 << 16):
         S = np.array([(mask >> i) & 1 for i in range(16)], bool)
         best = max(best, np.sum(S[g.u] & S[g.v]) / S.sum())
-    with mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision) as s:
+    flags = mwu._lib.FLAG_GENERIC if generic else 0
+    with mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision, flags=flags) as s:
         r = s.solve()
     assert r.certified
     assert r.lower <= best * (1 + 1e-9) and best <= r.upper * (1 + 1e-9)
