@@ -106,6 +106,60 @@ def cpu_baseline(g, gpu_iters, iters=8):
             "per_iteration_s": per_iter}
 
 
+def run_densest(args):
+    """Densest subgraph (Charikar's dual, D searched) on a seeded R-MAT graph,
+    scale 22, edge factor 16: fused program, chosen form vs plain FP64.  No
+    exact optimum exists at this size; a run counts when its bracket (level-set
+    lower bound, rescaled feasible upper bound) is within 1 + eps."""
+    import torch
+    import graphgen as gg
+    import paper_2307_03307_amd as mwu
+    assert torch.cuda.is_available(), "needs an MI355X"
+    t = time.perf_counter()
+    g = gg.cached(f"rmat{args.scale}_ef{args.edge_factor}_s3",
+                  lambda: gg.rmat(args.scale, args.edge_factor, seed=3))
+    log(f"graph: {g.num_vertices} vertices, {g.num_edges} edges ({time.perf_counter() - t:.1f}s)")
+
+    def run(precision, steps, warmup):
+        t = time.perf_counter()
+        s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision)
+        create = time.perf_counter() - t
+        walls, r = [], None
+        for i in range(warmup + steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = s.solve()
+            w = time.perf_counter() - t
+            if i >= warmup:
+                walls.append(w)
+            log(f"  precision={precision} densest solve {i}: {w:.3f}s obj={r.objective:.4f} "
+                f"[{r.lower:.4f}, {r.upper:.4f}] status={r.status} iters={r.total_iterations} "
+                f"probes={r.probes} passes={r.search_passes}")
+        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper))
+        s.close()
+        return create, walls, r, passes
+
+    c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, args.steps, args.warmup)
+    c64, w64, r64, p64 = run(mwu.FP64, 1, 0)
+    t32 = statistics.mean(w32)
+    out = {
+        "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * t32, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"densest subgraph LP (Charikar dual, D searched), R-MAT scale {args.scale}, "
+                               f"edge factor {args.edge_factor}, a/b/c=0.57/0.19/0.19, seed 3, eps=0.1",
+                   "vertices": g.num_vertices, "edges": g.num_edges, "variables": 2 * g.num_edges},
+        "certified": r32.certified, "objective": r32.objective, "bracket": [r32.lower, r32.upper],
+        "iterations": r32.total_iterations, "probes": r32.probes, "create_s": c32,
+        "fp64_plain_s": statistics.mean(w64), "fp64_certified": r64.certified,
+        "fp64_bracket": [r64.lower, r64.upper], "fp64_iterations": r64.total_iterations,
+        "speedup_vs_fp64": statistics.mean(w64) / t32,
+        "passes": {PASS_NAMES[k]: v for k, v in p32.items()},
+        "passes_fp64": {PASS_NAMES[k]: v for k, v in p64.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args):
     """Batched bipartite matching: 512 uneven instances (sides uniform in
     [1024, 65536], mean degree uniform in [4, 16]) solved together, against
@@ -206,8 +260,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--pass-reps", type=int, default=50)
-    ap.add_argument("--workload", choices=["vcover", "batched"], default="vcover",
-                    help="vcover: the headline R-MAT vertex cover; batched: 512 matching LPs")
+    ap.add_argument("--workload", choices=["vcover", "batched", "densest"], default="vcover",
+                    help="vcover: the headline R-MAT vertex cover; batched: 512 matching LPs; "
+                         "densest: R-MAT densest subgraph (use --scale 22)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--loop-sample", type=int, default=16)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -220,6 +275,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "densest":
+        run_densest(args)
         return
 
     import torch

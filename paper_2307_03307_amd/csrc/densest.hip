@@ -15,6 +15,8 @@
 // g_i / h_i = exp(eta (y_v - L_P) + eta (z_e - L_C) + ln(sP / sC)), with L_P and
 // L_C the LSE totals of the current point.
 // FP64 keeps the plain ratio of the stored weights, as the definition reads.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace mwu {
@@ -222,14 +224,21 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
         const int r = (i & 1) ? dd.ev[e] : dd.eu[e];
         const T x = dd.x[i] + a * dd.d[i];
         dd.x[i] = x;
-        const double g = sP * (double)dd.w[r] * invSw;
-        const double h = sC * (double)dd.u[e] * invSu;
+        // g and h from the stored weights: the FP64 direction and the
+        // certificates; the FP32 direction needs only y and z (below), and the
+        // densest outer search uses no weak-duality bound, so FP32 skips them
+        // unless they are being recorded
+        const bool need_gh = sizeof(T) == 8 || dd.g_dbg != nullptr;
+        const double g = need_gh ? sP * (double)dd.w[r] * invSw : INFINITY;
+        const double h = need_gh ? sC * (double)dd.u[e] * invSu : -INFINITY;
         double q;
         if (sizeof(T) == 4) {
             // log-domain ratio: no underflow of the FP32 weights, and
             // q = 1 - g/h = -expm1(ln(g/h)) without cancellation near g = h
+            // (FP32 expm1 of the FP64 log ratio: ~1e-7 relative in q, the
+            // precision the FP32 direction is stored in)
             const double lr = eta * (dd.y[r] - LP) + eta * (dd.z[e] - LC) + lnK;
-            q = -expm1(lr);
+            q = -(double)expm1_t((float)fmin(lr, 80.0));
         } else {
             q = h > 0.0 ? 1.0 - g / h : 0.0;
         }
@@ -423,6 +432,40 @@ __global__ __launch_bounds__(BLOCK) void dn_stats_fin(DnDev<T> dd, Ctl *ctl, con
     }
 }
 
+// ------------------------------------------------------------------ level sets
+
+// For the level-set rounding of the outer search: back[v] = number of
+// neighbours of v ranked before v (rank by descending load).  The edges of the
+// top-k vertices are then the prefix sums of back in rank order.  One wave per
+// vertex, no atomics.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void dn_backcount(DnDev<T> dd, const int32_t *rank, int32_t *back)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * BLOCK + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * BLOCK) >> 6;
+    for (int v = wave; v < dd.nv; v += nwaves) {
+        const int rv = rank[v];
+        int c = 0;
+        for (int q = dd.vptr[v] + lane; q < dd.vptr[v + 1]; q += 64) {
+            const int var = dd.vvar[q];
+            const int e = var >> 1;
+            const int w = (var & 1) ? dd.eu[e] : dd.ev[e];   // the other end of the edge
+            c += rank[w] < rv;
+        }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m);
+        if (lane == 0) back[v] = c;
+    }
+}
+
+template <class T>
+void dn_backcounts(const DnDev<T> &dd, const int32_t *rank, int32_t *back, hipStream_t st)
+{
+    const int grid = std::max(1, std::min(GRID_MAX * 4, (dd.nv + 3) / 4));
+    DLAUNCH(dn_backcount<T>, grid, dd, rank, back);
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <class T>
@@ -517,7 +560,8 @@ void dn_occupancy(int *per_cu_vt, int *per_cu_search)
     template void dn_iteration<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);             \
     template void dn_stats<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t);                 \
     template void dn_main<T>(const DnDev<T> &, Ctl *, const DnLaunch &, hipStream_t, int);             \
-    template void dn_occupancy<T>(int *, int *);
+    template void dn_occupancy<T>(int *, int *);                                                      \
+    template void dn_backcounts<T>(const DnDev<T> &, const int32_t *, int32_t *, hipStream_t);
 
 MWU_DN_INSTANTIATE(float)
 MWU_DN_INSTANTIATE(double)

@@ -193,6 +193,7 @@ template <class T> void dn_iteration(const DnDev<T> &dd, Ctl *ctl, const DnLaunc
 template <class T> void dn_stats(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st);
 template <class T> void dn_main(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st, int which);
 template <class T> void dn_occupancy(int *per_cu_vt, int *per_cu_search);
+template <class T> void dn_backcounts(const DnDev<T> &dd, const int32_t *rank, int32_t *back, hipStream_t st);
 
 // Batched matching program: many independent packing LPs max 1^T x s.t.
 // M_k x <= 1 (bipartite matching, Section 3) in concatenated arrays.  Tiles

@@ -89,6 +89,9 @@ struct Program {
     // 2 forward, 3 search): every index once, every dense vector once, every output once.
     virtual double algo_bytes(int which) const = 0;
     virtual double pass_nnz(int which) const = 0;
+    // Level-set rounding of the current vertex loads (densest subgraph):
+    // false when the program has no such structure (the host computes it).
+    virtual bool level_set_density(double *) { return false; }
 };
 
 // Many independent problems solved together (the batched programs).

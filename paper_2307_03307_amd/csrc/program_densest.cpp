@@ -185,6 +185,56 @@ class DensestProgram : public Program {
     }
     double pass_nnz(int which) const override { return which == 2 ? 2.0 * (double)ne_ : 0.0; }
 
+    // Largest density |E(S_k)| / k over the prefixes S_k of the vertices in
+    // descending load (ties to the smaller id): the level-set rounding that
+    // gives the outer search its lower bound.  Ranks come from a stable LSD
+    // radix sort of the loads on the host; the number of edges of every prefix
+    // is the prefix sum, in rank order, of each vertex's neighbours ranked
+    // before it, counted on the device.
+    bool level_set_density(double *out) override
+    {
+        const int64_t nv = nv_;
+        std::vector<double> load(nv);
+        copy_host(dd_.y, nv, load.data());
+        std::vector<uint64_t> key(nv), k2(nv);
+        std::vector<int32_t> id(nv), id2(nv);
+        for (int64_t v = 0; v < nv; ++v) {
+            uint64_t b;
+            const double l = load[v] > 0.0 ? load[v] : 0.0;
+            std::memcpy(&b, &l, 8);
+            key[v] = ~b;              // non-negative doubles order as their bits; ~ for descending
+            id[v] = (int32_t)v;
+        }
+        for (int shift = 0; shift < 64; shift += 16) {   // stable: ties keep id order
+            std::vector<int64_t> cnt(65537, 0);
+            for (int64_t v = 0; v < nv; ++v) cnt[((key[v] >> shift) & 0xffff) + 1]++;
+            for (int b = 0; b < 65536; ++b) cnt[b + 1] += cnt[b];
+            for (int64_t v = 0; v < nv; ++v) {
+                const int64_t p = cnt[(key[v] >> shift) & 0xffff]++;
+                k2[p] = key[v];
+                id2[p] = id[v];
+            }
+            key.swap(k2);
+            id.swap(id2);
+        }
+        std::vector<int32_t> rank(nv);
+        for (int64_t r = 0; r < nv; ++r) rank[id[r]] = (int32_t)r;
+        if (!rank_.p) { rank_.alloc(nv * 4); back_.alloc(nv * 4); }
+        HIP_OK(hipMemcpyAsync(rank_.p, rank.data(), nv * 4, hipMemcpyHostToDevice, s_.stream));
+        dn_backcounts<T>(dd_, rank_.as<int32_t>(), back_.as<int32_t>(), s_.stream);
+        std::vector<int32_t> back(nv);
+        HIP_OK(hipMemcpyAsync(back.data(), back_.p, nv * 4, hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        double best = 0.0;
+        int64_t edges = 0;
+        for (int64_t r = 0; r < nv; ++r) {
+            edges += back[id[r]];
+            best = std::max(best, (double)edges / (double)(r + 1));
+        }
+        *out = best;
+        return true;
+    }
+
   private:
     DnDev<T> dbg() const
     {
@@ -218,6 +268,7 @@ class DensestProgram : public Program {
     DnLaunch L_{};
     DevBuf eu_, ev_, vptr_, vvar_, vtiles_, lseg_, lfirst_, lcount_, lpart_, lpart64_;
     DevBuf x_, d_, xbest_, y_, dy_, w_, z_, dz_, u_, partials_, partials2_, forced_, dbg_g_, dbg_h_;
+    DevBuf rank_, back_;
 };
 
 std::unique_ptr<Program> make_densest_program(Solver &s, const EdgeList &el, const std::vector<int64_t> &vid,

@@ -604,9 +604,13 @@ static SolveOut solve_impl(Solver &s)
         } else {
             if (s.form == MWU_COVERING && c.cover_bound > lo) lo = c.cover_bound;
             if (s.level_sets) {
-                std::vector<double> load(s.prog->mP());
-                s.prog->read(4, load.data(), (int64_t)load.size());
-                lo = std::max(lo, level_set_density(s.dens_graph, load));
+                double lsd = 0.0;
+                if (!s.prog->level_set_density(&lsd)) {
+                    std::vector<double> load(s.prog->mP());
+                    s.prog->read(4, load.data(), (int64_t)load.size());
+                    lsd = level_set_density(s.dens_graph, load);
+                }
+                lo = std::max(lo, lsd);
             }
             if (feasible) {
                 const double val = s.form == MWU_COVERING ? f.sumx / f.zmin : (f.ymax / f.sP) / f.zmin;
