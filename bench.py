@@ -179,10 +179,12 @@ def run_batched(args):
     log(f"batch: {len(gs)} instances, {V} vertices, {E} edges ({time.perf_counter() - t:.1f}s)")
     spec = [(g.num_vertices, g.u, g.v) for g in gs]
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, tune=True):
         t = time.perf_counter()
-        b = mwu.BatchSolver(spec, precision=precision)
+        b = mwu.BatchSolver(spec, precision=precision, tune=tune)
         create = time.perf_counter() - t
+        layout = b.layout()
+        log(f"  precision={precision} create {create:.2f}s layout {layout}")
         walls, res = [], None
         for i in range(warmup + steps):
             torch.cuda.synchronize()
@@ -196,10 +198,11 @@ def run_batched(args):
             log(f"  precision={precision} batch solve {i}: {w:.3f}s certified {cert}/{len(res)} "
                 f"iterations {its} max probe count {max(r.probes for r in res)}")
         b.close()
-        return create, walls, res
+        return create, walls, res, layout
 
-    c32, w32, r32 = run(mwu.MIXED_FP32_FP64, args.steps, args.warmup)
-    c64, w64, r64 = run(mwu.FP64, 1, 0)
+    c32, w32, r32, lay32 = run(mwu.MIXED_FP32_FP64, args.steps, args.warmup)
+    c64, w64, r64, lay64 = run(mwu.FP64, 1, 0)
+    _, wdef, _, _ = run(mwu.MIXED_FP32_FP64, 1, 0, tune=False)
     # exact optima of a sample (Hopcroft-Karp; the bipartite matching LP is integral)
     sample = list(range(0, len(gs), max(1, len(gs) // 8)))
     ok = 0
@@ -240,6 +243,11 @@ def run_batched(args):
         "exact_optimum_in_bracket": f"{ok}/{len(sample)}",
         "iterations": sum(r.total_iterations for r in r32),
         "create_s": c32,
+        "layout": {k: lay32[k] for k in ("tile_edges", "tile_vertices", "workgroups_per_cu",
+                                         "search_launches", "source", "candidates_timed")},
+        "default_layout_s": wdef[0],
+        "layout_fp64": {k: lay64[k] for k in ("tile_edges", "tile_vertices", "workgroups_per_cu",
+                                              "search_launches")},
         "fp64_batched_s": statistics.mean(w64),
         "fp64_batched_certified": sum(r.certified for r in r64),
         "fp64_loop_s": loop_s,

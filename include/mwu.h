@@ -120,6 +120,7 @@ typedef struct {
 
 #define MWU_FLAG_NO_FACTOR2   1u  /* do not double the step when one side is a single row */
 #define MWU_FLAG_GENERIC      2u  /* force the generic CSR engine (no fused graph program) */
+#define MWU_FLAG_NO_TUNE      4u  /* batched: take the default layout, time nothing */
 
 typedef struct {
     double eps;                 /* accuracy, default 0.1 (Section 6.2) */
@@ -132,6 +133,8 @@ typedef struct {
     void *hip_stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
     double mixed_fixed_lambda;  /* MWU_MIXED: > 0 runs one feasibility probe at this lambda */
     uint64_t flags;
+    const char *tune_cache;     /* batched: text file of tuned layouts, read and appended;
+                                   NULL = layouts are remembered for the process only */
 } mwu_options;
 
 typedef struct {
@@ -161,6 +164,46 @@ mwu_status mwu_create(const mwu_problem *prob, const mwu_options *opt, void **ou
  * matchings).  Variables and results are concatenated in problem order. */
 mwu_status mwu_create_batch(const mwu_problem *probs, int32_t count, const mwu_options *opt,
                             void **out);
+
+/* ---------------------------------------------------------------------------
+ * Layout of a batched handle and its autotuner.  The batched passes visit
+ * edge tiles (start, column and statistics passes), element tiles of vertex
+ * rows (row and search passes) and nnz-balanced vertex tiles (forward
+ * product, fixed at BLOCK x 8 nonzeros) with persistent grids.  At
+ * mwu_create_batch the layout is chosen by timed sweeps over the batch itself
+ * (one coordinate-descent pass over the four fields below; each candidate
+ * runs the whole batched solve from its start for 0.4 s, host polling and
+ * probe turnovers included, and is rated by the edge-iterations completed per
+ * second), unless MWU_FLAG_NO_TUNE is set or a layout for the same device,
+ * precision and batch shape is listed in opt->tune_cache or already known to
+ * the process.  A sweep costs about 8 such windows at create.
+ * ------------------------------------------------------------------------- */
+
+#define MWU_LAYOUT_DEFAULT 0   /* built-in layout, nothing timed */
+#define MWU_LAYOUT_TUNED   1   /* chosen by a sweep at create */
+#define MWU_LAYOUT_CACHED  2   /* a sweep's result, found in memory or in the cache file */
+#define MWU_LAYOUT_SET     3   /* set by mwu_batch_set_layout */
+
+typedef struct {
+    int32_t tile_edges;          /* edges per edge tile: multiple of 256 in [256, 65536] */
+    int32_t tile_vertices;       /* vertices per element tile: multiple of 256 in [256, 65536] */
+    int32_t workgroups_per_cu;   /* cap on resident persistent workgroups per CU: 1..16 */
+    int32_t search_launches;     /* step-search passes launched per iteration slot: 1..4 */
+    int32_t source;              /* MWU_LAYOUT_* (output only) */
+    int32_t candidates_timed;    /* layouts timed by the sweep at create (output only) */
+    double edge_iters_per_sec;   /* sweep rating of this layout, 0 when not timed (output only) */
+} mwu_batch_layout;
+
+/* Current layout of a batched handle.  MWU_ERR_STATE for a single-problem
+ * handle, MWU_ERR_INVALID_ARG for NULL arguments. */
+mwu_status mwu_batch_get_layout(void *s, mwu_batch_layout *out);
+
+/* Replace the layout of a batched handle (the first four fields; the rest
+ * are ignored).  Rebuilds the tile lists and the captured launch sequence;
+ * results of later solves are those of the new layout (the same method, with
+ * sums reduced in another order).  MWU_ERR_INVALID_ARG for values outside the
+ * ranges above, MWU_ERR_STATE for a single-problem handle. */
+mwu_status mwu_batch_set_layout(void *s, const mwu_batch_layout *layout);
 
 /* Run the outer search (or the single fixed-lambda probe).
  * x_out: nullable, host, length = number of variables of the problem (batch:

@@ -246,7 +246,8 @@ class BatchSolver:
 
     def __init__(self, graphs, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
                  step_rule: int = STEP_BIN, precision: int = MIXED_FP32_FP64, device: int = 0,
-                 flags: int = 0):
+                 flags: int = 0, iters_per_launch: int = 0, tune: bool = True,
+                 tune_cache: Optional[str] = None):
         L = _lib.load()
         self._L = L
         mats = [incidence(nv, u, v) for (nv, u, v) in graphs]
@@ -259,7 +260,11 @@ class BatchSolver:
         opt = _lib.Options()
         L.mwu_default_options(ctypes.byref(opt))
         opt.eps, opt.max_iter, opt.max_probes = eps, max_iter, max_probes
-        opt.step_rule, opt.precision, opt.device, opt.flags = step_rule, precision, device, flags
+        opt.step_rule, opt.precision, opt.device = step_rule, precision, device
+        opt.flags = flags | (0 if tune else _lib.FLAG_NO_TUNE)
+        opt.iters_per_launch = iters_per_launch
+        self._cache = tune_cache.encode() if tune_cache else None   # kept alive for the call
+        opt.tune_cache = self._cache
         h = ctypes.c_void_p()
         _lib.check(L.mwu_create_batch(arr, len(mats), ctypes.byref(opt), ctypes.byref(h)),
                    "mwu_create_batch")
@@ -268,6 +273,17 @@ class BatchSolver:
     @property
     def count(self) -> int:
         return len(self._sizes)
+
+    def layout(self) -> dict:
+        """The handle's layout (``mwu_batch_get_layout``) as a dict."""
+        lay = _lib.BatchLayout()
+        _lib.check(self._L.mwu_batch_get_layout(self._h, ctypes.byref(lay)), "mwu_batch_get_layout")
+        return {f: getattr(lay, f) for f, _ in _lib.BatchLayout._fields_}
+
+    def set_layout(self, tile_edges: int, tile_vertices: int, workgroups_per_cu: int,
+                   search_launches: int) -> None:
+        lay = _lib.BatchLayout(tile_edges, tile_vertices, workgroups_per_cu, search_launches, 0, 0, 0.0)
+        _lib.check(self._L.mwu_batch_set_layout(self._h, ctypes.byref(lay)), "mwu_batch_set_layout")
 
     def solve(self):
         """List of per-instance Results (x per instance, in edge order)."""

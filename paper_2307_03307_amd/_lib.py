@@ -21,13 +21,15 @@ PACKING, COVERING, MIXED = 0, 1, 2
 MAT_CSR, MAT_INCIDENCE, MAT_INCIDENCE_T, MAT_EDGE_PAIR, MAT_INTERWEAVE = 0, 1, 2, 3, 4
 STEP_STD, STEP_BIN = 0, 1
 FP64, MIXED_FP32_FP64 = 0, 1
-FLAG_NO_FACTOR2, FLAG_GENERIC = 1, 2
+FLAG_NO_FACTOR2, FLAG_GENERIC, FLAG_NO_TUNE = 1, 2, 4
+LAYOUT_DEFAULT, LAYOUT_TUNED, LAYOUT_CACHED, LAYOUT_SET = 0, 1, 2, 3
 
 EXPORTED = [
     "mwu_default_options", "mwu_create", "mwu_create_batch", "mwu_solve", "mwu_destroy",
     "mwu_status_string", "mwu_num_variables", "mwu_probe_sizes", "mwu_probe_begin",
     "mwu_probe_run", "mwu_probe_direction", "mwu_probe_read", "mwu_probe_eval_steps",
     "mwu_potential_forward", "mwu_potential_backward", "mwu_time_pass",
+    "mwu_batch_get_layout", "mwu_batch_set_layout",
 ]
 
 
@@ -55,7 +57,15 @@ class Options(ctypes.Structure):
                 ("max_probes", ctypes.c_int32), ("step_rule", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
-                ("mixed_fixed_lambda", ctypes.c_double), ("flags", ctypes.c_uint64)]
+                ("mixed_fixed_lambda", ctypes.c_double), ("flags", ctypes.c_uint64),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+class BatchLayout(ctypes.Structure):
+    _fields_ = [("tile_edges", ctypes.c_int32), ("tile_vertices", ctypes.c_int32),
+                ("workgroups_per_cu", ctypes.c_int32), ("search_launches", ctypes.c_int32),
+                ("source", ctypes.c_int32), ("candidates_timed", ctypes.c_int32),
+                ("edge_iters_per_sec", ctypes.c_double)]
 
 
 class ResultInfo(ctypes.Structure):
@@ -111,6 +121,8 @@ def load() -> ctypes.CDLL:
     L.mwu_potential_forward.argtypes = [vp, vp, vp, vp]
     L.mwu_potential_backward.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     L.mwu_time_pass.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    L.mwu_batch_get_layout.argtypes = [vp, P(BatchLayout)]
+    L.mwu_batch_set_layout.argtypes = [vp, P(BatchLayout)]
     for name in EXPORTED:
         fn = getattr(L, name)
         if fn.restype is ctypes.c_int:  # default restype

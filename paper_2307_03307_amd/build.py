@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmwu.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["generic.hip", "vcover.hip", "batch.hip", "densest.hip", "program_generic.cpp",
-           "program_vcover.cpp", "program_batch.cpp", "program_densest.cpp", "solver.cpp"]
+           "program_vcover.cpp", "program_batch.cpp", "program_densest.cpp", "autotune.cpp", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -7,8 +7,8 @@
 // phases of their own probes at the same time; each kernel visits the tiles
 // of the instances that are in its phase and skips the others.  The iteration
 // slot launched (and captured in a hipGraph) is
-//   init-x, init-y (probe start), row, column, forward, search, search,
-//   statistics (probe end)
+//   init-x, init-y (probe start), row, column, forward, search (one or more
+//   passes), statistics (probe end)
 // with one finisher per pass that runs one workgroup per instance.  The host
 // drives only the outer search over M_k from a compact status array.
 #include <algorithm>
@@ -495,10 +495,10 @@ void batch_slots(const BatchDev<T> &b, const BLaunch &L, int slots, hipStream_t 
         BLAUNCH(kb_col_fin<T>, b.nb);
         BLAUNCH(kb_vfwd<T>, L.grid_v);       // FWD instances
         BLAUNCH(kb_vfwd_fin<T>, b.nb);
-        BLAUNCH(kb_search<T>, L.grid_w);
-        BLAUNCH(kb_search_fin<T>, b.nb);
-        BLAUNCH(kb_search<T>, L.grid_w);
-        BLAUNCH(kb_search_fin<T>, b.nb);
+        for (int j = 0; j < L.nsearch; ++j) {
+            BLAUNCH(kb_search<T>, L.grid_w);
+            BLAUNCH(kb_search_fin<T>, b.nb);
+        }
         BLAUNCH(kb_stats_v<T>, L.grid_v);
         BLAUNCH(kb_stats_e<T>, L.grid_e);
         BLAUNCH(kb_stats_fin<T>, b.nb);

@@ -233,6 +233,7 @@ struct BatchDev {
 
 struct BLaunch {
     int grid_v, grid_e, grid_w;           // persistent grids over vertex / edge / element tiles
+    int nsearch;                          // search passes launched per iteration slot
 };
 
 template <class T> void batch_slots(const BatchDev<T> &b, const BLaunch &L, int slots, hipStream_t st);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -102,7 +103,23 @@ struct BatchProgram {
     // x_out: concatenated variables of all instances (nullable); obj_out and
     // info: one entry per instance (nullable); iters_out: total iterations.
     virtual void solve(double *x_out, double *obj_out, int64_t *iters_out, mwu_result_info *info) = 0;
+    virtual mwu_batch_layout layout() const = 0;
+    virtual void set_layout(const mwu_batch_layout &L) = 0;   // L already validated
 };
+
+// Autotuner of batched layouts (autotune.cpp).
+bool layout_valid(const mwu_batch_layout &L);
+mwu_batch_layout default_layout();
+std::string tune_key(const char *program, bool fp32, int device, int num_cus, int32_t count, int64_t nv,
+                     int64_t ne, int64_t max_ne);
+bool tune_lookup(const std::string &key, const char *path, mwu_batch_layout *L, double *rate);
+void tune_store(const std::string &key, const char *path, const mwu_batch_layout &L, double rate);
+// One coordinate-descent pass over the fields in order (tile_edges,
+// tile_vertices, workgroups_per_cu, search_launches); cands[f] lists the
+// values tried for field f; rate() times a layout (higher is better).
+mwu_batch_layout tune_descent(const mwu_batch_layout &start, const std::vector<std::vector<int32_t>> &cands,
+                              const std::function<double(const mwu_batch_layout &)> &rate, int *timed,
+                              double *best_rate);
 
 struct Solver {
     mwu_options opt{};

@@ -13,8 +13,7 @@ namespace mwu {
 
 namespace {
 
-constexpr int kTileE = BLOCK * 8;    // edges per edge tile
-constexpr int kTileW = BLOCK * 16;   // vertices per element tile (row and search passes)
+constexpr double kTuneSeconds = 0.4;   // timed window per candidate layout
 constexpr double kMixedQminB = 1.0 / 65536.0;
 constexpr int kMaxHalvingsB = 2;
 
@@ -40,9 +39,8 @@ class BatchMatching : public BatchProgram {
         inst_.resize(count);
         std::vector<int32_t> eu, ev, vptr(1, 0), vedge;
         std::vector<BTile> vt, et;
-        std::vector<int32_t> vrec0(count), vrecn(count), erec0(count), erecn(count), nedge(count);
-        std::vector<int32_t> lrec0(count), lrecn(count), lseg, lfirst, lcount, wrec0(count), wrecn(count);
-        std::vector<BTile> wt;
+        std::vector<int32_t> vrec0(count), vrecn(count), nedge(count);
+        std::vector<int32_t> lrec0(count), lrecn(count), lseg, lfirst, lcount;
         int32_t nslots = 0;
         int64_t V = 0, E = 0;
         for (int32_t k = 0; k < count; ++k) {
@@ -111,16 +109,7 @@ class BatchMatching : public BatchProgram {
             }
             vrecn[k] = (int32_t)vt.size() - vrec0[k];
             lrecn[k] = (int32_t)lseg.size() - lrec0[k];
-            wrec0[k] = (int32_t)wt.size();
-            for (int64_t i = 0; i < kept; i += kTileW)
-                wt.push_back(BTile{k, (int32_t)(V + i), (int32_t)(V + std::min<int64_t>(i + kTileW, kept)),
-                                   0, 0, -1, 0, 0});
-            wrecn[k] = (int32_t)wt.size() - wrec0[k];
-            erec0[k] = (int32_t)et.size();
-            for (int64_t i = 0; i < ne; i += kTileE)
-                et.push_back(BTile{k, (int32_t)(E + i), (int32_t)(E + std::min<int64_t>(i + kTileE, ne)),
-                                   0, 0, -1, 0, 0});
-            erecn[k] = (int32_t)et.size() - erec0[k];
+            max_ne_ = std::max(max_ne_, ne);
             // outer-search bracket (as for any packing LP with unit entries):
             // hi = sum_i 1 / min_j P_ji = |E|; lo from the rescaled Algorithm 1 point
             I.hi0 = (double)ne;
@@ -140,17 +129,10 @@ class BatchMatching : public BatchProgram {
         up(vptr_, vptr.data(), vptr.size() * 4);
         up(vedge_, vedge.data(), vedge.size() * 4);
         up(vt_, vt.data(), vt.size() * sizeof(BTile));
-        up(et_, et.data(), et.size() * sizeof(BTile));
         up(vrec0_, vrec0.data(), count * 4);
         up(vrecn_, vrecn.data(), count * 4);
-        up(erec0_, erec0.data(), count * 4);
-        up(erecn_, erecn.data(), count * 4);
         up(nedge_, nedge.data(), count * 4);
         up(lrec0_, lrec0.data(), count * 4);
-        up(wt_, wt.data(), wt.size() * sizeof(BTile));
-        up(wrec0_, wrec0.data(), count * 4);
-        up(wrecn_, wrecn.data(), count * 4);
-        wpart_.alloc(wt.size() * QMAX * 8);
         up(lrecn_, lrecn.data(), count * 4);
         up(lseg_, lseg.data(), lseg.size() * 4);
         up(lfirst_, lfirst.data(), lfirst.size() * 4);
@@ -164,7 +146,6 @@ class BatchMatching : public BatchProgram {
         dy_.alloc(V * sizeof(T));
         w_.alloc(V * sizeof(T));
         vpart_.alloc(vt.size() * QMAX * 8);
-        epart_.alloc(et.size() * QMAX * 8);
         ctl_.alloc((size_t)count * sizeof(Ctl));
         stat_.alloc((size_t)count * 16);
         HIP_OK(hipMemset(ctl_.p, 0, ctl_.bytes));
@@ -180,29 +161,20 @@ class BatchMatching : public BatchProgram {
         bd_.eu = eu_.as<int32_t>(); bd_.ev = ev_.as<int32_t>();
         bd_.x = x_.as<T>(); bd_.d = d_.as<T>();
         bd_.y = y_.as<T>(); bd_.dy = dy_.as<T>(); bd_.w = w_.as<T>();
-        bd_.vt = vt_.as<BTile>(); bd_.et = et_.as<BTile>();
-        bd_.nvt = (int32_t)vt.size(); bd_.net = (int32_t)et.size();
+        bd_.vt = vt_.as<BTile>();
+        bd_.nvt = (int32_t)vt.size();
         bd_.vrec0 = vrec0_.as<int32_t>(); bd_.vrecn = vrecn_.as<int32_t>();
-        bd_.erec0 = erec0_.as<int32_t>(); bd_.erecn = erecn_.as<int32_t>();
         bd_.nedge = nedge_.as<int32_t>();
         bd_.vlong = LongSegs{lseg_.as<int32_t>(), lfirst_.as<int32_t>(), lcount_.as<int32_t>(),
                              (int32_t)lseg.size()};
         bd_.lrec0 = lrec0_.as<int32_t>(); bd_.lrecn = lrecn_.as<int32_t>();
-        bd_.wt = wt_.as<BTile>(); bd_.nwt = (int32_t)wt.size();
-        bd_.wrec0 = wrec0_.as<int32_t>(); bd_.wrecn = wrecn_.as<int32_t>();
-        bd_.wpart = wpart_.as<double>();
         bd_.lpart = lpart_.as<T>(); bd_.lpart64 = lpart64_.as<double>();
         bd_.ctl = ctl_.as<Ctl>();
         bd_.stat = stat_.as<int32_t>();
-        bd_.vpart = vpart_.as<double>(); bd_.epart = epart_.as<double>();
-        int occ_v = 1, occ_e = 1;
-        batch_occupancy<T>(&occ_v, &occ_e);
-        auto grid = [&](int64_t tiles, int occ) {
-            return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, (int64_t)occ * s.num_cus, (int64_t)65535}));
-        };
-        L_.grid_v = grid(bd_.nvt, occ_v);
-        L_.grid_w = grid(bd_.nwt, occ_e);
-        L_.grid_e = grid(bd_.net, occ_e);
+        bd_.vpart = vpart_.as<double>();
+        batch_occupancy<T>(&occ_v_, &occ_e_);
+        slots_ = s.opt.iters_per_launch > 0 ? s.opt.iters_per_launch : 8;
+        choose_layout();
     }
 
     ~BatchMatching() override
@@ -214,59 +186,23 @@ class BatchMatching : public BatchProgram {
 
     int32_t count() const override { return nb_; }
     int64_t total_variables() const override { return ne_; }
+    mwu_batch_layout layout() const override { return layout_; }
+
+    void set_layout(const mwu_batch_layout &L) override
+    {
+        relayout(L);
+        layout_.source = MWU_LAYOUT_SET;
+        layout_.candidates_timed = 0;
+        layout_.edge_iters_per_sec = 0.0;
+    }
 
     void solve(double *x_out, double *obj_out, int64_t *iters_out, mwu_result_info *info) override
     {
         const auto t0 = std::chrono::steady_clock::now();
         const double eps = s_.opt.eps;
-        for (int32_t k = 0; k < nb_; ++k) {
-            Inst &I = inst_[k];
-            I.lo = I.lo0; I.hi = I.hi0;
-            I.slo = I.lo; I.shi = I.hi; I.eps_probe = eps; I.halvings = 0; I.probes = 0;
-            I.iters = I.passes = I.final_iters = 0;
-            I.done = false; I.have_best = false; I.failed = false; I.best_scale = 1.0;
-            I.max_violation = 0.0;
-            if (!next_probe(k)) I.done = true;
-        }
-        push_state();
+        start_all();
         ensure_graph();
-        int64_t launches = 0;
-        const int64_t cap = ((int64_t)s_.opt.max_probes * (s_.opt.max_iter + 8) * 4) / std::max(1, slots_) + 64;
-        std::vector<int32_t> finished;
-        std::vector<int32_t> last((size_t)nb_ * 4, -1);
-        int stalled = 0;
-        while (true) {
-            int active = 0;
-            for (const Inst &I : inst_) active += !I.done;
-            if (!active) break;
-            if (launches++ > cap) throw ApiError{MWU_ERR_DEVICE, "batched solve did not finish"};
-            HIP_OK(hipGraphLaunch(graph_, s_.stream));
-            HIP_OK(hipMemcpyAsync(stat_host_, stat_.p, (size_t)nb_ * 16, hipMemcpyDeviceToHost, s_.stream));
-            HIP_OK(hipStreamSynchronize(s_.stream));
-            // every running instance advances its phase or iteration in a launch
-            if (std::equal(last.begin(), last.end(), stat_host_)) {
-                if (++stalled > 64) throw ApiError{MWU_ERR_DEVICE, "batched solve makes no progress"};
-            } else {
-                stalled = 0;
-                std::copy(stat_host_, stat_host_ + (size_t)nb_ * 4, last.begin());
-            }
-            finished.clear();
-            for (int32_t k = 0; k < nb_; ++k) {
-                const Inst &I = inst_[k];
-                if (I.done) continue;
-                if (stat_host_[4 * k] == PH_IDLE && stat_host_[4 * k + 3] == I.serial) finished.push_back(k);
-            }
-            if (finished.empty()) continue;
-            HIP_OK(hipMemcpyAsync(ctl_host_, ctl_.p, (size_t)nb_ * sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
-            HIP_OK(hipStreamSynchronize(s_.stream));
-            for (int32_t k : finished) {
-                probe_outcome(k);
-                if (!inst_[k].done && !next_probe(k)) inst_[k].done = true;
-            }
-            // nothing runs between the pull above and this push (one stream), so
-            // the blocks of running instances go back unchanged
-            push_state();
-        }
+        drive(INFINITY);
         HIP_OK(hipStreamSynchronize(s_.stream));
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         // outputs
@@ -302,6 +238,183 @@ class BatchMatching : public BatchProgram {
     }
 
   private:
+    // The outer search of every instance: launch the captured slots, poll the
+    // status array, hand finished probes to the host rules and start the next
+    // ones, until every search is over or the wall-clock limit has passed
+    // (false then).
+    bool drive(double seconds)
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        int64_t launches = 0;
+        const int64_t cap = ((int64_t)s_.opt.max_probes * (s_.opt.max_iter + 8) * 4) / std::max(1, slots_) + 64;
+        std::vector<int32_t> finished;
+        std::vector<int32_t> last((size_t)nb_ * 4, -1);
+        int stalled = 0;
+        while (true) {
+            int active = 0;
+            for (const Inst &I : inst_) active += !I.done;
+            if (!active) return true;
+            if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > seconds)
+                return false;
+            if (launches++ > cap) throw ApiError{MWU_ERR_DEVICE, "batched solve did not finish"};
+            HIP_OK(hipGraphLaunch(graph_, s_.stream));
+            HIP_OK(hipMemcpyAsync(stat_host_, stat_.p, (size_t)nb_ * 16, hipMemcpyDeviceToHost, s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            // every running instance advances its phase or iteration in a launch
+            if (std::equal(last.begin(), last.end(), stat_host_)) {
+                if (++stalled > 64) throw ApiError{MWU_ERR_DEVICE, "batched solve makes no progress"};
+            } else {
+                stalled = 0;
+                std::copy(stat_host_, stat_host_ + (size_t)nb_ * 4, last.begin());
+            }
+            finished.clear();
+            for (int32_t k = 0; k < nb_; ++k) {
+                const Inst &I = inst_[k];
+                if (I.done) continue;
+                if (stat_host_[4 * k] == PH_IDLE && stat_host_[4 * k + 3] == I.serial) finished.push_back(k);
+            }
+            if (finished.empty()) continue;
+            HIP_OK(hipMemcpyAsync(ctl_host_, ctl_.p, (size_t)nb_ * sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            for (int32_t k : finished) {
+                probe_outcome(k);
+                if (!inst_[k].done && !next_probe(k)) inst_[k].done = true;
+            }
+            // nothing runs between the pull above and this push (one stream), so
+            // the blocks of running instances go back unchanged
+            push_state();
+        }
+    }
+
+    // Every instance back to the start of its outer search, first probe
+    // configured and pushed.
+    void start_all()
+    {
+        for (int32_t k = 0; k < nb_; ++k) {
+            Inst &I = inst_[k];
+            I.lo = I.lo0; I.hi = I.hi0;
+            I.slo = I.lo; I.shi = I.hi; I.eps_probe = s_.opt.eps; I.halvings = 0; I.probes = 0;
+            I.iters = I.passes = I.final_iters = 0;
+            I.done = false; I.have_best = false; I.failed = false; I.best_scale = 1.0;
+            I.max_violation = 0.0;
+            if (!next_probe(k)) I.done = true;
+        }
+        push_state();
+    }
+
+    // Edge tiles and element tiles of every instance (never across
+    // instances), their record buffers and the persistent grids.
+    void relayout(const mwu_batch_layout &L)
+    {
+        std::vector<BTile> et, wt;
+        std::vector<int32_t> erec0(nb_), erecn(nb_), wrec0(nb_), wrecn(nb_);
+        for (int32_t k = 0; k < nb_; ++k) {
+            const Inst &I = inst_[k];
+            wrec0[k] = (int32_t)wt.size();
+            for (int64_t i = 0; i < I.nv; i += L.tile_vertices)
+                wt.push_back(BTile{k, (int32_t)(I.v0 + i), (int32_t)(I.v0 + std::min<int64_t>(i + L.tile_vertices, I.nv)),
+                                   0, 0, -1, 0, 0});
+            wrecn[k] = (int32_t)wt.size() - wrec0[k];
+            erec0[k] = (int32_t)et.size();
+            for (int64_t i = 0; i < I.ne; i += L.tile_edges)
+                et.push_back(BTile{k, (int32_t)(I.e0 + i), (int32_t)(I.e0 + std::min<int64_t>(i + L.tile_edges, I.ne)),
+                                   0, 0, -1, 0, 0});
+            erecn[k] = (int32_t)et.size() - erec0[k];
+        }
+        if (graph_) {
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            (void)hipGraphExecDestroy(graph_);
+            graph_ = nullptr;
+        }
+        auto up = [&](DevBuf &b, const void *src, size_t bytes) {
+            b.alloc(std::max<size_t>(bytes, 8));
+            if (bytes) HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        up(et_, et.data(), et.size() * sizeof(BTile));
+        up(wt_, wt.data(), wt.size() * sizeof(BTile));
+        up(erec0_, erec0.data(), nb_ * 4);
+        up(erecn_, erecn.data(), nb_ * 4);
+        up(wrec0_, wrec0.data(), nb_ * 4);
+        up(wrecn_, wrecn.data(), nb_ * 4);
+        epart_.alloc(et.size() * QMAX * 8);
+        wpart_.alloc(wt.size() * QMAX * 8);
+        bd_.et = et_.as<BTile>(); bd_.net = (int32_t)et.size();
+        bd_.erec0 = erec0_.as<int32_t>(); bd_.erecn = erecn_.as<int32_t>();
+        bd_.wt = wt_.as<BTile>(); bd_.nwt = (int32_t)wt.size();
+        bd_.wrec0 = wrec0_.as<int32_t>(); bd_.wrecn = wrecn_.as<int32_t>();
+        bd_.epart = epart_.as<double>(); bd_.wpart = wpart_.as<double>();
+        auto grid = [&](int64_t tiles, int occ) {
+            const int64_t per_cu = std::min<int64_t>(occ, L.workgroups_per_cu);
+            return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, per_cu * s_.num_cus, (int64_t)65535}));
+        };
+        L_.grid_v = grid(bd_.nvt, occ_v_);
+        L_.grid_w = grid(bd_.nwt, occ_e_);
+        L_.grid_e = grid(bd_.net, occ_e_);
+        L_.nsearch = L.search_launches;
+        layout_ = L;
+    }
+
+    // Edge-iterations per second of the current layout over the opening of a
+    // solve: the whole outer-search loop (probe turnovers included) from the
+    // start for a fixed wall-clock window, or to the end if it comes first.
+    double rate_current()
+    {
+        start_all();
+        ensure_graph();
+        const auto t0 = std::chrono::steady_clock::now();
+        const bool all_done = drive(kTuneSeconds);
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        double work = 0.0;
+        for (int32_t k = 0; k < nb_; ++k) {
+            const Inst &I = inst_[k];
+            int64_t it = I.iters;
+            if (!all_done && !I.done) it += std::max(0, stat_host_[4 * k + 2]);
+            work += (double)I.ne * (double)it;
+        }
+        return secs > 0.0 ? work / secs : 0.0;
+    }
+
+    // Layout at create: the process's or the cache file's record for this
+    // device and batch shape, else a sweep (MWU_FLAG_NO_TUNE: the default).
+    void choose_layout()
+    {
+        mwu_batch_layout L = default_layout();
+        if (s_.opt.flags & MWU_FLAG_NO_TUNE) {
+            relayout(L);
+            return;
+        }
+        const std::string key = tune_key("batch-matching", s_.fp32, s_.opt.device, s_.num_cus, nb_, nv_, ne_,
+                                         max_ne_);
+        double r = 0.0;
+        if (tune_lookup(key, s_.opt.tune_cache, &L, &r)) {
+            relayout(L);
+            layout_.source = MWU_LAYOUT_CACHED;
+            layout_.candidates_timed = 0;
+            layout_.edge_iters_per_sec = r;
+            return;
+        }
+        const std::vector<std::vector<int32_t>> cands = {
+            {BLOCK * 8, BLOCK * 16, BLOCK * 32},
+            {BLOCK * 4, BLOCK * 8, BLOCK * 16, BLOCK * 32},
+            {4, 8},
+            {1, 2},
+        };
+        int timed = 0;
+        const mwu_batch_layout best = tune_descent(
+            L, cands,
+            [&](const mwu_batch_layout &c) {
+                relayout(c);
+                return rate_current();
+            },
+            &timed, &r);
+        relayout(best);
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        layout_.source = MWU_LAYOUT_TUNED;
+        layout_.candidates_timed = timed;
+        layout_.edge_iters_per_sec = r;
+        tune_store(key, s_.opt.tune_cache, layout_, r);
+    }
+
     // Configure instance k's next probe in the host copy of its control block
     // (phase PH_INIT); false when its search is over.
     bool next_probe(int32_t k)
@@ -341,6 +454,7 @@ class BatchMatching : public BatchProgram {
         c.phase = PH_INIT;
         ++I.serial;
         stat_host_[4 * k + 0] = PH_INIT;      // pushed with the control blocks
+        stat_host_[4 * k + 2] = 0;
         stat_host_[4 * k + 3] = I.serial;
         return true;
     }
@@ -397,7 +511,10 @@ class BatchMatching : public BatchProgram {
     Solver &s_;
     int32_t nb_ = 0;
     int64_t nv_ = 0, ne_ = 0;
+    int64_t max_ne_ = 0;
     int slots_ = 8;
+    int occ_v_ = 1, occ_e_ = 1;
+    mwu_batch_layout layout_{};
     std::vector<Inst> inst_;
     BatchDev<T> bd_{};
     BLaunch L_{};

@@ -729,6 +729,27 @@ int64_t mwu_num_variables(void *h)
     return h ? static_cast<Solver *>(h)->n_user : -1;
 }
 
+mwu_status mwu_batch_get_layout(void *h, mwu_batch_layout *out)
+{
+    if (!h || !out) return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (!s.batch) return MWU_ERR_STATE;
+    *out = s.batch->layout();
+    return MWU_OK;
+}
+
+mwu_status mwu_batch_set_layout(void *h, const mwu_batch_layout *layout)
+{
+    if (!h || !layout) return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (!s.batch) return MWU_ERR_STATE;
+    if (!layout_valid(*layout)) return MWU_ERR_INVALID_ARG;
+    return run_guarded([&] {
+        HIP_OK(hipSetDevice(s.opt.device));
+        s.batch->set_layout(*layout);
+    });
+}
+
 mwu_status mwu_solve(void *h, double *x_out, double *objective_out, int64_t *iterations_out,
                      mwu_result_info *info)
 {

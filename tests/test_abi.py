@@ -79,6 +79,9 @@ def test_null_arguments():
     assert L.mwu_create(None, None, ctypes.byref(h)) == -1
     assert L.mwu_solve(None, None, None, None, None) == -1
     L.mwu_destroy(None)   # NULL-safe
+    lay = _lib.BatchLayout(2048, 4096, 8, 2, 0, 0, 0.0)
+    assert L.mwu_batch_get_layout(None, ctypes.byref(lay)) == -1
+    assert L.mwu_batch_set_layout(None, ctypes.byref(lay)) == -1
 
 
 def test_valid_problem_without_gpu_fails_loudly():

@@ -88,3 +88,88 @@ def test_batch_solve_twice_is_identical():
         assert a.total_iterations == c.total_iterations > 0
         assert a.objective == c.objective and a.lower == c.lower and a.upper == c.upper
         assert np.array_equal(a.x, c.x)
+
+
+# ------------------------------------------------------------------ autotuner
+
+TILE_E = {1024, 2048, 4096, 8192}
+TILE_V = {1024, 2048, 4096, 8192, 16384}
+
+
+def test_autotuner_sweeps_then_reuses(tmp_path):
+    """The first create times a sweep and appends its choice to the cache
+    file; a second create of the same batch shape reads it back; a record
+    written by hand for the same key is taken as it stands; the tuned layout
+    solves every instance to the exact optimum's bracket."""
+    import paper_2307_03307_amd as mwu
+    from paper_2307_03307_amd import _lib
+    gs = gg.batch_bipartite(64, scale_div=8)
+    spec = [(g.num_vertices, g.u, g.v) for g in gs]
+    cache = tmp_path / "layouts.txt"
+    with mwu.BatchSolver(spec, tune_cache=str(cache)) as b:
+        lay = b.layout()
+        print("tuned layout", lay)
+        assert lay["source"] in (_lib.LAYOUT_TUNED, _lib.LAYOUT_CACHED)
+        if lay["source"] == _lib.LAYOUT_TUNED:
+            assert lay["candidates_timed"] >= 4 and lay["edge_iters_per_sec"] > 0
+        assert lay["tile_edges"] in TILE_E and lay["tile_vertices"] in TILE_V
+        assert lay["workgroups_per_cu"] in (2, 4, 8) and lay["search_launches"] in (1, 2, 3)
+        res = b.solve()
+    for g, r in zip(gs, res):
+        _check(g, r, _nu(g))
+    lines = [ln for ln in cache.read_text().split("\n") if ln.strip()]
+    assert len(lines) == 1   # a sweep's record, or the process's record for the same shape
+    with mwu.BatchSolver(spec, tune_cache=str(cache)) as b:
+        again = b.layout()
+    assert again["source"] == _lib.LAYOUT_CACHED
+    assert all(again[f] == lay[f] for f in ("tile_edges", "tile_vertices", "workgroups_per_cu",
+                                            "search_launches"))
+    key = lines[-1].split()[0]
+    hand = tmp_path / "hand.txt"
+    hand.write_text("garbage line\n" + f"{key} 1024 8192 4 1 1.0e9\n")
+    with mwu.BatchSolver(spec, tune_cache=str(hand)) as b:
+        got = b.layout()
+        res = b.solve()
+    assert (got["tile_edges"], got["tile_vertices"], got["workgroups_per_cu"],
+            got["search_launches"], got["source"]) == (1024, 8192, 4, 1, _lib.LAYOUT_CACHED)
+    for g, r in zip(gs, res):
+        _check(g, r, _nu(g))
+
+
+def test_untuned_layout_is_the_default():
+    import paper_2307_03307_amd as mwu
+    from paper_2307_03307_amd import _lib
+    gs = _instances()[:4]
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs], tune=False) as b:
+        lay = b.layout()
+    assert lay["source"] == _lib.LAYOUT_DEFAULT and lay["candidates_timed"] == 0
+    assert (lay["tile_edges"], lay["tile_vertices"], lay["workgroups_per_cu"],
+            lay["search_launches"]) == (2048, 4096, 8, 2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_layout_solves(precision):
+    """Extreme layouts (one-wave tiles, one workgroup per CU, one search
+    launch per slot; 64Ki tiles, four search launches) give certified
+    answers around the exact optimum; an invalid layout is rejected and the
+    handle keeps working."""
+    import paper_2307_03307_amd as mwu
+    from paper_2307_03307_amd import _lib
+    gs = _instances()
+    nus = [_nu(g) for g in gs]
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs], precision=precision,
+                         tune=False) as b:
+        for lay in [(256, 256, 1, 1), (65536, 65536, 16, 4), (1024, 2048, 2, 3)]:
+            b.set_layout(*lay)
+            got = b.layout()
+            assert (got["tile_edges"], got["tile_vertices"], got["workgroups_per_cu"],
+                    got["search_launches"]) == lay and got["source"] == _lib.LAYOUT_SET
+            for g, r, nu in zip(gs, b.solve(), nus):
+                _check(g, r, nu)
+        for bad in [(300, 4096, 8, 2), (2048, 0, 8, 2), (2048, 4096, 0, 2), (2048, 4096, 8, 5),
+                    (131072, 4096, 8, 2)]:
+            with pytest.raises(_lib.MwuError) as e:
+                b.set_layout(*bad)
+            assert e.value.code == -1
+        for g, r, nu in zip(gs, b.solve(), nus):
+            _check(g, r, nu)
