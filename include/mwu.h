@@ -278,7 +278,8 @@ mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, do
  * direction pass, 2 forward pass (P d, C d; a no-op in fused programs that
  * form it inside the search), 3 step-search pass over the exponential grid
  * (8 candidates from 1), 4 step-search pass over a bisection grid (15
- * candidates in [1, 2]).  The kernel is launched reps times on the handle's
+ * candidates in [1, 2]), 5 the combined first pass of an iteration (the 8
+ * exponential candidates and the 15 of the bisection of [2, 4]).  The kernel is launched reps times on the handle's
  * stream with the probe state frozen (after one direction at the current
  * point; the finisher kernel of the pass is not launched), timed with HIP
  * events;

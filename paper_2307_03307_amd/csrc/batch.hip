@@ -18,9 +18,8 @@
 namespace mwu {
 
 template <class T>
-MWU_DEV void write_stat(const BatchDev<T> &b, int k)
+MWU_DEV void write_stat(const BatchDev<T> &b, int k, const Ctl *c)
 {
-    const Ctl *c = b.ctl + k;
     b.stat[4 * k + 0] = c->phase;
     b.stat[4 * k + 1] = c->status;
     b.stat[4 * k + 2] = c->iter;
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(BLOCK) void kb_initx_fin(BatchDev<T> b)
     if (threadIdx.x == 0) {
         finish_sumx(c, s_rec[0]);
         c->phase = PH_INIT_Y;
-        write_stat(b, k);
+        write_stat(b, k, c);
     }
 }
 
@@ -173,16 +172,16 @@ __global__ __launch_bounds__(BLOCK) void kb_vfwd_fin(BatchDev<T> b)
     }
     block_combine<2>(v, red, 0, s_wave, s_lng);
     fold_records<2>(b.vpart + (size_t)b.vrec0[k] * QMAX, b.vrecn[k], red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) {
+    on_ctl(c, [&](Ctl *cl) {
         for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
         if (init) {
-            finish_init_fwd(c, s_rec);
+            finish_init_fwd(cl, s_rec);
         } else {
-            c->dymax = s_rec[1];
-            begin_search(c, nullptr);
+            cl->dymax = s_rec[1];
+            begin_search(cl, nullptr);
         }
-        write_stat(b, k);
-    }
+        write_stat(b, k, cl);
+    });
 }
 
 // ------------------------------------------------------------------ iteration
@@ -224,10 +223,10 @@ __global__ __launch_bounds__(BLOCK) void kb_row_fin(BatchDev<T> b)
     if (c->phase != PH_ROW) return;
     const Red red{2, 1, 1};
     fold_records<4>(b.wpart + (size_t)b.wrec0[k] * QMAX, b.wrecn[k], red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) {
-        finish_row(c, s_rec);
-        write_stat(b, k);
-    }
+    on_ctl(c, [&](Ctl *cl) {
+        finish_row(cl, s_rec);
+        write_stat(b, k, cl);
+    });
 }
 
 // Column pass over edges: commit x += a d, then g = (w_u + w_v) / sum w,
@@ -284,17 +283,17 @@ __global__ __launch_bounds__(BLOCK) void kb_col_fin(BatchDev<T> b)
         if (threadIdx.x == 0) {
             c->alpha = 0.0;
             c->phase = PH_STATS;
-            write_stat(b, k);
+            write_stat(b, k, c);
         }
         return;
     }
     const Red red{1, 1, 2};
     fold_records<4>(b.epart + (size_t)b.erec0[k] * QMAX, b.erecn[k], red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) {
-        finish_col(c, s_rec);
-        if (c->phase == PH_DONE) c->phase = PH_STATS;
-        write_stat(b, k);
-    }
+    on_ctl(c, [&](Ctl *cl) {
+        finish_col(cl, s_rec);
+        if (cl->phase == PH_DONE) cl->phase = PH_STATS;
+        write_stat(b, k, cl);
+    });
 }
 
 // ------------------------------------------------------------------ step search
@@ -305,34 +304,13 @@ template <class T, int KIND>
 MWU_DEV void kb_search_rows(const BatchDev<T> &b, const BTile &tl, const Ctl *c, double *s_wave,
                             double *s_rec)
 {
-    const double eta = c->eta, a0 = c->cand[0], gdel = c->gdelta;
+    const double eta = c->eta, a0 = c->cand[0], ga0 = c->ga0, gdel = c->gdelta;
     const int nc = c->ncand;
     double s1[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) s1[k] = 0.0;
-    for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK) {
-        const T w = b.w[i], dy = b.dy[i];
-        if constexpr (KIND == SK_EXP) {
-            T m = expm1_t((T)(eta * a0 * (double)dy));
-#pragma unroll
-            for (int k = 0; k < KE; ++k) {
-                s1[k] += (double)(w * m);
-                m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
-            }
-        } else if constexpr (KIND == SK_GRID) {
-            T m = expm1_t((T)(eta * a0 * (double)dy));
-            const T mr = expm1_t((T)(eta * gdel * (double)dy));
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                s1[k] += (double)(w * m);
-                m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < KC; ++k)
-                if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * c->cand[k] * (double)dy)));
-        }
-    }
+    for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
+        pack_terms<T, KIND>(nc, c->cand, a0, ga0, gdel, eta, b.w[i], b.dy[i], s1);
     const Red redp{KC, 0, 0};
     block_combine<KC>(s1, redp, 0, s_wave, s_rec);
 }
@@ -372,6 +350,7 @@ __global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
         switch (c->skind) {
         case SK_EXP: kb_search_rows<T, SK_EXP>(b, tl, c, s_wave, s_rec); break;
         case SK_GRID: kb_search_rows<T, SK_GRID>(b, tl, c, s_wave, s_rec); break;
+        case SK_COMBO: kb_search_rows<T, SK_COMBO>(b, tl, c, s_wave, s_rec); break;
         default: kb_search_rows<T, SK_LIST>(b, tl, c, s_wave, s_rec); break;
         }
         if (threadIdx.x < KC) rec[threadIdx.x] = s_rec[threadIdx.x];
@@ -400,11 +379,11 @@ __global__ __launch_bounds__(BLOCK) void kb_search_fin(BatchDev<T> b)
         for (int q = KC + threadIdx.x; q < 4 * KC; q += BLOCK) s_rec[q] = 0.0;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        finish_search(c, s_rec);
-        if (c->phase == PH_DONE) c->phase = PH_STATS;
-        write_stat(b, k);
-    }
+    on_ctl(c, [&](Ctl *cl) {
+        finish_search(cl, s_rec);
+        if (cl->phase == PH_DONE) cl->phase = PH_STATS;
+        write_stat(b, k, cl);
+    });
 }
 
 // ------------------------------------------------------------------ probe end
@@ -473,7 +452,7 @@ __global__ __launch_bounds__(BLOCK) void kb_stats_fin(BatchDev<T> b)
         c->ymax = c->sP * fmax(s_rec[0], lmax);
         c->zmin = c->sC * s_rec2[0];
         c->phase = PH_IDLE;
-        write_stat(b, k);
+        write_stat(b, k, c);
     }
 }
 

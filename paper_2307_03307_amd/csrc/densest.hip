@@ -140,15 +140,15 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_fin(DnDev<T> dd, Ctl *ctl, const
     block_combine<1>(lv, rmax, 0, s_wave, s_l);
     fold_records<1>(pv, Gv, rmax, 0, s_wave, s_a);
     fold_records<1>(pe, Ge, rmin, 0, s_wave, s_b);
-    if (threadIdx.x == 0) {
+    on_ctl(ctl, [&](Ctl *c) {
         double rec[2] = {s_b[0], fmax(s_a[0], s_l[0])};   // [min over C rows | max over P rows]
         if (INIT) {
-            finish_init_fwd(ctl, rec);
-        } else if (!held(ctl)) {
-            ctl->dymax = rec[1];
-            begin_search(ctl, dd.forced);
+            finish_init_fwd(c, rec);
+        } else if (!held(c)) {
+            c->dymax = rec[1];
+            begin_search(c, dd.forced);
         }
-    }
+    });
 }
 
 // ------------------------------------------------------------------ row pass
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(BLOCK) void dn_row_fin(Ctl *ctl, const double *part
     if (ctl->phase != PH_ROW) return;
     const Red red{2, 1, 1};
     fold_records<4>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) finish_row(ctl, s_rec);
+    on_ctl(ctl, [&](Ctl *c) { finish_row(c, s_rec); });
 }
 
 // ------------------------------------------------------------------ column pass
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col_fin(Ctl *ctl, const double *part
     }
     const Red red{1, 1, 2};
     fold_records<4>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) finish_col(ctl, s_rec);
+    on_ctl(ctl, [&](Ctl *c) { finish_col(c, s_rec); });
 }
 
 // ------------------------------------------------------------------ step search
@@ -282,42 +282,22 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
     const int r0 = blockIdx.x * BLOCK + threadIdx.x;
     const int nc = ctl->ncand;
     const double *cand = ctl->cand;
-    const double a0 = ctl->cand[0], gdel = ctl->gdelta;
+    const double a0 = ctl->cand[0], ga0 = ctl->ga0, gdel = ctl->gdelta;
     {
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
-        for (int r = r0; r < dd.nv; r += stride) {
-            const T w = dd.w[r], dy = dd.dy[r];
-            if constexpr (KIND == SK_EXP) {
-                T m = expm1_t((T)(eta * a0 * (double)dy));
-#pragma unroll
-                for (int k = 0; k < KE; ++k) {
-                    s1[k] += (double)(w * m);
-                    m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
-                }
-            } else if constexpr (KIND == SK_GRID) {
-                T m = expm1_t((T)(eta * a0 * (double)dy));
-                const T mr = expm1_t((T)(eta * gdel * (double)dy));
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    s1[k] += (double)(w * m);
-                    m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < KC; ++k)
-                    if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
-            }
-        }
+        for (int r = r0; r < dd.nv; r += stride)
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], dd.dy[r], s1);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }
     {
         CovAcc<T, double> ca;
-        ca.init(KIND != SK_GRID);
+        ca.init(pass_minima<KIND>());
         for (int e = r0; e < dd.ne; e += stride)
-            cov_terms<T, KIND, double>(nc, cand, a0, gdel, eta, dd.u[e], dd.z[e], dd.dz[e], ca.acc, ca.zmn);
+            cov_terms<T, KIND, double>(nc, cand, a0, ga0, gdel, eta, dd.u[e], dd.z[e], dd.dz[e], ca.acc,
+                                       ca.zmn);
         ca.combine(s_wave, s_rec + KC);
     }
 }
@@ -357,6 +337,7 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
     switch (kind) {
     case SK_EXP: dn_search_rows<T, SK_EXP>(dd, ctl, s_wave, s_rec); break;
     case SK_GRID: dn_search_rows<T, SK_GRID>(dd, ctl, s_wave, s_rec); break;
+    case SK_COMBO: dn_search_rows<T, SK_COMBO>(dd, ctl, s_wave, s_rec); break;
     default: dn_search_rows<T, SK_LIST>(dd, ctl, s_wave, s_rec); break;
     }
     store_record(s_rec, 4 * KC, part);
@@ -374,7 +355,7 @@ __global__ __launch_bounds__(BLOCK) void dn_search_fin(Ctl *ctl, const double *p
         const Red red{3 * KC, KC, 0};
         fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
     }
-    if (threadIdx.x == 0) finish_search(ctl, s_rec);
+    on_ctl(ctl, [&](Ctl *c) { finish_search(c, s_rec); });
 }
 
 // ------------------------------------------------------------------ FP64 statistics
@@ -509,13 +490,16 @@ void dn_search_pass(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t
     DLAUNCH(dn_search_fin, 1, ctl, (const double *)L.partials, L.grid_s);
 }
 
+// One iteration slot with a single search launch: most iterations finish
+// their step search in the combined first pass; one that needs more passes
+// takes them in the following slots, whose other passes see the search phase
+// and return at once.
 template <class T>
 void dn_iteration(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st)
 {
     dn_row_pass<T>(dd, ctl, L, st);
     dn_col_pass<T>(dd, ctl, L, st);
     dn_fwd_pass<T>(dd, ctl, L, st);
-    dn_search_pass<T>(dd, ctl, L, st);
     dn_search_pass<T>(dd, ctl, L, st);
 }
 

@@ -332,22 +332,73 @@ MWU_DEV Acc long_sum(int lid, const Acc *lpart, const int32_t *lfirst, const int
     return tot;
 }
 
-// Covering-row terms of one search pass for candidate k (KIND fixed per
-// launch, no data-dependent branches): acc[k] += u expm1(-b_k), acc[KC+k] +=
-// u e^{-b_k}, zmn[k] = min(zmn[k], z + a_k dz) with b_k = eta a_k dz.  On the
-// exponential grid a_k = a0 2^k, so expm1(-b_k) follows from expm1(2x) =
-// expm1(x)(expm1(x) + 2) and e^{-b_k} from squaring (float re-seeds the
-// squared term from exp every 4 candidates); on the bisection grid a_k = a0 +
-// k gdel and expm1(x + y) = expm1(x) + expm1(y) + expm1(x) expm1(y).  A zero
-// weight or a zero dz needs no special case: the terms come out as 0 and u.
-template <class T, int KIND, class Z = T>
-MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, double eta, T u, Z z, T dz,
-                       T *acc, Z *zmn)
+// Candidates carried by a pass of each kind (the list kind checks k < nc).
+template <int KIND>
+constexpr int pass_cands()
 {
-    constexpr int NK = KIND == SK_EXP ? KE : KC;
+    return KIND == SK_EXP ? KE : KIND == SK_GRID ? KG : KIND == SK_LIST ? KL : KC;
+}
+// Leading candidates whose minima min(z + a dz) the replay can read: those of
+// the exponential phase (the bisection never reads them).
+template <int KIND>
+constexpr int pass_minima()
+{
+    return KIND == SK_EXP || KIND == SK_COMBO ? KE : KIND == SK_LIST ? KL : 0;
+}
+
+// Covering terms s1[k] += u expm1(-b_k), s2[k] += u e^{-b_k} for b_k = b0
+// 2^k, k < N: expm1(2x) = expm1(x)(expm1(x) + 2) and e^{-2x} by squaring
+// (float re-seeds the squared term from exp every 4 candidates).
+template <class T, int N>
+MWU_DEV void cov_doubling(double b0d, T u, T *s1, T *s2)
+{
+    const T b0 = (T)b0d;
+    T m = expm1_t(-b0);
+    T t = exp_arg(-b0d, T(0));
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        s1[k] += u * m;
+        s2[k] += u * t;
+        m = m * (m + T(2));
+        if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < N)
+            t = exp_arg(-b0d * (double)(1 << (k + 1)), T(0));
+        else
+            t = t * t;
+    }
+}
+
+// The same for b_k = b0 + k bd: expm1(x + y) = expm1(x) + expm1(y) +
+// expm1(x) expm1(y) and e^{-(x+y)} = e^{-x} e^{-y}.
+template <class T, int N>
+MWU_DEV void cov_adding(double b0d, double bdd, T u, T *s1, T *s2)
+{
+    T m = expm1_t(-(T)b0d);
+    T t = exp_arg(-b0d, T(0));
+    const T mr = expm1_t(-(T)bdd);
+    const T tr = exp_arg(-bdd, T(0));
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        s1[k] += u * m;
+        s2[k] += u * t;
+        m = m + mr + m * mr;
+        t = t * tr;
+    }
+}
+
+// Covering-row terms of one search pass (KIND fixed per launch, no
+// data-dependent branches): acc[k] += u expm1(-b_k), acc[KC+k] += u
+// e^{-b_k}, zmn[k] = min(zmn[k], z + a_k dz) for the leading pass_minima
+// candidates, with b_k = eta a_k dz.  On the exponential grid a_k = a0 2^k,
+// on the bisection grid a_k = a0 + k gdel, on the combined pass both (the
+// bisection part from ga0).  A zero weight or a zero dz needs no special
+// case: the terms come out as 0 and u.
+template <class T, int KIND, class Z = T>
+MWU_DEV void cov_terms(int nc, const double *cand, double a0, double ga0, double gdel, double eta, T u, Z z,
+                       T dz, T *acc, Z *zmn)
+{
     if constexpr (KIND == SK_LIST) {   // arbitrary candidates, direct evaluation
 #pragma unroll
-        for (int k = 0; k < KC; ++k)
+        for (int k = 0; k < KL; ++k)
             if (k < nc) {
                 const double a = cand[k];
                 zmn[k] = fmin(zmn[k], z + (Z)a * (Z)dz);
@@ -356,42 +407,54 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double gdel, doubl
                 acc[KC + k] += u * exp_t(-b);
             }
     } else {
-        if constexpr (KIND == SK_EXP) {   // the bisection replay never reads the minima
+        if constexpr (pass_minima<KIND>() > 0) {
             Z ak = (Z)a0;
 #pragma unroll
-            for (int k = 0; k < NK; ++k) {
+            for (int k = 0; k < pass_minima<KIND>(); ++k) {
                 zmn[k] = fmin(zmn[k], z + ak * (Z)dz);
                 ak = ak + ak;
             }
         }
-        const double b0d = eta * a0 * (double)dz;
-        const T b0 = (T)b0d;
-        T m = expm1_t(-b0);
-        T t = exp_arg(-b0d, T(0));
-        if constexpr (KIND == SK_EXP) {
+        const double dzd = (double)dz;
+        if constexpr (KIND == SK_EXP || KIND == SK_COMBO) cov_doubling<T, KE>(eta * a0 * dzd, u, acc, acc + KC);
+        if constexpr (KIND == SK_GRID) cov_adding<T, KG>(eta * a0 * dzd, eta * gdel * dzd, u, acc, acc + KC);
+        if constexpr (KIND == SK_COMBO)
+            cov_adding<T, KG>(eta * ga0 * dzd, eta * gdel * dzd, u, acc + KE, acc + KC + KE);
+    }
+}
+
+// Packing-row terms of one search pass: s1[k] += w expm1(eta a_k dy), with
+// the candidates of cov_terms.
+template <class T, int KIND>
+MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, double gdel, double eta, T w, T dy,
+                        double *s1)
+{
+    const double dyd = (double)dy;
+    auto doubling = [&](double b0, double *o) {
+        T m = expm1_t((T)b0);
 #pragma unroll
-            for (int k = 0; k < NK; ++k) {
-                acc[k] += u * m;
-                acc[KC + k] += u * t;
-                m = m * (m + T(2));
-                if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < NK)
-                    t = exp_arg(-b0d * (double)(1 << (k + 1)), T(0));
-                else
-                    t = t * t;
-            }
-        } else {
-            const double bdd = eta * gdel * (double)dz;
-            const T bd = (T)bdd;
-            const T mr = expm1_t(-bd);
-            const T tr = exp_arg(-bdd, T(0));
-#pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                acc[k] += u * m;
-                acc[KC + k] += u * t;
-                m = m + mr + m * mr;
-                t = t * tr;
-            }
+        for (int k = 0; k < KE; ++k) {
+            o[k] += (double)(w * m);
+            m = m * (m + T(2));                      // expm1(2x) = expm1(x)(expm1(x)+2)
         }
+    };
+    auto adding = [&](double b0, double bd, double *o) {
+        T m = expm1_t((T)b0);
+        const T mr = expm1_t((T)bd);
+#pragma unroll
+        for (int k = 0; k < KG; ++k) {
+            o[k] += (double)(w * m);
+            m = m + mr + m * mr;                     // expm1(x+y) from expm1(x), expm1(y)
+        }
+    };
+    if constexpr (KIND == SK_LIST) {
+#pragma unroll
+        for (int k = 0; k < KL; ++k)
+            if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
+    } else {
+        if constexpr (KIND == SK_EXP || KIND == SK_COMBO) doubling(eta * a0 * dyd, s1);
+        if constexpr (KIND == SK_GRID) adding(eta * a0 * dyd, eta * gdel * dyd, s1);
+        if constexpr (KIND == SK_COMBO) adding(eta * ga0 * dyd, eta * gdel * dyd, s1 + KE);
     }
 }
 
@@ -402,14 +465,37 @@ template <class T, class Z = T>
 struct CovAcc {
     T acc[2 * KC];
     Z zmn[KC];
-    // Bisection passes leave the minima at -inf: the replay never reads them,
+    // Minima past the first nmin stay at -inf: the replay never reads them,
     // and -inf can never pass for an early return.
-    MWU_DEV void init(bool minima = true)
+    MWU_DEV void init(int nmin)
     {
 #pragma unroll
         for (int k = 0; k < 2 * KC; ++k) acc[k] = T(0);
 #pragma unroll
-        for (int k = 0; k < KC; ++k) zmn[k] = minima ? Z(INFINITY) : Z(-INFINITY);
+        for (int k = 0; k < KC; ++k) zmn[k] = k < nmin ? Z(INFINITY) : Z(-INFINITY);
+    }
+    // Compact block record of a pass of kind KIND, [s1C(N) | s2C(N) |
+    // zmin(M)] with N = pass_cands and M = pass_minima: the finisher folds
+    // only what the pass produced.
+    template <int KIND>
+    MWU_DEV void combine_compact(double *s_wave, double *out)
+    {
+        constexpr int N = pass_cands<KIND>(), M = pass_minima<KIND>();
+        double ad[2 * N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            ad[k] = (double)acc[k];
+            ad[N + k] = (double)acc[KC + k];
+        }
+        const Red rs{2 * N, 0, 0};
+        block_combine<2 * N>(ad, rs, 0, s_wave, out);
+        if constexpr (M > 0) {
+            double zd[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) zd[k] = (double)zmn[k];
+            const Red rm{0, M, 0};
+            block_combine<M>(zd, rm, 0, s_wave, out + 2 * N);
+        }
     }
     // block-combine into out[0..3KC): [s1C | s2C | zmin]
     MWU_DEV void combine(double *s_wave, double *out)
@@ -427,6 +513,31 @@ struct CovAcc {
     }
 };
 
+// Doubles in a compact covering record of a pass of kind KIND.
+template <int KIND>
+constexpr int cov_record_q()
+{
+    return 2 * pass_cands<KIND>() + pass_minima<KIND>();
+}
+
+// Finisher side of the compact records: fold them and spread the totals to
+// out = [s1C(KC) | s2C(KC) | zmin(KC)] (sums the pass did not form are 0,
+// minima it did not form -inf, which no early return can take).  All threads
+// call; out is complete on return.
+template <int KIND>
+MWU_DEV void fold_cov_compact(const double *part, int G, double *s_wave, double *s_tmp, double *out)
+{
+    constexpr int N = pass_cands<KIND>(), M = pass_minima<KIND>();
+    const Red r{2 * N, M, 0};
+    fold_records<cov_record_q<KIND>()>(part, G, r, 0, s_wave, s_tmp);
+    for (int k = threadIdx.x; k < KC; k += blockDim.x) {
+        out[k] = k < N ? s_tmp[k] : 0.0;
+        out[KC + k] = k < N ? s_tmp[N + k] : 0.0;
+        out[2 * KC + k] = k < M ? s_tmp[2 * N + k] : -INFINITY;
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------------ step-search replay
 //
 // The search kernels evaluate up to KC candidate steps per pass.  After a
@@ -435,6 +546,26 @@ struct CovAcc {
 // produce, the next pass is set up and the replay resumes from its state.
 
 struct Eval { double psi, phi, zmin; int ok; };
+
+// A finisher's state update is one thread walking long dependent chains of
+// control-block fields (the replay above all); from device memory every link
+// costs an L2 round trip.  The workgroup stages the block in LDS with one
+// load per thread, thread 0 runs f on the copy, and the workgroup writes the
+// whole block back.  All threads of the workgroup must call.
+template <class F>
+MWU_DEV void on_ctl(Ctl *g, F &&f)
+{
+    static_assert(sizeof(Ctl) % 8 == 0, "control block is copied in 8-byte words");
+    constexpr int W = sizeof(Ctl) / 8;
+    __shared__ uint64_t s_ctl[W];
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(g);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) s_ctl[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) f(reinterpret_cast<Ctl *>(s_ctl));
+    __syncthreads();
+    uint64_t *dst = reinterpret_cast<uint64_t *>(g);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = s_ctl[i];
+}
 
 MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
 {
@@ -484,9 +615,8 @@ MWU_DEV void setup_exp(Ctl *c, double a0)
 
 // Candidates of the bisection of [lb, ub] to depth 4, computed with exactly
 // the midpoint arithmetic of the sequential search, in ascending order.
-MWU_DEV void setup_grid(Ctl *c, double lb, double ub)
+MWU_DEV void grid_values(double lb, double ub, double *v)
 {
-    double v[15];
     // in-order positions of a complete binary tree of depth 4
     double lo1 = lb, hi1 = ub;
     double m1 = (lo1 + hi1) / 2.0;
@@ -497,9 +627,38 @@ MWU_DEV void setup_grid(Ctl *c, double lb, double ub)
     v[4] = (m2a + m3b) / 2.0;  v[5] = m3b; v[6] = (m3b + m1) / 2.0;  v[7] = m1;
     v[8] = (m1 + m3c) / 2.0;   v[9] = m3c; v[10] = (m3c + m2b) / 2.0; v[11] = m2b;
     v[12] = (m2b + m3d) / 2.0; v[13] = m3d; v[14] = (m3d + hi1) / 2.0;
+}
+
+MWU_DEV void setup_grid(Ctl *c, double lb, double ub)
+{
+    double v[KG];
+    grid_values(lb, ub, v);
     c->skind = SK_GRID;
-    c->ncand = 15;
-    for (int k = 0; k < 15; ++k) c->cand[k] = v[k];
+    c->ncand = KG;
+    for (int k = 0; k < KG; ++k) c->cand[k] = v[k];
+    c->ga0 = v[0];
+    c->gdelta = (ub - lb) / 16.0;
+}
+
+// First pass of an iteration: the exponential grid from 1 and, when the
+// previous step lay in an octave [2^j, 2^(j+1)) whose upper end the grid
+// reaches, the bisection tree of that octave in the same pass.  Steps change
+// slowly from one iteration to the next, so the sequential search usually
+// finds every value it asks for in this one pass; otherwise the replay sets
+// up the pass it needs, as after a plain exponential pass.
+MWU_DEV void setup_first(Ctl *c)
+{
+    setup_exp(c, 1.0);
+    const double la = c->last_alpha;
+    if (!(la >= 1.0 && la < (double)(1 << (KE - 1)))) return;
+    int e = 0;
+    (void)frexp(la, &e);                       // la = f 2^e, f in [0.5, 1)
+    const double lb = ldexp(1.0, e - 1), ub = 2.0 * lb;
+    double v[KG];
+    grid_values(lb, ub, v);
+    for (int k = 0; k < KG; ++k) c->cand[KE + k] = v[k];
+    c->skind = SK_COMBO;
+    c->ncand = KC;
     c->ga0 = v[0];
     c->gdelta = (ub - lb) / 16.0;
 }
@@ -619,7 +778,7 @@ MWU_DEV void begin_search(Ctl *c, const double *forced)
     c->amode = AM_EXP;
     c->exp_next = 1.0;
     c->have_cur = 0;
-    setup_exp(c, 1.0);
+    setup_first(c);
     c->phase = PH_SEARCH;
 }
 

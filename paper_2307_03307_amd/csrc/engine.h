@@ -10,8 +10,10 @@ namespace mwu {
 constexpr int BLOCK = 256;               // threads per workgroup (4 wave64)
 constexpr int ITEMS = 8;                 // nonzeros per thread in a segment tile
 constexpr int TILE_NZ = BLOCK * ITEMS;   // nonzeros per tile
-constexpr int KC = 16;                   // step candidates per search pass
-constexpr int KE = 8;            // candidates of an exponential-grid pass (1 .. 128 from a0 = 1)
+constexpr int KE = 8;                    // candidates of an exponential-grid pass (1 .. 128 from a0 = 1)
+constexpr int KG = 15;                   // candidates of a bisection pass (complete tree of depth 4)
+constexpr int KC = KE + KG;              // most step candidates in one search pass
+constexpr int KL = 16;                   // most candidates of a list pass (direct evaluation)
 constexpr int QMAX = 4 * KC + 8;         // doubles per block in a reduction record
 
 // Phase of the per-probe state machine.  Every kernel of the iteration graph
@@ -40,7 +42,9 @@ enum SKind : int32_t {
     SK_EXP = 0,      // cand[k] = a0 * 2^k           (exponential phase of Algorithm 3)
     SK_GRID = 1,     // cand[j] ~ a0 + j * delta      (bisection tree of depth 4)
     SK_LIST = 2,     // arbitrary values, direct evaluation
-    SK_REFINE = 3    // one value, max-shifted evaluation of both LSE differences
+    SK_REFINE = 3,   // one value, max-shifted evaluation of both LSE differences
+    SK_COMBO = 4     // the exponential grid from 1 (KE) followed by the bisection tree of the
+                     // octave the previous step fell in (KG): cand[KE + j] ~ ga0 + j * delta
 };
 
 enum AMode : int32_t { AM_EXP = 0, AM_BIS = 1, AM_FORCED = 2, AM_EVAL = 3 };

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_row_fin(Ctl *ctl, const double *part,
     if (ctl->phase != PH_ROW) return;
     const Red red{2, 1, 1};
     fold_records<4>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) finish_row(ctl, s_rec);
+    on_ctl(ctl, [&](Ctl *c) { finish_row(c, s_rec); });
 }
 
 template <class T>
@@ -227,10 +227,10 @@ __global__ __launch_bounds__(BLOCK) void k_col_fin(GenericDev<T> gd, Ctl *ctl, c
                                                gd.clong.lcount), v);
     block_combine<4>(v, red, 0, s_wave, s_lng);
     fold_records<4>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) {
+    on_ctl(ctl, [&](Ctl *c) {
         for (int q = 0; q < 4; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
-        finish_col(ctl, s_rec);
-    }
+        finish_col(c, s_rec);
+    });
 }
 
 // Forward product vout = (scaled rows) * vin.  INIT: y = Px, z = Cx at the
@@ -275,15 +275,15 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_fin(GenericDev<T> gd, Ctl *ctl, T
         ep(gd.rlong.lseg[l], long_sum<T>(l, gd.rlpart, gd.rlong.lfirst, gd.rlong.lcount), v);
     block_combine<2>(v, red, 0, s_wave, s_lng);
     fold_records<2>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) {
+    on_ctl(ctl, [&](Ctl *c) {
         for (int q = 0; q < 2; ++q) s_rec[q] = red_op(s_rec[q], s_lng[q], q, red);
         if (INIT) {
-            finish_init_fwd(ctl, s_rec);
-        } else if (!held(ctl)) {
-            ctl->dymax = s_rec[1];
-            begin_search(ctl, gd.forced);
+            finish_init_fwd(c, s_rec);
+        } else if (!held(c)) {
+            c->dymax = s_rec[1];
+            begin_search(c, gd.forced);
         }
-    }
+    });
 }
 
 // Certificate statistics of the current x in FP64 whatever the storage type:
@@ -345,43 +345,22 @@ __device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_w
     const int mPc = gd.mPc, mR = gd.mR;
     const int nc = ctl->ncand;
     const double *cand = ctl->cand;
-    const double a0 = ctl->cand[0];
+    const double a0 = ctl->cand[0], ga0 = ctl->ga0;
     const double gdel = ctl->gdelta;
     {
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
-        for (int r = r0; r < mPc; r += stride) {
-            const T w = gd.wu[r], dy = gd.dyz[r];
-            if constexpr (KIND == SK_EXP) {
-                T m = expm1_t((T)(eta * a0 * (double)dy));
-#pragma unroll
-                for (int k = 0; k < KE; ++k) {
-                    s1[k] += (double)(w * m);
-                    m = m * (m + T(2));                    // expm1(2x) = expm1(x)(expm1(x)+2)
-                }
-            } else if constexpr (KIND == SK_GRID) {
-                T m = expm1_t((T)(eta * a0 * (double)dy));
-                const T mr = expm1_t((T)(eta * gdel * (double)dy));
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    s1[k] += (double)(w * m);
-                    m = m + mr + m * mr;                   // expm1(x+y) from expm1(x), expm1(y)
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < KC; ++k)
-                    if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
-            }
-        }
+        for (int r = r0; r < mPc; r += stride)
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.dyz[r], s1);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }
     {
         CovAcc<T> ca;
-        ca.init(KIND != SK_GRID);
+        ca.init(pass_minima<KIND>());
         for (int r = mPc + r0; r < mR; r += stride)
-            cov_terms<T, KIND>(nc, cand, a0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
+            cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
         ca.combine(s_wave, s_rec + KC);
     }
 }
@@ -428,6 +407,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
     switch (kind) {
     case SK_EXP: search_rows<T, SK_EXP>(gd, ctl, s_wave, s_rec); break;
     case SK_GRID: search_rows<T, SK_GRID>(gd, ctl, s_wave, s_rec); break;
+    case SK_COMBO: search_rows<T, SK_COMBO>(gd, ctl, s_wave, s_rec); break;
     default: search_rows<T, SK_LIST>(gd, ctl, s_wave, s_rec); break;
     }
     store_record(s_rec, 4 * KC, part);
@@ -445,7 +425,7 @@ __global__ __launch_bounds__(BLOCK) void k_search_fin(Ctl *ctl, const double *pa
         const Red red{3 * KC, KC, 0};
         fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
     }
-    if (threadIdx.x == 0) finish_search(ctl, s_rec);
+    on_ctl(ctl, [&](Ctl *c) { finish_search(c, s_rec); });
 }
 
 template <class T>
@@ -551,13 +531,16 @@ void generic_search(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream
     LAUNCH(k_search_fin, 1, ctl, (const double *)L.partials, L.grid_search);
 }
 
+// One iteration slot with a single search launch: most iterations finish
+// their step search in the combined first pass; one that needs more passes
+// takes them in the following slots, whose other passes see the search phase
+// and return at once.
 template <class T>
 void generic_iteration(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStream_t st)
 {
     generic_row(g, ctl, L, st);
     generic_col(g, ctl, L, st);
     generic_fwd(g, ctl, L, st);
-    generic_search(g, ctl, L, st);
     generic_search(g, ctl, L, st);
 }
 

@@ -477,7 +477,7 @@ static void run_probe(Solver &s, int64_t max_iters)
     ensure_graph(s);
     pull_ctl(s);
     const int64_t start = s.ctl_host->iter;
-    const int64_t cap_launches = (max_iters + 4) * 4 / std::max(1, s.opt.iters_per_launch) + 16;
+    const int64_t cap_launches = (max_iters + 4) * 8 / std::max(1, s.opt.iters_per_launch) + 16;
     for (int64_t l = 0; l < cap_launches; ++l) {
         if (s.ctl_host->phase == PH_DONE || s.ctl_host->status != ST_RUNNING) break;
         if (s.ctl_host->iter - start >= max_iters) break;
@@ -903,7 +903,7 @@ mwu_status mwu_probe_read(void *h, int32_t which, double *out, int64_t len)
 mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new)
 {
-    if (!h || !alphas || count < 1 || count > KC || !psi || !phi) return MWU_ERR_INVALID_ARG;
+    if (!h || !alphas || count < 1 || count > KL || !psi || !phi) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
     if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
@@ -949,7 +949,7 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
 mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, double *bytes,
                          double *nnz)
 {
-    if (!h || which < 0 || which > 4 || reps < 1 || !avg_us) return MWU_ERR_INVALID_ARG;
+    if (!h || which < 0 || which > 5 || reps < 1 || !avg_us) return MWU_ERR_INVALID_ARG;
     Solver &s = *static_cast<Solver *>(h);
     if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
@@ -967,16 +967,23 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         pull_ctl(s);
         Ctl &c = *s.ctl_host;
         c.eval_mode = 0;
-        static const int phase_of[5] = {PH_ROW, PH_COL, PH_FWD, PH_SEARCH, PH_SEARCH};
+        static const int phase_of[6] = {PH_ROW, PH_COL, PH_FWD, PH_SEARCH, PH_SEARCH, PH_SEARCH};
         c.hold = phase_of[which];
         c.phase = phase_of[which];
         c.alpha = 0.0;
         if (which == 4) {   // bisection grid of [1, 2] to depth 4
             c.skind = SK_GRID;
-            c.ncand = 15;
+            c.ncand = KG;
             for (int k = 0; k < KC; ++k) c.cand[k] = 1.0 + (k + 1) / 16.0;
             c.ga0 = 1.0 + 1.0 / 16.0;
             c.gdelta = 1.0 / 16.0;
+        } else if (which == 5) {   // exponential grid from 1 and the bisection tree of [2, 4]
+            c.skind = SK_COMBO;
+            c.ncand = KC;
+            for (int k = 0; k < KE; ++k) c.cand[k] = std::ldexp(1.0, k);
+            for (int k = 0; k < KG; ++k) c.cand[KE + k] = 2.0 + 2.0 * (k + 1) / 16.0;
+            c.ga0 = 2.0 + 2.0 / 16.0;
+            c.gdelta = 2.0 / 16.0;
         } else {            // exponential grid from 1
             c.skind = SK_EXP;
             c.ncand = KE;
@@ -986,7 +993,7 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         }
         push_ctl(s);
         // the pass's main kernel only (its finisher leaves a held state alone)
-        auto launch = [&] { s.prog->main_kernel(which == 4 ? 3 : which); };
+        auto launch = [&] { s.prog->main_kernel(which >= 4 ? 3 : which); };
         launch();   // warm caches
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
@@ -1000,8 +1007,8 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *avg_us = 1000.0 * ms / reps;
-        if (bytes) *bytes = s.prog->algo_bytes(which == 4 ? 3 : which);
-        if (nnz) *nnz = s.prog->pass_nnz(which == 4 ? 3 : which);
+        if (bytes) *bytes = s.prog->algo_bytes(which >= 4 ? 3 : which);
+        if (nnz) *nnz = s.prog->pass_nnz(which >= 4 ? 3 : which);
         *s.ctl_host = saved;   // the probe continues from where it was
         push_ctl(s);
         HIP_OK(hipStreamSynchronize(s.stream));

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, con
     if (ctl->phase != PH_ROW) return;
     const Red red{1, 1, 0};
     fold_records<2>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) finish_vcA(ctl, s_rec);
+    on_ctl(ctl, [&](Ctl *c) { finish_vcA(c, s_rec); });
 }
 
 template <class T>
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_fin(VcDev<T> vd, Ctl *ctl, con
     }
     const Red red{1, 0, 2};
     fold_records<3>(part, G, red, 0, s_wave, s_rec);
-    if (threadIdx.x == 0) finish_vcB(ctl, s_rec, vd.forced);
+    on_ctl(ctl, [&](Ctl *c) { finish_vcB(c, s_rec, vd.forced); });
 }
 
 // K-candidate covering sums of one search pass over the edge list (KIND fixed
@@ -355,19 +355,19 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
 {
     const int nc = ctl->ncand;
     const double *cand = ctl->cand;
-    const double eta = ctl->eta, a0 = ctl->cand[0];
+    const double eta = ctl->eta, a0 = ctl->cand[0], ga0 = ctl->ga0;
     const double gdel = ctl->gdelta, Lw = ctl->LCw;
     CovAcc<T> ca;
-    ca.init(KIND != SK_GRID);
+    ca.init(pass_minima<KIND>());
     auto visit = [&](XD<T> pu, XD<T> pw, int) {
         const double zd = (double)pu.x + (double)pw.x;
         const T z = (T)zd;
         const T dz = pu.d + pw.d;
         const T u = exp_arg(-eta * (zd - Lw), T(0));
-        cov_terms<T, KIND>(nc, cand, a0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
+        cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
     };
     for_edges<T>(vd, visit);
-    ca.combine(s_wave, s_rec);
+    ca.template combine_compact<KIND>(s_wave, s_rec);
 }
 
 template <class T>
@@ -394,18 +394,32 @@ __device__ __forceinline__ void vc_search_body(const VcDev<T> &vd, Ctl *ctl, dou
         store_record(s_rec, 2, part);
         return;
     }
+    // compact records of the covering sums only (no packing rows)
     switch (kind) {
-    case SK_EXP: vc_search_edges<T, SK_EXP>(vd, ctl, s_wave, s_rec); break;
-    case SK_GRID: vc_search_edges<T, SK_GRID>(vd, ctl, s_wave, s_rec); break;
-    default: vc_search_edges<T, SK_LIST>(vd, ctl, s_wave, s_rec); break;
+    case SK_EXP:
+        vc_search_edges<T, SK_EXP>(vd, ctl, s_wave, s_rec);
+        store_record(s_rec, cov_record_q<SK_EXP>(), part);
+        break;
+    case SK_GRID:
+        vc_search_edges<T, SK_GRID>(vd, ctl, s_wave, s_rec);
+        store_record(s_rec, cov_record_q<SK_GRID>(), part);
+        break;
+    case SK_COMBO:
+        vc_search_edges<T, SK_COMBO>(vd, ctl, s_wave, s_rec);
+        store_record(s_rec, cov_record_q<SK_COMBO>(), part);
+        break;
+    default:
+        vc_search_edges<T, SK_LIST>(vd, ctl, s_wave, s_rec);
+        store_record(s_rec, cov_record_q<SK_LIST>(), part);
+        break;
     }
-    store_record(s_rec, 3 * KC, part);   // records hold the covering sums only
 }
 
-// The FP32 search fits five waves per SIMD; ask the compiler to keep it there.
+// The FP32 search fits four waves per SIMD without spills (the combined pass
+// holds 54 accumulators); ask the compiler to keep it there.
 template <class T> __global__ void vc_search_k(VcDev<T> vd, Ctl *ctl, double *part);
 template <>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 void vc_search_k<float>(VcDev<float> vd, Ctl *ctl, double *part) { vc_search_body<float>(vd, ctl, part); }
 template <>
 __global__ __launch_bounds__(BLOCK)
@@ -419,21 +433,26 @@ __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *p
     if (ctl->skind == SK_REFINE) {
         const Red red{1, 1, 0};
         fold_records<2>(part, G, red, 0, s_wave, s_rec);
-        if (threadIdx.x == 0) {
+        on_ctl(ctl, [&](Ctl *c) {
             // finish_search expects pass 1 [min z' | max eta*y'], pass 2 [sumP | sumC]
             double r[2];
-            if (ctl->ref_valid == 0) { r[0] = s_rec[1]; r[1] = -INFINITY; }
+            if (c->ref_valid == 0) { r[0] = s_rec[1]; r[1] = -INFINITY; }
             else { r[0] = 1.0; r[1] = s_rec[0]; }
-            finish_search(ctl, r);
-        }
+            finish_search(c, r);
+        });
         return;
     }
-    const Red redc{2 * KC, KC, 0};
-    fold_records<3 * KC>(part, G, redc, 0, s_wave, s_rec + KC);
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < KC; ++k) s_rec[k] = 0.0;   // no packing rows: Psi = a * dy1
-        finish_search(ctl, s_rec);
+    __shared__ double s_tmp[QMAX];
+    switch (ctl->skind) {
+    case SK_EXP: fold_cov_compact<SK_EXP>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    case SK_GRID: fold_cov_compact<SK_GRID>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    case SK_COMBO: fold_cov_compact<SK_COMBO>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    default: fold_cov_compact<SK_LIST>(part, G, s_wave, s_tmp, s_rec + KC); break;
     }
+    on_ctl(ctl, [&](Ctl *c) {
+        for (int k = 0; k < KC; ++k) s_rec[k] = 0.0;   // no packing rows: Psi = a * dy1
+        finish_search(c, s_rec);
+    });
 }
 
 template <class T>
@@ -498,12 +517,15 @@ void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
     VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_e);
 }
 
+// One iteration slot with a single search launch: most iterations finish
+// their step search in the combined first pass; one that needs more passes
+// takes them in the following slots, whose other passes see the search phase
+// and return at once.
 template <class T>
 void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
     vc_passA(v, ctl, L, st);
     vc_passB(v, ctl, L, st);
-    vc_search(v, ctl, L, st);
     vc_search(v, ctl, L, st);
 }
 
