@@ -20,10 +20,13 @@ MWU_DEV double exp_t(double v) { return exp(v); }
 // in base 2 in double, v log2(e) = n + f with |f| <= 1/2, so the hardware
 // 2^f (v_exp_f32, about 1 ulp) sees a small reduced argument and ldexp adds
 // n exactly; the result carries no error from rounding a large argument to
-// float.  Double: the library exp.
+// float.  The argument is first clamped to |v| <= 1e4 (far outside the
+// float range either way): beyond 2^52 the contracted v log2(e) - n keeps the
+// product's rounding error, which can exceed the range of 2^f.  Double: the
+// library exp.
 MWU_DEV float exp_arg(double v, float)
 {
-    const double a = v * 1.4426950408889634;
+    const double a = fmin(fmax(v, -1.0e4), 1.0e4) * 1.4426950408889634;
     const double n = rint(a);
     return ldexpf(__builtin_amdgcn_exp2f((float)(a - n)), (int)fmax(n, -300.0));
 }
@@ -547,6 +550,24 @@ MWU_DEV void fold_cov_compact(const double *part, int G, double *s_wave, double 
 
 struct Eval { double psi, phi, zmin; int ok; };
 
+// eta (z - L) beyond which a covering weight exp(-eta (z - L)) is exactly
+// zero in the storage type (below half the smallest subnormal).
+template <class T>
+constexpr double zero_weight_exponent()
+{
+    return sizeof(T) == 4 ? 106.0 : 746.0;
+}
+
+// The active lists of the sparse passes hold every covering row whose weight
+// can be nonzero while the weight shift Lw has moved by at most act_mu / eta
+// since they were built: z only grows (x and d are nonnegative), so a row
+// left out then still has eta (z - Lw) above the zero-weight exponent.
+// Evaluation mode always takes the full lists.
+MWU_DEV bool act_valid(const Ctl *c, double Lw)
+{
+    return c->act_on && !c->eval_mode && c->eta * (Lw - c->act_L) <= c->act_mu;
+}
+
 // A finisher's state update is one thread walking long dependent chains of
 // control-block fields (the replay above all); from device memory every link
 // costs an L2 round trip.  The workgroup stages the block in LDS with one
@@ -584,6 +605,10 @@ MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
     } else {
         const double s1 = c->rS1C[k] * c->invSu;
         e.zmin = c->rZmin[k];
+        // a pass over the active list gives the minima of the active rows; a
+        // left-out row can only decide min z' >= 1 when it started below 1,
+        // and then the full-list refinement settles it
+        if (c->pass_sparse && e.zmin >= 1.0 && c->act_zfloor < 1.0) e.ok = 0;
         if (1.0 + s1 >= 0.5) {
             e.phi = -log1p(s1) / c->eta;
         } else {

@@ -87,6 +87,13 @@ struct Ctl {
     double sumx;                // sum of x (init / final statistics)
     double *trace;              // nullable device array: accepted step of each iteration
     int32_t trace_cap, pad3;
+    // ---- sparse passes (fused vertex cover): covering rows whose weight is
+    // exactly zero in the storage type are left out of the passes
+    int32_t act_on, act_ne;     // lists built; edges in the active search list
+    int32_t pass_sparse, pad5;  // the last search pass ran over the active list
+    double act_L;               // weight shift the lists were built against
+    double act_mu;              // eta * (shift drift) the lists stay valid for
+    double act_zfloor;          // min z over the left-out edges when the lists were built
     // ---- search state (replay of Algorithm 3)
     int32_t skind, ncand, amode, have_cur;
     double cand[KC];
@@ -156,6 +163,9 @@ struct VcDev {
     T *h;                               // unnormalized C^T u per vertex
     double *h_dbg;                      // nullable
     const double *forced;
+    // sparse passes: fcol with left-out neighbours marked (bit 31), the active
+    // edges of the search in edge-list order, per-block counts of the build
+    int32_t *fcol_act, *aeu, *aew, *acnt;
 };
 
 // Fused densest-subgraph program: variables z_{2e}, z_{2e+1} are the two ends
@@ -288,6 +298,7 @@ struct VcLaunch {
     int grid_v;        // element-wise over vertices
     int grid_ftile;    // full-adjacency tiles
     int grid_e;        // edge passes (search, min z, export)
+    int grid_act;      // blocks of the active-list build (contiguous edge ranges)
     double *partials;
 };
 template <class T> void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,
@@ -296,6 +307,9 @@ template <class T> void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch
 template <class T> void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
 template <class T> void vc_passB(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
 template <class T> void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);
+// Build the active lists against the current weight shift (margin mu).
+template <class T> void vc_build_active(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,
+                                        double mu);
 // which: 0 = x, 1 = d (vertex vectors, double out); 2 = z, 3 = dz (edge vectors, canonical order)
 template <class T> void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st);
 template <class T> void vc_import_x(const VcDev<T> &v, const double *src, hipStream_t st);

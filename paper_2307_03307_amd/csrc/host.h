@@ -90,6 +90,9 @@ struct Program {
     // 2 forward, 3 search): every index once, every dense vector once, every output once.
     virtual double algo_bytes(int which) const = 0;
     virtual double pass_nnz(int which) const = 0;
+    // Called by the probe driver after every graph launch with the pulled
+    // control block; may enqueue work on the solver stream before the next.
+    virtual void between_launches(const Ctl &) {}
     // Level-set rounding of the current vertex loads (densest subgraph):
     // false when the program has no such structure (the host computes it).
     virtual bool level_set_density(double *) { return false; }

@@ -93,6 +93,9 @@ class VcoverProgram : public Program {
         up(flfirst_, ft.lfirst.data(), ft.lfirst.size() * 4);
         up(flcount_, ft.lcount.data(), ft.lcount.size() * 4);
         flpart_.alloc(std::max<int32_t>(ft.nslots, 1) * sizeof(T));
+        fcol_act_.alloc(fcol.size() * 4);
+        aeu_.alloc(std::max<int64_t>(ne_, 1) * 4);
+        aew_.alloc(std::max<int64_t>(ne_, 1) * 4);
         xd_.alloc(nv * sizeof(XD<T>));
         xbest_.alloc(nv * sizeof(XD<T>));
         h_.alloc(nv * sizeof(T));
@@ -110,6 +113,8 @@ class VcoverProgram : public Program {
         vd_.flpart = flpart_.as<T>();
         vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>(); vd_.xs = xs_.as<T>();
         vd_.h_dbg = nullptr; vd_.forced = nullptr;
+        vd_.fcol_act = fcol_act_.as<int32_t>();
+        vd_.aeu = aeu_.as<int32_t>(); vd_.aew = aew_.as<int32_t>();
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
             return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
@@ -122,6 +127,9 @@ class VcoverProgram : public Program {
         // (at most 4 per CU: measured faster than 5 for the FP32 search, whose
         // per-workgroup combine is then amortized over more edges)
         L_.grid_e = clampg(ne_, BLOCK * 8, std::min<int64_t>(GRID_MAX, (int64_t)std::min(occ_e, 4) * s.num_cus));
+        L_.grid_act = clampg(ne_, BLOCK * 16, GRID_MAX);
+        acnt_.alloc((size_t)L_.grid_act * 4);
+        vd_.acnt = acnt_.as<int32_t>();
         L_.partials = partials_.as<double>();
     }
 
@@ -149,6 +157,24 @@ class VcoverProgram : public Program {
     }
 
     void final_stats() override { vc_init<T>(vd_, ctl(), L_, s_.stream, true); }
+
+    // Active lists of the sparse passes: built once a probe has run a few
+    // iterations, rebuilt when the weight shift has used half the margin (the
+    // passes fall back to the full lists once it is used up).  A build whose
+    // lists keep most edges is not repeated until they expire.
+    void between_launches(const Ctl &c) override
+    {
+        if (c.eval_mode || c.hold || c.status != ST_RUNNING || c.phase == PH_DONE) return;
+        if (c.iter < kActFirstIter) return;
+        if (c.act_on) {
+            const double drift = c.eta * (c.LC - c.act_L);
+            if (drift <= 0.5 * kActMu) return;
+            const bool dense = (double)c.act_ne > kActDense * (double)ne_;
+            if (dense && (drift <= kActMu || c.iter - built_iter_ < kActFirstIter)) return;
+        }
+        vc_build_active<T>(vd_, ctl(), L_, s_.stream, kActMu);
+        built_iter_ = c.iter;
+    }
 
     void save_best() override
     {
@@ -289,15 +315,19 @@ class VcoverProgram : public Program {
         return canon_;
     }
 
+    static constexpr double kActMu = 32.0;       // margin, in units of 1 / eta
+    static constexpr int kActFirstIter = 16;
+    static constexpr double kActDense = 0.8;
     Solver &s_;
     int64_t nv_ = 0, ne_ = 0;
+    int64_t built_iter_ = 0;
     bool debug_ = false;
     VcDev<T> vd_{};
     VcLaunch L_{};
     std::vector<int32_t> dev_;     // compact vertex id -> device vertex id
     std::vector<int64_t> canon_;
     DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
-    DevBuf xd_, xs_, xbest_, h_, partials_, forced_, hdbg_;
+    DevBuf xd_, xs_, xbest_, h_, partials_, forced_, hdbg_, fcol_act_, aeu_, aew_, acnt_;
 };
 
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,

@@ -483,6 +483,7 @@ static void run_probe(Solver &s, int64_t max_iters)
         if (s.ctl_host->iter - start >= max_iters) break;
         HIP_OK(hipGraphLaunch(s.graph, s.stream));
         pull_ctl(s);
+        s.prog->between_launches(*s.ctl_host);
     }
 }
 

@@ -88,27 +88,35 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
     __syncthreads();
 }
 
-// Visit every edge once: visit(x_d of u, x_d of w, e).  Grid-stride over the
-// edge list, U edges per step so that their gathers are in flight together
-// (fewer in FP64, where the search accumulators take twice the registers).
+// Visit every edge of the list (eu, ew, ne) once: visit(x_d of u, x_d of w,
+// e).  Grid-stride over the list, U edges per step so that their gathers are
+// in flight together (fewer in FP64, where the search accumulators take twice
+// the registers).
 template <class T, class VisitF>
-MWU_DEV void for_edges(const VcDev<T> &vd, VisitF &visit)
+MWU_DEV void for_edge_list(const VcDev<T> &vd, const int32_t *__restrict__ eu, const int32_t *__restrict__ ew,
+                           int ne, VisitF &visit)
 {
     constexpr int U = sizeof(T) == 4 ? 3 : 2;
     const int stride = gridDim.x * BLOCK;
     int e = blockIdx.x * BLOCK + threadIdx.x;
-    const int ne = vd.ne;
     for (; e + (U - 1) * stride < ne; e += U * stride) {
         int iu[U], iw[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) { iu[j] = vd.eu[e + j * stride]; iw[j] = vd.ew[e + j * stride]; }
+        for (int j = 0; j < U; ++j) { iu[j] = eu[e + j * stride]; iw[j] = ew[e + j * stride]; }
         XD<T> pu[U], pw[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) { pu[j] = vd.xd[iu[j]]; pw[j] = vd.xd[iw[j]]; }
 #pragma unroll
         for (int j = 0; j < U; ++j) visit(pu[j], pw[j], e + j * stride);
     }
-    for (; e < ne; e += stride) visit(vd.xd[vd.eu[e]], vd.xd[vd.ew[e]], e);
+    for (; e < ne; e += stride) visit(vd.xd[eu[e]], vd.xd[ew[e]], e);
+}
+
+// Every edge of the graph.
+template <class T, class VisitF>
+MWU_DEV void for_edges(const VcDev<T> &vd, VisitF &visit)
+{
+    for_edge_list<T>(vd, vd.eu, vd.ew, vd.ne, visit);
 }
 
 // ------------------------------------------------------------------ finishers
@@ -254,9 +262,18 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     if (ctl->phase != PH_ROW) return;
     const double eta = ctl->eta, Lw = ctl->LC;
     double v[2] = {0.0, INFINITY};   // sum h | min z
-    auto stage = [&](int k) -> T { return vd.xs[vd.fcol[k]]; };
+    // Left-out neighbours are not gathered: they stage -1 (x is never
+    // negative) and give the weight 0 they would give from their own x.  They
+    // never hold the minimum either, which an active row always does (eta
+    // (min z - Lw) stays below ln m).
+    const int32_t *__restrict__ fc = act_valid(ctl, Lw) ? vd.fcol_act : vd.fcol;
+    auto stage = [&](int k) -> T {
+        const int32_t c = fc[k];
+        return c >= 0 ? vd.xs[c] : T(-1);
+    };
     auto segval = [&](int u) -> T { return vd.xs[u]; };
     auto term = [&](T xu, T xw) -> T {
+        if (xw < T(0)) return T(0);
         const double z = (double)xu + (double)xw;
         v[1] = fmin(v[1], z);
         return exp_arg(-eta * (z - Lw), T(0));
@@ -366,7 +383,8 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
         const T u = exp_arg(-eta * (zd - Lw), T(0));
         cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
     };
-    for_edges<T>(vd, visit);
+    if (act_valid(ctl, Lw)) for_edge_list<T>(vd, vd.aeu, vd.aew, ctl->act_ne, visit);
+    else for_edges<T>(vd, visit);
     ca.template combine_compact<KIND>(s_wave, s_rec);
 }
 
@@ -451,6 +469,7 @@ __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *p
     }
     on_ctl(ctl, [&](Ctl *c) {
         for (int k = 0; k < KC; ++k) s_rec[k] = 0.0;   // no packing rows: Psi = a * dy1
+        c->pass_sparse = act_valid(c, c->LCw);          // as the search kernel decided
         finish_search(c, s_rec);
     });
 }
@@ -478,6 +497,164 @@ __global__ void vc_import_k(VcDev<T> vd, const double *src)
         p.d = T(0);
         vd.xd[i] = p;
         vd.xs[i] = p.x;
+    }
+}
+
+// ------------------------------------------------------------------ active lists
+// Built between graph launches against the current weight shift L = LC with
+// margin mu: a covering row (edge) is left out when eta (z_e - L) exceeds the
+// zero-weight exponent plus mu, z_e from the committed x (z only grows, so
+// this stays true while the shift drifts by less than mu / eta).
+
+template <class T>
+MWU_DEV bool left_out(double z, double eta, double L, double mu)
+{
+    return eta * (z - L) > zero_weight_exponent<T>() + mu;
+}
+
+// Mark the left-out neighbours of every row of the full adjacency (bit 31 of
+// fcol_act), tile by tile.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_mark_k(VcDev<T> vd, const Ctl *ctl, double mu)
+{
+    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    const double eta = ctl->eta, L = ctl->LC;
+    for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
+        const Tile tl = vd.ftiles[t];
+        if (tl.lid >= 0) {   // chunk of one long row
+            const double xu = (double)vd.xs[tl.s0];
+            for (int k = tl.k0 + threadIdx.x; k < tl.k1; k += BLOCK) {
+                const int32_t c = vd.fcol[k];
+                vd.fcol_act[k] = left_out<T>(xu + (double)vd.xs[c], eta, L, mu) ? (c | INT32_MIN) : c;
+            }
+            continue;
+        }
+        const int S_ = tl.s1 - tl.s0;
+        const int N = tl.k1 - tl.k0;
+        for (int i = threadIdx.x; i <= S_; i += BLOCK) s_ptr[i] = vd.fptr[tl.s0 + i] - tl.k0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < N; k += BLOCK) {
+            int lo = 0, hi = S_;   // s_ptr[lo] <= k < s_ptr[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_ptr[mid] <= k) lo = mid; else hi = mid;
+            }
+            const int32_t c = vd.fcol[tl.k0 + k];
+            const double z = (double)vd.xs[tl.s0 + lo] + (double)vd.xs[c];
+            vd.fcol_act[tl.k0 + k] = left_out<T>(z, eta, L, mu) ? (c | INT32_MIN) : c;
+        }
+        __syncthreads();
+    }
+}
+
+// Edge range of block b in the active-list build: contiguous, whole waves.
+MWU_DEV void act_range(int ne, int &e0, int &e1)
+{
+    const int G = gridDim.x;
+    const int ch = ((ne + G - 1) / G + BLOCK - 1) / BLOCK * BLOCK;
+    e0 = min(ne, blockIdx.x * ch);
+    e1 = min(ne, e0 + ch);
+}
+
+// Per block: active edges of its range, and min z over the left-out ones.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_act_count_k(VcDev<T> vd, const Ctl *ctl, double mu, double *part)
+{
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_rec[QMAX];
+    const double eta = ctl->eta, L = ctl->LC;
+    int e0, e1;
+    act_range(vd.ne, e0, e1);
+    double v[2] = {0.0, INFINITY};   // active count | min z left out
+    for (int e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        const double z = (double)vd.xs[vd.eu[e]] + (double)vd.xs[vd.ew[e]];
+        if (left_out<T>(z, eta, L, mu)) v[1] = fmin(v[1], z);
+        else v[0] += 1.0;
+    }
+    const Red red{1, 1, 0};
+    block_combine<2>(v, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) vd.acnt[blockIdx.x] = (int32_t)s_rec[0];
+    store_record(s_rec, 2, part);
+}
+
+// One workgroup: exclusive scan of the block counts (in place), the list
+// length, the floor of the left-out minima, and the lists switched on.
+__global__ __launch_bounds__(BLOCK) void vc_act_scan_k(int32_t *acnt, int G, Ctl *ctl, const double *part,
+                                                       double mu)
+{
+    __shared__ int32_t s_sum[BLOCK];
+    __shared__ double s_wave[4];
+    __shared__ double s_rec[QMAX];
+    const int per = (G + BLOCK - 1) / BLOCK;
+    const int i0 = min(G, threadIdx.x * per), i1 = min(G, i0 + per);
+    int tot = 0;
+    for (int i = i0; i < i1; ++i) tot += acnt[i];
+    s_sum[threadIdx.x] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < BLOCK; ++t) {
+            const int c = s_sum[t];
+            s_sum[t] = run;
+            run += c;
+        }
+        ctl->act_ne = run;
+    }
+    __syncthreads();
+    int run = s_sum[threadIdx.x];
+    for (int i = i0; i < i1; ++i) {
+        const int c = acnt[i];
+        acnt[i] = run;
+        run += c;
+    }
+    const Red red{0, 1, 0};
+    double v[1] = {INFINITY};
+    for (int b = threadIdx.x; b < G; b += BLOCK) v[0] = fmin(v[0], part[(size_t)b * QMAX + 1]);
+    block_combine<1>(v, red, 0, s_wave, s_rec);
+    if (threadIdx.x == 0) {
+        ctl->act_zfloor = s_rec[0];
+        ctl->act_L = ctl->LC;
+        ctl->act_mu = mu;
+        ctl->act_on = 1;
+    }
+}
+
+// Scatter the active edges of each block's range to its offset, in order.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_act_scatter_k(VcDev<T> vd, const Ctl *ctl, double mu)
+{
+    __shared__ int32_t s_cnt[BLOCK / 64];
+    const double eta = ctl->eta, L = ctl->act_L;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int e0, e1;
+    act_range(vd.ne, e0, e1);
+    int base = vd.acnt[blockIdx.x];
+    for (int c0 = e0; c0 < e1; c0 += BLOCK) {
+        const int e = c0 + threadIdx.x;
+        int u = 0, w = 0;
+        bool keep = false;
+        if (e < e1) {
+            u = vd.eu[e];
+            w = vd.ew[e];
+            keep = !left_out<T>((double)vd.xs[u] + (double)vd.xs[w], eta, L, mu);
+        }
+        const unsigned long long m = __ballot(keep);
+        if (lane == 0) s_cnt[wv] = __popcll(m);
+        __syncthreads();
+        int off = 0, total = 0;
+        for (int q = 0; q < BLOCK / 64; ++q) {
+            if (q < wv) off += s_cnt[q];
+            total += s_cnt[q];
+        }
+        if (keep) {
+            const int pos = base + off + __popcll(m & ((1ull << lane) - 1ull));
+            if (pos < vd.ne) {   // always: the count pass made the same decisions
+                vd.aeu[pos] = u;
+                vd.aew[pos] = w;
+            }
+        }
+        base += total;
+        __syncthreads();
     }
 }
 
@@ -530,6 +707,15 @@ void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st
 }
 
 template <class T>
+void vc_build_active(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, double mu)
+{
+    VLAUNCH(vc_mark_k<T>, L.grid_ftile, v, ctl, mu);
+    VLAUNCH(vc_act_count_k<T>, L.grid_act, v, ctl, mu, L.partials);
+    VLAUNCH(vc_act_scan_k, 1, v.acnt, L.grid_act, ctl, (const double *)L.partials, mu);
+    VLAUNCH(vc_act_scatter_k<T>, L.grid_act, v, ctl, mu);
+}
+
+template <class T>
 void vc_export(const VcDev<T> &v, int which, double *out, hipStream_t st)
 {
     const int g = which < 2 ? std::max(1, std::min(GRID_MAX, (v.nv + BLOCK - 1) / BLOCK))
@@ -574,6 +760,7 @@ void vc_occupancy(int *per_cu_ftile, int *per_cu_edge)
     template void vc_passA<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);           \
     template void vc_passB<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);           \
     template void vc_search<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t);          \
+    template void vc_build_active<T>(const VcDev<T> &, Ctl *, const VcLaunch &, hipStream_t, double); \
     template void vc_export<T>(const VcDev<T> &, int, double *, hipStream_t);                    \
     template void vc_import_x<T>(const VcDev<T> &, const double *, hipStream_t);                 \
     template void vc_occupancy<T>(int *, int *);                                                  \
