@@ -129,6 +129,48 @@ MWU_DEV void store_record(const double *s_rec, int Q, double *partials)
     if (threadIdx.x < Q) partials[(size_t)blockIdx.x * QMAX + threadIdx.x] = s_rec[threadIdx.x];
 }
 
+// Records stored entry-major (entry q of workgroup b at q * G + b, G the
+// grid): a finisher then reads each entry of all records with full-width
+// coalesced loads, which matters for records of dozens of entries.
+MWU_DEV void store_record_qmajor(const double *s_rec, int Q, double *partials)
+{
+    if (threadIdx.x < Q) partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_rec[threadIdx.x];
+}
+
+template <int Q>
+MWU_DEV void fold_records_qmajor(const double *partials, int G, Red r, double *s_wave, double *out)
+{
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = red_id(q, r);
+    for (int b = threadIdx.x; b < G; b += BLOCK) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], partials[(size_t)q * G + b], q, r);
+    }
+    block_combine<Q>(v, r, 0, s_wave, out);
+}
+
+// First stage of a two-level fold: workgroup j of the F = gridDim.x folds
+// the entry-major records [G j / F, G (j + 1) / F) into record j of an
+// entry-major array of F records, so the one-workgroup finisher reads F
+// records instead of G.
+template <int Q>
+MWU_DEV void fold_stage_qmajor(const double *partials, int G, Red r, double *s_wave, double *s_out,
+                               double *out)
+{
+    const int F = gridDim.x, j = blockIdx.x;
+    const int b0 = (int)((int64_t)G * j / F), b1 = (int)((int64_t)G * (j + 1) / F);
+    double v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = red_id(q, r);
+    for (int b = b0 + threadIdx.x; b < b1; b += BLOCK) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], partials[(size_t)q * G + b], q, r);
+    }
+    block_combine<Q>(v, r, 0, s_wave, s_out);
+    if (threadIdx.x < Q) out[(size_t)threadIdx.x * F + j] = s_out[threadIdx.x];
+}
+
 // Fold the G records of a pass (finisher kernel, one workgroup): thread t
 // folds whole records t, t + BLOCK, ... in order (all Q loads of a record in
 // flight at once), then the block combines.  Record entry q is reduced with
@@ -523,7 +565,17 @@ constexpr int cov_record_q()
     return 2 * pass_cands<KIND>() + pass_minima<KIND>();
 }
 
-// Finisher side of the compact records: fold them and spread the totals to
+// First stage of the fold of compact covering records (see fold_stage_qmajor).
+template <int KIND>
+MWU_DEV void fold_cov_stage(const double *part, int G, double *s_wave, double *s_tmp, double *out)
+{
+    constexpr int N = pass_cands<KIND>(), M = pass_minima<KIND>();
+    const Red r{2 * N, M, 0};
+    fold_stage_qmajor<cov_record_q<KIND>()>(part, G, r, s_wave, s_tmp, out);
+}
+
+// Finisher side of the compact records (stored entry-major): fold them and
+// spread the totals to
 // out = [s1C(KC) | s2C(KC) | zmin(KC)] (sums the pass did not form are 0,
 // minima it did not form -inf, which no early return can take).  All threads
 // call; out is complete on return.
@@ -532,7 +584,7 @@ MWU_DEV void fold_cov_compact(const double *part, int G, double *s_wave, double 
 {
     constexpr int N = pass_cands<KIND>(), M = pass_minima<KIND>();
     const Red r{2 * N, M, 0};
-    fold_records<cov_record_q<KIND>()>(part, G, r, 0, s_wave, s_tmp);
+    fold_records_qmajor<cov_record_q<KIND>()>(part, G, r, s_wave, s_tmp);
     for (int k = threadIdx.x; k < KC; k += blockDim.x) {
         out[k] = k < N ? s_tmp[k] : 0.0;
         out[KC + k] = k < N ? s_tmp[N + k] : 0.0;
@@ -573,6 +625,29 @@ MWU_DEV bool act_valid(const Ctl *c, double Lw)
 // costs an L2 round trip.  The workgroup stages the block in LDS with one
 // load per thread, thread 0 runs f on the copy, and the workgroup writes the
 // whole block back.  All threads of the workgroup must call.
+template <class F>
+MWU_DEV void on_ctl(Ctl *g, F &&f);
+
+// The same with a step all threads run on the staged copy first (it
+// synchronizes on its own where it needs to).
+template <class P, class F>
+MWU_DEV void on_ctl_all(Ctl *g, P &&pre, F &&f)
+{
+    static_assert(sizeof(Ctl) % 8 == 0, "control block is copied in 8-byte words");
+    constexpr int W = sizeof(Ctl) / 8;
+    __shared__ uint64_t s_ctl[W];
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(g);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) s_ctl[i] = src[i];
+    __syncthreads();
+    Ctl *c = reinterpret_cast<Ctl *>(s_ctl);
+    pre(c);
+    __syncthreads();
+    if (threadIdx.x == 0) f(c);
+    __syncthreads();
+    uint64_t *dst = reinterpret_cast<uint64_t *>(g);
+    for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = s_ctl[i];
+}
+
 template <class F>
 MWU_DEV void on_ctl(Ctl *g, F &&f)
 {
@@ -725,10 +800,37 @@ MWU_DEV int lookup(const Ctl *c, double a, Eval *e)
     }
     for (int k = 0; k < c->ncand; ++k)
         if (c->cand[k] == a) {
-            *e = eval_cand(c, k, a);
+            if (c->ev_cached) {
+                e->psi = c->ev_psi[k]; e->phi = c->ev_phi[k]; e->zmin = c->ev_zmin[k]; e->ok = c->ev_ok[k];
+            } else {
+                *e = eval_cand(c, k, a);
+            }
             return e->ok ? 0 : 2;
         }
     return 1;
+}
+
+// Store the reduced record of a grid or list pass and evaluate all its
+// candidates at once, candidate k on lane k, into the ev_ arrays: the
+// sequential replay then reads them instead of forming each logarithm on one
+// lane.  All threads of the finisher call, with c staged in LDS; follow with
+// finish_search(c, rec, true) on one thread.
+MWU_DEV void pre_eval_search(Ctl *c, const double *rec)
+{
+    const int k = threadIdx.x;
+    if (k < KC) {
+        c->rS1P[k] = rec[k];
+        c->rS1C[k] = rec[KC + k];
+        c->rS2C[k] = rec[2 * KC + k];
+        c->rZmin[k] = rec[3 * KC + k];
+    }
+    __syncthreads();
+    if (k < c->ncand) {
+        const Eval e = eval_cand(c, k, c->cand[k]);
+        c->ev_psi[k] = e.psi; c->ev_phi[k] = e.phi; c->ev_zmin[k] = e.zmin; c->ev_ok[k] = e.ok;
+    }
+    if (k == 0) c->ev_cached = 1;
+    __syncthreads();
 }
 
 constexpr double ALPHA_CAP = 1125899906842624.0;   // 2^50
@@ -810,7 +912,7 @@ MWU_DEV void begin_search(Ctl *c, const double *forced)
 // Store the reduced record of a search pass and advance the state machine.
 // rec layout: grid passes [s1P(KC) | s1C(KC) | s2C(KC) | zmin'(KC)];
 // refine pass 1 [min z' | max eta*y']; refine pass 2 [sumP | sumC].
-MWU_DEV void finish_search(Ctl *c, const double *rec)
+MWU_DEV void finish_search(Ctl *c, const double *rec, bool pre_evaluated = false)
 {
     if (held(c)) return;
     c->search_passes += 1;
@@ -833,13 +935,14 @@ MWU_DEV void finish_search(Ctl *c, const double *rec)
             const int k = c->ev_cur;
             c->ev_psi[k] = psi; c->ev_phi[k] = phi; c->ev_zmin[k] = zmn; c->ev_ok[k] = 1;
         }
-    } else {
+    } else if (!pre_evaluated) {
         for (int k = 0; k < KC; ++k) {
             c->rS1P[k] = rec[k];
             c->rS1C[k] = rec[KC + k];
             c->rS2C[k] = rec[2 * KC + k];
             c->rZmin[k] = rec[3 * KC + k];
         }
+        c->ev_cached = 0;
         if (c->eval_mode) {
             for (int k = 0; k < c->ncand; ++k) {
                 Eval e = eval_cand(c, k, c->cand[k]);

@@ -90,7 +90,8 @@ struct Ctl {
     // ---- sparse passes (fused vertex cover): covering rows whose weight is
     // exactly zero in the storage type are left out of the passes
     int32_t act_on, act_ne;     // lists built; edges in the active search list
-    int32_t pass_sparse, pad5;  // the last search pass ran over the active list
+    int32_t pass_sparse;        // the last search pass ran over the active list
+    int32_t ev_cached;          // ev_* hold the evaluations of the last grid or list pass
     double act_L;               // weight shift the lists were built against
     double act_mu;              // eta * (shift drift) the lists stay valid for
     double act_zfloor;          // min z over the left-out edges when the lists were built
@@ -300,7 +301,9 @@ struct VcLaunch {
     int grid_e;        // edge passes (search, min z, export)
     int grid_act;      // blocks of the active-list build (contiguous edge ranges)
     double *partials;
+    double *partials2; // first-stage folds of the search records (SEARCH_FOLD records)
 };
+constexpr int SEARCH_FOLD = 16;   // workgroups of the first stage of the search fold
 template <class T> void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,
                                 bool have_x0);
 template <class T> void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);

@@ -416,19 +416,19 @@ __device__ __forceinline__ void vc_search_body(const VcDev<T> &vd, Ctl *ctl, dou
     switch (kind) {
     case SK_EXP:
         vc_search_edges<T, SK_EXP>(vd, ctl, s_wave, s_rec);
-        store_record(s_rec, cov_record_q<SK_EXP>(), part);
+        store_record_qmajor(s_rec, cov_record_q<SK_EXP>(), part);
         break;
     case SK_GRID:
         vc_search_edges<T, SK_GRID>(vd, ctl, s_wave, s_rec);
-        store_record(s_rec, cov_record_q<SK_GRID>(), part);
+        store_record_qmajor(s_rec, cov_record_q<SK_GRID>(), part);
         break;
     case SK_COMBO:
         vc_search_edges<T, SK_COMBO>(vd, ctl, s_wave, s_rec);
-        store_record(s_rec, cov_record_q<SK_COMBO>(), part);
+        store_record_qmajor(s_rec, cov_record_q<SK_COMBO>(), part);
         break;
     default:
         vc_search_edges<T, SK_LIST>(vd, ctl, s_wave, s_rec);
-        store_record(s_rec, cov_record_q<SK_LIST>(), part);
+        store_record_qmajor(s_rec, cov_record_q<SK_LIST>(), part);
         break;
     }
 }
@@ -443,7 +443,24 @@ template <>
 __global__ __launch_bounds__(BLOCK)
 void vc_search_k<double>(VcDev<double> vd, Ctl *ctl, double *part) { vc_search_body<double>(vd, ctl, part); }
 
-__global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G)
+// First stage of the fold of the search records (grid and list passes; the
+// records of a refinement pass are folded by the finisher directly).
+__global__ __launch_bounds__(BLOCK) void vc_search_fold(const Ctl *ctl, const double *part, int G, double *part2)
+{
+    __shared__ double s_wave[4 * 3 * KC];
+    __shared__ double s_tmp[QMAX];
+    if (ctl->phase != PH_SEARCH || ctl->skind == SK_REFINE) return;
+    switch (ctl->skind) {
+    case SK_EXP: fold_cov_stage<SK_EXP>(part, G, s_wave, s_tmp, part2); break;
+    case SK_GRID: fold_cov_stage<SK_GRID>(part, G, s_wave, s_tmp, part2); break;
+    case SK_COMBO: fold_cov_stage<SK_COMBO>(part, G, s_wave, s_tmp, part2); break;
+    default: fold_cov_stage<SK_LIST>(part, G, s_wave, s_tmp, part2); break;
+    }
+}
+
+// part: the records of the search kernel (G of them); part2: the first-stage
+// folds (SEARCH_FOLD of them) of a grid or list pass.
+__global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G, const double *part2)
 {
     __shared__ double s_wave[4 * 3 * KC];
     __shared__ double s_rec[QMAX];
@@ -462,16 +479,18 @@ __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *p
     }
     __shared__ double s_tmp[QMAX];
     switch (ctl->skind) {
-    case SK_EXP: fold_cov_compact<SK_EXP>(part, G, s_wave, s_tmp, s_rec + KC); break;
-    case SK_GRID: fold_cov_compact<SK_GRID>(part, G, s_wave, s_tmp, s_rec + KC); break;
-    case SK_COMBO: fold_cov_compact<SK_COMBO>(part, G, s_wave, s_tmp, s_rec + KC); break;
-    default: fold_cov_compact<SK_LIST>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    case SK_EXP: fold_cov_compact<SK_EXP>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
+    case SK_GRID: fold_cov_compact<SK_GRID>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
+    case SK_COMBO: fold_cov_compact<SK_COMBO>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
+    default: fold_cov_compact<SK_LIST>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
     }
-    on_ctl(ctl, [&](Ctl *c) {
-        for (int k = 0; k < KC; ++k) s_rec[k] = 0.0;   // no packing rows: Psi = a * dy1
-        c->pass_sparse = act_valid(c, c->LCw);          // as the search kernel decided
-        finish_search(c, s_rec);
-    });
+    auto pre = [&](Ctl *c) {
+        if (threadIdx.x < KC) s_rec[threadIdx.x] = 0.0;     // no packing rows: Psi = a * dy1
+        if (threadIdx.x == 0) c->pass_sparse = act_valid(c, c->LCw);   // as the search kernel decided
+        __syncthreads();
+        if (!c->hold) pre_eval_search(c, s_rec);
+    };
+    on_ctl_all(ctl, pre, [&](Ctl *c) { finish_search(c, s_rec, true); });
 }
 
 template <class T>
@@ -691,7 +710,8 @@ template <class T>
 void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
     VLAUNCH(vc_search_k<T>, L.grid_e, v, ctl, L.partials);
-    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_e);
+    VLAUNCH(vc_search_fold, SEARCH_FOLD, ctl, (const double *)L.partials, L.grid_e, L.partials2);
+    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_e, (const double *)L.partials2);
 }
 
 // One iteration slot with a single search launch: most iterations finish
