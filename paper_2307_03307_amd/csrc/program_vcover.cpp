@@ -317,7 +317,7 @@ class VcoverProgram : public Program {
         return canon_;
     }
 
-    static constexpr double kActMu = 32.0;       // margin, in units of 1 / eta
+    static constexpr double kActMu = 64.0;       // margin, in units of 1 / eta
     static constexpr int kActFirstIter = 16;
     static constexpr double kActDense = 0.8;
     Solver &s_;
