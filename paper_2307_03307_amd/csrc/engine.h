@@ -164,9 +164,11 @@ struct VcDev {
     T *h;                               // unnormalized C^T u per vertex
     double *h_dbg;                      // nullable
     const double *forced;
-    // sparse passes: fcol with left-out neighbours marked (bit 31), the active
-    // edges of the search in edge-list order, per-block counts of the build
-    int32_t *fcol_act, *aeu, *aew, *acnt;
+    // sparse passes: the active neighbours of each adjacency tile packed at
+    // the start of its range, the packed row starts and the tiles' active
+    // counts; the active edges of the search in edge-list order; per-block
+    // counts of the build
+    int32_t *fcol_pk, *fptr_pk, *tile_na, *aeu, *aew, *acnt;
 };
 
 // Fused densest-subgraph program: variables z_{2e}, z_{2e+1} are the two ends

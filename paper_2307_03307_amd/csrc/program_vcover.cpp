@@ -93,7 +93,9 @@ class VcoverProgram : public Program {
         up(flfirst_, ft.lfirst.data(), ft.lfirst.size() * 4);
         up(flcount_, ft.lcount.data(), ft.lcount.size() * 4);
         flpart_.alloc(std::max<int32_t>(ft.nslots, 1) * sizeof(T));
-        fcol_act_.alloc(fcol.size() * 4);
+        fcol_pk_.alloc(fcol.size() * 4);
+        fptr_pk_.alloc((size_t)(nv + 1) * 4);
+        tile_na_.alloc(std::max<size_t>(ft.tiles.size(), 1) * 4);
         aeu_.alloc(std::max<int64_t>(ne_, 1) * 4);
         aew_.alloc(std::max<int64_t>(ne_, 1) * 4);
         xd_.alloc(nv * sizeof(XD<T>));
@@ -113,7 +115,9 @@ class VcoverProgram : public Program {
         vd_.flpart = flpart_.as<T>();
         vd_.xd = xd_.as<XD<T>>(); vd_.h = h_.as<T>(); vd_.xs = xs_.as<T>();
         vd_.h_dbg = nullptr; vd_.forced = nullptr;
-        vd_.fcol_act = fcol_act_.as<int32_t>();
+        vd_.fcol_pk = fcol_pk_.as<int32_t>();
+        vd_.fptr_pk = fptr_pk_.as<int32_t>();
+        vd_.tile_na = tile_na_.as<int32_t>();
         vd_.aeu = aeu_.as<int32_t>(); vd_.aew = aew_.as<int32_t>();
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
@@ -329,7 +333,7 @@ class VcoverProgram : public Program {
     std::vector<int32_t> dev_;     // compact vertex id -> device vertex id
     std::vector<int64_t> canon_;
     DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
-    DevBuf xd_, xs_, xbest_, h_, partials_, partials2_, forced_, hdbg_, fcol_act_, aeu_, aew_, acnt_;
+    DevBuf xd_, xs_, xbest_, h_, partials_, partials2_, forced_, hdbg_, fcol_pk_, fptr_pk_, tile_na_, aeu_, aew_, acnt_;
 };
 
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,

@@ -36,7 +36,8 @@ MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, Stag
     const int S_ = tl.s1 - tl.s0;
     const int base = tl.k0;
     const int N = tl.k1 - tl.k0;
-    for (int i = tid; i <= S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+    for (int i = tid; i < S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
+    if (tid == 0) s_ptr[S_] = N;   // = ptr[s1] - base in a full layout; packed tiles end early
     for (int i = tid; i < S_; i += BLOCK) s_seg[i] = segval(tl.s0 + i);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -262,18 +263,16 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     if (ctl->phase != PH_ROW) return;
     const double eta = ctl->eta, Lw = ctl->LC;
     double v[2] = {0.0, INFINITY};   // sum h | min z
-    // Left-out neighbours are not gathered: they stage -1 (x is never
-    // negative) and give the weight 0 they would give from their own x.  They
-    // never hold the minimum either, which an active row always does (eta
-    // (min z - Lw) stays below ln m).
-    const int32_t *__restrict__ fc = act_valid(ctl, Lw) ? vd.fcol_act : vd.fcol;
-    auto stage = [&](int k) -> T {
-        const int32_t c = fc[k];
-        return c >= 0 ? vd.xs[c] : T(-1);
-    };
+    // Sparse: each tile's active neighbours packed at the start of its range
+    // (fptr_pk, fcol_pk, tile_na); left-out ones have weight 0 and never hold
+    // the minimum, which an active row always does (eta (min z - Lw) stays
+    // below ln m).
+    const bool sparse = act_valid(ctl, Lw);
+    const int32_t *__restrict__ fc = sparse ? vd.fcol_pk : vd.fcol;
+    const int32_t *__restrict__ fp = sparse ? vd.fptr_pk : vd.fptr;
+    auto stage = [&](int k) -> T { return vd.xs[fc[k]]; };
     auto segval = [&](int u) -> T { return vd.xs[u]; };
     auto term = [&](T xu, T xw) -> T {
-        if (xw < T(0)) return T(0);
         const double z = (double)xu + (double)xw;
         v[1] = fmin(v[1], z);
         return exp_arg(-eta * (z - Lw), T(0));
@@ -283,9 +282,10 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
         v[0] += (double)acc;
     };
     for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
-        const Tile tl = vd.ftiles[t];
+        Tile tl = vd.ftiles[t];
+        if (sparse) tl.k1 = tl.k0 + vd.tile_na[t];
         if (tl.lid < 0) {
-            seg_tile_rows<T, T>(tl, vd.fptr, stage, segval, term, epi, s_val, s_seg, s_ptr);
+            seg_tile_rows<T, T>(tl, fp, stage, segval, term, epi, s_val, s_seg, s_ptr);
         } else {
             const T xu = segval(tl.s0);
             auto elem = [&](int k) -> T { return term(xu, stage(k)); };
@@ -531,38 +531,61 @@ MWU_DEV bool left_out(double z, double eta, double L, double mu)
     return eta * (z - L) > zero_weight_exponent<T>() + mu;
 }
 
-// Mark the left-out neighbours of every row of the full adjacency (bit 31 of
-// fcol_act), tile by tile.
+// Pack the active neighbours of each tile of the full adjacency at the start
+// of the tile's range (fcol_pk, in order), with the packed start of each row
+// of a multi-row tile (fptr_pk) and the active count of every tile (tile_na).
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_mark_k(VcDev<T> vd, const Ctl *ctl, double mu)
+__global__ __launch_bounds__(BLOCK) void vc_pack_k(VcDev<T> vd, const Ctl *ctl, double mu)
 {
     __shared__ int32_t s_ptr[TILE_NZ + 1];
+    __shared__ int32_t s_cnt[BLOCK / 64];
     const double eta = ctl->eta, L = ctl->LC;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
         const Tile tl = vd.ftiles[t];
-        if (tl.lid >= 0) {   // chunk of one long row
-            const double xu = (double)vd.xs[tl.s0];
-            for (int k = tl.k0 + threadIdx.x; k < tl.k1; k += BLOCK) {
-                const int32_t c = vd.fcol[k];
-                vd.fcol_act[k] = left_out<T>(xu + (double)vd.xs[c], eta, L, mu) ? (c | INT32_MIN) : c;
-            }
-            continue;
-        }
+        const bool chunk = tl.lid >= 0;     // a piece of one long row
         const int S_ = tl.s1 - tl.s0;
         const int N = tl.k1 - tl.k0;
-        for (int i = threadIdx.x; i <= S_; i += BLOCK) s_ptr[i] = vd.fptr[tl.s0 + i] - tl.k0;
-        __syncthreads();
-        for (int k = threadIdx.x; k < N; k += BLOCK) {
-            int lo = 0, hi = S_;   // s_ptr[lo] <= k < s_ptr[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_ptr[mid] <= k) lo = mid; else hi = mid;
-            }
-            const int32_t c = vd.fcol[tl.k0 + k];
-            const double z = (double)vd.xs[tl.s0 + lo] + (double)vd.xs[c];
-            vd.fcol_act[tl.k0 + k] = left_out<T>(z, eta, L, mu) ? (c | INT32_MIN) : c;
+        if (!chunk) {
+            for (int i = threadIdx.x; i < S_; i += BLOCK) s_ptr[i] = vd.fptr[tl.s0 + i] - tl.k0;
+            if (threadIdx.x == 0) s_ptr[S_] = N;
         }
         __syncthreads();
+        const double xrow = (double)vd.xs[tl.s0];
+        int base = 0;
+        for (int c0 = 0; c0 < N; c0 += BLOCK) {
+            const int k = c0 + threadIdx.x;
+            bool keep = false, first = false;
+            int col = 0, lo = 0;
+            if (k < N) {
+                col = vd.fcol[tl.k0 + k];
+                double zr = xrow;
+                if (!chunk) {
+                    int hi = S_;   // s_ptr[lo] <= k < s_ptr[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_ptr[mid] <= k) lo = mid; else hi = mid;
+                    }
+                    zr = (double)vd.xs[tl.s0 + lo];
+                    first = s_ptr[lo] == k;
+                }
+                keep = !left_out<T>(zr + (double)vd.xs[col], eta, L, mu);
+            }
+            const unsigned long long m = __ballot(keep);
+            if (lane == 0) s_cnt[wv] = __popcll(m);
+            __syncthreads();
+            int off = 0, total = 0;
+            for (int q = 0; q < BLOCK / 64; ++q) {
+                if (q < wv) off += s_cnt[q];
+                total += s_cnt[q];
+            }
+            const int rank = base + off + __popcll(m & ((1ull << lane) - 1ull));   // active before k
+            if (keep) vd.fcol_pk[tl.k0 + rank] = col;
+            if (first) vd.fptr_pk[tl.s0 + lo] = tl.k0 + rank;
+            base += total;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) vd.tile_na[t] = base;
     }
 }
 
@@ -729,7 +752,7 @@ void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st
 template <class T>
 void vc_build_active(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, double mu)
 {
-    VLAUNCH(vc_mark_k<T>, L.grid_ftile, v, ctl, mu);
+    VLAUNCH(vc_pack_k<T>, L.grid_ftile, v, ctl, mu);
     VLAUNCH(vc_act_count_k<T>, L.grid_act, v, ctl, mu, L.partials);
     VLAUNCH(vc_act_scan_k, 1, v.acnt, L.grid_act, ctl, (const double *)L.partials, mu);
     VLAUNCH(vc_act_scatter_k<T>, L.grid_act, v, ctl, mu);
