@@ -166,8 +166,8 @@ class VcoverProgram : public Program {
 
     // Active lists of the sparse passes: built once a probe has run a few
     // iterations, rebuilt when the weight shift has used half the margin (the
-    // passes fall back to the full lists once it is used up).  A build whose
-    // lists keep most edges is not repeated until they expire.
+    // passes fall back to the full lists once it is used up).  A build costs
+    // about one full pass A plus two reads of the edge list.
     void between_launches(const Ctl &c) override
     {
         if (c.eval_mode || c.hold || c.status != ST_RUNNING || c.phase == PH_DONE) return;
@@ -175,11 +175,8 @@ class VcoverProgram : public Program {
         if (c.act_on) {
             const double drift = c.eta * (c.LC - c.act_L);
             if (drift <= 0.5 * kActMu) return;
-            const bool dense = (double)c.act_ne > kActDense * (double)ne_;
-            if (dense && (drift <= kActMu || c.iter - built_iter_ < kActFirstIter)) return;
         }
         vc_build_active<T>(vd_, ctl(), L_, s_.stream, kActMu);
-        built_iter_ = c.iter;
     }
 
     void save_best() override
@@ -322,11 +319,9 @@ class VcoverProgram : public Program {
     }
 
     static constexpr double kActMu = 64.0;       // margin, in units of 1 / eta
-    static constexpr int kActFirstIter = 16;
-    static constexpr double kActDense = 0.8;
+    static constexpr int kActFirstIter = 8;
     Solver &s_;
     int64_t nv_ = 0, ne_ = 0;
-    int64_t built_iter_ = 0;
     bool debug_ = false;
     VcDev<T> vd_{};
     VcLaunch L_{};
