@@ -96,6 +96,7 @@ class VcoverProgram : public Program {
         fcol_pk_.alloc(fcol.size() * 4);
         fptr_pk_.alloc((size_t)(nv + 1) * 4);
         tile_na_.alloc(std::max<size_t>(ft.tiles.size(), 1) * 4);
+        nftiles_ = (int64_t)ft.tiles.size();
         aeu_.alloc(std::max<int64_t>(ne_, 1) * 4);
         aew_.alloc(std::max<int64_t>(ne_, 1) * 4);
         xd_.alloc(nv * sizeof(XD<T>));
@@ -248,22 +249,48 @@ class VcoverProgram : public Program {
         throw ApiError{MWU_ERR_STATE, "potential is provided by the generic engine (MWU_FLAG_GENERIC)"};
     }
 
+    // Algorithmic bytes of one launch at the current (held) state: over the
+    // active lists when the pass runs on them.
     double algo_bytes(int which) const override
     {
-        const double t = sizeof(T), V = (double)nv_, E = (double)ne_;
+        const double t = sizeof(T), V = (double)nv_;
+        const PassSize p = pass_size(which);
         switch (which) {
-        case 0: return 4.0 * (V + 1) + 8.0 * E + t * V + t * V;       // fptr, fcol, x, h
+        case 0:   // row starts, columns (+ tile counts when packed), x, h
+            return p.sparse ? 4.0 * (V + 1) + 4.0 * p.nnz + 4.0 * (double)nftiles_ + 2.0 * t * V
+                            : 4.0 * (V + 1) + 4.0 * p.nnz + 2.0 * t * V;
         case 1: return 4.0 * t * V + t * V;                           // xd read+write, h
-        case 3: return 8.0 * E + 2.0 * t * V;                           // eu, ew, xd
+        case 3: return 8.0 * p.edges + 2.0 * t * V;                   // eu, ew (active), xd
         }
         return 0.0;
     }
     double pass_nnz(int which) const override
     {
-        return which == 0 ? 2.0 * (double)ne_ : which == 3 ? (double)ne_ : 0.0;
+        const PassSize p = pass_size(which);
+        return which == 0 ? p.nnz : which == 3 ? p.edges : 0.0;
     }
 
   private:
+    // Nonzeros of pass A and edges of the search at the current state (the
+    // same test the kernels make on the control block).
+    struct PassSize { bool sparse; double nnz, edges; };
+    PassSize pass_size(int which) const
+    {
+        Ctl c;
+        HIP_OK(hipMemcpyAsync(&c, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        const double Lw = which == 0 ? c.LC : c.LCw;
+        PassSize p{c.act_on && !c.eval_mode && c.eta * (Lw - c.act_L) <= c.act_mu, 2.0 * (double)ne_,
+                   (double)ne_};
+        if (!p.sparse) return p;
+        p.edges = (double)c.act_ne;
+        std::vector<int32_t> na(std::max<int64_t>(nftiles_, 1));
+        HIP_OK(hipMemcpyAsync(na.data(), tile_na_.p, na.size() * 4, hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        p.nnz = 0.0;
+        for (int64_t i = 0; i < nftiles_; ++i) p.nnz += na[i];
+        return p;
+    }
     VcDev<T> dbg() const
     {
         VcDev<T> v = vd_;
@@ -321,7 +348,7 @@ class VcoverProgram : public Program {
     static constexpr double kActMu = 64.0;       // margin, in units of 1 / eta
     static constexpr int kActFirstIter = 8;
     Solver &s_;
-    int64_t nv_ = 0, ne_ = 0;
+    int64_t nv_ = 0, ne_ = 0, nftiles_ = 0;
     bool debug_ = false;
     VcDev<T> vd_{};
     VcLaunch L_{};

@@ -9,8 +9,15 @@ whose readings fix the scale between counter units and bytes on this chip.
 kernel sources; ``load_traffic`` returns those bytes only while the sources
 still hash the same, so a stale measurement is never reported.
 
+``trace_summary`` turns a ``rocprofv3 --kernel-trace --stats`` run into a
+short markdown summary: the per-kernel statistics of the whole run, the mean
+duration of the last ``LAST`` dispatches of each named kernel (the held
+repetitions bench.py times, which its ``avg_launch_us`` must match), and
+selected fields of the bench line.
+
 Usage:
     python -m paper_2307_03307_amd.profiling FETCH_DIR WRITE_DIR KERNEL COPY_MIB OUT [LAST]
+    python -m paper_2307_03307_amd.profiling trace TRACE_DIR TITLE COMMAND OUT BENCH_JSON LAST KERNEL...
 """
 from __future__ import annotations
 
@@ -105,7 +112,53 @@ def load_traffic(path: str, kernel: str):
         return None
 
 
-if __name__ == "__main__":
+BENCH_KEYS = ("value", "unit", "fp64_plain_s", "speedup_vs_fp64", "iterations", "fp64_iterations",
+              "certified", "roofline", "passes", "fp64_batched_s", "fp64_loop_s", "speedup_vs_fp64_loop",
+              "speedup_vs_fp64_batched", "exact_optimum_in_bracket", "layout", "default_layout_s")
+
+
+def trace_summary(trace_dir: str, title: str, command: str, out: str, bench_json: str, last: int,
+                  kernels) -> None:
+    import json
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    rows = list(csv.DictReader(open(stats[0])))
+    held = {}
+    traces = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if traces and kernels:
+        disp = []
+        with open(traces[0]) as fh:
+            for r in csv.DictReader(fh):
+                disp.append((int(r["Start_Timestamp"]), r["Kernel_Name"],
+                             int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        disp.sort()
+        for k in kernels:
+            d = [ns for _, n, ns in disp if k in n]
+            if d:
+                held[k] = statistics.mean(d[-last:]) / 1e3
+    with open(out, "w") as f:
+        f.write(f"# {title}\n\nCommand (run from the repository root on one MI355X):\n\n```\n{command}\n```\n\n")
+        f.write("rocprofv3 kernel statistics of the whole run (every dispatch, including no-op launches\n"
+                "of kernels whose phase was inactive in a captured iteration slot, passes over the\n"
+                "full lists before the active lists exist, and the held timing repetitions):\n\n")
+        f.write("| kernel | calls | avg us | total ms | % |\n|---|---:|---:|---:|---:|\n")
+        for r in rows[:30]:
+            name = r["Name"].split("(")[0].replace("void ", "").replace("mwu::", "")
+            f.write(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                    f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.2f} |\n")
+        if held:
+            f.write(f"\nMean duration of the last {last} dispatches (the held repetitions bench.py times):\n\n")
+            for k, v in held.items():
+                f.write(f"- `{k}`: {v:.2f} us\n")
+        if bench_json and os.path.exists(bench_json):
+            d = json.loads(open(bench_json).read().strip().splitlines()[-1])
+            keep = {k: d[k] for k in BENCH_KEYS if k in d}
+            f.write("\nBench line of the same run (selected fields):\n\n```\n" + json.dumps(keep, indent=1) + "\n```\n")
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "trace":
+    trace_dir, title, command, out, bench_json, last = sys.argv[2:8]
+    trace_summary(trace_dir, title, command, out, bench_json, int(last), sys.argv[8:])
+elif __name__ == "__main__":
     fetch_dir, write_dir, kernel, copy_mib, out = sys.argv[1:6]
     last = int(sys.argv[6]) if len(sys.argv) > 6 else 10
     r = summarize(fetch_dir, write_dir, kernel, int(copy_mib), last)
