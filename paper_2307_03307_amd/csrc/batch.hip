@@ -304,13 +304,14 @@ template <class T, int KIND>
 MWU_DEV void kb_search_rows(const BatchDev<T> &b, const BTile &tl, const Ctl *c, double *s_wave,
                             double *s_rec)
 {
-    const double eta = c->eta, a0 = c->cand[0], ga0 = c->ga0, gdel = c->gdelta;
+    const double eta = c->eta, a0 = c->cand[0], ga0 = c->ga0, gdel = c->gdelta, dymax = c->dymax;
+    const uint32_t shm = shifted_mask(c);
     const int nc = c->ncand;
     double s1[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) s1[k] = 0.0;
     for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
-        pack_terms<T, KIND>(nc, c->cand, a0, ga0, gdel, eta, b.w[i], b.dy[i], s1);
+        pack_terms<T, KIND>(nc, c->cand, a0, ga0, gdel, eta, b.w[i], b.dy[i], dymax, shm, s1);
     const Red redp{KC, 0, 0};
     block_combine<KC>(s1, redp, 0, s_wave, s_rec);
 }

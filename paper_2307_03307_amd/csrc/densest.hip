@@ -282,13 +282,14 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
     const int r0 = blockIdx.x * BLOCK + threadIdx.x;
     const int nc = ctl->ncand;
     const double *cand = ctl->cand;
-    const double a0 = ctl->cand[0], ga0 = ctl->ga0, gdel = ctl->gdelta;
+    const double a0 = ctl->cand[0], ga0 = ctl->ga0, gdel = ctl->gdelta, dymax = ctl->dymax;
+    const uint32_t shm = shifted_mask(ctl);
     {
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
         for (int r = r0; r < dd.nv; r += stride)
-            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], dd.dy[r], s1);
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], dd.dy[r], dymax, shm, s1);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }

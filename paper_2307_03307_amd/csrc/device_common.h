@@ -468,38 +468,82 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double ga0, double
     }
 }
 
-// Packing-row terms of one search pass: s1[k] += w expm1(eta a_k dy), with
-// the candidates of cov_terms.
+// Candidates of a pass whose packing exponent eta a dymax passes psi_lim
+// (bit k for candidate k): their packing sums are formed max-shifted (see
+// pack_terms).  The replay makes the same test on the same doubles.
+MWU_DEV uint32_t shifted_mask(const Ctl *c)
+{
+    uint32_t m = 0;
+    for (int k = 0; k < c->ncand && k < 32; ++k)
+        if (c->eta * c->cand[k] * c->dymax > c->psi_lim) m |= 1u << k;
+    return m;
+}
+
+// Packing-row terms of one search pass: s1[k] += w expm1(eta a_k dy) with
+// the candidates of cov_terms, or, for the candidates in shmask, the
+// max-shifted s1[k] += w e^{eta a_k (dy - dymax)}, which cannot overflow
+// (dy <= dymax); Psi of such a candidate is (eta a_k dymax + log(s1 / sum w))
+// / eta.  The shifted terms follow the same recurrences (squaring on the
+// exponential grid, float re-seeded every 4 steps; products on the bisection
+// grid).
 template <class T, int KIND>
 MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, double gdel, double eta, T w, T dy,
-                        double *s1)
+                        double dymax, uint32_t shmask, double *s1)
 {
     const double dyd = (double)dy;
-    auto doubling = [&](double b0, double *o) {
+    const double dsh = dyd - dymax;   // <= 0
+    auto doubling = [&](double b0, double c0, double *o) {
         T m = expm1_t((T)b0);
+        if (!shmask) {
+#pragma unroll
+            for (int k = 0; k < KE; ++k) {
+                o[k] += (double)(w * m);
+                m = m * (m + T(2));                  // expm1(2x) = expm1(x)(expm1(x)+2)
+            }
+            return;
+        }
+        T t = exp_arg(c0, T(0));
 #pragma unroll
         for (int k = 0; k < KE; ++k) {
-            o[k] += (double)(w * m);
-            m = m * (m + T(2));                      // expm1(2x) = expm1(x)(expm1(x)+2)
+            o[k] += (double)(w * (((shmask >> k) & 1u) ? t : m));
+            m = m * (m + T(2));
+            if (sizeof(T) == 4 && (k & 3) == 3 && k + 1 < KE) t = exp_arg(c0 * (double)(1 << (k + 1)), T(0));
+            else t = t * t;
         }
     };
-    auto adding = [&](double b0, double bd, double *o) {
+    auto adding = [&](double b0, double bd, double c0, double cd, int k0, double *o) {
         T m = expm1_t((T)b0);
         const T mr = expm1_t((T)bd);
+        if (!shmask) {
+#pragma unroll
+            for (int k = 0; k < KG; ++k) {
+                o[k] += (double)(w * m);
+                m = m + mr + m * mr;                 // expm1(x+y) from expm1(x), expm1(y)
+            }
+            return;
+        }
+        T t = exp_arg(c0, T(0));
+        const T tr = exp_arg(cd, T(0));
 #pragma unroll
         for (int k = 0; k < KG; ++k) {
-            o[k] += (double)(w * m);
-            m = m + mr + m * mr;                     // expm1(x+y) from expm1(x), expm1(y)
+            o[k] += (double)(w * (((shmask >> (k0 + k)) & 1u) ? t : m));
+            m = m + mr + m * mr;
+            t = t * tr;
         }
     };
     if constexpr (KIND == SK_LIST) {
 #pragma unroll
         for (int k = 0; k < KL; ++k)
-            if (k < nc) s1[k] += (double)(w * expm1_t((T)(eta * cand[k] * (double)dy)));
+            if (k < nc) {
+                const T v = ((shmask >> k) & 1u) ? exp_arg(eta * cand[k] * dsh, T(0))
+                                                 : expm1_t((T)(eta * cand[k] * dyd));
+                s1[k] += (double)(w * v);
+            }
     } else {
-        if constexpr (KIND == SK_EXP || KIND == SK_COMBO) doubling(eta * a0 * dyd, s1);
-        if constexpr (KIND == SK_GRID) adding(eta * a0 * dyd, eta * gdel * dyd, s1);
-        if constexpr (KIND == SK_COMBO) adding(eta * ga0 * dyd, eta * gdel * dyd, s1 + KE);
+        if constexpr (KIND == SK_EXP || KIND == SK_COMBO) doubling(eta * a0 * dyd, eta * a0 * dsh, s1);
+        if constexpr (KIND == SK_GRID) adding(eta * a0 * dyd, eta * gdel * dyd, eta * a0 * dsh, eta * gdel * dsh, 0, s1);
+        if constexpr (KIND == SK_COMBO)
+            adding(eta * ga0 * dyd, eta * gdel * dyd, eta * ga0 * dsh, eta * gdel * dsh, KE, s1 + KE);
     }
 }
 
@@ -671,7 +715,11 @@ MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
         e.psi = alpha * c->dy1;
     } else {
         const double s1 = c->rS1P[k] * c->invSw;
-        if (c->eta * alpha * c->dymax > c->psi_lim || !isfinite(s1)) { e.ok = 0; e.psi = 0; }
+        const double B = c->eta * alpha * c->dymax;
+        if (B > c->psi_lim) {   // the pass formed the max-shifted sum (shifted_mask)
+            if (s1 > 0.0 && isfinite(s1)) e.psi = (B + log(s1)) / c->eta;
+            else { e.ok = 0; e.psi = 0; }
+        } else if (!isfinite(s1)) { e.ok = 0; e.psi = 0; }
         else e.psi = log1p(s1) / c->eta;
     }
     if (c->onesC) {

@@ -345,14 +345,15 @@ __device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_w
     const int mPc = gd.mPc, mR = gd.mR;
     const int nc = ctl->ncand;
     const double *cand = ctl->cand;
-    const double a0 = ctl->cand[0], ga0 = ctl->ga0;
+    const double a0 = ctl->cand[0], ga0 = ctl->ga0, dymax = ctl->dymax;
+    const uint32_t shm = shifted_mask(ctl);
     const double gdel = ctl->gdelta;
     {
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
         for (int r = r0; r < mPc; r += stride)
-            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.dyz[r], s1);
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.dyz[r], dymax, shm, s1);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }
