@@ -308,12 +308,18 @@ __global__ __launch_bounds__(BLOCK) void vc_long_k(VcDev<T> vd, const Ctl *ctl)
     if (l < vd.flong.nlong) vd.h[vd.flong.lseg[l]] = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
 }
 
+// with_long: the finisher also completes the long rows (when they are few,
+// instead of a launch of vc_long_k).
 template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, const double *part, int G)
+__global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, const double *part, int G,
+                                                      int with_long)
 {
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_ROW) return;
+    if (with_long)
+        for (int l = threadIdx.x; l < vd.flong.nlong; l += BLOCK)
+            vd.h[vd.flong.lseg[l]] = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
     const Red red{1, 1, 0};
     fold_records<2>(part, G, red, 0, s_wave, s_rec);
     on_ctl(ctl, [&](Ctl *c) { finish_vcA(c, s_rec); });
@@ -718,8 +724,10 @@ void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
     VLAUNCH(vc_commit_k<T>, L.grid_v, v, ctl);
     VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials);
-    if (v.flong.nlong > 0) VLAUNCH(vc_long_k<T>, (v.flong.nlong + BLOCK - 1) / BLOCK, v, ctl);
-    VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile);
+    // up to 2 BLOCK long rows are completed by the finisher itself
+    const int with_long = v.flong.nlong <= 2 * BLOCK;
+    if (!with_long) VLAUNCH(vc_long_k<T>, (v.flong.nlong + BLOCK - 1) / BLOCK, v, ctl);
+    VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile, with_long);
 }
 
 template <class T>
