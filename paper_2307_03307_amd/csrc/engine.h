@@ -90,6 +90,7 @@ struct Ctl {
     // ---- sparse passes (fused vertex cover): covering rows whose weight is
     // exactly zero in the storage type are left out of the passes
     int32_t act_on, act_ne;     // lists built; edges in the active search list
+    int32_t act_nitems, pad6;   // work items of the packed transpose pass
     int32_t pass_sparse;        // the last search pass ran over the active list
     int32_t ev_cached;          // ev_* hold the evaluations of the last grid or list pass
     double act_L;               // weight shift the lists were built against
@@ -166,9 +167,14 @@ struct VcDev {
     const double *forced;
     // sparse passes: the active neighbours of each adjacency tile packed at
     // the start of its range, the packed row starts and the tiles' active
-    // counts; the active edges of the search in edge-list order; per-block
-    // counts of the build
-    int32_t *fcol_pk, *fptr_pk, *tile_na, *aeu, *aew, *acnt;
+    // counts; the same neighbours concatenated over all tiles (ccol, row
+    // starts cst, tile offsets goff) and the work items of the packed pass
+    // (runs of consecutive tiles that fit one tile together); the static row
+    // prefix over tiles; the active edges of the search in edge-list order;
+    // per-block counts of the build
+    int32_t *fcol_pk, *fptr_pk, *tile_na, *ccol, *cst, *goff, *tile_rows;
+    Tile *items;
+    int32_t *aeu, *aew, *acnt;
 };
 
 // Fused densest-subgraph program: variables z_{2e}, z_{2e+1} are the two ends

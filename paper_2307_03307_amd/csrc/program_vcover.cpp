@@ -97,6 +97,18 @@ class VcoverProgram : public Program {
         fptr_pk_.alloc((size_t)(nv + 1) * 4);
         tile_na_.alloc(std::max<size_t>(ft.tiles.size(), 1) * 4);
         nftiles_ = (int64_t)ft.tiles.size();
+        ccol_.alloc(fcol.size() * 4);
+        cst_.alloc((size_t)(nv + 1) * 4);
+        goff_.alloc((size_t)(nftiles_ + 1) * 4);
+        items_.alloc(std::max<size_t>(ft.tiles.size(), 1) * sizeof(Tile));
+        {   // rows per tile, prefix (a chunk tile counts as more rows than a run may hold)
+            std::vector<int32_t> rp(nftiles_ + 1, 0);
+            for (int64_t t = 0; t < nftiles_; ++t) {
+                const Tile &tl = ft.tiles[t];
+                rp[t + 1] = rp[t] + (tl.lid >= 0 ? TILE_NZ + 1 : tl.s1 - tl.s0);
+            }
+            up(tile_rows_, rp.data(), rp.size() * 4);
+        }
         aeu_.alloc(std::max<int64_t>(ne_, 1) * 4);
         aew_.alloc(std::max<int64_t>(ne_, 1) * 4);
         xd_.alloc(nv * sizeof(XD<T>));
@@ -119,6 +131,8 @@ class VcoverProgram : public Program {
         vd_.fcol_pk = fcol_pk_.as<int32_t>();
         vd_.fptr_pk = fptr_pk_.as<int32_t>();
         vd_.tile_na = tile_na_.as<int32_t>();
+        vd_.ccol = ccol_.as<int32_t>(); vd_.cst = cst_.as<int32_t>(); vd_.goff = goff_.as<int32_t>();
+        vd_.tile_rows = tile_rows_.as<int32_t>(); vd_.items = items_.as<Tile>();
         vd_.aeu = aeu_.as<int32_t>(); vd_.aew = aew_.as<int32_t>();
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
@@ -256,8 +270,8 @@ class VcoverProgram : public Program {
         const double t = sizeof(T), V = (double)nv_;
         const PassSize p = pass_size(which);
         switch (which) {
-        case 0:   // row starts, columns (+ tile counts when packed), x, h
-            return p.sparse ? 4.0 * (V + 1) + 4.0 * p.nnz + 4.0 * (double)nftiles_ + 2.0 * t * V
+        case 0:   // row starts, columns (+ the work items when packed), x, h
+            return p.sparse ? 4.0 * (V + 1) + 4.0 * p.nnz + (double)sizeof(Tile) * p.items + 2.0 * t * V
                             : 4.0 * (V + 1) + 4.0 * p.nnz + 2.0 * t * V;
         case 1: return 4.0 * t * V + t * V;                           // xd read+write, h
         case 3: return 8.0 * p.edges + 2.0 * t * V;                   // eu, ew (active), xd
@@ -273,7 +287,7 @@ class VcoverProgram : public Program {
   private:
     // Nonzeros of pass A and edges of the search at the current state (the
     // same test the kernels make on the control block).
-    struct PassSize { bool sparse; double nnz, edges; };
+    struct PassSize { bool sparse; double nnz, edges, items; };
     PassSize pass_size(int which) const
     {
         Ctl c;
@@ -281,9 +295,10 @@ class VcoverProgram : public Program {
         HIP_OK(hipStreamSynchronize(s_.stream));
         const double Lw = which == 0 ? c.LC : c.LCw;
         PassSize p{c.act_on && !c.eval_mode && c.eta * (Lw - c.act_L) <= c.act_mu, 2.0 * (double)ne_,
-                   (double)ne_};
+                   (double)ne_, (double)nftiles_};
         if (!p.sparse) return p;
         p.edges = (double)c.act_ne;
+        p.items = (double)c.act_nitems;
         std::vector<int32_t> na(std::max<int64_t>(nftiles_, 1));
         HIP_OK(hipMemcpyAsync(na.data(), tile_na_.p, na.size() * 4, hipMemcpyDeviceToHost, s_.stream));
         HIP_OK(hipStreamSynchronize(s_.stream));
@@ -356,6 +371,7 @@ class VcoverProgram : public Program {
     std::vector<int64_t> canon_;
     DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
     DevBuf xd_, xs_, xbest_, h_, partials_, partials2_, forced_, hdbg_, fcol_pk_, fptr_pk_, tile_na_, aeu_, aew_, acnt_;
+    DevBuf ccol_, cst_, goff_, items_, tile_rows_;
 };
 
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,

@@ -263,13 +263,15 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     if (ctl->phase != PH_ROW) return;
     const double eta = ctl->eta, Lw = ctl->LC;
     double v[2] = {0.0, INFINITY};   // sum h | min z
-    // Sparse: each tile's active neighbours packed at the start of its range
-    // (fptr_pk, fcol_pk, tile_na); left-out ones have weight 0 and never hold
-    // the minimum, which an active row always does (eta (min z - Lw) stays
-    // below ln m).
+    // Sparse: the active neighbours concatenated over all tiles (ccol, cst),
+    // visited by work items that merge runs of tiles; left-out neighbours
+    // have weight 0 and never hold the minimum, which an active row always
+    // does (eta (min z - Lw) stays below ln m).
     const bool sparse = act_valid(ctl, Lw);
-    const int32_t *__restrict__ fc = sparse ? vd.fcol_pk : vd.fcol;
-    const int32_t *__restrict__ fp = sparse ? vd.fptr_pk : vd.fptr;
+    const int32_t *__restrict__ fc = sparse ? vd.ccol : vd.fcol;
+    const int32_t *__restrict__ fp = sparse ? vd.cst : vd.fptr;
+    const Tile *__restrict__ tiles = sparse ? vd.items : vd.ftiles;
+    const int ntiles = sparse ? ctl->act_nitems : vd.nftiles;
     auto stage = [&](int k) -> T { return vd.xs[fc[k]]; };
     auto segval = [&](int u) -> T { return vd.xs[u]; };
     auto term = [&](T xu, T xw) -> T {
@@ -281,9 +283,8 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
         vd.h[u] = acc;
         v[0] += (double)acc;
     };
-    for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
-        Tile tl = vd.ftiles[t];
-        if (sparse) tl.k1 = tl.k0 + vd.tile_na[t];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
         if (tl.lid < 0) {
             seg_tile_rows<T, T>(tl, fp, stage, segval, term, epi, s_val, s_seg, s_ptr);
         } else {
@@ -595,6 +596,86 @@ __global__ __launch_bounds__(BLOCK) void vc_pack_k(VcDev<T> vd, const Ctl *ctl, 
     }
 }
 
+// One workgroup over all tiles: tile offsets goff of the concatenated packed
+// neighbours (exclusive prefix of tile_na), then the work items of the packed
+// pass.  Tile t joins the largest aligned run of 2^l tiles (l <= 6) that
+// holds at most TILE_NZ rows and TILE_NZ active neighbours in total, so a run
+// fits one tile's LDS staging; chunk tiles of long rows never join a run
+// (tile_rows counts them as TILE_NZ + 1 rows).  tile_rows holds the static
+// exclusive prefix of rows per tile (nftiles + 1 entries).
+__global__ __launch_bounds__(BLOCK) void vc_items_k(const Tile *tiles, int nt, const int32_t *tile_na,
+                                                    const int32_t *tile_rows, int32_t *goff, Tile *items,
+                                                    Ctl *ctl)
+{
+    __shared__ int32_t s_sum[BLOCK];
+    const int per = (nt + BLOCK - 1) / BLOCK;
+    const int i0 = min(nt, (int)threadIdx.x * per), i1 = min(nt, i0 + per);
+    // 1. goff = exclusive prefix of tile_na (goff[nt] = total)
+    int tot = 0;
+    for (int i = i0; i < i1; ++i) tot += tile_na[i];
+    s_sum[threadIdx.x] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < BLOCK; ++t) { const int c = s_sum[t]; s_sum[t] = run; run += c; }
+        goff[nt] = run;
+    }
+    __syncthreads();
+    int run = s_sum[threadIdx.x];
+    for (int i = i0; i < i1; ++i) { goff[i] = run; run += tile_na[i]; }
+    __syncthreads();
+    // 2. run length of each tile's run; heads are counted, then written in order
+    constexpr int LMAX = 6;
+    auto run_level = [&](int t) {
+        int lev = 0;
+        for (int l = 1; l <= LMAX; ++l) {
+            const int a = (t >> l) << l, b = min(nt, a + (1 << l));
+            if (tile_rows[b] - tile_rows[a] > TILE_NZ || goff[b] - goff[a] > TILE_NZ) break;
+            lev = l;
+        }
+        return lev;
+    };
+    int heads = 0;
+    for (int i = i0; i < i1; ++i) {
+        const int l = run_level(i);
+        heads += ((i >> l) << l) == i;
+    }
+    __syncthreads();
+    s_sum[threadIdx.x] = heads;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int t = 0; t < BLOCK; ++t) { const int c = s_sum[t]; s_sum[t] = r; r += c; }
+        ctl->act_nitems = r;
+    }
+    __syncthreads();
+    int pos = s_sum[threadIdx.x];
+    for (int i = i0; i < i1; ++i) {
+        const int l = run_level(i);
+        if (((i >> l) << l) != i) continue;
+        const int last = min(nt, i + (1 << l)) - 1;
+        Tile it = tiles[i];
+        it.s1 = tiles[last].s1;
+        it.k0 = goff[i];
+        it.k1 = goff[last + 1];
+        items[pos++] = it;   // a chunk tile keeps its lid and cidx (runs of length 1)
+    }
+}
+
+// Concatenate the packed neighbours of every tile at its offset goff, and
+// the concatenated start of every row of a multi-row tile.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void vc_concat_k(VcDev<T> vd)
+{
+    for (int t = blockIdx.x; t < vd.nftiles; t += gridDim.x) {
+        const Tile tl = vd.ftiles[t];
+        const int na = vd.tile_na[t], g = vd.goff[t];
+        for (int i = threadIdx.x; i < na; i += BLOCK) vd.ccol[g + i] = vd.fcol_pk[tl.k0 + i];
+        if (tl.lid < 0)
+            for (int r = tl.s0 + threadIdx.x; r < tl.s1; r += BLOCK) vd.cst[r] = g + (vd.fptr_pk[r] - tl.k0);
+    }
+}
+
 // Edge range of block b in the active-list build: contiguous, whole waves.
 MWU_DEV void act_range(int ne, int &e0, int &e1)
 {
@@ -761,6 +842,9 @@ template <class T>
 void vc_build_active(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, double mu)
 {
     VLAUNCH(vc_pack_k<T>, L.grid_ftile, v, ctl, mu);
+    VLAUNCH(vc_items_k, 1, v.ftiles, v.nftiles, (const int32_t *)v.tile_na, (const int32_t *)v.tile_rows, v.goff,
+            v.items, ctl);
+    VLAUNCH(vc_concat_k<T>, L.grid_ftile, v);
     VLAUNCH(vc_act_count_k<T>, L.grid_act, v, ctl, mu, L.partials);
     VLAUNCH(vc_act_scan_k, 1, v.acnt, L.grid_act, ctl, (const double *)L.partials, mu);
     VLAUNCH(vc_act_scatter_k<T>, L.grid_act, v, ctl, mu);
