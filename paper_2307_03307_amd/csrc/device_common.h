@@ -658,10 +658,16 @@ constexpr double zero_weight_exponent()
 // can be nonzero while the weight shift Lw has moved by at most act_mu / eta
 // since they were built: z only grows (x and d are nonnegative), so a row
 // left out then still has eta (z - Lw) above the zero-weight exponent.
-// Evaluation mode always takes the full lists.
+// The transpose pass may use them in evaluation mode too (its sums and
+// minimum are exact either way); the search never does there, since its
+// minima over the active rows alone are only bounds (act_valid).
+MWU_DEV bool act_rows_valid(const Ctl *c, double Lw)
+{
+    return c->act_on && c->eta * (Lw - c->act_L) <= c->act_mu;
+}
 MWU_DEV bool act_valid(const Ctl *c, double Lw)
 {
-    return c->act_on && !c->eval_mode && c->eta * (Lw - c->act_L) <= c->act_mu;
+    return !c->eval_mode && act_rows_valid(c, Lw);
 }
 
 // A finisher's state update is one thread walking long dependent chains of

@@ -294,7 +294,7 @@ class VcoverProgram : public Program {
         HIP_OK(hipMemcpyAsync(&c, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
         HIP_OK(hipStreamSynchronize(s_.stream));
         const double Lw = which == 0 ? c.LC : c.LCw;
-        PassSize p{c.act_on && !c.eval_mode && c.eta * (Lw - c.act_L) <= c.act_mu, 2.0 * (double)ne_,
+        PassSize p{c.act_on && (which == 0 || !c.eval_mode) && c.eta * (Lw - c.act_L) <= c.act_mu, 2.0 * (double)ne_,
                    (double)ne_, (double)nftiles_};
         if (!p.sparse) return p;
         p.edges = (double)c.act_ne;

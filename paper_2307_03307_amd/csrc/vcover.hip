@@ -267,7 +267,7 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     // visited by work items that merge runs of tiles; left-out neighbours
     // have weight 0 and never hold the minimum, which an active row always
     // does (eta (min z - Lw) stays below ln m).
-    const bool sparse = act_valid(ctl, Lw);
+    const bool sparse = act_rows_valid(ctl, Lw);
     const int32_t *__restrict__ fc = sparse ? vd.ccol : vd.fcol;
     const int32_t *__restrict__ fp = sparse ? vd.cst : vd.fptr;
     const Tile *__restrict__ tiles = sparse ? vd.items : vd.ftiles;

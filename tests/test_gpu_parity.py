@@ -23,7 +23,7 @@ import graphgen as gg
 import oracle
 import paper_2307_03307_amd as mwu
 
-from gpu_common import (EPS, bmatch_case, densest_case, domset_case, rel_err, start_point,
+from gpu_common import (EPS, bmatch_case, densest_case, domset_case, ones_row, rel_err, start_point,
                         vcover_case, weighted_packing_case)
 
 pytestmark = pytest.mark.gpu
@@ -162,6 +162,35 @@ def test_decision_replay_mixed(name):
     err = abs(xg.sum() - r.x.sum()) / r.x.sum()
     print(f"{name}: mixed replay objective rel err {err:.2e}")
     assert err <= MIXED_REPLAY_TOL[name]
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+def test_sparse_transpose_pass(precision):
+    """Per-pass parity of the transpose and direction passes over the active
+    lists (R17): 600 iterations into a near-optimum vertex-cover probe most
+    covering rows carry exactly zero weight in FP32 and the transpose pass
+    visits only the active neighbours; g, h and d at that point match the
+    oracle's full sums at the same x."""
+    g = gg.rmat(13, 16, seed=2)
+    C, keep = oracle.vertex_cover_matrix(g)
+    n = C.cols
+    param = 1.02 * _opt_vcover(g)
+    sP = 1.0 / param
+    with mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision) as s:
+        s.probe_begin(param)
+        info = s.probe_run(600)
+        assert info.status == mwu._lib.PROBE_RUNNING
+        _, _, nnz = s.time_pass(0, 2)      # nonzeros the transpose pass visits now
+        s.probe_direction()
+        x = s.probe_read("x", n)            # the point the passes saw (pending step committed)
+        got = {k: s.probe_read(k, n) for k in ("g", "h", "d")}
+    ref = oracle.iteration_terms(ones_row(n), sP, C, 1.0, EPS, x)
+    errs = {k: rel_err(got[k], ref[k]) for k in ("g", "h", "d")}
+    print(f"precision {precision}: transpose pass over {nnz:.0f} of {2 * C.rows} nonzeros; {errs}")
+    if precision == mwu.MIXED_FP32_FP64:
+        assert nnz < 0.6 * 2 * C.rows
+    tol = 1e-9 if precision == mwu.FP64 else FP32_TOL
+    assert all(v <= tol for v in errs.values()), errs
 
 
 def _opt_bmatch(g):
