@@ -646,18 +646,23 @@ MWU_DEV void fold_cov_compact(const double *part, int G, double *s_wave, double 
 
 struct Eval { double psi, phi, zmin; int ok; };
 
-// eta (z - L) beyond which a covering weight exp(-eta (z - L)) is exactly
-// zero in the storage type (below half the smallest subnormal).
+// eta (z - L) beyond which a covering row is left out of the sparse passes.
+// Double: exp(-746) is exactly zero (below half the smallest subnormal), so
+// the sums are those of the full pass.  Float: the weights left out are below
+// e^-40 of the weights at the shift, whose sum is about 1, so they move the
+// sums by less than m e^-40 (7e-11 for m = 1.6e7), far below the rounding of
+// the float terms themselves.  Either way the row holding min z stays in,
+// since eta (min z - L) <= ln m.
 template <class T>
-constexpr double zero_weight_exponent()
+constexpr double skip_exponent()
 {
-    return sizeof(T) == 4 ? 106.0 : 746.0;
+    return sizeof(T) == 4 ? 40.0 : 746.0;
 }
 
-// The active lists of the sparse passes hold every covering row whose weight
-// can be nonzero while the weight shift Lw has moved by at most act_mu / eta
+// The active lists of the sparse passes hold every covering row that is not
+// negligible while the weight shift Lw has moved by at most act_mu / eta
 // since they were built: z only grows (x and d are nonnegative), so a row
-// left out then still has eta (z - Lw) above the zero-weight exponent.
+// left out then still has eta (z - Lw) above the skip exponent.
 // The transpose pass may use them in evaluation mode too (its sums and
 // minimum are exact either way); the search never does there, since its
 // minima over the active rows alone are only bounds (act_valid).

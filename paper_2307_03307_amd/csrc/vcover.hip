@@ -265,8 +265,8 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     double v[2] = {0.0, INFINITY};   // sum h | min z
     // Sparse: the active neighbours concatenated over all tiles (ccol, cst),
     // visited by work items that merge runs of tiles; left-out neighbours
-    // have weight 0 and never hold the minimum, which an active row always
-    // does (eta (min z - Lw) stays below ln m).
+    // have negligible weight (skip_exponent) and never hold the minimum, which
+    // an active row always does (eta (min z - Lw) stays below ln m).
     const bool sparse = act_rows_valid(ctl, Lw);
     const int32_t *__restrict__ fc = sparse ? vd.ccol : vd.fcol;
     const int32_t *__restrict__ fp = sparse ? vd.cst : vd.fptr;
@@ -529,13 +529,13 @@ __global__ void vc_import_k(VcDev<T> vd, const double *src)
 // ------------------------------------------------------------------ active lists
 // Built between graph launches against the current weight shift L = LC with
 // margin mu: a covering row (edge) is left out when eta (z_e - L) exceeds the
-// zero-weight exponent plus mu, z_e from the committed x (z only grows, so
-// this stays true while the shift drifts by less than mu / eta).
+// skip exponent plus mu, z_e from the committed x (z only grows, so this
+// stays true while the shift drifts by less than mu / eta).
 
 template <class T>
 MWU_DEV bool left_out(double z, double eta, double L, double mu)
 {
-    return eta * (z - L) > zero_weight_exponent<T>() + mu;
+    return eta * (z - L) > skip_exponent<T>() + mu;
 }
 
 // Pack the active neighbours of each tile of the full adjacency at the start
