@@ -172,7 +172,7 @@ struct VcDev {
     // (runs of consecutive tiles that fit one tile together); the static row
     // prefix over tiles; the active edges of the search in edge-list order;
     // per-block counts of the build
-    int32_t *fcol_pk, *fptr_pk, *tile_na, *ccol, *cst, *goff, *tile_rows;
+    int32_t *fcol_pk, *fptr_pk, *tile_na, *ccol, *cst, *goff, *tile_rows, *thead, *thpos;
     Tile *items;
     int32_t *aeu, *aew, *acnt;
 };

@@ -101,6 +101,8 @@ class VcoverProgram : public Program {
         cst_.alloc((size_t)(nv + 1) * 4);
         goff_.alloc((size_t)(nftiles_ + 1) * 4);
         items_.alloc(std::max<size_t>(ft.tiles.size(), 1) * sizeof(Tile));
+        thead_.alloc((size_t)(nftiles_ + 1) * 4);
+        thpos_.alloc((size_t)(nftiles_ + 1) * 4);
         {   // rows per tile, prefix (a chunk tile counts as more rows than a run may hold)
             std::vector<int32_t> rp(nftiles_ + 1, 0);
             for (int64_t t = 0; t < nftiles_; ++t) {
@@ -133,6 +135,7 @@ class VcoverProgram : public Program {
         vd_.tile_na = tile_na_.as<int32_t>();
         vd_.ccol = ccol_.as<int32_t>(); vd_.cst = cst_.as<int32_t>(); vd_.goff = goff_.as<int32_t>();
         vd_.tile_rows = tile_rows_.as<int32_t>(); vd_.items = items_.as<Tile>();
+        vd_.thead = thead_.as<int32_t>(); vd_.thpos = thpos_.as<int32_t>();
         vd_.aeu = aeu_.as<int32_t>(); vd_.aew = aew_.as<int32_t>();
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
@@ -371,7 +374,7 @@ class VcoverProgram : public Program {
     std::vector<int64_t> canon_;
     DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
     DevBuf xd_, xs_, xbest_, h_, partials_, partials2_, forced_, hdbg_, fcol_pk_, fptr_pk_, tile_na_, aeu_, aew_, acnt_;
-    DevBuf ccol_, cst_, goff_, items_, tile_rows_;
+    DevBuf ccol_, cst_, goff_, items_, tile_rows_, thead_, thpos_;
 };
 
 std::unique_ptr<Program> make_vcover_program(Solver &s, const EdgeList &el,

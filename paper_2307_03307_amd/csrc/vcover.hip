@@ -596,70 +596,100 @@ __global__ __launch_bounds__(BLOCK) void vc_pack_k(VcDev<T> vd, const Ctl *ctl, 
     }
 }
 
-// One workgroup over all tiles: tile offsets goff of the concatenated packed
-// neighbours (exclusive prefix of tile_na), then the work items of the packed
-// pass.  Tile t joins the largest aligned run of 2^l tiles (l <= 6) that
-// holds at most TILE_NZ rows and TILE_NZ active neighbours in total, so a run
-// fits one tile's LDS staging; chunk tiles of long rows never join a run
-// (tile_rows counts them as TILE_NZ + 1 rows).  tile_rows holds the static
-// exclusive prefix of rows per tile (nftiles + 1 entries).
-__global__ __launch_bounds__(BLOCK) void vc_items_k(const Tile *tiles, int nt, const int32_t *tile_na,
-                                                    const int32_t *tile_rows, int32_t *goff, Tile *items,
-                                                    Ctl *ctl)
+// Exclusive prefix of src[0..n) into dst[0..n] (dst[n] = total) by one
+// workgroup, in batches of ROUNDS x BLOCK elements (each thread holds its
+// elements of a batch in registers first, so their loads are in flight
+// together).
+template <int ROUNDS>
+MWU_DEV void block_exclusive_scan(const int32_t *src, int n, int32_t *dst)
 {
-    __shared__ int32_t s_sum[BLOCK];
-    const int per = (nt + BLOCK - 1) / BLOCK;
-    const int i0 = min(nt, (int)threadIdx.x * per), i1 = min(nt, i0 + per);
-    // 1. goff = exclusive prefix of tile_na (goff[nt] = total)
-    int tot = 0;
-    for (int i = i0; i < i1; ++i) tot += tile_na[i];
-    s_sum[threadIdx.x] = tot;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int t = 0; t < BLOCK; ++t) { const int c = s_sum[t]; s_sum[t] = run; run += c; }
-        goff[nt] = run;
-    }
-    __syncthreads();
-    int run = s_sum[threadIdx.x];
-    for (int i = i0; i < i1; ++i) { goff[i] = run; run += tile_na[i]; }
-    __syncthreads();
-    // 2. run length of each tile's run; heads are counted, then written in order
-    constexpr int LMAX = 6;
-    auto run_level = [&](int t) {
-        int lev = 0;
-        for (int l = 1; l <= LMAX; ++l) {
-            const int a = (t >> l) << l, b = min(nt, a + (1 << l));
-            if (tile_rows[b] - tile_rows[a] > TILE_NZ || goff[b] - goff[a] > TILE_NZ) break;
-            lev = l;
+    __shared__ int32_t s_w[BLOCK / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int run = 0;
+    for (int base = 0; base < n; base += ROUNDS * BLOCK) {
+        int32_t v[ROUNDS];
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int i = base + r * BLOCK + threadIdx.x;
+            v[r] = i < n ? src[i] : 0;
         }
-        return lev;
-    };
-    int heads = 0;
-    for (int i = i0; i < i1; ++i) {
-        const int l = run_level(i);
-        heads += ((i >> l) << l) == i;
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            int x = v[r];                                   // inclusive scan in the wave
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(x, d);
+                if (lane >= d) x += y;
+            }
+            if (lane == 63) s_w[wv] = x;
+            __syncthreads();
+            int off = run, tot = 0;
+            for (int w = 0; w < BLOCK / 64; ++w) {
+                if (w < wv) off += s_w[w];
+                tot += s_w[w];
+            }
+            const int i = base + r * BLOCK + threadIdx.x;
+            if (i < n) dst[i] = off + x - v[r];
+            run += tot;
+            __syncthreads();
+        }
     }
-    __syncthreads();
-    s_sum[threadIdx.x] = heads;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int r = 0;
-        for (int t = 0; t < BLOCK; ++t) { const int c = s_sum[t]; s_sum[t] = r; r += c; }
-        ctl->act_nitems = r;
+    if (threadIdx.x == 0) dst[n] = run;
+}
+
+constexpr int ITEM_SCAN_ROUNDS = 16;
+
+// Tile offsets goff of the concatenated packed neighbours (exclusive prefix
+// of tile_na).
+__global__ __launch_bounds__(BLOCK) void vc_goff_k(const int32_t *tile_na, int nt, int32_t *goff)
+{
+    block_exclusive_scan<ITEM_SCAN_ROUNDS>(tile_na, nt, goff);
+}
+
+// Work items of the packed pass: tile t joins the largest aligned run of 2^l
+// tiles (l <= 6) that holds at most TILE_NZ rows and TILE_NZ active
+// neighbours in total, so a run fits one tile's LDS staging; chunk tiles of
+// long rows never join a run (tile_rows, the static exclusive prefix of rows
+// per tile, counts them as TILE_NZ + 1 rows).  head[t] = 1 when tile t
+// starts its run; run[t] = the run's length.
+MWU_DEV int run_level(int t, int nt, const int32_t *tile_rows, const int32_t *goff)
+{
+    int lev = 0;
+    for (int l = 1; l <= 6; ++l) {
+        const int a = (t >> l) << l, b = min(nt, a + (1 << l));
+        if (tile_rows[b] - tile_rows[a] > TILE_NZ || goff[b] - goff[a] > TILE_NZ) break;
+        lev = l;
     }
+    return lev;
+}
+
+__global__ __launch_bounds__(BLOCK) void vc_runs_k(int nt, const int32_t *tile_rows, const int32_t *goff,
+                                                   int32_t *head)
+{
+    for (int t = blockIdx.x * BLOCK + threadIdx.x; t < nt; t += gridDim.x * BLOCK) {
+        const int l = run_level(t, nt, tile_rows, goff);
+        head[t] = ((t >> l) << l) == t ? 1 : 0;
+    }
+}
+
+// One workgroup: positions of the run heads, then the items in order.
+__global__ __launch_bounds__(BLOCK) void vc_items_k(const Tile *tiles, int nt, const int32_t *tile_rows,
+                                                    const int32_t *goff, const int32_t *head, int32_t *hpos,
+                                                    Tile *items, Ctl *ctl)
+{
+    block_exclusive_scan<ITEM_SCAN_ROUNDS>(head, nt, hpos);
     __syncthreads();
-    int pos = s_sum[threadIdx.x];
-    for (int i = i0; i < i1; ++i) {
-        const int l = run_level(i);
-        if (((i >> l) << l) != i) continue;
-        const int last = min(nt, i + (1 << l)) - 1;
-        Tile it = tiles[i];
+    for (int t = threadIdx.x; t < nt; t += BLOCK) {
+        if (!head[t]) continue;
+        const int l = run_level(t, nt, tile_rows, goff);
+        const int last = min(nt, t + (1 << l)) - 1;
+        Tile it = tiles[t];
         it.s1 = tiles[last].s1;
-        it.k0 = goff[i];
+        it.k0 = goff[t];
         it.k1 = goff[last + 1];
-        items[pos++] = it;   // a chunk tile keeps its lid and cidx (runs of length 1)
+        items[hpos[t]] = it;   // a chunk tile keeps its lid and cidx (runs of length 1)
     }
+    if (threadIdx.x == 0) ctl->act_nitems = hpos[nt];
 }
 
 // Concatenate the packed neighbours of every tile at its offset goff, and
@@ -842,8 +872,11 @@ template <class T>
 void vc_build_active(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st, double mu)
 {
     VLAUNCH(vc_pack_k<T>, L.grid_ftile, v, ctl, mu);
-    VLAUNCH(vc_items_k, 1, v.ftiles, v.nftiles, (const int32_t *)v.tile_na, (const int32_t *)v.tile_rows, v.goff,
-            v.items, ctl);
+    VLAUNCH(vc_goff_k, 1, (const int32_t *)v.tile_na, v.nftiles, v.goff);
+    VLAUNCH(vc_runs_k, std::max(1, std::min(GRID_MAX, (v.nftiles + BLOCK - 1) / BLOCK)), v.nftiles,
+            (const int32_t *)v.tile_rows, (const int32_t *)v.goff, v.thead);
+    VLAUNCH(vc_items_k, 1, v.ftiles, v.nftiles, (const int32_t *)v.tile_rows, (const int32_t *)v.goff,
+            (const int32_t *)v.thead, v.thpos, v.items, ctl);
     VLAUNCH(vc_concat_k<T>, L.grid_ftile, v);
     VLAUNCH(vc_act_count_k<T>, L.grid_act, v, ctl, mu, L.partials);
     VLAUNCH(vc_act_scan_k, 1, v.acnt, L.grid_act, ctl, (const double *)L.partials, mu);
