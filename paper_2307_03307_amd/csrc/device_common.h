@@ -470,10 +470,13 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double ga0, double
 
 // Candidates of a pass whose packing exponent eta a dymax passes psi_lim
 // (bit k for candidate k): their packing sums are formed max-shifted (see
-// pack_terms).  The replay makes the same test on the same doubles.
+// pack_terms) when psi_shift is on (the chosen form; FP64 refines such steps
+// in two exact passes instead).  The replay makes the same test on the same
+// doubles.
 MWU_DEV uint32_t shifted_mask(const Ctl *c)
 {
     uint32_t m = 0;
+    if (!c->psi_shift) return m;
     for (int k = 0; k < c->ncand && k < 32; ++k)
         if (c->eta * c->cand[k] * c->dymax > c->psi_lim) m |= 1u << k;
     return m;
@@ -727,7 +730,8 @@ MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
     } else {
         const double s1 = c->rS1P[k] * c->invSw;
         const double B = c->eta * alpha * c->dymax;
-        if (B > c->psi_lim) {   // the pass formed the max-shifted sum (shifted_mask)
+        if (B > c->psi_lim && !c->psi_shift) { e.ok = 0; e.psi = 0; }   // full-list refinement
+        else if (B > c->psi_lim) {   // the pass formed the max-shifted sum (shifted_mask)
             if (s1 > 0.0 && isfinite(s1)) e.psi = (B + log(s1)) / c->eta;
             else { e.ok = 0; e.psi = 0; }
         } else if (!isfinite(s1)) { e.ok = 0; e.psi = 0; }

@@ -90,7 +90,8 @@ struct Ctl {
     // ---- sparse passes (fused vertex cover): covering rows whose weight is
     // exactly zero in the storage type are left out of the passes
     int32_t act_on, act_ne;     // lists built; edges in the active search list
-    int32_t act_nitems, pad6;   // work items of the packed transpose pass
+    int32_t act_nitems;         // work items of the packed transpose pass
+    int32_t psi_shift;          // search passes form max-shifted packing sums past psi_lim
     int32_t pass_sparse;        // the last search pass ran over the active list
     int32_t ev_cached;          // ev_* hold the evaluations of the last grid or list pass
     double act_L;               // weight shift the lists were built against

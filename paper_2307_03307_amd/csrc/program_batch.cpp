@@ -443,6 +443,7 @@ class BatchMatching : public BatchProgram {
         c.psi_lim = s_.fp32 ? 80.0 : 700.0;
         c.s2_min = s_.fp32 ? 1e-25 : 1e-280;
         c.qmin = s_.fp32 ? kMixedQminB : 0.0;
+        c.psi_shift = s_.fp32 ? 1 : 0;
         c.onesP = 0;
         c.onesC = 1;
         c.step_rule = s_.opt.step_rule;

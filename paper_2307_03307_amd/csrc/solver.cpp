@@ -440,6 +440,7 @@ static void begin_probe(Solver &s, double param, const double *x0, double eps_pr
     c.psi_lim = s.fp32 ? 80.0 : 700.0;
     c.s2_min = s.fp32 ? 1e-25 : 1e-280;
     c.qmin = s.fp32 ? kMixedQmin : 0.0;
+    c.psi_shift = s.fp32 ? 1 : 0;
     c.onesP = s.onesP;
     c.onesC = s.onesC;
     c.step_rule = s.opt.step_rule;
