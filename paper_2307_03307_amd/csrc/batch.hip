@@ -380,8 +380,11 @@ __global__ __launch_bounds__(BLOCK) void kb_search_fin(BatchDev<T> b)
         for (int q = KC + threadIdx.x; q < 4 * KC; q += BLOCK) s_rec[q] = 0.0;
         __syncthreads();
     }
-    on_ctl(c, [&](Ctl *cl) {
-        finish_search(cl, s_rec);
+    auto pre = [&](Ctl *cl) {   // all candidates at once, one per lane
+        if (cl->skind != SK_REFINE && !cl->hold) pre_eval_search(cl, s_rec);
+    };
+    on_ctl_all(c, pre, [&](Ctl *cl) {
+        finish_search(cl, s_rec, cl->skind != SK_REFINE);
         if (cl->phase == PH_DONE) cl->phase = PH_STATS;
         write_stat(b, k, cl);
     });

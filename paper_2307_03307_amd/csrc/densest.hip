@@ -356,7 +356,12 @@ __global__ __launch_bounds__(BLOCK) void dn_search_fin(Ctl *ctl, const double *p
         const Red red{3 * KC, KC, 0};
         fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
     }
-    on_ctl(ctl, [&](Ctl *c) { finish_search(c, s_rec); });
+    // every candidate of a grid or list pass is evaluated at once, one per
+    // lane, before the sequential replay
+    auto pre = [&](Ctl *c) {
+        if (c->skind != SK_REFINE && !c->hold) pre_eval_search(c, s_rec);
+    };
+    on_ctl_all(ctl, pre, [&](Ctl *c) { finish_search(c, s_rec, c->skind != SK_REFINE); });
 }
 
 // ------------------------------------------------------------------ FP64 statistics

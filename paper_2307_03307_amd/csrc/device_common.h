@@ -150,27 +150,6 @@ MWU_DEV void fold_records_qmajor(const double *partials, int G, Red r, double *s
     block_combine<Q>(v, r, 0, s_wave, out);
 }
 
-// First stage of a two-level fold: workgroup j of the F = gridDim.x folds
-// the entry-major records [G j / F, G (j + 1) / F) into record j of an
-// entry-major array of F records, so the one-workgroup finisher reads F
-// records instead of G.
-template <int Q>
-MWU_DEV void fold_stage_qmajor(const double *partials, int G, Red r, double *s_wave, double *s_out,
-                               double *out)
-{
-    const int F = gridDim.x, j = blockIdx.x;
-    const int b0 = (int)((int64_t)G * j / F), b1 = (int)((int64_t)G * (j + 1) / F);
-    double v[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = red_id(q, r);
-    for (int b = b0 + threadIdx.x; b < b1; b += BLOCK) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], partials[(size_t)q * G + b], q, r);
-    }
-    block_combine<Q>(v, r, 0, s_wave, s_out);
-    if (threadIdx.x < Q) out[(size_t)threadIdx.x * F + j] = s_out[threadIdx.x];
-}
-
 // Fold the G records of a pass (finisher kernel, one workgroup): thread t
 // folds whole records t, t + BLOCK, ... in order (all Q loads of a record in
 // flight at once), then the block combines.  Record entry q is reduced with
@@ -612,15 +591,6 @@ constexpr int cov_record_q()
     return 2 * pass_cands<KIND>() + pass_minima<KIND>();
 }
 
-// First stage of the fold of compact covering records (see fold_stage_qmajor).
-template <int KIND>
-MWU_DEV void fold_cov_stage(const double *part, int G, double *s_wave, double *s_tmp, double *out)
-{
-    constexpr int N = pass_cands<KIND>(), M = pass_minima<KIND>();
-    const Red r{2 * N, M, 0};
-    fold_stage_qmajor<cov_record_q<KIND>()>(part, G, r, s_wave, s_tmp, out);
-}
-
 // Finisher side of the compact records (stored entry-major): fold them and
 // spread the totals to
 // out = [s1C(KC) | s2C(KC) | zmin(KC)] (sums the pass did not form are 0,
@@ -683,6 +653,27 @@ MWU_DEV bool act_valid(const Ctl *c, double Lw)
 // costs an L2 round trip.  The workgroup stages the block in LDS with one
 // load per thread, thread 0 runs f on the copy, and the workgroup writes the
 // whole block back.  All threads of the workgroup must call.
+// A finisher may stage the block before anything else: its phase test then
+// reads the staged copy, so the block is fetched in the same round trip as
+// the test and not again after the fold.  All threads call ctl_stage (which
+// returns the staged block) and, when the finisher changed it,
+// ctl_write_back.
+constexpr int CTL_WORDS = sizeof(Ctl) / 8;
+MWU_DEV Ctl *ctl_stage(const Ctl *g, uint64_t *s_ctl)
+{
+    static_assert(sizeof(Ctl) % 8 == 0, "control block is copied in 8-byte words");
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(g);
+    for (int i = threadIdx.x; i < CTL_WORDS; i += blockDim.x) s_ctl[i] = src[i];
+    __syncthreads();
+    return reinterpret_cast<Ctl *>(s_ctl);
+}
+MWU_DEV void ctl_write_back(Ctl *g, const uint64_t *s_ctl)
+{
+    __syncthreads();
+    uint64_t *dst = reinterpret_cast<uint64_t *>(g);
+    for (int i = threadIdx.x; i < CTL_WORDS; i += blockDim.x) dst[i] = s_ctl[i];
+}
+
 template <class F>
 MWU_DEV void on_ctl(Ctl *g, F &&f);
 
@@ -853,24 +844,45 @@ MWU_DEV void stop_infeasible(Ctl *c)
     c->phase = PH_DONE;
 }
 
+// The candidates of the pass being replayed, copied once into registers of
+// the replaying thread: the control block sits in shared memory, and a search
+// over it would be a chain of dependent loads, one per candidate, at every
+// lookup.  The candidates do not change during a replay (a new pass ends it).
+struct CandRegs {
+    double v[KC];
+    int n;
+    MWU_DEV explicit CandRegs(const Ctl *c) : n(c->ncand)
+    {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) v[k] = c->cand[k];
+    }
+    // index of the first candidate equal to a, or -1
+    MWU_DEV int find(double a) const
+    {
+        int hit = -1;
+#pragma unroll
+        for (int k = KC - 1; k >= 0; --k)
+            if (k < n && v[k] == a) hit = k;
+        return hit;
+    }
+};
+
 // Find the evaluation of step a: a refined value, or a grid candidate.
 // Returns 0 = found (e filled), 1 = not in the grid, 2 = needs refinement.
-MWU_DEV int lookup(const Ctl *c, double a, Eval *e)
+MWU_DEV int lookup(const Ctl *c, const CandRegs &cr, double a, Eval *e)
 {
     if (c->ref_valid == 1 && c->ref_alpha == a) {
         e->psi = c->ref_psi; e->phi = c->ref_phi; e->zmin = c->ref_zmin; e->ok = 1;
         return 0;
     }
-    for (int k = 0; k < c->ncand; ++k)
-        if (c->cand[k] == a) {
-            if (c->ev_cached) {
-                e->psi = c->ev_psi[k]; e->phi = c->ev_phi[k]; e->zmin = c->ev_zmin[k]; e->ok = c->ev_ok[k];
-            } else {
-                *e = eval_cand(c, k, a);
-            }
-            return e->ok ? 0 : 2;
-        }
-    return 1;
+    const int k = cr.find(a);
+    if (k < 0) return 1;
+    if (c->ev_cached) {
+        e->psi = c->ev_psi[k]; e->phi = c->ev_phi[k]; e->zmin = c->ev_zmin[k]; e->ok = c->ev_ok[k];
+    } else {
+        *e = eval_cand(c, k, a);
+    }
+    return e->ok ? 0 : 2;
 }
 
 // Store the reduced record of a grid or list pass and evaluate all its
@@ -900,11 +912,12 @@ constexpr double ALPHA_CAP = 1125899906842624.0;   // 2^50
 
 MWU_DEV void replay(Ctl *c)
 {
+    const CandRegs cr(c);
     for (int guard = 0; guard < 256; ++guard) {
         if (c->amode == AM_FORCED) {
             const double a = c->cur_alpha;
             Eval e;
-            int r = lookup(c, a, &e);
+            int r = lookup(c, cr, a, &e);
             if (r == 1) { c->skind = SK_LIST; c->ncand = 1; c->cand[0] = a; return; }
             if (r == 2) { setup_refine(c, a); return; }
             c->evaluations += 1;
@@ -915,7 +928,7 @@ MWU_DEV void replay(Ctl *c)
         if (c->amode == AM_EXP) {
             const double a = c->exp_next;
             Eval e;
-            int r = lookup(c, a, &e);
+            int r = lookup(c, cr, a, &e);
             if (r == 1) { setup_exp(c, a); return; }
             if (r == 2) { setup_refine(c, a); return; }
             c->evaluations += 1;
@@ -936,7 +949,7 @@ MWU_DEV void replay(Ctl *c)
         if (!(c->ub - c->lb > c->eps * c->lb)) { accept_step(c, c->lb, c->lb_psi, c->lb_phi); return; }
         const double beta = (c->lb + c->ub) / 2.0;
         Eval e;
-        int r = lookup(c, beta, &e);
+        int r = lookup(c, cr, beta, &e);
         if (r == 1) { setup_grid(c, c->lb, c->ub); return; }
         if (r == 2) { setup_refine(c, beta); return; }
         c->evaluations += 1;

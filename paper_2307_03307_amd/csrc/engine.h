@@ -310,9 +310,7 @@ struct VcLaunch {
     int grid_e;        // edge passes (search, min z, export)
     int grid_act;      // blocks of the active-list build (contiguous edge ranges)
     double *partials;
-    double *partials2; // first-stage folds of the search records (SEARCH_FOLD records)
 };
-constexpr int SEARCH_FOLD = 16;   // workgroups of the first stage of the search fold
 template <class T> void vc_init(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st,
                                 bool have_x0);
 template <class T> void vc_iteration(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st);

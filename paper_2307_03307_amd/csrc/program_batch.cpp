@@ -254,6 +254,10 @@ class BatchMatching : public BatchProgram {
             int active = 0;
             for (const Inst &I : inst_) active += !I.done;
             if (!active) return true;
+            if (2 * active <= tiled_active_) {
+                retile_active(active);
+                ensure_graph();
+            }
             if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > seconds)
                 return false;
             if (launches++ > cap) throw ApiError{MWU_ERR_DEVICE, "batched solve did not finish"};
@@ -290,6 +294,7 @@ class BatchMatching : public BatchProgram {
     // configured and pushed.
     void start_all()
     {
+        if (tiled_active_ != nb_) relayout(layout_);
         for (int32_t k = 0; k < nb_; ++k) {
             Inst &I = inst_[k];
             I.lo = I.lo0; I.hi = I.hi0;
@@ -302,22 +307,51 @@ class BatchMatching : public BatchProgram {
         push_state();
     }
 
-    // Edge tiles and element tiles of every instance (never across
-    // instances), their record buffers and the persistent grids.
+    // The layout L for the whole batch: tiles, grids and the reported layout.
     void relayout(const mwu_batch_layout &L)
+    {
+        tile(L, L.tile_edges, L.tile_vertices, false);
+        layout_ = L;
+        tiled_active_ = nb_;
+    }
+
+    // As instances finish their searches, the tiles of the others are
+    // rebuilt (finished instances get none) with the tile sizes of the layout
+    // halved while the tiles of one kind would not fill one round of resident
+    // workgroups: the few instances left at the end of a solve then still
+    // spread over the whole chip.  Called between graph launches.
+    void retile_active(int active)
+    {
+        const mwu_batch_layout &L = layout_;
+        int64_t ev = 0, vv = 0;
+        for (const Inst &I : inst_)
+            if (!I.done) { ev += I.ne; vv += I.nv; }
+        const int64_t round_e = (int64_t)std::min(occ_e_, L.workgroups_per_cu) * s_.num_cus;
+        int32_t te = L.tile_edges, tv = L.tile_vertices;
+        while (te > BLOCK && (ev + te - 1) / te < round_e) te /= 2;
+        while (tv > BLOCK && (vv + tv - 1) / tv < round_e) tv /= 2;
+        tile(L, te % BLOCK ? BLOCK : te, tv % BLOCK ? BLOCK : tv, true);
+        tiled_active_ = active;
+    }
+
+    // Edge tiles and element tiles of every instance (never across
+    // instances; of the instances still searching when active_only), their
+    // record buffers and the persistent grids of layout L.
+    void tile(const mwu_batch_layout &L, int32_t tile_edges, int32_t tile_vertices, bool active_only)
     {
         std::vector<BTile> et, wt;
         std::vector<int32_t> erec0(nb_), erecn(nb_), wrec0(nb_), wrecn(nb_);
         for (int32_t k = 0; k < nb_; ++k) {
             const Inst &I = inst_[k];
+            const bool skip = active_only && I.done;
             wrec0[k] = (int32_t)wt.size();
-            for (int64_t i = 0; i < I.nv; i += L.tile_vertices)
-                wt.push_back(BTile{k, (int32_t)(I.v0 + i), (int32_t)(I.v0 + std::min<int64_t>(i + L.tile_vertices, I.nv)),
+            for (int64_t i = 0; !skip && i < I.nv; i += tile_vertices)
+                wt.push_back(BTile{k, (int32_t)(I.v0 + i), (int32_t)(I.v0 + std::min<int64_t>(i + tile_vertices, I.nv)),
                                    0, 0, -1, 0, 0});
             wrecn[k] = (int32_t)wt.size() - wrec0[k];
             erec0[k] = (int32_t)et.size();
-            for (int64_t i = 0; i < I.ne; i += L.tile_edges)
-                et.push_back(BTile{k, (int32_t)(I.e0 + i), (int32_t)(I.e0 + std::min<int64_t>(i + L.tile_edges, I.ne)),
+            for (int64_t i = 0; !skip && i < I.ne; i += tile_edges)
+                et.push_back(BTile{k, (int32_t)(I.e0 + i), (int32_t)(I.e0 + std::min<int64_t>(i + tile_edges, I.ne)),
                                    0, 0, -1, 0, 0});
             erecn[k] = (int32_t)et.size() - erec0[k];
         }
@@ -351,7 +385,6 @@ class BatchMatching : public BatchProgram {
         L_.grid_w = grid(bd_.nwt, occ_e_);
         L_.grid_e = grid(bd_.net, occ_e_);
         L_.nsearch = L.search_launches;
-        layout_ = L;
     }
 
     // Edge-iterations per second of the current layout over the opening of a
@@ -516,6 +549,7 @@ class BatchMatching : public BatchProgram {
     int slots_ = 8;
     int occ_v_ = 1, occ_e_ = 1;
     mwu_batch_layout layout_{};
+    int32_t tiled_active_ = 0;   // instances the current tiles were built for (nb_: the whole batch)
     std::vector<Inst> inst_;
     BatchDev<T> bd_{};
     BLaunch L_{};

@@ -153,8 +153,6 @@ class VcoverProgram : public Program {
         acnt_.alloc((size_t)L_.grid_act * 4);
         vd_.acnt = acnt_.as<int32_t>();
         L_.partials = partials_.as<double>();
-        partials2_.alloc((size_t)SEARCH_FOLD * QMAX * 8);
-        L_.partials2 = partials2_.as<double>();
     }
 
     int64_t n() const override { return nv_; }
@@ -373,7 +371,7 @@ class VcoverProgram : public Program {
     std::vector<int32_t> dev_;     // compact vertex id -> device vertex id
     std::vector<int64_t> canon_;
     DevBuf eu_, ew_, fptr_, fcol_, ftiles_, flseg_, flfirst_, flcount_, flpart_;
-    DevBuf xd_, xs_, xbest_, h_, partials_, partials2_, forced_, hdbg_, fcol_pk_, fptr_pk_, tile_na_, aeu_, aew_, acnt_;
+    DevBuf xd_, xs_, xbest_, h_, partials_, forced_, hdbg_, fcol_pk_, fptr_pk_, tile_na_, aeu_, aew_, acnt_;
     DevBuf ccol_, cst_, goff_, items_, tile_rows_, thead_, thpos_;
 };
 

@@ -317,13 +317,16 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, con
 {
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
-    if (ctl->phase != PH_ROW) return;
+    __shared__ uint64_t s_ctl[CTL_WORDS];
+    Ctl *c = ctl_stage(ctl, s_ctl);
+    if (c->phase != PH_ROW) return;
     if (with_long)
         for (int l = threadIdx.x; l < vd.flong.nlong; l += BLOCK)
             vd.h[vd.flong.lseg[l]] = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
     const Red red{1, 1, 0};
     fold_records<2>(part, G, red, 0, s_wave, s_rec);
-    on_ctl(ctl, [&](Ctl *c) { finish_vcA(c, s_rec); });
+    if (threadIdx.x == 0) finish_vcA(c, s_rec);
+    ctl_write_back(ctl, s_ctl);
 }
 
 template <class T>
@@ -361,15 +364,19 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_fin(VcDev<T> vd, Ctl *ctl, con
 {
     __shared__ double s_wave[4 * 3];
     __shared__ double s_rec[QMAX];
-    const int ph = ctl->phase;
+    __shared__ uint64_t s_ctl[CTL_WORDS];
+    Ctl *c = ctl_stage(ctl, s_ctl);
+    const int ph = c->phase;
     if (ph != PH_COL && ph != PH_COMMIT) return;
     if (ph == PH_COMMIT) {
-        if (threadIdx.x == 0 && !held(ctl)) { ctl->alpha = 0.0; ctl->phase = PH_DONE; }
+        if (threadIdx.x == 0 && !held(c)) { c->alpha = 0.0; c->phase = PH_DONE; }
+        ctl_write_back(ctl, s_ctl);
         return;
     }
     const Red red{1, 0, 2};
     fold_records<3>(part, G, red, 0, s_wave, s_rec);
-    on_ctl(ctl, [&](Ctl *c) { finish_vcB(c, s_rec, vd.forced); });
+    if (threadIdx.x == 0) finish_vcB(c, s_rec, vd.forced);
+    ctl_write_back(ctl, s_ctl);
 }
 
 // K-candidate covering sums of one search pass over the edge list (KIND fixed
@@ -450,54 +457,44 @@ template <>
 __global__ __launch_bounds__(BLOCK)
 void vc_search_k<double>(VcDev<double> vd, Ctl *ctl, double *part) { vc_search_body<double>(vd, ctl, part); }
 
-// First stage of the fold of the search records (grid and list passes; the
-// records of a refinement pass are folded by the finisher directly).
-__global__ __launch_bounds__(BLOCK) void vc_search_fold(const Ctl *ctl, const double *part, int G, double *part2)
-{
-    __shared__ double s_wave[4 * 3 * KC];
-    __shared__ double s_tmp[QMAX];
-    if (ctl->phase != PH_SEARCH || ctl->skind == SK_REFINE) return;
-    switch (ctl->skind) {
-    case SK_EXP: fold_cov_stage<SK_EXP>(part, G, s_wave, s_tmp, part2); break;
-    case SK_GRID: fold_cov_stage<SK_GRID>(part, G, s_wave, s_tmp, part2); break;
-    case SK_COMBO: fold_cov_stage<SK_COMBO>(part, G, s_wave, s_tmp, part2); break;
-    default: fold_cov_stage<SK_LIST>(part, G, s_wave, s_tmp, part2); break;
-    }
-}
-
-// part: the records of the search kernel (G of them); part2: the first-stage
-// folds (SEARCH_FOLD of them) of a grid or list pass.
-__global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G, const double *part2)
+// part: the records of the search kernel (G of them, one per workgroup),
+// folded here in one stage (each thread folds whole records, the loads of a
+// record in flight together).
+__global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *part, int G)
 {
     __shared__ double s_wave[4 * 3 * KC];
     __shared__ double s_rec[QMAX];
-    if (ctl->phase != PH_SEARCH) return;
-    if (ctl->skind == SK_REFINE) {
+    __shared__ double s_tmp[QMAX];
+    __shared__ uint64_t s_ctl[CTL_WORDS];
+    Ctl *c = ctl_stage(ctl, s_ctl);
+    if (c->phase != PH_SEARCH) return;
+    const int kind = c->skind;
+    if (kind == SK_REFINE) {
         const Red red{1, 1, 0};
         fold_records<2>(part, G, red, 0, s_wave, s_rec);
-        on_ctl(ctl, [&](Ctl *c) {
+        if (threadIdx.x == 0) {
             // finish_search expects pass 1 [min z' | max eta*y'], pass 2 [sumP | sumC]
             double r[2];
             if (c->ref_valid == 0) { r[0] = s_rec[1]; r[1] = -INFINITY; }
             else { r[0] = 1.0; r[1] = s_rec[0]; }
             finish_search(c, r);
-        });
+        }
+        ctl_write_back(ctl, s_ctl);
         return;
     }
-    __shared__ double s_tmp[QMAX];
-    switch (ctl->skind) {
-    case SK_EXP: fold_cov_compact<SK_EXP>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
-    case SK_GRID: fold_cov_compact<SK_GRID>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
-    case SK_COMBO: fold_cov_compact<SK_COMBO>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
-    default: fold_cov_compact<SK_LIST>(part2, SEARCH_FOLD, s_wave, s_tmp, s_rec + KC); break;
+    switch (kind) {
+    case SK_EXP: fold_cov_compact<SK_EXP>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    case SK_GRID: fold_cov_compact<SK_GRID>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    case SK_COMBO: fold_cov_compact<SK_COMBO>(part, G, s_wave, s_tmp, s_rec + KC); break;
+    default: fold_cov_compact<SK_LIST>(part, G, s_wave, s_tmp, s_rec + KC); break;
     }
-    auto pre = [&](Ctl *c) {
-        if (threadIdx.x < KC) s_rec[threadIdx.x] = 0.0;     // no packing rows: Psi = a * dy1
-        if (threadIdx.x == 0) c->pass_sparse = act_valid(c, c->LCw);   // as the search kernel decided
-        __syncthreads();
-        if (!c->hold) pre_eval_search(c, s_rec);
-    };
-    on_ctl_all(ctl, pre, [&](Ctl *c) { finish_search(c, s_rec, true); });
+    if (threadIdx.x < KC) s_rec[threadIdx.x] = 0.0;     // no packing rows: Psi = a * dy1
+    if (threadIdx.x == 0) c->pass_sparse = act_valid(c, c->LCw);   // as the search kernel decided
+    __syncthreads();
+    if (!c->hold) pre_eval_search(c, s_rec);
+    __syncthreads();
+    if (threadIdx.x == 0) finish_search(c, s_rec, true);
+    ctl_write_back(ctl, s_ctl);
 }
 
 template <class T>
@@ -597,53 +594,56 @@ __global__ __launch_bounds__(BLOCK) void vc_pack_k(VcDev<T> vd, const Ctl *ctl, 
 }
 
 // Exclusive prefix of src[0..n) into dst[0..n] (dst[n] = total) by one
-// workgroup, in batches of ROUNDS x BLOCK elements (each thread holds its
-// elements of a batch in registers first, so their loads are in flight
-// together).
-template <int ROUNDS>
+// workgroup, in batches of PER x BLOCK elements: each thread loads and sums
+// PER consecutive elements, one scan over the thread totals places them, and
+// each thread writes its elements' prefixes (two barriers per batch).
+template <int PER>
 MWU_DEV void block_exclusive_scan(const int32_t *src, int n, int32_t *dst)
 {
     __shared__ int32_t s_w[BLOCK / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int run = 0;
-    for (int base = 0; base < n; base += ROUNDS * BLOCK) {
-        int32_t v[ROUNDS];
+    for (int base = 0; base < n; base += PER * BLOCK) {
+        const int i0 = base + threadIdx.x * PER;
+        int32_t v[PER];
+        int tsum = 0;
 #pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-            const int i = base + r * BLOCK + threadIdx.x;
-            v[r] = i < n ? src[i] : 0;
+        for (int r = 0; r < PER; ++r) {
+            v[r] = i0 + r < n ? src[i0 + r] : 0;
+            tsum += v[r];
         }
+        int x = tsum;                                       // inclusive scan in the wave
 #pragma unroll
-        for (int r = 0; r < ROUNDS; ++r) {
-            int x = v[r];                                   // inclusive scan in the wave
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int y = __shfl_up(x, d);
-                if (lane >= d) x += y;
-            }
-            if (lane == 63) s_w[wv] = x;
-            __syncthreads();
-            int off = run, tot = 0;
-            for (int w = 0; w < BLOCK / 64; ++w) {
-                if (w < wv) off += s_w[w];
-                tot += s_w[w];
-            }
-            const int i = base + r * BLOCK + threadIdx.x;
-            if (i < n) dst[i] = off + x - v[r];
-            run += tot;
-            __syncthreads();
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d);
+            if (lane >= d) x += y;
         }
+        if (lane == 63) s_w[wv] = x;
+        __syncthreads();
+        int off = run, tot = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            if (w < wv) off += s_w[w];
+            tot += s_w[w];
+        }
+        int p = off + x - tsum;
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            if (i0 + r < n) dst[i0 + r] = p;
+            p += v[r];
+        }
+        run += tot;
+        __syncthreads();
     }
     if (threadIdx.x == 0) dst[n] = run;
 }
 
-constexpr int ITEM_SCAN_ROUNDS = 16;
+constexpr int ITEM_SCAN_PER = 16;
 
 // Tile offsets goff of the concatenated packed neighbours (exclusive prefix
 // of tile_na).
 __global__ __launch_bounds__(BLOCK) void vc_goff_k(const int32_t *tile_na, int nt, int32_t *goff)
 {
-    block_exclusive_scan<ITEM_SCAN_ROUNDS>(tile_na, nt, goff);
+    block_exclusive_scan<ITEM_SCAN_PER>(tile_na, nt, goff);
 }
 
 // Work items of the packed pass: tile t joins the largest aligned run of 2^l
@@ -672,14 +672,19 @@ __global__ __launch_bounds__(BLOCK) void vc_runs_k(int nt, const int32_t *tile_r
     }
 }
 
-// One workgroup: positions of the run heads, then the items in order.
-__global__ __launch_bounds__(BLOCK) void vc_items_k(const Tile *tiles, int nt, const int32_t *tile_rows,
-                                                    const int32_t *goff, const int32_t *head, int32_t *hpos,
-                                                    Tile *items, Ctl *ctl)
+// One workgroup: positions of the run heads and the number of items.
+__global__ __launch_bounds__(BLOCK) void vc_hscan_k(const int32_t *head, int nt, int32_t *hpos, Ctl *ctl)
 {
-    block_exclusive_scan<ITEM_SCAN_ROUNDS>(head, nt, hpos);
-    __syncthreads();
-    for (int t = threadIdx.x; t < nt; t += BLOCK) {
+    block_exclusive_scan<ITEM_SCAN_PER>(head, nt, hpos);
+    if (threadIdx.x == 0) ctl->act_nitems = hpos[nt];   // written by this thread
+}
+
+// The items in order, one thread per run head.
+__global__ __launch_bounds__(BLOCK) void vc_items_k(const Tile *tiles, int nt, const int32_t *tile_rows,
+                                                    const int32_t *goff, const int32_t *head,
+                                                    const int32_t *hpos, Tile *items)
+{
+    for (int t = blockIdx.x * BLOCK + threadIdx.x; t < nt; t += gridDim.x * BLOCK) {
         if (!head[t]) continue;
         const int l = run_level(t, nt, tile_rows, goff);
         const int last = min(nt, t + (1 << l)) - 1;
@@ -689,7 +694,6 @@ __global__ __launch_bounds__(BLOCK) void vc_items_k(const Tile *tiles, int nt, c
         it.k1 = goff[last + 1];
         items[hpos[t]] = it;   // a chunk tile keeps its lid and cidx (runs of length 1)
     }
-    if (threadIdx.x == 0) ctl->act_nitems = hpos[nt];
 }
 
 // Concatenate the packed neighbours of every tile at its offset goff, and
@@ -852,8 +856,7 @@ template <class T>
 void vc_search(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
 {
     VLAUNCH(vc_search_k<T>, L.grid_e, v, ctl, L.partials);
-    VLAUNCH(vc_search_fold, SEARCH_FOLD, ctl, (const double *)L.partials, L.grid_e, L.partials2);
-    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_e, (const double *)L.partials2);
+    VLAUNCH(vc_search_fin, 1, ctl, (const double *)L.partials, L.grid_e);
 }
 
 // One iteration slot with a single search launch: most iterations finish
@@ -873,10 +876,11 @@ void vc_build_active(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t
 {
     VLAUNCH(vc_pack_k<T>, L.grid_ftile, v, ctl, mu);
     VLAUNCH(vc_goff_k, 1, (const int32_t *)v.tile_na, v.nftiles, v.goff);
-    VLAUNCH(vc_runs_k, std::max(1, std::min(GRID_MAX, (v.nftiles + BLOCK - 1) / BLOCK)), v.nftiles,
-            (const int32_t *)v.tile_rows, (const int32_t *)v.goff, v.thead);
-    VLAUNCH(vc_items_k, 1, v.ftiles, v.nftiles, (const int32_t *)v.tile_rows, (const int32_t *)v.goff,
-            (const int32_t *)v.thead, v.thpos, v.items, ctl);
+    const int gt = std::max(1, std::min(GRID_MAX, (v.nftiles + BLOCK - 1) / BLOCK));
+    VLAUNCH(vc_runs_k, gt, v.nftiles, (const int32_t *)v.tile_rows, (const int32_t *)v.goff, v.thead);
+    VLAUNCH(vc_hscan_k, 1, (const int32_t *)v.thead, v.nftiles, v.thpos, ctl);
+    VLAUNCH(vc_items_k, gt, v.ftiles, v.nftiles, (const int32_t *)v.tile_rows, (const int32_t *)v.goff,
+            (const int32_t *)v.thead, (const int32_t *)v.thpos, v.items);
     VLAUNCH(vc_concat_k<T>, L.grid_ftile, v);
     VLAUNCH(vc_act_count_k<T>, L.grid_act, v, ctl, mu, L.partials);
     VLAUNCH(vc_act_scan_k, 1, v.acnt, L.grid_act, ctl, (const double *)L.partials, mu);
