@@ -37,9 +37,13 @@ def make_graph(scale, edge_factor, seed):
     return gg.cached(f"rmat{scale}_ef{edge_factor}_s{seed}", lambda: gg.rmat(scale, edge_factor, seed=seed))
 
 
-def run_solves(mwu, g, precision, steps, warmup):
+def step_rule_of(mwu, args):
+    return mwu.STEP_BIN_WARM if args.step_rule == "warm" else mwu.STEP_BIN
+
+
+def run_solves(mwu, g, precision, steps, warmup, step_rule):
     t0 = time.perf_counter()
-    s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision)
+    s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, step_rule=step_rule)
     create_s = time.perf_counter() - t0
     res = []
     for i in range(warmup + steps):
@@ -130,7 +134,8 @@ def run_densest(args):
 
     def run(precision, steps, warmup):
         t = time.perf_counter()
-        s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision)
+        s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision,
+                                 step_rule=step_rule_of(mwu, args))
         create = time.perf_counter() - t
         walls, r = [], None
         for i in range(warmup + steps):
@@ -156,7 +161,8 @@ def run_densest(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"densest subgraph LP (Charikar dual, D searched), R-MAT scale {args.scale}, "
                                f"edge factor {args.edge_factor}, a/b/c=0.57/0.19/0.19, seed 3, eps=0.1",
-                   "vertices": g.num_vertices, "edges": g.num_edges, "variables": 2 * g.num_edges},
+                   "vertices": g.num_vertices, "edges": g.num_edges, "variables": 2 * g.num_edges,
+                   "step_rule": args.step_rule},
         "certified": r32.certified, "objective": r32.objective, "bracket": [r32.lower, r32.upper],
         "iterations": r32.total_iterations, "probes": r32.probes, "create_s": c32,
         "fp64_plain_s": statistics.mean(w64), "fp64_certified": r64.certified,
@@ -189,7 +195,7 @@ def run_batched(args):
 
     def run(precision, steps, warmup, tune=True):
         t = time.perf_counter()
-        b = mwu.BatchSolver(spec, precision=precision, tune=tune)
+        b = mwu.BatchSolver(spec, precision=precision, tune=tune, step_rule=step_rule_of(mwu, args))
         create = time.perf_counter() - t
         layout = b.layout()
         log(f"  precision={precision} create {create:.2f}s layout {layout}")
@@ -246,7 +252,7 @@ def run_batched(args):
         "data": "synthetic",
         "config": {"workload": f"batched bipartite matching LPs: {len(gs)} instances, sides uniform in "
                                f"[1024, 65536], mean degree uniform in [4, 16], eps=0.1",
-                   "instances": len(gs), "vertices": V, "edges": E},
+                   "instances": len(gs), "vertices": V, "edges": E, "step_rule": args.step_rule},
         "certified": sum(r.certified for r in r32),
         "exact_optimum_in_bracket": f"{ok}/{len(sample)}",
         "iterations": sum(r.total_iterations for r in r32),
@@ -283,6 +289,8 @@ def main():
                          "densest: R-MAT densest subgraph (use --scale 22)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--loop-sample", type=int, default=16)
+    ap.add_argument("--step-rule", choices=["bin", "warm"], default="bin",
+                    help="bin: Algorithm 3 from 1 in every iteration; warm: started at the previous step")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -310,7 +318,8 @@ def main():
     if args.copy_calib_mib:
         copy_calibration(args.copy_calib_mib)
     torch.cuda.synchronize()
-    s32, create32, r32 = run_solves(mwu, g, mwu.MIXED_FP32_FP64, args.steps, args.warmup)
+    rule = step_rule_of(mwu, args)
+    s32, create32, r32 = run_solves(mwu, g, mwu.MIXED_FP32_FP64, args.steps, args.warmup, rule)
     torch.cuda.synchronize()
     t32 = statistics.mean(w for w, _ in r32)
     last32 = r32[-1][1]
@@ -322,7 +331,7 @@ def main():
     last64 = None
     passes64 = None
     if not args.no_fp64:
-        s64, create64, r64 = run_solves(mwu, g, mwu.FP64, args.steps, args.warmup)
+        s64, create64, r64 = run_solves(mwu, g, mwu.FP64, args.steps, args.warmup, rule)
         torch.cuda.synchronize()
         t64 = statistics.mean(w for w, _ in r64)
         last64 = r64[-1][1]
@@ -372,7 +381,7 @@ def main():
         "config": {"workload": f"vertex cover LP, R-MAT scale {args.scale}, edge factor "
                                f"{args.edge_factor}, a/b/c=0.57/0.19/0.19, seed 2, eps=0.1",
                    "vertices": g.num_vertices, "edges": g.num_edges, "eps": 0.1,
-                   "form": "mixed FP32 vectors / FP64 totals and decisions"},
+                   "form": "mixed FP32 vectors / FP64 totals and decisions", "step_rule": args.step_rule},
         "certified": last32.certified,
         "objective": last32.objective,
         "bracket": [last32.lower, last32.upper],

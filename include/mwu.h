@@ -113,6 +113,12 @@ typedef struct {
 
 #define MWU_STEP_STD 0   /* alpha = 1 (Algorithm 1) */
 #define MWU_STEP_BIN 1   /* exponential + binary search (Algorithm 3) */
+/* Algorithm 3 started at the step the probe accepted last (the setting of
+ * the Bin column of Table 2): doubling from there while the test holds, or
+ * halving while it fails (never below 1; a failing test at 1 ends the probe
+ * as infeasible), then the same bisection.  The first iteration of a probe
+ * starts at 1. */
+#define MWU_STEP_BIN_WARM 2
 
 #define MWU_FP64 0               /* plain: every vector and sum in double */
 #define MWU_MIXED_FP32_FP64 1    /* vectors and per-element terms in float; LSE totals, search sums,
@@ -126,7 +132,7 @@ typedef struct {
     double eps;                 /* accuracy, default 0.1 (Section 6.2) */
     int32_t max_iter;           /* iterations per probe, default 5000 (Section 6.2) */
     int32_t max_probes;         /* outer search cap, default 64 */
-    int32_t step_rule;          /* MWU_STEP_BIN (default) or MWU_STEP_STD */
+    int32_t step_rule;          /* MWU_STEP_BIN (default), MWU_STEP_BIN_WARM or MWU_STEP_STD */
     int32_t precision;          /* MWU_MIXED_FP32_FP64 (default) or MWU_FP64 */
     int32_t iters_per_launch;   /* iterations captured per graph launch; 0 = default (8) */
     int32_t device;             /* HIP device ordinal, default 0 */

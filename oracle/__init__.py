@@ -35,7 +35,7 @@ _LIB = os.path.join(_HERE, "libmwu_oracle.so")
 
 STATUS_NAMES = {0: "RUNNING", 1: "FEASIBLE", 2: "INFEASIBLE", 3: "MAX_ITER"}
 FEASIBLE, INFEASIBLE, MAX_ITER = 1, 2, 3
-STEP_STD, STEP_BIN = 0, 1
+STEP_STD, STEP_BIN, STEP_BIN_WARM = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -108,6 +108,10 @@ def lib():
                                             vp, vp, vp, ctypes.c_int64, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, vp]
         L.orc_step_search_terms.restype = ctypes.c_double
+        L.orc_step_search_terms_from.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_double,
+                                                 vp, vp, vp, ctypes.c_int64, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
+        L.orc_step_search_terms_from.restype = ctypes.c_double
         L.orc_potential.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double,
                                     ctypes.c_double, vp, vp]
         L.orc_potential.restype = ctypes.c_double
@@ -375,14 +379,18 @@ def phi(z, dz, u, eta_, L, alpha):
     return v, zm.value
 
 
-def step_search(y, dy, w, LP, z, dz, u, LC, eta_, eps):
-    """Algorithm 3 on given vectors; returns (alpha, number of T evaluations)."""
+def step_search(y, dy, w, LP, z, dz, u, LC, eta_, eps, start=None):
+    """Algorithm 3 on given vectors; returns (alpha, number of T evaluations).
+    start (above 1): the warm-started search of reading R19 from that step."""
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (y, dy, w, z, dz, u)]
     ev = ctypes.c_int64()
-    a = lib().orc_step_search_terms(arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
-                                    arrs[0].shape[0], LP, arrs[3].ctypes.data, arrs[4].ctypes.data,
-                                    arrs[5].ctypes.data, arrs[3].shape[0], LC, eta_, eps,
-                                    ctypes.addressof(ev))
+    head = (arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data, arrs[0].shape[0], LP,
+            arrs[3].ctypes.data, arrs[4].ctypes.data, arrs[5].ctypes.data, arrs[3].shape[0], LC,
+            eta_, eps)
+    if start is None:
+        a = lib().orc_step_search_terms(*head, ctypes.addressof(ev))
+    else:
+        a = lib().orc_step_search_terms_from(*head, float(start), ctypes.addressof(ev))
     return a, ev.value
 
 

@@ -48,6 +48,17 @@
  *       1+eps.  When the search bracket closes first, the probes continue at
  *       half the tolerance (a feasible probe then overshoots its M by about
  *       eps/2 instead of eps) from the certified bracket, at most twice.
+ *   R19 warm start (ORC_STEP_BIN_WARM; the setting of the Bin column of
+ *       Table 2, which starts each search at the previous step): the search
+ *       of an iteration starts at the step the probe accepted last (1 in a
+ *       probe's first iteration).  If T holds there, the search goes on
+ *       exactly as Algorithm 3 from that value (doubling with the early
+ *       return, then the bisection).  If T fails there, the value is halved
+ *       until T holds (a halving below 1 evaluates 1 instead, and a failing
+ *       T(1) ends the probe as in R4); the first value where T holds is
+ *       returned at once when it satisfies every covering row (R2), and
+ *       otherwise the bracket [it, the last failing value] is bisected as in
+ *       R1.
  */
 #include <math.h>
 #include <stdint.h>
@@ -62,7 +73,7 @@ typedef struct {
 } orc_mat;
 
 enum { ORC_RUNNING = 0, ORC_FEASIBLE = 1, ORC_INFEASIBLE = 2, ORC_MAX_ITER = 3 };
-enum { ORC_STEP_STD = 0, ORC_STEP_BIN = 1 };
+enum { ORC_STEP_STD = 0, ORC_STEP_BIN = 1, ORC_STEP_BIN_WARM = 2 };
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_UNBOUNDED = -2, ORC_ERR_OOM = -3 };
 
 /* Threshold below which 1 + sum(u*expm1(-b)) is taken as too cancelled and the
@@ -236,15 +247,44 @@ static orc_eval evaluate(orc_state *st, double alpha)
     return e;
 }
 
-/* Algorithm 3: exponential search from alpha = 1, then binary search on
- * [alpha/2, alpha] until (ub-lb) <= eps*lb; returns lb.  Returns a value < 1
- * when T(1) fails (R4). */
-static double step_search(orc_state *st, int64_t *evals)
+/* Bisection of [lb, ub] (T holds at lb, fails at ub) until (ub-lb) <= eps*lb
+ * (R1); returns lb. */
+static double bisect(orc_state *st, double lb, double ub, int64_t *evals)
 {
-    double alpha = 1.0;
+    while (ub - lb > st->eps * lb) {
+        double beta = (lb + ub) / 2.0;
+        orc_eval eb = evaluate(st, beta);
+        ++*evals;
+        if (eb.pass) lb = beta; else ub = beta;
+    }
+    return lb;
+}
+
+/* Algorithm 3 from alpha = start (start = 1: the algorithm as printed):
+ * doubling while T holds, with the early return (R2), then the bisection of
+ * [alpha, 2 alpha].  When T fails at start > 1 the search halves downward
+ * (R19).  Returns a value < 1 when T(1) fails (R4). */
+static double step_search_from(orc_state *st, double start, int64_t *evals)
+{
+    double alpha = start;
     orc_eval e = evaluate(st, alpha);
     ++*evals;
-    if (!e.pass) return 0.5;
+    if (!e.pass) {
+        if (!(start > 1.0)) return 0.5;
+        double ub = start;
+        for (;;) {                                    /* downward (R19) */
+            double b = ub / 2.0;
+            if (b < 1.0) b = 1.0;
+            orc_eval eb = evaluate(st, b);
+            ++*evals;
+            if (eb.pass) {
+                if (eb.zmin_new >= 1.0) return b;
+                return bisect(st, b, ub, evals);
+            }
+            if (b <= 1.0) return 0.5;
+            ub = b;
+        }
+    }
     for (;;) {
         if (e.zmin_new >= 1.0) return alpha;          /* early return (R2) */
         if (alpha >= ORC_ALPHA_CAP) return alpha;
@@ -255,14 +295,15 @@ static double step_search(orc_state *st, int64_t *evals)
         alpha = next;
         e = en;
     }
-    double lb = alpha, ub = 2.0 * alpha;
-    while (ub - lb > st->eps * lb) {                  /* (R1) */
-        double beta = (lb + ub) / 2.0;
-        orc_eval eb = evaluate(st, beta);
-        ++*evals;
-        if (eb.pass) lb = beta; else ub = beta;
-    }
-    return lb;
+    return bisect(st, alpha, 2.0 * alpha, evals);
+}
+
+/* Algorithm 3: exponential search from alpha = 1, then binary search on
+ * [alpha/2, alpha] until (ub-lb) <= eps*lb; returns lb.  Returns a value < 1
+ * when T(1) fails (R4). */
+static double step_search(orc_state *st, int64_t *evals)
+{
+    return step_search_from(st, 1.0, evals);
 }
 
 static double col_max_P(const orc_state *st, double *colmax)
@@ -401,6 +442,8 @@ int orc_probe(const orc_mat *P, double sP, const orc_mat *C, double sC, double e
         double alpha;
         if (forced_alpha && t < n_forced) alpha = forced_alpha[t];
         else if (step_rule == ORC_STEP_STD) alpha = 1.0;
+        else if (step_rule == ORC_STEP_BIN_WARM && res->last_alpha > 1.0)
+            alpha = step_search_from(&st, res->last_alpha, &res->evaluations);   /* (R19) */
         else alpha = step_search(&st, &res->evaluations);
         if (alpha < 1.0) { res->status = ORC_INFEASIBLE; break; }
         if (alpha_trace && t < trace_cap) alpha_trace[t] = alpha;
@@ -777,12 +820,15 @@ done:
 
 /*
  * Algorithm 3 on given vectors (w = grad smax(y), u = grad smin(z), L_P =
- * smax(y), L_C = smin(z)), for testing the search on its own.  Returns the
- * accepted alpha (< 1 means T(1) failed) and the number of T evaluations.
+ * smax(y), L_C = smin(z)), for testing the search on its own, started at
+ * `start` (1: the algorithm as printed; above 1: the warm start of R19).
+ * Returns the accepted alpha (< 1 means T(1) failed) and the number of T
+ * evaluations.
  */
-double orc_step_search_terms(const double *y, const double *dy, const double *w, int64_t mP,
-                             double LP, const double *z, const double *dz, const double *u,
-                             int64_t mC, double LC, double eta, double eps, int64_t *evals)
+double orc_step_search_terms_from(const double *y, const double *dy, const double *w, int64_t mP,
+                                  double LP, const double *z, const double *dz, const double *u,
+                                  int64_t mC, double LC, double eta, double eps, double start,
+                                  int64_t *evals)
 {
     orc_state st;
     memset(&st, 0, sizeof st);
@@ -790,5 +836,13 @@ double orc_step_search_terms(const double *y, const double *dy, const double *w,
     st.z = (double *)z; st.dz = (double *)dz; st.u = (double *)u; st.mC = mC; st.LC = LC;
     st.eta = eta; st.eps = eps;
     *evals = 0;
-    return step_search(&st, evals);
+    return step_search_from(&st, start, evals);
+}
+
+/* The search from alpha = 1 (Algorithm 3 as printed). */
+double orc_step_search_terms(const double *y, const double *dy, const double *w, int64_t mP,
+                             double LP, const double *z, const double *dz, const double *u,
+                             int64_t mC, double LC, double eta, double eps, int64_t *evals)
+{
+    return orc_step_search_terms_from(y, dy, w, mP, LP, z, dz, u, mC, LC, eta, eps, 1.0, evals);
 }

@@ -817,6 +817,22 @@ MWU_DEV void setup_first(Ctl *c)
     c->gdelta = (ub - lb) / 16.0;
 }
 
+// First pass of a warm-started search (step rule MWU_STEP_BIN_WARM, from
+// the previous step la > 1): the ladder la/8 .. 16 la, which holds the
+// first halvings and doublings, and the bisection tree of [la, 2 la), the
+// bracket when the step stays in its octave.
+MWU_DEV void setup_first_warm(Ctl *c, double la)
+{
+    setup_exp(c, la / 8.0);
+    double v[KG];
+    grid_values(la, 2.0 * la, v);
+    for (int k = 0; k < KG; ++k) c->cand[KE + k] = v[k];
+    c->skind = SK_COMBO;
+    c->ncand = KC;
+    c->ga0 = v[0];
+    c->gdelta = la / 16.0;
+}
+
 MWU_DEV void setup_refine(Ctl *c, double a)
 {
     c->skind = SK_REFINE;
@@ -933,7 +949,14 @@ MWU_DEV void replay(Ctl *c)
             if (r == 2) { setup_refine(c, a); return; }
             c->evaluations += 1;
             if (!(e.phi >= e.psi)) {
-                if (!c->have_cur) { stop_infeasible(c); return; }   // T(1) fails: alpha < 1
+                if (!c->have_cur) {
+                    // T fails at the start: at 1 the probe ends (alpha < 1);
+                    // at a warm start above 1 the search halves downward
+                    if (!(a > 1.0)) { stop_infeasible(c); return; }
+                    c->ub = a;
+                    c->amode = AM_DOWN;
+                    continue;
+                }
                 c->lb = c->cur_alpha; c->ub = a;
                 c->lb_psi = c->cur_psi; c->lb_phi = c->cur_phi;
                 c->amode = AM_BIS;
@@ -943,6 +966,23 @@ MWU_DEV void replay(Ctl *c)
             c->cur_alpha = a; c->cur_psi = e.psi; c->cur_phi = e.phi;
             if (e.zmin >= 1.0 || a >= ALPHA_CAP) { accept_step(c, a, e.psi, e.phi); return; }
             c->exp_next = 2.0 * a;
+            continue;
+        }
+        if (c->amode == AM_DOWN) {   // halving from a failing warm start (never below 1)
+            const double b = fmax(c->ub / 2.0, 1.0);
+            Eval e;
+            int r = lookup(c, cr, b, &e);
+            if (r == 1) { setup_exp(c, b / (double)(1 << (KE - 1))); return; }   // the next KE halvings
+            if (r == 2) { setup_refine(c, b); return; }
+            c->evaluations += 1;
+            if (e.phi >= e.psi) {
+                if (e.zmin >= 1.0) { accept_step(c, b, e.psi, e.phi); return; }
+                c->lb = b; c->lb_psi = e.psi; c->lb_phi = e.phi;   // ub: the last failing value
+                c->amode = AM_BIS;
+                continue;
+            }
+            if (!(b > 1.0)) { stop_infeasible(c); return; }
+            c->ub = b;
             continue;
         }
         // AM_BIS
@@ -974,14 +1014,19 @@ MWU_DEV void begin_search(Ctl *c, const double *forced)
         c->phase = PH_SEARCH;
         return;
     }
-    if (c->step_rule == 0) {   // standard step alpha = 1; predicted LSE moves are safe bounds
+    if (c->step_rule == SR_STD) {   // standard step alpha = 1; predicted LSE moves are safe bounds
         accept_step(c, 1.0, c->onesP ? 0.0 : c->dymax, 0.0);
         return;
     }
     c->amode = AM_EXP;
-    c->exp_next = 1.0;
     c->have_cur = 0;
-    setup_first(c);
+    if (c->step_rule == SR_BIN_WARM && c->last_alpha > 1.0) {   // warm start at the previous step
+        c->exp_next = c->last_alpha;
+        setup_first_warm(c, c->last_alpha);
+    } else {
+        c->exp_next = 1.0;
+        setup_first(c);
+    }
     c->phase = PH_SEARCH;
 }
 

@@ -47,7 +47,9 @@ enum SKind : int32_t {
                      // octave the previous step fell in (KG): cand[KE + j] ~ ga0 + j * delta
 };
 
-enum AMode : int32_t { AM_EXP = 0, AM_BIS = 1, AM_FORCED = 2, AM_EVAL = 3 };
+enum AMode : int32_t { AM_EXP = 0, AM_BIS = 1, AM_FORCED = 2, AM_EVAL = 3, AM_DOWN = 4 };
+// Ctl::step_rule values (the MWU_STEP_* of the C interface)
+enum StepRule : int32_t { SR_STD = 0, SR_BIN = 1, SR_BIN_WARM = 2 };
 
 // A contiguous piece of a CSR-like structure handled by one workgroup:
 // segments [s0, s1) with nonzeros [k0, k1).  A segment longer than TILE_NZ is

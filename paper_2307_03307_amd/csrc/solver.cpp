@@ -222,6 +222,9 @@ static void setup_device(Solver &s)
     std::memset(s.ctl_host, 0, sizeof(Ctl));
 }
 
+static_assert(MWU_STEP_STD == SR_STD && MWU_STEP_BIN == SR_BIN && MWU_STEP_BIN_WARM == SR_BIN_WARM,
+              "device step rules follow the C interface");
+
 static void build(Solver &s, const mwu_problem &p)
 {
     s.form = p.form;
@@ -229,8 +232,9 @@ static void build(Solver &s, const mwu_problem &p)
           MWU_ERR_INVALID_ARG, "bad form");
     check(s.opt.eps > 0.0 && s.opt.eps < 1.0, MWU_ERR_INVALID_ARG, "eps must be in (0,1)");
     check(s.opt.max_iter >= 1 && s.opt.max_probes >= 1, MWU_ERR_INVALID_ARG, "bad iteration caps");
-    check(s.opt.step_rule == MWU_STEP_STD || s.opt.step_rule == MWU_STEP_BIN, MWU_ERR_INVALID_ARG,
-          "bad step rule");
+    check(s.opt.step_rule == MWU_STEP_STD || s.opt.step_rule == MWU_STEP_BIN ||
+              s.opt.step_rule == MWU_STEP_BIN_WARM,
+          MWU_ERR_INVALID_ARG, "bad step rule");
     check(s.opt.precision == MWU_FP64 || s.opt.precision == MWU_MIXED_FP32_FP64,
           MWU_ERR_INVALID_ARG, "bad precision");
     if (s.opt.iters_per_launch <= 0) s.opt.iters_per_launch = 8;
@@ -706,8 +710,9 @@ mwu_status mwu_create_batch(const mwu_problem *probs, int32_t count, const mwu_o
     mwu_status st = run_guarded([&] {
         check(s->opt.eps > 0.0 && s->opt.eps < 1.0, MWU_ERR_INVALID_ARG, "eps must be in (0,1)");
         check(s->opt.max_iter >= 1 && s->opt.max_probes >= 1, MWU_ERR_INVALID_ARG, "bad iteration caps");
-        check(s->opt.step_rule == MWU_STEP_STD || s->opt.step_rule == MWU_STEP_BIN, MWU_ERR_INVALID_ARG,
-              "bad step rule");
+        check(s->opt.step_rule == MWU_STEP_STD || s->opt.step_rule == MWU_STEP_BIN ||
+                  s->opt.step_rule == MWU_STEP_BIN_WARM,
+              MWU_ERR_INVALID_ARG, "bad step rule");
         check(s->opt.precision == MWU_FP64 || s->opt.precision == MWU_MIXED_FP32_FP64, MWU_ERR_INVALID_ARG,
               "bad precision");
         s->fp32 = s->opt.precision == MWU_MIXED_FP32_FP64;

@@ -145,6 +145,30 @@ def test_decision_replay_fp64(name):
     assert free.iterations == info.iterations and np.array_equal(free.alphas, alphas)
 
 
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "domset", "densest", "densest-generic"])
+def test_decision_replay_fp64_warm(name):
+    """Warm-started search (reading R19, MWU_STEP_BIN_WARM): in FP64 the GPU's
+    free run takes the warm-started oracle's decisions step for step, halvings
+    from a failing start included."""
+    case = CASES[name]()
+    sP, sC = case.sP(case.param), case.sC(case.param)
+    with case.make_gpu(precision=mwu.FP64, step_rule=mwu.STEP_BIN_WARM) as s:
+        s.probe_begin(case.param)
+        info = s.probe_run(5000)
+        alphas = s.probe_read("alpha", info.iterations)
+        xg = s.probe_read("x", s.sizes().n)
+    free = oracle.probe(case.P, sP, case.C, sC, EPS, step_rule=oracle.STEP_BIN_WARM)
+    down = int(np.sum(alphas[1:] < alphas[:-1]))   # searches that went below their start
+    bin3 = oracle.probe(case.P, sP, case.C, sC, EPS)
+    print(f"{name}: warm {info.iterations} iterations, {info.search_passes} passes, "
+          f"{free.evaluations} oracle evaluations ({down} downward); Algorithm 3 from 1: "
+          f"{bin3.iterations} iterations, {bin3.evaluations} evaluations")
+    assert info.status == free.status
+    assert info.iterations == free.iterations and np.array_equal(alphas, free.alphas)
+    assert abs(xg.sum() - free.x.sum()) <= FP64_TOL * free.x.sum()
+    assert rel_err(xg, free.x) <= 1e-6
+
+
 # FP32 storage of x and d rounds every step by ~6e-8; with eta ~ 900 and steps
 # up to 3e5 that is ~5e-5 in the exponents of the next weights.  Rows of one
 # weight each (densest: every g_i and h_i is a single weight) carry it
@@ -283,6 +307,35 @@ def test_solve_densest(precision, generic):
     assert (z[0::2] + z[1::2]).min() >= 1 - 1e-9
     load = np.bincount(g.u, weights=z[0::2], minlength=16) + np.bincount(g.v, weights=z[1::2], minlength=16)
     assert load.max() == pytest.approx(r.objective, rel=1e-9)
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+def test_solve_warm_start(precision):
+    """Whole solves with the warm-started search: the vertex cover and the
+    densest subgraph of the tests above, certified around the exact optima,
+    and in FP64 within the oracle's warm-started result."""
+    g = gg.rmat(13, 16, seed=2)
+    opt = _opt_vcover(g)
+    with mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision,
+                          step_rule=mwu.STEP_BIN_WARM) as s:
+        r = s.solve()
+    assert r.certified
+    assert r.lower <= opt * (1 + 1e-12) and opt <= r.upper * (1 + 1e-12)
+    assert r.objective / opt <= 1 + EPS
+    assert (r.x[g.u] + r.x[g.v]).min() >= 1 - 1e-9 and r.x.min() >= 0
+    if precision == mwu.FP64:
+        ro = oracle.solve_vcover(g, step_rule=oracle.STEP_BIN_WARM)
+        assert ro.certified and r.objective == pytest.approx(ro.objective, rel=EPS)
+    gd = gg.gnm_random(16, 34, seed=5)
+    best = 0.0
+    for mask in range(1, 1 << 16):
+        S = np.array([(mask >> i) & 1 for i in range(16)], bool)
+        best = max(best, np.sum(S[gd.u] & S[gd.v]) / S.sum())
+    with mwu.densest_subgraph(gd.num_vertices, gd.u, gd.v, precision=precision,
+                              step_rule=mwu.STEP_BIN_WARM) as s:
+        rd = s.solve()
+    assert rd.certified
+    assert rd.lower <= best * (1 + 1e-9) and best <= rd.upper * (1 + 1e-9)
 
 
 def test_solve_weighted_packing():

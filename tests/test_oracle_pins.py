@@ -159,6 +159,104 @@ def test_algorithm3_early_return(oracle_mod):
     assert a == 2.0 and ev == 2
 
 
+def _crossing(T, a, hi_factor=2.0, n=401):
+    """First grid point in [a, hi_factor a] where T fails (hi_factor a if none)."""
+    grid = a * np.linspace(1.0, hi_factor, n)
+    ok = np.array([T(b) for b in grid])
+    return grid[np.argmin(ok)] if not ok.all() else hi_factor * a
+
+
+def test_warm_search_brackets_from_any_start(oracle_mod):
+    """Warm start (reading R19): from any start above 1, upward or downward,
+    the search still returns lb with T(lb) true and the largest admissible
+    step within [lb, (1+eps) lb]; a failing T(1) still gives alpha < 1."""
+    rng = np.random.default_rng(12)
+    eta = 300.0
+    down = up = 0
+    for trial in range(10):
+        y = rng.uniform(0, 0.5, 20)
+        dy = rng.uniform(0, 1e-3, 20)
+        z = rng.uniform(0, 0.3, 25)
+        dz = rng.uniform(1e-4, 2e-3, 25) * rng.uniform(0.5, 4)
+        LP, w, LC, u, T = _scan(oracle_mod, y, dy, z, dz, eta)
+        a3, _ = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS)
+        for s in (1.5, 3.0 * max(a3, 1.0), 37.0 * max(a3, 1.0), 0.4 * max(a3, 1.0)):
+            if s <= 1.0:
+                continue
+            a, ev = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, start=s)
+            if not T(1.0):
+                assert a < 1.0
+                continue
+            assert a >= 1.0 and T(a)
+            if T(s):
+                up += 1
+            else:
+                down += 1
+                assert a < s
+            if np.min(z + a * dz) >= 1.0:
+                continue  # early return
+            cross = _crossing(T, a)
+            assert a <= cross <= a * (1 + EPS) * (1 + 1e-9)
+    assert down > 3 and up > 3
+
+
+def test_warm_search_from_one_is_algorithm3(oracle_mod):
+    """Start 1 is Algorithm 3 as printed: same step, same evaluation count."""
+    rng = np.random.default_rng(13)
+    eta = 200.0
+    for trial in range(5):
+        y = rng.uniform(0, 0.5, 10)
+        dy = rng.uniform(0, 1e-3, 10)
+        z = rng.uniform(0, 0.3, 12)
+        dz = rng.uniform(1e-4, 2e-3, 12)
+        LP, w, LC, u, _ = _scan(oracle_mod, y, dy, z, dz, eta)
+        assert (oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, start=1.0)
+                == oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS))
+
+
+def test_warm_search_counts(oracle_mod):
+    """Evaluation counts of the warm start: from s with T(s) true and T(2s)
+    false, one doubling then at most 4 bisection steps (width s/16 <= eps s);
+    from 2^k s it halves k times first; an early return on the way down
+    stops at once."""
+    rng = np.random.default_rng(14)
+    eta = 300.0
+    y = rng.uniform(0, 0.5, 20)
+    dy = rng.uniform(0, 1e-3, 20)
+    z = rng.uniform(0, 0.3, 25)
+    dz = rng.uniform(1e-4, 2e-3, 25)
+    LP, w, LC, u, T = _scan(oracle_mod, y, dy, z, dz, eta)
+    a3, ev3 = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS)
+    assert a3 > 8.0 and np.min(z + a3 * dz) < 1.0      # a case with a long doubling phase
+    cross = _crossing(T, a3)
+    s = cross / 1.5                                     # T(s) holds, T(2 s) fails
+    assert T(s) and not T(2 * s)
+    a, ev = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, start=s)
+    assert 5 <= ev <= 6 and ev < ev3
+    assert a <= cross <= a * (1 + EPS) * (1 + 1e-9)
+    a8, ev8 = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, start=8 * s)
+    assert ev8 == ev + 3 - 1      # 8s, 4s, 2s fail, s holds (s itself not doubled again)
+    # downward early return: T fails at s0, holds at s0 / 2^k, which covers
+    # every row (Psi overtakes the linear Phi = 0.06 alpha near alpha = 5)
+    y2 = np.array([0.1, 0.2])
+    dy2 = np.array([0.08, 0.01])
+    z2 = np.array([0.9, 0.95])
+    dz2 = np.array([0.06, 0.06])
+    eta2 = 50.0
+    LP2, w2 = oracle_mod.smax(y2, eta2)
+    LC2, u2 = oracle_mod.smin(z2, eta2)
+    T2 = lambda b: (oracle_mod.phi(z2, dz2, u2, eta2, LC2, b)[0]
+                    >= oracle_mod.psi(y2, dy2, w2, eta2, LP2, b))
+    assert T2(2.0) and not T2(64.0)
+    s0 = 2.0
+    while T2(s0) and s0 < 64.0:
+        s0 *= 2.0
+    a2, ev2 = oracle_mod.step_search(y2, dy2, w2, LP2, z2, dz2, u2, LC2, eta2, EPS, start=s0)
+    assert T2(a2) and np.min(z2 + a2 * dz2) >= 1.0
+    k = int(round(np.log2(s0 / a2)))
+    assert k >= 1 and a2 == s0 / 2 ** k and ev2 == k + 1
+
+
 # --------------------------------------------------------- whole iterations
 
 def _bmatch_problem(g):
