@@ -183,6 +183,17 @@ def _from_pairs(n: int, pairs) -> Graph:
     return Graph(n, u, v)
 
 
+def hub_graph(hubs: int, hub_degree: int, leaves: int, seed: int) -> Graph:
+    """Vertices [0, hubs) each joined to hub_degree distinct uniform leaves
+    among [hubs, hubs + leaves): many rows longer than one tile at once."""
+    rng = _rng(seed)
+    u = np.repeat(np.arange(hubs, dtype=np.int64), hub_degree)
+    v = np.concatenate([hubs + rng.choice(leaves, hub_degree, replace=False) for _ in range(hubs)])
+    n = hubs + leaves
+    cu, cv = canonical_edges(u, v, n)
+    return Graph(n, cu, cv)
+
+
 def complete_graph(n: int) -> Graph:
     return _from_pairs(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
 

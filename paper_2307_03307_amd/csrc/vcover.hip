@@ -341,7 +341,14 @@ __global__ __launch_bounds__(BLOCK) void vc_passB_k(VcDev<T> vd, Ctl *ctl, doubl
     double v[3] = {0.0, -INFINITY, -INFINITY};   // sum d | max d | max h
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < vd.nv; i += gridDim.x * BLOCK) {
         XD<T> p = vd.xd[i];
-        const double h = (double)vd.h[i] * invSu;
+        T hr;
+        if (i < vd.nlong_b) {   // a long row (vertex i is long row i): its chunk partials, in order
+            hr = long_sum<T>(i, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
+            vd.h[i] = hr;
+        } else {
+            hr = vd.h[i];
+        }
+        const double h = (double)hr * invSu;
         double di = 0.0;
         if (h > 0.0) {
             const double q = 1.0 - g / h;
@@ -841,7 +848,7 @@ void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
     VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials);
     // up to 2 BLOCK long rows are completed by the finisher itself
     const int with_long = v.flong.nlong <= 2 * BLOCK;
-    if (!with_long) VLAUNCH(vc_long_k<T>, (v.flong.nlong + BLOCK - 1) / BLOCK, v, ctl);
+    if (!with_long && v.nlong_b == 0) VLAUNCH(vc_long_k<T>, (v.flong.nlong + BLOCK - 1) / BLOCK, v, ctl);
     VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile, with_long);
 }
 

@@ -44,6 +44,9 @@ def _cases():
         "vcover": lambda: vcover_case(gnm),
         "vcover-generic": lambda: vcover_case(gnm, generic=True),
         "vcover-star": lambda: vcover_case(star, param=2.0),       # a row of 5000 > one tile
+        # 600 rows of 2100 > one tile: more long rows than the pass A finisher
+        # takes, completed by the direction pass
+        "vcover-hubs": lambda: vcover_case(gg.hub_graph(600, 2100, 20000, seed=26), param=400.0),
         "domset": lambda: domset_case(pl),
         "domset-star": lambda: domset_case(gg.star_graph(6000), param=3.0),
         "densest": lambda: densest_case(gg.gnm_random(400, 3000, seed=24)),
@@ -102,8 +105,8 @@ def test_per_pass_fp64(name):
     _per_pass(CASES[name](), mwu.FP64, FP64_TOL)
 
 
-@pytest.mark.parametrize("name", ["bmatch", "vcover", "vcover-star", "domset", "weighted", "densest",
-                                  "densest-powerlaw"])
+@pytest.mark.parametrize("name", ["bmatch", "vcover", "vcover-star", "vcover-hubs", "domset", "weighted",
+                                  "densest", "densest-powerlaw"])
 def test_per_pass_mixed(name):
     """The fused densest program forms g_i / h_i in the log domain, so its FP32
     direction matches even where both FP32 weights underflow."""
