@@ -134,7 +134,8 @@ typedef struct {
     int32_t max_probes;         /* outer search cap, default 64 */
     int32_t step_rule;          /* MWU_STEP_BIN (default), MWU_STEP_BIN_WARM or MWU_STEP_STD */
     int32_t precision;          /* MWU_MIXED_FP32_FP64 (default) or MWU_FP64 */
-    int32_t iters_per_launch;   /* iterations captured per graph launch; 0 = default (8) */
+    int32_t iters_per_launch;   /* iterations captured per graph launch; 0 = default (16 for one
+                                   instance, 8 for a batch) */
     int32_t device;             /* HIP device ordinal, default 0 */
     void *hip_stream;           /* hipStream_t to run on; NULL = a stream owned by the handle */
     double mixed_fixed_lambda;  /* MWU_MIXED: > 0 runs one feasibility probe at this lambda */
