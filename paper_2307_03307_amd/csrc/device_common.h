@@ -126,7 +126,7 @@ MWU_DEV void block_combine(const double (&v)[Q], Red r, int qoff, double *s_wave
 // gfx950 does both, and throws away the cached vertex vectors).
 MWU_DEV void store_record(const double *s_rec, int Q, double *partials)
 {
-    if (threadIdx.x < Q) partials[(size_t)blockIdx.x * QMAX + threadIdx.x] = s_rec[threadIdx.x];
+    if ((int)threadIdx.x < Q) partials[(size_t)blockIdx.x * QMAX + threadIdx.x] = s_rec[threadIdx.x];
 }
 
 // Records stored entry-major (entry q of workgroup b at q * G + b, G the
@@ -134,7 +134,7 @@ MWU_DEV void store_record(const double *s_rec, int Q, double *partials)
 // coalesced loads, which matters for records of dozens of entries.
 MWU_DEV void store_record_qmajor(const double *s_rec, int Q, double *partials)
 {
-    if (threadIdx.x < Q) partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_rec[threadIdx.x];
+    if ((int)threadIdx.x < Q) partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_rec[threadIdx.x];
 }
 
 template <int Q>

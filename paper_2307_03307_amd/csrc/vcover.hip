@@ -28,16 +28,18 @@ namespace mwu {
 // consecutive nonzeros, accumulating term(segment value, staged value), and
 // epi(seg, sum) is called once per segment.  Segments crossing thread
 // boundaries are completed through seg_carry.
+static_assert(TILE_NZ <= 32767, "tile row starts are staged in 16 bits");
+
 template <class S, class Acc, class StageF, class SegF, class TermF, class EpiF>
 MWU_DEV void seg_tile_rows(const Tile &tl, const int32_t *__restrict__ ptr, StageF &stage, SegF &segval,
-                           TermF &term, EpiF &epi, S *s_val, S *s_seg, int32_t *s_ptr)
+                           TermF &term, EpiF &epi, S *s_val, S *s_seg, int16_t *s_ptr)
 {
     const int tid = threadIdx.x;
     const int S_ = tl.s1 - tl.s0;
     const int base = tl.k0;
     const int N = tl.k1 - tl.k0;
-    for (int i = tid; i < S_; i += BLOCK) s_ptr[i] = ptr[tl.s0 + i] - base;
-    if (tid == 0) s_ptr[S_] = N;   // = ptr[s1] - base in a full layout; packed tiles end early
+    for (int i = tid; i < S_; i += BLOCK) s_ptr[i] = (int16_t)(ptr[tl.s0 + i] - base);
+    if (tid == 0) s_ptr[S_] = (int16_t)N;   // = ptr[s1] - base in a full layout; packed tiles end early
     for (int i = tid; i < S_; i += BLOCK) s_seg[i] = segval(tl.s0 + i);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -256,7 +258,9 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
 {
     __shared__ T s_val[TILE_LDS];
     __shared__ T s_seg[TILE_NZ];
-    __shared__ int32_t s_ptr[TILE_NZ + 1];
+    // row starts within the tile (at most TILE_NZ) in 16 bits: with them the
+    // pass fits 7 workgroups per CU instead of 6
+    __shared__ int16_t s_ptr[TILE_NZ + 1];
     __shared__ T s_tacc[BLOCK / 64];
     __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
