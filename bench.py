@@ -295,7 +295,7 @@ def main():
                     help="also run a plain copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
 
