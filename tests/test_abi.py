@@ -51,6 +51,8 @@ def test_invalid_graphs_rejected():
     assert _code(lambda: mwu.vertex_cover(0, [], [])) == -1             # empty graph
     assert _code(lambda: mwu.bmatch(3, u, v, eps=0.0)) == -1            # eps outside (0,1)
     assert _code(lambda: mwu.bmatch(3, u, v, eps=1.5)) == -1
+    assert _code(lambda: mwu.bmatch(3, u, v, step_rule=3)) == -1        # unknown step rule
+    assert _code(lambda: mwu.bmatch(3, u, v, step_rule=-1)) == -1
 
 
 def test_invalid_csr_rejected():
@@ -89,6 +91,9 @@ def test_valid_problem_without_gpu_fails_loudly():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _code(lambda: mwu.bmatch(4, [0, 1], [2, 3])) == -8
+    # every step rule passes validation and reaches the device
+    for rule in (mwu.STEP_STD, mwu.STEP_BIN, mwu.STEP_BIN_WARM):
+        assert _code(lambda: mwu.bmatch(4, [0, 1], [2, 3], step_rule=rule)) == -8
 
 
 def test_create_batch_rejects_unsupported_problems():
