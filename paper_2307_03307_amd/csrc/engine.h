@@ -178,10 +178,9 @@ struct VcDev {
     int32_t *fcol_pk, *fptr_pk, *tile_na, *ccol, *cst, *goff, *tile_rows, *thead, *thpos;
     Tile *items;
     int32_t *aeu, *aew, *acnt;
-    // long rows that pass B completes itself (the chunk partials of pass A
-    // in chunk order): the vertices [0, nlong_b), when the long rows are
-    // exactly that prefix of the degree-ordered vertices; 0 when vc_long_k
-    // or the pass A finisher completes them
+    // long rows completed by pass B from the chunk partials of pass A (in
+    // chunk order): the vertices [0, nlong_b) of the degree order when there
+    // are more than the pass A finisher takes, else 0
     int32_t nlong_b;
 };
 

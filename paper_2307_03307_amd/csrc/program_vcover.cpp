@@ -137,11 +137,13 @@ class VcoverProgram : public Program {
         vd_.tile_rows = tile_rows_.as<int32_t>(); vd_.items = items_.as<Tile>();
         vd_.thead = thead_.as<int32_t>(); vd_.thpos = thpos_.as<int32_t>();
         vd_.aeu = aeu_.as<int32_t>(); vd_.aew = aew_.as<int32_t>();
-        {   // degree order puts the long rows first: pass B can complete them
-            bool prefix = true;
-            for (size_t l = 0; l < ft.lseg.size(); ++l) prefix = prefix && ft.lseg[l] == (int32_t)l;
-            vd_.nlong_b = prefix && (int64_t)ft.lseg.size() > 2 * BLOCK ? (int32_t)ft.lseg.size() : 0;
-        }
+        // Rows longer than a tile are chunked and the vertices are in degree
+        // order, so the long rows are the vertices [0, nlong).  Up to 2 BLOCK
+        // of them the pass A finisher completes; more, pass B does (vertex i
+        // is long row i).
+        for (size_t l = 0; l < ft.lseg.size(); ++l)
+            if (ft.lseg[l] != (int32_t)l) throw ApiError{MWU_ERR_DEVICE, "long rows are not the leading vertices"};
+        vd_.nlong_b = (int64_t)ft.lseg.size() > 2 * BLOCK ? (int32_t)ft.lseg.size() : 0;
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
             int64_t g = (items + per - 1) / per;
             return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));

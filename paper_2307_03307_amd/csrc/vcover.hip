@@ -303,18 +303,8 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     store_record(s_rec, 2, part);
 }
 
-// h of the vertices whose rows were split into chunks: the chunk partials in
-// chunk order (one thread per long row, many workgroups).
-template <class T>
-__global__ __launch_bounds__(BLOCK) void vc_long_k(VcDev<T> vd, const Ctl *ctl)
-{
-    if (ctl->phase != PH_ROW) return;
-    const int l = blockIdx.x * BLOCK + threadIdx.x;
-    if (l < vd.flong.nlong) vd.h[vd.flong.lseg[l]] = long_sum<T>(l, vd.flpart, vd.flong.lfirst, vd.flong.lcount);
-}
-
-// with_long: the finisher also completes the long rows (when they are few,
-// instead of a launch of vc_long_k).
+// with_long: the finisher also completes the long rows (when they are few;
+// more of them pass B completes).
 template <class T>
 __global__ __launch_bounds__(BLOCK) void vc_passA_fin(VcDev<T> vd, Ctl *ctl, const double *part, int G,
                                                       int with_long)
@@ -852,7 +842,6 @@ void vc_passA(const VcDev<T> &v, Ctl *ctl, const VcLaunch &L, hipStream_t st)
     VLAUNCH(vc_passA_k<T>, L.grid_ftile, v, ctl, L.partials);
     // up to 2 BLOCK long rows are completed by the finisher itself
     const int with_long = v.flong.nlong <= 2 * BLOCK;
-    if (!with_long && v.nlong_b == 0) VLAUNCH(vc_long_k<T>, (v.flong.nlong + BLOCK - 1) / BLOCK, v, ctl);
     VLAUNCH(vc_passA_fin<T>, 1, v, ctl, (const double *)L.partials, L.grid_ftile, with_long);
 }
 
