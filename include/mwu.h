@@ -260,11 +260,15 @@ mwu_status mwu_probe_begin(void *s, double param, const double *x0);
 
 /* Run up to max_iters iterations of Algorithm 2 (stops early on any outcome).
  * forced_alpha (host, nullable, n_forced entries): use these steps instead
- * of the search for the next n_forced iterations (decision replay). */
+ * of the search for the next n_forced iterations (decision replay).  While
+ * the probe is still running on return, its last accepted step is applied
+ * by the next iteration's row pass: x, y and z read then are the iterate
+ * before that step (mwu_probe_direction applies it first). */
 mwu_status mwu_probe_run(void *s, int32_t max_iters, const double *forced_alpha, int32_t n_forced,
                          mwu_probe_info *info);
 
-/* Compute g, h, d, P d, C d at the current x without stepping. */
+/* Compute g, h, d, P d, C d at the current x (after applying a pending
+ * accepted step, see mwu_probe_run) without taking a new step. */
 mwu_status mwu_probe_direction(void *s);
 
 /* Copy an internal vector to the host (double).  which: 0 x, 1 d, 2 g, 3 h,

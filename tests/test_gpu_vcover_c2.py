@@ -1,0 +1,81 @@
+"""Vertex cover LP at full C2 size (R-MAT scale 20, edge factor 16,
+a/b/c = 0.57/0.19/0.19, seed 2, eps = 0.1) in the launch configuration that
+bench.py times (library defaults):
+
+- the solve in both forms is certified, its point covers every edge, and the
+  exact LP optimum (half a maximum matching of the bipartite double cover,
+  Hopcroft-Karp) lies in the certified bracket, within (1 + eps) of the
+  objective;
+- 600 iterations into a probe at the middle of the final bracket (the state
+  bench.py times its passes in, with the active lists of the chosen form in
+  use), the transpose pass, the direction and the step sums of the
+  exponential grid match the FP64 oracle at the GPU's own iterate, element
+  by element over all 646k vertices and 15.7M edges."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import maximum_bipartite_matching
+
+import graphgen as gg
+import oracle
+from gpu_common import EPS, rel_err, vcover_case
+
+pytestmark = pytest.mark.gpu
+
+EXP_ALPHAS = [float(2 ** k) for k in range(8)]
+# per-element tolerance of the per-pass quantities (as for the small cases:
+# FP32 storage in the chosen form, reduction order in FP64)
+TOL = {0: 1e-9, 1: 5e-3}
+
+
+@pytest.fixture(scope="module")
+def c2():
+    g = gg.cached("rmat20_ef16_s2", lambda: gg.rmat(20, 16, seed=2))
+    n = g.num_vertices
+    r = np.concatenate([g.u, g.v])
+    c = np.concatenate([g.v, g.u])
+    B = sp.csr_matrix((np.ones(r.shape[0], np.int8), (r, c)), shape=(n, n))
+    opt = int((maximum_bipartite_matching(B, perm_type="column") >= 0).sum()) / 2.0
+    return g, opt
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c2_solve_brackets_exact_optimum(c2, precision):
+    import paper_2307_03307_amd as mwu
+    g, opt = c2
+    with mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision) as s:
+        r = s.solve()
+    print(f"C2 precision {precision}: objective {r.objective:.2f} bracket [{r.lower:.2f}, {r.upper:.2f}] "
+          f"exact LP optimum {opt:.1f} iterations {r.total_iterations}")
+    assert r.certified
+    assert r.lower <= opt * (1 + 1e-12) and opt <= r.upper * (1 + 1e-12)
+    assert r.objective / opt <= 1 + EPS
+    assert (r.x[g.u] + r.x[g.v]).min() >= 1 - 1e-9 and r.x.min() >= 0
+    assert r.x.sum() == pytest.approx(r.objective, rel=1e-9)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c2_passes_mid_probe(c2, precision):
+    import paper_2307_03307_amd as mwu
+    g, opt = c2
+    case = vcover_case(g, param=1.005 * opt)   # between the bounds, as bench.py's probe
+    sP, sC = case.sP(case.param), case.sC(case.param)
+    with case.make_gpu(precision=precision) as s:
+        n = s.sizes().n
+        s.probe_begin(case.param)
+        info = s.probe_run(600)
+        assert info.status == 0 and info.iterations >= 600   # still running
+        s.probe_direction()            # applies the last accepted step first
+        x = s.probe_read("x", n)
+        got = {k: s.probe_read(k, n) for k in ("g", "h", "d")}
+        psi, phi, zm = s.probe_eval_steps(EXP_ALPHAS)
+    ref = oracle.iteration_terms(case.P, sP, case.C, sC, EPS, x, alphas=EXP_ALPHAS)
+    errs = {k: rel_err(got[k], ref[k]) for k in ("g", "h", "d")}
+    scale = np.maximum(np.abs(ref["psi"]), np.abs(ref["phi"]))
+    errs["psi"] = float(np.max(np.abs(psi - ref["psi"]) / scale))
+    errs["phi"] = float(np.max(np.abs(phi - ref["phi"]) / scale))
+    errs["zmin"] = rel_err(zm, ref["zmin_new"])
+    print(f"C2 precision {precision}, 600 iterations in: " +
+          ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= TOL[precision]}
+    assert not bad, bad
