@@ -90,6 +90,21 @@ def test_batch_solve_twice_is_identical():
         assert np.array_equal(a.x, c.x)
 
 
+def test_batch_full_c5():
+    """The full C5 batch (512 instances, sides uniform in [1024, 65536], mean
+    degree uniform in [4, 16], 164M edges) in the chosen form with the layout
+    the autotuner picks, as bench.py runs it: every instance certified, and
+    for every 16th instance the exact optimum in the bracket with a feasible
+    x (per-vertex loads at most 1)."""
+    import paper_2307_03307_amd as mwu
+    gs = gg.batch_bipartite(512)
+    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs]) as b:
+        res = b.solve()
+    assert sum(r.certified for r in res) == len(gs)
+    for k in range(0, len(gs), 16):
+        _check(gs[k], res[k], _nu(gs[k]))
+
+
 # ------------------------------------------------------------------ autotuner
 
 TILE_E = {1024, 2048, 4096, 8192}

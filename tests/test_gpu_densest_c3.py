@@ -1,0 +1,70 @@
+"""Densest subgraph LP at full C3 size (R-MAT scale 22, edge factor 16,
+a/b/c = 0.57/0.19/0.19, seed 3: 64.2M edges, 128.3M variables, eps = 0.1),
+fused program, in the launch configuration that bench.py times.  No exact
+optimum is available at this size:
+- the solve in each form is certified (level-set lower bound, rescaled
+  feasible upper bound within 1 + eps), its point covers every edge row, its
+  largest vertex load is the objective, and the two forms' brackets overlap;
+- 200 iterations into a probe inside the bracket, the transpose products,
+  the direction and the step sums of the exponential grid match the FP64
+  oracle at the GPU's own iterate over all variables and rows."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_common import EPS, densest_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+EXP_ALPHAS = [float(2 ** k) for k in range(8)]
+TOL = {0: 1e-9, 1: 5e-3}   # as for the small densest cases (FP32 storage in the chosen form)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return gg.cached("rmat22_ef16_s3", lambda: gg.rmat(22, 16, seed=3))
+
+
+def test_c3_solves_certified(c3):
+    import paper_2307_03307_amd as mwu
+    g = c3
+    res = {}
+    for precision in (1, 0):
+        with mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision) as s:
+            r = s.solve()
+        print(f"C3 precision {precision}: objective {r.objective:.4f} bracket [{r.lower:.4f}, {r.upper:.4f}] "
+              f"iterations {r.total_iterations}")
+        assert r.certified and r.upper <= (1 + EPS) * r.lower
+        z = r.x
+        assert (z[0::2] + z[1::2]).min() >= 1 - 1e-9 and z.min() >= 0
+        load = np.bincount(g.u, weights=z[0::2], minlength=g.num_vertices) + \
+            np.bincount(g.v, weights=z[1::2], minlength=g.num_vertices)
+        assert load.max() == pytest.approx(r.objective, rel=1e-9)
+        res[precision] = r
+    assert max(res[0].lower, res[1].lower) <= min(res[0].upper, res[1].upper)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c3_passes_mid_probe(c3, precision):
+    case = densest_case(c3, param=695.0)
+    sP, sC = case.sP(case.param), case.sC(case.param)
+    with case.make_gpu(precision=precision) as s:
+        n = s.sizes().n
+        s.probe_begin(case.param)
+        info = s.probe_run(200)
+        assert info.status == 0 and info.iterations >= 200   # still running
+        s.probe_direction()            # applies the last accepted step first
+        x = s.probe_read("x", n)
+        got = {k: s.probe_read(k, n) for k in ("g", "h", "d")}
+        psi, phi, zm = s.probe_eval_steps(EXP_ALPHAS)
+    ref = oracle.iteration_terms(case.P, sP, case.C, sC, EPS, x, alphas=EXP_ALPHAS)
+    errs = {k: rel_err(got[k], ref[k]) for k in ("g", "h", "d")}
+    scale = np.maximum(np.abs(ref["psi"]), np.abs(ref["phi"]))
+    errs["psi"] = float(np.max(np.abs(psi - ref["psi"]) / scale))
+    errs["phi"] = float(np.max(np.abs(phi - ref["phi"]) / scale))
+    errs["zmin"] = rel_err(zm, ref["zmin_new"])
+    print(f"C3 precision {precision}, {info.iterations} iterations in: " +
+          ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= TOL[precision]}
+    assert not bad, bad
