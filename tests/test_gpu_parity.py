@@ -373,11 +373,12 @@ def test_tiny_and_degenerate():
     assert r.status == mwu.CERTIFIED and r.objective <= 4.0 * (1 + EPS)
 
 
-def test_deterministic_rerun():
+@pytest.mark.parametrize("step_rule", [mwu.STEP_BIN, mwu.STEP_BIN_WARM])
+def test_deterministic_rerun(step_rule):
     g = gg.rmat(12, 8, seed=6)
     out = []
     for _ in range(2):
-        with mwu.vertex_cover(g.num_vertices, g.u, g.v) as s:
+        with mwu.vertex_cover(g.num_vertices, g.u, g.v, step_rule=step_rule) as s:
             out.append(s.solve())
     assert out[0].objective == out[1].objective
     assert np.array_equal(out[0].x, out[1].x)
