@@ -100,6 +100,29 @@ def bipartite_uniform(n_left: int, n_right: int, num_edges: int, seed: int) -> G
     return Graph(n_left + n_right, u, v, n_left=n_left)
 
 
+def user_item(users: int, items: int, deg_lo: int, deg_hi: int, zipf: float, seed: int) -> Graph:
+    """A user-item rating graph (bipartite, users [0, users), items after):
+    every user rates distinct items, as many as a uniform draw from
+    [deg_lo, deg_hi] (fewer only if its draws hold fewer distinct items),
+    with item popularity proportional to (rank + 1)^-zipf (a long tail, as in
+    rating data).  Each user draws 3 deg_hi items with replacement, the
+    distinct ones are put in a random order and the first ones kept."""
+    rng = _rng(seed)
+    w = (np.arange(items, dtype=np.float64) + 1.0) ** -zipf
+    cdf = np.cumsum(w / w.sum())
+    cdf[-1] = 1.0
+    deg = rng.integers(deg_lo, deg_hi + 1, size=users)
+    draws = np.searchsorted(cdf, rng.random((users, 3 * deg_hi)), side="right").astype(np.int64)
+    pairs = np.unique(np.arange(users, dtype=np.int64)[:, None] * items + draws)
+    pu, pi = pairs // items, pairs % items
+    order = np.lexsort((rng.random(pairs.shape[0]), pu))
+    pu, pi = pu[order], pi[order]
+    first = np.searchsorted(pu, np.arange(users))
+    keep = np.arange(pu.shape[0]) - first[pu] < deg[pu]
+    cu, cv = canonical_edges(pu[keep], users + pi[keep], users + items)
+    return Graph(users + items, cu, cv, n_left=users)
+
+
 def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
          c: float = 0.19, relabel: bool = True) -> Graph:
     """Graph500-style R-MAT: ``edge_factor * 2**scale`` sampled pairs.
