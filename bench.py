@@ -301,11 +301,11 @@ def run_genmatch(args):
                         (np.concatenate([g.u, g.v]), np.concatenate([e, e]))), shape=(V, E))
     Cs = sp.csr_matrix((np.full(E, 1.0 / lb_user), (g.u, e)), shape=(users, E))
 
-    def make(precision):
+    def make(precision, iters_per_launch=0):
         return mwu.Solver(mwu.MIXED, P=mwu.incidence(V, g.u, g.v),
                           C=mwu.csr_matrix(ptr, e.astype(np.int32), shape=(users, E)),
                           b_P=ub, b_C=lb, fixed_lambda=1.0, precision=precision,
-                          step_rule=step_rule_of(mwu, args))
+                          step_rule=step_rule_of(mwu, args), iters_per_launch=iters_per_launch)
 
     def run(precision, steps, warmup):
         walls, r = [], None
@@ -323,12 +323,12 @@ def run_genmatch(args):
 
     w32, r32 = run(mwu.MIXED_FP32_FP64, args.steps, args.warmup)
     w64, r64 = run(mwu.FP64, 1, 0)
-    curve = []
-    with make(mwu.MIXED_FP32_FP64) as s:
+    curve = []   # (iterations, max violation), in steps of 2 iterations (a graph launch of 2)
+    with make(mwu.MIXED_FP32_FP64, iters_per_launch=2) as s:
         n = s.sizes().n
         s.probe_begin(1.0)
         while True:
-            info = s.probe_run(16)
+            info = s.probe_run(2)
             x = s.probe_read("x", n)
             viol = max(0.0, (Ps @ x).max() - 1.0, 1.0 - (Cs @ x).min())
             curve.append([int(info.iterations), float(viol)])
