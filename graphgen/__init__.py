@@ -179,10 +179,11 @@ def batch_bipartite(count: int, base_seed: int = 5_000_000, side_lo: int = 1024,
                     scale_div: int = 1) -> List[Graph]:
     """Independent uniform bipartite instances of uneven size.
 
-    Instance k uses seed ``base_seed + k``: both side sizes uniform in
-    [side_lo, side_hi], mean left degree uniform in [deg_lo, deg_hi], and
-    ``round(n_left * degree)`` distinct uniform pairs.  ``scale_div`` divides
-    the side range (for small test batches).
+    Instance k draws its shape with seed ``base_seed + k``: both side sizes
+    uniform in [side_lo, side_hi] and the mean left degree uniform in
+    [deg_lo, deg_hi]; its ``round(n_left * degree)`` distinct uniform pairs
+    come from seed ``base_seed + k + 7919 count``.  ``scale_div`` divides the
+    side range (for small test batches).
     """
     out = []
     for k in range(count):
