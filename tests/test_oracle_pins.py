@@ -520,6 +520,54 @@ def test_infeasible_probe_reports_infeasible(oracle_mod):
     assert z >= 1.0 and Px.max() / z <= 1 + EPS + 1e-12
 
 
+def test_genmatch_probe_agrees_with_highs(oracle_mod):
+    """Generalized matching (appendix): l <= M x <= u with users matched 3 to 5
+    times and items at most `cap` times, as a fixed-lambda probe over P = M
+    scaled by 1/u and C = the user rows scaled by 1/l.  HiGHS gives the
+    smallest feasible cap (here set by a bottleneck of popular items, well
+    above the average load) and decides each cap independently.  The theorem
+    of Section 4.1 binds the verdicts: FEASIBLE only where the (1 + eps)-relaxed
+    LP is feasible, with Px <= 1 + eps and Cx >= 1; INFEASIBLE only where the
+    exact LP is infeasible.  With 5% slack on either side the verdict must be
+    reached."""
+    g = gg.user_item(60, 40, 3, 5, 1.5, seed=3)
+    U, V, E = g.n_left, g.num_vertices, g.num_edges
+    e = np.arange(E)
+    M = np.zeros((V, E))
+    M[g.u, e] = 1.0
+    M[g.v, e] = 1.0
+    Mu, Mi = M[:U], M[U:]
+    lo, hi = 3.0, 5.0
+
+    def lp_feasible(user_hi, cap):
+        A = np.vstack([Mi, Mu, -Mu])
+        b = np.concatenate([np.full(V - U, cap), np.full(U, user_hi), np.full(U, -lo)])
+        st = linprog(np.zeros(E), A_ub=A, b_ub=b, bounds=(0, None)).status
+        assert st in (0, 2)
+        return st == 0
+
+    # smallest cap: min t s.t. Mi x <= t, lo <= Mu x <= hi, x >= 0
+    A = np.block([[Mi, -np.ones((V - U, 1))], [Mu, np.zeros((U, 1))], [-Mu, np.zeros((U, 1))]])
+    b = np.concatenate([np.zeros(V - U), np.full(U, hi), np.full(U, -lo)])
+    cap_star = linprog(np.r_[np.zeros(E), 1.0], A_ub=A, b_ub=b, bounds=(0, None)).fun
+    assert cap_star > 1.5 * lo * U / (V - U)
+    decided = {1.05 * cap_star: oracle_mod.FEASIBLE, 0.98 * cap_star / (1 + EPS): oracle_mod.INFEASIBLE}
+    for cap in sorted(set(decided) | {0.7 * cap_star, 0.9 * cap_star, 1.2 * cap_star, 2.0 * cap_star}):
+        ub = np.where(np.arange(V) < U, hi, cap)
+        P = oracle_mod.CSR.from_coo(V, E, np.r_[g.u, g.v], np.r_[e, e], np.r_[1.0 / ub[g.u], 1.0 / ub[g.v]])
+        C = oracle_mod.CSR.from_coo(U, E, g.u, e, np.full(E, 1.0 / lo))
+        r = oracle_mod.probe(P, 1.0, C, 1.0, EPS)
+        if cap in decided:
+            assert r.status == decided[cap], (cap / cap_star, r.status)
+        if r.status == oracle_mod.FEASIBLE:
+            assert lp_feasible((1 + EPS) * hi, (1 + EPS) * cap)
+            assert (Mi @ r.x).max() <= (1 + EPS) * cap * (1 + 1e-12)
+            assert (Mu @ r.x).max() <= (1 + EPS) * hi * (1 + 1e-12)
+            assert (Mu @ r.x).min() >= lo * (1 - 1e-12) and r.x.min() >= 0
+        elif r.status == oracle_mod.INFEASIBLE:
+            assert not lp_feasible(hi, cap)
+
+
 def test_step_rule_effect(oracle_mod):
     """Table 2: the standard step needs orders of magnitude more iterations than
     the searched step on the same probe."""
