@@ -16,5 +16,12 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
+    src = os.environ.get("ORACLE_SRC_OVERRIDE")
+    if src:
+        # the planted-mistake test runs the pins against an altered copy of
+        # the oracle's source (tests/test_oracle_mutants.py)
+        oracle._SRC = src
+        oracle._LIB = os.path.splitext(src)[0] + ".so"
+        oracle._lib = None
     oracle.build()
     return oracle

@@ -91,6 +91,28 @@ def test_phi_psi_forms_match_definition(oracle_mod, alpha):
     assert zmn == pytest.approx(float(np.min(z + alpha * dz)), rel=1e-15)
 
 
+@pytest.mark.parametrize("alpha", [300.0, 3000.0])
+def test_phi_psi_large_steps_match_definition(oracle_mod, alpha):
+    """Section 4.1 at steps where eta*alpha*d reaches the thousands and the
+    moved point keeps several comparable rows (near-uniform dy and dz), so
+    that both log-sum terms of the shifted forms matter: 60-digit evaluation
+    of the plain differences."""
+    rng = np.random.default_rng(int(alpha))
+    eta = 200.0
+    m = 9
+    y = rng.uniform(0.2, 0.21, m)
+    dy = 1e-2 * (1 + rng.uniform(0, 1e-5, m))
+    z = rng.uniform(0.1, 0.11, m)
+    dz = 2e-2 * (1 + rng.uniform(0, 1e-5, m))
+    LP, w = oracle_mod.smax(y, eta)
+    LC, u = oracle_mod.smin(z, eta)
+    psi = oracle_mod.psi(y, dy, w, eta, LP, alpha)
+    phi, _ = oracle_mod.phi(z, dz, u, eta, LC, alpha)
+    e_psi, e_phi = _phi_psi_decimal(y, dy, z, dz, eta, alpha)
+    assert psi == pytest.approx(e_psi, rel=1e-12)
+    assert phi == pytest.approx(e_phi, rel=1e-12)
+
+
 def test_bang_for_buck_is_monotone(oracle_mod):
     """Proposition 1 (Section 4.1): f = Phi/Psi decreases in alpha."""
     rng = np.random.default_rng(7)
@@ -296,6 +318,79 @@ def test_iteration_invariants(oracle_mod):
         tt = oracle_mod.iteration_terms(P, 1.0, ones, 1.0 / M, EPS, x, alphas=[a])
         assert tt["phi"][0] >= tt["psi"][0]
         x = x + a * t["d"]
+
+
+def _weighted_mixed(mP, mC, n, seed):
+    """Dense P (mP x n) and C (mC x n) with spread positive entries; column 0
+    has tiny packing entries and a unit entry in every covering row, so its
+    ratio g_0/h_0 is below 1e-6 at any point."""
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(0.05, 2.0, (mP, n)) * (rng.random((mP, n)) < 0.5)
+    C = rng.uniform(0.05, 2.0, (mC, n)) * (rng.random((mC, n)) < 0.5)
+    P[:, 0] = 1e-7
+    C[:, 0] = 1.0
+    P[0, 1:] = np.where(P[0, 1:] > 0, P[0, 1:], 0.3)      # every column has a packing entry
+    return P, C
+
+
+@pytest.mark.parametrize("mP,mC,s", [(30, 20, 0.5), (25, 1, 1.0), (1, 18, 1.0)])
+def test_smoothing_and_step_constants(oracle_mod, mP, mC, s):
+    """Algorithm 1 fixes eta = 10 ln(m)/eps with m the rows of both sides, and
+    Algorithm 2's direction scale s/eta, with s = 1/2 and s = 1 when one side
+    is a single row (end of Section 2.2).  The smoothed max and min the probe
+    carries equal 60-digit evaluations of their definitions at that eta, and a
+    coordinate whose packing weight is negligible against its covering weight
+    moves by (s/eta) x_i, the largest step the direction allows."""
+    n = 40
+    Pd, Cd = _weighted_mixed(mP, mC, n, seed=mP + 7 * mC)
+    P, C = oracle_mod.CSR.from_dense(Pd), oracle_mod.CSR.from_dense(Cd)
+    eta = 10.0 * math.log(mP + mC) / EPS
+    x = np.random.default_rng(1).uniform(0.01, 0.05, n)
+    t = oracle_mod.iteration_terms(P, 1.0, C, 1.0, EPS, x)
+    assert t["LP"] == pytest.approx(float(d_smax(Pd @ x, eta)), rel=1e-13, abs=1e-14)
+    assert t["LC"] == pytest.approx(float(d_smin(Cd @ x, eta)), rel=1e-13, abs=1e-14)
+    ratio = t["d"] / x * eta / s
+    assert ratio.max() <= 1 + 1e-12
+    assert ratio[0] >= 1 - 1e-5
+
+
+def test_initial_point_tight_per_column(oracle_mod):
+    """Algorithm 1's start: every coordinate sits at eps/n of its tightest
+    packing row, so P x0 <= eps 1 whatever the column scales (here spread
+    over two orders of magnitude)."""
+    Pd, Cd = _weighted_mixed(12, 5, 30, seed=3)
+    P = oracle_mod.CSR.from_dense(Pd)
+    n = P.cols
+    x0 = np.zeros(n)
+    assert oracle_mod.lib().orc_initial_point(P.c, 1.0, EPS, x0.ctypes.data) == 0
+    assert (Pd @ x0).max() <= EPS * (1 + 1e-12)
+    np.testing.assert_allclose((Pd * x0).max(axis=0), EPS / n, rtol=1e-14)
+
+
+def test_probe_stops_at_first_covered_iterate(oracle_mod):
+    """Algorithm 2 returns as soon as Cx >= 1: the iterate one accepted step
+    earlier (the forced replay of all steps but the last) still has an
+    uncovered row, and the returned one has none."""
+    g = gg.bipartite_uniform(50, 60, 300, seed=4)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    ones = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    opt = hopcroft_karp(g)
+    rng = np.random.default_rng(5)
+    Pd = rng.uniform(0.05, 2.0, (20, 30)) * (rng.random((20, 30)) < 0.5)
+    Pd[0] = np.where(Pd[0] > 0, Pd[0], 0.3)
+    Cd = rng.uniform(0.05, 2.0, (12, 30)) * (rng.random((12, 30)) < 0.5)
+    Cd[:, 0] += 0.1
+    cases = [(P, ones, 1.0 / (0.8 * opt)), (P, ones, 1.0 / (0.95 * opt)),
+             (oracle_mod.CSR.from_dense(Pd), oracle_mod.CSR.from_dense(Cd), 2.0)]
+    for Pc, Cc, sC in cases:
+        r = oracle_mod.probe(Pc, 1.0, Cc, sC, EPS)
+        assert r.status == oracle_mod.FEASIBLE and r.iterations >= 2
+        assert (sC * Cc.dense() @ r.x).min() >= 1.0
+        prev = oracle_mod.probe(Pc, 1.0, Cc, sC, EPS, max_iter=r.iterations - 1,
+                                forced_alpha=r.alphas[:-1])
+        assert prev.status == oracle_mod.MAX_ITER
+        assert (sC * Cc.dense() @ prev.x).min() < 1.0
 
 
 def test_probe_trajectory_matches_forced_replay(oracle_mod):
