@@ -6,6 +6,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# the planted-mistake test (tests/test_oracle_mutants.py) runs the pins
+# against an altered copy of the oracle package placed first on the path
+if os.environ.get("ORACLE_PKG_OVERRIDE"):
+    sys.path.insert(0, os.environ["ORACLE_PKG_OVERRIDE"])
 
 
 def pytest_configure(config):
@@ -16,12 +20,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
-    src = os.environ.get("ORACLE_SRC_OVERRIDE")
-    if src:
-        # the planted-mistake test runs the pins against an altered copy of
-        # the oracle's source (tests/test_oracle_mutants.py)
-        oracle._SRC = src
-        oracle._LIB = os.path.splitext(src)[0] + ".so"
-        oracle._lib = None
     oracle.build()
     return oracle

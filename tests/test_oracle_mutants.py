@@ -1,19 +1,21 @@
-"""Planted mistakes: each case alters one line of a copy of the oracle's C
-source in the way a plausible slip would (a dropped term, a flipped sign, a
-wrong or transposed operand, an inverted test) and runs the pins of
-tests/test_oracle_pins.py against that copy.  Every altered oracle must fail
+"""Planted mistakes: each case alters one or two lines of a copy of the
+oracle package (its C source, or the Python module that builds the graph
+problems' matrices) in the way a plausible slip would (a dropped term, a
+flipped sign, a wrong or transposed operand, an inverted test) and runs the
+pins of tests/test_oracle_pins.py against that copy.  Every altered oracle must fail
 at least one pin, which shows that the pins bind each step of the oracle and
 do not merely re-run it.  CPU only; the oracle in the tree is not touched."""
 import os
+import shutil
 import subprocess
 import sys
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "oracle", "mwu_oracle.c")
+PKG = os.path.join(ROOT, "oracle")
 
-# (what the slip is, the exact text of the line, the altered text)
+# C source: (what the slip is, the exact text of the line, the altered text)
 MUTANTS = [
     ("smax: max shift dropped from the value",
      "return ymax + log(sum) / eta;", "return log(sum) / eta;"),
@@ -69,16 +71,61 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.parametrize("what,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_fails_a_pin(tmp_path, what, old, new):
-    text = open(SRC).read()
+# Python matrix builders (Section 3 formulations)
+PY_MUTANTS = [
+    ("dominating set: identity left out of I + A",
+     "    r = np.concatenate([g.u, g.v, ar])\n    c = np.concatenate([g.v, g.u, ar])",
+     "    r = np.concatenate([g.u, g.v])\n    c = np.concatenate([g.v, g.u])"),
+    ("dominating set: A taken one way only",
+     "    r = np.concatenate([g.u, g.v, ar])\n    c = np.concatenate([g.v, g.u, ar])",
+     "    r = np.concatenate([g.u, ar])\n    c = np.concatenate([g.v, ar])"),
+    ("incidence: second endpoint replaced by the first",
+     "np.concatenate([u, v]), np.concatenate([e, e]))", "np.concatenate([u, u]), np.concatenate([e, e]))"),
+    ("vertex cover: edge rows hold one endpoint twice",
+     "np.concatenate([newid[g.u], newid[g.v]]))", "np.concatenate([newid[g.u], newid[g.u]]))"),
+    ("densest: W rows cover one orientation twice",
+     "W = CSR.from_coo(m, 2 * m, np.concatenate([e, e]), np.concatenate([2 * e, 2 * e + 1]))",
+     "W = CSR.from_coo(m, 2 * m, np.concatenate([e, e]), np.concatenate([2 * e, 2 * e]))"),
+    ("packing normalisation: objective weights dropped",
+     "A.val / (b[rows] * c[A.idx])", "A.val / b[rows]"),
+]
+
+CASES = [("mwu_oracle.c",) + m for m in MUTANTS] + [("__init__.py",) + m for m in PY_MUTANTS]
+
+
+@pytest.mark.parametrize("fname,what,old,new", CASES, ids=[c[1] for c in CASES])
+def test_planted_mistake_fails_a_pin(tmp_path, fname, what, old, new):
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("mwu_oracle.c", "__init__.py"):
+        shutil.copy(os.path.join(PKG, f), pkg / f)
+    text = (pkg / fname).read_text()
     assert text.count(old) == 1, f"mutation site not unique or missing: {old!r}"
-    src = tmp_path / "mwu_oracle.c"
-    src.write_text(text.replace(old, new))
-    env = dict(os.environ, ORACLE_SRC_OVERRIDE=str(src))
+    (pkg / fname).write_text(text.replace(old, new))
+    env = dict(os.environ, ORACLE_PKG_OVERRIDE=str(tmp_path))
     p = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     tail = "\n".join(p.stdout.splitlines()[-3:])
     # 1: a pin failed (0 would mean the mistake went unnoticed)
     assert p.returncode == 1, f"{what}: pytest exit {p.returncode}\n{tail}"
+
+
+def test_unaltered_copy_passes(tmp_path):
+    """The harness itself: the copied package, unaltered, passes every pin,
+    so each failure above comes from its planted slip."""
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("mwu_oracle.c", "__init__.py"):
+        shutil.copy(os.path.join(PKG, f), pkg / f)
+    env = dict(os.environ, ORACLE_PKG_OVERRIDE=str(tmp_path))
+    code = ("import sys, os; sys.path.insert(0, os.environ['ORACLE_PKG_OVERRIDE']); import oracle; "
+            "print(oracle.__file__)")
+    where = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           check=True).stdout.strip()
+    assert where == str(pkg / "__init__.py")
+    p = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        "-q", "-p", "no:cacheprovider", "-m", "not gpu"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert p.returncode == 0, p.stdout[-2000:]
+    assert (pkg / "libmwu_oracle.so").exists()        # the pins ran against the copy
