@@ -2,9 +2,10 @@
 oracle package (its C source, or the Python module that builds the graph
 problems' matrices) in the way a plausible slip would (a dropped term, a
 flipped sign, a wrong or transposed operand, an inverted test) and runs the
-pins of tests/test_oracle_pins.py against that copy.  Every altered oracle must fail
-at least one pin, which shows that the pins bind each step of the oracle and
-do not merely re-run it.  CPU only; the oracle in the tree is not touched."""
+pins of tests/test_oracle_pins.py against that copy.  Every altered oracle
+must fail at least one pin, which shows that the pins bind each step of the
+oracle and do not merely re-run it.  CPU only; the oracle in the tree is not
+touched."""
 import os
 import shutil
 import subprocess
