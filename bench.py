@@ -1,18 +1,29 @@
 """Benchmark: time-to-(1+eps) of the MWU solver on one MI355X, chosen form
-(FP32 vectors, FP64 totals and decisions) against the plain FP64 form, plus
-the HBM throughput of the sparse product passes.
+(FP32 weights and search terms, FP64 totals, decisions and, where rounding
+would grow, the direction) against the plain FP64 form, plus the HBM
+throughput of the sparse product passes.
 
-Workload: vertex cover LP (min 1^T x s.t. M^T x >= 1) on a seeded R-MAT graph,
-scale 20, edge factor 16, a/b/c = 0.57/0.19/0.19, self-loops and duplicates
-removed, eps = 0.1 -- a synthetic stand-in for the paper's Graph500 Kronecker
-inputs.  A step is one full solve (outer search over M, every MWU iteration,
-step searches and certificates) with the graph already resident in HBM.
+Headline workload (the largest configuration that fits one GPU): the densest
+subgraph LP (the dual of Charikar's LP with D searched, Section 3 of the
+paper) on a seeded R-MAT graph, scale 22, edge factor 16, a/b/c =
+0.57/0.19/0.19, self-loops and duplicates removed, eps = 0.1: 64.2M edges,
+128.3M variables.  A synthetic stand-in for the paper's Graph500 Kronecker
+inputs.  A step is one full solve (outer search over D, every MWU iteration,
+step searches, level-set bounds and certificates) with the graph already
+resident in HBM.
+
+The line also carries the vertex-cover LP on R-MAT scale 20 and the batch of
+512 bipartite-matching LPs as extra keys (``--no-extra`` leaves them out), the
+roofline of the dominant kernel (algorithmic bytes over its mean launch
+duration, HIP events on the solver stream) and the plain FP64 CPU oracle
+timed on a bounded sample of the same workload on one host core.
 
 Prints one JSON line.
 """
 import argparse
 import json
 import os
+import platform
 import statistics
 import sys
 import time
@@ -22,9 +33,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-(1+eps) at eps=0.1 + A/A^T nnz/s (HBM GB/s), chosen vs plain FP64"
 HBM_PEAK_GBPS = 8000.0
-PASS_NAMES = {0: "transpose_pass", 1: "direction_pass", 2: "forward_pass", 3: "search_pass_exp",
+PASS_NAMES = {0: "row_pass", 1: "column_pass", 2: "forward_pass", 3: "search_pass_exp",
               4: "search_pass_bisect", 5: "search_pass_combined"}
-KERNEL_NAMES = {0: "vc_passA_k", 1: "vc_passB_k", 3: "vc_search_k"}
+VC_PASS_NAMES = {0: "transpose_pass", 1: "direction_pass", 2: "forward_pass", 3: "search_pass_exp",
+                 4: "search_pass_bisect", 5: "search_pass_combined"}
+DN_KERNELS = {0: "dn_row", 1: "dn_col", 2: "dn_fwd_v", 3: "dn_search"}
+VC_KERNELS = {0: "vc_passA_k", 1: "vc_passB_k", 3: "vc_search_k"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -32,7 +46,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_graph(scale, edge_factor, seed):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def rmat_graph(scale, edge_factor, seed):
     import graphgen as gg
     return gg.cached(f"rmat{scale}_ef{edge_factor}_s{seed}", lambda: gg.rmat(scale, edge_factor, seed=seed))
 
@@ -41,140 +66,231 @@ def step_rule_of(mwu, args):
     return mwu.STEP_BIN_WARM if args.step_rule == "warm" else mwu.STEP_BIN
 
 
-def run_solves(mwu, g, precision, steps, warmup, step_rule):
-    t0 = time.perf_counter()
-    s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, step_rule=step_rule)
-    create_s = time.perf_counter() - t0
-    res = []
+def timed_solves(s, steps, warmup, tag):
+    import torch
+    walls, r = [], None
     for i in range(warmup + steps):
+        torch.cuda.synchronize()
         t = time.perf_counter()
         r = s.solve()
-        wall = time.perf_counter() - t
+        w = time.perf_counter() - t
         if i >= warmup:
-            res.append((wall, r))
-        log(f"  precision={precision} solve {i}: {wall:.4f}s obj={r.objective:.2f} "
-            f"[{r.lower:.2f}, {r.upper:.2f}] status={r.status} iters={r.total_iterations} "
-            f"probes={r.probes} passes={r.search_passes}")
-    return s, create_s, res
+            walls.append(w)
+        log(f"  {tag} solve {i}: {w:.4f}s obj={r.objective:.4f} [{r.lower:.4f}, {r.upper:.4f}] "
+            f"status={r.status} iters={r.total_iterations} probes={r.probes} passes={r.search_passes} "
+            f"evaluations={r.evaluations}")
+    return walls, r
 
 
 def pass_times(s, reps, param, warm_iters=0):
     """Average duration of each pass's main kernel (HIP events on the solver
     stream, state held), its algorithmic bytes and nonzeros, after warm_iters
-    iterations of a probe at param (so that the passes run over the lists
-    they use in most of a solve)."""
+    iterations of a probe at param."""
     out = {}
     s.probe_begin(param)
     if warm_iters:
         info = s.probe_run(warm_iters)
         log(f"  pass timing at iteration {info.iterations} of a probe at {param:.6g} (status {info.status})")
-    # the transpose pass last: every timing first forms one direction (a
-    # transpose pass of its own), so its held launches are then the last ones
-    # of its kernel, as the counter summaries under profiles/ assume
-    for which in (1, 3, 4, 5, 0):
+    # the row/transpose pass last: every timing first forms one direction (a
+    # row pass of its own), so its held launches are the last ones of its
+    # kernel, as the summaries under profiles/ assume
+    for which in (1, 2, 3, 4, 5, 0):
         us, by, nz = s.time_pass(which, reps)
+        if by <= 0.0:       # a pass fused into another one (no kernel of its own)
+            continue
         out[which] = {"us": us, "bytes": by, "nnz": nz, "GBps": by / us / 1e3,
                       "nnz_per_s": nz / (us * 1e-6) if nz else None}
     return out
 
 
-def copy_calibration(mib):
-    """A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
-    readings give the scale between counter units and bytes."""
-    import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    log(f"copy calibration: 3 copies of {mib} MiB")
+def dominant(passes, r, kernels, names, tag, workload):
+    """The pass with the largest share of one iteration: one row pass, one
+    column pass, one forward pass, and the search passes (the combined first
+    pass, plus exponential-grid or bisection passes in the iterations the
+    combined pass does not settle).  Its roofline is reported for its common
+    launch (the combined pass for the search)."""
+    from paper_2307_03307_amd import profiling
+    spi = r.search_passes / max(1, r.total_iterations)
+    extra = max(0.0, spi - 1.0)
+    fallback_us = 0.5 * (passes[3]["us"] + passes[4]["us"])
+    search_us = (passes[5]["us"] + extra * fallback_us) / (1.0 + extra)
+    share = {k: passes[k]["us"] for k in (0, 1, 2) if k in passes and k in kernels}
+    share[3] = spi * search_us
+    dom = max(share, key=share.get)
+    dom_pass = 5 if dom == 3 else dom
+    kernel = kernels[dom]
+    tname = "float" if tag == "f32" else "double"
+    full = f"{kernel}<{tname}, false>" if kernel.endswith("_fwd_v") else f"{kernel}<{tname}>"
+    us, by = passes[dom_pass]["us"], passes[dom_pass]["bytes"]
+    achieved = by / us / 1e3
+    traffic = profiling.load_traffic(os.path.join(PROFILES, f"{kernel}_{workload}_{tag}_traffic.txt"), full)
+    return {"bound": "hbm", "kernel": full,
+            "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic, "avg_launch_us": us, "algorithmic_bytes": by, "pass": names[dom_pass],
+            "share_of_iteration": share[dom] / sum(share.values()),
+            "pass_share": {names[5 if k == 3 else k]: v / sum(share.values()) for k, v in share.items()}}
 
 
-def cpu_baseline(g, gpu_iters, iters=8):
-    """The plain FP64 oracle on this host: a bounded number of iterations of the
-    first probe, scaled to the GPU's iteration count."""
+# ------------------------------------------------------------------ CPU oracle
+
+def cpu_baseline_densest(g, param, gpu_iters, gpu_evals):
+    """The plain FP64 oracle on one host core, on a bounded sample of the same
+    workload: one and two iterations of a probe with the standard step (no
+    search) give the per-iteration cost of the passes; one iteration with
+    Algorithm 3 adds its evaluations of the test.  The GPU solve's iteration
+    and evaluation counts (the evaluations a one-at-a-time Algorithm 3 makes,
+    counted on the device) scale the two costs."""
+    import oracle
+    oracle.build()
+    t = time.perf_counter()
+    O, W, keep = oracle.densest_matrices(g)
+    build_s = time.perf_counter() - t
+    sP = 1.0 / param
+
+    def run(rule, iters):
+        t = time.perf_counter()
+        r = oracle.probe(O, sP, W, 1.0, 0.1, max_iter=iters, step_rule=rule)
+        return time.perf_counter() - t, r
+
+    t1, _ = run(oracle.STEP_STD, 1)
+    t2, _ = run(oracle.STEP_STD, 2)
+    tb, rb = run(oracle.STEP_BIN, 1)
+    per_iter = max(t2 - t1, 1e-9)
+    per_eval = max(tb - t1, 0.0) / max(1, rb.evaluations)
+    est = per_iter * gpu_iters + per_eval * gpu_evals
+    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (plain single-threaded FP64 C, gcc -O2) on the same graph and LP at D = {param:.6g}: "
+                       f"probes of 1 and 2 iterations with the standard step ({t1:.1f} s, {t2:.1f} s) and one "
+                       f"iteration of Algorithm 3 ({tb:.1f} s, {rb.evaluations} evaluations); "
+                       f"{per_iter:.2f} s per iteration x {gpu_iters} iterations + {per_eval:.2f} s per "
+                       f"evaluation x {gpu_evals} evaluations of the GPU solve; explicit matrix build "
+                       f"{build_s:.1f} s not counted"),
+            "per_iteration_s": per_iter, "per_evaluation_s": per_eval, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
+
+
+def cpu_baseline_vcover(g, gpu_iters, gpu_evals, param):
+    """As cpu_baseline_densest, for the vertex-cover LP."""
     import numpy as np
     import oracle
     oracle.build()
     C, keep = oracle.vertex_cover_matrix(g)
     n = C.cols
     ones = oracle.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
-    M = 0.5 * n   # any probe: the per-iteration cost does not depend on M
-    t = time.perf_counter()
-    oracle.probe(ones, 1.0 / M, C, 1.0, 0.1, max_iter=1)
-    t1 = time.perf_counter() - t
-    t = time.perf_counter()
-    r = oracle.probe(ones, 1.0 / M, C, 1.0, 0.1, max_iter=1 + iters)
-    tk = time.perf_counter() - t
-    per_iter = (tk - t1) / iters
-    setup = max(t1 - per_iter, 0.0)
-    est = per_iter * gpu_iters
+
+    def run(rule, iters):
+        t = time.perf_counter()
+        r = oracle.probe(ones, 1.0 / param, C, 1.0, 0.1, max_iter=iters, step_rule=rule)
+        return time.perf_counter() - t, r
+
+    t1, _ = run(oracle.STEP_STD, 1)
+    t2, _ = run(oracle.STEP_STD, 3)
+    tb, rb = run(oracle.STEP_BIN, 1)
+    per_iter = max(t2 - t1, 1e-9) / 2
+    per_eval = max(tb - t1, 0.0) / max(1, rb.evaluations)
+    est = per_iter * gpu_iters + per_eval * gpu_evals
     return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"{iters} MWU iterations (Algorithm 2 + 3, {r.evaluations} step evaluations "
-                       f"over {1 + iters} iterations) of one vertex-cover probe on the same graph, "
-                       f"single-threaded FP64 C (gcc -O2); {per_iter:.3f} s per iteration times the "
-                       f"{gpu_iters} iterations the GPU solve took; probe setup {setup:.2f} s not counted"),
-            "per_iteration_s": per_iter}
+            "sample": (f"oracle on the same graph at M = {param:.6g}: 1 and 3 standard-step iterations, one "
+                       f"Algorithm 3 iteration ({rb.evaluations} evaluations); {per_iter:.3f} s per iteration x "
+                       f"{gpu_iters} + {per_eval:.3f} s per evaluation x {gpu_evals}"),
+            "per_iteration_s": per_iter, "per_evaluation_s": per_eval, "cpu_model": cpu_model()}
 
 
-def run_densest(args):
-    """Densest subgraph (Charikar's dual, D searched) on a seeded R-MAT graph,
-    scale 22, edge factor 16: fused program, chosen form vs plain FP64.  No
-    exact optimum exists at this size; a run counts when its bracket (level-set
-    lower bound, rescaled feasible upper bound) is within 1 + eps."""
+# ------------------------------------------------------------------ workloads
+
+def run_densest(args, steps, warmup, with_cpu=True):
+    """Densest subgraph (Charikar's dual, D searched): fused program, chosen
+    form vs plain FP64.  No exact optimum exists at this size; a run counts
+    when its bracket (level-set lower bound, rescaled feasible upper bound) is
+    within 1 + eps."""
     import torch
-    import graphgen as gg
     import paper_2307_03307_amd as mwu
     assert torch.cuda.is_available(), "needs an MI355X"
     t = time.perf_counter()
-    g = gg.cached(f"rmat{args.scale}_ef{args.edge_factor}_s3",
-                  lambda: gg.rmat(args.scale, args.edge_factor, seed=3))
+    g = rmat_graph(args.scale, args.edge_factor, 3)
     log(f"graph: {g.num_vertices} vertices, {g.num_edges} edges ({time.perf_counter() - t:.1f}s)")
 
     def run(precision, steps, warmup):
         t = time.perf_counter()
-        s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision,
-                                 step_rule=step_rule_of(mwu, args))
+        s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=precision, step_rule=step_rule_of(mwu, args))
         create = time.perf_counter() - t
-        walls, r = [], None
-        for i in range(warmup + steps):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r = s.solve()
-            w = time.perf_counter() - t
-            if i >= warmup:
-                walls.append(w)
-            log(f"  precision={precision} densest solve {i}: {w:.3f}s obj={r.objective:.4f} "
-                f"[{r.lower:.4f}, {r.upper:.4f}] status={r.status} iters={r.total_iterations} "
-                f"probes={r.probes} passes={r.search_passes}")
-        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper))
+        walls, r = timed_solves(s, steps, warmup, f"densest precision={precision}")
+        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=args.pass_warm_iters)
         s.close()
         return create, walls, r, passes
 
-    c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, args.steps, args.warmup)
-    c64, w64, r64, p64 = run(mwu.FP64, 1, 0)
-    t32 = statistics.mean(w32)
+    c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
+    c64, w64, r64, p64 = run(mwu.FP64, args.fp64_steps, 1 if args.fp64_steps > 1 else 0)
+    t32, t64 = statistics.mean(w32), statistics.mean(w64)
+    workload = f"rmat{args.scale}"
     out = {
-        "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1000.0 * t32, "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": 1000.0 * t32, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"densest subgraph LP (Charikar dual, D searched), R-MAT scale {args.scale}, "
                                f"edge factor {args.edge_factor}, a/b/c=0.57/0.19/0.19, seed 3, eps=0.1",
                    "vertices": g.num_vertices, "edges": g.num_edges, "variables": 2 * g.num_edges,
+                   "form": "FP32 weights and search terms; FP64 x, d, rows, totals and decisions",
                    "step_rule": args.step_rule},
         "certified": r32.certified, "objective": r32.objective, "bracket": [r32.lower, r32.upper],
-        "iterations": r32.total_iterations, "probes": r32.probes, "create_s": c32,
-        "fp64_plain_s": statistics.mean(w64), "fp64_certified": r64.certified,
+        "iterations": r32.total_iterations, "probes": r32.probes, "search_passes": r32.search_passes,
+        "evaluations": r32.evaluations, "create_s": c32,
+        "fp64_plain_s": t64, "fp64_steps": len(w64), "fp64_certified": r64.certified,
         "fp64_bracket": [r64.lower, r64.upper], "fp64_iterations": r64.total_iterations,
-        "speedup_vs_fp64": statistics.mean(w64) / t32,
+        "fp64_search_passes": r64.search_passes, "speedup_vs_fp64": t64 / t32,
         "passes": {PASS_NAMES[k]: v for k, v in p32.items()},
         "passes_fp64": {PASS_NAMES[k]: v for k, v in p64.items()},
+        "roofline": dominant(p32, r32, DN_KERNELS, PASS_NAMES, "f32", workload),
+        "roofline_fp64": dominant(p64, r64, DN_KERNELS, PASS_NAMES, "f64", workload),
     }
-    print(json.dumps(out), flush=True)
+    out["A_nnz_per_s"] = p32[2]["nnz_per_s"] if 2 in p32 else None
+    if with_cpu:
+        log("cpu baseline (oracle sample) ...")
+        out["cpu_baseline"] = cpu_baseline_densest(g, 0.5 * (r32.lower + r32.upper), r32.total_iterations,
+                                                   r32.evaluations)
+    return out
 
 
-def run_batched(args):
+def run_vcover(args, steps, warmup, scale=20, with_cpu=False):
+    """Vertex cover LP (min 1^T x s.t. M^T x >= 1) via the implicit edge-list
+    incidence on R-MAT scale 20: fused program with sparse passes."""
+    import torch
+    import paper_2307_03307_amd as mwu
+    assert torch.cuda.is_available(), "needs an MI355X"
+    t = time.perf_counter()
+    g = rmat_graph(scale, args.edge_factor, 2)
+    log(f"graph: {g.num_vertices} vertices, {g.num_edges} edges ({time.perf_counter() - t:.1f}s)")
+
+    def run(precision, steps, warmup):
+        t = time.perf_counter()
+        s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, step_rule=step_rule_of(mwu, args))
+        create = time.perf_counter() - t
+        walls, r = timed_solves(s, steps, warmup, f"vcover precision={precision}")
+        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=600)
+        s.close()
+        return create, walls, r, passes
+
+    c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
+    c64, w64, r64, p64 = run(mwu.FP64, max(1, steps // 2), 1)
+    t32, t64 = statistics.mean(w32), statistics.mean(w64)
+    out = {
+        "workload": f"vertex cover LP, R-MAT scale {scale}, edge factor {args.edge_factor}, seed 2, eps=0.1",
+        "vertices": g.num_vertices, "edges": g.num_edges, "value": t32, "unit": "s", "steps": steps,
+        "certified": r32.certified, "objective": r32.objective, "bracket": [r32.lower, r32.upper],
+        "iterations": r32.total_iterations, "probes": r32.probes, "search_passes": r32.search_passes,
+        "evaluations": r32.evaluations, "create_s": c32, "fp64_plain_s": t64, "fp64_certified": r64.certified,
+        "fp64_iterations": r64.total_iterations, "speedup_vs_fp64": t64 / t32,
+        "passes": {VC_PASS_NAMES[k]: v for k, v in p32.items()},
+        "passes_fp64": {VC_PASS_NAMES[k]: v for k, v in p64.items()},
+        "roofline": dominant(p32, r32, VC_KERNELS, VC_PASS_NAMES, "f32", f"rmat{scale}"),
+    }
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline_vcover(g, r32.total_iterations, r32.evaluations,
+                                                  0.5 * (r32.lower + r32.upper))
+    return out
+
+
+def run_batched(args, steps, warmup):
     """Batched bipartite matching: 512 uneven instances (sides uniform in
     [1024, 65536], mean degree uniform in [4, 16]) solved together, against
     the plain FP64 form of the same batch and a host loop of single-instance
@@ -214,7 +330,7 @@ def run_batched(args):
         b.close()
         return create, walls, res, layout
 
-    c32, w32, r32, lay32 = run(mwu.MIXED_FP32_FP64, args.steps, args.warmup)
+    c32, w32, r32, lay32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
     c64, w64, r64, lay64 = run(mwu.FP64, 1, 0)
     _, wdef, _, _ = run(mwu.MIXED_FP32_FP64, 1, 0, tune=False)
     # exact optima of a sample (Hopcroft-Karp; the bipartite matching LP is integral)
@@ -237,39 +353,20 @@ def run_batched(args):
         e_loop += g.num_edges
     loop_s = (time.perf_counter() - t) * E / e_loop
     t32 = statistics.mean(w32)
-    out = {
-        "metric": METRIC,
-        "value": t32,
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * t32,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"batched bipartite matching LPs: {len(gs)} instances, sides uniform in "
-                               f"[1024, 65536], mean degree uniform in [4, 16], eps=0.1",
-                   "instances": len(gs), "vertices": V, "edges": E, "step_rule": args.step_rule},
-        "certified": sum(r.certified for r in r32),
-        "exact_optimum_in_bracket": f"{ok}/{len(sample)}",
-        "iterations": sum(r.total_iterations for r in r32),
-        "create_s": c32,
+    return {
+        "workload": f"batched bipartite matching LPs: {len(gs)} instances, sides uniform in [1024, 65536], "
+                    f"mean degree uniform in [4, 16], eps=0.1",
+        "instances": len(gs), "vertices": V, "edges": E, "value": t32, "unit": "s", "steps": steps,
+        "certified": sum(r.certified for r in r32), "exact_optimum_in_bracket": f"{ok}/{len(sample)}",
+        "iterations": sum(r.total_iterations for r in r32), "create_s": c32,
         "layout": {k: lay32[k] for k in ("tile_edges", "tile_vertices", "workgroups_per_cu",
                                          "search_launches", "source", "candidates_timed")},
         "default_layout_s": wdef[0],
-        "layout_fp64": {k: lay64[k] for k in ("tile_edges", "tile_vertices", "workgroups_per_cu",
-                                              "search_launches")},
-        "fp64_batched_s": statistics.mean(w64),
-        "fp64_batched_certified": sum(r.certified for r in r64),
+        "fp64_batched_s": statistics.mean(w64), "fp64_batched_certified": sum(r.certified for r in r64),
         "fp64_loop_s": loop_s,
         "fp64_loop_sample": f"{loop_n} instances ({e_loop} edges) timed, scaled by total edges",
-        "speedup_vs_fp64_batched": statistics.mean(w64) / t32,
-        "speedup_vs_fp64_loop": loop_s / t32,
+        "speedup_vs_fp64_batched": statistics.mean(w64) / t32, "speedup_vs_fp64_loop": loop_s / t32,
     }
-    print(json.dumps(out), flush=True)
 
 
 def run_genmatch(args):
@@ -351,143 +448,61 @@ def run_genmatch(args):
     }
 
 
+def headline(args, d, workload):
+    """Wrap a workload record in the fields of the one-line bench contract."""
+    out = {"metric": METRIC, "value": d["value"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1000.0 * d["value"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": workload, "step_rule": args.step_rule}}
+    out.update({k: v for k, v in d.items() if k not in ("value", "unit", "steps", "workload")})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch"], default="densest",
+                    help="densest: the headline R-MAT scale 22 densest subgraph (default); vcover: R-MAT "
+                         "vertex cover; batched: 512 matching LPs; genmatch: generalized matching")
+    ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default 22 densest, 20 vcover)")
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only: leave out the vertex-cover and batched records")
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed solves of the plain FP64 form")
     ap.add_argument("--pass-reps", type=int, default=50)
-    ap.add_argument("--pass-warm-iters", type=int, default=600,
-                    help="iterations of a near-optimum probe before the passes are timed")
-    ap.add_argument("--workload", choices=["vcover", "batched", "densest", "genmatch"], default="vcover",
-                    help="vcover: the headline R-MAT vertex cover; batched: 512 matching LPs; "
-                         "densest: R-MAT densest subgraph (use --scale 22)")
+    ap.add_argument("--pass-warm-iters", type=int, default=48,
+                    help="densest: iterations of a probe at the middle of the final bracket before the "
+                         "passes are timed")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--gm-users", type=int, default=200000)
     ap.add_argument("--gm-items", type=int, default=20000)
     ap.add_argument("--loop-sample", type=int, default=16)
     ap.add_argument("--step-rule", choices=["bin", "warm"], default="bin",
                     help="bin: Algorithm 3 from 1 in every iteration; warm: started at the previous step")
-    ap.add_argument("--copy-calib-mib", type=int, default=0,
-                    help="also run a plain copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if args.scale is None:
+        args.scale = 20 if args.workload == "vcover" else 22
 
-    if args.workload == "batched":
-        run_batched(args)
-        return
     if args.workload == "densest":
-        run_densest(args)
-        return
-    if args.workload == "genmatch":
-        print(json.dumps(run_genmatch(args)))
-        return
-
-    import torch
-    import paper_2307_03307_amd as mwu
-    assert torch.cuda.is_available(), "needs an MI355X"
-
-    t = time.perf_counter()
-    g = make_graph(args.scale, args.edge_factor, seed=2)
-    log(f"graph: {g.num_vertices} vertices, {g.num_edges} edges, max degree {int(g.degrees().max())} "
-        f"({time.perf_counter() - t:.1f}s)")
-
-    if args.copy_calib_mib:
-        copy_calibration(args.copy_calib_mib)
-    torch.cuda.synchronize()
-    rule = step_rule_of(mwu, args)
-    s32, create32, r32 = run_solves(mwu, g, mwu.MIXED_FP32_FP64, args.steps, args.warmup, rule)
-    torch.cuda.synchronize()
-    t32 = statistics.mean(w for w, _ in r32)
-    last32 = r32[-1][1]
-    passes32 = pass_times(s32, args.pass_reps, param=0.5 * (last32.lower + last32.upper),
-                          warm_iters=args.pass_warm_iters)
-    s32.close()
-
-    t64 = None
-    last64 = None
-    passes64 = None
-    if not args.no_fp64:
-        s64, create64, r64 = run_solves(mwu, g, mwu.FP64, args.steps, args.warmup, rule)
-        torch.cuda.synchronize()
-        t64 = statistics.mean(w for w, _ in r64)
-        last64 = r64[-1][1]
-        passes64 = pass_times(s64, args.pass_reps, param=0.5 * (last64.lower + last64.upper),
-                              warm_iters=args.pass_warm_iters)
-        s64.close()
-
-    # dominant kernel: the pass with the largest share of one iteration (one
-    # transpose pass, one direction pass, and search passes: the combined
-    # first pass, plus exponential-grid or bisection passes in the iterations
-    # the combined pass does not settle, all launches of vc_search_k).  Its
-    # roofline is reported for its common launch: the transpose pass, or the
-    # combined search pass.
-    spi = last32.search_passes / max(1, last32.total_iterations)
-    extra = max(0.0, spi - 1.0)
-    fallback_us = 0.5 * (passes32[3]["us"] + passes32[4]["us"])
-    search_us = (passes32[5]["us"] + extra * fallback_us) / (1.0 + extra)
-    share = {0: passes32[0]["us"], 1: passes32[1]["us"], 3: spi * search_us}
-    dom = max(share, key=share.get)
-    dom_pass = 5 if dom == 3 else dom
-    dom_us = passes32[dom_pass]["us"]
-    dom_bytes = passes32[dom_pass]["bytes"]
-    kernel = KERNEL_NAMES[dom]
-    from paper_2307_03307_amd import profiling
-    traffic = profiling.load_traffic(
-        os.path.join(PROFILES, f"{kernel}_rmat{args.scale}_f32_traffic.txt"), f"{kernel}<float>")
-    achieved = dom_bytes / dom_us / 1e3
-    roofline = {"bound": "hbm", "kernel": kernel + "<float>", "achieved": achieved,
-                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": traffic, "avg_launch_us": dom_us, "algorithmic_bytes": dom_bytes,
-                "pass": PASS_NAMES[dom_pass],
-                "share_of_iteration": share[dom] / sum(share.values())}
-
-    out = {
-        "metric": METRIC,
-        "value": t32,
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * t32,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"vertex cover LP, R-MAT scale {args.scale}, edge factor "
-                               f"{args.edge_factor}, a/b/c=0.57/0.19/0.19, seed 2, eps=0.1",
-                   "vertices": g.num_vertices, "edges": g.num_edges, "eps": 0.1,
-                   "form": "mixed FP32 vectors / FP64 totals and decisions", "step_rule": args.step_rule},
-        "certified": last32.certified,
-        "objective": last32.objective,
-        "bracket": [last32.lower, last32.upper],
-        "iterations": last32.total_iterations,
-        "probes": last32.probes,
-        "search_passes": last32.search_passes,
-        "create_s": create32,
-        "fp64_plain_s": t64,
-        "speedup_vs_fp64": (t64 / t32) if t64 else None,
-        "fp64_certified": last64.certified if last64 else None,
-        "fp64_objective": last64.objective if last64 else None,
-        "fp64_iterations": last64.total_iterations if last64 else None,
-        "passes": {PASS_NAMES[k]: v for k, v in passes32.items()},
-        "passes_fp64": {PASS_NAMES[k]: v for k, v in passes64.items()} if passes64 else None,
-        "A_nnz_per_s": passes32[5]["nnz"] / (passes32[5]["us"] * 1e-6),
-        "AT_nnz_per_s": passes32[0]["nnz_per_s"],
-        "roofline": roofline,
-    }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, last32.total_iterations)
-        out["cpu_baseline"]["host_cpus"] = os.cpu_count()
+        out = run_densest(args, args.steps, args.warmup, with_cpu=not args.no_cpu_baseline)
+        if not args.no_extra:
+            out["vcover_rmat20"] = run_vcover(args, 3, 1)
+            out["batched_512"] = run_batched(args, 2, 1)
+    elif args.workload == "vcover":
+        d = run_vcover(args, args.steps, args.warmup, scale=args.scale, with_cpu=not args.no_cpu_baseline)
+        out = headline(args, d, d["workload"])
+    elif args.workload == "batched":
+        d = run_batched(args, args.steps, args.warmup)
+        out = headline(args, d, d["workload"])
+    else:
+        out = run_genmatch(args)
     print(json.dumps(out), flush=True)
 
 

@@ -55,6 +55,11 @@ typedef int32_t mwu_status;
 #define MWU_FEASIBLE_UNCERTIFIED 1  /* feasible x, bracket not closed (probe cap or iteration cap) */
 #define MWU_INFEASIBLE           2  /* single-probe mode: the feasibility LP is infeasible */
 #define MWU_MAX_ITER             3  /* single-probe mode: iteration cap reached */
+#define MWU_FEASIBLE_POINT       4  /* single-probe mode (MWU_MIXED with mixed_fixed_lambda): Algorithm 2
+                                       stopped with C x >= b_C (Section 4); x_out is that point, not
+                                       rescaled, objective_out = max_i (A_P x)_i / b_P,i (its lambda,
+                                       at most about (1 + eps) times the lambda asked for), and
+                                       max_violation = max{0, max(Px)/lambda - 1, 1 - min(Cx)} of it */
 
 /* probe outcome (mwu_probe_info.status) */
 #define MWU_PROBE_RUNNING    0
@@ -155,6 +160,8 @@ typedef struct {
     int64_t probes;
     double max_violation;       /* max{0, max(Px)-1, 1-min(Cx)} of the last probe's x (Sec. 6.3) */
     double seconds_solve;       /* wall time of mwu_solve */
+    int64_t evaluations;        /* tests Phi(alpha) >= Psi(alpha) the step searches made, counted
+                                   as a one-at-a-time Algorithm 3 (Section 4.2) makes them */
 } mwu_result_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -250,6 +257,7 @@ typedef struct {
     double alpha;              /* last accepted step */
     double L_P, L_C;           /* smax(Px), smin(Cx) (Section 2.2) */
     double pack_bound, cover_bound;   /* weak-duality bounds seen so far */
+    int64_t evaluations;       /* tests of Phi >= Psi, counted as a one-at-a-time Algorithm 3 makes them */
 } mwu_probe_info;
 
 mwu_status mwu_probe_sizes(void *s, mwu_sizes *out);
@@ -258,7 +266,8 @@ mwu_status mwu_probe_sizes(void *s, mwu_sizes *out);
  * point; NULL = the Algorithm 1 initial point eps / (n max_j P_ji). */
 mwu_status mwu_probe_begin(void *s, double param, const double *x0);
 
-/* Run up to max_iters iterations of Algorithm 2 (stops early on any outcome).
+/* Run max_iters more iterations of Algorithm 2 (fewer when the probe ends
+ * first); a running probe pauses after exactly max_iters accepted steps.
  * forced_alpha (host, nullable, n_forced entries): use these steps instead
  * of the search for the next n_forced iterations (decision replay).  While
  * the probe is still running on return, its last accepted step is applied
@@ -268,7 +277,11 @@ mwu_status mwu_probe_run(void *s, int32_t max_iters, const double *forced_alpha,
                          mwu_probe_info *info);
 
 /* Compute g, h, d, P d, C d at the current x (after applying a pending
- * accepted step, see mwu_probe_run) without taking a new step. */
+ * accepted step, see mwu_probe_run) without taking a new step.  The probe
+ * then waits at the step search of this iteration: a later mwu_probe_run
+ * continues there (first the stop tests of Algorithm 2 at this point), so
+ * running, forming a direction and running again takes the same steps as
+ * running alone.  MWU_ERR_STATE unless the probe is at an iteration start. */
 mwu_status mwu_probe_direction(void *s);
 
 /* Copy an internal vector to the host (double).  which: 0 x, 1 d, 2 g, 3 h,
@@ -280,7 +293,9 @@ mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
 
 /* Evaluate Psi(alpha_k), Phi(alpha_k) (Section 4.1) and min(Cx + alpha_k Cd)
  * at the current x and direction, for k < count (count <= 16).  Outputs are
- * host arrays of length count; zmin_new is nullable. */
+ * host arrays of length count; zmin_new is nullable.  Needs the direction of
+ * mwu_probe_direction (MWU_ERR_STATE otherwise); changes no vector, so a
+ * later mwu_probe_run continues as after mwu_probe_direction alone. */
 mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new);
 
@@ -290,11 +305,13 @@ mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, do
  * form it inside the search), 3 step-search pass over the exponential grid
  * (8 candidates from 1), 4 step-search pass over a bisection grid (15
  * candidates in [1, 2]), 5 the combined first pass of an iteration (the 8
- * exponential candidates and the 15 of the bisection of [2, 4]).  The kernel is launched reps times on the handle's
- * stream with the probe state frozen (after one direction at the current
- * point; the finisher kernel of the pass is not launched), timed with HIP
- * events;
- * the probe state is restored afterwards.  Outputs (host): average duration
+ * exponential candidates and the 15 of the bisection of [2, 4]).  First the
+ * pending accepted step is committed and one direction is formed at that
+ * point; then the kernel is launched reps times on the handle's stream with
+ * the probe state held (the finisher kernel of the pass is not launched),
+ * timed with HIP events.  Afterwards the probe continues from the committed
+ * point with a full iteration: the same iterate a run without the call
+ * reaches, its LSE totals renormalized by a row pass with no step.  Outputs (host): average duration
  * in microseconds, algorithmic HBM bytes of one launch (every index, dense
  * vector and output counted once; nullable) and the nonzeros the pass visits
  * (nullable).  Needs a probe at an iteration start (mwu_probe_begin). */

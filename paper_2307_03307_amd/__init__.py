@@ -17,13 +17,13 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib
-from ._lib import (CERTIFIED, COVERING, FEASIBLE_UNCERTIFIED, FP64, INFEASIBLE, MAX_ITER,
+from ._lib import (CERTIFIED, COVERING, FEASIBLE_POINT, FEASIBLE_UNCERTIFIED, FP64, INFEASIBLE, MAX_ITER,
                    MIXED, MIXED_FP32_FP64, PACKING, STEP_BIN, STEP_BIN_WARM, STEP_STD, MwuError)
 
 __all__ = ["Solver", "BatchSolver", "Result", "csr_matrix", "incidence", "incidence_t", "edge_pair",
            "interweave", "bmatch", "vertex_cover", "dominating_set", "densest_subgraph",
            "MwuError", "PACKING", "COVERING", "MIXED", "FP64", "MIXED_FP32_FP64", "STEP_BIN", "STEP_BIN_WARM",
-           "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER"]
+           "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER", "FEASIBLE_POINT"]
 
 VEC = {"x": 0, "d": 1, "g": 2, "h": 3, "y": 4, "z": 5, "dy": 6, "dz": 7, "alpha": 8}
 
@@ -96,6 +96,7 @@ class Result:
     probes: int
     max_violation: float
     seconds: float
+    evaluations: int = 0
 
     @property
     def certified(self) -> bool:
@@ -153,7 +154,7 @@ class Solver:
                                      ctypes.byref(info)), "mwu_solve")
         return Result(x, info.objective, info.status, info.lower_bound, info.upper_bound,
                       info.total_iterations, info.final_probe_iterations, info.search_passes,
-                      info.probes, info.max_violation, info.seconds_solve)
+                      info.probes, info.max_violation, info.seconds_solve, info.evaluations)
 
     # ---- probe-level access -------------------------------------------------
     def sizes(self) -> _lib.Sizes:
@@ -299,7 +300,8 @@ class BatchSolver:
             r = info[k]
             out.append(Result(x[off:off + ne].copy(), r.objective, r.status, r.lower_bound,
                               r.upper_bound, r.total_iterations, r.final_probe_iterations,
-                              r.search_passes, r.probes, r.max_violation, r.seconds_solve))
+                              r.search_passes, r.probes, r.max_violation, r.seconds_solve,
+                              r.evaluations))
             off += ne
         return out
 

@@ -15,7 +15,7 @@ ERRORS = {
     -8: "MWU_ERR_DEVICE", -9: "MWU_ERR_UNBOUNDED", -10: "MWU_ERR_STATE",
 }
 # outcomes
-CERTIFIED, FEASIBLE_UNCERTIFIED, INFEASIBLE, MAX_ITER = 0, 1, 2, 3
+CERTIFIED, FEASIBLE_UNCERTIFIED, INFEASIBLE, MAX_ITER, FEASIBLE_POINT = 0, 1, 2, 3, 4
 PROBE_RUNNING, PROBE_FEASIBLE, PROBE_INFEASIBLE, PROBE_MAX_ITER = 0, 1, 2, 3
 PACKING, COVERING, MIXED = 0, 1, 2
 MAT_CSR, MAT_INCIDENCE, MAT_INCIDENCE_T, MAT_EDGE_PAIR, MAT_INTERWEAVE = 0, 1, 2, 3, 4
@@ -73,7 +73,8 @@ class ResultInfo(ctypes.Structure):
                 ("lower_bound", ctypes.c_double), ("upper_bound", ctypes.c_double),
                 ("total_iterations", ctypes.c_int64), ("final_probe_iterations", ctypes.c_int64),
                 ("search_passes", ctypes.c_int64), ("probes", ctypes.c_int64),
-                ("max_violation", ctypes.c_double), ("seconds_solve", ctypes.c_double)]
+                ("max_violation", ctypes.c_double), ("seconds_solve", ctypes.c_double),
+                ("evaluations", ctypes.c_int64)]
 
 
 class Sizes(ctypes.Structure):
@@ -85,7 +86,8 @@ class ProbeInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("search_passes", ctypes.c_int64), ("alpha", ctypes.c_double),
                 ("L_P", ctypes.c_double), ("L_C", ctypes.c_double),
-                ("pack_bound", ctypes.c_double), ("cover_bound", ctypes.c_double)]
+                ("pack_bound", ctypes.c_double), ("cover_bound", ctypes.c_double),
+                ("evaluations", ctypes.c_int64)]
 
 
 _lib = None

@@ -11,10 +11,14 @@
 //
 // The direction compares g_i with h_i.  In FP32 both weights of a variable
 // whose edge is well covered and whose vertex is lightly loaded underflow, so
-// the ratio is formed in the log domain from y_v and z_e in FP64:
+// the chosen form forms the ratio in the log domain from y_v and z_e:
 // g_i / h_i = exp(eta (y_v - L_P) + eta (z_e - L_C) + ln(sP / sC)), with L_P and
-// L_C the LSE totals of the current point.
-// FP64 keeps the plain ratio of the stored weights, as the definition reads.
+// L_C the LSE totals of the current point, and q = 1 - g_i / h_i by an FP64
+// expm1.  FP64 keeps the plain ratio of the stored weights, as the definition
+// reads.  In both forms x, d, y, z, Pd and Cd are FP64: with single-weight
+// rows and steps up to ~1e5, a relative perturbation of 1e-7 in any of them
+// (FP32 storage or an FP32 expm1) grows to 1e-5..1e-2 in the objective of a
+// probe, so only the weights and the search terms are stored in T.
 #include <algorithm>
 
 #include "device_common.h"
@@ -34,18 +38,18 @@ __global__ __launch_bounds__(BLOCK) void dn_init_x(DnDev<T> dd, Ctl *ctl, int ha
     const double eps = ctl->eps, sP = ctl->sP;
     double v[1] = {0.0};
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += gridDim.x * BLOCK) {
-        T x;
+        double x;
         if (src) {
-            x = (T)src[i];
+            x = src[i];
             dd.x[i] = x;
         } else if (!have_x0) {
-            x = (T)(eps / ((double)dd.n * sP));   // Algorithm 1: eps / (n max_j P_ji), P_ji = sP
+            x = eps / ((double)dd.n * sP);   // Algorithm 1: eps / (n max_j P_ji), P_ji = sP
             dd.x[i] = x;
         } else {
             x = dd.x[i];
         }
-        dd.d[i] = T(0);
-        v[0] += (double)x;
+        dd.d[i] = 0.0;
+        v[0] += x;
     }
     const Red red{1, 0, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
@@ -67,26 +71,26 @@ __global__ __launch_bounds__(BLOCK) void dn_init_x_fin(Ctl *ctl, const double *p
 template <class T, bool INIT>
 __global__ __launch_bounds__(BLOCK) void dn_fwd_v(DnDev<T> dd, Ctl *ctl, double *part)
 {
-    __shared__ T s_acc[TILE_LDS];
+    __shared__ double s_acc[TILE_LDS];
     __shared__ int32_t s_ptr[TILE_NZ + 1];
-    __shared__ T s_tacc[BLOCK / 64];
+    __shared__ double s_tacc[BLOCK / 64];
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
     if (!INIT && ctl->phase != PH_FWD) return;
-    const T *src = INIT ? dd.x : dd.d;
-    const T sP = (T)ctl->sP;
+    const double *src = INIT ? dd.x : dd.d;
+    const double sP = ctl->sP;
     double v[1] = {-INFINITY};
-    auto elem = [&](int k) -> T { return src[dd.vvar[k]]; };
-    auto epi = [&](int r, T acc) {
+    auto elem = [&](int k) -> double { return src[dd.vvar[k]]; };
+    auto epi = [&](int r, double acc) {
         acc = sP * acc;
-        if (INIT) { dd.y[r] = (double)acc; dd.dy[r] = T(0); }
+        if (INIT) { dd.y[r] = acc; dd.dy[r] = 0.0; }
         else dd.dy[r] = acc;
-        v[0] = fmax(v[0], (double)acc);
+        v[0] = fmax(v[0], acc);
     };
     for (int t = blockIdx.x; t < dd.nvtiles; t += gridDim.x) {
         const Tile tl = dd.vtiles[t];
-        if (tl.lid < 0) seg_tile<T>(tl, dd.vptr, elem, epi, s_acc, s_ptr, nullptr, nullptr);
-        else chunk_tile<T>(tl, elem, s_tacc, dd.lpart, dd.vlong.lfirst);
+        if (tl.lid < 0) seg_tile<double>(tl, dd.vptr, elem, epi, s_acc, s_ptr, nullptr, nullptr);
+        else chunk_tile<double>(tl, elem, s_tacc, dd.lpart, dd.vlong.lfirst);
     }
     const Red red{0, 0, 1};
     block_combine<1>(v, red, 0, s_wave, s_rec);
@@ -100,20 +104,19 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_e(DnDev<T> dd, Ctl *ctl, double 
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
     if (!INIT && ctl->phase != PH_FWD) return;
-    const T *src = INIT ? dd.x : dd.d;
-    const T sC = (T)ctl->sC;
+    const double *src = INIT ? dd.x : dd.d;
+    const double sC = ctl->sC;
     double v[1] = {INFINITY};
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK) {
+        const double2 pr = reinterpret_cast<const double2 *>(src)[e];
+        const double val = sC * (pr.x + pr.y);
         if (INIT) {
-            const double val = (double)sC * ((double)src[2 * e] + (double)src[2 * e + 1]);
             dd.z[e] = val;
-            dd.dz[e] = T(0);
-            v[0] = fmin(v[0], val);
+            dd.dz[e] = 0.0;
         } else {
-            const T val = sC * (src[2 * e] + src[2 * e + 1]);
             dd.dz[e] = val;
-            v[0] = fmin(v[0], (double)val);
         }
+        v[0] = fmin(v[0], val);
     }
     const Red red{0, 1, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
@@ -127,14 +130,14 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_fin(DnDev<T> dd, Ctl *ctl, const
     __shared__ double s_wave[4];
     __shared__ double s_a[QMAX], s_b[QMAX], s_l[QMAX];
     if (!INIT && ctl->phase != PH_FWD) return;
-    const T sP = (T)ctl->sP;
+    const double sP = ctl->sP;
     double lv[1] = {-INFINITY};
     for (int l = threadIdx.x; l < dd.vlong.nlong; l += BLOCK) {
-        const T acc = sP * long_sum<T>(l, dd.lpart, dd.vlong.lfirst, dd.vlong.lcount);
+        const double acc = sP * long_sum<double>(l, dd.lpart, dd.vlong.lfirst, dd.vlong.lcount);
         const int r = dd.vlong.lseg[l];
-        if (INIT) { dd.y[r] = (double)acc; dd.dy[r] = T(0); }
+        if (INIT) { dd.y[r] = acc; dd.dy[r] = 0.0; }
         else dd.dy[r] = acc;
-        lv[0] = fmax(lv[0], (double)acc);
+        lv[0] = fmax(lv[0], acc);
     }
     const Red rmax{0, 0, 1}, rmin{0, 1, 0};
     block_combine<1>(lv, rmax, 0, s_wave, s_l);
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(BLOCK) void dn_row(DnDev<T> dd, Ctl *ctl, double *p
     double v[4] = {0.0, 0.0, INFINITY, -INFINITY};
     const int stride = gridDim.x * BLOCK;
     for (int r = blockIdx.x * BLOCK + threadIdx.x; r < dd.nv; r += stride) {
-        const double y = dd.y[r] + a * (double)dd.dy[r];
+        const double y = dd.y[r] + a * dd.dy[r];
         dd.y[r] = y;
         const T w = exp_arg(eta * (y - LP), T(0));
         dd.w[r] = w;
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void dn_row(DnDev<T> dd, Ctl *ctl, double *p
         v[3] = fmax(v[3], y);
     }
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
-        const double z = dd.z[e] + a * (double)dd.dz[e];
+        const double z = dd.z[e] + a * dd.dz[e];
         dd.z[e] = z;
         const T u = exp_arg(-eta * (z - LC), T(0));
         dd.u[e] = u;
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     __shared__ double s_rec[QMAX];
     const int ph = ctl->phase;
     if (ph != PH_COL && ph != PH_COMMIT) return;
-    const T a = (T)ctl->alpha;
+    const double a = ctl->alpha;
     const int stride = gridDim.x * BLOCK;
     if (ph == PH_COMMIT) {
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += stride) dd.x[i] = dd.x[i] + a * dd.d[i];
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += stride) {
         const int e = i >> 1;
         const int r = (i & 1) ? dd.ev[e] : dd.eu[e];
-        const T x = dd.x[i] + a * dd.d[i];
+        const double x = dd.x[i] + a * dd.d[i];
         dd.x[i] = x;
         // g and h from the stored weights: the FP64 direction and the
         // certificates; the FP32 direction needs only y and z (below), and the
@@ -235,20 +238,17 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
         if (sizeof(T) == 4) {
             // log-domain ratio: no underflow of the FP32 weights, and
             // q = 1 - g/h = -expm1(ln(g/h)) without cancellation near g = h
-            // (FP32 expm1 of the FP64 log ratio: ~1e-7 relative in q, the
-            // precision the FP32 direction is stored in)
             const double lr = eta * (dd.y[r] - LP) + eta * (dd.z[e] - LC) + lnK;
-            q = -(double)expm1_t((float)fmin(lr, 80.0));
+            q = -expm1(fmin(lr, 80.0));
         } else {
             q = h > 0.0 ? 1.0 - g / h : 0.0;
         }
         double di = 0.0;
-        if (q > qmin) di = step * q * (double)x;
-        const T dt = (T)di;
-        dd.d[i] = dt;
-        v[0] += (double)dt;
+        if (q > qmin) di = step * q * x;
+        dd.d[i] = di;
+        v[0] += di;
         v[1] = fmin(v[1], g);
-        v[2] = fmax(v[2], (double)dt);
+        v[2] = fmax(v[2], di);
         v[3] = fmax(v[3], h);
         if (dd.g_dbg) { dd.g_dbg[i] = g; dd.h_dbg[i] = h; }
     }
@@ -289,7 +289,7 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
         for (int r = r0; r < dd.nv; r += stride)
-            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], dd.dy[r], dymax, shm, s1);
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], (T)dd.dy[r], dymax, shm, s1);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }
@@ -297,7 +297,7 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
         CovAcc<T, double> ca;
         ca.init(pass_minima<KIND>());
         for (int e = r0; e < dd.ne; e += stride)
-            cov_terms<T, KIND, double>(nc, cand, a0, ga0, gdel, eta, dd.u[e], dd.z[e], dd.dz[e], ca.acc,
+            cov_terms<T, KIND, double>(nc, cand, a0, ga0, gdel, eta, dd.u[e], dd.z[e], (T)dd.dz[e], ca.acc,
                                        ca.zmn);
         ca.combine(s_wave, s_rec + KC);
     }
@@ -318,17 +318,17 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
         if (ctl->ref_valid == 0) {   // [min z' | max eta y']
             v[0] = INFINITY;
             v[1] = -INFINITY;
-            for (int r = r0; r < dd.nv; r += stride) v[1] = fmax(v[1], eta * (dd.y[r] + a * (double)dd.dy[r]));
-            for (int e = r0; e < dd.ne; e += stride) v[0] = fmin(v[0], dd.z[e] + a * (double)dd.dz[e]);
+            for (int r = r0; r < dd.nv; r += stride) v[1] = fmax(v[1], eta * (dd.y[r] + a * dd.dy[r]));
+            for (int e = r0; e < dd.ne; e += stride) v[0] = fmin(v[0], dd.z[e] + a * dd.dz[e]);
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
         } else {                     // [sum over packing rows | sum over covering rows]
             const double pm = ctl->rfPm, zm = ctl->rfZmin;
             v[0] = 0.0;
             v[1] = 0.0;
-            for (int r = r0; r < dd.nv; r += stride) v[0] += exp(eta * (dd.y[r] + a * (double)dd.dy[r]) - pm);
+            for (int r = r0; r < dd.nv; r += stride) v[0] += exp(eta * (dd.y[r] + a * dd.dy[r]) - pm);
             for (int e = r0; e < dd.ne; e += stride)
-                v[1] += exp(-eta * ((dd.z[e] + a * (double)dd.dz[e]) - zm));
+                v[1] += exp(-eta * ((dd.z[e] + a * dd.dz[e]) - zm));
             const Red red{2, 0, 0};
             block_combine<2>(v, red, 0, s_wave, s_rec);
         }
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void dn_stats_v(DnDev<T> dd, double *part)
     __shared__ double s_wave[4];
     __shared__ double s_rec[QMAX];
     double v[1] = {-INFINITY};
-    auto elem = [&](int k) -> double { return (double)dd.x[dd.vvar[k]]; };
+    auto elem = [&](int k) -> double { return dd.x[dd.vvar[k]]; };
     auto epi = [&](int, double acc) { v[0] = fmax(v[0], acc); };
     for (int t = blockIdx.x; t < dd.nvtiles; t += gridDim.x) {
         const Tile tl = dd.vtiles[t];
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(BLOCK) void dn_stats_e(DnDev<T> dd, double *part)
     __shared__ double s_rec[QMAX];
     double v[1] = {INFINITY};
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK)
-        v[0] = fmin(v[0], (double)dd.x[2 * e] + (double)dd.x[2 * e + 1]);
+        v[0] = fmin(v[0], dd.x[2 * e] + dd.x[2 * e + 1]);
     const Red red{0, 1, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
     store_record(s_rec, 1, part);

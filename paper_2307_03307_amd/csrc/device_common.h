@@ -851,7 +851,9 @@ MWU_DEV void accept_step(Ctl *c, double a, double psi, double phi)
     c->amode = AM_EXP;
     c->have_cur = 0;
     c->ref_valid = 0;
-    c->phase = PH_ROW;
+    // the step is pending: the next row pass applies it (the probe API may
+    // stop here after a given number of iterations and resume later)
+    c->phase = (c->iter_stop > 0 && c->iter >= c->iter_stop) ? PH_IDLE : PH_ROW;
 }
 
 MWU_DEV void stop_infeasible(Ctl *c)

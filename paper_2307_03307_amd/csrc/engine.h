@@ -1,5 +1,5 @@
-// Internal definitions shared by the host driver (solver.cpp) and the gfx950
-// kernels (kernels.hip).  Not part of the public C ABI.
+// Internal definitions shared by the host driver (solver.cpp and the
+// program_*.cpp files) and the gfx950 kernels (the .hip files).  Not part of the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -70,7 +70,8 @@ struct Ctl {
     int32_t step_rule, max_iter;
     int32_t n_forced, forced_pos;
     int32_t eval_mode, ev_cur;
-    int32_t hold, pad4;         // nonzero: finishers keep this phase and change nothing (timing)
+    int32_t hold;               // nonzero: finishers keep this phase and change nothing (timing)
+    int32_t iter_stop;          // > 0: a probe pauses (PH_IDLE, still running) once iter reaches it
     // ---- status
     int32_t status, phase, iter, pad1;
     int64_t search_passes, evaluations;
@@ -186,9 +187,11 @@ struct VcDev {
 
 // Fused densest-subgraph program: variables z_{2e}, z_{2e+1} are the two ends
 // of edge e; vertex rows (packing, scaled by 1/D) are segmented sums over
-// vptr/vvar, edge rows (covering) are pairs.  The row values y, z are kept in
-// FP64 in both forms: every variable sees one weight on each side, so the
-// exponents eta (y - L) must not carry storage rounding.
+// vptr/vvar, edge rows (covering) are pairs.  Every variable lies in one row
+// of each side, so g_i and h_i are single weights and nothing averages the
+// rounding of the direction out: the iterate x, the direction d, the rows y,
+// z and the products Pd, Cd are FP64 in both forms.  T is the type of the
+// stored weights w, u and of the search terms built from them.
 template <class T>
 struct DnDev {
     int32_t nv, ne, n;                    // non-isolated vertices, edges, variables (2 ne)
@@ -196,14 +199,16 @@ struct DnDev {
     const Tile *vtiles;
     int32_t nvtiles;
     LongSegs vlong;
-    T *lpart;
-    double *lpart64;
+    double *lpart;                        // chunk partials of the forward products
+    double *lpart64;                      // chunk partials of the statistics
     const int32_t *eu, *ev;               // vertex rows of variables 2e and 2e+1
-    T *x, *d;                             // variables
-    double *y;                            // vertex rows (scaled by sP), FP64 in both forms
-    T *dy, *w;
-    double *z;                            // edge rows, FP64 in both forms
-    T *dz, *u;
+    double *x, *d;                        // variables
+    double *y;                            // vertex rows (scaled by sP)
+    double *dy;
+    T *w;
+    double *z;                            // edge rows
+    double *dz;
+    T *u;
     double *g_dbg, *h_dbg;                // nullable
     const double *forced;
 };
@@ -309,6 +314,10 @@ template <class T> void widen(const T *src, double *dst, int64_t n, hipStream_t 
 template <class T> void narrow(const double *src, T *dst, int64_t n, hipStream_t st);
 // Set ctl->phase (single thread).
 void set_phase(Ctl *ctl, int phase, hipStream_t st);
+// Continue a probe whose direction was formed in evaluation mode: the stop
+// tests of the iteration, then its step search (forced: the program's forced
+// steps, nullable).
+void resume_search(Ctl *ctl, const double *forced, hipStream_t st);
 
 struct VcLaunch {
     int grid_v;        // element-wise over vertices

@@ -450,6 +450,23 @@ __global__ void k_narrow(const double *src, T *dst, int64_t n)
 
 __global__ void k_set_phase(Ctl *ctl, int phase) { ctl->phase = phase; }
 
+// Continue a probe after a direction formed in evaluation mode (the probe
+// API): the checks of Algorithm 2 that evaluation mode skipped (covered,
+// iteration cap, zero direction), then the step search of this iteration,
+// exactly as the finishers of an uninterrupted iteration would start it.
+__global__ void k_resume_search(Ctl *c, const double *forced)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    c->eval_mode = 0;
+    c->hold = 0;
+    c->ev_cached = 0;
+    c->alpha = 0.0;
+    if (c->zmin >= 1.0) { c->status = ST_FEASIBLE; c->phase = PH_DONE; return; }
+    if (c->iter >= c->max_iter) { c->status = ST_MAX_ITER; c->phase = PH_DONE; return; }
+    if (!(c->dmax > 0.0)) { c->status = ST_INFEASIBLE; c->phase = PH_DONE; return; }
+    begin_search(c, forced);
+}
+
 __global__ void k_potential_finish(const double *g, const double *h, int n, double scale,
                                    double *out, const Ctl *ctl, double *val)
 {
@@ -571,6 +588,11 @@ void narrow(const double *src, T *dst, int64_t n, hipStream_t st)
 void set_phase(Ctl *ctl, int phase, hipStream_t st)
 {
     hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(1), 0, st, ctl, phase);
+}
+
+void resume_search(Ctl *ctl, const double *forced, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resume_search, dim3(1), dim3(64), 0, st, ctl, forced);
 }
 
 // The main kernel of one pass alone (no finisher): timing of held passes.

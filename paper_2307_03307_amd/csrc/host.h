@@ -86,6 +86,9 @@ struct Program {
                            hipStream_t st) = 0;
     virtual void set_debug(bool on) = 0;
     virtual void set_forced(const double *host, int count) = 0;
+    // Continue the probe after a direction formed in evaluation mode
+    // (mwu_probe_direction): its stop tests, then the step search.
+    virtual void resume_search() = 0;
     // Algorithmic HBM bytes of one launch of a pass (0 row/transpose, 1 column/direction,
     // 2 forward, 3 search): every index once, every dense vector once, every output once.
     virtual double algo_bytes(int which) const = 0;
@@ -150,6 +153,7 @@ struct Solver {
     hipGraphExec_t graph = nullptr;
     int graph_slots = 0;
     bool in_probe = false;
+    bool dir_pending = false;        // a direction was formed in evaluation mode: resume at its search
     double probe_param = 0.0;
     ~Solver();
 };

@@ -23,7 +23,7 @@ struct Inst {
     double lo0 = 0, hi0 = 0;                  // starting bracket
     double lo = 0, hi = 0, slo = 0, shi = 0, eps_probe = 0, param = 0;
     int halvings = 0, probes = 0, serial = 0;
-    int64_t iters = 0, passes = 0, final_iters = 0;
+    int64_t iters = 0, passes = 0, final_iters = 0, evals = 0;
     bool done = false, have_best = false, failed = false;
     double best_scale = 1.0, x_start_scale = 1.0, max_violation = 0.0;
 };
@@ -232,6 +232,7 @@ class BatchMatching : public BatchProgram {
                 r.probes = I.probes;
                 r.max_violation = I.max_violation;
                 r.seconds_solve = secs;
+                r.evaluations = I.evals;
             }
         }
         if (iters_out) *iters_out = total;
@@ -299,7 +300,7 @@ class BatchMatching : public BatchProgram {
             Inst &I = inst_[k];
             I.lo = I.lo0; I.hi = I.hi0;
             I.slo = I.lo; I.shi = I.hi; I.eps_probe = s_.opt.eps; I.halvings = 0; I.probes = 0;
-            I.iters = I.passes = I.final_iters = 0;
+            I.iters = I.passes = I.final_iters = I.evals = 0;
             I.done = false; I.have_best = false; I.failed = false; I.best_scale = 1.0;
             I.max_violation = 0.0;
             if (!next_probe(k)) I.done = true;
@@ -504,6 +505,7 @@ class BatchMatching : public BatchProgram {
         I.iters += c.iter;
         I.final_iters = c.iter;
         I.passes += c.search_passes;
+        I.evals += c.evaluations;
         I.max_violation = std::max({0.0, c.ymax - 1.0, 1.0 - c.zmin});
         if (c.status == ST_NUMERIC) { I.failed = true; I.done = true; return; }
         if (c.pack_bound < I.hi) I.hi = c.pack_bound;

@@ -47,11 +47,12 @@ class DensestProgram : public Program {
         up(lseg_, vt.lseg.data(), vt.lseg.size() * 4);
         up(lfirst_, vt.lfirst.data(), vt.lfirst.size() * 4);
         up(lcount_, vt.lcount.data(), vt.lcount.size() * 4);
-        lpart_.alloc(std::max<int32_t>(vt.nslots, 1) * sizeof(T));
+        lpart_.alloc(std::max<int32_t>(vt.nslots, 1) * 8);
         lpart64_.alloc(std::max<int32_t>(vt.nslots, 1) * 8);
-        x_.alloc(n_ * sizeof(T)); d_.alloc(n_ * sizeof(T)); xbest_.alloc(n_ * sizeof(T));
-        y_.alloc(nv * 8); dy_.alloc(nv * sizeof(T)); w_.alloc(nv * sizeof(T));
-        z_.alloc(ne_ * 8); dz_.alloc(ne_ * sizeof(T)); u_.alloc(ne_ * sizeof(T));
+        // x, d, y, z, Pd, Cd in FP64 in both forms; the weights in T
+        x_.alloc(n_ * 8); d_.alloc(n_ * 8); xbest_.alloc(n_ * 8);
+        y_.alloc(nv * 8); dy_.alloc(nv * 8); w_.alloc(nv * sizeof(T));
+        z_.alloc(ne_ * 8); dz_.alloc(ne_ * 8); u_.alloc(ne_ * sizeof(T));
         HIP_OK(hipMemset(x_.p, 0, x_.bytes));
         HIP_OK(hipMemset(d_.p, 0, d_.bytes));
         partials_.alloc((size_t)GRID_MAX * QMAX * 8);
@@ -63,11 +64,11 @@ class DensestProgram : public Program {
         dd_.vtiles = vtiles_.as<Tile>(); dd_.nvtiles = (int32_t)vt.tiles.size();
         dd_.vlong = LongSegs{lseg_.as<int32_t>(), lfirst_.as<int32_t>(), lcount_.as<int32_t>(),
                              (int32_t)vt.lseg.size()};
-        dd_.lpart = lpart_.as<T>(); dd_.lpart64 = lpart64_.as<double>();
+        dd_.lpart = lpart_.as<double>(); dd_.lpart64 = lpart64_.as<double>();
         dd_.eu = eu_.as<int32_t>(); dd_.ev = ev_.as<int32_t>();
-        dd_.x = x_.as<T>(); dd_.d = d_.as<T>();
-        dd_.y = y_.as<double>(); dd_.dy = dy_.as<T>(); dd_.w = w_.as<T>();
-        dd_.z = z_.as<double>(); dd_.dz = dz_.as<T>(); dd_.u = u_.as<T>();
+        dd_.x = x_.as<double>(); dd_.d = d_.as<double>();
+        dd_.y = y_.as<double>(); dd_.dy = dy_.as<double>(); dd_.w = w_.as<T>();
+        dd_.z = z_.as<double>(); dd_.dz = dz_.as<double>(); dd_.u = u_.as<T>();
         dd_.g_dbg = nullptr; dd_.h_dbg = nullptr; dd_.forced = nullptr;
         int occ_v = 1, occ_s = 1;
         dn_occupancy<T>(&occ_v, &occ_s);
@@ -93,10 +94,7 @@ class DensestProgram : public Program {
 
     void upload_x(const double *host_x) override
     {
-        DevBuf tmp;
-        tmp.alloc(n_ * 8);
-        HIP_OK(hipMemcpyAsync(tmp.p, host_x, n_ * 8, hipMemcpyHostToDevice, s_.stream));
-        narrow<T>(tmp.as<double>(), dd_.x, n_, s_.stream);
+        HIP_OK(hipMemcpyAsync(dd_.x, host_x, n_ * 8, hipMemcpyHostToDevice, s_.stream));
         HIP_OK(hipStreamSynchronize(s_.stream));
     }
 
@@ -109,16 +107,16 @@ class DensestProgram : public Program {
 
     void save_best() override
     {
-        HIP_OK(hipMemcpyAsync(xbest_.p, x_.p, n_ * sizeof(T), hipMemcpyDeviceToDevice, s_.stream));
+        HIP_OK(hipMemcpyAsync(xbest_.p, x_.p, n_ * 8, hipMemcpyDeviceToDevice, s_.stream));
     }
 
-    void best_to_host(double *out) override { to_host(xbest_.as<T>(), n_, out); }
+    void best_to_host(double *out) override { copy_host(xbest_.as<double>(), n_, out); }
 
     void read(int which, double *out, int64_t len) override
     {
         switch (which) {
-        case 0: need(len, n_); to_host(dd_.x, n_, out); return;
-        case 1: need(len, n_); to_host(dd_.d, n_, out); return;
+        case 0: need(len, n_); copy_host(dd_.x, n_, out); return;
+        case 1: need(len, n_); copy_host(dd_.d, n_, out); return;
         case 2:
         case 3:
             need(len, n_);
@@ -128,9 +126,9 @@ class DensestProgram : public Program {
             HIP_OK(hipStreamSynchronize(s_.stream));
             return;
         case 4: need(len, nv_); copy_host(dd_.y, nv_, out); return;
-        case 6: need(len, nv_); to_host(dd_.dy, nv_, out); return;
+        case 6: need(len, nv_); copy_host(dd_.dy, nv_, out); return;
         case 5: need(len, ne_); copy_host(dd_.z, ne_, out); return;
-        case 7: need(len, ne_); to_host(dd_.dz, ne_, out); return;
+        case 7: need(len, ne_); copy_host(dd_.dz, ne_, out); return;
         }
         throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
     }
@@ -146,6 +144,8 @@ class DensestProgram : public Program {
         if (on && !dbg_g_.p) { dbg_g_.alloc(n_ * 8); dbg_h_.alloc(n_ * 8); }
         debug_ = on;
     }
+
+    void resume_search() override { mwu::resume_search(ctl(), dd_.forced, s_.stream); }
 
     void set_forced(const double *host, int count) override
     {
@@ -172,14 +172,20 @@ class DensestProgram : public Program {
                              grad_dev, ctl(), val_dev, st);
     }
 
+    // t: bytes of a stored weight; x, d, y, z, dy, dz are 8-byte values
     double algo_bytes(int which) const override
     {
         const double t = sizeof(T), V = (double)nv_, E = (double)ne_;
         switch (which) {
-        case 0: return (16.0 + 2.0 * t) * (V + E);                     // y rw, dy, w; z rw, dz, u
-        case 1: return 8.0 * E + 4.0 * t * 2.0 * E + 3.0 * t * V + 2.0 * t * E;   // eu, ev; x, d rw; w, y; u, z
-        case 2: return 4.0 * (V + 1) + 4.0 * 2.0 * E + 2.0 * t * 2.0 * E + t * V + t * E;
-        case 3: return 2.0 * t * V + 3.0 * t * E;
+        case 0: return (24.0 + t) * (V + E);                            // y rw, dy, w; z rw, dz, u
+        // eu, ev; x, d read and written (2E variables); y (V) and z (E) for
+        // the log-domain ratio, or the weights w (V) and u (E) in FP64
+        case 1: return 8.0 * E + 32.0 * 2.0 * E + 8.0 * (V + E);
+        // the vertex rows (the kernel timed for this pass): vptr, vvar, d
+        // gathered, Pd written; the edge rows (d read, Cd written) are a
+        // separate kernel of 24E bytes
+        case 2: return 4.0 * (V + 1) + 4.0 * 2.0 * E + 8.0 * 2.0 * E + 8.0 * V;
+        case 3: return (t + 8.0) * V + (t + 16.0) * E;                  // w, dy; u, z, dz
         }
         return 0.0;
     }
@@ -246,15 +252,6 @@ class DensestProgram : public Program {
     {
         if (len != want) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
     }
-    void to_host(const T *src, int64_t len, double *out)
-    {
-        DevBuf tmp;
-        tmp.alloc(std::max<int64_t>(len, 1) * 8);
-        widen<T>(src, tmp.as<double>(), len, s_.stream);
-        HIP_OK(hipMemcpyAsync(out, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
-        HIP_OK(hipStreamSynchronize(s_.stream));
-    }
-
     void copy_host(const double *src, int64_t len, double *out)
     {
         HIP_OK(hipMemcpyAsync(out, src, len * 8, hipMemcpyDeviceToHost, s_.stream));

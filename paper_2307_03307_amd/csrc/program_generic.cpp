@@ -251,6 +251,8 @@ class GenericProgram : public Program {
         debug_ = on;
     }
 
+    void resume_search() override { mwu::resume_search(ctl(), gd_.forced, s_.stream); }
+
     void set_forced(const double *host, int count) override
     {
         if (count > 0) {

@@ -254,6 +254,8 @@ class VcoverProgram : public Program {
         debug_ = on;
     }
 
+    void resume_search() override { mwu::resume_search(ctl(), vd_.forced, s_.stream); }
+
     void set_forced(const double *host, int count) override
     {
         if (count > 0) {

@@ -463,6 +463,7 @@ static void begin_probe(Solver &s, double param, const double *x0, double eps_pr
     if (x0) s.prog->upload_x(x0);
     s.prog->probe_init(x0 != nullptr);
     s.in_probe = true;
+    s.dir_pending = false;
     s.probe_param = param;
 }
 
@@ -488,11 +489,20 @@ static void run_probe(Solver &s, int64_t max_iters)
     const int64_t cap_launches = (max_iters + 4) * 8 / std::max(1, s.opt.iters_per_launch) + 16;
     for (int64_t l = 0; l < cap_launches; ++l) {
         if (s.ctl_host->phase == PH_DONE || s.ctl_host->status != ST_RUNNING) break;
+        if (s.ctl_host->phase == PH_IDLE) break;   // paused at the probe API's iteration stop
         if (s.ctl_host->iter - start >= max_iters) break;
         HIP_OK(hipGraphLaunch(s.graph, s.stream));
         pull_ctl(s);
         s.prog->between_launches(*s.ctl_host);
     }
+}
+
+// A probe paused by mwu_probe_run's iteration stop (a pending step, PH_IDLE)
+// continues at its next row pass.
+static void unpause(Solver &s)
+{
+    Ctl &c = *s.ctl_host;
+    if (!s.dir_pending && c.phase == PH_IDLE && c.status == ST_RUNNING) c.phase = PH_ROW;
 }
 
 static void finish_probe_stats(Solver &s)
@@ -527,7 +537,7 @@ static double level_set_density(const EdgeList &g, const std::vector<double> &sc
 struct SolveOut {
     int32_t status;
     double objective, lower, upper, best_scale;
-    int64_t probes, total_iters, final_iters, passes;
+    int64_t probes, total_iters, final_iters, passes, evals;
     double max_violation;
     bool have_best_dev;
 };
@@ -551,6 +561,7 @@ static SolveOut solve_impl(Solver &s)
         o.total_iters += c.iter;
         o.final_iters = c.iter;
         o.passes += c.search_passes;
+        o.evals += c.evaluations;
         return c;
     };
     if (s.form == MWU_MIXED && s.opt.mixed_fixed_lambda > 0.0) {
@@ -558,13 +569,18 @@ static SolveOut solve_impl(Solver &s)
         Ctl c = probe_done(lam);
         finish_probe_stats(s);
         const Ctl f = *s.ctl_host;
+        // x_out, objective_out and max_violation all describe the probe's
+        // final point x (not rescaled): objective = lambda(x) = max_i (P x)_i
+        // in the caller's scale, and with C x >= 1 at a feasible stop it
+        // bounds the least lambda from above
         s.prog->save_best();
         o.have_best_dev = true;
         o.best_scale = 1.0;
-        o.status = c.status == ST_FEASIBLE ? MWU_CERTIFIED
+        o.status = c.status == ST_FEASIBLE ? MWU_FEASIBLE_POINT
                    : c.status == ST_INFEASIBLE ? MWU_INFEASIBLE : MWU_MAX_ITER;
-        o.objective = (f.ymax / f.sP) / f.zmin;
-        o.lower = c.status == ST_INFEASIBLE ? lam : 0.0;
+        o.objective = f.ymax / f.sP;
+        const double cf = s.fp32 ? 1.0 - kMixedQmin : 1.0;
+        o.lower = c.status == ST_INFEASIBLE ? lam * cf : 0.0;
         o.upper = c.status == ST_FEASIBLE ? o.objective : INFINITY;
         o.max_violation = std::max({0.0, f.ymax - 1.0, 1.0 - f.zmin});
         return o;
@@ -799,6 +815,7 @@ mwu_status mwu_solve(void *h, double *x_out, double *objective_out, int64_t *ite
             info->probes = o.probes;
             info->max_violation = o.max_violation;
             info->seconds_solve = secs;
+            info->evaluations = o.evals;
         }
         s.in_probe = false;
     });
@@ -840,6 +857,7 @@ static void fill_probe_info(const Ctl &c, mwu_probe_info *info)
     info->L_C = c.LC;
     info->pack_bound = c.pack_bound;
     info->cover_bound = c.cover_bound;
+    info->evaluations = c.evaluations;
 }
 
 mwu_status mwu_probe_run(void *h, int32_t max_iters, const double *forced_alpha, int32_t n_forced,
@@ -861,7 +879,17 @@ mwu_status mwu_probe_run(void *h, int32_t max_iters, const double *forced_alpha,
             s.ctl_host->n_forced = 0;
         }
         s.ctl_host->eval_mode = 0;
+        // pause after exactly max_iters more accepted steps
+        s.ctl_host->iter_stop = (int32_t)std::min<int64_t>((int64_t)s.ctl_host->iter + std::max(1, max_iters),
+                                                           INT32_MAX - 1);
+        unpause(s);
         push_ctl(s);
+        if (s.dir_pending) {
+            // the direction of this iteration was formed by mwu_probe_direction:
+            // continue at its step search, as an uninterrupted iteration would
+            s.prog->resume_search();
+            s.dir_pending = false;
+        }
         run_probe(s, max_iters);
         pull_ctl(s);
         fill_probe_info(*s.ctl_host, info);
@@ -876,6 +904,7 @@ mwu_status mwu_probe_direction(void *h)
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
         pull_ctl(s);
+        unpause(s);
         if (s.ctl_host->phase != PH_ROW) throw ApiError{MWU_ERR_STATE, "probe is not at an iteration start"};
         s.ctl_host->eval_mode = 1;
         push_ctl(s);
@@ -884,10 +913,10 @@ mwu_status mwu_probe_direction(void *h)
         s.prog->col_pass();
         s.prog->fwd_pass();
         s.prog->set_debug(false);
-        pull_ctl(s);
-        s.ctl_host->eval_mode = 0;
-        push_ctl(s);
         HIP_OK(hipStreamSynchronize(s.stream));
+        // the pending step is committed and the direction formed; the device
+        // waits in PH_IDLE until mwu_probe_run resumes at the step search
+        s.dir_pending = true;
     });
 }
 
@@ -918,9 +947,9 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
     if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
+        if (!s.dir_pending) throw ApiError{MWU_ERR_STATE, "no direction formed (mwu_probe_direction)"};
         pull_ctl(s);
         Ctl &c = *s.ctl_host;
-        // the direction must have been computed (mwu_probe_direction)
         bool dbl = count == KE, ari = count == 15;
         for (int k = 1; k < count; ++k) {
             if (alphas[k] != 2.0 * alphas[k - 1]) dbl = false;
@@ -949,7 +978,9 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
             phi[k] = r.ev_phi[k];
             if (zmin_new) zmin_new[k] = r.ev_zmin[k];
         }
-        s.ctl_host->eval_mode = 0;
+        // the evaluations change no vector: the probe still waits at this
+        // iteration's step search (mwu_probe_run resumes there)
+        s.ctl_host->eval_mode = 1;
         s.ctl_host->phase = PH_IDLE;
         push_ctl(s);
         HIP_OK(hipStreamSynchronize(s.stream));
@@ -966,8 +997,8 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
     return run_guarded([&] {
         HIP_OK(hipSetDevice(s.opt.device));
         pull_ctl(s);
+        unpause(s);
         if (s.ctl_host->phase != PH_ROW) throw ApiError{MWU_ERR_STATE, "probe is not at an iteration start"};
-        const Ctl saved = *s.ctl_host;
         // one direction so that d, Pd, Cd are those of a real iteration
         s.ctl_host->eval_mode = 1;
         push_ctl(s);
@@ -975,6 +1006,8 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         s.prog->col_pass();
         s.prog->fwd_pass();
         pull_ctl(s);
+        // the pending step is committed now: the probe resumes from this point
+        Ctl resume = *s.ctl_host;
         Ctl &c = *s.ctl_host;
         c.eval_mode = 0;
         static const int phase_of[6] = {PH_ROW, PH_COL, PH_FWD, PH_SEARCH, PH_SEARCH, PH_SEARCH};
@@ -1019,8 +1052,16 @@ mwu_status mwu_time_pass(void *h, int32_t which, int32_t reps, double *avg_us, d
         *avg_us = 1000.0 * ms / reps;
         if (bytes) *bytes = s.prog->algo_bytes(which >= 4 ? 3 : which);
         if (nnz) *nnz = s.prog->pass_nnz(which >= 4 ? 3 : which);
-        *s.ctl_host = saved;   // the probe continues from where it was
+        // The held launches rewrote the weights and the direction at the
+        // committed point; the probe continues there with a full iteration
+        // (a row pass with no step renormalizes the LSE totals and weights).
+        resume.phase = PH_ROW;
+        resume.alpha = 0.0;
+        resume.hold = 0;
+        resume.eval_mode = 0;
+        *s.ctl_host = resume;
         push_ctl(s);
+        s.dir_pending = false;
         HIP_OK(hipStreamSynchronize(s.stream));
     });
 }
@@ -1038,6 +1079,7 @@ mwu_status mwu_potential_forward(void *h, const double *x_dev, double *value_out
         HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
         DevBuf val;
         val.alloc(8);
+        s.dir_pending = false;
         s.prog->potential(x_dev, val.as<double>(), 1.0, nullptr, st);
         HIP_OK(hipMemcpyAsync(value_out, val.p, 8, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
@@ -1057,6 +1099,7 @@ mwu_status mwu_potential_backward(void *h, const double *x_dev, double grad_scal
         pull_ctl(s);
         s.ctl_host->eval_mode = 2;
         HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        s.dir_pending = false;
         s.prog->potential(x_dev, nullptr, grad_scale, grad_dev, st);
         HIP_OK(hipStreamSynchronize(st));
         HIP_OK(hipMemcpy(s.ctl_host, s.ctl_buf.p, sizeof(Ctl), hipMemcpyDeviceToHost));

@@ -17,6 +17,7 @@ import pytest
 import graphgen as gg
 import oracle
 from gpu_common import EPS, rel_err
+import paper_2307_03307_amd as mwu
 
 pytestmark = pytest.mark.gpu
 
@@ -48,12 +49,14 @@ def genmatch_problem(g, cap):
     return make, P, C
 
 
+def rows(M, x):
+    out = np.zeros(M.rows)
+    oracle.lib().orc_matvec(M.c, 1.0, np.ascontiguousarray(x).ctypes.data, out.ctypes.data)
+    return out
+
+
 def violation(P, C, x):
-    y = np.zeros(P.rows)
-    z = np.zeros(C.rows)
-    oracle.lib().orc_matvec(P.c, 1.0, np.ascontiguousarray(x).ctypes.data, y.ctypes.data)
-    oracle.lib().orc_matvec(C.c, 1.0, np.ascontiguousarray(x).ctypes.data, z.ctypes.data)
-    return max(0.0, y.max() - 1.0, 1.0 - z.min())
+    return max(0.0, rows(P, x).max() - 1.0, 1.0 - rows(C, x).min())
 
 
 @pytest.fixture(scope="module")
@@ -91,13 +94,17 @@ def test_genmatch_fp64_follows_oracle(small):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_genmatch_solve(small, precision):
-    """The fixed-lambda solve in both forms: certified feasible, and the
-    returned x meets every bound within the reported max violation."""
+    """The fixed-lambda solve in both forms: a feasible verdict whose point
+    meets every bound within the reported max violation, and whose reported
+    objective is the lambda of that same point."""
     make, P, C = genmatch_problem(small, cap=60)
     with make(precision=precision) as s:
         r = s.solve()
     print(f"genmatch precision {precision}: status {r.status} iterations {r.total_iterations} "
           f"max violation {r.max_violation:.3g}")
-    assert r.certified
+    assert r.status == mwu.FEASIBLE_POINT
     assert r.max_violation <= EPS
     assert violation(P, C, r.x) <= r.max_violation * (1 + 1e-6) + 1e-9
+    assert rows(C, r.x).min() >= 1 - 1e-9
+    # lambda of the returned point: the largest packing row (P carries 1/u)
+    assert r.objective == pytest.approx(rows(P, r.x).max(), rel=1e-9)
