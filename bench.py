@@ -135,9 +135,9 @@ def dominant(passes, r, kernels, names, tag, workload):
 
 def cpu_baseline_densest(g, param, gpu_iters, gpu_evals):
     """The plain FP64 oracle on one host core, on a bounded sample of the same
-    workload: one and two iterations of a probe with the standard step (no
-    search) give the per-iteration cost of the passes; one iteration with
-    Algorithm 3 adds its evaluations of the test.  The GPU solve's iteration
+    workload: a probe set up with no iteration and one with one iteration of
+    the standard step (no search) give the per-iteration cost of the passes;
+    one iteration with Algorithm 3 adds its evaluations of the test.  The GPU solve's iteration
     and evaluation counts (the evaluations a one-at-a-time Algorithm 3 makes,
     counted on the device) scale the two costs."""
     import oracle
@@ -152,15 +152,15 @@ def cpu_baseline_densest(g, param, gpu_iters, gpu_evals):
         r = oracle.probe(O, sP, W, 1.0, 0.1, max_iter=iters, step_rule=rule)
         return time.perf_counter() - t, r
 
+    t0, _ = run(oracle.STEP_STD, 0)
     t1, _ = run(oracle.STEP_STD, 1)
-    t2, _ = run(oracle.STEP_STD, 2)
     tb, rb = run(oracle.STEP_BIN, 1)
-    per_iter = max(t2 - t1, 1e-9)
+    per_iter = max(t1 - t0, 1e-9)
     per_eval = max(tb - t1, 0.0) / max(1, rb.evaluations)
     est = per_iter * gpu_iters + per_eval * gpu_evals
     return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle (plain single-threaded FP64 C, gcc -O2) on the same graph and LP at D = {param:.6g}: "
-                       f"probes of 1 and 2 iterations with the standard step ({t1:.1f} s, {t2:.1f} s) and one "
+                       f"probes of 0 and 1 iterations with the standard step ({t0:.1f} s, {t1:.1f} s) and one "
                        f"iteration of Algorithm 3 ({tb:.1f} s, {rb.evaluations} evaluations); "
                        f"{per_iter:.2f} s per iteration x {gpu_iters} iterations + {per_eval:.2f} s per "
                        f"evaluation x {gpu_evals} evaluations of the GPU solve; explicit matrix build "

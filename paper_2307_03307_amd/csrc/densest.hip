@@ -15,10 +15,12 @@
 // g_i / h_i = exp(eta (y_v - L_P) + eta (z_e - L_C) + ln(sP / sC)), with L_P and
 // L_C the LSE totals of the current point, and q = 1 - g_i / h_i by an FP64
 // expm1.  FP64 keeps the plain ratio of the stored weights, as the definition
-// reads.  In both forms x, d, y, z, Pd and Cd are FP64: with single-weight
-// rows and steps up to ~1e5, a relative perturbation of 1e-7 in any of them
-// (FP32 storage or an FP32 expm1) grows to 1e-5..1e-2 in the objective of a
-// probe, so only the weights and the search terms are stored in T.
+// reads.  In both forms x, d, y, z, Pd, Cd, the weights as the row pass forms
+// them and their LSE totals are FP64: with single-weight rows and steps up to
+// ~1e5, a relative perturbation of 1e-7 in any of them (FP32 storage, an FP32
+// expm1, totals summed from FP32-rounded weights) grows to 1e-5..1e-2 in the
+// objective of a probe.  Only the stored weights that the step search reads
+// and the search terms are T.
 #include <algorithm>
 
 #include "device_common.h"
@@ -97,54 +99,76 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_v(DnDev<T> dd, Ctl *ctl, double 
     store_record(s_rec, 1, part);
 }
 
-// Edge rows: INIT z = sC (x_2e + x_2e+1) (clears dz), else dz.  Record [min].
+// Long vertex rows (more variables than one tile) from the chunk partials of
+// dn_fwd_v, one wave per long row, chunks summed lane-strided and folded in a
+// fixed order; INIT also forms the edge rows z = sC (x_2e + x_2e+1) (clearing
+// dz; in an iteration the column pass writes Cd).  Record [min z | max over
+// the long rows] (INIT) or [max over the long rows].
 template <class T, bool INIT>
 __global__ __launch_bounds__(BLOCK) void dn_fwd_e(DnDev<T> dd, Ctl *ctl, double *part)
 {
-    __shared__ double s_wave[4];
+    __shared__ double s_wave[4 * 2];
     __shared__ double s_rec[QMAX];
     if (!INIT && ctl->phase != PH_FWD) return;
-    const double *src = INIT ? dd.x : dd.d;
-    const double sC = ctl->sC;
-    double v[1] = {INFINITY};
-    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK) {
-        const double2 pr = reinterpret_cast<const double2 *>(src)[e];
-        const double val = sC * (pr.x + pr.y);
-        if (INIT) {
+    const double sP = ctl->sP;
+    double mn = INFINITY, mx = -INFINITY;
+    if (INIT) {
+        const double sC = ctl->sC;
+        for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK) {
+            const double2 pr = reinterpret_cast<const double2 *>(dd.x)[e];
+            const double val = sC * (pr.x + pr.y);
             dd.z[e] = val;
             dd.dz[e] = 0.0;
-        } else {
-            dd.dz[e] = val;
+            mn = fmin(mn, val);
         }
-        v[0] = fmin(v[0], val);
     }
-    const Red red{0, 1, 0};
-    block_combine<1>(v, red, 0, s_wave, s_rec);
-    store_record(s_rec, 1, part);
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (BLOCK / 64);
+    for (int l = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); l < dd.vlong.nlong; l += nwaves) {
+        const int f = dd.vlong.lfirst[l], c = dd.vlong.lcount[l];
+        double acc = 0.0;
+        for (int i = lane; i < c; i += 64) acc += dd.lpart[f + i];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+        acc = sP * acc;
+        if (lane == 0) {
+            const int r = dd.vlong.lseg[l];
+            if (INIT) { dd.y[r] = acc; dd.dy[r] = 0.0; }
+            else dd.dy[r] = acc;
+        }
+        mx = fmax(mx, acc);
+    }
+    if (INIT) {
+        double v[2] = {mn, mx};
+        const Red red{0, 1, 1};
+        block_combine<2>(v, red, 0, s_wave, s_rec);
+        store_record(s_rec, 2, part);
+    } else {
+        double v[1] = {mx};
+        const Red red{0, 0, 1};
+        block_combine<1>(v, red, 0, s_wave, s_rec);
+        store_record(s_rec, 1, part);
+    }
 }
 
 template <class T, bool INIT>
 __global__ __launch_bounds__(BLOCK) void dn_fwd_fin(DnDev<T> dd, Ctl *ctl, const double *pv, int Gv,
                                                      const double *pe, int Ge)
 {
-    __shared__ double s_wave[4];
-    __shared__ double s_a[QMAX], s_b[QMAX], s_l[QMAX];
+    __shared__ double s_wave[4 * 2];
+    __shared__ double s_a[QMAX], s_b[QMAX];
     if (!INIT && ctl->phase != PH_FWD) return;
-    const double sP = ctl->sP;
-    double lv[1] = {-INFINITY};
-    for (int l = threadIdx.x; l < dd.vlong.nlong; l += BLOCK) {
-        const double acc = sP * long_sum<double>(l, dd.lpart, dd.vlong.lfirst, dd.vlong.lcount);
-        const int r = dd.vlong.lseg[l];
-        if (INIT) { dd.y[r] = acc; dd.dy[r] = 0.0; }
-        else dd.dy[r] = acc;
-        lv[0] = fmax(lv[0], acc);
-    }
-    const Red rmax{0, 0, 1}, rmin{0, 1, 0};
-    block_combine<1>(lv, rmax, 0, s_wave, s_l);
+    const Red rmax{0, 0, 1};
     fold_records<1>(pv, Gv, rmax, 0, s_wave, s_a);
-    fold_records<1>(pe, Ge, rmin, 0, s_wave, s_b);
+    if (INIT) {
+        const Red rlast{0, 1, 1};
+        fold_records<2>(pe, Ge, rlast, 0, s_wave, s_b);
+    } else {
+        fold_records<1>(pe, Ge, rmax, 0, s_wave, s_b);
+    }
     on_ctl(ctl, [&](Ctl *c) {
-        double rec[2] = {s_b[0], fmax(s_a[0], s_l[0])};   // [min over C rows | max over P rows]
+        // [min over C rows | max over P rows]
+        double rec[2] = {INIT ? s_b[0] : 0.0, fmax(s_a[0], INIT ? s_b[1] : s_b[0])};
         if (INIT) {
             finish_init_fwd(c, rec);
         } else if (!held(c)) {
@@ -157,7 +181,9 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_fin(DnDev<T> dd, Ctl *ctl, const
 // ------------------------------------------------------------------ row pass
 
 // y += a dy, w = exp(eta (y - L_P)) over vertices; z += a dz, u = exp(-eta (z
-// - L_C)) over edges.  Record [sum w | sum u | min z | max y].
+// - L_C)) over edges.  Record [sum w | sum u | min z | max y].  The weights
+// are formed and summed in FP64 in both forms (the LSE totals they give enter
+// every log-domain ratio of the direction) and stored in T for the search.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void dn_row(DnDev<T> dd, Ctl *ctl, double *part)
 {
@@ -171,17 +197,17 @@ __global__ __launch_bounds__(BLOCK) void dn_row(DnDev<T> dd, Ctl *ctl, double *p
     for (int r = blockIdx.x * BLOCK + threadIdx.x; r < dd.nv; r += stride) {
         const double y = dd.y[r] + a * dd.dy[r];
         dd.y[r] = y;
-        const T w = exp_arg(eta * (y - LP), T(0));
-        dd.w[r] = w;
-        v[0] += (double)w;
+        const double w = exp(eta * (y - LP));
+        dd.w[r] = (T)w;
+        v[0] += w;
         v[3] = fmax(v[3], y);
     }
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
         const double z = dd.z[e] + a * dd.dz[e];
         dd.z[e] = z;
-        const T u = exp_arg(-eta * (z - LC), T(0));
-        dd.u[e] = u;
-        v[1] += (double)u;
+        const double u = exp(-eta * (z - LC));
+        dd.u[e] = (T)u;
+        v[1] += u;
         v[2] = fmin(v[2], z);
     }
     const Red red{2, 1, 1};
@@ -201,7 +227,9 @@ __global__ __launch_bounds__(BLOCK) void dn_row_fin(Ctl *ctl, const double *part
 
 // ------------------------------------------------------------------ column pass
 
-// Commit x += a d, then g, h and the direction of every variable.  Record
+// Commit x += a d, then g, h and the direction of every variable, and the
+// edge rows of the direction Cd = sC (d_2e + d_2e+1).  One thread per edge
+// takes its two variables (16-byte loads and stores of the pairs).  Record
 // [sum d | min g | max d | max h].  In PH_COMMIT only the commit.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *part)
@@ -212,8 +240,13 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     if (ph != PH_COL && ph != PH_COMMIT) return;
     const double a = ctl->alpha;
     const int stride = gridDim.x * BLOCK;
+    double2 *x2 = reinterpret_cast<double2 *>(dd.x);
+    double2 *d2 = reinterpret_cast<double2 *>(dd.d);
     if (ph == PH_COMMIT) {
-        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += stride) dd.x[i] = dd.x[i] + a * dd.d[i];
+        for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
+            const double2 xv = x2[e], dv = d2[e];
+            x2[e] = make_double2(xv.x + a * dv.x, xv.y + a * dv.y);
+        }
         return;
     }
     const double sP = ctl->sP, sC = ctl->sC, invSw = ctl->invSw, invSu = ctl->invSu;
@@ -221,36 +254,43 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     // after the row pass L_P and L_C are the exact LSE totals: the normalized
     // weights are exp(eta (y - L_P)) and exp(-eta (z - L_C))
     const double lnK = log(sP / sC);
+    // g and h from the stored weights: the FP64 direction and the
+    // certificates; the FP32 direction needs only y and z, and the densest
+    // outer search uses no weak-duality bound, so FP32 skips them unless they
+    // are being recorded
+    const bool need_gh = sizeof(T) == 8 || dd.g_dbg != nullptr;
     double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += stride) {
-        const int e = i >> 1;
-        const int r = (i & 1) ? dd.ev[e] : dd.eu[e];
-        const double x = dd.x[i] + a * dd.d[i];
-        dd.x[i] = x;
-        // g and h from the stored weights: the FP64 direction and the
-        // certificates; the FP32 direction needs only y and z (below), and the
-        // densest outer search uses no weak-duality bound, so FP32 skips them
-        // unless they are being recorded
-        const bool need_gh = sizeof(T) == 8 || dd.g_dbg != nullptr;
-        const double g = need_gh ? sP * (double)dd.w[r] * invSw : INFINITY;
+    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
+        const int ru = dd.eu[e], rv = dd.ev[e];
+        const double2 xv = x2[e], dv = d2[e];
+        const double xs[2] = {xv.x + a * dv.x, xv.y + a * dv.y};
         const double h = need_gh ? sC * (double)dd.u[e] * invSu : -INFINITY;
-        double q;
-        if (sizeof(T) == 4) {
-            // log-domain ratio: no underflow of the FP32 weights, and
-            // q = 1 - g/h = -expm1(ln(g/h)) without cancellation near g = h
-            const double lr = eta * (dd.y[r] - LP) + eta * (dd.z[e] - LC) + lnK;
-            q = -expm1(fmin(lr, 80.0));
-        } else {
-            q = h > 0.0 ? 1.0 - g / h : 0.0;
+        const double ze = sizeof(T) == 4 ? dd.z[e] : 0.0;
+        double ds[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = k ? rv : ru;
+            const double g = need_gh ? sP * (double)dd.w[r] * invSw : INFINITY;
+            double q;
+            if (sizeof(T) == 4) {
+                // log-domain ratio: no underflow of the FP32 weights, and
+                // q = 1 - g/h = -expm1(ln(g/h)) without cancellation near g = h
+                const double lr = eta * (dd.y[r] - LP) + eta * (ze - LC) + lnK;
+                q = -expm1(fmin(lr, 80.0));
+            } else {
+                q = h > 0.0 ? 1.0 - g / h : 0.0;
+            }
+            const double di = q > qmin ? step * q * xs[k] : 0.0;
+            ds[k] = di;
+            v[0] += di;
+            v[1] = fmin(v[1], g);
+            v[2] = fmax(v[2], di);
+            if (dd.g_dbg) { dd.g_dbg[2 * e + k] = g; dd.h_dbg[2 * e + k] = h; }
         }
-        double di = 0.0;
-        if (q > qmin) di = step * q * x;
-        dd.d[i] = di;
-        v[0] += di;
-        v[1] = fmin(v[1], g);
-        v[2] = fmax(v[2], di);
         v[3] = fmax(v[3], h);
-        if (dd.g_dbg) { dd.g_dbg[i] = g; dd.h_dbg[i] = h; }
+        x2[e] = make_double2(xs[0], xs[1]);
+        d2[e] = make_double2(ds[0], ds[1]);
+        dd.dz[e] = sC * (ds[0] + ds[1]);
     }
     const Red red{1, 1, 2};
     block_combine<4>(v, red, 0, s_wave, s_rec);

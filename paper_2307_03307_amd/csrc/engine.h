@@ -190,8 +190,8 @@ struct VcDev {
 // vptr/vvar, edge rows (covering) are pairs.  Every variable lies in one row
 // of each side, so g_i and h_i are single weights and nothing averages the
 // rounding of the direction out: the iterate x, the direction d, the rows y,
-// z and the products Pd, Cd are FP64 in both forms.  T is the type of the
-// stored weights w, u and of the search terms built from them.
+// z, the products Pd, Cd and the LSE totals are FP64 in both forms.  T is the
+// type of the stored weights w, u and of the search terms built from them.
 template <class T>
 struct DnDev {
     int32_t nv, ne, n;                    // non-isolated vertices, edges, variables (2 ne)

@@ -179,8 +179,9 @@ class DensestProgram : public Program {
         switch (which) {
         case 0: return (24.0 + t) * (V + E);                            // y rw, dy, w; z rw, dz, u
         // eu, ev; x, d read and written (2E variables); y (V) and z (E) for
-        // the log-domain ratio, or the weights w (V) and u (E) in FP64
-        case 1: return 8.0 * E + 32.0 * 2.0 * E + 8.0 * (V + E);
+        // the log-domain ratio, or the weights w (V) and u (E) in FP64; Cd
+        // written (E)
+        case 1: return 8.0 * E + 32.0 * 2.0 * E + 8.0 * (V + E) + 8.0 * E;
         // the vertex rows (the kernel timed for this pass): vptr, vvar, d
         // gathered, Pd written; the edge rows (d read, Cd written) are a
         // separate kernel of 24E bytes

@@ -407,19 +407,29 @@ def test_max_iter_and_standard_step():
     assert info.status == ref.status and info.iterations == ref.iterations
 
 
-@pytest.mark.parametrize("name", ["bmatch", "vcover", "densest", "domset"])
+# probes long enough to interrupt (FP64 oracle iteration counts: bmatch 134,
+# vcover 180, domset 177, densest 53)
+LONG_PROBES = {
+    "bmatch": lambda: bmatch_case(gg.bipartite_uniform(700, 650, 9000, seed=21), param=630.0),
+    "vcover": lambda: vcover_case(gg.gnm_random(900, 7000, seed=22), param=495.0),
+    "domset": lambda: domset_case(gg.chung_lu(3000, 2.3, 8.0, seed=23), param=646.5),
+    "densest": CASES["densest"],
+}
+
+
+@pytest.mark.parametrize("name", list(LONG_PROBES))
 def test_probe_resumes_after_direction(name):
     """Running, forming the direction (and evaluating steps along it), then
     running again takes exactly the steps of an uninterrupted run (FP64)."""
-    case = CASES[name]()
+    case = LONG_PROBES[name]()
     with case.make_gpu(precision=mwu.FP64) as s:
         s.probe_begin(case.param)
         ref = s.probe_run(5000)
         ref_alphas = s.probe_read("alpha", ref.iterations)
-        assert ref.iterations > 6
+        assert ref.iterations > 20
         s.probe_begin(case.param)
-        first = s.probe_run(5)
-        assert first.status == mwu._lib.PROBE_RUNNING and first.iterations == 5
+        first = s.probe_run(7)
+        assert first.status == mwu._lib.PROBE_RUNNING and first.iterations == 7
         s.probe_direction()
         s.probe_eval_steps(EXP_ALPHAS)
         info = s.probe_run(5000)
@@ -428,21 +438,21 @@ def test_probe_resumes_after_direction(name):
     assert np.array_equal(alphas, ref_alphas)
 
 
-@pytest.mark.parametrize("name", ["bmatch", "vcover", "densest"])
+@pytest.mark.parametrize("name", list(LONG_PROBES))
 def test_probe_continues_after_time_pass(name):
     """mwu_time_pass commits the pending step and times held launches; the
     probe then continues from the committed point and takes the steps an
     uninterrupted run takes from there (FP64; the LSE totals are renormalized
     by a row pass with no step, so the comparison covers the next 10 steps)."""
-    case = CASES[name]()
+    case = LONG_PROBES[name]()
     with case.make_gpu(precision=mwu.FP64) as s:
         s.probe_begin(case.param)
         ref = s.probe_run(5000)
         ref_alphas = s.probe_read("alpha", ref.iterations)
-        assert ref.iterations > 16
+        assert ref.iterations > 20
         s.probe_begin(case.param)
         s.probe_run(5)
-        for which in (1, 3, 4, 5, 0):
+        for which in (1, 2, 3, 4, 5, 0):
             s.time_pass(which, 2)
         info = s.probe_run(10)
         alphas = s.probe_read("alpha", info.iterations)
