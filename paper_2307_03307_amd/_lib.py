@@ -93,6 +93,23 @@ class ProbeInfo(ctypes.Structure):
 _lib = None
 
 
+def _open_torch_device_first() -> None:
+    """PyTorch ships its own HIP runtime, separate from the /opt/rocm runtime
+    libmwu.so links.  When both use the GPU in one process, torch's runtime
+    has to open the device first: opened after this library's runtime has
+    created its streams, it can find no device.  So on a machine where torch
+    sees a GPU its runtime is initialized before the library is loaded."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except RuntimeError:
+        pass
+
+
 def load() -> ctypes.CDLL:
     """Load libmwu.so; raises if the library has not been built."""
     global _lib
@@ -101,6 +118,7 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2307_03307_amd.build` (hipcc, gfx950)")
+    _open_torch_device_first()
     L = ctypes.CDLL(LIB_PATH)
     vp, P = ctypes.c_void_p, ctypes.POINTER
     L.mwu_default_options.argtypes = [P(Options)]

@@ -95,6 +95,7 @@ def _per_pass(case, precision, tol, seed=0, direction=True):
         # below float range; their error is reported, not bounded
         for k in ("d", "dy", "dz", "psi", "phi", "psi_list", "phi_list", "zmin", "zmin_list"):
             errs.pop(k)
+    print(f"per-pass {case.name} precision {precision}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, (case.name, bad)
     return errs
