@@ -329,6 +329,21 @@ mwu_status mwu_potential_forward(void *s, const double *x_dev, double *value_out
 mwu_status mwu_potential_backward(void *s, const double *x_dev, double grad_scale, double *grad_dev,
                                   void *stream);
 
+/* mwu_potential_backward for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same gradient, written to grad_dev as grad_scale (g - h),
+ * with no allocation in the call.  Every reduction record and chunk partial
+ * of its passes lives in a static device array of 8 MiB per GPU (held until
+ * the process ends, shared by all calls on that GPU: calls that overlap on one
+ * GPU race).  value_out (host, nullable) receives Phi(x) =
+ * smax(Px) - smin(Cx), as mwu_potential_forward returns it.  Errors:
+ * MWU_ERR_TOO_LARGE when the problem's records and chunk partials exceed the
+ * array; MWU_ERR_STATE for programs without a potential (the fused vertex
+ * cover), batch handles, or no probe begun; MWU_ERR_INVALID_ARG for NULL x_dev
+ * or grad_dev. */
+mwu_status mwu_potential_backward_noalloc(void *s, const double *x_dev, double grad_scale, double *grad_dev,
+                                          double *value_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

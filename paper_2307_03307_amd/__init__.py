@@ -221,6 +221,17 @@ class Solver:
                                                   ctypes.c_void_p(stream or 0)),
                    "mwu_potential_backward")
 
+    def potential_backward_noalloc(self, x_dev_ptr: int, grad_scale: float, grad_dev_ptr: int,
+                                   stream: Optional[int] = None) -> float:
+        """potential_backward with every scratch buffer in the library's static
+        device array (no allocation in the call); returns the potential at x."""
+        v = ctypes.c_double()
+        _lib.check(self._L.mwu_potential_backward_noalloc(self._h, ctypes.c_void_p(x_dev_ptr),
+                                                          float(grad_scale), ctypes.c_void_p(grad_dev_ptr),
+                                                          ctypes.addressof(v), ctypes.c_void_p(stream or 0)),
+                   "mwu_potential_backward_noalloc")
+        return v.value
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.mwu_destroy(self._h)

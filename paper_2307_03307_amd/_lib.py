@@ -28,7 +28,7 @@ EXPORTED = [
     "mwu_default_options", "mwu_create", "mwu_create_batch", "mwu_solve", "mwu_destroy",
     "mwu_status_string", "mwu_num_variables", "mwu_probe_sizes", "mwu_probe_begin",
     "mwu_probe_run", "mwu_probe_direction", "mwu_probe_read", "mwu_probe_eval_steps",
-    "mwu_potential_forward", "mwu_potential_backward", "mwu_time_pass",
+    "mwu_potential_forward", "mwu_potential_backward", "mwu_potential_backward_noalloc", "mwu_time_pass",
     "mwu_batch_get_layout", "mwu_batch_set_layout",
 ]
 
@@ -140,6 +140,7 @@ def load() -> ctypes.CDLL:
     L.mwu_probe_eval_steps.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.mwu_potential_forward.argtypes = [vp, vp, vp, vp]
     L.mwu_potential_backward.argtypes = [vp, vp, ctypes.c_double, vp, vp]
+    L.mwu_potential_backward_noalloc.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp]
     L.mwu_time_pass.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.mwu_batch_get_layout.argtypes = [vp, P(BatchLayout)]
     L.mwu_batch_set_layout.argtypes = [vp, P(BatchLayout)]

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmwu.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["generic.hip", "vcover.hip", "batch.hip", "densest.hip", "program_generic.cpp",
+SOURCES = ["generic.hip", "vcover.hip", "batch.hip", "densest.hip", "noalloc.hip", "program_generic.cpp",
            "program_vcover.cpp", "program_batch.cpp", "program_densest.cpp", "autotune.cpp", "solver.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

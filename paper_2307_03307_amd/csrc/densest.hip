@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     // certificates; the FP32 direction needs only y and z, and the densest
     // outer search uses no weak-duality bound, so FP32 skips them unless they
     // are being recorded
-    const bool need_gh = sizeof(T) == 8 || dd.g_dbg != nullptr;
+    const bool need_gh = sizeof(T) == 8 || dd.g_dbg != nullptr || dd.grad != nullptr;
     double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
         const int ru = dd.eu[e], rv = dd.ev[e];
@@ -286,6 +286,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
             v[1] = fmin(v[1], g);
             v[2] = fmax(v[2], di);
             if (dd.g_dbg) { dd.g_dbg[2 * e + k] = g; dd.h_dbg[2 * e + k] = h; }
+            if (dd.grad) dd.grad[2 * e + k] = dd.grad_scale * (g - h);
         }
         v[3] = fmax(v[3], h);
         x2[e] = make_double2(xs[0], xs[1]);

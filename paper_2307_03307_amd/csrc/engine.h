@@ -147,6 +147,8 @@ struct GenericDev {
     // vectors
     T *x, *d, *yz, *dyz, *wu;
     double *g_dbg, *h_dbg;              // nullable: debug copies of g, h
+    double *grad;                       // nullable: grad_scale (g - h) per column
+    double grad_scale;
     const double *forced;               // forced steps (host-provided), nullable
 };
 
@@ -210,6 +212,8 @@ struct DnDev {
     double *dz;
     T *u;
     double *g_dbg, *h_dbg;                // nullable
+    double *grad;                         // nullable: grad_scale (g - h) per variable
+    double grad_scale;
     const double *forced;
 };
 

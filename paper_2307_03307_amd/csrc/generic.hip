@@ -51,6 +51,7 @@ struct ColEpi {
         v[2] = fmax(v[2], (double)dt);
         v[3] = fmax(v[3], h);
         if (gd.g_dbg) { gd.g_dbg[i] = g; gd.h_dbg[i] = h; }
+        if (gd.grad) gd.grad[i] = gd.grad_scale * (g - h);
     }
 };
 

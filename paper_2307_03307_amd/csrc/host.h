@@ -63,6 +63,13 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Size of the static device scratch of mwu_potential_backward_noalloc
+// (noalloc.hip): the reduction records of two passes (2 x GRID_MAX x QMAX
+// doubles, 3.1 MiB) and the chunk partials of the long rows and columns.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+// Device address of this GPU's scratch array (the device must be current).
+void *noalloc_scratch(int device);
+
 // Interface of a device program (the generic CSR engine, the fused graph
 // programs).  All launches go to the solver stream.
 struct Program {
@@ -84,6 +91,13 @@ struct Program {
     virtual void main_kernel(int which) = 0;          // a pass's main kernel alone (timing)
     virtual void potential(const double *x_dev, double *val_dev, double scale, double *grad_dev,
                            hipStream_t st) = 0;
+    // The same gradient with every record and chunk partial in the caller's
+    // scratch (no allocation): grad = scale (g - h) written by the column
+    // pass.  False when the scratch is too small for this problem.
+    virtual bool potential_static(const double *, double, double *, void *, size_t, hipStream_t)
+    {
+        throw ApiError{MWU_ERR_STATE, "this program has no potential (use MWU_FLAG_GENERIC)"};
+    }
     virtual void set_debug(bool on) = 0;
     virtual void set_forced(const double *host, int count) = 0;
     // Continue the probe after a direction formed in evaluation mode

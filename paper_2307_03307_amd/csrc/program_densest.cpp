@@ -70,6 +70,8 @@ class DensestProgram : public Program {
         dd_.y = y_.as<double>(); dd_.dy = dy_.as<double>(); dd_.w = w_.as<T>();
         dd_.z = z_.as<double>(); dd_.dz = dz_.as<double>(); dd_.u = u_.as<T>();
         dd_.g_dbg = nullptr; dd_.h_dbg = nullptr; dd_.forced = nullptr;
+        dd_.grad = nullptr; dd_.grad_scale = 0.0;
+        vslots_ = vt.nslots;
         int occ_v = 1, occ_s = 1;
         dn_occupancy<T>(&occ_v, &occ_s);
         auto clampg = [](int64_t items, int64_t per, int64_t cap) {
@@ -172,6 +174,30 @@ class DensestProgram : public Program {
                              grad_dev, ctl(), val_dev, st);
     }
 
+    bool potential_static(const double *x_dev, double grad_scale, double *grad_dev, void *scr, size_t bytes,
+                          hipStream_t st) override
+    {
+        // [records of the vertex passes | records of the edge passes | chunk partials]
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t rec = al((size_t)GRID_MAX * QMAX * 8);
+        const size_t lp = al((size_t)std::max<int32_t>(vslots_, 1) * 8);
+        if (2 * rec + lp > bytes) return false;
+        char *b = static_cast<char *>(scr);
+        DnDev<T> g = dd_;
+        g.lpart = reinterpret_cast<double *>(b + 2 * rec);
+        g.g_dbg = nullptr;
+        g.h_dbg = nullptr;
+        g.grad = grad_dev;
+        g.grad_scale = grad_scale;
+        DnLaunch L = L_;
+        L.partials = reinterpret_cast<double *>(b);
+        L.partials2 = reinterpret_cast<double *>(b + rec);
+        dn_init<T>(g, ctl(), L, st, true, x_dev);
+        dn_row_pass<T>(g, ctl(), L, st);
+        dn_col_pass<T>(g, ctl(), L, st);
+        return true;
+    }
+
     // t: bytes of a stored weight; x, d, y, z, dy, dz are 8-byte values
     double algo_bytes(int which) const override
     {
@@ -267,6 +293,7 @@ class DensestProgram : public Program {
     DevBuf eu_, ev_, vptr_, vvar_, vtiles_, lseg_, lfirst_, lcount_, lpart_, lpart64_;
     DevBuf x_, d_, xbest_, y_, dy_, w_, z_, dz_, u_, partials_, partials2_, forced_, dbg_g_, dbg_h_;
     DevBuf rank_, back_;
+    int32_t vslots_ = 0;   // chunk partial slots of the long vertex rows
 };
 
 std::unique_ptr<Program> make_densest_program(Solver &s, const EdgeList &el, const std::vector<int64_t> &vid,

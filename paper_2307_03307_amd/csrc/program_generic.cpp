@@ -156,6 +156,9 @@ class GenericProgram : public Program {
         gd_.x = x_.as<T>(); gd_.d = d_.as<T>(); gd_.yz = yz_.as<T>(); gd_.dyz = dyz_.as<T>();
         gd_.wu = wu_.as<T>();
         gd_.g_dbg = nullptr; gd_.h_dbg = nullptr; gd_.forced = nullptr;
+        gd_.grad = nullptr; gd_.grad_scale = 0.0;
+        rslots_ = rt.nslots;
+        cslots_ = ct.nslots;
 
         auto clampg = [](int64_t items, int64_t per) {
             int64_t g = (items + per - 1) / per;
@@ -278,6 +281,31 @@ class GenericProgram : public Program {
                              grad_dev, ctl(), val_dev, st);
     }
 
+    bool potential_static(const double *x_dev, double grad_scale, double *grad_dev, void *scr, size_t bytes,
+                          hipStream_t st) override
+    {
+        // [reduction records | row chunk partials | column chunk partials]
+        auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t rec = al((size_t)GRID_MAX * QMAX * 8);
+        const size_t rl = al((size_t)std::max<int32_t>(rslots_, 1) * sizeof(T));
+        const size_t cl = al((size_t)std::max<int32_t>(cslots_, 1) * 2 * sizeof(T));
+        if (rec + rl + cl > bytes) return false;
+        char *b = static_cast<char *>(scr);
+        GenericDev<T> g = gd_;
+        g.rlpart = reinterpret_cast<T *>(b + rec);
+        g.clpart = b + rec + rl;
+        g.g_dbg = nullptr;
+        g.h_dbg = nullptr;
+        g.grad = grad_dev;
+        g.grad_scale = grad_scale;
+        Launch L = L_;
+        L.partials = reinterpret_cast<double *>(b);
+        generic_load_x<T>(g, ctl(), L, st, x_dev);
+        generic_row<T>(g, ctl(), L, st);
+        generic_col<T>(g, ctl(), L, st);
+        return true;
+    }
+
     double algo_bytes(int which) const override
     {
         const double t = sizeof(T), nnz = (double)nnz_, vb = vals_ ? t : 0.0;
@@ -328,6 +356,7 @@ class GenericProgram : public Program {
     DevBuf rptr_, rcol_, rval_, cptr_, crow_, cval_, colmax_, rtiles_, ctiles_;
     DevBuf rlseg_, rlfirst_, rlcount_, clseg_, clfirst_, clcount_, rlpart_, clpart_, rlpart64_, rval64_;
     DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, forced_, dbg_g_, dbg_h_;
+    int32_t rslots_ = 0, cslots_ = 0;   // chunk partial slots of the long rows and columns
 };
 
 std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C)

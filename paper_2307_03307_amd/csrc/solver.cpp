@@ -1106,4 +1106,28 @@ mwu_status mwu_potential_backward(void *h, const double *x_dev, double grad_scal
     });
 }
 
+mwu_status mwu_potential_backward_noalloc(void *h, const double *x_dev, double grad_scale, double *grad_dev,
+                                          double *value_out, void *stream)
+{
+    if (!h || !x_dev || !grad_dev) return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
+    if (!s.in_probe) return MWU_ERR_STATE;
+    return run_guarded([&] {
+        HIP_OK(hipSetDevice(s.opt.device));
+        void *scr = noalloc_scratch(s.opt.device);
+        hipStream_t st = stream ? (hipStream_t)stream : s.stream;
+        pull_ctl(s);
+        s.ctl_host->eval_mode = 2;
+        HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        s.dir_pending = false;
+        if (!s.prog->potential_static(x_dev, grad_scale, grad_dev, scr, kNoAllocScratchBytes, st))
+            throw ApiError{MWU_ERR_TOO_LARGE, "reduction records and chunk partials exceed the static scratch"};
+        HIP_OK(hipStreamSynchronize(st));
+        HIP_OK(hipMemcpy(s.ctl_host, s.ctl_buf.p, sizeof(Ctl), hipMemcpyDeviceToHost));
+        // after the row pass L_P and L_C are smax(Px) and smin(Cx) at x
+        if (value_out) *value_out = s.ctl_host->LP - s.ctl_host->LC;
+    });
+}
+
 }  // extern "C"
