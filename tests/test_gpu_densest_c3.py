@@ -18,7 +18,16 @@ from gpu_common import EPS, densest_case, rel_err
 pytestmark = pytest.mark.gpu
 
 EXP_ALPHAS = [float(2 ** k) for k in range(8)]
-TOL = {0: 1e-9, 1: 5e-3}   # as for the small densest cases (FP32 storage in the chosen form)
+# FP64: reduction order.  Chosen form: g and h are the stored FP32 weights
+# (U = 2^-24); d is formed in FP64 from the rows and the LSE totals, except
+# that the chosen form's threshold q > 2^-16 leaves d = 0 where the oracle's
+# exact rule moves a coordinate by at most 2^-16 s x / eta; Psi and Phi carry
+# the FP32 terms of the search; min z' is FP64.  Observed 3.8e-8 (g), 4.6e-8
+# (h), 2.3e-5 (d), 2.1e-9 (Psi), 9.3e-9 (Phi), 5.8e-11 (min z'); each bound is
+# 2-4x that.
+U = 2.0 ** -24
+TOL = {0: {k: 1e-9 for k in ("g", "h", "d", "psi", "phi", "zmin")},
+       1: {"g": 2 * U, "h": 2 * U, "d": 3 * 2.0 ** -16, "psi": 1e-8, "phi": 3e-8, "zmin": 2e-10}}
 
 
 @pytest.fixture(scope="module")
@@ -66,5 +75,5 @@ def test_c3_passes_mid_probe(c3, precision):
     errs["zmin"] = rel_err(zm, ref["zmin_new"])
     print(f"C3 precision {precision}, {info.iterations} iterations in: " +
           ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= TOL[precision]}
+    bad = {k: v for k, v in errs.items() if not v <= TOL[precision][k]}
     assert not bad, bad

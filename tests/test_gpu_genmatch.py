@@ -79,13 +79,13 @@ def test_genmatch_fp64_follows_oracle(small):
     assert info.status == r.status == oracle.FEASIBLE
     assert info.iterations == r.iterations and np.array_equal(alphas, r.alphas)
     # same steps; the iterate carries the reduction-order differences of g
-    # and h, amplified by the steps (R13; observed 3e-8 on the sum and
-    # 1.2e-6 on the largest coordinate difference here)
+    # and h, amplified by the steps (R13; observed 2.8e-8 on the sum and
+    # 1.2e-6 on the largest coordinate difference here; bounds about 4x)
     e_sum = abs(xg.sum() - r.x.sum()) / r.x.sum()
     e_x = rel_err(xg, r.x)
     print(f"genmatch FP64 iterate: sum rel err {e_sum:.2e}, x rel err {e_x:.2e}")
-    assert e_sum <= 1e-6
-    assert e_x <= 1e-5
+    assert e_sum <= 1e-7
+    assert e_x <= 5e-6
     curve = []
     for t in sorted({1, 2, 4, 8, 16, 32, r.iterations} & set(range(1, r.iterations + 1))):
         rt = oracle.probe(P, 1.0, C, 1.0, EPS, max_iter=t, forced_alpha=alphas[:t])

@@ -3,8 +3,8 @@
 Modes (oracle vs gfx950 library):
   per-pass      identical x fed to both: y = Px, z = Cx, g, h, d, Pd, Cd and
                 Psi, Phi, min(z + a Cd) at candidate steps.  FP64 form: max
-                relative error <= 1e-9.  Mixed FP32/FP64 form: <= 5e-3 (the
-                weights carry eta * 2^-24 ~ 1e-4 relative error).
+                relative error <= 1e-9.  Mixed FP32/FP64 form: per-quantity
+                bounds in units of 2^-24 (MIXED_TOL).
   replay        the oracle is forced to the GPU's step sequence: FP64 final x
                 objective within 1e-9 (final x within 1e-6), mixed form final
                 objective within 1e-5.
@@ -29,7 +29,18 @@ from gpu_common import (EPS, bmatch_case, densest_case, domset_case, ones_row, r
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-9
-FP32_TOL = 5e-3
+# Chosen form, per quantity, in units of the FP32 unit roundoff U = 2^-24:
+# x, y, z are FP32-stored values and FP32 row sums; g and h are normalized
+# weights, whose common shift (the LSE total) cancels the rounding of the
+# dominant rows, so they keep O(U) too; d = (s/eta) q x multiplies the
+# rounding of g/h by x and the products Pd, Cd sum it over the rows; Psi and
+# Phi (relative to the scale of the test Phi >= Psi) carry the FP32 terms of
+# the search.  Each bound is about 3x the largest error seen over the cases
+# below, so an error ten times larger fails.
+U = 2.0 ** -24
+MIXED_TOL = {"x": 4 * U, "y": 6 * U, "z": 6 * U, "g": 6 * U, "h": 24 * U, "d": 64 * U, "dy": 32 * U,
+             "dz": 64 * U, "psi": 24 * U, "phi": 12 * U, "psi_list": 24 * U, "phi_list": 12 * U,
+             "zmin": 4 * U, "zmin_list": 4 * U}
 EXP_ALPHAS = [float(2 ** k) for k in range(8)]    # one exponential-grid pass
 LIST_ALPHAS = [0.37, 1.0, 3.5, 11.0, 70.0]
 
@@ -96,7 +107,7 @@ def _per_pass(case, precision, tol, seed=0, direction=True):
         for k in ("d", "dy", "dz", "psi", "phi", "psi_list", "phi_list", "zmin", "zmin_list"):
             errs.pop(k)
     print(f"per-pass {case.name} precision {precision}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= tol}
+    bad = {k: v for k, v in errs.items() if not v <= (tol[k] if isinstance(tol, dict) else tol)}
     assert not bad, (case.name, bad)
     return errs
 
@@ -111,14 +122,16 @@ def test_per_pass_fp64(name):
 def test_per_pass_mixed(name):
     """The fused densest program forms g_i / h_i in the log domain, so its FP32
     direction matches even where both FP32 weights underflow."""
-    _per_pass(CASES[name](), mwu.MIXED_FP32_FP64, FP32_TOL)
+    _per_pass(CASES[name](), mwu.MIXED_FP32_FP64, MIXED_TOL)
 
 
 def test_per_pass_mixed_densest_generic_weights():
     """Generic engine on the densest-subgraph LP in the mixed form: both sides
     are exponential weights, so coordinates whose weights underflow float get
     d = 0; the weights, g and h themselves still match to float accuracy."""
-    _per_pass(CASES["densest-generic"](), mwu.MIXED_FP32_FP64, FP32_TOL, direction=False)
+    # h sums one covering weight per variable (single-weight rows): observed 2.8e-6
+    tol = dict(MIXED_TOL, h=128 * U)
+    _per_pass(CASES["densest-generic"](), mwu.MIXED_FP32_FP64, tol, direction=False)
 
 
 def _replay(case, precision):
@@ -219,8 +232,9 @@ def test_sparse_transpose_pass(precision):
     print(f"precision {precision}: transpose pass over {nnz:.0f} of {2 * C.rows} nonzeros; {errs}")
     if precision == mwu.MIXED_FP32_FP64:
         assert nnz < 0.6 * 2 * C.rows
-    tol = 1e-9 if precision == mwu.FP64 else FP32_TOL
-    assert all(v <= tol for v in errs.values()), errs
+    # observed 1.6e-7 on h and d in the chosen form
+    tol = {k: 1e-9 for k in errs} if precision == mwu.FP64 else {"g": 6 * U, "h": 8 * U, "d": 8 * U}
+    assert all(v <= tol[k] for k, v in errs.items()), errs
 
 
 def _opt_bmatch(g):

@@ -23,9 +23,15 @@ from gpu_common import EPS, rel_err, vcover_case
 pytestmark = pytest.mark.gpu
 
 EXP_ALPHAS = [float(2 ** k) for k in range(8)]
-# per-element tolerance of the per-pass quantities (as for the small cases:
-# FP32 storage in the chosen form, reduction order in FP64)
-TOL = {0: 1e-9, 1: 5e-3}
+# per-element tolerance of the per-pass quantities: reduction order in FP64;
+# in the chosen form the FP32 rounding (U = 2^-24) of h and min z', and for d
+# the direction threshold q > 2^-16 of the chosen form (a coordinate with q
+# below it keeps d = 0 where the oracle's exact rule moves it by at most
+# 2^-16 s x / eta); observed 2e-7 (h, min z'), 2.1e-5 (d), 2.8e-9 and 5.2e-9
+# (Psi, Phi); each bound is 2-4x the observed error
+U = 2.0 ** -24
+TOL = {0: {k: 1e-9 for k in ("g", "h", "d", "psi", "phi", "zmin")},
+       1: {"g": 6 * U, "h": 8 * U, "d": 3 * 2.0 ** -16, "psi": 1e-8, "phi": 2e-8, "zmin": 8 * U}}
 
 
 @pytest.fixture(scope="module")
@@ -77,5 +83,5 @@ def test_c2_passes_mid_probe(c2, precision):
     errs["zmin"] = rel_err(zm, ref["zmin_new"])
     print(f"C2 precision {precision}, 600 iterations in: " +
           ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= TOL[precision]}
+    bad = {k: v for k, v in errs.items() if not v <= TOL[precision][k]}
     assert not bad, bad
