@@ -299,6 +299,28 @@ mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
 mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new);
 
+/* Probe-level access to a batched handle: one probe of Algorithm 2 (with the
+ * handle's step rule) on every instance at once, instance k at params[k] =
+ * M_k (its objective row is (1/M_k) 1^T x, end of Section 2.2), started from
+ * the Algorithm 1 point and run by the batched kernels in the handle's
+ * layout.  A probe that is still running after max_iters accepted steps
+ * pauses there (max_iters = 0: every probe runs to its outcome); calling
+ * again starts new probes.  params: host, count entries, each > 0.  info:
+ * host, count entries, nullable.  MWU_ERR_STATE on a single-problem handle,
+ * MWU_ERR_INVALID_ARG for NULL params, max_iters < 0 or a parameter <= 0.
+ * A later mwu_solve starts every outer search afresh. */
+mwu_status mwu_batch_probe_run(void *s, const double *params, int32_t max_iters, mwu_probe_info *info);
+
+/* A vector of instance `instance` after mwu_batch_probe_run, as
+ * mwu_probe_read defines them: 0 x (the instance's edges, in its caller's
+ * order), 1 d, 4 y = Px (its non-isolated vertices in vertex order), 6 dy =
+ * Pd, 8 the accepted steps of its probe (len = its iteration count).  When a
+ * probe paused, x is the iterate before its last accepted step and d the
+ * direction formed at x.  MWU_ERR_STATE before any batched probe,
+ * MWU_ERR_INVALID_ARG for an unknown vector, an instance out of range or a
+ * length mismatch. */
+mwu_status mwu_batch_probe_read(void *s, int32_t instance, int32_t which, double *out, int64_t len);
+
 /* Time the main kernel of one pass of the iteration: which = 0 row /
  * transpose pass (the weights, their LSE totals and C^T u, P^T w), 1 column /
  * direction pass, 2 forward pass (P d, C d; a no-op in fused programs that

@@ -316,6 +316,22 @@ class BatchSolver:
             off += ne
         return out
 
+    def probe_run(self, params: Sequence[float], max_iters: int = 0):
+        """One probe per instance at params[k] in the batched kernels
+        (``mwu_batch_probe_run``); list of per-instance ProbeInfo."""
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        assert p.shape == (self.count,)
+        info = (_lib.ProbeInfo * self.count)()
+        _lib.check(self._L.mwu_batch_probe_run(self._h, p.ctypes.data, int(max_iters), ctypes.addressof(info)),
+                   "mwu_batch_probe_run")
+        return [info[k] for k in range(self.count)]
+
+    def probe_read(self, instance: int, which: str, length: int) -> np.ndarray:
+        out = np.zeros(length)
+        _lib.check(self._L.mwu_batch_probe_read(self._h, int(instance), VEC[which], out.ctypes.data, length),
+                   "mwu_batch_probe_read")
+        return out
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._L.mwu_destroy(self._h)

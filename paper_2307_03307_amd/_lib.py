@@ -29,7 +29,7 @@ EXPORTED = [
     "mwu_status_string", "mwu_num_variables", "mwu_probe_sizes", "mwu_probe_begin",
     "mwu_probe_run", "mwu_probe_direction", "mwu_probe_read", "mwu_probe_eval_steps",
     "mwu_potential_forward", "mwu_potential_backward", "mwu_potential_backward_noalloc", "mwu_time_pass",
-    "mwu_batch_get_layout", "mwu_batch_set_layout",
+    "mwu_batch_get_layout", "mwu_batch_set_layout", "mwu_batch_probe_run", "mwu_batch_probe_read",
 ]
 
 
@@ -141,6 +141,8 @@ def load() -> ctypes.CDLL:
     L.mwu_potential_forward.argtypes = [vp, vp, vp, vp]
     L.mwu_potential_backward.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     L.mwu_potential_backward_noalloc.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp]
+    L.mwu_batch_probe_run.argtypes = [vp, vp, ctypes.c_int32, vp]
+    L.mwu_batch_probe_read.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64]
     L.mwu_time_pass.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.mwu_batch_get_layout.argtypes = [vp, P(BatchLayout)]
     L.mwu_batch_set_layout.argtypes = [vp, P(BatchLayout)]

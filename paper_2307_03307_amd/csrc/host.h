@@ -125,6 +125,13 @@ struct BatchProgram {
     virtual void solve(double *x_out, double *obj_out, int64_t *iters_out, mwu_result_info *info) = 0;
     virtual mwu_batch_layout layout() const = 0;
     virtual void set_layout(const mwu_batch_layout &L) = 0;   // L already validated
+    // One probe on every instance at once (instance k at params[k]), in the
+    // batched kernels, pausing after max_iters accepted steps (0: no pause);
+    // info: one entry per instance (nullable).
+    virtual void probe_run(const double *params, int32_t max_iters, mwu_probe_info *info) = 0;
+    // A vector of instance k after probe_run (the mwu_probe_read codes 0 x,
+    // 1 d, 4 y, 6 dy, 8 accepted steps).
+    virtual void probe_read(int32_t k, int32_t which, double *out, int64_t len) = 0;
 };
 
 // Autotuner of batched layouts (autotune.cpp).

@@ -238,6 +238,87 @@ class BatchMatching : public BatchProgram {
         if (iters_out) *iters_out = total;
     }
 
+    void probe_run(const double *params, int32_t max_iters, mwu_probe_info *info) override
+    {
+        for (int32_t k = 0; k < nb_; ++k)
+            if (!(params[k] > 0.0) || !std::isfinite(params[k]))
+                throw ApiError{MWU_ERR_INVALID_ARG, "probe parameters must be positive"};
+        if (tiled_active_ != nb_) relayout(layout_);
+        const int32_t cap_iter = s_.opt.max_iter;
+        if (!trace_.p) trace_.alloc((size_t)nb_ * cap_iter * 8);
+        for (int32_t k = 0; k < nb_; ++k) {
+            Inst &I = inst_[k];
+            I.eps_probe = s_.opt.eps;
+            I.param = params[k];
+            I.done = false;
+            configure_probe(k);
+            Ctl &c = ctl_host_[k];
+            c.trace = trace_.as<double>() + (size_t)k * cap_iter;
+            c.trace_cap = cap_iter;
+            c.iter_stop = max_iters > 0 ? max_iters : 0;
+        }
+        push_state();
+        ensure_graph();
+        // every instance ends its probe (PH_IDLE after the statistics pass)
+        // or pauses at the iteration stop (PH_IDLE, still running)
+        const int64_t cap = ((int64_t)cap_iter + 8) * 8 / std::max(1, slots_) + 64;
+        for (int64_t l = 0;; ++l) {
+            if (l > cap) throw ApiError{MWU_ERR_DEVICE, "batched probe did not finish"};
+            HIP_OK(hipGraphLaunch(graph_, s_.stream));
+            HIP_OK(hipMemcpyAsync(stat_host_, stat_.p, (size_t)nb_ * 16, hipMemcpyDeviceToHost, s_.stream));
+            HIP_OK(hipStreamSynchronize(s_.stream));
+            bool all = true;
+            for (int32_t k = 0; k < nb_ && all; ++k) all = stat_host_[4 * k] == PH_IDLE;
+            if (all) break;
+        }
+        HIP_OK(hipMemcpyAsync(ctl_host_, ctl_.p, (size_t)nb_ * sizeof(Ctl), hipMemcpyDeviceToHost, s_.stream));
+        HIP_OK(hipStreamSynchronize(s_.stream));
+        for (int32_t k = 0; k < nb_; ++k) {
+            inst_[k].done = true;   // a later solve starts every search afresh
+            if (!info) continue;
+            const Ctl &c = ctl_host_[k];
+            mwu_probe_info &r = info[k];
+            r.status = c.status;
+            r.iterations = c.iter;
+            r.search_passes = c.search_passes;
+            r.alpha = c.last_alpha;
+            r.L_P = c.LP;
+            r.L_C = c.LC;
+            r.pack_bound = c.pack_bound;
+            r.cover_bound = c.cover_bound;
+            r.evaluations = c.evaluations;
+        }
+        probed_ = true;
+    }
+
+    void probe_read(int32_t k, int32_t which, double *out, int64_t len) override
+    {
+        if (!probed_) throw ApiError{MWU_ERR_STATE, "no batched probe has run"};
+        if (k < 0 || k >= nb_) throw ApiError{MWU_ERR_INVALID_ARG, "instance out of range"};
+        const Inst &I = inst_[k];
+        auto get = [&](const T *base, int64_t off, int64_t n) {
+            if (len != n) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
+            std::vector<T> t((size_t)std::max<int64_t>(n, 1));
+            HIP_OK(hipMemcpy(t.data(), base + off, n * sizeof(T), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) out[i] = (double)t[i];
+        };
+        switch (which) {
+        case 0: get(x_.as<T>(), I.e0, I.ne); return;
+        case 1: get(d_.as<T>(), I.e0, I.ne); return;
+        case 4: get(y_.as<T>(), I.v0, I.nv); return;
+        case 6: get(dy_.as<T>(), I.v0, I.nv); return;
+        case 8: {
+            const int64_t it = ctl_host_[k].iter;
+            if (len != it) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
+            if (it > 0)
+                HIP_OK(hipMemcpy(out, trace_.as<double>() + (size_t)k * s_.opt.max_iter, it * 8,
+                                 hipMemcpyDeviceToHost));
+            return;
+        }
+        }
+        throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
+    }
+
   private:
     // The outer search of every instance: launch the captured slots, poll the
     // status array, hand finished probes to the host rules and start the next
@@ -465,6 +546,15 @@ class BatchMatching : public BatchProgram {
             I.shi = I.hi;
         }
         I.param = std::sqrt(I.slo * I.shi);
+        configure_probe(k);
+        return true;
+    }
+
+    // Instance k's probe at I.param and I.eps_probe in the host copy of its
+    // control block (phase PH_INIT), with a new serial number.
+    void configure_probe(int32_t k)
+    {
+        Inst &I = inst_[k];
         Ctl &c = ctl_host_[k];
         std::memset(&c, 0, sizeof(Ctl));
         const int64_t m = I.nv + 1;                              // vertex rows + objective row
@@ -491,7 +581,6 @@ class BatchMatching : public BatchProgram {
         stat_host_[4 * k + 0] = PH_INIT;      // pushed with the control blocks
         stat_host_[4 * k + 2] = 0;
         stat_host_[4 * k + 3] = I.serial;
-        return true;
     }
 
     // Apply the finished probe of instance k to its brackets (the packing
@@ -561,6 +650,8 @@ class BatchMatching : public BatchProgram {
     DevBuf eu_, ev_, vptr_, vedge_, vt_, et_, vrec0_, vrecn_, erec0_, erecn_, nedge_;
     DevBuf lrec0_, lrecn_, lseg_, lfirst_, lcount_, lpart_, lpart64_, wt_, wrec0_, wrecn_, wpart_;
     DevBuf x_, d_, xbest_, y_, dy_, w_, vpart_, epart_, ctl_, stat_;
+    DevBuf trace_;          // accepted steps of the probe API's probes (max_iter per instance)
+    bool probed_ = false;
 };
 
 std::unique_ptr<BatchProgram> make_batch_matching(Solver &s, const mwu_problem *probs, int32_t count)

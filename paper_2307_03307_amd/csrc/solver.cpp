@@ -776,6 +776,28 @@ mwu_status mwu_batch_set_layout(void *h, const mwu_batch_layout *layout)
     });
 }
 
+mwu_status mwu_batch_probe_run(void *h, const double *params, int32_t max_iters, mwu_probe_info *info)
+{
+    if (!h || !params || max_iters < 0) return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (!s.batch) return MWU_ERR_STATE;
+    return run_guarded([&] {
+        HIP_OK(hipSetDevice(s.opt.device));
+        s.batch->probe_run(params, max_iters, info);
+    });
+}
+
+mwu_status mwu_batch_probe_read(void *h, int32_t instance, int32_t which, double *out, int64_t len)
+{
+    if (!h || !out || len < 0) return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (!s.batch) return MWU_ERR_STATE;
+    return run_guarded([&] {
+        HIP_OK(hipSetDevice(s.opt.device));
+        s.batch->probe_read(instance, which, out, len);
+    });
+}
+
 mwu_status mwu_solve(void *h, double *x_out, double *objective_out, int64_t *iterations_out,
                      mwu_result_info *info)
 {
