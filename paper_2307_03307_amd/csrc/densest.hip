@@ -2,8 +2,9 @@
 // fixed (Section 3), W z >= 1, (1/D) O z <= 1, z >= 0, run through Algorithm 2
 // with the step search of Algorithm 3 (Section 4).
 //
-// Variables are the edge ends: z_{2e} on the first endpoint of edge e and
-// z_{2e+1} on the second.  Every variable lies in exactly one packing row (its
+// Variables are the edge ends (the caller's z_{2e} and z_{2e+1}; internally
+// the first and second end of edge e in degree order, stored as two arrays).
+// Every variable lies in exactly one packing row (its
 // vertex) and one covering row (its edge), so the transpose products need no
 // index structure: g_i = w_{v(i)} / (D sum w), h_i = u_{e(i)} / sum u.  The
 // vertex rows are segmented sums over each vertex's variables (nnz-balanced
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(BLOCK) void dn_init_x(DnDev<T> dd, Ctl *ctl, int ha
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < dd.n; i += gridDim.x * BLOCK) {
         double x;
         if (src) {
-            x = src[i];
+            x = src[dd.cpos[i]];   // caller order -> internal
             dd.x[i] = x;
         } else if (!have_x0) {
             x = eps / ((double)dd.n * sP);   // Algorithm 1: eps / (n max_j P_ji), P_ji = sP
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_v(DnDev<T> dd, Ctl *ctl, double 
 
 // Long vertex rows (more variables than one tile) from the chunk partials of
 // dn_fwd_v, one wave per long row, chunks summed lane-strided and folded in a
-// fixed order; INIT also forms the edge rows z = sC (x_2e + x_2e+1) (clearing
+// fixed order; INIT also forms the edge rows z = sC (x_first + x_second) (clearing
 // dz; in an iteration the column pass writes Cd).  Record [min z | max over
 // the long rows] (INIT) or [max over the long rows].
 template <class T, bool INIT>
@@ -115,8 +116,7 @@ __global__ __launch_bounds__(BLOCK) void dn_fwd_e(DnDev<T> dd, Ctl *ctl, double 
     if (INIT) {
         const double sC = ctl->sC;
         for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK) {
-            const double2 pr = reinterpret_cast<const double2 *>(dd.x)[e];
-            const double val = sC * (pr.x + pr.y);
+            const double val = sC * (dd.x[e] + dd.x[dd.ne + e]);
             dd.z[e] = val;
             dd.dz[e] = 0.0;
             mn = fmin(mn, val);
@@ -228,8 +228,8 @@ __global__ __launch_bounds__(BLOCK) void dn_row_fin(Ctl *ctl, const double *part
 // ------------------------------------------------------------------ column pass
 
 // Commit x += a d, then g, h and the direction of every variable, and the
-// edge rows of the direction Cd = sC (d_2e + d_2e+1).  One thread per edge
-// takes its two variables (16-byte loads and stores of the pairs).  Record
+// edge rows of the direction Cd = sC (d_first + d_second).  One thread per
+// edge takes its two variables (coalesced in both halves of x and d).  Record
 // [sum d | min g | max d | max h].  In PH_COMMIT only the commit.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *part)
@@ -240,12 +240,11 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     if (ph != PH_COL && ph != PH_COMMIT) return;
     const double a = ctl->alpha;
     const int stride = gridDim.x * BLOCK;
-    double2 *x2 = reinterpret_cast<double2 *>(dd.x);
-    double2 *d2 = reinterpret_cast<double2 *>(dd.d);
+    const int ne = dd.ne;
     if (ph == PH_COMMIT) {
-        for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
-            const double2 xv = x2[e], dv = d2[e];
-            x2[e] = make_double2(xv.x + a * dv.x, xv.y + a * dv.y);
+        for (int e = blockIdx.x * BLOCK + threadIdx.x; e < ne; e += stride) {
+            dd.x[e] = dd.x[e] + a * dd.d[e];
+            dd.x[ne + e] = dd.x[ne + e] + a * dd.d[ne + e];
         }
         return;
     }
@@ -262,8 +261,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
     double v[4] = {0.0, INFINITY, -INFINITY, -INFINITY};
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
         const int ru = dd.eu[e], rv = dd.ev[e];
-        const double2 xv = x2[e], dv = d2[e];
-        const double xs[2] = {xv.x + a * dv.x, xv.y + a * dv.y};
+        const double xs[2] = {dd.x[e] + a * dd.d[e], dd.x[ne + e] + a * dd.d[ne + e]};
         const double h = need_gh ? sC * (double)dd.u[e] * invSu : -INFINITY;
         const double ze = sizeof(T) == 4 ? dd.z[e] : 0.0;
         double ds[2];
@@ -285,12 +283,14 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
             v[0] += di;
             v[1] = fmin(v[1], g);
             v[2] = fmax(v[2], di);
-            if (dd.g_dbg) { dd.g_dbg[2 * e + k] = g; dd.h_dbg[2 * e + k] = h; }
-            if (dd.grad) dd.grad[2 * e + k] = dd.grad_scale * (g - h);
+            if (dd.g_dbg) { dd.g_dbg[k * ne + e] = g; dd.h_dbg[k * ne + e] = h; }
+            if (dd.grad) dd.grad[dd.cpos[k * ne + e]] = dd.grad_scale * (g - h);   // caller order
         }
         v[3] = fmax(v[3], h);
-        x2[e] = make_double2(xs[0], xs[1]);
-        d2[e] = make_double2(ds[0], ds[1]);
+        dd.x[e] = xs[0];
+        dd.x[ne + e] = xs[1];
+        dd.d[e] = ds[0];
+        dd.d[ne + e] = ds[1];
         dd.dz[e] = sC * (ds[0] + ds[1]);
     }
     const Red red{1, 1, 2};
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(BLOCK) void dn_stats_e(DnDev<T> dd, double *part)
     __shared__ double s_rec[QMAX];
     double v[1] = {INFINITY};
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += gridDim.x * BLOCK)
-        v[0] = fmin(v[0], dd.x[2 * e] + dd.x[2 * e + 1]);
+        v[0] = fmin(v[0], dd.x[e] + dd.x[dd.ne + e]);
     const Red red{0, 1, 0};
     block_combine<1>(v, red, 0, s_wave, s_rec);
     store_record(s_rec, 1, part);
@@ -477,8 +477,9 @@ __global__ __launch_bounds__(BLOCK) void dn_backcount(DnDev<T> dd, const int32_t
         int c = 0;
         for (int q = dd.vptr[v] + lane; q < dd.vptr[v + 1]; q += 64) {
             const int var = dd.vvar[q];
-            const int e = var >> 1;
-            const int w = (var & 1) ? dd.eu[e] : dd.ev[e];   // the other end of the edge
+            const bool second = var >= dd.ne;
+            const int e = second ? var - dd.ne : var;
+            const int w = second ? dd.eu[e] : dd.ev[e];   // the other end of the edge
             c += rank[w] < rv;
         }
 #pragma unroll
@@ -492,6 +493,19 @@ void dn_backcounts(const DnDev<T> &dd, const int32_t *rank, int32_t *back, hipSt
 {
     const int grid = std::max(1, std::min(GRID_MAX * 4, (dd.nv + 3) / 4));
     DLAUNCH(dn_backcount<T>, grid, dd, rank, back);
+}
+
+// Internal variables -> the caller's order: dst[cpos[p]] = src[p] (a
+// permutation: every destination written once).
+__global__ __launch_bounds__(BLOCK) void dn_to_caller_k(const double *src, const int32_t *cpos, double *dst, int n)
+{
+    for (int p = blockIdx.x * BLOCK + threadIdx.x; p < n; p += gridDim.x * BLOCK) dst[cpos[p]] = src[p];
+}
+
+void dn_to_caller(const double *src, const int32_t *cpos, double *dst, int64_t n, hipStream_t st)
+{
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + BLOCK - 1) / BLOCK, 4 * GRID_MAX));
+    DLAUNCH(dn_to_caller_k, grid, src, cpos, dst, (int)n);
 }
 
 // ------------------------------------------------------------------ launchers

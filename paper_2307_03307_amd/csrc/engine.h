@@ -187,9 +187,14 @@ struct VcDev {
     int32_t nlong_b;
 };
 
-// Fused densest-subgraph program: variables z_{2e}, z_{2e+1} are the two ends
-// of edge e; vertex rows (packing, scaled by 1/D) are segmented sums over
-// vptr/vvar, edge rows (covering) are pairs.  Every variable lies in one row
+// Fused densest-subgraph program: the variables of edge e are its two ends;
+// vertex rows (packing, scaled by 1/D) are segmented sums over vptr/vvar,
+// edge rows (covering) are pairs.  Internally vertices are numbered by
+// descending degree and edges sorted by (first end, second end), and the
+// variables are two arrays: the first end of internal edge e at e, its second
+// end at ne + e.  A vertex's first-end variables are then one contiguous run
+// and its second-end variables advance together with those of its
+// neighbouring ids.  Every variable lies in one row
 // of each side, so g_i and h_i are single weights and nothing averages the
 // rounding of the direction out: the iterate x, the direction d, the rows y,
 // z, the products Pd, Cd and the LSE totals are FP64 in both forms.  T is the
@@ -203,8 +208,9 @@ struct DnDev {
     LongSegs vlong;
     double *lpart;                        // chunk partials of the forward products
     double *lpart64;                      // chunk partials of the statistics
-    const int32_t *eu, *ev;               // vertex rows of variables 2e and 2e+1
-    double *x, *d;                        // variables
+    const int32_t *eu, *ev;               // first and second end of internal edge e (eu[e] < ev[e])
+    const int32_t *cpos;                  // caller's index (2e' + j) of internal variable p
+    double *x, *d;                        // variables: [first ends (ne) | second ends (ne)]
     double *y;                            // vertex rows (scaled by sP)
     double *dy;
     T *w;
@@ -233,6 +239,8 @@ template <class T> void dn_stats(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L
 template <class T> void dn_main(const DnDev<T> &dd, Ctl *ctl, const DnLaunch &L, hipStream_t st, int which);
 template <class T> void dn_occupancy(int *per_cu_vt, int *per_cu_search);
 template <class T> void dn_backcounts(const DnDev<T> &dd, const int32_t *rank, int32_t *back, hipStream_t st);
+// dst[cpos[p]] = src[p] for p < n (internal variables to the caller's order)
+void dn_to_caller(const double *src, const int32_t *cpos, double *dst, int64_t n, hipStream_t st);
 
 // Batched matching program: many independent packing LPs max 1^T x s.t.
 // M_k x <= 1 (bipartite matching, Section 3) in concatenated arrays.  Tiles

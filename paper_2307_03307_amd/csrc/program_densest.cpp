@@ -19,20 +19,63 @@ class DensestProgram : public Program {
         ne_ = el.ne;
         n_ = 2 * ne_;
         if (n_ >= INT32_MAX) throw ApiError{MWU_ERR_TOO_LARGE, "too many edges"};
-        std::vector<int32_t> eu(ne_), ev(ne_), vptr(nv + 1, 0), vvar(n_);
+        // Internal vertex ids by descending degree (ties: compact id), so the
+        // vertices most edges touch share cache lines.
+        std::vector<int64_t> deg(nv, 0);
+        for (int64_t e = 0; e < ne_; ++e) { deg[vid[el.u[e]]]++; deg[vid[el.v[e]]]++; }
+        int64_t maxdeg = 0;
+        for (int64_t v = 0; v < nv; ++v) maxdeg = std::max(maxdeg, deg[v]);
+        vorder_.assign(nv, 0);
+        std::vector<int32_t> vint(nv);
+        {
+            std::vector<int64_t> cnt(maxdeg + 2, 0);
+            for (int64_t v = 0; v < nv; ++v) cnt[maxdeg - deg[v] + 1]++;
+            for (int64_t b = 0; b <= maxdeg; ++b) cnt[b + 1] += cnt[b];
+            for (int64_t v = 0; v < nv; ++v) vorder_[cnt[maxdeg - deg[v]]++] = (int32_t)v;
+            for (int64_t r = 0; r < nv; ++r) vint[vorder_[r]] = (int32_t)r;
+        }
+        // Internal edges sorted by (first end, second end), first < second in
+        // the internal ids: a stable counting sort by the second end, then by
+        // the first.
+        std::vector<int32_t> fa(ne_), sb(ne_);
+        std::vector<uint8_t> flip(ne_);
         for (int64_t e = 0; e < ne_; ++e) {
-            eu[e] = (int32_t)vid[el.u[e]];
-            ev[e] = (int32_t)vid[el.v[e]];
-            vptr[eu[e] + 1]++;
-            vptr[ev[e] + 1]++;
+            const int32_t a = vint[vid[el.u[e]]], b = vint[vid[el.v[e]]];
+            fa[e] = std::min(a, b);
+            sb[e] = std::max(a, b);
+            flip[e] = a > b;   // the caller's first end is the internal second end
+        }
+        std::vector<int32_t> tmp(ne_), order(ne_);
+        {
+            std::vector<int64_t> cnt(nv + 1, 0);
+            for (int64_t e = 0; e < ne_; ++e) cnt[sb[e] + 1]++;
+            for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+            for (int64_t e = 0; e < ne_; ++e) tmp[cnt[sb[e]]++] = (int32_t)e;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int64_t e = 0; e < ne_; ++e) cnt[fa[e] + 1]++;
+            for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+            for (int64_t i = 0; i < ne_; ++i) order[cnt[fa[tmp[i]]]++] = tmp[i];
+        }
+        edge_of_.assign(order.begin(), order.end());   // internal edge -> caller edge
+        std::vector<int32_t> eu(ne_), ev(ne_), vptr(nv + 1, 0), vvar(n_);
+        cpos_.resize(n_);
+        for (int64_t ie = 0; ie < ne_; ++ie) {
+            const int32_t e = order[ie];
+            eu[ie] = fa[e];
+            ev[ie] = sb[e];
+            // caller variable 2e + j (j = 0: the caller's first end)
+            cpos_[ie] = (int32_t)(2 * (int64_t)e + (flip[e] ? 1 : 0));
+            cpos_[ne_ + ie] = (int32_t)(2 * (int64_t)e + (flip[e] ? 0 : 1));
+            vptr[eu[ie] + 1]++;
+            vptr[ev[ie] + 1]++;
         }
         for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
         {
+            // the variables of a vertex in increasing position: its first ends
+            // (one run of internal edges), then its second ends
             std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
-            for (int64_t e = 0; e < ne_; ++e) {   // variables of a vertex in increasing order
-                vvar[fill[eu[e]]++] = (int32_t)(2 * e);
-                vvar[fill[ev[e]]++] = (int32_t)(2 * e + 1);
-            }
+            for (int64_t ie = 0; ie < ne_; ++ie) vvar[fill[eu[ie]]++] = (int32_t)ie;
+            for (int64_t ie = 0; ie < ne_; ++ie) vvar[fill[ev[ie]]++] = (int32_t)(ne_ + ie);
         }
         TilePlan vt = build_tiles(vptr, nv);
         auto up = [&](DevBuf &b, const void *src, size_t bytes) {
@@ -41,6 +84,7 @@ class DensestProgram : public Program {
         };
         up(eu_, eu.data(), ne_ * 4);
         up(ev_, ev.data(), ne_ * 4);
+        up(cpos_d_, cpos_.data(), n_ * 4);
         up(vptr_, vptr.data(), vptr.size() * 4);
         up(vvar_, vvar.data(), vvar.size() * 4);
         up(vtiles_, vt.tiles.data(), vt.tiles.size() * sizeof(Tile));
@@ -65,7 +109,7 @@ class DensestProgram : public Program {
         dd_.vlong = LongSegs{lseg_.as<int32_t>(), lfirst_.as<int32_t>(), lcount_.as<int32_t>(),
                              (int32_t)vt.lseg.size()};
         dd_.lpart = lpart_.as<double>(); dd_.lpart64 = lpart64_.as<double>();
-        dd_.eu = eu_.as<int32_t>(); dd_.ev = ev_.as<int32_t>();
+        dd_.eu = eu_.as<int32_t>(); dd_.ev = ev_.as<int32_t>(); dd_.cpos = cpos_d_.as<int32_t>();
         dd_.x = x_.as<double>(); dd_.d = d_.as<double>();
         dd_.y = y_.as<double>(); dd_.dy = dy_.as<double>(); dd_.w = w_.as<T>();
         dd_.z = z_.as<double>(); dd_.dz = dz_.as<double>(); dd_.u = u_.as<T>();
@@ -96,7 +140,9 @@ class DensestProgram : public Program {
 
     void upload_x(const double *host_x) override
     {
-        HIP_OK(hipMemcpyAsync(dd_.x, host_x, n_ * 8, hipMemcpyHostToDevice, s_.stream));
+        std::vector<double> t(n_);
+        for (int64_t p = 0; p < n_; ++p) t[p] = host_x[cpos_[p]];
+        HIP_OK(hipMemcpyAsync(dd_.x, t.data(), n_ * 8, hipMemcpyHostToDevice, s_.stream));
         HIP_OK(hipStreamSynchronize(s_.stream));
     }
 
@@ -112,25 +158,23 @@ class DensestProgram : public Program {
         HIP_OK(hipMemcpyAsync(xbest_.p, x_.p, n_ * 8, hipMemcpyDeviceToDevice, s_.stream));
     }
 
-    void best_to_host(double *out) override { copy_host(xbest_.as<double>(), n_, out); }
+    void best_to_host(double *out) override { vars_to_host(xbest_.as<double>(), out); }
 
     void read(int which, double *out, int64_t len) override
     {
         switch (which) {
-        case 0: need(len, n_); copy_host(dd_.x, n_, out); return;
-        case 1: need(len, n_); copy_host(dd_.d, n_, out); return;
+        case 0: need(len, n_); vars_to_host(dd_.x, out); return;
+        case 1: need(len, n_); vars_to_host(dd_.d, out); return;
         case 2:
         case 3:
             need(len, n_);
             if (!dbg_g_.p) throw ApiError{MWU_ERR_STATE, "g/h are recorded by mwu_probe_direction"};
-            HIP_OK(hipMemcpyAsync(out, which == 2 ? dbg_g_.p : dbg_h_.p, n_ * 8, hipMemcpyDeviceToHost,
-                                  s_.stream));
-            HIP_OK(hipStreamSynchronize(s_.stream));
+            vars_to_host(which == 2 ? dbg_g_.as<double>() : dbg_h_.as<double>(), out);
             return;
-        case 4: need(len, nv_); copy_host(dd_.y, nv_, out); return;
-        case 6: need(len, nv_); copy_host(dd_.dy, nv_, out); return;
-        case 5: need(len, ne_); copy_host(dd_.z, ne_, out); return;
-        case 7: need(len, ne_); copy_host(dd_.dz, ne_, out); return;
+        case 4: need(len, nv_); rows_to_host(dd_.y, nv_, vorder_, out); return;
+        case 6: need(len, nv_); rows_to_host(dd_.dy, nv_, vorder_, out); return;
+        case 5: need(len, ne_); rows_to_host(dd_.z, ne_, edge_of_, out); return;
+        case 7: need(len, ne_); rows_to_host(dd_.dz, ne_, edge_of_, out); return;
         }
         throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
     }
@@ -164,14 +208,15 @@ class DensestProgram : public Program {
     void potential(const double *x_dev, double *val_dev, double scale, double *grad_dev,
                    hipStream_t st) override
     {
-        set_debug(true);
-        DnDev<T> g = dbg();
+        // x_dev and grad_dev are in the caller's variable order: the column
+        // pass writes grad_dev through the position map
+        DnDev<T> g = dd_;
+        g.grad = grad_dev;
+        g.grad_scale = scale;
         dn_init<T>(g, ctl(), L_, st, true, x_dev);
         dn_row_pass<T>(g, ctl(), L_, st);
         dn_col_pass<T>(g, ctl(), L_, st);
-        if (grad_dev || val_dev)
-            potential_finish(dbg_g_.as<double>(), dbg_h_.as<double>(), grad_dev ? (int)n_ : 0, scale,
-                             grad_dev, ctl(), val_dev, st);
+        if (val_dev) potential_finish(nullptr, nullptr, 0, scale, nullptr, ctl(), val_dev, st);
     }
 
     bool potential_static(const double *x_dev, double grad_scale, double *grad_dev, void *scr, size_t bytes,
@@ -279,6 +324,22 @@ class DensestProgram : public Program {
     {
         if (len != want) throw ApiError{MWU_ERR_INVALID_ARG, "length mismatch"};
     }
+    // internal variables (first ends, second ends) -> the caller's order,
+    // permuted on the device before the copy
+    void vars_to_host(const double *src, double *out)
+    {
+        if (!export_.p) export_.alloc(n_ * 8);
+        dn_to_caller(src, dd_.cpos, export_.as<double>(), n_, s_.stream);
+        copy_host(export_.as<double>(), n_, out);
+    }
+    // internal rows -> the caller's order (map: internal index -> caller index)
+    void rows_to_host(const double *src, int64_t len, const std::vector<int32_t> &map, double *out)
+    {
+        std::vector<double> t(len);
+        copy_host(src, len, t.data());
+        for (int64_t i = 0; i < len; ++i) out[map[i]] = t[i];
+    }
+
     void copy_host(const double *src, int64_t len, double *out)
     {
         HIP_OK(hipMemcpyAsync(out, src, len * 8, hipMemcpyDeviceToHost, s_.stream));
@@ -292,7 +353,10 @@ class DensestProgram : public Program {
     DnLaunch L_{};
     DevBuf eu_, ev_, vptr_, vvar_, vtiles_, lseg_, lfirst_, lcount_, lpart_, lpart64_;
     DevBuf x_, d_, xbest_, y_, dy_, w_, z_, dz_, u_, partials_, partials2_, forced_, dbg_g_, dbg_h_;
-    DevBuf rank_, back_;
+    DevBuf rank_, back_, cpos_d_, export_;
+    std::vector<int32_t> cpos_;     // internal variable -> caller variable (2e + j)
+    std::vector<int32_t> vorder_;   // internal vertex -> compact vertex id (vertex order)
+    std::vector<int32_t> edge_of_;  // internal edge -> caller edge
     int32_t vslots_ = 0;   // chunk partial slots of the long vertex rows
 };
 
