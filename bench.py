@@ -458,6 +458,38 @@ def run_genmatch(args):
     }
 
 
+def run_reuse(args):
+    """Probe-to-probe reuse (MWU_FLAG_REUSE): probes, iterations, search
+    passes and time of whole solves with and without it, chosen form, for the
+    vertex cover (R-MAT 20), densest subgraph (R-MAT 22) and dominating set
+    (Chung-Lu, 2M vertices) workloads, with Algorithm 3 from 1 and with the
+    warm-started search."""
+    import torch
+    import graphgen as gg
+    import paper_2307_03307_amd as mwu
+    assert torch.cuda.is_available(), "needs an MI355X"
+    g2 = rmat_graph(20, args.edge_factor, 2)
+    g3 = rmat_graph(22, args.edge_factor, 3)
+    g4 = gg.cached("chunglu2m_g23_d10_s4", lambda: gg.chung_lu(2_000_000, 2.3, 10.0, seed=4))
+    ptr4, col4 = gg.adjacency_csr(g4, with_identity=True)
+    makers = {
+        "vcover_rmat20": lambda **k: mwu.vertex_cover(g2.num_vertices, g2.u, g2.v, **k),
+        "densest_rmat22": lambda **k: mwu.densest_subgraph(g3.num_vertices, g3.u, g3.v, **k),
+        "domset_chunglu2m": lambda **k: mwu.dominating_set(ptr4, col4, g4.num_vertices, **k),
+    }
+    out = {"metric": "time-to-(1+eps) with and without probe-to-probe reuse", "unit": "s", "runs": {}}
+    for name, make in makers.items():
+        for rule_name, rule in (("bin", mwu.STEP_BIN), ("warm", mwu.STEP_BIN_WARM)):
+            for reuse in (False, True):
+                s = make(precision=mwu.MIXED_FP32_FP64, step_rule=rule, flags=mwu._lib.FLAG_REUSE if reuse else 0)
+                walls, r = timed_solves(s, 2, 1, f"{name} {rule_name} reuse={reuse}")
+                s.close()
+                out["runs"][f"{name}/{rule_name}/{'reuse' if reuse else 'fresh'}"] = {
+                    "s": statistics.mean(walls), "certified": r.certified, "bracket": [r.lower, r.upper],
+                    "probes": r.probes, "iterations": r.total_iterations, "search_passes": r.search_passes}
+    return out
+
+
 def headline(args, d, workload):
     """Wrap a workload record in the fields of the one-line bench contract."""
     out = {"metric": METRIC, "value": d["value"], "unit": "s", "n_gpus": 1, "steps": args.steps,
@@ -473,7 +505,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch"], default="densest",
+    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch", "reuse"], default="densest",
                     help="densest: the headline R-MAT scale 22 densest subgraph (default); vcover: R-MAT "
                          "vertex cover; batched: 512 matching LPs; genmatch: generalized matching")
     ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default 22 densest, 20 vcover)")
@@ -511,6 +543,8 @@ def main():
     elif args.workload == "batched":
         d = run_batched(args, args.steps, args.warmup)
         out = headline(args, d, d["workload"])
+    elif args.workload == "reuse":
+        out = run_reuse(args)
     else:
         out = run_genmatch(args)
     print(json.dumps(out), flush=True)

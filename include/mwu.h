@@ -132,6 +132,12 @@ typedef struct {
 #define MWU_FLAG_NO_FACTOR2   1u  /* do not double the step when one side is a single row */
 #define MWU_FLAG_GENERIC      2u  /* force the generic CSR engine (no fused graph program) */
 #define MWU_FLAG_NO_TUNE      4u  /* batched: take the default layout, time nothing */
+/* Outer search: every probe after the first starts from the previous probe's
+ * iterate, scaled so that its largest packing row (in the new probe's scale)
+ * is eps -- the level the Algorithm 1 point starts from -- and, with
+ * MWU_STEP_BIN_WARM, searches its first step from the previous probe's last
+ * step.  Single-problem handles; the batched program ignores it. */
+#define MWU_FLAG_REUSE        8u
 
 typedef struct {
     double eps;                 /* accuracy, default 0.1 (Section 6.2) */

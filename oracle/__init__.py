@@ -79,14 +79,17 @@ def lib():
         L.orc_probe.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
                                 vp, ctypes.c_int64, P(_ProbeResult)]
+        L.orc_probe_from.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
+                                     vp, ctypes.c_int64, ctypes.c_double, P(_ProbeResult)]
         L.orc_iteration_terms.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double,
                                           ctypes.c_double, vp] + [vp] * 9 + [vp, vp, vp,
                                                                              ctypes.c_int64, vp, vp, vp]
         for name in ("orc_solve_packing", "orc_solve_covering"):
             getattr(L, name).argtypes = [P(_Mat), ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                                         ctypes.c_int32, vp, P(_SolveResult)]
+                                         ctypes.c_int32, ctypes.c_int32, vp, P(_SolveResult)]
         L.orc_solve_densest.argtypes = [P(_Mat), P(_Mat), vp, vp, ctypes.c_double, ctypes.c_int32,
-                                        ctypes.c_int32, ctypes.c_int32, vp, P(_SolveResult)]
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, P(_SolveResult)]
         L.orc_smax.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
         L.orc_smax.restype = ctypes.c_double
         L.orc_smin.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
@@ -112,6 +115,8 @@ def lib():
                                                  vp, vp, vp, ctypes.c_int64, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
         L.orc_step_search_terms_from.restype = ctypes.c_double
+        L.orc_reuse_start.argtypes = [P(_Mat), ctypes.c_double, ctypes.c_double, vp]
+        L.orc_reuse_start.restype = ctypes.c_int
         L.orc_potential.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double,
                                     ctypes.c_double, vp, vp]
         L.orc_potential.restype = ctypes.c_double
@@ -243,20 +248,29 @@ class ProbeResult:
 
 def probe(P: CSR, sP: float, C: CSR, sC: float, eps: float = 0.1, max_iter: int = 5000,
           step_rule: int = STEP_BIN, x0: Optional[np.ndarray] = None,
-          forced_alpha: Optional[Sequence[float]] = None) -> ProbeResult:
+          forced_alpha: Optional[Sequence[float]] = None, start_alpha: float = 0.0) -> ProbeResult:
     """One MWU feasibility probe (Algorithm 2 + Algorithm 3)."""
     n = P.cols
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     fa = None if forced_alpha is None else np.ascontiguousarray(forced_alpha, dtype=np.float64)
     trace = np.zeros(max_iter)
     r = _ProbeResult()
-    rc = lib().orc_probe(P.c, sP, C.c, sC, eps, max_iter, step_rule, int(x0 is not None),
+    rc = lib().orc_probe_from(P.c, sP, C.c, sC, eps, max_iter, step_rule, int(x0 is not None),
                          x.ctypes.data, _p(fa), 0 if fa is None else fa.shape[0],
-                         trace.ctypes.data, max_iter, ctypes.byref(r))
+                         trace.ctypes.data, max_iter, start_alpha, ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_probe failed: {rc}")
     return ProbeResult(r.status, r.iterations, r.evaluations, r.pack_bound, r.cover_bound,
                        r.last_alpha, r.max_violation, x, trace[:r.iterations].copy())
+
+
+def reuse_start(P: CSR, sP: float, eps: float, x: np.ndarray) -> np.ndarray:
+    """The start of a probe that reuses its predecessor's point (R21): x
+    scaled so that max(sP P x) = eps."""
+    out = np.array(x, dtype=np.float64)
+    if not lib().orc_reuse_start(P.c, sP, eps, out.ctypes.data):
+        raise ValueError("no positive packing row")
+    return out
 
 
 def iteration_terms(P: CSR, sP: float, C: CSR, sC: float, eps: float, x: np.ndarray,
@@ -307,10 +321,10 @@ def _solve_result(r, x) -> SolveResult:
 
 
 def solve_packing(P: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
-                  step_rule: int = STEP_BIN) -> SolveResult:
+                  step_rule: int = STEP_BIN, reuse: bool = False) -> SolveResult:
     x = np.zeros(P.cols)
     r = _SolveResult()
-    rc = lib().orc_solve_packing(P.c, eps, max_iter, max_probes, step_rule, x.ctypes.data,
+    rc = lib().orc_solve_packing(P.c, eps, max_iter, max_probes, step_rule, int(reuse), x.ctypes.data,
                                  ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_solve_packing failed: {rc}")
@@ -318,10 +332,10 @@ def solve_packing(P: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: in
 
 
 def solve_covering(C: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
-                   step_rule: int = STEP_BIN) -> SolveResult:
+                   step_rule: int = STEP_BIN, reuse: bool = False) -> SolveResult:
     x = np.zeros(C.cols)
     r = _SolveResult()
-    rc = lib().orc_solve_covering(C.c, eps, max_iter, max_probes, step_rule, x.ctypes.data,
+    rc = lib().orc_solve_covering(C.c, eps, max_iter, max_probes, step_rule, int(reuse), x.ctypes.data,
                                   ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_solve_covering failed: {rc}")
@@ -329,7 +343,7 @@ def solve_covering(C: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: i
 
 
 def solve_densest(g, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
-                  step_rule: int = STEP_BIN) -> SolveResult:
+                  step_rule: int = STEP_BIN, reuse: bool = False) -> SolveResult:
     O, W, keep = densest_matrices(g)
     _, newid = _nonisolated(g)
     eu = np.ascontiguousarray(newid[g.u], dtype=np.int32)
@@ -337,7 +351,7 @@ def solve_densest(g, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 6
     z = np.zeros(O.cols)
     r = _SolveResult()
     rc = lib().orc_solve_densest(O.c, W.c, eu.ctypes.data, ev.ctypes.data, eps, max_iter,
-                                 max_probes, step_rule, z.ctypes.data, ctypes.byref(r))
+                                 max_probes, step_rule, int(reuse), z.ctypes.data, ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_solve_densest failed: {rc}")
     return _solve_result(r, z)

@@ -405,10 +405,27 @@ int orc_initial_point(const orc_mat *P, double sP, double eps, double *x)
  * replay mode used to compare trajectories.  alpha_trace (nullable, trace_cap
  * entries) receives the accepted steps.
  */
+int orc_probe_from(const orc_mat *P, double sP, const orc_mat *C, double sC, double eps,
+                   int32_t max_iter, int32_t step_rule, int32_t x0_given, double *x,
+                   const double *forced_alpha, int64_t n_forced,
+                   double *alpha_trace, int64_t trace_cap, double start_alpha, orc_probe_result *res);
+
 int orc_probe(const orc_mat *P, double sP, const orc_mat *C, double sC, double eps,
               int32_t max_iter, int32_t step_rule, int32_t x0_given, double *x,
               const double *forced_alpha, int64_t n_forced,
               double *alpha_trace, int64_t trace_cap, orc_probe_result *res)
+{
+    return orc_probe_from(P, sP, C, sC, eps, max_iter, step_rule, x0_given, x, forced_alpha, n_forced,
+                          alpha_trace, trace_cap, 0.0, res);
+}
+
+/* As orc_probe; with the warm-started search (ORC_STEP_BIN_WARM) the first
+ * iteration's search starts at start_alpha when it exceeds 1 (the last step
+ * of a previous probe, R21) instead of at 1. */
+int orc_probe_from(const orc_mat *P, double sP, const orc_mat *C, double sC, double eps,
+                   int32_t max_iter, int32_t step_rule, int32_t x0_given, double *x,
+                   const double *forced_alpha, int64_t n_forced,
+                   double *alpha_trace, int64_t trace_cap, double start_alpha, orc_probe_result *res)
 {
     orc_state st;
     int rc = state_init(&st, P, sP, C, sC, eps, x);
@@ -423,6 +440,7 @@ int orc_probe(const orc_mat *P, double sP, const orc_mat *C, double sC, double e
     orc_matvec(P, sP, x, st.y);            /* y = P x, z = C x */
     orc_matvec(C, sC, x, st.z);
     res->status = ORC_MAX_ITER;
+    double warm = start_alpha;   /* where a warm-started search begins */
     int64_t t;
     for (t = 0; t < max_iter; ++t) {
         double zmin = INFINITY;
@@ -442,12 +460,13 @@ int orc_probe(const orc_mat *P, double sP, const orc_mat *C, double sC, double e
         double alpha;
         if (forced_alpha && t < n_forced) alpha = forced_alpha[t];
         else if (step_rule == ORC_STEP_STD) alpha = 1.0;
-        else if (step_rule == ORC_STEP_BIN_WARM && res->last_alpha > 1.0)
-            alpha = step_search_from(&st, res->last_alpha, &res->evaluations);   /* (R19) */
+        else if (step_rule == ORC_STEP_BIN_WARM && warm > 1.0)
+            alpha = step_search_from(&st, warm, &res->evaluations);   /* (R19) */
         else alpha = step_search(&st, &res->evaluations);
         if (alpha < 1.0) { res->status = ORC_INFEASIBLE; break; }
         if (alpha_trace && t < trace_cap) alpha_trace[t] = alpha;
         res->last_alpha = alpha;
+        warm = alpha;
         for (int64_t i = 0; i < st.n; ++i) x[i] += alpha * st.d[i];
         for (int64_t r = 0; r < st.mP; ++r) st.y[r] += alpha * st.dy[r];
         for (int64_t r = 0; r < st.mC; ++r) st.z[r] += alpha * st.dz[r];
@@ -510,6 +529,25 @@ double orc_eta(int64_t rows_total, double eps) { return 10.0 * log((double)rows_
 
 /* ------------------------------------------------------------ outer search */
 
+/* Start of the next probe when probes reuse their predecessor's point (R21):
+ * the previous iterate x scaled so that its largest packing row under the
+ * next probe's P (values scaled by sP) is eps -- the level the Algorithm 1
+ * point starts from (P x0 <= eps).  Returns 0 when x has no positive
+ * packing row (the caller then takes the Algorithm 1 point). */
+int orc_reuse_start(const orc_mat *P, double sP, double eps, double *x)
+{
+    double *y = malloc((size_t)P->rows * sizeof(double));
+    if (!y) return 0;
+    orc_matvec(P, sP, x, y);
+    double ymax = 0.0;
+    for (int64_t j = 0; j < P->rows; ++j) if (y[j] > ymax) ymax = y[j];
+    free(y);
+    if (!(ymax > 0.0) || !isfinite(ymax)) return 0;
+    double th = eps / ymax;
+    for (int64_t i = 0; i < P->cols; ++i) x[i] *= th;
+    return 1;
+}
+
 typedef struct {
     int32_t status;            /* 0 certified, 1 uncertified, <0 error */
     double objective;          /* value of the returned feasible solution */
@@ -542,8 +580,9 @@ static void ones_row_free(ones_row *o) { free(o->idx); free(o->val); }
  * hi <= (1+eps) lo.
  */
 int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t max_probes,
-                      int32_t step_rule, double *x_best, orc_solve_result *r)
+                      int32_t step_rule, int32_t reuse, double *x_best, orc_solve_result *r)
 {
+    double last = 0.0;   /* the previous probe's last step (R21) */
     int64_t n = P->cols;
     memset(r, 0, sizeof(*r));
     ones_row one;
@@ -586,9 +625,13 @@ int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t ma
         }
         double M = sqrt(slo * shi);
         orc_probe_result pr;
-        rc = orc_probe(P, 1.0, &one.m, 1.0 / M, ep, max_iter, step_rule, 0, x,
-                       NULL, 0, NULL, 0, &pr);
+        {
+            const int warm = reuse && r->probes > 0 && orc_reuse_start(P, 1.0, ep, x);
+            rc = orc_probe_from(P, 1.0, &one.m, 1.0 / M, ep, max_iter, step_rule, warm, x,
+                                NULL, 0, NULL, 0, warm ? last : 0.0, &pr);
+        }
         if (rc) goto done;
+        last = pr.last_alpha;
         r->probes++;
         r->total_iterations += pr.iterations;
         r->final_probe_iterations = pr.iterations;
@@ -628,8 +671,9 @@ done:
  * gives the starting lo).
  */
 int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t max_probes,
-                       int32_t step_rule, double *x_best, orc_solve_result *r)
+                       int32_t step_rule, int32_t reuse, double *x_best, orc_solve_result *r)
 {
+    double last = 0.0;   /* the previous probe's last step (R21) */
     int64_t n = C->cols;
     memset(r, 0, sizeof(*r));
     ones_row one;
@@ -672,9 +716,13 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
         }
         double M = sqrt(slo * shi);
         orc_probe_result pr;
-        rc = orc_probe(&one.m, 1.0 / M, C, 1.0, ep, max_iter, step_rule, 0, x,
-                       NULL, 0, NULL, 0, &pr);
+        {
+            const int warm = reuse && r->probes > 0 && orc_reuse_start(&one.m, 1.0 / M, ep, x);
+            rc = orc_probe_from(&one.m, 1.0 / M, C, 1.0, ep, max_iter, step_rule, warm, x,
+                                NULL, 0, NULL, 0, warm ? last : 0.0, &pr);
+        }
         if (rc) goto done;
+        last = pr.last_alpha;
         r->probes++;
         r->total_iterations += pr.iterations;
         r->final_probe_iterations = pr.iterations;
@@ -756,8 +804,9 @@ out:
  */
 int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, const int32_t *ev,
                       double eps, int32_t max_iter, int32_t max_probes, int32_t step_rule,
-                      double *z_best, orc_solve_result *r)
+                      int32_t reuse, double *z_best, orc_solve_result *r)
 {
+    double last = 0.0;   /* the previous probe's last step (R21) */
     int64_t n = O->cols, nv = O->rows, ne = W->rows;
     memset(r, 0, sizeof(*r));
     double *z = malloc((size_t)n * sizeof(double));
@@ -784,9 +833,13 @@ int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, con
         }
         double D = sqrt(slo * shi);
         orc_probe_result pr;
-        rc = orc_probe(O, 1.0 / D, W, 1.0, ep, max_iter, step_rule, 0, z,
-                       NULL, 0, NULL, 0, &pr);
+        {
+            const int warm = reuse && r->probes > 0 && orc_reuse_start(O, 1.0 / D, ep, z);
+            rc = orc_probe_from(O, 1.0 / D, W, 1.0, ep, max_iter, step_rule, warm, z,
+                                NULL, 0, NULL, 0, warm ? last : 0.0, &pr);
+        }
         if (rc) goto done;
+        last = pr.last_alpha;
         r->probes++;
         r->total_iterations += pr.iterations;
         r->final_probe_iterations = pr.iterations;

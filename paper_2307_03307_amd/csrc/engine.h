@@ -326,6 +326,8 @@ template <class T> void widen(const T *src, double *dst, int64_t n, hipStream_t 
 template <class T> void narrow(const double *src, T *dst, int64_t n, hipStream_t st);
 // Set ctl->phase (single thread).
 void set_phase(Ctl *ctl, int phase, hipStream_t st);
+// v[i * stride] *= th for i < n (a probe started from a scaled earlier point)
+template <class T> void scale_vec(T *v, int64_t n, int64_t stride, double th, hipStream_t st);
 // Continue a probe whose direction was formed in evaluation mode: the stop
 // tests of the iteration, then its step search (forced: the program's forced
 // steps, nullable).

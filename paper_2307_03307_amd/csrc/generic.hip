@@ -451,6 +451,13 @@ __global__ void k_narrow(const double *src, T *dst, int64_t n)
 
 __global__ void k_set_phase(Ctl *ctl, int phase) { ctl->phase = phase; }
 
+template <class T>
+__global__ void k_scale(T *v, int64_t n, int64_t stride, double th)
+{
+    for (int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        v[i * stride] = (T)(th * (double)v[i * stride]);
+}
+
 // Continue a probe after a direction formed in evaluation mode (the probe
 // API): the checks of Algorithm 2 that evaluation mode skipped (covered,
 // iteration cap, zero direction), then the step search of this iteration,
@@ -590,6 +597,14 @@ void set_phase(Ctl *ctl, int phase, hipStream_t st)
 {
     hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(1), 0, st, ctl, phase);
 }
+
+template <class T>
+void scale_vec(T *v, int64_t n, int64_t stride, double th, hipStream_t st)
+{
+    LAUNCH(k_scale<T>, grid_for(n), v, n, stride, th);
+}
+template void scale_vec<float>(float *, int64_t, int64_t, double, hipStream_t);
+template void scale_vec<double>(double *, int64_t, int64_t, double, hipStream_t);
 
 void resume_search(Ctl *ctl, const double *forced, hipStream_t st)
 {

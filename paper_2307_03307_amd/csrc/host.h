@@ -79,6 +79,7 @@ struct Program {
     virtual int64_t mC() const = 0;
     virtual void probe_init(bool have_x0) = 0;
     virtual void upload_x(const double *host_x) = 0;   // host double -> device x
+    virtual void scale_x(double th) = 0;               // device x *= th (the next probe's start)
     virtual void iterations(int slots) = 0;            // enqueue iteration slots
     virtual void final_stats() = 0;                    // fresh Px, Cx statistics into ctl
     virtual void save_best() = 0;

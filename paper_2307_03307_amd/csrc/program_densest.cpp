@@ -146,6 +146,8 @@ class DensestProgram : public Program {
         HIP_OK(hipStreamSynchronize(s_.stream));
     }
 
+    void scale_x(double th) override { scale_vec<double>(dd_.x, n_, 1, th, s_.stream); }
+
     void iterations(int slots) override
     {
         for (int i = 0; i < slots; ++i) dn_iteration<T>(dd_, ctl(), L_, s_.stream);

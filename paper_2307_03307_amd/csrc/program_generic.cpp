@@ -195,6 +195,8 @@ class GenericProgram : public Program {
         HIP_OK(hipStreamSynchronize(s_.stream));
     }
 
+    void scale_x(double th) override { scale_vec<T>(gd_.x, n_, 1, th, s_.stream); }
+
     void iterations(int slots) override
     {
         for (int i = 0; i < slots; ++i) generic_iteration<T>(gd_, ctl(), L_, s_.stream);

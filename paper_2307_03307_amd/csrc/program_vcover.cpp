@@ -180,6 +180,9 @@ class VcoverProgram : public Program {
         HIP_OK(hipStreamSynchronize(s_.stream));
     }
 
+    // x of the interleaved (x, d) pairs; the probe start copies it to xs
+    void scale_x(double th) override { scale_vec<T>(reinterpret_cast<T *>(vd_.xd), nv_, 2, th, s_.stream); }
+
     void iterations(int slots) override
     {
         for (int i = 0; i < slots; ++i) vc_iteration<T>(vd_, ctl(), L_, s_.stream);

@@ -431,7 +431,11 @@ static constexpr double kMixedQmin = 1.0 / 65536.0;
 // without a certified (1 + eps) bracket.
 static constexpr int kMaxHalvings = 2;
 
-static void begin_probe(Solver &s, double param, const double *x0, double eps_probe = 0.0)
+// Start a probe at param: from the Algorithm 1 point, from the host point x0,
+// or (device_x0) from the point the device holds, with the warm-started
+// search beginning at start_alpha in its first iteration.
+static void begin_probe(Solver &s, double param, const double *x0, double eps_probe = 0.0,
+                        bool device_x0 = false, double start_alpha = 0.0)
 {
     Ctl &c = *s.ctl_host;
     std::memset(&c, 0, sizeof(Ctl));
@@ -459,9 +463,10 @@ static void begin_probe(Solver &s, double param, const double *x0, double eps_pr
     c.trace_cap = s.opt.max_iter;
     c.status = ST_RUNNING;
     c.phase = PH_IDLE;
+    c.last_alpha = start_alpha;
     push_ctl(s);
     if (x0) s.prog->upload_x(x0);
-    s.prog->probe_init(x0 != nullptr);
+    s.prog->probe_init(x0 != nullptr || device_x0);
     s.in_probe = true;
     s.dir_pending = false;
     s.probe_param = param;
@@ -550,8 +555,20 @@ static SolveOut solve_impl(Solver &s)
     o.have_best_dev = false;
     o.best_scale = 1.0;
     double eps_probe = eps;
+    // probes after the first may start from their predecessor's point (R21):
+    // its iterate scaled so that the largest packing row of the next probe is
+    // eps (the level of the Algorithm 1 point), and its last step
+    const bool reuse = (s.opt.flags & MWU_FLAG_REUSE) != 0;
+    double prev_pmax = 0.0, prev_sP = 0.0, prev_alpha = 0.0;   // max(P x) in the previous probe's scale
     auto probe_done = [&](double param) {
-        begin_probe(s, param, nullptr, eps_probe);
+        const double sPn = probe_scale_P(s, param);
+        const double pmax = prev_sP > 0.0 ? prev_pmax * sPn / prev_sP : 0.0;
+        if (reuse && o.probes > 0 && pmax > 0.0 && std::isfinite(pmax)) {
+            s.prog->scale_x(eps_probe / pmax);
+            begin_probe(s, param, nullptr, eps_probe, true, prev_alpha);
+        } else {
+            begin_probe(s, param, nullptr, eps_probe);
+        }
         run_probe(s, s.opt.max_iter);
         pull_ctl(s);
         Ctl c = *s.ctl_host;
@@ -562,7 +579,13 @@ static SolveOut solve_impl(Solver &s)
         o.final_iters = c.iter;
         o.passes += c.search_passes;
         o.evals += c.evaluations;
+        prev_alpha = c.last_alpha;
         return c;
+    };
+    // the statistics of the probe just ended (for the next probe's start)
+    auto note_stats = [&](const Ctl &f) {
+        prev_pmax = f.ymax;
+        prev_sP = f.sP;
     };
     if (s.form == MWU_MIXED && s.opt.mixed_fixed_lambda > 0.0) {
         const double lam = s.opt.mixed_fixed_lambda;
@@ -608,6 +631,7 @@ static SolveOut solve_impl(Solver &s)
         const Ctl c = probe_done(param);
         finish_probe_stats(s);
         const Ctl f = *s.ctl_host;
+        note_stats(f);
         if (trace)
             std::fprintf(stderr, "[mwu] probe %lld eps %.4g param %.10g status %d iters %d passes %lld alpha %.6g "
                          "sumx %.10g ymax %.10g zmin %.10g bounds %.10g %.10g bracket %.10g %.10g\n",

@@ -473,3 +473,87 @@ def test_probe_continues_after_time_pass(name):
         alphas = s.probe_read("alpha", info.iterations)
     assert info.iterations == 15
     assert np.array_equal(alphas, ref_alphas[:15])
+
+
+# ------------------------------------------------------------------ probe-to-probe reuse (R21)
+
+def _reuse_start(P, sP, x, eps=EPS):
+    """The previous iterate scaled so that its largest packing row (values
+    scaled by sP) is eps, as the oracle's outer search does."""
+    y = np.zeros(P.rows)
+    oracle.lib().orc_matvec(P.c, sP, np.ascontiguousarray(x).ctypes.data, y.ctypes.data)
+    return x * (eps / y.max())
+
+
+@pytest.mark.parametrize("name", ["vcover", "densest", "domset"])
+def test_probe_from_reused_point_fp64(name):
+    """A probe started from the previous probe's rescaled iterate (FP64).  At
+    that point the direction, g and h match the oracle's to 1e-9; from it the
+    GPU takes the oracle's first 16 steps exactly and ends with its verdict.
+    Whole trajectories are compared for the densest probe only: the covering
+    probes here run 160-170 iterations from a non-uniform start, and the
+    oracle itself amplifies a 1e-13 perturbation of that start 1e11- to
+    1e12-fold by their end (R13), so their late steps are not a kernel check."""
+    case = LONG_PROBES[name]()
+    p2 = case.param * (0.97 if name == "densest" else 1.03)
+    sP2, sC2 = case.sP(p2), case.sC(p2)
+    with case.make_gpu(precision=mwu.FP64) as s:
+        n = s.sizes().n
+        s.probe_begin(case.param)
+        first = s.probe_run(5000)
+        x_prev = s.probe_read("x", n)
+        x0 = _reuse_start(case.P, sP2, x_prev)
+        s.probe_begin(p2, x0)
+        s.probe_direction()
+        got = {k: s.probe_read(k, n) for k in ("g", "h", "d")}
+        info = s.probe_run(5000)
+        alphas = s.probe_read("alpha", info.iterations)
+        xg = s.probe_read("x", n)
+    ref = oracle.iteration_terms(case.P, sP2, case.C, sC2, EPS, x0)
+    errs = {k: rel_err(got[k], ref[k]) for k in ("g", "h", "d")}
+    free = oracle.probe(case.P, sP2, case.C, sC2, EPS, x0=x0)
+    print(f"{name}: first probe {first.iterations} iterations; reused start {info.iterations} "
+          f"(from the Algorithm 1 point: {oracle.probe(case.P, sP2, case.C, sC2, EPS).iterations}); {errs}")
+    assert all(v <= FP64_TOL for v in errs.values()), errs
+    assert info.iterations > 16 and np.array_equal(alphas[:16], free.alphas[:16])
+    assert info.status == free.status
+    if name == "densest":
+        r = oracle.probe(case.P, sP2, case.C, sC2, EPS, x0=x0, forced_alpha=alphas)
+        assert np.array_equal(alphas, free.alphas) and info.iterations == r.iterations
+        assert abs(xg.sum() - r.x.sum()) <= 1e-9 * r.x.sum()
+
+
+@pytest.mark.parametrize("precision", [mwu.FP64, mwu.MIXED_FP32_FP64])
+def test_solve_with_reuse(precision):
+    """Whole outer searches with MWU_FLAG_REUSE: certified brackets around the
+    exact optima (vertex cover, dominating set, densest subgraph, matching)."""
+    from scipy.optimize import linprog
+    F = mwu._lib.FLAG_REUSE
+    g = gg.rmat(13, 16, seed=2)
+    opt = _opt_vcover(g)
+    with mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, flags=F) as s:
+        r = s.solve()
+    assert r.certified and r.lower <= opt * (1 + 1e-12) and opt <= r.upper * (1 + 1e-12)
+    pl = gg.chung_lu(400, 2.3, 6.0, seed=4)
+    ptr, col = gg.adjacency_csr(pl, with_identity=True)
+    D = oracle.dominating_set_matrix(pl).dense()
+    dopt = linprog(np.ones(D.shape[1]), A_ub=-D, b_ub=-np.ones(D.shape[0]), bounds=(0, None)).fun
+    with mwu.dominating_set(ptr, col, pl.num_vertices, precision=precision, flags=F) as s:
+        rd = s.solve()
+    assert rd.certified and rd.lower <= dopt * (1 + 1e-9) and dopt <= rd.upper * (1 + 1e-9)
+    gd = gg.gnm_random(16, 34, seed=5)
+    best = 0.0
+    for mask in range(1, 1 << 16):
+        S = np.array([(mask >> i) & 1 for i in range(16)], bool)
+        best = max(best, np.sum(S[gd.u] & S[gd.v]) / S.sum())
+    with mwu.densest_subgraph(gd.num_vertices, gd.u, gd.v, precision=precision, flags=F) as s:
+        rn = s.solve()
+    assert rn.certified and rn.lower <= best * (1 + 1e-9) and best <= rn.upper * (1 + 1e-9)
+    b = gg.bipartite_uniform(2000, 2000, 20000, seed=1)
+    bopt = _opt_bmatch(b)
+    with mwu.bmatch(b.num_vertices, b.u, b.v, precision=precision, flags=F) as s:
+        rb = s.solve()
+    assert rb.certified and rb.lower <= bopt <= rb.upper * (1 + 1e-12)
+    print(f"reuse precision {precision}: vcover {r.probes} probes {r.total_iterations} iterations; "
+          f"domset {rd.probes}/{rd.total_iterations}; densest {rn.probes}/{rn.total_iterations}; "
+          f"bmatch {rb.probes}/{rb.total_iterations}")

@@ -18,6 +18,8 @@ PKG = os.path.join(ROOT, "oracle")
 
 # C source: (what the slip is, the exact text of the line, the altered text)
 MUTANTS = [
+    ("reuse: start not rescaled to the Algorithm 1 level",
+     "double th = eps / ymax;", "double th = 1.0 / ymax;"),
     ("smax: max shift dropped from the value",
      "return ymax + log(sum) / eta;", "return log(sum) / eta;"),
     ("smin: wrong sign of the log term",

@@ -741,3 +741,72 @@ def test_potential_value_and_gradient(oracle_mod, eta):
             return sum((e * t).exp() for t in y).ln() / e + sum((-e * t).exp() for t in z).ln() / e
         fd = (pot(xp) - pot(xm)) / (2 * h)
         assert abs(Decimal(repr(float(gr[i]))) - fd) < Decimal("1e-12") * max(Decimal(1), abs(fd))
+
+
+# ------------------------------------------------------------------ probe-to-probe reuse (R21)
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_reuse_solves_bracket_exact_optima(oracle_mod, seed):
+    """Outer searches whose probes start from their predecessor's rescaled
+    point (and, warm-started, from its last step) still end certified around
+    the exact optima: Hopcroft-Karp for matching, the double-cover matching
+    for vertex cover, brute force for densest, HiGHS for dominating set."""
+    for rule in (oracle_mod.STEP_BIN, oracle_mod.STEP_BIN_WARM):
+        g = gg.bipartite_uniform(80, 80, 400, seed=seed)
+        r = oracle_mod.solve_bmatch(g, step_rule=rule, reuse=True)
+        assert r.certified and r.probes >= 2
+        _check_packing(g, r, hopcroft_karp(g))
+        g = gg.gnm_random(60, 200, seed=seed)
+        C, keep = oracle_mod.vertex_cover_matrix(g)
+        r = oracle_mod.solve_vcover(g, step_rule=rule, reuse=True)
+        assert r.certified
+        opt = _double_cover_matching(g) / 2.0
+        assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+        g = gg.gnm_random(14, 30, seed=seed + 4)
+        r = oracle_mod.solve_densest(g, step_rule=rule, reuse=True)
+        _check_densest(oracle_mod, g, r, brute_force_density(g))
+        g = gg.chung_lu(200, 2.3, 6.0, seed=seed)
+        D = oracle_mod.dominating_set_matrix(g).dense()
+        opt = linprog(np.ones(D.shape[1]), A_ub=-D, b_ub=-np.ones(D.shape[0]), bounds=(0, None)).fun
+        r = oracle_mod.solve_domset(g, step_rule=rule, reuse=True)
+        assert r.certified
+        _check_covering(D, r, opt)
+
+
+def test_reuse_start_level_and_first_step(oracle_mod):
+    """The reused start sits where the Algorithm 1 point does, max(P x0) = eps
+    under the next probe's scale, and a warm-started probe given a start
+    step searches its first step from there: the first accepted step is the
+    warm search from that value on the same vectors, with the same number of
+    tests (counted by the probe)."""
+    g = gg.bipartite_uniform(60, 50, 300, seed=3)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    one = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    nu = hopcroft_karp(g)
+    r1 = oracle_mod.probe(P, 1.0, one, 1.0 / (0.9 * nu), EPS)
+    x0 = oracle_mod.reuse_start(P, 1.0, EPS, r1.x)
+    assert (P.dense() @ x0).max() == pytest.approx(EPS, rel=1e-14)
+    assert np.allclose(x0 / r1.x, x0[0] / r1.x[0], rtol=1e-14)   # a uniform rescaling
+    # and under a scaled P (the covering form's objective row (1/M) 1^T)
+    C, keep = oracle_mod.vertex_cover_matrix(gg.gnm_random(40, 120, seed=2))
+    nc = C.cols
+    row = oracle_mod.CSR(1, nc, np.array([0, nc]), np.arange(nc), np.ones(nc))
+    xc = np.random.default_rng(5).uniform(0.1, 1.0, nc)
+    xs = oracle_mod.reuse_start(row, 1.0 / 37.0, EPS, xc)
+    assert xs.sum() / 37.0 == pytest.approx(EPS, rel=1e-14)
+    M2 = 0.95 * nu
+    start = float(r1.last_alpha)
+    assert start > 1.0
+    r2 = oracle_mod.probe(P, 1.0, one, 1.0 / M2, EPS, x0=x0, step_rule=oracle_mod.STEP_BIN_WARM,
+                          start_alpha=start, max_iter=1)
+    t = oracle_mod.iteration_terms(P, 1.0, one, 1.0 / M2, EPS, x0)
+    eta = oracle_mod.eta(P.rows + 1, EPS)
+    a, ev = oracle_mod.step_search(t["y"], t["dy"], t["w"], t["LP"], t["z"], t["dz"], t["u"], t["LC"],
+                                   eta, EPS, start=start)
+    assert r2.iterations == 1 and r2.alphas[0] == a and r2.evaluations == ev
+    # without a start step the first search is Algorithm 3 from 1
+    r3 = oracle_mod.probe(P, 1.0, one, 1.0 / M2, EPS, x0=x0, step_rule=oracle_mod.STEP_BIN_WARM, max_iter=1)
+    a1, ev1 = oracle_mod.step_search(t["y"], t["dy"], t["w"], t["LP"], t["z"], t["dz"], t["u"], t["LC"],
+                                     eta, EPS)
+    assert r3.alphas[0] == a1 and r3.evaluations == ev1
