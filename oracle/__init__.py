@@ -35,7 +35,7 @@ _LIB = os.path.join(_HERE, "libmwu_oracle.so")
 
 STATUS_NAMES = {0: "RUNNING", 1: "FEASIBLE", 2: "INFEASIBLE", 3: "MAX_ITER"}
 FEASIBLE, INFEASIBLE, MAX_ITER = 1, 2, 3
-STEP_STD, STEP_BIN, STEP_BIN_WARM = 0, 1, 2
+STEP_STD, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -115,6 +115,13 @@ def lib():
                                                  vp, vp, vp, ctypes.c_int64, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
         L.orc_step_search_terms_from.restype = ctypes.c_double
+        L.orc_newton_search_terms.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_double,
+                                              vp, vp, vp, ctypes.c_int64, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
+        L.orc_newton_search_terms.restype = ctypes.c_double
+        L.orc_step_derivatives.argtypes = [vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int64, ctypes.c_double,
+                                           ctypes.c_double, vp, vp]
+        L.orc_step_derivatives.restype = None
         L.orc_reuse_start.argtypes = [P(_Mat), ctypes.c_double, ctypes.c_double, vp]
         L.orc_reuse_start.restype = ctypes.c_int
         L.orc_potential.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double,
@@ -406,6 +413,28 @@ def step_search(y, dy, w, LP, z, dz, u, LC, eta_, eps, start=None):
     else:
         a = lib().orc_step_search_terms_from(*head, float(start), ctypes.addressof(ev))
     return a, ev.value
+
+
+def newton_search(y, dy, w, LP, z, dz, u, LC, eta_, eps, start):
+    """The Newton step search of reading R20 from `start` on given vectors;
+    returns (alpha, number of T evaluations)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (y, dy, w, z, dz, u)]
+    ev = ctypes.c_int64()
+    a = lib().orc_newton_search_terms(arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                                      arrs[0].shape[0], LP, arrs[3].ctypes.data, arrs[4].ctypes.data,
+                                      arrs[5].ctypes.data, arrs[3].shape[0], LC, eta_, eps, float(start),
+                                      ctypes.addressof(ev))
+    return a, ev.value
+
+
+def step_derivatives(y, dy, z, dz, eta_, alpha):
+    """(Psi'(alpha), Phi'(alpha)) as the Newton search forms them."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (y, dy, z, dz)]
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().orc_step_derivatives(arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[0].shape[0],
+                               arrs[2].ctypes.data, arrs[3].ctypes.data, arrs[2].shape[0], eta_, float(alpha),
+                               ctypes.addressof(a), ctypes.addressof(b))
+    return a.value, b.value
 
 
 def level_set_density(nv: int, eu: np.ndarray, ev: np.ndarray, score: np.ndarray) -> float:

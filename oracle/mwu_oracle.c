@@ -59,6 +59,36 @@
  *       returned at once when it satisfies every covering row (R2), and
  *       otherwise the bracket [it, the last failing value] is bisected as in
  *       R1.
+ *   R20 Newton step search (ORC_STEP_NEWTON; Section 4.2): Newton's method on
+ *       g(alpha) = Phi(alpha)/Psi(alpha) - 1 with g' = (Psi Phi' - Phi Psi') /
+ *       Psi^2, where Psi' and Phi' are the averages of P d and C d under the
+ *       weights of the moved point (the paper's formulas, the denominator of
+ *       Psi' read with Px in place of its printed Pd).  It starts at the step
+ *       the probe accepted last; in a probe's first iteration Algorithm 3
+ *       from 1 gives the step (the exponential search).  Each Newton step
+ *       evaluates the test at its alpha (one evaluation).  A value where the
+ *       test holds and every covering row is met (or alpha = 2^50) is
+ *       returned at once (R2); a failing test at 1 ends the probe (R4).  The
+ *       values tested bracket the largest admissible step between lo (the
+ *       largest that passed, 0 before one has) and hi (the smallest that
+ *       failed, infinite before one has); once hi <= (1 + eps) lo, lo is the
+ *       step, as in Algorithm 3.  Newton's method converges only near its
+ *       root, which a start far from it is not, so a Newton iterate outside
+ *       (lo, hi), or none (Psi = 0, g' >= 0, a value that is not finite), is
+ *       replaced by a safeguard step: 2 alpha while hi is infinite, hi/2
+ *       while lo is 0, else sqrt(lo hi).  Every iterate is clamped to
+ *       [1, 2^50].  Newton stops at alpha_k when its correction |g/g'| is at
+ *       most eps alpha_k (returning alpha_k if the test holds there), or
+ *       after 8 evaluations.  From the alpha it stopped at, the values
+ *       alpha (1-eps)^p, p = 1, 2, ..., each the previous one times (1 - eps)
+ *       and at least 1, are tested in turn; the first where the test holds is
+ *       the step, one at or below lo gives lo (it holds there), and a failing
+ *       test at 1 ends the probe as in R4.
+ *   R21 probe-to-probe reuse (the reuse argument of the outer searches): a
+ *       probe after the first starts from its predecessor's iterate scaled so
+ *       that its largest packing row, under the new probe's scale, is eps --
+ *       the level the Algorithm 1 point starts from -- and a warm-started
+ *       search begins its first iteration at the predecessor's last step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -73,7 +103,7 @@ typedef struct {
 } orc_mat;
 
 enum { ORC_RUNNING = 0, ORC_FEASIBLE = 1, ORC_INFEASIBLE = 2, ORC_MAX_ITER = 3 };
-enum { ORC_STEP_STD = 0, ORC_STEP_BIN = 1, ORC_STEP_BIN_WARM = 2 };
+enum { ORC_STEP_STD = 0, ORC_STEP_BIN = 1, ORC_STEP_BIN_WARM = 2, ORC_STEP_NEWTON = 3 };
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_UNBOUNDED = -2, ORC_ERR_OOM = -3 };
 
 /* Threshold below which 1 + sum(u*expm1(-b)) is taken as too cancelled and the
@@ -86,6 +116,8 @@ enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_UNBOUNDED = -2, ORC_ERR_OOM = -3 };
 #define ORC_MAX_HALVINGS 2
 /* Cap of the exponential phase of Algorithm 3. */
 #define ORC_ALPHA_CAP 1125899906842624.0 /* 2^50 */
+/* Most evaluations of the Newton iteration before its back-off (R20). */
+#define ORC_NEWTON_STEPS 8
 
 /* ------------------------------------------------------------------ basics */
 
@@ -298,6 +330,100 @@ static double step_search_from(orc_state *st, double start, int64_t *evals)
     return bisect(st, alpha, 2.0 * alpha, evals);
 }
 
+/* Psi'(alpha) and Phi'(alpha) (Section 4.2): the averages of dy and dz under
+ * the weights of the moved rows y' = y + alpha dy, z' = z + alpha dz, each
+ * formed with the shift of its largest weight so that no term overflows or
+ * all underflow.  A single row gives its own dy or dz. */
+static void derivatives(const orc_state *st, double alpha, double *dpsi, double *dphi)
+{
+    if (st->mP == 1) *dpsi = st->dy[0];
+    else {
+        double ymx = -INFINITY, num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < st->mP; ++i) {
+            double yp = st->y[i] + alpha * st->dy[i];
+            if (yp > ymx) ymx = yp;
+        }
+        for (int64_t i = 0; i < st->mP; ++i) {
+            double t = exp(st->eta * (st->y[i] + alpha * st->dy[i] - ymx));
+            num += st->dy[i] * t;
+            den += t;
+        }
+        *dpsi = num / den;
+    }
+    if (st->mC == 1) *dphi = st->dz[0];
+    else {
+        double zmn = INFINITY, num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < st->mC; ++j) {
+            double zp = st->z[j] + alpha * st->dz[j];
+            if (zp < zmn) zmn = zp;
+        }
+        for (int64_t j = 0; j < st->mC; ++j) {
+            double t = exp(-st->eta * (st->z[j] + alpha * st->dz[j] - zmn));
+            num += st->dz[j] * t;
+            den += t;
+        }
+        *dphi = num / den;
+    }
+}
+
+/* Newton's method for the step (R20), from `start` (>= 1): Newton steps on
+ * g = Phi/Psi - 1 kept inside the bracket of the values tested so far, each
+ * one evaluation of the test, then the (1-eps)^p back-off from the alpha it
+ * stopped at.  Returns a value < 1 when the test fails at 1. */
+static double step_search_newton(orc_state *st, double start, int64_t *evals)
+{
+    double a = start < 1.0 ? 1.0 : start;
+    double lo = 0.0, hi = INFINITY;        /* largest passing, smallest failing alpha tested */
+    orc_eval e;
+    for (int k = 0;; ++k) {
+        e = evaluate(st, a);
+        ++*evals;
+        if (e.pass) {
+            if (e.zmin_new >= 1.0 || a >= ORC_ALPHA_CAP) return a;     /* (R2) */
+            lo = a;
+        } else {
+            if (!(a > 1.0)) return 0.5;                                /* T(1) fails (R4) */
+            hi = a;
+        }
+        if (hi <= (1.0 + st->eps) * lo) return lo;                     /* bracket of Algorithm 3 */
+        if (k + 1 >= ORC_NEWTON_STEPS) break;
+        double next = NAN;
+        if (e.psi > 0.0) {
+            double dpsi, dphi;
+            derivatives(st, a, &dpsi, &dphi);
+            double g = e.phi / e.psi - 1.0;
+            double gp = (e.psi * dphi - e.phi * dpsi) / (e.psi * e.psi);
+            if (gp < 0.0 && isfinite(g)) {
+                double corr = g / gp;
+                if (fabs(corr) <= st->eps * a) {                       /* converged at a */
+                    if (e.pass) return a;
+                    break;
+                }
+                next = a - corr;
+            }
+        }
+        if (!(next > lo && next < hi)) {                               /* safeguard step */
+            if (hi == INFINITY) next = 2.0 * a;
+            else if (lo == 0.0) next = hi / 2.0;
+            else next = sqrt(lo * hi);
+        }
+        if (next < 1.0) next = 1.0;
+        if (next > ORC_ALPHA_CAP) next = ORC_ALPHA_CAP;
+        a = next;
+    }
+    if (e.pass) return a;
+    double b = a;
+    for (;;) {                                                      /* (1-eps)^p back-off */
+        b *= 1.0 - st->eps;
+        if (b <= lo) return lo;
+        if (b < 1.0) b = 1.0;
+        orc_eval eb = evaluate(st, b);
+        ++*evals;
+        if (eb.pass) return b;
+        if (!(b > 1.0)) return 0.5;                                 /* T(1) fails (R4) */
+    }
+}
+
 /* Algorithm 3: exponential search from alpha = 1, then binary search on
  * [alpha/2, alpha] until (ub-lb) <= eps*lb; returns lb.  Returns a value < 1
  * when T(1) fails (R4). */
@@ -462,6 +588,8 @@ int orc_probe_from(const orc_mat *P, double sP, const orc_mat *C, double sC, dou
         else if (step_rule == ORC_STEP_STD) alpha = 1.0;
         else if (step_rule == ORC_STEP_BIN_WARM && warm > 1.0)
             alpha = step_search_from(&st, warm, &res->evaluations);   /* (R19) */
+        else if (step_rule == ORC_STEP_NEWTON && warm >= 1.0)
+            alpha = step_search_newton(&st, warm, &res->evaluations);   /* (R20) */
         else alpha = step_search(&st, &res->evaluations);
         if (alpha < 1.0) { res->status = ORC_INFEASIBLE; break; }
         if (alpha_trace && t < trace_cap) alpha_trace[t] = alpha;
@@ -890,6 +1018,34 @@ double orc_step_search_terms_from(const double *y, const double *dy, const doubl
     st.eta = eta; st.eps = eps;
     *evals = 0;
     return step_search_from(&st, start, evals);
+}
+
+/* The Newton search of R20 from `start` on given vectors, and the two
+ * derivatives it uses at alpha (testing the search on its own). */
+double orc_newton_search_terms(const double *y, const double *dy, const double *w, int64_t mP,
+                               double LP, const double *z, const double *dz, const double *u,
+                               int64_t mC, double LC, double eta, double eps, double start,
+                               int64_t *evals)
+{
+    orc_state st;
+    memset(&st, 0, sizeof st);
+    st.y = (double *)y; st.dy = (double *)dy; st.w = (double *)w; st.mP = mP; st.LP = LP;
+    st.z = (double *)z; st.dz = (double *)dz; st.u = (double *)u; st.mC = mC; st.LC = LC;
+    st.eta = eta; st.eps = eps;
+    *evals = 0;
+    return step_search_newton(&st, start, evals);
+}
+
+void orc_step_derivatives(const double *y, const double *dy, int64_t mP, const double *z,
+                          const double *dz, int64_t mC, double eta, double alpha, double *dpsi,
+                          double *dphi)
+{
+    orc_state st;
+    memset(&st, 0, sizeof st);
+    st.y = (double *)y; st.dy = (double *)dy; st.mP = mP;
+    st.z = (double *)z; st.dz = (double *)dz; st.mC = mC;
+    st.eta = eta;
+    derivatives(&st, alpha, dpsi, dphi);
 }
 
 /* The search from alpha = 1 (Algorithm 3 as printed). */

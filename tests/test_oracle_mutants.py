@@ -69,6 +69,16 @@ MUTANTS = [
      "if (cov[e] < cmin) cmin = cov[e];", "if (cov[e] > cmin || cmin == INFINITY) cmin = cov[e];"),
     ("densest: returned point not rescaled",
      "z_best[i] = z[i] / cmin;", "z_best[i] = z[i];"),
+    ("Newton: covering derivative weighted toward the largest row",
+     "double t = exp(-st->eta * (st->z[j] + alpha * st->dz[j] - zmn));",
+     "double t = exp(st->eta * (st->z[j] + alpha * st->dz[j] - zmn));"),
+    ("Newton: quotient rule with the wrong sign",
+     "double gp = (e.psi * dphi - e.phi * dpsi) / (e.psi * e.psi);",
+     "double gp = (e.psi * dphi + e.phi * dpsi) / (e.psi * e.psi);"),
+    ("Newton: step taken against the correction",
+     "next = a - corr;", "next = a + corr;"),
+    ("Newton: iterates not kept inside the bracket",
+     "if (!(next > lo && next < hi)) {", "if (!(next == next)) {"),
     ("level sets: edge counted at its first endpoint",
      "cnt[(a > b ? a : b) + 1]++;", "cnt[(a < b ? a : b) + 1]++;"),
 ]

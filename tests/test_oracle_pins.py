@@ -810,3 +810,123 @@ def test_reuse_start_level_and_first_step(oracle_mod):
     a1, ev1 = oracle_mod.step_search(t["y"], t["dy"], t["w"], t["LP"], t["z"], t["dz"], t["u"], t["LC"],
                                      eta, EPS)
     assert r3.alphas[0] == a1 and r3.evaluations == ev1
+
+
+# ------------------------------------------------------------------ Newton step search (R20)
+
+@pytest.mark.parametrize("alpha", [0.5, 7.0, 300.0])
+def test_newton_derivatives_match_definition(oracle_mod, alpha):
+    """Psi'(alpha) and Phi'(alpha) against 60-digit central differences of
+    the definitions (differences of smax and smin, Section 4.1)."""
+    rng = np.random.default_rng(int(alpha * 10) + 3)
+    eta = 200.0
+    m = 9
+    y = rng.uniform(0.2, 0.9, m)
+    dy = rng.uniform(0, 2e-3, m)
+    z = rng.uniform(0.1, 0.8, m)
+    dz = rng.uniform(0, 4e-3, m)
+    dpsi, dphi = oracle_mod.step_derivatives(y, dy, z, dz, eta, alpha)
+    D = lambda v: Decimal(repr(float(v)))
+    E = D(eta)
+
+    def moved(base, step, a, sign):            # sign*ln sum exp(sign*eta*(base+a*step)) / eta
+        return sum((sign * E * (D(b) + a * D(t))).exp() for b, t in zip(base, step)).ln() / E
+
+    a0, h = D(alpha), D(alpha) * Decimal("1e-12")
+    e_psi = (moved(y, dy, a0 + h, 1) - moved(y, dy, a0 - h, 1)) / (2 * h)
+    e_phi = (moved(z, dz, a0 - h, -1) - moved(z, dz, a0 + h, -1)) / (2 * h)
+    assert dpsi == pytest.approx(float(e_psi), rel=1e-12)
+    assert dphi == pytest.approx(float(e_phi), rel=1e-12)
+    # a single row is its own average: the closed form of the embedded objective row
+    a, b = oracle_mod.step_derivatives(y[:1], dy[:1], z[:1], dz[:1], eta, alpha)
+    assert a == dy[0] and b == dz[0]
+
+
+def test_newton_search_lands_below_the_crossing(oracle_mod):
+    """The Newton search returns a step where the test holds (Phi >= Psi),
+    at least 1, within (1 - eps)^2 of the largest admissible step (bracketed
+    by Algorithm 3), from starts far below or above it too (the safeguard
+    steps of R20), unless it returned early with every covering row met;
+    from a start near the crossing it needs few tests."""
+    rng = np.random.default_rng(21)
+    eta = 300.0
+    checked = 0
+    near_evals = []
+    for trial in range(12):
+        y = rng.uniform(0, 0.5, 20)
+        dy = rng.uniform(0, 1e-3, 20)
+        z = rng.uniform(0, 0.3, 25)
+        dz = rng.uniform(1e-4, 2e-3, 25) * rng.uniform(0.5, 4)
+        LP, w, LC, u, T = _scan(oracle_mod, y, dy, z, dz, eta)
+        if not T(1.0):
+            a, _ = oracle_mod.newton_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, 3.0)
+            assert a < 1.0
+            continue
+        a3, _ = oracle_mod.step_search(y, dy, w, LP, z, dz, u, LC, eta, EPS)
+        for s in (1.0, 0.7 * a3 + 0.3, (1 + EPS) * a3, 1.3 * a3, 20.0 * a3):
+            a, ev = oracle_mod.newton_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, max(s, 1.0))
+            assert a >= 1.0 and T(a)
+            if s in (0.7 * a3 + 0.3, 1.3 * a3):
+                near_evals.append(ev)
+            if np.min(z + a * dz) >= 1.0:
+                continue                      # early return (R2)
+            # T is monotone and Algorithm 3 brackets the largest admissible step in [a3, (1+eps) a3]
+            assert a <= (1 + EPS) * a3 and a >= (1 - EPS) ** 2 * a3
+            checked += 1
+    assert checked >= 20
+    # near its root Newton converges in a few steps: within 30% of the
+    # crossing, three tests per search on average (Algorithm 3 needs 8-15 here)
+    assert len(near_evals) >= 20 and np.mean(near_evals) <= 3.0
+
+
+def test_newton_back_off_and_first_iteration(oracle_mod):
+    """Reading R20 on a probe: its first iteration takes Algorithm 3's step
+    from 1 (same step, same count of tests), and a failing test at 1 ends
+    the search below 1 (the probe is infeasible)."""
+    g = gg.bipartite_uniform(60, 50, 300, seed=3)
+    P = oracle_mod.incidence(g)
+    n = P.cols
+    one = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    M = 0.9 * hopcroft_karp(g)
+    r_n = oracle_mod.probe(P, 1.0, one, 1.0 / M, EPS, step_rule=oracle_mod.STEP_NEWTON, max_iter=1)
+    r_b = oracle_mod.probe(P, 1.0, one, 1.0 / M, EPS, step_rule=oracle_mod.STEP_BIN, max_iter=1)
+    assert r_n.alphas[0] == r_b.alphas[0] and r_n.evaluations == r_b.evaluations
+    # T(1) failing: d pointing out of the packing region
+    y = np.array([0.98, 0.5])
+    dy = np.array([0.5, 0.0])
+    z = np.array([0.2, 0.3])
+    dz = np.array([1e-6, 2e-6])
+    eta = 300.0
+    LP, w = oracle_mod.smax(y, eta)
+    LC, u = oracle_mod.smin(z, eta)
+    assert oracle_mod.psi(y, dy, w, eta, LP, 1.0) > oracle_mod.phi(z, dz, u, eta, LC, 1.0)[0]
+    a, ev = oracle_mod.newton_search(y, dy, w, LP, z, dz, u, LC, eta, EPS, 5.0)
+    assert a < 1.0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_newton_solves_bracket_exact_optima(oracle_mod, seed):
+    """Outer searches with the Newton step (R20) end certified around the
+    exact optima; the Newton search tests fewer steps per iteration than
+    Algorithm 3 (Table 2's Nwt and Bin columns)."""
+    rule = oracle_mod.STEP_NEWTON
+    g = gg.bipartite_uniform(80, 80, 400, seed=seed)
+    r = oracle_mod.solve_bmatch(g, step_rule=rule)
+    assert r.certified
+    _check_packing(g, r, hopcroft_karp(g))
+    rb = oracle_mod.solve_bmatch(g)
+    assert r.evaluations / r.total_iterations < rb.evaluations / rb.total_iterations
+    g = gg.gnm_random(60, 200, seed=seed)
+    r = oracle_mod.solve_vcover(g, step_rule=rule)
+    assert r.certified
+    opt = _double_cover_matching(g) / 2.0
+    assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+    g = gg.gnm_random(14, 30, seed=seed + 4)
+    r = oracle_mod.solve_densest(g, step_rule=rule)
+    _check_densest(oracle_mod, g, r, brute_force_density(g))
+    g = gg.chung_lu(200, 2.3, 6.0, seed=seed)
+    D = oracle_mod.dominating_set_matrix(g).dense()
+    opt = linprog(np.ones(D.shape[1]), A_ub=-D, b_ub=-np.ones(D.shape[0]), bounds=(0, None)).fun
+    r = oracle_mod.solve_domset(g, step_rule=rule)
+    assert r.certified
+    _check_covering(D, r, opt)
