@@ -124,6 +124,17 @@ typedef struct {
  * as infeasible), then the same bisection.  The first iteration of a probe
  * starts at 1. */
 #define MWU_STEP_BIN_WARM 2
+/* Newton's method for the step (Section 4.2, the Nwt column of Table 2):
+ * Newton steps on g(alpha) = Phi(alpha)/Psi(alpha) - 1 from the step the
+ * probe accepted last, g' formed from Psi' and Phi' (averages of P d and C d
+ * under the weights of the moved point), each iterate tested once and kept
+ * inside the bracket of the values tested so far (2 alpha, hi/2 or
+ * sqrt(lo hi) replace an iterate outside it); it stops when the correction
+ * is at most eps alpha or after 8 tests, and the values alpha (1-eps)^p are
+ * then tested until one passes.  The first iteration of a probe takes
+ * Algorithm 3's step; with MWU_FLAG_REUSE a probe after the first starts
+ * Newton at the previous probe's last step. */
+#define MWU_STEP_NEWTON 3
 
 #define MWU_FP64 0               /* plain: every vector and sum in double */
 #define MWU_MIXED_FP32_FP64 1    /* vectors and per-element terms in float; LSE totals, search sums,
@@ -143,7 +154,8 @@ typedef struct {
     double eps;                 /* accuracy, default 0.1 (Section 6.2) */
     int32_t max_iter;           /* iterations per probe, default 5000 (Section 6.2) */
     int32_t max_probes;         /* outer search cap, default 64 */
-    int32_t step_rule;          /* MWU_STEP_BIN (default), MWU_STEP_BIN_WARM or MWU_STEP_STD */
+    int32_t step_rule;          /* MWU_STEP_BIN (default), MWU_STEP_BIN_WARM, MWU_STEP_NEWTON or
+                                   MWU_STEP_STD */
     int32_t precision;          /* MWU_MIXED_FP32_FP64 (default) or MWU_FP64 */
     int32_t iters_per_launch;   /* iterations captured per graph launch; 0 = default (16 for one
                                    instance, 8 for a batch) */
@@ -304,6 +316,14 @@ mwu_status mwu_probe_read(void *s, int32_t which, double *out, int64_t len);
  * later mwu_probe_run continues as after mwu_probe_direction alone. */
 mwu_status mwu_probe_eval_steps(void *s, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new);
+
+/* The Newton pass of MWU_STEP_NEWTON at one step alpha > 0: Psi(alpha),
+ * Phi(alpha) and their derivatives Psi'(alpha), Phi'(alpha) (Section 4.2:
+ * the averages of P d and C d under the weights of the moved point
+ * Px + alpha Pd, Cx + alpha Cd), at the current x and direction.  Outputs
+ * are host scalars.  Same state rules as mwu_probe_eval_steps. */
+mwu_status mwu_probe_eval_newton(void *s, double alpha, double *psi, double *phi, double *dpsi,
+                                 double *dphi);
 
 /* Probe-level access to a batched handle: one probe of Algorithm 2 (with the
  * handle's step rule) on every instance at once, instance k at params[k] =

@@ -18,12 +18,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CERTIFIED, COVERING, FEASIBLE_POINT, FEASIBLE_UNCERTIFIED, FP64, INFEASIBLE, MAX_ITER,
-                   MIXED, MIXED_FP32_FP64, PACKING, STEP_BIN, STEP_BIN_WARM, STEP_STD, MwuError)
+                   MIXED, MIXED_FP32_FP64, PACKING, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON, STEP_STD, MwuError)
 
 __all__ = ["Solver", "BatchSolver", "Result", "csr_matrix", "incidence", "incidence_t", "edge_pair",
            "interweave", "bmatch", "vertex_cover", "dominating_set", "densest_subgraph",
            "MwuError", "PACKING", "COVERING", "MIXED", "FP64", "MIXED_FP32_FP64", "STEP_BIN", "STEP_BIN_WARM",
-           "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER", "FEASIBLE_POINT"]
+           "STEP_NEWTON", "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER", "FEASIBLE_POINT"]
 
 VEC = {"x": 0, "d": 1, "g": 2, "h": 3, "y": 4, "z": 5, "dy": 6, "dz": 7, "alpha": 8}
 
@@ -195,6 +195,13 @@ class Solver:
                                                 phi.ctypes.data, zm.ctypes.data),
                    "mwu_probe_eval_steps")
         return psi, phi, zm
+
+    def probe_eval_newton(self, alpha: float):
+        """(Psi, Phi, Psi', Phi') at step alpha: the Newton pass of STEP_NEWTON."""
+        out = [ctypes.c_double() for _ in range(4)]
+        _lib.check(self._L.mwu_probe_eval_newton(self._h, float(alpha), *[ctypes.byref(v) for v in out]),
+                   "mwu_probe_eval_newton")
+        return tuple(v.value for v in out)
 
     def time_pass(self, which: int, reps: int = 20):
         """(average microseconds, algorithmic bytes, nonzeros) of one pass launch."""

@@ -19,7 +19,7 @@ CERTIFIED, FEASIBLE_UNCERTIFIED, INFEASIBLE, MAX_ITER, FEASIBLE_POINT = 0, 1, 2,
 PROBE_RUNNING, PROBE_FEASIBLE, PROBE_INFEASIBLE, PROBE_MAX_ITER = 0, 1, 2, 3
 PACKING, COVERING, MIXED = 0, 1, 2
 MAT_CSR, MAT_INCIDENCE, MAT_INCIDENCE_T, MAT_EDGE_PAIR, MAT_INTERWEAVE = 0, 1, 2, 3, 4
-STEP_STD, STEP_BIN, STEP_BIN_WARM = 0, 1, 2
+STEP_STD, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON = 0, 1, 2, 3
 FP64, MIXED_FP32_FP64 = 0, 1
 FLAG_NO_FACTOR2, FLAG_GENERIC, FLAG_NO_TUNE, FLAG_REUSE = 1, 2, 4, 8
 LAYOUT_DEFAULT, LAYOUT_TUNED, LAYOUT_CACHED, LAYOUT_SET = 0, 1, 2, 3
@@ -28,6 +28,7 @@ EXPORTED = [
     "mwu_default_options", "mwu_create", "mwu_create_batch", "mwu_solve", "mwu_destroy",
     "mwu_status_string", "mwu_num_variables", "mwu_probe_sizes", "mwu_probe_begin",
     "mwu_probe_run", "mwu_probe_direction", "mwu_probe_read", "mwu_probe_eval_steps",
+    "mwu_probe_eval_newton",
     "mwu_potential_forward", "mwu_potential_backward", "mwu_potential_backward_noalloc", "mwu_time_pass",
     "mwu_batch_get_layout", "mwu_batch_set_layout", "mwu_batch_probe_run", "mwu_batch_probe_read",
 ]
@@ -138,6 +139,7 @@ def load() -> ctypes.CDLL:
     L.mwu_probe_direction.argtypes = [vp]
     L.mwu_probe_read.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int64]
     L.mwu_probe_eval_steps.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+    L.mwu_probe_eval_newton.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
     L.mwu_potential_forward.argtypes = [vp, vp, vp, vp]
     L.mwu_potential_backward.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     L.mwu_potential_backward_noalloc.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp]

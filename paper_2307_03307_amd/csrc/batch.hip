@@ -307,11 +307,12 @@ MWU_DEV void kb_search_rows(const BatchDev<T> &b, const BTile &tl, const Ctl *c,
     const double eta = c->eta, a0 = c->cand[0], ga0 = c->ga0, gdel = c->gdelta, dymax = c->dymax;
     const uint32_t shm = shifted_mask(c);
     const int nc = c->ncand;
+    const bool deriv = c->skind == SK_NEWTON;
     double s1[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) s1[k] = 0.0;
     for (int i = tl.i0 + threadIdx.x; i < tl.i1; i += BLOCK)
-        pack_terms<T, KIND>(nc, c->cand, a0, ga0, gdel, eta, b.w[i], b.dy[i], dymax, shm, s1);
+        pack_terms<T, KIND>(nc, c->cand, a0, ga0, gdel, eta, b.w[i], b.dy[i], dymax, shm, s1, deriv);
     const Red redp{KC, 0, 0};
     block_combine<KC>(s1, redp, 0, s_wave, s_rec);
 }
@@ -329,6 +330,7 @@ __global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
             const double a = c->ref_alpha, eta = c->eta;
             double v[2];
             const int i1 = tl.i1;
+            int nq = 2;
             if (c->ref_valid == 0) {          // pass 1: [min z' (no covering rows) | max eta y']
                 v[0] = INFINITY;
                 v[1] = -INFINITY;
@@ -336,16 +338,20 @@ __global__ __launch_bounds__(BLOCK) void kb_search(BatchDev<T> b)
                     v[1] = fmax(v[1], eta * ((double)b.y[i] + a * (double)b.dy[i]));
                 const Red red{0, 1, 1};
                 block_combine<2>(v, red, 0, s_wave, s_rec);
-            } else {                          // pass 2: [sum exp(eta y' - pm) | -]
+            } else {                          // pass 2: [sum exp(eta y' - pm) | - | its derivative sum | -]
                 const double pm = c->rfPm;
-                v[0] = 0.0;
-                v[1] = 0.0;
-                for (int i = tl.i0 + threadIdx.x; i < i1; i += BLOCK)
-                    v[0] += exp(eta * ((double)b.y[i] + a * (double)b.dy[i]) - pm);
-                const Red red{2, 0, 0};
-                block_combine<2>(v, red, 0, s_wave, s_rec);
+                double v4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int i = tl.i0 + threadIdx.x; i < i1; i += BLOCK) {
+                    const double dv = (double)b.dy[i];
+                    const double t = exp(eta * ((double)b.y[i] + a * dv) - pm);
+                    v4[0] += t;
+                    v4[2] += dv * t;
+                }
+                const Red red{4, 0, 0};
+                block_combine<4>(v4, red, 0, s_wave, s_rec);
+                nq = 4;
             }
-            if (threadIdx.x < 2) rec[threadIdx.x] = s_rec[threadIdx.x];
+            if (threadIdx.x < nq) rec[threadIdx.x] = s_rec[threadIdx.x];
             return;
         }
         switch (c->skind) {
@@ -370,8 +376,8 @@ __global__ __launch_bounds__(BLOCK) void kb_search_fin(BatchDev<T> b)
     const double *part = b.wpart + (size_t)b.wrec0[k] * QMAX;
     const int G = b.wrecn[k];
     if (c->skind == SK_REFINE) {
-        const Red red = c->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
-        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+        if (c->ref_valid == 0) fold_records<2>(part, G, Red{0, 1, 1}, 0, s_wave, s_rec);
+        else fold_records<4>(part, G, Red{4, 0, 0}, 0, s_wave, s_rec);
     } else {
         const Red red{KC, 0, 0};
         fold_records<KC>(part, G, red, 0, s_wave, s_rec);

@@ -325,12 +325,13 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
     const double *cand = ctl->cand;
     const double a0 = ctl->cand[0], ga0 = ctl->ga0, gdel = ctl->gdelta, dymax = ctl->dymax;
     const uint32_t shm = shifted_mask(ctl);
+    const bool deriv = ctl->skind == SK_NEWTON;
     {
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
         for (int r = r0; r < dd.nv; r += stride)
-            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], (T)dd.dy[r], dymax, shm, s1);
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], (T)dd.dy[r], dymax, shm, s1, deriv);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }
@@ -339,7 +340,7 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
         ca.init(pass_minima<KIND>());
         for (int e = r0; e < dd.ne; e += stride)
             cov_terms<T, KIND, double>(nc, cand, a0, ga0, gdel, eta, dd.u[e], dd.z[e], (T)dd.dz[e], ca.acc,
-                                       ca.zmn);
+                                       ca.zmn, deriv);
         ca.combine(s_wave, s_rec + KC);
     }
 }
@@ -355,25 +356,30 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
         const double a = ctl->ref_alpha, eta = ctl->eta;
         const int stride = gridDim.x * BLOCK;
         const int r0 = blockIdx.x * BLOCK + threadIdx.x;
-        double v[2];
         if (ctl->ref_valid == 0) {   // [min z' | max eta y']
-            v[0] = INFINITY;
-            v[1] = -INFINITY;
+            double v[2] = {INFINITY, -INFINITY};
             for (int r = r0; r < dd.nv; r += stride) v[1] = fmax(v[1], eta * (dd.y[r] + a * dd.dy[r]));
             for (int e = r0; e < dd.ne; e += stride) v[0] = fmin(v[0], dd.z[e] + a * dd.dz[e]);
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
-        } else {                     // [sum over packing rows | sum over covering rows]
+            store_record(s_rec, 2, part);
+        } else {                     // [sum over packing rows | over covering rows | their derivative sums]
             const double pm = ctl->rfPm, zm = ctl->rfZmin;
-            v[0] = 0.0;
-            v[1] = 0.0;
-            for (int r = r0; r < dd.nv; r += stride) v[0] += exp(eta * (dd.y[r] + a * dd.dy[r]) - pm);
-            for (int e = r0; e < dd.ne; e += stride)
-                v[1] += exp(-eta * ((dd.z[e] + a * dd.dz[e]) - zm));
-            const Red red{2, 0, 0};
-            block_combine<2>(v, red, 0, s_wave, s_rec);
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int r = r0; r < dd.nv; r += stride) {
+                const double t = exp(eta * (dd.y[r] + a * dd.dy[r]) - pm);
+                v[0] += t;
+                v[2] += dd.dy[r] * t;
+            }
+            for (int e = r0; e < dd.ne; e += stride) {
+                const double t = exp(-eta * ((dd.z[e] + a * dd.dz[e]) - zm));
+                v[1] += t;
+                v[3] += dd.dz[e] * t;
+            }
+            const Red red{4, 0, 0};
+            block_combine<4>(v, red, 0, s_wave, s_rec);
+            store_record(s_rec, 4, part);
         }
-        store_record(s_rec, 2, part);
         return;
     }
     switch (kind) {
@@ -391,8 +397,8 @@ __global__ __launch_bounds__(BLOCK) void dn_search_fin(Ctl *ctl, const double *p
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_SEARCH) return;
     if (ctl->skind == SK_REFINE) {
-        const Red red = ctl->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
-        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+        if (ctl->ref_valid == 0) fold_records<2>(part, G, Red{0, 1, 1}, 0, s_wave, s_rec);
+        else fold_records<4>(part, G, Red{4, 0, 0}, 0, s_wave, s_rec);
     } else {
         const Red red{3 * KC, KC, 0};
         fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);

@@ -418,7 +418,7 @@ MWU_DEV void cov_adding(double b0d, double bdd, T u, T *s1, T *s2)
 // case: the terms come out as 0 and u.
 template <class T, int KIND, class Z = T>
 MWU_DEV void cov_terms(int nc, const double *cand, double a0, double ga0, double gdel, double eta, T u, Z z,
-                       T dz, T *acc, Z *zmn)
+                       T dz, T *acc, Z *zmn, bool deriv = false)
 {
     if constexpr (KIND == SK_LIST) {   // arbitrary candidates, direct evaluation
 #pragma unroll
@@ -430,6 +430,8 @@ MWU_DEV void cov_terms(int nc, const double *cand, double a0, double ga0, double
                 acc[k] += u * expm1_t(-b);
                 acc[KC + k] += u * exp_t(-b);
             }
+        // Newton pass: the sum of Phi' at cand[0], u dz e^{-b_0} (slot KN, past its values)
+        if (deriv) acc[KN] += u * dz * exp_t(-(T)(eta * cand[0] * (double)dz));
     } else {
         if constexpr (pass_minima<KIND>() > 0) {
             Z ak = (Z)a0;
@@ -470,7 +472,7 @@ MWU_DEV uint32_t shifted_mask(const Ctl *c)
 // grid).
 template <class T, int KIND>
 MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, double gdel, double eta, T w, T dy,
-                        double dymax, uint32_t shmask, double *s1)
+                        double dymax, uint32_t shmask, double *s1, bool deriv = false)
 {
     const double dyd = (double)dy;
     const double dsh = dyd - dymax;   // <= 0
@@ -521,6 +523,12 @@ MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, doubl
                                                  : expm1_t((T)(eta * cand[k] * dyd));
                 s1[k] += (double)(w * v);
             }
+        // Newton pass: the sum of Psi' at cand[0], w dy e^{eta a_0 dy}, max-shifted as
+        // cand[0]'s own sum is (slot KN, past its values)
+        if (deriv) {
+            const T v0 = (shmask & 1u) ? exp_arg(eta * cand[0] * dsh, T(0)) : exp_arg(eta * cand[0] * dyd, T(0));
+            s1[KN] += (double)(w * dy * v0);
+        }
     } else {
         if constexpr (KIND == SK_EXP || KIND == SK_COMBO) doubling(eta * a0 * dyd, eta * a0 * dsh, s1);
         if constexpr (KIND == SK_GRID) adding(eta * a0 * dyd, eta * gdel * dyd, eta * a0 * dsh, eta * gdel * dsh, 0, s1);
@@ -833,6 +841,32 @@ MWU_DEV void setup_first_warm(Ctl *c, double la)
     c->gdelta = la / 16.0;
 }
 
+// Values per Newton pass: the iterate and the first back-off values below it.
+constexpr int NB = 4;
+// Most Newton evaluations of one step search before the back-off.
+constexpr int NEWTON_STEPS = 8;
+
+// A list pass over a and the back-off values after it, a (1-eps), a
+// (1-eps)^2, ..., each the previous one times (1 - eps) with exactly the
+// arithmetic of the sequential back-off, the first one at most 1 clamped to
+// 1 and last; at most nmax values.  A Newton pass (kind SK_NEWTON) also forms
+// the derivative sums at a.
+MWU_DEV void setup_ladder(Ctl *c, double a, int kind, int nmax)
+{
+    int n = 0;
+    double b = a;
+    c->cand[n++] = b;
+    while (n < nmax && b > 1.0) {
+        b *= 1.0 - c->eps;
+        if (b < 1.0) b = 1.0;
+        c->cand[n++] = b;
+    }
+    c->skind = kind;
+    c->ncand = n;
+    c->ga0 = a;
+    c->gdelta = 0.0;
+}
+
 MWU_DEV void setup_refine(Ctl *c, double a)
 {
     c->skind = SK_REFINE;
@@ -901,6 +935,52 @@ MWU_DEV int lookup(const Ctl *c, const CandRegs &cr, double a, Eval *e)
         *e = eval_cand(c, k, a);
     }
     return e->ok ? 0 : 2;
+}
+
+// Psi'(a) and Phi'(a) at the first value a of a Newton pass (Section 4.2):
+// the averages of P d and C d under the weights of the moved point, each the
+// pass's slot-KN sum over a's own sum (sum w e^{eta a dy} = sum w + the
+// expm1 sum, or the max-shifted sum when a's packing sum took that form;
+// sum u e^{-eta a dz} on the covering side).  False when a denominator is
+// not usable: the refinement then forms both with exact shifts.
+MWU_DEV bool newton_derivs(const Ctl *c, double *dpsi, double *dphi)
+{
+    if (c->onesP) {
+        *dpsi = c->dy1;
+    } else {
+        const bool sh = c->psi_shift && c->eta * c->cand[0] * c->dymax > c->psi_lim;
+        const double den = sh ? c->rS1P[0] : 1.0 / c->invSw + c->rS1P[0];
+        if (!(den > 0.0)) return false;
+        *dpsi = c->rS1P[KN] / den;
+    }
+    if (c->onesC) {
+        *dphi = c->dz1;
+    } else {
+        const double den = c->rS2C[0];
+        if (!(den > 0.0)) return false;
+        *dphi = c->rS1C[KN] / den;
+    }
+    return isfinite(*dpsi) && isfinite(*dphi);
+}
+
+// The evaluation of a Newton iterate a with its derivatives: from a
+// refinement at a, or as the first value of a Newton pass.  Returns 0 =
+// found, 1 = no pass has it, 2 = needs refinement.
+MWU_DEV int newton_lookup(const Ctl *c, double a, Eval *e, double *dpsi, double *dphi)
+{
+    if (c->ref_valid == 1 && c->ref_alpha == a) {
+        e->psi = c->ref_psi; e->phi = c->ref_phi; e->zmin = c->ref_zmin; e->ok = 1;
+        *dpsi = c->ref_dpsi; *dphi = c->ref_dphi;
+        return 0;
+    }
+    if (c->skind != SK_NEWTON || c->cand[0] != a) return 1;
+    if (c->ev_cached) {
+        e->psi = c->ev_psi[0]; e->phi = c->ev_phi[0]; e->zmin = c->ev_zmin[0]; e->ok = c->ev_ok[0];
+    } else {
+        *e = eval_cand(c, 0, a);
+    }
+    if (!e->ok) return 2;
+    return newton_derivs(c, dpsi, dphi) ? 0 : 2;
 }
 
 // Store the reduced record of a grid or list pass and evaluate all its
@@ -987,6 +1067,67 @@ MWU_DEV void replay(Ctl *c)
             c->ub = b;
             continue;
         }
+        if (c->amode == AM_NEWTON) {
+            // Newton's method on g = Phi/Psi - 1 inside the bracket (lb, ub) of
+            // the values tested (Section 4.2, reading R20): one evaluation
+            // per iterate, which leads its own pass
+            const double a = c->cur_alpha;
+            Eval e;
+            double dps = 0.0, dph = 0.0;
+            const int r = newton_lookup(c, a, &e, &dps, &dph);
+            if (r == 1) { setup_ladder(c, a, SK_NEWTON, NB); return; }
+            if (r == 2) { setup_refine(c, a); return; }
+            c->evaluations += 1;
+            c->nw_evals += 1;
+            const bool pass = e.phi >= e.psi;
+            if (pass) {
+                if (e.zmin >= 1.0 || a >= ALPHA_CAP) { accept_step(c, a, e.psi, e.phi); return; }
+                c->lb = a; c->lb_psi = e.psi; c->lb_phi = e.phi;
+            } else {
+                if (!(a > 1.0)) { stop_infeasible(c); return; }
+                c->ub = a;
+            }
+            if (c->ub <= (1.0 + c->eps) * c->lb) { accept_step(c, c->lb, c->lb_psi, c->lb_phi); return; }
+            bool stop = c->nw_evals >= NEWTON_STEPS;
+            double next = NAN;
+            if (!stop && e.psi > 0.0) {
+                const double g = e.phi / e.psi - 1.0;
+                const double gp = (e.psi * dph - e.phi * dps) / (e.psi * e.psi);
+                if (gp < 0.0 && isfinite(g)) {
+                    const double corr = g / gp;
+                    if (fabs(corr) <= c->eps * a) stop = true;   // converged at a
+                    else next = a - corr;
+                }
+            }
+            if (stop) {
+                if (pass) { accept_step(c, a, e.psi, e.phi); return; }
+                c->amode = AM_BACKOFF;   // from a (cur_alpha)
+                continue;
+            }
+            if (!(next > c->lb && next < c->ub)) {   // safeguard step
+                if (c->ub == INFINITY) next = 2.0 * a;
+                else if (c->lb == 0.0) next = c->ub / 2.0;
+                else next = sqrt(c->lb * c->ub);
+            }
+            if (next < 1.0) next = 1.0;
+            if (next > ALPHA_CAP) next = ALPHA_CAP;
+            c->cur_alpha = next;
+            continue;
+        }
+        if (c->amode == AM_BACKOFF) {   // b = a (1-eps)^p below the value Newton stopped at
+            double b = c->cur_alpha * (1.0 - c->eps);
+            if (b <= c->lb) { accept_step(c, c->lb, c->lb_psi, c->lb_phi); return; }
+            if (b < 1.0) b = 1.0;
+            Eval e;
+            const int r = lookup(c, cr, b, &e);
+            if (r == 1) { setup_ladder(c, b, SK_LIST, KN); return; }
+            if (r == 2) { setup_refine(c, b); return; }
+            c->evaluations += 1;
+            if (e.phi >= e.psi) { accept_step(c, b, e.psi, e.phi); return; }
+            if (!(b > 1.0)) { stop_infeasible(c); return; }
+            c->cur_alpha = b;
+            continue;
+        }
         // AM_BIS
         if (!(c->ub - c->lb > c->eps * c->lb)) { accept_step(c, c->lb, c->lb_psi, c->lb_phi); return; }
         const double beta = (c->lb + c->ub) / 2.0;
@@ -1022,7 +1163,14 @@ MWU_DEV void begin_search(Ctl *c, const double *forced)
     }
     c->amode = AM_EXP;
     c->have_cur = 0;
-    if (c->step_rule == SR_BIN_WARM && c->last_alpha > 1.0) {   // warm start at the previous step
+    if (c->step_rule == SR_NEWTON && c->last_alpha >= 1.0) {   // Newton from the previous step
+        c->amode = AM_NEWTON;
+        c->cur_alpha = c->last_alpha;
+        c->lb = 0.0;
+        c->ub = INFINITY;
+        c->nw_evals = 0;
+        setup_ladder(c, c->cur_alpha, SK_NEWTON, NB);
+    } else if (c->step_rule == SR_BIN_WARM && c->last_alpha > 1.0) {   // warm start at the previous step
         c->exp_next = c->last_alpha;
         setup_first_warm(c, c->last_alpha);
     } else {
@@ -1034,7 +1182,9 @@ MWU_DEV void begin_search(Ctl *c, const double *forced)
 
 // Store the reduced record of a search pass and advance the state machine.
 // rec layout: grid passes [s1P(KC) | s1C(KC) | s2C(KC) | zmin'(KC)];
-// refine pass 1 [min z' | max eta*y']; refine pass 2 [sumP | sumC].
+// refine pass 1 [min z' | max eta*y']; refine pass 2 [sumP | sumC | sumP' |
+// sumC'], the last two the derivative sums sum dy e^{eta y' - pm} and
+// sum dz e^{-eta (z' - zm)} with the shifts of the first two.
 MWU_DEV void finish_search(Ctl *c, const double *rec, bool pre_evaluated = false)
 {
     if (held(c)) return;
@@ -1047,16 +1197,18 @@ MWU_DEV void finish_search(Ctl *c, const double *rec, bool pre_evaluated = false
             return;
         }
         const double a = c->ref_alpha;
-        double psi, phi, zmn;
-        if (c->onesP) psi = a * c->dy1;
-        else psi = (c->rfPm + log(rec[0])) / c->eta - c->LP;
-        if (c->onesC) { phi = a * c->dz1; zmn = c->z1 + a * c->dz1; }
-        else { zmn = c->rfZmin; phi = zmn - c->LC - log(rec[1]) / c->eta; }
+        double psi, phi, zmn, dps, dph;
+        if (c->onesP) { psi = a * c->dy1; dps = c->dy1; }
+        else { psi = (c->rfPm + log(rec[0])) / c->eta - c->LP; dps = rec[2] / rec[0]; }
+        if (c->onesC) { phi = a * c->dz1; zmn = c->z1 + a * c->dz1; dph = c->dz1; }
+        else { zmn = c->rfZmin; phi = zmn - c->LC - log(rec[1]) / c->eta; dph = rec[3] / rec[1]; }
         c->ref_psi = psi; c->ref_phi = phi; c->ref_zmin = zmn;
+        c->ref_dpsi = dps; c->ref_dphi = dph;
         c->ref_valid = 1;
         if (c->eval_mode) {
             const int k = c->ev_cur;
             c->ev_psi[k] = psi; c->ev_phi[k] = phi; c->ev_zmin[k] = zmn; c->ev_ok[k] = 1;
+            if (k == 0) { c->ev_dpsi = dps; c->ev_dphi = dph; }
         }
     } else if (!pre_evaluated) {
         for (int k = 0; k < KC; ++k) {
@@ -1072,6 +1224,12 @@ MWU_DEV void finish_search(Ctl *c, const double *rec, bool pre_evaluated = false
                 c->ev_psi[k] = e.psi; c->ev_phi[k] = e.phi; c->ev_zmin[k] = e.zmin; c->ev_ok[k] = e.ok;
             }
         }
+    }
+    if (c->eval_mode && c->skind == SK_NEWTON) {
+        // derivatives at cand[0]; when the pass cannot give them, cand[0] is refined
+        double dps, dph;
+        if (c->ev_ok[0] && newton_derivs(c, &dps, &dph)) { c->ev_dpsi = dps; c->ev_dphi = dph; }
+        else c->ev_ok[0] = 0;
     }
     if (c->eval_mode) {
         // refine, one at a time, every candidate the grid pass could not resolve

@@ -14,6 +14,7 @@ constexpr int KE = 8;                    // candidates of an exponential-grid pa
 constexpr int KG = 15;                   // candidates of a bisection pass (complete tree of depth 4)
 constexpr int KC = KE + KG;              // most step candidates in one search pass
 constexpr int KL = 16;                   // most candidates of a list pass (direct evaluation)
+constexpr int KN = KL - 1;               // values of a Newton pass; its slot KN holds the derivative sums
 constexpr int QMAX = 4 * KC + 8;         // doubles per block in a reduction record
 
 // Phase of the per-probe state machine.  Every kernel of the iteration graph
@@ -43,13 +44,16 @@ enum SKind : int32_t {
     SK_GRID = 1,     // cand[j] ~ a0 + j * delta      (bisection tree of depth 4)
     SK_LIST = 2,     // arbitrary values, direct evaluation
     SK_REFINE = 3,   // one value, max-shifted evaluation of both LSE differences
-    SK_COMBO = 4     // the exponential grid from 1 (KE) followed by the bisection tree of the
+    SK_COMBO = 4,    // the exponential grid from 1 (KE) followed by the bisection tree of the
                      // octave the previous step fell in (KG): cand[KE + j] ~ ga0 + j * delta
+    SK_NEWTON = 5    // a list pass (at most KN values, the Newton iterate first) that also
+                     // forms, in slot KN, the sums of Psi' and Phi' at cand[0]
 };
 
-enum AMode : int32_t { AM_EXP = 0, AM_BIS = 1, AM_FORCED = 2, AM_EVAL = 3, AM_DOWN = 4 };
+enum AMode : int32_t { AM_EXP = 0, AM_BIS = 1, AM_FORCED = 2, AM_EVAL = 3, AM_DOWN = 4, AM_NEWTON = 5,
+                       AM_BACKOFF = 6 };
 // Ctl::step_rule values (the MWU_STEP_* of the C interface)
-enum StepRule : int32_t { SR_STD = 0, SR_BIN = 1, SR_BIN_WARM = 2 };
+enum StepRule : int32_t { SR_STD = 0, SR_BIN = 1, SR_BIN_WARM = 2, SR_NEWTON = 3 };
 
 // A contiguous piece of a CSR-like structure handled by one workgroup:
 // segments [s0, s1) with nonzeros [k0, k1).  A segment longer than TILE_NZ is
@@ -106,8 +110,10 @@ struct Ctl {
     double ga0, gdelta;
     double exp_next, cur_alpha, cur_psi, cur_phi;
     double lb, ub, lb_psi, lb_phi;
-    int32_t ref_valid, pad2;
+    int32_t ref_valid, nw_evals;       // nw_evals: Newton evaluations of this search
     double ref_alpha, ref_psi, ref_phi, ref_zmin;
+    double ref_dpsi, ref_dphi;          // Psi', Phi' at ref_alpha (refine pass 2)
+    double ev_dpsi, ev_dphi;            // evaluation mode: Psi', Phi' at cand[0] of a Newton pass
     // results of the last grid pass (raw sums, before normalization)
     double rS1P[KC], rS1C[KC], rS2C[KC], rZmin[KC];
     // results of the last refine pass (max-shifted pairs)

@@ -349,12 +349,13 @@ __device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_w
     const double a0 = ctl->cand[0], ga0 = ctl->ga0, dymax = ctl->dymax;
     const uint32_t shm = shifted_mask(ctl);
     const double gdel = ctl->gdelta;
+    const bool deriv = ctl->skind == SK_NEWTON;
     {
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
         for (int r = r0; r < mPc; r += stride)
-            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.dyz[r], dymax, shm, s1);
+            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.dyz[r], dymax, shm, s1, deriv);
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }
@@ -362,7 +363,8 @@ __device__ void search_rows(const GenericDev<T> &gd, const Ctl *ctl, double *s_w
         CovAcc<T> ca;
         ca.init(pass_minima<KIND>());
         for (int r = mPc + r0; r < mR; r += stride)
-            cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn);
+            cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, gd.wu[r], gd.yz[r], gd.dyz[r], ca.acc, ca.zmn,
+                               deriv);
         ca.combine(s_wave, s_rec + KC);
     }
 }
@@ -392,17 +394,25 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
             store_record(s_rec, 2, part);
-        } else {
+        } else {                  // [sumP | sumC | sumP' | sumC']
             const double pm = ctl->rfPm, zm = ctl->rfZmin;
-            double v[2] = {0.0, 0.0};
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
             for (int r = r0; r < mR; r += stride) {
-                const double yp = (double)gd.yz[r] + a * (double)gd.dyz[r];
-                if (r < mPc) v[0] += exp(eta * yp - pm);
-                else v[1] += exp(-eta * (yp - zm));
+                const double dv = (double)gd.dyz[r];
+                const double yp = (double)gd.yz[r] + a * dv;
+                if (r < mPc) {
+                    const double t = exp(eta * yp - pm);
+                    v[0] += t;
+                    v[2] += dv * t;
+                } else {
+                    const double t = exp(-eta * (yp - zm));
+                    v[1] += t;
+                    v[3] += dv * t;
+                }
             }
-            const Red red{2, 0, 0};
-            block_combine<2>(v, red, 0, s_wave, s_rec);
-            store_record(s_rec, 2, part);
+            const Red red{4, 0, 0};
+            block_combine<4>(v, red, 0, s_wave, s_rec);
+            store_record(s_rec, 4, part);
         }
         return;
     }
@@ -421,8 +431,8 @@ __global__ __launch_bounds__(BLOCK) void k_search_fin(Ctl *ctl, const double *pa
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_SEARCH) return;
     if (ctl->skind == SK_REFINE) {
-        const Red red = ctl->ref_valid == 0 ? Red{0, 1, 1} : Red{2, 0, 0};
-        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+        if (ctl->ref_valid == 0) fold_records<2>(part, G, Red{0, 1, 1}, 0, s_wave, s_rec);
+        else fold_records<4>(part, G, Red{4, 0, 0}, 0, s_wave, s_rec);
     } else {
         const Red red{3 * KC, KC, 0};
         fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);

@@ -222,7 +222,8 @@ static void setup_device(Solver &s)
     std::memset(s.ctl_host, 0, sizeof(Ctl));
 }
 
-static_assert(MWU_STEP_STD == SR_STD && MWU_STEP_BIN == SR_BIN && MWU_STEP_BIN_WARM == SR_BIN_WARM,
+static_assert(MWU_STEP_STD == SR_STD && MWU_STEP_BIN == SR_BIN && MWU_STEP_BIN_WARM == SR_BIN_WARM &&
+                  MWU_STEP_NEWTON == SR_NEWTON,
               "device step rules follow the C interface");
 
 static void build(Solver &s, const mwu_problem &p)
@@ -233,7 +234,7 @@ static void build(Solver &s, const mwu_problem &p)
     check(s.opt.eps > 0.0 && s.opt.eps < 1.0, MWU_ERR_INVALID_ARG, "eps must be in (0,1)");
     check(s.opt.max_iter >= 1 && s.opt.max_probes >= 1, MWU_ERR_INVALID_ARG, "bad iteration caps");
     check(s.opt.step_rule == MWU_STEP_STD || s.opt.step_rule == MWU_STEP_BIN ||
-              s.opt.step_rule == MWU_STEP_BIN_WARM,
+              s.opt.step_rule == MWU_STEP_BIN_WARM || s.opt.step_rule == MWU_STEP_NEWTON,
           MWU_ERR_INVALID_ARG, "bad step rule");
     check(s.opt.precision == MWU_FP64 || s.opt.precision == MWU_MIXED_FP32_FP64,
           MWU_ERR_INVALID_ARG, "bad precision");
@@ -754,7 +755,7 @@ mwu_status mwu_create_batch(const mwu_problem *probs, int32_t count, const mwu_o
         check(s->opt.eps > 0.0 && s->opt.eps < 1.0, MWU_ERR_INVALID_ARG, "eps must be in (0,1)");
         check(s->opt.max_iter >= 1 && s->opt.max_probes >= 1, MWU_ERR_INVALID_ARG, "bad iteration caps");
         check(s->opt.step_rule == MWU_STEP_STD || s->opt.step_rule == MWU_STEP_BIN ||
-                  s->opt.step_rule == MWU_STEP_BIN_WARM,
+                  s->opt.step_rule == MWU_STEP_BIN_WARM || s->opt.step_rule == MWU_STEP_NEWTON,
               MWU_ERR_INVALID_ARG, "bad step rule");
         check(s->opt.precision == MWU_FP64 || s->opt.precision == MWU_MIXED_FP32_FP64, MWU_ERR_INVALID_ARG,
               "bad precision");
@@ -985,6 +986,42 @@ mwu_status mwu_probe_read(void *h, int32_t which, double *out, int64_t len)
     });
 }
 
+// One evaluation pass of the candidates alphas[0..count) in evaluation mode
+// (kind SK_NEWTON also forms Psi', Phi' at alphas[0]), with the
+// refinements it needs; leaves the results in the host copy of the control
+// block and the probe waiting at this iteration's step search (the
+// evaluations change no vector, so mwu_probe_run resumes there).
+static void eval_pass(Solver &s, int kind, const double *alphas, int count)
+{
+    if (!s.dir_pending) throw ApiError{MWU_ERR_STATE, "no direction formed (mwu_probe_direction)"};
+    pull_ctl(s);
+    Ctl &c = *s.ctl_host;
+    c.skind = kind;
+    c.ncand = count;
+    for (int k = 0; k < KC; ++k) c.cand[k] = k < count ? alphas[k] : 0.0;
+    c.ga0 = alphas[0];
+    c.gdelta = 0.0;
+    c.eval_mode = 1;
+    c.ref_valid = 0;
+    for (int k = 0; k < KC; ++k) c.ev_ok[k] = 1;
+    c.phase = PH_SEARCH;
+    push_ctl(s);
+    for (int pass = 0; pass < 3 * KC + 2; ++pass) {
+        s.prog->search_pass();
+        pull_ctl(s);
+        if (s.ctl_host->phase != PH_SEARCH) break;
+    }
+    if (s.ctl_host->phase != PH_IDLE) throw ApiError{MWU_ERR_STATE, "evaluation did not finish"};
+}
+
+static void eval_resume(Solver &s)
+{
+    s.ctl_host->eval_mode = 1;
+    s.ctl_host->phase = PH_IDLE;
+    push_ctl(s);
+    HIP_OK(hipStreamSynchronize(s.stream));
+}
+
 mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, double *psi,
                                 double *phi, double *zmin_new)
 {
@@ -993,43 +1030,38 @@ mwu_status mwu_probe_eval_steps(void *h, const double *alphas, int32_t count, do
     if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
     if (!s.in_probe) return MWU_ERR_STATE;
     return run_guarded([&] {
-        if (!s.dir_pending) throw ApiError{MWU_ERR_STATE, "no direction formed (mwu_probe_direction)"};
-        pull_ctl(s);
-        Ctl &c = *s.ctl_host;
-        bool dbl = count == KE, ari = count == 15;
+        // a doubling ladder of KE values runs as the exponential-grid pass
+        bool dbl = count == KE;
         for (int k = 1; k < count; ++k) {
             if (alphas[k] != 2.0 * alphas[k - 1]) dbl = false;
         }
-        c.skind = SK_LIST;
-        if (dbl) c.skind = SK_EXP;
-        (void)ari;
-        c.ncand = count;
-        for (int k = 0; k < KC; ++k) c.cand[k] = k < count ? alphas[k] : 0.0;
-        c.ga0 = alphas[0];
-        c.gdelta = 0.0;
-        c.eval_mode = 1;
-        c.ref_valid = 0;
-        for (int k = 0; k < KC; ++k) c.ev_ok[k] = 1;
-        c.phase = PH_SEARCH;
-        push_ctl(s);
-        for (int pass = 0; pass < 3 * KC + 2; ++pass) {
-            s.prog->search_pass();
-            pull_ctl(s);
-            if (s.ctl_host->phase != PH_SEARCH) break;
-        }
+        eval_pass(s, dbl ? SK_EXP : SK_LIST, alphas, count);
         const Ctl &r = *s.ctl_host;
-        if (r.phase != PH_IDLE) throw ApiError{MWU_ERR_STATE, "evaluation did not finish"};
         for (int k = 0; k < count; ++k) {
             psi[k] = r.ev_psi[k];
             phi[k] = r.ev_phi[k];
             if (zmin_new) zmin_new[k] = r.ev_zmin[k];
         }
-        // the evaluations change no vector: the probe still waits at this
-        // iteration's step search (mwu_probe_run resumes there)
-        s.ctl_host->eval_mode = 1;
-        s.ctl_host->phase = PH_IDLE;
-        push_ctl(s);
-        HIP_OK(hipStreamSynchronize(s.stream));
+        eval_resume(s);
+    });
+}
+
+mwu_status mwu_probe_eval_newton(void *h, double alpha, double *psi, double *phi, double *dpsi,
+                                 double *dphi)
+{
+    if (!h || !(alpha > 0.0) || !std::isfinite(alpha) || !psi || !phi || !dpsi || !dphi)
+        return MWU_ERR_INVALID_ARG;
+    Solver &s = *static_cast<Solver *>(h);
+    if (s.batch) return MWU_ERR_STATE;   // probe-level calls need a single problem
+    if (!s.in_probe) return MWU_ERR_STATE;
+    return run_guarded([&] {
+        eval_pass(s, SK_NEWTON, &alpha, 1);
+        const Ctl &r = *s.ctl_host;
+        *psi = r.ev_psi[0];
+        *phi = r.ev_phi[0];
+        *dpsi = r.ev_dpsi;
+        *dphi = r.ev_dphi;
+        eval_resume(s);
     });
 }
 

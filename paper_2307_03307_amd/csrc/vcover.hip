@@ -389,6 +389,7 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
     const double *cand = ctl->cand;
     const double eta = ctl->eta, a0 = ctl->cand[0], ga0 = ctl->ga0;
     const double gdel = ctl->gdelta, Lw = ctl->LCw;
+    const bool deriv = ctl->skind == SK_NEWTON;
     CovAcc<T> ca;
     ca.init(pass_minima<KIND>());
     auto visit = [&](XD<T> pu, XD<T> pw, int) {
@@ -396,7 +397,7 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
         const T z = (T)zd;
         const T dz = pu.d + pw.d;
         const T u = exp_arg(-eta * (zd - Lw), T(0));
-        cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, u, z, dz, ca.acc, ca.zmn);
+        cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, u, z, dz, ca.acc, ca.zmn, deriv);
     };
     if (act_valid(ctl, Lw)) for_edge_list<T>(vd, vd.aeu, vd.aew, ctl->act_ne, visit);
     else for_edges<T>(vd, visit);
@@ -415,16 +416,23 @@ __device__ __forceinline__ void vc_search_body(const VcDev<T> &vd, Ctl *ctl, dou
         const double a = ctl->ref_alpha;
         const bool second = ctl->ref_valid != 0;
         const double zm = ctl->rfZmin;
-        double v[2] = {0.0, INFINITY};   // pass 2: [sum | -]; pass 1: [- | min z']
+        // pass 2: [sum | derivative sum | -]; pass 1: [- | - | min z']
+        double v[3] = {0.0, 0.0, INFINITY};
         auto visit = [&](XD<T> pu, XD<T> pw, int) {
-            const double zp = ((double)pu.x + (double)pw.x) + a * ((double)pu.d + (double)pw.d);
-            if (second) v[0] += exp(-eta * (zp - zm));
-            else v[1] = fmin(v[1], zp);
+            const double dzp = (double)pu.d + (double)pw.d;
+            const double zp = ((double)pu.x + (double)pw.x) + a * dzp;
+            if (second) {
+                const double t = exp(-eta * (zp - zm));
+                v[0] += t;
+                v[1] += dzp * t;
+            } else {
+                v[2] = fmin(v[2], zp);
+            }
         };
         for_edges<T>(vd, visit);
-        const Red red{1, 1, 0};
-        block_combine<2>(v, red, 0, s_wave, s_rec);
-        store_record(s_rec, 2, part);
+        const Red red{2, 1, 0};
+        block_combine<3>(v, red, 0, s_wave, s_rec);
+        store_record(s_rec, 3, part);
         return;
     }
     // compact records of the covering sums only (no packing rows)
@@ -471,13 +479,14 @@ __global__ __launch_bounds__(BLOCK) void vc_search_fin(Ctl *ctl, const double *p
     if (c->phase != PH_SEARCH) return;
     const int kind = c->skind;
     if (kind == SK_REFINE) {
-        const Red red{1, 1, 0};
-        fold_records<2>(part, G, red, 0, s_wave, s_rec);
+        const Red red{2, 1, 0};
+        fold_records<3>(part, G, red, 0, s_wave, s_rec);
         if (threadIdx.x == 0) {
-            // finish_search expects pass 1 [min z' | max eta*y'], pass 2 [sumP | sumC]
-            double r[2];
-            if (c->ref_valid == 0) { r[0] = s_rec[1]; r[1] = -INFINITY; }
-            else { r[0] = 1.0; r[1] = s_rec[0]; }
+            // finish_search expects pass 1 [min z' | max eta*y'], pass 2
+            // [sumP | sumC | sumP' | sumC'] (no packing rows: Psi = a dy1)
+            double r[4];
+            if (c->ref_valid == 0) { r[0] = s_rec[2]; r[1] = -INFINITY; r[2] = r[3] = 0.0; }
+            else { r[0] = 1.0; r[1] = s_rec[0]; r[2] = 0.0; r[3] = s_rec[1]; }
             finish_search(c, r);
         }
         ctl_write_back(ctl, s_ctl);

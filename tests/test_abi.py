@@ -51,7 +51,7 @@ def test_invalid_graphs_rejected():
     assert _code(lambda: mwu.vertex_cover(0, [], [])) == -1             # empty graph
     assert _code(lambda: mwu.bmatch(3, u, v, eps=0.0)) == -1            # eps outside (0,1)
     assert _code(lambda: mwu.bmatch(3, u, v, eps=1.5)) == -1
-    assert _code(lambda: mwu.bmatch(3, u, v, step_rule=3)) == -1        # unknown step rule
+    assert _code(lambda: mwu.bmatch(3, u, v, step_rule=4)) == -1        # unknown step rule
     assert _code(lambda: mwu.bmatch(3, u, v, step_rule=-1)) == -1
 
 
