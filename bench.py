@@ -63,7 +63,7 @@ def rmat_graph(scale, edge_factor, seed):
 
 
 def step_rule_of(mwu, args):
-    return mwu.STEP_BIN_WARM if args.step_rule == "warm" else mwu.STEP_BIN
+    return {"bin": mwu.STEP_BIN, "warm": mwu.STEP_BIN_WARM, "newton": mwu.STEP_NEWTON}[args.step_rule]
 
 
 def timed_solves(s, steps, warmup, tag):
@@ -84,19 +84,19 @@ def timed_solves(s, steps, warmup, tag):
     return walls, r
 
 
-def pass_times(s, reps, param, warm_iters=0):
+def pass_times(s, reps, param, warm_iters=0, last=0):
     """Average duration of each pass's main kernel (HIP events on the solver
     stream, state held), its algorithmic bytes and nonzeros, after warm_iters
-    iterations of a probe at param."""
+    iterations of a probe at param.  Pass `last` (the dominant one) is timed
+    last: every timing first forms one direction (a row, column and forward
+    pass of its own), so only then are its held launches the last ones of its
+    kernel, as the summaries under profiles/ assume."""
     out = {}
     s.probe_begin(param)
     if warm_iters:
         info = s.probe_run(warm_iters)
         log(f"  pass timing at iteration {info.iterations} of a probe at {param:.6g} (status {info.status})")
-    # the row/transpose pass last: every timing first forms one direction (a
-    # row pass of its own), so its held launches are the last ones of its
-    # kernel, as the summaries under profiles/ assume
-    for which in (1, 2, 3, 4, 5, 0):
+    for which in [w for w in (0, 1, 2, 3, 4, 5) if w != last] + [last]:
         us, by, nz = s.time_pass(which, reps)
         if by <= 0.0:       # a pass fused into another one (no kernel of its own)
             continue
@@ -222,7 +222,8 @@ def run_densest(args, steps, warmup, with_cpu=True):
         rx = s.solve(want_x=True)
         x_host = time.perf_counter() - t - statistics.mean(walls)
         assert rx.total_iterations == r.total_iterations
-        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=args.pass_warm_iters)
+        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=args.pass_warm_iters,
+                            last=1)
         s.close()
         passes["x_to_host_s"] = x_host
         return create, walls, r, passes
@@ -261,6 +262,41 @@ def run_densest(args, steps, warmup, with_cpu=True):
     return out
 
 
+def run_passes_only(args):
+    """Counter runs: the held pass timings of one precision at a fixed probe
+    parameter, with no solve, then (``--copy-calib-mib``) the calibration
+    copy.  Prints the pass timings as one JSON line."""
+    import torch
+    import paper_2307_03307_amd as mwu
+    assert torch.cuda.is_available(), "needs an MI355X"
+    prec = mwu.FP64 if args.precision == "fp64" else mwu.MIXED_FP32_FP64
+    if args.workload == "densest":
+        g = rmat_graph(args.scale, args.edge_factor, 3)
+        s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=prec, step_rule=step_rule_of(mwu, args))
+        passes = pass_times(s, args.pass_reps, args.pass_only, warm_iters=args.pass_warm_iters, last=1)
+        names = PASS_NAMES
+    else:
+        g = rmat_graph(args.scale, args.edge_factor, 2)
+        s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=prec, step_rule=step_rule_of(mwu, args))
+        passes = pass_times(s, args.pass_reps, args.pass_only, warm_iters=600, last=0)
+        names = VC_PASS_NAMES
+    s.close()
+    return {"workload": args.workload, "scale": args.scale, "param": args.pass_only, "precision": args.precision,
+            "passes": {names[k]: v for k, v in passes.items()}}
+
+
+def copy_calibration(mib):
+    """A plain device copy of `mib` MiB (the counters' scale reference)."""
+    import torch
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def run_vcover(args, steps, warmup, scale=20, with_cpu=False):
     """Vertex cover LP (min 1^T x s.t. M^T x >= 1) via the implicit edge-list
     incidence on R-MAT scale 20: fused program with sparse passes."""
@@ -276,7 +312,7 @@ def run_vcover(args, steps, warmup, scale=20, with_cpu=False):
         s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, step_rule=step_rule_of(mwu, args))
         create = time.perf_counter() - t
         walls, r = timed_solves(s, steps, warmup, f"vcover precision={precision}")
-        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=600)
+        passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=600, last=0)
         s.close()
         return create, walls, r, passes
 
@@ -458,12 +494,14 @@ def run_genmatch(args):
     }
 
 
-def run_reuse(args):
-    """Probe-to-probe reuse (MWU_FLAG_REUSE): probes, iterations, search
-    passes and time of whole solves with and without it, chosen form, for the
-    vertex cover (R-MAT 20), densest subgraph (R-MAT 22) and dominating set
-    (Chung-Lu, 2M vertices) workloads, with Algorithm 3 from 1 and with the
-    warm-started search."""
+def run_steprules(args):
+    """Step rules and probe-to-probe reuse (MWU_FLAG_REUSE) compared on whole
+    solves, chosen form: Algorithm 3 from 1 (bin), Algorithm 3 from the
+    previous step (warm) and Newton's method (newton, Section 4.2), each
+    without and with reuse, on the vertex cover (R-MAT 20), densest subgraph
+    (R-MAT 22) and dominating set (Chung-Lu, 2M vertices) workloads: time,
+    probes, iterations, search passes (launches of the search kernel) and
+    tests of the step (evaluations), with their per-iteration rates."""
     import torch
     import graphgen as gg
     import paper_2307_03307_amd as mwu
@@ -477,16 +515,21 @@ def run_reuse(args):
         "densest_rmat22": lambda **k: mwu.densest_subgraph(g3.num_vertices, g3.u, g3.v, **k),
         "domset_chunglu2m": lambda **k: mwu.dominating_set(ptr4, col4, g4.num_vertices, **k),
     }
-    out = {"metric": "time-to-(1+eps) with and without probe-to-probe reuse", "unit": "s", "runs": {}}
+    out = {"metric": "time-to-(1+eps) by step rule, with and without probe-to-probe reuse", "unit": "s",
+           "runs": {}}
+    rules = (("bin", mwu.STEP_BIN), ("warm", mwu.STEP_BIN_WARM), ("newton", mwu.STEP_NEWTON))
     for name, make in makers.items():
-        for rule_name, rule in (("bin", mwu.STEP_BIN), ("warm", mwu.STEP_BIN_WARM)):
+        for rule_name, rule in rules:
             for reuse in (False, True):
                 s = make(precision=mwu.MIXED_FP32_FP64, step_rule=rule, flags=mwu._lib.FLAG_REUSE if reuse else 0)
                 walls, r = timed_solves(s, 2, 1, f"{name} {rule_name} reuse={reuse}")
                 s.close()
+                it = max(1, r.total_iterations)
                 out["runs"][f"{name}/{rule_name}/{'reuse' if reuse else 'fresh'}"] = {
                     "s": statistics.mean(walls), "certified": r.certified, "bracket": [r.lower, r.upper],
-                    "probes": r.probes, "iterations": r.total_iterations, "search_passes": r.search_passes}
+                    "probes": r.probes, "iterations": r.total_iterations, "search_passes": r.search_passes,
+                    "evaluations": r.evaluations, "passes_per_iteration": r.search_passes / it,
+                    "evaluations_per_iteration": r.evaluations / it}
     return out
 
 
@@ -505,9 +548,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch", "reuse"], default="densest",
+    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch", "steprules"],
+                    default="densest",
                     help="densest: the headline R-MAT scale 22 densest subgraph (default); vcover: R-MAT "
-                         "vertex cover; batched: 512 matching LPs; genmatch: generalized matching")
+                         "vertex cover; batched: 512 matching LPs; genmatch: generalized matching; "
+                         "steprules: step rules and probe reuse compared on three workloads")
     ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default 22 densest, 20 vcover)")
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -522,8 +567,15 @@ def main():
     ap.add_argument("--gm-users", type=int, default=200000)
     ap.add_argument("--gm-items", type=int, default=20000)
     ap.add_argument("--loop-sample", type=int, default=16)
-    ap.add_argument("--step-rule", choices=["bin", "warm"], default="bin",
-                    help="bin: Algorithm 3 from 1 in every iteration; warm: started at the previous step")
+    ap.add_argument("--pass-only", type=float, default=None,
+                    help="counter runs: time the passes of a probe at this parameter (densest D, vcover M) "
+                         "and solve nothing")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed", help="with --pass-only")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="end with a plain device copy of this many MiB (scale of the HBM counters)")
+    ap.add_argument("--step-rule", choices=["bin", "warm", "newton"], default="bin",
+                    help="bin: Algorithm 3 from 1 in every iteration; warm: started at the previous step; "
+                         "newton: Newton's method from the previous step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -532,7 +584,9 @@ def main():
     if args.scale is None:
         args.scale = 20 if args.workload == "vcover" else 22
 
-    if args.workload == "densest":
+    if args.pass_only is not None:
+        out = run_passes_only(args)
+    elif args.workload == "densest":
         out = run_densest(args, args.steps, args.warmup, with_cpu=not args.no_cpu_baseline)
         if not args.no_extra:
             out["vcover_rmat20"] = run_vcover(args, 3, 1)
@@ -543,10 +597,12 @@ def main():
     elif args.workload == "batched":
         d = run_batched(args, args.steps, args.warmup)
         out = headline(args, d, d["workload"])
-    elif args.workload == "reuse":
-        out = run_reuse(args)
+    elif args.workload == "steprules":
+        out = run_steprules(args)
     else:
         out = run_genmatch(args)
+    if args.copy_calib_mib:
+        copy_calibration(args.copy_calib_mib)
     print(json.dumps(out), flush=True)
 
 
