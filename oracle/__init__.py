@@ -81,10 +81,11 @@ def lib():
                                 vp, ctypes.c_int64, P(_ProbeResult)]
         L.orc_probe_from.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
-                                     vp, ctypes.c_int64, ctypes.c_double, P(_ProbeResult)]
+                                     vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P(_ProbeResult)]
         L.orc_iteration_terms.argtypes = [P(_Mat), ctypes.c_double, P(_Mat), ctypes.c_double,
                                           ctypes.c_double, vp] + [vp] * 9 + [vp, vp, vp,
-                                                                             ctypes.c_int64, vp, vp, vp]
+                                                                             ctypes.c_int64, vp, vp, vp,
+                                                                             ctypes.c_int32, ctypes.c_double]
         for name in ("orc_solve_packing", "orc_solve_covering"):
             getattr(L, name).argtypes = [P(_Mat), ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, vp, P(_SolveResult)]
@@ -255,8 +256,10 @@ class ProbeResult:
 
 def probe(P: CSR, sP: float, C: CSR, sC: float, eps: float = 0.1, max_iter: int = 5000,
           step_rule: int = STEP_BIN, x0: Optional[np.ndarray] = None,
-          forced_alpha: Optional[Sequence[float]] = None, start_alpha: float = 0.0) -> ProbeResult:
-    """One MWU feasibility probe (Algorithm 2 + Algorithm 3)."""
+          forced_alpha: Optional[Sequence[float]] = None, start_alpha: float = 0.0,
+          drop: bool = False) -> ProbeResult:
+    """One MWU feasibility probe (Algorithm 2 + Algorithm 3); drop: leave the
+    satisfied covering rows out of every iteration (R22)."""
     n = P.cols
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     fa = None if forced_alpha is None else np.ascontiguousarray(forced_alpha, dtype=np.float64)
@@ -264,7 +267,7 @@ def probe(P: CSR, sP: float, C: CSR, sC: float, eps: float = 0.1, max_iter: int 
     r = _ProbeResult()
     rc = lib().orc_probe_from(P.c, sP, C.c, sC, eps, max_iter, step_rule, int(x0 is not None),
                          x.ctypes.data, _p(fa), 0 if fa is None else fa.shape[0],
-                         trace.ctypes.data, max_iter, start_alpha, ctypes.byref(r))
+                         trace.ctypes.data, max_iter, start_alpha, int(drop), ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_probe failed: {rc}")
     return ProbeResult(r.status, r.iterations, r.evaluations, r.pack_bound, r.cover_bound,
@@ -281,8 +284,10 @@ def reuse_start(P: CSR, sP: float, eps: float, x: np.ndarray) -> np.ndarray:
 
 
 def iteration_terms(P: CSR, sP: float, C: CSR, sC: float, eps: float, x: np.ndarray,
-                    alphas: Sequence[float] = ()) -> dict:
-    """All per-iteration vectors at point x, plus (Psi, Phi, min z') at each alpha."""
+                    alphas: Sequence[float] = (), drop: bool = False, eta_: Optional[float] = None) -> dict:
+    """All per-iteration vectors at point x, plus (Psi, Phi, min z') at each
+    alpha; drop leaves the satisfied covering rows out (R22); eta_ replaces
+    the eta of the row count."""
     n, mP, mC = P.cols, P.rows, C.rows
     out = {k: np.zeros(n) for k in ("g", "h", "d")}
     out.update({k: np.zeros(mP) for k in ("y", "w", "dy")})
@@ -297,11 +302,11 @@ def iteration_terms(P: CSR, sP: float, C: CSR, sC: float, eps: float, x: np.ndar
                                                                    "d", "dy", "dz")],
                                    ctypes.addressof(LP), ctypes.addressof(LC),
                                    _p(a) if k else None, k, psi.ctypes.data, phi.ctypes.data,
-                                   zmn.ctypes.data)
+                                   zmn.ctypes.data, int(drop), float(eta_ or 0.0))
     if rc != 0:
         raise RuntimeError(f"orc_iteration_terms failed: {rc}")
     out.update(LP=LP.value, LC=LC.value, psi=psi, phi=phi, zmin_new=zmn,
-               eta=eta(mP + mC, eps))
+               eta=eta_ if eta_ else eta(mP + mC, eps))
     return out
 
 
@@ -322,16 +327,22 @@ class SolveResult:
     x: np.ndarray
 
 
+def _flags(reuse: bool, drop: bool) -> int:
+    """Outer-search flags: probe-to-probe reuse (R21), dropping satisfied
+    covering rows (R22)."""
+    return (1 if reuse else 0) | (2 if drop else 0)
+
+
 def _solve_result(r, x) -> SolveResult:
     return SolveResult(r.status == 0, r.objective, r.lower, r.upper, r.probes,
                        r.total_iterations, r.final_probe_iterations, r.evaluations, x)
 
 
 def solve_packing(P: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
-                  step_rule: int = STEP_BIN, reuse: bool = False) -> SolveResult:
+                  step_rule: int = STEP_BIN, reuse: bool = False, drop: bool = False) -> SolveResult:
     x = np.zeros(P.cols)
     r = _SolveResult()
-    rc = lib().orc_solve_packing(P.c, eps, max_iter, max_probes, step_rule, int(reuse), x.ctypes.data,
+    rc = lib().orc_solve_packing(P.c, eps, max_iter, max_probes, step_rule, _flags(reuse, drop), x.ctypes.data,
                                  ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_solve_packing failed: {rc}")
@@ -339,10 +350,10 @@ def solve_packing(P: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: in
 
 
 def solve_covering(C: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
-                   step_rule: int = STEP_BIN, reuse: bool = False) -> SolveResult:
+                   step_rule: int = STEP_BIN, reuse: bool = False, drop: bool = False) -> SolveResult:
     x = np.zeros(C.cols)
     r = _SolveResult()
-    rc = lib().orc_solve_covering(C.c, eps, max_iter, max_probes, step_rule, int(reuse), x.ctypes.data,
+    rc = lib().orc_solve_covering(C.c, eps, max_iter, max_probes, step_rule, _flags(reuse, drop), x.ctypes.data,
                                   ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_solve_covering failed: {rc}")
@@ -350,7 +361,7 @@ def solve_covering(C: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: i
 
 
 def solve_densest(g, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
-                  step_rule: int = STEP_BIN, reuse: bool = False) -> SolveResult:
+                  step_rule: int = STEP_BIN, reuse: bool = False, drop: bool = False) -> SolveResult:
     O, W, keep = densest_matrices(g)
     _, newid = _nonisolated(g)
     eu = np.ascontiguousarray(newid[g.u], dtype=np.int32)
@@ -358,7 +369,7 @@ def solve_densest(g, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 6
     z = np.zeros(O.cols)
     r = _SolveResult()
     rc = lib().orc_solve_densest(O.c, W.c, eu.ctypes.data, ev.ctypes.data, eps, max_iter,
-                                 max_probes, step_rule, int(reuse), z.ctypes.data, ctypes.byref(r))
+                                 max_probes, step_rule, _flags(reuse, drop), z.ctypes.data, ctypes.byref(r))
     if rc != 0:
         raise RuntimeError(f"orc_solve_densest failed: {rc}")
     return _solve_result(r, z)

@@ -84,6 +84,16 @@
  *       and at least 1, are tested in turn; the first where the test holds is
  *       the step, one at or below lo gives lo (it holds there), and a failing
  *       test at 1 ends the probe as in R4.
+ *   R22 dropping satisfied covering rows (ORC_FLAG_DROP; the line
+ *       C <- {c_i : c_i^T x < 1} of Algorithms 1 and 2, which the paper's own
+ *       runs leave out): every iteration works on the covering rows with
+ *       z_i < 1 only -- smin, its gradient u (0 on the other rows), h, Phi,
+ *       and the early return and the stop test over those rows, with eta
+ *       still from the full m.  z only grows, so a row once left out stays
+ *       out, and the set is that of the algorithm from the end of the first
+ *       iteration on; a row already satisfied at the start is left out of
+ *       the first iteration too (the set is a function of the current point
+ *       alone).  The probe stops FEASIBLE when no row is left.
  *   R21 probe-to-probe reuse (the reuse argument of the outer searches): a
  *       probe after the first starts from its predecessor's iterate scaled so
  *       that its largest packing row, under the new probe's scale, is eps --
@@ -104,6 +114,8 @@ typedef struct {
 
 enum { ORC_RUNNING = 0, ORC_FEASIBLE = 1, ORC_INFEASIBLE = 2, ORC_MAX_ITER = 3 };
 enum { ORC_STEP_STD = 0, ORC_STEP_BIN = 1, ORC_STEP_BIN_WARM = 2, ORC_STEP_NEWTON = 3 };
+/* flags of the outer searches: probe-to-probe reuse (R21), dropping satisfied covering rows (R22) */
+enum { ORC_FLAG_REUSE = 1, ORC_FLAG_DROP = 2 };
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_UNBOUNDED = -2, ORC_ERR_OOM = -3 };
 
 /* Threshold below which 1 + sum(u*expm1(-b)) is taken as too cancelled and the
@@ -252,6 +264,12 @@ typedef struct {
     double eta, eps, step;      /* step = s/eta in the direction formula */
     double *x, *y, *z, *d, *dy, *dz, *w, *u, *g, *h;
     double LP, LC;              /* smax(y), smin(z) of the current point */
+    /* the covering rows the iteration works on (R22): all of them, or with
+     * drop set the rows with z < 1, gathered into za, dza, ua (na rows) */
+    int drop;
+    int64_t na;
+    int64_t *ai;                /* their row indices */
+    double *za, *dza, *ua;
 } orc_state;
 
 typedef struct {
@@ -273,7 +291,7 @@ static orc_eval evaluate(orc_state *st, double alpha)
 {
     orc_eval e;
     e.psi = orc_psi(st->y, st->dy, st->w, st->mP, st->eta, st->LP, alpha);
-    e.phi = orc_phi(st->z, st->dz, st->u, st->mC, st->eta, st->LC, alpha, &e.zmin_new);
+    e.phi = orc_phi(st->za, st->dza, st->ua, st->na, st->eta, st->LC, alpha, &e.zmin_new);
     /* bang-for-buck: f = Phi/Psi >= 1, i.e. Phi >= Psi (Psi >= 0) */
     e.pass = (e.phi >= e.psi);
     return e;
@@ -452,7 +470,16 @@ static double col_max_P(const orc_state *st, double *colmax)
 static double direction(orc_state *st)
 {
     st->LP = orc_smax(st->y, st->mP, st->eta, st->w);
-    st->LC = orc_smin(st->z, st->mC, st->eta, st->u);
+    if (st->drop) {                 /* (R22) smin and u over the rows with z < 1 */
+        st->na = 0;
+        for (int64_t j = 0; j < st->mC; ++j)
+            if (st->z[j] < 1.0) { st->ai[st->na] = j; st->za[st->na] = st->z[j]; ++st->na; }
+        st->LC = orc_smin(st->za, st->na, st->eta, st->ua);
+        for (int64_t j = 0; j < st->mC; ++j) st->u[j] = 0.0;
+        for (int64_t k = 0; k < st->na; ++k) st->u[st->ai[k]] = st->ua[k];
+    } else {
+        st->LC = orc_smin(st->z, st->mC, st->eta, st->u);
+    }
     orc_matvec_t(st->P, st->sP, st->w, st->g);
     orc_matvec_t(st->C, st->sC, st->u, st->h);
     double dmax = 0.0;
@@ -467,6 +494,8 @@ static double direction(orc_state *st)
     }
     orc_matvec(st->P, st->sP, st->d, st->dy);
     orc_matvec(st->C, st->sC, st->d, st->dz);
+    if (st->drop)
+        for (int64_t k = 0; k < st->na; ++k) st->dza[k] = st->dz[st->ai[k]];
     return dmax;
 }
 
@@ -474,10 +503,11 @@ static void state_free(orc_state *st)
 {
     free(st->y); free(st->z); free(st->d); free(st->dy); free(st->dz);
     free(st->w); free(st->u); free(st->g); free(st->h);
+    if (st->drop) { free(st->ai); free(st->za); free(st->dza); free(st->ua); }
 }
 
 static int state_init(orc_state *st, const orc_mat *P, double sP, const orc_mat *C,
-                      double sC, double eps, double *x)
+                      double sC, double eps, double *x, int drop)
 {
     memset(st, 0, sizeof(*st));
     if (!P || !C || P->cols != C->cols || P->rows < 1 || C->rows < 1 || !(eps > 0.0 && eps < 1.0))
@@ -502,6 +532,17 @@ static int state_init(orc_state *st, const orc_mat *P, double sP, const orc_mat 
     if (!st->y || !st->z || !st->dy || !st->dz || !st->w || !st->u || !st->d || !st->g || !st->h) {
         state_free(st);
         return ORC_ERR_OOM;
+    }
+    st->drop = drop != 0;
+    st->na = st->mC;
+    if (st->drop) {
+        st->ai = calloc((size_t)st->mC, sizeof(int64_t));
+        st->za = calloc((size_t)st->mC, sizeof(double));
+        st->dza = calloc((size_t)st->mC, sizeof(double));
+        st->ua = calloc((size_t)st->mC, sizeof(double));
+        if (!st->ai || !st->za || !st->dza || !st->ua) { state_free(st); return ORC_ERR_OOM; }
+    } else {
+        st->za = st->z; st->dza = st->dz; st->ua = st->u;
     }
     return ORC_OK;
 }
@@ -534,7 +575,8 @@ int orc_initial_point(const orc_mat *P, double sP, double eps, double *x)
 int orc_probe_from(const orc_mat *P, double sP, const orc_mat *C, double sC, double eps,
                    int32_t max_iter, int32_t step_rule, int32_t x0_given, double *x,
                    const double *forced_alpha, int64_t n_forced,
-                   double *alpha_trace, int64_t trace_cap, double start_alpha, orc_probe_result *res);
+                   double *alpha_trace, int64_t trace_cap, double start_alpha, int32_t drop,
+                   orc_probe_result *res);
 
 int orc_probe(const orc_mat *P, double sP, const orc_mat *C, double sC, double eps,
               int32_t max_iter, int32_t step_rule, int32_t x0_given, double *x,
@@ -542,19 +584,21 @@ int orc_probe(const orc_mat *P, double sP, const orc_mat *C, double sC, double e
               double *alpha_trace, int64_t trace_cap, orc_probe_result *res)
 {
     return orc_probe_from(P, sP, C, sC, eps, max_iter, step_rule, x0_given, x, forced_alpha, n_forced,
-                          alpha_trace, trace_cap, 0.0, res);
+                          alpha_trace, trace_cap, 0.0, 0, res);
 }
 
 /* As orc_probe; with the warm-started search (ORC_STEP_BIN_WARM) the first
  * iteration's search starts at start_alpha when it exceeds 1 (the last step
- * of a previous probe, R21) instead of at 1. */
+ * of a previous probe, R21) instead of at 1, and with drop set the
+ * iterations leave the satisfied covering rows out (R22). */
 int orc_probe_from(const orc_mat *P, double sP, const orc_mat *C, double sC, double eps,
                    int32_t max_iter, int32_t step_rule, int32_t x0_given, double *x,
                    const double *forced_alpha, int64_t n_forced,
-                   double *alpha_trace, int64_t trace_cap, double start_alpha, orc_probe_result *res)
+                   double *alpha_trace, int64_t trace_cap, double start_alpha, int32_t drop,
+                   orc_probe_result *res)
 {
     orc_state st;
-    int rc = state_init(&st, P, sP, C, sC, eps, x);
+    int rc = state_init(&st, P, sP, C, sC, eps, x, drop);
     if (rc) return rc;
     memset(res, 0, sizeof(*res));
     res->pack_bound = INFINITY;
@@ -616,21 +660,26 @@ int orc_probe_from(const orc_mat *P, double sP, const orc_mat *C, double sC, dou
 /*
  * Quantities of one iteration at a given point, for per-pass comparison:
  * y = Px, z = Cx, w, u, g, h, d, dy, dz, and (Psi, Phi, min z') at each of
- * the n_alpha step sizes.  Every output pointer is nullable.
+ * the n_alpha step sizes.  Every output pointer is nullable.  drop: leave
+ * the satisfied covering rows out (R22); eta_override > 0 replaces eta.
  */
 int orc_iteration_terms(const orc_mat *P, double sP, const orc_mat *C, double sC,
                         double eps, const double *x_in,
                         double *y, double *z, double *w, double *u, double *g, double *h,
                         double *d, double *dy, double *dz, double *LP, double *LC,
                         const double *alphas, int64_t n_alpha,
-                        double *psi, double *phi, double *zmin_new)
+                        double *psi, double *phi, double *zmin_new, int32_t drop, double eta_override)
 {
     orc_state st;
     double *x = malloc((size_t)P->cols * sizeof(double));
     if (!x) return ORC_ERR_OOM;
     memcpy(x, x_in, (size_t)P->cols * sizeof(double));
-    int rc = state_init(&st, P, sP, C, sC, eps, x);
+    int rc = state_init(&st, P, sP, C, sC, eps, x, drop);
     if (rc) { free(x); return rc; }
+    if (eta_override > 0.0) {       /* the eta of a larger row set (checks of R22) */
+        st.step *= st.eta / eta_override;
+        st.eta = eta_override;
+    }
     orc_matvec(P, sP, x, st.y);
     orc_matvec(C, sC, x, st.z);
     direction(&st);
@@ -708,7 +757,7 @@ static void ones_row_free(ones_row *o) { free(o->idx); free(o->val); }
  * hi <= (1+eps) lo.
  */
 int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t max_probes,
-                      int32_t step_rule, int32_t reuse, double *x_best, orc_solve_result *r)
+                      int32_t step_rule, int32_t flags, double *x_best, orc_solve_result *r)
 {
     double last = 0.0;   /* the previous probe's last step (R21) */
     int64_t n = P->cols;
@@ -754,9 +803,9 @@ int orc_solve_packing(const orc_mat *P, double eps, int32_t max_iter, int32_t ma
         double M = sqrt(slo * shi);
         orc_probe_result pr;
         {
-            const int warm = reuse && r->probes > 0 && orc_reuse_start(P, 1.0, ep, x);
+            const int warm = (flags & ORC_FLAG_REUSE) && r->probes > 0 && orc_reuse_start(P, 1.0, ep, x);
             rc = orc_probe_from(P, 1.0, &one.m, 1.0 / M, ep, max_iter, step_rule, warm, x,
-                                NULL, 0, NULL, 0, warm ? last : 0.0, &pr);
+                                NULL, 0, NULL, 0, warm ? last : 0.0, (flags & ORC_FLAG_DROP) != 0, &pr);
         }
         if (rc) goto done;
         last = pr.last_alpha;
@@ -799,7 +848,7 @@ done:
  * gives the starting lo).
  */
 int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t max_probes,
-                       int32_t step_rule, int32_t reuse, double *x_best, orc_solve_result *r)
+                       int32_t step_rule, int32_t flags, double *x_best, orc_solve_result *r)
 {
     double last = 0.0;   /* the previous probe's last step (R21) */
     int64_t n = C->cols;
@@ -845,9 +894,9 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
         double M = sqrt(slo * shi);
         orc_probe_result pr;
         {
-            const int warm = reuse && r->probes > 0 && orc_reuse_start(&one.m, 1.0 / M, ep, x);
+            const int warm = (flags & ORC_FLAG_REUSE) && r->probes > 0 && orc_reuse_start(&one.m, 1.0 / M, ep, x);
             rc = orc_probe_from(&one.m, 1.0 / M, C, 1.0, ep, max_iter, step_rule, warm, x,
-                                NULL, 0, NULL, 0, warm ? last : 0.0, &pr);
+                                NULL, 0, NULL, 0, warm ? last : 0.0, (flags & ORC_FLAG_DROP) != 0, &pr);
         }
         if (rc) goto done;
         last = pr.last_alpha;
@@ -932,7 +981,7 @@ out:
  */
 int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, const int32_t *ev,
                       double eps, int32_t max_iter, int32_t max_probes, int32_t step_rule,
-                      int32_t reuse, double *z_best, orc_solve_result *r)
+                      int32_t flags, double *z_best, orc_solve_result *r)
 {
     double last = 0.0;   /* the previous probe's last step (R21) */
     int64_t n = O->cols, nv = O->rows, ne = W->rows;
@@ -962,9 +1011,9 @@ int orc_solve_densest(const orc_mat *O, const orc_mat *W, const int32_t *eu, con
         double D = sqrt(slo * shi);
         orc_probe_result pr;
         {
-            const int warm = reuse && r->probes > 0 && orc_reuse_start(O, 1.0 / D, ep, z);
+            const int warm = (flags & ORC_FLAG_REUSE) && r->probes > 0 && orc_reuse_start(O, 1.0 / D, ep, z);
             rc = orc_probe_from(O, 1.0 / D, W, 1.0, ep, max_iter, step_rule, warm, z,
-                                NULL, 0, NULL, 0, warm ? last : 0.0, &pr);
+                                NULL, 0, NULL, 0, warm ? last : 0.0, (flags & ORC_FLAG_DROP) != 0, &pr);
         }
         if (rc) goto done;
         last = pr.last_alpha;
@@ -1015,6 +1064,7 @@ double orc_step_search_terms_from(const double *y, const double *dy, const doubl
     memset(&st, 0, sizeof st);
     st.y = (double *)y; st.dy = (double *)dy; st.w = (double *)w; st.mP = mP; st.LP = LP;
     st.z = (double *)z; st.dz = (double *)dz; st.u = (double *)u; st.mC = mC; st.LC = LC;
+    st.za = st.z; st.dza = st.dz; st.ua = st.u; st.na = mC;
     st.eta = eta; st.eps = eps;
     *evals = 0;
     return step_search_from(&st, start, evals);
@@ -1031,6 +1081,7 @@ double orc_newton_search_terms(const double *y, const double *dy, const double *
     memset(&st, 0, sizeof st);
     st.y = (double *)y; st.dy = (double *)dy; st.w = (double *)w; st.mP = mP; st.LP = LP;
     st.z = (double *)z; st.dz = (double *)dz; st.u = (double *)u; st.mC = mC; st.LC = LC;
+    st.za = st.z; st.dza = st.dz; st.ua = st.u; st.na = mC;
     st.eta = eta; st.eps = eps;
     *evals = 0;
     return step_search_newton(&st, start, evals);

@@ -79,6 +79,10 @@ MUTANTS = [
      "next = a - corr;", "next = a + corr;"),
     ("Newton: iterates not kept inside the bracket",
      "if (!(next > lo && next < hi)) {", "if (!(next == next)) {"),
+    ("drop: met rows kept in the smoothed minimum",
+     "if (st->z[j] < 1.0) { st->ai[st->na] = j;", "if (st->z[j] < 2.0) { st->ai[st->na] = j;"),
+    ("drop: weights of met rows left in u",
+     "for (int64_t j = 0; j < st->mC; ++j) st->u[j] = 0.0;", "for (int64_t j = 0; j < 0; ++j) st->u[j] = 0.0;"),
     ("level sets: edge counted at its first endpoint",
      "cnt[(a > b ? a : b) + 1]++;", "cnt[(a < b ? a : b) + 1]++;"),
 ]

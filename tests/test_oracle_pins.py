@@ -930,3 +930,110 @@ def test_newton_solves_bracket_exact_optima(oracle_mod, seed):
     r = oracle_mod.solve_domset(g, step_rule=rule)
     assert r.certified
     _check_covering(D, r, opt)
+
+
+# ------------------------------------------------------------ general (non-bipartite) matching
+
+def _fractional_matching_number(g):
+    """nu_f(G) = nu(G x K2) / 2: the fractional matching LP has a
+    half-integral optimum, and half-integral matchings of G correspond to
+    matchings of its bipartite double cover."""
+    return _double_cover_matching(g) / 2.0
+
+
+@pytest.mark.parametrize("name", ["C5", "C9", "K5", "K8", "gnm", "chunglu", "odd-components"])
+def test_general_matching_lp_equals_fractional_matching_number(oracle_mod, name):
+    """Section 3's matching LP on graphs that are not bipartite: the packing
+    LP max 1^T x s.t. M x <= 1 has the fractional matching number as its
+    optimum, which exceeds the maximum matching on odd cycles (n/2 against
+    (n-1)/2); certified brackets around nu(G x K2)/2, cross-checked with
+    HiGHS, and a feasible x within (1 + eps)."""
+    g = {"C5": lambda: gg.cycle_graph(5), "C9": lambda: gg.cycle_graph(9),
+         "K5": lambda: gg.complete_graph(5), "K8": lambda: gg.complete_graph(8),
+         "gnm": lambda: gg.gnm_random(80, 240, seed=31),
+         "chunglu": lambda: gg.chung_lu(300, 2.3, 5.0, seed=32),
+         # three disjoint triangles and a 5-cycle: nu_f = 3 * 1.5 + 2.5 = 7, nu = 5
+         "odd-components": lambda: gg._from_pairs(14, [(0, 1), (1, 2), (2, 0), (3, 4), (4, 5), (5, 3),
+                                                      (6, 7), (7, 8), (8, 6), (9, 10), (10, 11), (11, 12),
+                                                      (12, 13), (13, 9)])}[name]()
+    opt = _fractional_matching_number(g)
+    M = oracle_mod.incidence(g).dense()
+    highs = linprog(-np.ones(M.shape[1]), A_ub=M, b_ub=np.ones(M.shape[0]), bounds=(0, None)).fun
+    assert -highs == pytest.approx(opt, rel=1e-9)
+    closed = {"C5": 2.5, "C9": 4.5, "K5": 2.5, "K8": 4.0, "odd-components": 7.0}
+    if name in closed:
+        assert opt == closed[name]
+    r = oracle_mod.solve_bmatch(g)
+    assert r.certified
+    _check_packing(g, r, opt)
+
+
+# ------------------------------------------------------------ dropping satisfied covering rows (R22)
+
+@pytest.mark.parametrize("name", ["vcover", "domset"])
+def test_drop_is_the_iteration_on_the_unsatisfied_rows(oracle_mod, name):
+    """Algorithm 2's drop line C <- {c_i : c_i^T x < 1} (R22): at a point
+    where part of the covering rows is met, the iteration with dropping is
+    the plain iteration (no dropping) on the LP whose covering side holds
+    only the unmet rows, with the eta of the full row count: the same
+    smoothed minimum, u (and 0 on the met rows), h, d, Cd on the kept rows,
+    Psi, Phi and min z'.  Keeping the met rows changes h."""
+    rng = np.random.default_rng(7)
+    if name == "vcover":
+        g = gg.gnm_random(80, 300, seed=8)
+        C, keep = oracle_mod.vertex_cover_matrix(g)
+    else:
+        C = oracle_mod.dominating_set_matrix(gg.chung_lu(150, 2.3, 5.0, seed=9))
+    n = C.cols
+    one = oracle_mod.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+    Cd = C.dense()
+    if name == "vcover":
+        # every z_e = x_u + x_w within 2% of 1: the met rows still carry weight
+        x = 0.5 + rng.uniform(-0.01, 0.01, n)
+    else:
+        x = rng.uniform(0.0, 0.8, n) / np.maximum(1.0, Cd.sum(axis=1).mean() / 2)
+    z = Cd @ x
+    met = z >= 1.0
+    assert 0.2 < met.mean() < 0.8, met.mean()
+    sP = 1.0 / (0.6 * n)
+    alphas = [0.5, 3.0, 40.0]
+    full = oracle_mod.iteration_terms(one, sP, C, 1.0, EPS, x, alphas=alphas, drop=True)
+    R = Cd[~met]
+    Rs = sp.csr_matrix(R)
+    red = oracle_mod.CSR(R.shape[0], n, Rs.indptr.astype(np.int64), Rs.indices.astype(np.int32), Rs.data)
+    ref = oracle_mod.iteration_terms(one, sP, red, 1.0, EPS, x, alphas=alphas, eta_=full["eta"])
+    assert full["LC"] == pytest.approx(ref["LC"], rel=1e-14)
+    assert np.array_equal(full["u"][met], np.zeros(met.sum()))
+    assert np.allclose(full["u"][~met], ref["u"], rtol=1e-13, atol=0)
+    for k in ("h", "d", "g"):
+        assert np.allclose(full[k], ref[k], rtol=1e-13, atol=1e-300), k
+    assert np.allclose(full["dz"][~met], ref["dz"], rtol=1e-13, atol=0)
+    for k in ("psi", "phi", "zmin_new"):
+        assert np.allclose(full[k], ref[k], rtol=1e-12, atol=0), k
+    if name == "vcover":
+        kept = oracle_mod.iteration_terms(one, sP, C, 1.0, EPS, x)
+        # variables all of whose rows are met lose their h (and so their step)
+        gone = (full["h"] == 0.0) & (kept["h"] > 0.0)
+        assert gone.sum() >= 3
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_drop_solves_bracket_exact_optima(oracle_mod, seed):
+    """Outer searches whose probes drop satisfied covering rows end certified
+    around the exact optima of the covering LPs and the densest subgraph."""
+    g = gg.gnm_random(60, 200, seed=seed)
+    r = oracle_mod.solve_vcover(g, drop=True)
+    assert r.certified
+    opt = _double_cover_matching(g) / 2.0
+    assert r.lower <= opt * (1 + 1e-9) and opt <= r.upper * (1 + 1e-9)
+    C, keep = oracle_mod.vertex_cover_matrix(g)
+    assert (C.dense() @ r.x[keep]).min() >= 1 - 1e-9
+    g = gg.chung_lu(200, 2.3, 6.0, seed=seed)
+    D = oracle_mod.dominating_set_matrix(g).dense()
+    dopt = linprog(np.ones(D.shape[1]), A_ub=-D, b_ub=-np.ones(D.shape[0]), bounds=(0, None)).fun
+    r = oracle_mod.solve_domset(g, drop=True)
+    assert r.certified
+    _check_covering(D, r, dopt)
+    g = gg.gnm_random(14, 30, seed=seed + 4)
+    r = oracle_mod.solve_densest(g, drop=True)
+    _check_densest(oracle_mod, g, r, brute_force_density(g))
