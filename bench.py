@@ -495,10 +495,11 @@ def run_genmatch(args):
 
 
 def run_steprules(args):
-    """Step rules and probe-to-probe reuse (MWU_FLAG_REUSE) compared on whole
-    solves, chosen form: Algorithm 3 from 1 (bin), Algorithm 3 from the
-    previous step (warm) and Newton's method (newton, Section 4.2), each
-    without and with reuse, on the vertex cover (R-MAT 20), densest subgraph
+    """Step rules, probe-to-probe reuse (MWU_FLAG_REUSE) and dropping satisfied
+    covering rows (MWU_FLAG_DROP_SATISFIED) compared on whole solves, chosen
+    form: Algorithm 3 from 1 (bin), Algorithm 3 from the previous step (warm)
+    and Newton's method (newton, Section 4.2), each without and with reuse,
+    and the drop with two of them, on the vertex cover (R-MAT 20), densest subgraph
     (R-MAT 22) and dominating set (Chung-Lu, 2M vertices) workloads: time,
     probes, iterations, search passes (launches of the search kernel) and
     tests of the step (evaluations), with their per-iteration rates."""
@@ -515,21 +516,26 @@ def run_steprules(args):
         "densest_rmat22": lambda **k: mwu.densest_subgraph(g3.num_vertices, g3.u, g3.v, **k),
         "domset_chunglu2m": lambda **k: mwu.dominating_set(ptr4, col4, g4.num_vertices, **k),
     }
-    out = {"metric": "time-to-(1+eps) by step rule, with and without probe-to-probe reuse", "unit": "s",
+    out = {"metric": "time-to-(1+eps) by step rule, probe-to-probe reuse and dropping met rows", "unit": "s",
            "runs": {}}
     rules = (("bin", mwu.STEP_BIN), ("warm", mwu.STEP_BIN_WARM), ("newton", mwu.STEP_NEWTON))
+    F_REUSE, F_DROP = mwu._lib.FLAG_REUSE, mwu._lib.FLAG_DROP_SATISFIED
+    # every rule with and without reuse; dropping satisfied covering rows
+    # with Algorithm 3 fresh and with the warm start and reuse
+    configs = [(rn, r, f) for rn, r in rules for f in (0, F_REUSE)]
+    configs += [("bin", mwu.STEP_BIN, F_DROP), ("warm", mwu.STEP_BIN_WARM, F_REUSE | F_DROP)]
     for name, make in makers.items():
-        for rule_name, rule in rules:
-            for reuse in (False, True):
-                s = make(precision=mwu.MIXED_FP32_FP64, step_rule=rule, flags=mwu._lib.FLAG_REUSE if reuse else 0)
-                walls, r = timed_solves(s, 2, 1, f"{name} {rule_name} reuse={reuse}")
-                s.close()
-                it = max(1, r.total_iterations)
-                out["runs"][f"{name}/{rule_name}/{'reuse' if reuse else 'fresh'}"] = {
-                    "s": statistics.mean(walls), "certified": r.certified, "bracket": [r.lower, r.upper],
-                    "probes": r.probes, "iterations": r.total_iterations, "search_passes": r.search_passes,
-                    "evaluations": r.evaluations, "passes_per_iteration": r.search_passes / it,
-                    "evaluations_per_iteration": r.evaluations / it}
+        for rule_name, rule, flags in configs:
+            tag = ("reuse" if flags & F_REUSE else "fresh") + ("+drop" if flags & F_DROP else "")
+            s = make(precision=mwu.MIXED_FP32_FP64, step_rule=rule, flags=flags)
+            walls, r = timed_solves(s, 2, 1, f"{name} {rule_name} {tag}")
+            s.close()
+            it = max(1, r.total_iterations)
+            out["runs"][f"{name}/{rule_name}/{tag}"] = {
+                "s": statistics.mean(walls), "certified": r.certified, "bracket": [r.lower, r.upper],
+                "probes": r.probes, "iterations": r.total_iterations, "search_passes": r.search_passes,
+                "evaluations": r.evaluations, "passes_per_iteration": r.search_passes / it,
+                "evaluations_per_iteration": r.evaluations / it}
     return out
 
 

@@ -149,6 +149,13 @@ typedef struct {
  * MWU_STEP_BIN_WARM, searches its first step from the previous probe's last
  * step.  Single-problem handles; the batched program ignores it. */
 #define MWU_FLAG_REUSE        8u
+/* Drop satisfied covering rows: every iteration leaves out the covering rows
+ * with (C x)_i >= 1 (weight 0 in the smoothed minimum, h, Phi and the step
+ * search), the line C <- {c_i : c_i^T x < 1} of Algorithms 1 and 2 (Section
+ * 2.2, Section 4), which the paper's own experiments leave out.  eta stays
+ * that of the full row count.  Single-problem handles; the batched program
+ * (no explicit covering rows) ignores it. */
+#define MWU_FLAG_DROP_SATISFIED 16u
 
 typedef struct {
     double eps;                 /* accuracy, default 0.1 (Section 6.2) */

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void dn_row(DnDev<T> dd, Ctl *ctl, double *p
     for (int e = blockIdx.x * BLOCK + threadIdx.x; e < dd.ne; e += stride) {
         const double z = dd.z[e] + a * dd.dz[e];
         dd.z[e] = z;
-        const double u = exp(-eta * (z - LC));
+        const double u = row_met(ctl, z) ? 0.0 : exp(-eta * (z - LC));
         dd.u[e] = (T)u;
         v[1] += u;
         v[2] = fmin(v[2], z);
@@ -264,6 +264,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
         const double xs[2] = {dd.x[e] + a * dd.d[e], dd.x[ne + e] + a * dd.d[ne + e]};
         const double h = need_gh ? sC * (double)dd.u[e] * invSu : -INFINITY;
         const double ze = sizeof(T) == 4 ? dd.z[e] : 0.0;
+        const bool met = sizeof(T) == 4 && row_met(ctl, ze);   // FP64: u = 0 gives h = 0
         double ds[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(BLOCK) void dn_col(DnDev<T> dd, Ctl *ctl, double *p
                 // log-domain ratio: no underflow of the FP32 weights, and
                 // q = 1 - g/h = -expm1(ln(g/h)) without cancellation near g = h
                 const double lr = eta * (dd.y[r] - LP) + eta * (ze - LC) + lnK;
-                q = -expm1(fmin(lr, 80.0));
+                q = met ? 0.0 : -expm1(fmin(lr, 80.0));
             } else {
                 q = h > 0.0 ? 1.0 - g / h : 0.0;
             }
@@ -359,7 +360,8 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
         if (ctl->ref_valid == 0) {   // [min z' | max eta y']
             double v[2] = {INFINITY, -INFINITY};
             for (int r = r0; r < dd.nv; r += stride) v[1] = fmax(v[1], eta * (dd.y[r] + a * dd.dy[r]));
-            for (int e = r0; e < dd.ne; e += stride) v[0] = fmin(v[0], dd.z[e] + a * dd.dz[e]);
+            for (int e = r0; e < dd.ne; e += stride)
+                if (!row_met(ctl, dd.z[e])) v[0] = fmin(v[0], dd.z[e] + a * dd.dz[e]);
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
             store_record(s_rec, 2, part);
@@ -372,6 +374,7 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
                 v[2] += dd.dy[r] * t;
             }
             for (int e = r0; e < dd.ne; e += stride) {
+                if (row_met(ctl, dd.z[e])) continue;
                 const double t = exp(-eta * ((dd.z[e] + a * dd.dz[e]) - zm));
                 v[1] += t;
                 v[3] += dd.dz[e] * t;

@@ -640,6 +640,14 @@ constexpr double skip_exponent()
     return sizeof(T) == 4 ? 40.0 : 746.0;
 }
 
+// A covering row the iteration leaves out when satisfied rows are dropped
+// (Algorithms 1 and 2 keep only the rows with c_i^T x < 1): its weight is 0,
+// so it adds nothing to the smoothed minimum, h, Phi or their refinements.
+// z only grows, so a row once met stays out.  The minimum of z is still
+// taken over every row: a met row is at least 1, so it changes neither the
+// stop test nor the early return.
+MWU_DEV bool row_met(const Ctl *c, double z) { return c->drop && z >= 1.0; }
+
 // The active lists of the sparse passes hold every covering row that is not
 // negligible while the weight shift Lw has moved by at most act_mu / eta
 // since they were built: z only grows (x and d are nonnegative), so a row
@@ -1275,10 +1283,14 @@ MWU_DEV void finish_row(Ctl *c, const double *rec)
         c->zmin = c->z1;
     } else {
         const double su = rec[1];
-        bad |= !(su > 0.0) || !isfinite(su);
-        c->LC -= log(su) / c->eta;
-        c->invSu = 1.0 / su;
         c->zmin = rec[2];
+        if (c->drop && c->zmin >= 1.0) {
+            // every row met and left out: no weights, the probe ends below
+        } else {
+            bad |= !(su > 0.0) || !isfinite(su);
+            c->LC -= log(su) / c->eta;
+            c->invSu = 1.0 / su;
+        }
     }
     if (c->eval_mode) { c->phase = PH_COL; return; }
     if (bad) { c->status = ST_NUMERIC; c->phase = PH_COMMIT; return; }

@@ -93,7 +93,8 @@ struct Ctl {
     double last_alpha;
     double sumx;                // sum of x (init / final statistics)
     double *trace;              // nullable device array: accepted step of each iteration
-    int32_t trace_cap, pad3;
+    int32_t trace_cap;
+    int32_t drop;               // nonzero: covering rows with z >= 1 are left out (weight 0)
     // ---- sparse passes (fused vertex cover): covering rows whose weight is
     // exactly zero in the storage type are left out of the passes
     int32_t act_on, act_ne;     // lists built; edges in the active search list

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(BLOCK) void k_row(GenericDev<T> gd, Ctl *ctl, doubl
             v[0] += (double)w;
             v[3] = fmax(v[3], (double)y);
         } else {
-            const T u = exp_arg(-eta * ((double)y - LC), T(0));
+            const T u = row_met(ctl, (double)y) ? T(0) : exp_arg(-eta * ((double)y - LC), T(0));
             gd.wu[r] = u;
             v[1] += (double)u;
             v[2] = fmin(v[2], (double)y);
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             for (int r = r0; r < mR; r += stride) {
                 const double yp = (double)gd.yz[r] + a * (double)gd.dyz[r];
                 if (r < mPc) v[1] = fmax(v[1], eta * yp);
-                else v[0] = fmin(v[0], yp);
+                else if (!row_met(ctl, (double)gd.yz[r])) v[0] = fmin(v[0], yp);
             }
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
                     const double t = exp(eta * yp - pm);
                     v[0] += t;
                     v[2] += dv * t;
-                } else {
+                } else if (!row_met(ctl, (double)gd.yz[r])) {
                     const double t = exp(-eta * (yp - zm));
                     v[1] += t;
                     v[3] += dv * t;

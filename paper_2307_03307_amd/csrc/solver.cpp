@@ -465,6 +465,7 @@ static void begin_probe(Solver &s, double param, const double *x0, double eps_pr
     c.status = ST_RUNNING;
     c.phase = PH_IDLE;
     c.last_alpha = start_alpha;
+    c.drop = (s.opt.flags & MWU_FLAG_DROP_SATISFIED) ? 1 : 0;
     push_ctl(s);
     if (x0) s.prog->upload_x(x0);
     s.prog->probe_init(x0 != nullptr || device_x0);
@@ -1154,6 +1155,7 @@ mwu_status mwu_potential_forward(void *h, const double *x_dev, double *value_out
         hipStream_t st = stream ? (hipStream_t)stream : s.stream;
         pull_ctl(s);
         s.ctl_host->eval_mode = 2;
+        s.ctl_host->drop = 0;   // the potential is over every row
         HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
         DevBuf val;
         val.alloc(8);
@@ -1176,6 +1178,7 @@ mwu_status mwu_potential_backward(void *h, const double *x_dev, double grad_scal
         hipStream_t st = stream ? (hipStream_t)stream : s.stream;
         pull_ctl(s);
         s.ctl_host->eval_mode = 2;
+        s.ctl_host->drop = 0;   // the potential is over every row
         HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
         s.dir_pending = false;
         s.prog->potential(x_dev, nullptr, grad_scale, grad_dev, st);
@@ -1197,6 +1200,7 @@ mwu_status mwu_potential_backward_noalloc(void *h, const double *x_dev, double g
         hipStream_t st = stream ? (hipStream_t)stream : s.stream;
         pull_ctl(s);
         s.ctl_host->eval_mode = 2;
+        s.ctl_host->drop = 0;   // the potential is over every row
         HIP_OK(hipMemcpyAsync(s.ctl_buf.p, s.ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st));
         s.dir_pending = false;
         if (!s.prog->potential_static(x_dev, grad_scale, grad_dev, scr, kNoAllocScratchBytes, st))

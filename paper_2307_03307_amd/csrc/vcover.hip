@@ -146,11 +146,15 @@ MWU_DEV void finish_vcA(Ctl *c, const double *rec)
     c->ymax = c->y1;
     c->invSw = 1.0;
     const double su = 0.5 * rec[0];
-    const bool bad = !(su > 0.0) || !isfinite(su);
-    c->LCw = c->LC;
-    c->LC = c->LCw - log(su) / c->eta;
-    c->invSu = 1.0 / su;
     c->zmin = rec[1];
+    // every edge met and left out (dropped rows): no weights, the probe ends
+    const bool all_met = c->drop && c->zmin >= 1.0;
+    const bool bad = !all_met && (!(su > 0.0) || !isfinite(su));
+    c->LCw = c->LC;
+    if (!all_met) {
+        c->LC = c->LCw - log(su) / c->eta;
+        c->invSu = 1.0 / su;
+    }
     if (c->eval_mode) { c->phase = PH_COL; return; }
     if (bad) { c->status = ST_NUMERIC; c->phase = PH_COMMIT; return; }
     if (c->zmin >= 1.0) { c->status = ST_FEASIBLE; c->phase = PH_COMMIT; }
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(BLOCK) void vc_passA_k(VcDev<T> vd, Ctl *ctl, doubl
     auto term = [&](T xu, T xw) -> T {
         const double z = (double)xu + (double)xw;
         v[1] = fmin(v[1], z);
-        return exp_arg(-eta * (z - Lw), T(0));
+        return row_met(ctl, z) ? T(0) : exp_arg(-eta * (z - Lw), T(0));
     };
     auto epi = [&](int u, T acc) {
         vd.h[u] = acc;
@@ -396,7 +400,7 @@ __device__ void vc_search_edges(const VcDev<T> &vd, const Ctl *ctl, double *s_wa
         const double zd = (double)pu.x + (double)pw.x;
         const T z = (T)zd;
         const T dz = pu.d + pw.d;
-        const T u = exp_arg(-eta * (zd - Lw), T(0));
+        const T u = row_met(ctl, zd) ? T(0) : exp_arg(-eta * (zd - Lw), T(0));
         cov_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, u, z, dz, ca.acc, ca.zmn, deriv);
     };
     if (act_valid(ctl, Lw)) for_edge_list<T>(vd, vd.aeu, vd.aew, ctl->act_ne, visit);
@@ -420,6 +424,7 @@ __device__ __forceinline__ void vc_search_body(const VcDev<T> &vd, Ctl *ctl, dou
         double v[3] = {0.0, 0.0, INFINITY};
         auto visit = [&](XD<T> pu, XD<T> pw, int) {
             const double dzp = (double)pu.d + (double)pw.d;
+            if (row_met(ctl, (double)pu.x + (double)pw.x)) return;
             const double zp = ((double)pu.x + (double)pw.x) + a * dzp;
             if (second) {
                 const double t = exp(-eta * (zp - zm));
@@ -540,9 +545,9 @@ __global__ void vc_import_k(VcDev<T> vd, const double *src)
 // stays true while the shift drifts by less than mu / eta).
 
 template <class T>
-MWU_DEV bool left_out(double z, double eta, double L, double mu)
+MWU_DEV bool left_out(double z, double eta, double L, double mu, bool drop)
 {
-    return eta * (z - L) > skip_exponent<T>() + mu;
+    return eta * (z - L) > skip_exponent<T>() + mu || (drop && z >= 1.0);
 }
 
 // Pack the active neighbours of each tile of the full adjacency at the start
@@ -583,7 +588,7 @@ __global__ __launch_bounds__(BLOCK) void vc_pack_k(VcDev<T> vd, const Ctl *ctl, 
                     zr = (double)vd.xs[tl.s0 + lo];
                     first = s_ptr[lo] == k;
                 }
-                keep = !left_out<T>(zr + (double)vd.xs[col], eta, L, mu);
+                keep = !left_out<T>(zr + (double)vd.xs[col], eta, L, mu, ctl->drop != 0);
             }
             const unsigned long long m = __ballot(keep);
             if (lane == 0) s_cnt[wv] = __popcll(m);
@@ -741,7 +746,7 @@ __global__ __launch_bounds__(BLOCK) void vc_act_count_k(VcDev<T> vd, const Ctl *
     double v[2] = {0.0, INFINITY};   // active count | min z left out
     for (int e = e0 + threadIdx.x; e < e1; e += BLOCK) {
         const double z = (double)vd.xs[vd.eu[e]] + (double)vd.xs[vd.ew[e]];
-        if (left_out<T>(z, eta, L, mu)) v[1] = fmin(v[1], z);
+        if (left_out<T>(z, eta, L, mu, ctl->drop != 0)) v[1] = fmin(v[1], z);
         else v[0] += 1.0;
     }
     const Red red{1, 1, 0};
@@ -809,7 +814,7 @@ __global__ __launch_bounds__(BLOCK) void vc_act_scatter_k(VcDev<T> vd, const Ctl
         if (e < e1) {
             u = vd.eu[e];
             w = vd.ew[e];
-            keep = !left_out<T>((double)vd.xs[u] + (double)vd.xs[w], eta, L, mu);
+            keep = !left_out<T>((double)vd.xs[u] + (double)vd.xs[w], eta, L, mu, ctl->drop != 0);
         }
         const unsigned long long m = __ballot(keep);
         if (lane == 0) s_cnt[wv] = __popcll(m);

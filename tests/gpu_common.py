@@ -16,6 +16,14 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / scale) if b.size else 0.0
 
 
+def _merge_flags(kw, flags):
+    """Keyword arguments of a solver factory with `flags` or-ed into any the
+    caller passes."""
+    out = dict(kw)
+    out["flags"] = out.get("flags", 0) | flags
+    return out
+
+
 def ones_row(n):
     return oracle.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
 
@@ -43,7 +51,7 @@ def vcover_case(g, param=None, generic=False):
     flags = mwu._lib.FLAG_GENERIC if generic else 0
     param = param or 0.3 * n
     return Case("vcover" + ("-generic" if generic else ""),
-                lambda **kw: mwu.vertex_cover(g.num_vertices, g.u, g.v, flags=flags, **kw),
+                lambda **kw: mwu.vertex_cover(g.num_vertices, g.u, g.v, **_merge_flags(kw, flags)),
                 ones_row(n), C, lambda p: 1.0 / p, lambda p: 1.0, param)
 
 
@@ -61,7 +69,7 @@ def densest_case(g, param=None, generic=False):
     param = param or 1.2 * g.num_edges / keep.shape[0]
     flags = mwu._lib.FLAG_GENERIC if generic else 0
     return Case("densest" + ("-generic" if generic else ""),
-                lambda **kw: mwu.densest_subgraph(g.num_vertices, g.u, g.v, flags=flags, **kw), O, W,
+                lambda **kw: mwu.densest_subgraph(g.num_vertices, g.u, g.v, **_merge_flags(kw, flags)), O, W,
                 lambda p: 1.0 / p, lambda p: 1.0, param)
 
 
