@@ -91,6 +91,9 @@ def lib():
                                          ctypes.c_int32, ctypes.c_int32, vp, P(_SolveResult)]
         L.orc_solve_densest.argtypes = [P(_Mat), P(_Mat), vp, vp, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, P(_SolveResult)]
+        L.orc_solve_mixed_opt.argtypes = [P(_Mat), P(_Mat), vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                          P(_SolveResult)]
         L.orc_smax.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
         L.orc_smax.restype = ctypes.c_double
         L.orc_smin.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
@@ -358,6 +361,23 @@ def solve_covering(C: CSR, eps: float = 0.1, max_iter: int = 5000, max_probes: i
     if rc != 0:
         raise RuntimeError(f"orc_solve_covering failed: {rc}")
     return _solve_result(r, x)
+
+
+def solve_mixed_opt(P: CSR, C: CSR, c, maximize: bool, eps: float = 0.1, max_iter: int = 5000,
+                    max_probes: int = 64, step_rule: int = STEP_BIN, reuse: bool = False, drop: bool = False):
+    """max (maximize) or min c^T x s.t. P x <= 1, C x >= 1, x >= 0 with the
+    objective embedded as one more row and its level M searched (R23).
+    Returns (SolveResult, violation), violation = max{0, max(P x) - 1} of
+    the returned x."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    x = np.zeros(P.cols)
+    v = ctypes.c_double()
+    r = _SolveResult()
+    rc = lib().orc_solve_mixed_opt(P.c, C.c, c.ctypes.data, int(maximize), eps, max_iter, max_probes, step_rule,
+                                   _flags(reuse, drop), x.ctypes.data, ctypes.addressof(v), ctypes.byref(r))
+    if rc != 0:
+        raise RuntimeError(f"orc_solve_mixed_opt failed: {rc}")
+    return _solve_result(r, x), v.value
 
 
 def solve_densest(g, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,

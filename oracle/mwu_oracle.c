@@ -94,6 +94,14 @@
  *       iteration on; a row already satisfied at the start is left out of
  *       the first iteration too (the set is a function of the current point
  *       alone).  The probe stops FEASIBLE when no row is left.
+ *   R23 mixed optimization (orc_solve_mixed_opt; the last sentence of
+ *       Section 2.2): the objective of max/min c^T x s.t. P x <= 1, C x >= 1
+ *       is embedded as the row (1/M) c^T x >= 1 (covering side, maximizing)
+ *       or <= 1 (packing side, minimizing) and M is searched geometrically;
+ *       infeasible probes bound OPT exactly, feasible ones give points with
+ *       C x >= 1 and P x within Algorithm 2's 1 + eps of 1 (the violation is
+ *       reported); when minimizing, M grows fourfold until a probe is
+ *       feasible.
  *   R21 probe-to-probe reuse (the reuse argument of the outer searches): a
  *       probe after the first starts from its predecessor's iterate scaled so
  *       that its largest packing row, under the new probe's scale, is eps --
@@ -927,6 +935,143 @@ int orc_solve_covering(const orc_mat *C, double eps, int32_t max_iter, int32_t m
 done:
     free(x); free(z); free(cs);
     ones_row_free(&one);
+    return rc;
+}
+
+/* ------------------------------------------------ mixed optimization (R23) */
+
+/*
+ * maximize (maximize = 1) or minimize (maximize = 0) c^T x
+ *   s.t.  P x <= 1,  C x >= 1,  x >= 0      (rows already normalized by b)
+ * The objective is embedded as one more row, (1/M) c^T x >= 1 on the
+ * covering side (maximization) or (1/M) c^T x <= 1 on the packing side
+ * (minimization), and M is searched geometrically (end of Section 2.2).
+ * An infeasible probe at M proves OPT < M (maximization) or OPT > M
+ * (minimization); a feasible probe returns x with C x >= 1, the objective
+ * row met, and P x <= max(Px), which Algorithm 2 keeps within about 1 + eps
+ * of 1.  Bracket: [largest feasible M, smallest infeasible M] when
+ * maximizing (the upper end starts at sum_i c_i / max_j P_ji, which bounds
+ * OPT), [largest infeasible M, smallest feasible M] when minimizing (the
+ * lower end starts at the uniform dual bound m_C min_i c_i / (1^T C)_i of
+ * the covering rows, and the probes grow M fourfold until one is feasible).
+ * x_best is the point of the best feasible probe; r->objective its c^T x;
+ * *violation its max{0, max(Px) - 1}.
+ */
+int orc_solve_mixed_opt(const orc_mat *P, const orc_mat *C, const double *c, int32_t maximize, double eps,
+                        int32_t max_iter, int32_t max_probes, int32_t step_rule, int32_t flags,
+                        double *x_best, double *violation, orc_solve_result *r)
+{
+    const int64_t n = P->cols;
+    memset(r, 0, sizeof(*r));
+    *violation = 0.0;
+    if (C->cols != n || P->rows < 1 || C->rows < 1) return ORC_ERR_ARG;
+    for (int64_t i = 0; i < n; ++i) if (!(c[i] > 0.0) || !isfinite(c[i])) return ORC_ERR_ARG;
+    /* the side that receives the objective row, as a copy with one more row */
+    const orc_mat *S = maximize ? C : P;
+    const int64_t nnz = S->ptr[S->rows];
+    int64_t *ptr = malloc((size_t)(S->rows + 2) * sizeof(int64_t));
+    int32_t *idx = malloc((size_t)(nnz + n) * sizeof(int32_t));
+    double *val = malloc((size_t)(nnz + n) * sizeof(double));
+    double *x = malloc((size_t)n * sizeof(double));
+    double *y = malloc((size_t)P->rows * sizeof(double));
+    double *cm = calloc((size_t)n, sizeof(double));
+    double *cs = calloc((size_t)n, sizeof(double));
+    int rc = ORC_OK;
+    if (!ptr || !idx || !val || !x || !y || !cm || !cs) { rc = ORC_ERR_OOM; goto done; }
+    memcpy(ptr, S->ptr, (size_t)(S->rows + 1) * sizeof(int64_t));
+    memcpy(idx, S->idx, (size_t)nnz * sizeof(int32_t));
+    memcpy(val, S->val, (size_t)nnz * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) idx[nnz + i] = (int32_t)i;
+    ptr[S->rows + 1] = nnz + n;
+    orc_mat A = {S->rows + 1, n, ptr, idx, val};
+    const orc_mat *Pp = maximize ? P : &A, *Cp = maximize ? &A : C;
+    /* starting brackets */
+    double lo, hi, slo, shi;
+    if (maximize) {
+        for (int64_t j = 0; j < P->rows; ++j)
+            for (int64_t k = P->ptr[j]; k < P->ptr[j + 1]; ++k)
+                if (P->val[k] > cm[P->idx[k]]) cm[P->idx[k]] = P->val[k];
+        hi = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(cm[i] > 0.0)) { rc = ORC_ERR_UNBOUNDED; goto done; }
+            hi += c[i] / cm[i];
+        }
+        lo = 0.0;
+        shi = hi;
+        slo = hi / 1048576.0;
+    } else {
+        for (int64_t j = 0; j < C->rows; ++j)
+            for (int64_t k = C->ptr[j]; k < C->ptr[j + 1]; ++k) cs[C->idx[k]] += C->val[k];
+        double t = INFINITY;
+        for (int64_t i = 0; i < n; ++i) if (cs[i] > 0.0 && c[i] / cs[i] < t) t = c[i] / cs[i];
+        if (!isfinite(t)) { rc = ORC_ERR_ARG; goto done; }
+        lo = (double)C->rows * t;
+        hi = INFINITY;
+        /* the value of the covering-feasible point x_i = max_{j: C_ji>0} 1/(C_ji nnz_j) */
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        for (int64_t j = 0; j < C->rows; ++j) {
+            const double nz = (double)(C->ptr[j + 1] - C->ptr[j]);
+            for (int64_t k = C->ptr[j]; k < C->ptr[j + 1]; ++k) {
+                const double v = 1.0 / (C->val[k] * nz);
+                if (v > x[C->idx[k]]) x[C->idx[k]] = v;
+            }
+        }
+        double cx = 0.0;
+        for (int64_t i = 0; i < n; ++i) cx += c[i] * x[i];
+        slo = lo;
+        shi = cx > 2.0 * lo ? cx : 2.0 * lo;
+    }
+    double last = 0.0;
+    int have = 0;
+    while (r->probes < max_probes && !(hi <= (1.0 + eps) * lo)) {
+        /* minimization before any feasible probe: probe the top of the bracket */
+        const int grow = !maximize && !have;
+        if (!grow && !(shi > (1.0 + eps / 16.0) * slo)) break;
+        const double M = grow ? shi : sqrt(slo * shi);
+        for (int64_t i = 0; i < n; ++i) val[nnz + i] = c[i] / M;
+        orc_probe_result pr;
+        const int warm = (flags & ORC_FLAG_REUSE) && r->probes > 0 && orc_reuse_start(Pp, 1.0, eps, x);
+        rc = orc_probe_from(Pp, 1.0, Cp, 1.0, eps, max_iter, step_rule, warm, x, NULL, 0, NULL, 0,
+                            warm ? last : 0.0, (flags & ORC_FLAG_DROP) != 0, &pr);
+        if (rc) goto done;
+        last = pr.last_alpha;
+        r->probes++;
+        r->total_iterations += pr.iterations;
+        r->final_probe_iterations = pr.iterations;
+        r->evaluations += pr.evaluations;
+        const int feasible = pr.status == ORC_FEASIBLE;
+        if (feasible) {
+            double cx = 0.0, ym = 0.0;
+            for (int64_t i = 0; i < n; ++i) cx += c[i] * x[i];
+            orc_matvec(P, 1.0, x, y);
+            for (int64_t j = 0; j < P->rows; ++j) if (y[j] > ym) ym = y[j];
+            const int better = !have || (maximize ? M > lo : M < hi);
+            if (better) {
+                memcpy(x_best, x, (size_t)n * sizeof(double));
+                r->objective = cx;
+                *violation = ym > 1.0 ? ym - 1.0 : 0.0;
+                have = 1;
+            }
+            if (maximize) { if (M > lo) lo = M; slo = M; }
+            else { if (M < hi) hi = M; shi = M; }
+        } else {
+            if (maximize) {
+                if (pr.status == ORC_INFEASIBLE && M < hi) hi = M;
+                shi = M;
+            } else {
+                if (pr.status == ORC_INFEASIBLE && M > lo) lo = M;
+                slo = M;
+                if (grow) shi = 4.0 * M;
+            }
+        }
+        if (slo < lo) slo = lo;
+        if (shi > hi) shi = hi;
+    }
+    r->lower = lo;
+    r->upper = hi;
+    r->status = (have && hi <= (1.0 + eps) * lo) ? 0 : 1;
+done:
+    free(ptr); free(idx); free(val); free(x); free(y); free(cm); free(cs);
     return rc;
 }
 

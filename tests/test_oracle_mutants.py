@@ -83,6 +83,10 @@ MUTANTS = [
      "if (st->z[j] < 1.0) { st->ai[st->na] = j;", "if (st->z[j] < 2.0) { st->ai[st->na] = j;"),
     ("drop: weights of met rows left in u",
      "for (int64_t j = 0; j < st->mC; ++j) st->u[j] = 0.0;", "for (int64_t j = 0; j < 0; ++j) st->u[j] = 0.0;"),
+    ("mixed optimization: objective row scaled by M instead of 1/M",
+     "for (int64_t i = 0; i < n; ++i) val[nnz + i] = c[i] / M;", "for (int64_t i = 0; i < n; ++i) val[nnz + i] = c[i] * M;"),
+    ("mixed optimization: a feasible minimization probe moves the lower end",
+     "else { if (M < hi) hi = M; shi = M; }", "else { if (M > lo) lo = M; shi = M; }"),
     ("level sets: edge counted at its first endpoint",
      "cnt[(a > b ? a : b) + 1]++;", "cnt[(a < b ? a : b) + 1]++;"),
 ]

@@ -1037,3 +1037,61 @@ def test_drop_solves_bracket_exact_optima(oracle_mod, seed):
     g = gg.gnm_random(14, 30, seed=seed + 4)
     r = oracle_mod.solve_densest(g, drop=True)
     _check_densest(oracle_mod, g, r, brute_force_density(g))
+
+
+# ------------------------------------------------------------ mixed optimization (R23)
+
+def _rand_mixed_lp(seed, n=30, mP=12, mC=8, dens=0.25):
+    rng = np.random.default_rng(seed)
+    draw = lambda k: rng.uniform(0.5, 2.0, k)
+    P = sp.random(mP, n, density=dens, random_state=rng, data_rvs=draw).tolil()
+    C = sp.random(mC, n, density=dens, random_state=rng, data_rvs=draw).tolil()
+    for j in range(n):                       # every variable in some packing row
+        if P[:, j].nnz == 0:
+            P[rng.integers(mP), j] = 1.0
+    for i in range(mC):                      # no empty covering row
+        if C[i].nnz == 0:
+            C[i, rng.integers(n)] = 1.0
+    return P.tocsr(), C.tocsr(), rng.uniform(0.5, 2.0, n)
+
+
+def _as_csr(oracle_mod, A):
+    return oracle_mod.CSR(A.shape[0], A.shape[1], A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                          A.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("maximize", [True, False])
+def test_mixed_optimization_brackets_the_lp_optimum(oracle_mod, seed, maximize):
+    """End of Section 2.2: a mixed packing/covering optimization LP solved by
+    embedding its objective as one more row and searching its level (R23).
+    Against HiGHS on random LPs: the infeasible verdicts bound OPT exactly
+    (maximizing: OPT <= upper; minimizing: lower <= OPT), the returned x
+    meets every covering row and the objective level of the bracket end it
+    comes from, it is feasible for the packing rows relaxed by the reported
+    violation (so its objective is at most / at least the relaxed LP's
+    optimum), the violation stays within eps, and the bracket is certified
+    within 1 + eps."""
+    P, C, c = _rand_mixed_lp(seed)
+    r, viol = oracle_mod.solve_mixed_opt(_as_csr(oracle_mod, P), _as_csr(oracle_mod, C), c, maximize)
+    sgn = -1.0 if maximize else 1.0
+    A = np.vstack([P.toarray(), -C.toarray()])
+
+    def lp(slack):
+        b = np.concatenate([np.full(P.shape[0], 1.0 + slack), -np.ones(C.shape[0])])
+        res = linprog(sgn * c, A_ub=A, b_ub=b, bounds=(0, None))
+        assert res.status == 0
+        return sgn * res.fun
+
+    opt, relaxed = lp(0.0), lp(viol)
+    x = r.x
+    assert r.certified and r.upper <= (1 + EPS) * r.lower * (1 + 1e-12)
+    assert (C.toarray() @ x).min() >= 1 - 1e-9 and x.min() >= 0
+    assert (P.toarray() @ x).max() <= 1 + viol + 1e-12 and viol <= EPS
+    assert r.objective == pytest.approx(float(c @ x), rel=1e-12)
+    if maximize:
+        assert opt <= r.upper * (1 + 1e-12)
+        assert r.objective >= r.lower * (1 - 1e-12) and r.objective <= relaxed * (1 + 1e-9)
+    else:
+        assert r.lower <= opt * (1 + 1e-12)
+        assert r.objective >= relaxed * (1 - 1e-9)
