@@ -156,6 +156,9 @@ class CSR:
         self.val = np.ascontiguousarray(self.val, dtype=np.float64)
         self._c = _Mat(self.rows, self.cols, self.ptr.ctypes.data, self.idx.ctypes.data,
                        self.val.ctypes.data)
+        # the struct holds raw addresses: let it own the arrays, so that
+        # `.c` of a temporary CSR stays valid for the call it is passed to
+        self._c._arrays = (self.ptr, self.idx, self.val)
 
     @property
     def c(self):

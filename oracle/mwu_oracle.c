@@ -948,14 +948,16 @@ done:
  * (minimization), and M is searched geometrically (end of Section 2.2).
  * An infeasible probe at M proves OPT < M (maximization) or OPT > M
  * (minimization); a feasible probe returns x with C x >= 1, the objective
- * row met, and P x <= max(Px), which Algorithm 2 keeps within about 1 + eps
- * of 1.  Bracket: [largest feasible M, smallest infeasible M] when
+ * row met, and every packing row (the objective row too when minimizing)
+ * at most max(Px), which Algorithm 2 keeps within about 1 + eps of 1.
+ * Bracket: [largest feasible M, smallest infeasible M] when
  * maximizing (the upper end starts at sum_i c_i / max_j P_ji, which bounds
  * OPT), [largest infeasible M, smallest feasible M] when minimizing (the
  * lower end starts at the uniform dual bound m_C min_i c_i / (1^T C)_i of
  * the covering rows, and the probes grow M fourfold until one is feasible).
  * x_best is the point of the best feasible probe; r->objective its c^T x;
- * *violation its max{0, max(Px) - 1}.
+ * *violation its max{0, max(Px) - 1} over those packing rows.  The probes
+ * start from the Algorithm 1 point (probe reuse is not applied here).
  */
 int orc_solve_mixed_opt(const orc_mat *P, const orc_mat *C, const double *c, int32_t maximize, double eps,
                         int32_t max_iter, int32_t max_probes, int32_t step_rule, int32_t flags,
@@ -973,7 +975,7 @@ int orc_solve_mixed_opt(const orc_mat *P, const orc_mat *C, const double *c, int
     int32_t *idx = malloc((size_t)(nnz + n) * sizeof(int32_t));
     double *val = malloc((size_t)(nnz + n) * sizeof(double));
     double *x = malloc((size_t)n * sizeof(double));
-    double *y = malloc((size_t)P->rows * sizeof(double));
+    double *y = malloc((size_t)(P->rows + 1) * sizeof(double));
     double *cm = calloc((size_t)n, sizeof(double));
     double *cs = calloc((size_t)n, sizeof(double));
     int rc = ORC_OK;
@@ -1021,7 +1023,6 @@ int orc_solve_mixed_opt(const orc_mat *P, const orc_mat *C, const double *c, int
         slo = lo;
         shi = cx > 2.0 * lo ? cx : 2.0 * lo;
     }
-    double last = 0.0;
     int have = 0;
     while (r->probes < max_probes && !(hi <= (1.0 + eps) * lo)) {
         /* minimization before any feasible probe: probe the top of the bracket */
@@ -1030,11 +1031,10 @@ int orc_solve_mixed_opt(const orc_mat *P, const orc_mat *C, const double *c, int
         const double M = grow ? shi : sqrt(slo * shi);
         for (int64_t i = 0; i < n; ++i) val[nnz + i] = c[i] / M;
         orc_probe_result pr;
-        const int warm = (flags & ORC_FLAG_REUSE) && r->probes > 0 && orc_reuse_start(Pp, 1.0, eps, x);
-        rc = orc_probe_from(Pp, 1.0, Cp, 1.0, eps, max_iter, step_rule, warm, x, NULL, 0, NULL, 0,
-                            warm ? last : 0.0, (flags & ORC_FLAG_DROP) != 0, &pr);
+        /* every probe starts from the Algorithm 1 point (no reuse here) */
+        rc = orc_probe_from(Pp, 1.0, Cp, 1.0, eps, max_iter, step_rule, 0, x, NULL, 0, NULL, 0,
+                            0.0, (flags & ORC_FLAG_DROP) != 0, &pr);
         if (rc) goto done;
-        last = pr.last_alpha;
         r->probes++;
         r->total_iterations += pr.iterations;
         r->final_probe_iterations = pr.iterations;
@@ -1043,8 +1043,8 @@ int orc_solve_mixed_opt(const orc_mat *P, const orc_mat *C, const double *c, int
         if (feasible) {
             double cx = 0.0, ym = 0.0;
             for (int64_t i = 0; i < n; ++i) cx += c[i] * x[i];
-            orc_matvec(P, 1.0, x, y);
-            for (int64_t j = 0; j < P->rows; ++j) if (y[j] > ym) ym = y[j];
+            orc_matvec(Pp, 1.0, x, y);      /* the packing rows with the objective row if there */
+            for (int64_t j = 0; j < Pp->rows; ++j) if (y[j] > ym) ym = y[j];
             const int better = !have || (maximize ? M > lo : M < hi);
             if (better) {
                 memcpy(x_best, x, (size_t)n * sizeof(double));

@@ -1095,3 +1095,4 @@ def test_mixed_optimization_brackets_the_lp_optimum(oracle_mod, seed, maximize):
     else:
         assert r.lower <= opt * (1 + 1e-12)
         assert r.objective >= relaxed * (1 - 1e-9)
+        assert r.objective <= r.upper * (1 + viol) * (1 + 1e-12)   # the objective row, within the violation
