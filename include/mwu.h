@@ -70,9 +70,29 @@ typedef int32_t mwu_status;
 typedef enum {
     MWU_PACKING = 0,   /* max c^T x  s.t. A x <= b, x >= 0        (eq. LPDef; pure packing, Sec. 2.2) */
     MWU_COVERING = 1,  /* min c^T x  s.t. A x >= b, x >= 0        (pure covering, Sec. 2.2)          */
-    MWU_MIXED = 2      /* min lambda s.t. P x <= lambda b_P, C x >= b_C, x >= 0: the densest
+    MWU_MIXED = 2,     /* min lambda s.t. P x <= lambda b_P, C x >= b_C, x >= 0: the densest
                           subgraph "min D" form (Section 3); with opts.mixed_fixed_lambda > 0 a
                           single feasibility probe P x <= lambda b_P, C x >= b_C (eq. NormFeasibleLP) */
+    /* Mixed optimization (last sentence of Section 2.2): max (MIXED_MAX) or
+     * min (MIXED_MIN) c^T x s.t. P x <= b_P, C x >= b_C, x >= 0, c > 0
+     * required.  The objective is embedded as one more row, (1/M) c^T x >= 1
+     * among the covering rows (max) or <= 1 among the packing rows (min), and
+     * M is searched: an infeasible probe at M proves OPT < M (max) or
+     * OPT > M (min); a feasible one gives x with C x >= b_C and the objective
+     * row met, its packing rows (the objective row too when minimizing)
+     * within Algorithm 2's (1 + eps).  Results: x_out is the best feasible
+     * probe's point, objective_out its c^T x, [lower, upper] the bracket
+     * (max: largest feasible M, smallest infeasible M; min: largest
+     * infeasible M, smallest feasible M), max_violation its
+     * max{0, max_i (P x)_i / b_P,i - 1} (minimizing, the objective row
+     * c^T x / M counts among the packing rows).  CERTIFIED when the bracket
+     * is within 1 + eps; INFEASIBLE when no probe was feasible (x_out is
+     * then all zero).  Maximizing, a column without a packing entry is
+     * rejected (MWU_ERR_UNBOUNDED); minimizing, a column without a covering
+     * entry is kept and never moves from its start.  Generic CSR engine;
+     * probe reuse is not applied. */
+    MWU_MIXED_MAX = 3,
+    MWU_MIXED_MIN = 4
 } mwu_form;
 
 typedef enum {

@@ -18,11 +18,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CERTIFIED, COVERING, FEASIBLE_POINT, FEASIBLE_UNCERTIFIED, FP64, INFEASIBLE, MAX_ITER,
-                   MIXED, MIXED_FP32_FP64, PACKING, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON, STEP_STD, MwuError)
+                   MIXED, MIXED_FP32_FP64, MIXED_MAX, MIXED_MIN, PACKING, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON,
+                   STEP_STD, MwuError)
 
 __all__ = ["Solver", "BatchSolver", "Result", "csr_matrix", "incidence", "incidence_t", "edge_pair",
            "interweave", "bmatch", "vertex_cover", "dominating_set", "densest_subgraph",
-           "MwuError", "PACKING", "COVERING", "MIXED", "FP64", "MIXED_FP32_FP64", "STEP_BIN", "STEP_BIN_WARM",
+           "MwuError", "PACKING", "COVERING", "MIXED", "MIXED_MAX", "MIXED_MIN", "FP64", "MIXED_FP32_FP64", "STEP_BIN", "STEP_BIN_WARM",
            "STEP_NEWTON", "STEP_STD", "CERTIFIED", "FEASIBLE_UNCERTIFIED", "INFEASIBLE", "MAX_ITER", "FEASIBLE_POINT"]
 
 VEC = {"x": 0, "d": 1, "g": 2, "h": 3, "y": 4, "z": 5, "dy": 6, "dz": 7, "alpha": 8}

@@ -17,7 +17,7 @@ ERRORS = {
 # outcomes
 CERTIFIED, FEASIBLE_UNCERTIFIED, INFEASIBLE, MAX_ITER, FEASIBLE_POINT = 0, 1, 2, 3, 4
 PROBE_RUNNING, PROBE_FEASIBLE, PROBE_INFEASIBLE, PROBE_MAX_ITER = 0, 1, 2, 3
-PACKING, COVERING, MIXED = 0, 1, 2
+PACKING, COVERING, MIXED, MIXED_MAX, MIXED_MIN = 0, 1, 2, 3, 4
 MAT_CSR, MAT_INCIDENCE, MAT_INCIDENCE_T, MAT_EDGE_PAIR, MAT_INTERWEAVE = 0, 1, 2, 3, 4
 STEP_STD, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON = 0, 1, 2, 3
 FP64, MIXED_FP32_FP64 = 0, 1

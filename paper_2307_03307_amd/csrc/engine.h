@@ -335,6 +335,12 @@ template <class T> void narrow(const double *src, T *dst, int64_t n, hipStream_t
 void set_phase(Ctl *ctl, int phase, hipStream_t st);
 // v[i * stride] *= th for i < n (a probe started from a scaled earlier point)
 template <class T> void scale_vec(T *v, int64_t n, int64_t stride, double th, hipStream_t st);
+// Every entry of one row set to v: its row-structure values rval[k0, k0+n)
+// (and the FP64 copy), its column-structure values cval[pos[j]]; with colmax
+// (an objective row among the packing rows) colmax[j] = max(base[j], v).
+template <class T> void generic_set_row(T *rval, double *rval64, int64_t k0, int64_t n, T *cval,
+                                        const int32_t *pos, double v, double *colmax, const double *base,
+                                        hipStream_t st);
 // Continue a probe whose direction was formed in evaluation mode: the stop
 // tests of the iteration, then its step search (forced: the program's forced
 // steps, nullable).

@@ -613,6 +613,29 @@ void scale_vec(T *v, int64_t n, int64_t stride, double th, hipStream_t st)
 {
     LAUNCH(k_scale<T>, grid_for(n), v, n, stride, th);
 }
+template <class T>
+__global__ void k_set_row(T *rval, double *rval64, int64_t k0, int64_t n, T *cval, const int32_t *pos, double v,
+                          double *colmax, const double *base)
+{
+    for (int64_t j = blockIdx.x * (int64_t)BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
+        rval[k0 + j] = (T)v;
+        rval64[k0 + j] = v;
+        cval[pos[j]] = (T)v;
+        if (colmax) colmax[j] = fmax(base[j], v);
+    }
+}
+
+template <class T>
+void generic_set_row(T *rval, double *rval64, int64_t k0, int64_t n, T *cval, const int32_t *pos, double v,
+                     double *colmax, const double *base, hipStream_t st)
+{
+    LAUNCH(k_set_row<T>, grid_for(n), rval, rval64, k0, n, cval, pos, v, colmax, base);
+}
+template void generic_set_row<float>(float *, double *, int64_t, int64_t, float *, const int32_t *, double,
+                                     double *, const double *, hipStream_t);
+template void generic_set_row<double>(double *, double *, int64_t, int64_t, double *, const int32_t *, double,
+                                      double *, const double *, hipStream_t);
+
 template void scale_vec<float>(float *, int64_t, int64_t, double, hipStream_t);
 template void scale_vec<double>(double *, int64_t, int64_t, double, hipStream_t);
 

@@ -114,6 +114,9 @@ struct Program {
     // Level-set rounding of the current vertex loads (densest subgraph):
     // false when the program has no such structure (the host computes it).
     virtual bool level_set_density(double *) { return false; }
+    // Mixed optimization (MWU_MIXED_MAX/MIN): the embedded objective row's
+    // value v = 1/M on every entry, set before each probe.
+    virtual void set_objective_level(double) { throw ApiError{MWU_ERR_STATE, "no objective row"}; }
 };
 
 // Many independent problems solved together (the batched programs).
@@ -188,7 +191,10 @@ struct TilePlan {
 TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg);
 
 // Program builders.
-std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C);
+// obj_row: index (in the concatenated packing-then-covering row space) of an
+// embedded objective row whose values set_objective_level rewrites, or -1.
+std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C,
+                                              int64_t obj_row = -1);
 // Vertex cover from a validated edge list; newid maps vertices to compact ids (-1 = isolated).
 // Densest subgraph from the edge list of an (O/D, W) problem; vid maps vertices
 // to compact ids (-1 isolated), in vertex order.

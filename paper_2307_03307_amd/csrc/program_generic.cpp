@@ -48,7 +48,7 @@ TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg)
 template <class T>
 class GenericProgram : public Program {
   public:
-    GenericProgram(Solver &s, const HostCSR *P, const HostCSR *C) : s_(s)
+    GenericProgram(Solver &s, const HostCSR *P, const HostCSR *C, int64_t obj_row) : s_(s)
     {
         const int64_t mPc = s.onesP ? 0 : P->rows;
         const int64_t mCc = s.onesC ? 0 : C->rows;
@@ -56,7 +56,7 @@ class GenericProgram : public Program {
         mPc_ = mPc;
         mR_ = mPc + mCc;
         if (mR_ < 1) throw ApiError{MWU_ERR_INVALID_ARG, "no explicit constraint rows"};
-        const bool vals = (!s.onesP && !P->val.empty()) || (!s.onesC && !C->val.empty());
+        const bool vals = (!s.onesP && !P->val.empty()) || (!s.onesC && !C->val.empty()) || obj_row >= 0;
         const int64_t nnz = (s.onesP ? 0 : P->nnz()) + (s.onesC ? 0 : C->nnz());
         if (nnz >= INT32_MAX || mR_ >= INT32_MAX || n_ >= INT32_MAX)
             throw ApiError{MWU_ERR_TOO_LARGE, "structure exceeds 32-bit device indices"};
@@ -81,6 +81,7 @@ class GenericProgram : public Program {
         std::vector<T> cval(vals ? nnz : 0);
         for (int64_t q = 0; q < nnz; ++q) cptr[rcol[q] + 1]++;
         for (int64_t i = 0; i < n_; ++i) cptr[i + 1] += cptr[i];
+        std::vector<int32_t> opos;   // positions of the objective row's entries in the column structure
         {
             std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
             for (int64_t rr = 0; rr < mR_; ++rr)
@@ -88,13 +89,21 @@ class GenericProgram : public Program {
                     const int32_t pos = fill[rcol[q]]++;
                     crow[pos] = (int32_t)rr;
                     if (vals) cval[pos] = rval[q];
+                    if (rr == obj_row) opos.push_back(pos);
                 }
         }
-        // max_j P_ji per column (Algorithm 1 initial point)
+        if (obj_row >= 0) {
+            obj_k0_ = rptr[obj_row];
+            obj_n_ = rptr[obj_row + 1] - rptr[obj_row];
+            obj_in_P_ = obj_row < mPc;
+        }
+        // max_j P_ji per column (Algorithm 1 initial point); an objective row
+        // in P enters at each probe (its level changes)
         std::vector<double> colmax;
         if (!s.onesP) {
             colmax.assign(n_, 0.0);
-            for (int64_t q = 0; q < P->nnz(); ++q)
+            const int64_t lastq = (obj_row >= 0 && obj_row < mPc) ? rptr[obj_row] : P->nnz();
+            for (int64_t q = 0; q < lastq; ++q)
                 colmax[P->idx[q]] = std::max(colmax[P->idx[q]], P->v(q));
         }
         nnz_ = nnz;
@@ -113,6 +122,10 @@ class GenericProgram : public Program {
         up(crow_, crow.data(), crow.size() * 4);
         up(cval_, cval.data(), cval.size() * sizeof(T));
         up(colmax_, colmax.data(), colmax.size() * 8);
+        if (obj_row >= 0) {
+            up(opos_, opos.data(), opos.size() * 4);
+            up(colmax_base_, colmax.data(), colmax.size() * 8);
+        }
         up(rtiles_, rt.tiles.data(), rt.tiles.size() * sizeof(Tile));
         up(ctiles_, ct.tiles.data(), ct.tiles.size() * sizeof(Tile));
         up(rlseg_, rt.lseg.data(), rt.lseg.size() * 4);
@@ -196,6 +209,13 @@ class GenericProgram : public Program {
     }
 
     void scale_x(double th) override { scale_vec<T>(gd_.x, n_, 1, th, s_.stream); }
+
+    void set_objective_level(double v) override
+    {
+        if (obj_n_ <= 0) throw ApiError{MWU_ERR_STATE, "no objective row"};
+        generic_set_row<T>(rval_.as<T>(), rval64_.as<double>(), obj_k0_, obj_n_, cval_.as<T>(), opos_.as<int32_t>(), v,
+                           obj_in_P_ ? colmax_.as<double>() : nullptr, colmax_base_.as<double>(), s_.stream);
+    }
 
     void iterations(int slots) override
     {
@@ -359,12 +379,15 @@ class GenericProgram : public Program {
     DevBuf rlseg_, rlfirst_, rlcount_, clseg_, clfirst_, clcount_, rlpart_, clpart_, rlpart64_, rval64_;
     DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, forced_, dbg_g_, dbg_h_;
     int32_t rslots_ = 0, cslots_ = 0;   // chunk partial slots of the long rows and columns
+    DevBuf opos_, colmax_base_;         // embedded objective row: its column positions, colmax without it
+    int64_t obj_k0_ = 0, obj_n_ = 0;
+    bool obj_in_P_ = false;
 };
 
-std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C)
+std::unique_ptr<Program> make_generic_program(Solver &s, const HostCSR *P, const HostCSR *C, int64_t obj_row)
 {
-    if (s.fp32) return std::unique_ptr<Program>(new GenericProgram<float>(s, P, C));
-    return std::unique_ptr<Program>(new GenericProgram<double>(s, P, C));
+    if (s.fp32) return std::unique_ptr<Program>(new GenericProgram<float>(s, P, C, obj_row));
+    return std::unique_ptr<Program>(new GenericProgram<double>(s, P, C, obj_row));
 }
 
 }  // namespace mwu

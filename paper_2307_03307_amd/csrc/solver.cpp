@@ -172,9 +172,26 @@ static HostCSR drop_rows(const HostCSR &A, const std::vector<char> &keep)
     return B;
 }
 
+// Renumbers the columns of A by newid; entries of removed columns (newid < 0)
+// leave the structure with them.
 static void remap_cols(HostCSR &A, const std::vector<int64_t> &newid, int64_t ncols)
 {
-    for (auto &c : A.idx) c = (int32_t)newid[c];
+    int64_t k = 0;
+    const bool vals = !A.val.empty();
+    for (int64_t r = 0; r < A.rows; ++r) {
+        const int64_t q0 = A.ptr[r], q1 = A.ptr[r + 1];
+        A.ptr[r] = k;
+        for (int64_t q = q0; q < q1; ++q) {
+            const int64_t c = newid[A.idx[q]];
+            if (c < 0) continue;
+            A.idx[k] = (int32_t)c;
+            if (vals) A.val[k] = A.val[q];
+            ++k;
+        }
+    }
+    A.ptr[A.rows] = k;
+    A.idx.resize(k);
+    if (vals) A.val.resize(k);
     A.cols = ncols;
 }
 
@@ -229,8 +246,10 @@ static_assert(MWU_STEP_STD == SR_STD && MWU_STEP_BIN == SR_BIN && MWU_STEP_BIN_W
 static void build(Solver &s, const mwu_problem &p)
 {
     s.form = p.form;
-    check(p.form == MWU_PACKING || p.form == MWU_COVERING || p.form == MWU_MIXED,
+    check(p.form == MWU_PACKING || p.form == MWU_COVERING || p.form == MWU_MIXED || p.form == MWU_MIXED_MAX ||
+              p.form == MWU_MIXED_MIN,
           MWU_ERR_INVALID_ARG, "bad form");
+    const bool mixed_opt = p.form == MWU_MIXED_MAX || p.form == MWU_MIXED_MIN;
     check(s.opt.eps > 0.0 && s.opt.eps < 1.0, MWU_ERR_INVALID_ARG, "eps must be in (0,1)");
     check(s.opt.max_iter >= 1 && s.opt.max_probes >= 1, MWU_ERR_INVALID_ARG, "bad iteration caps");
     check(s.opt.step_rule == MWU_STEP_STD || s.opt.step_rule == MWU_STEP_BIN ||
@@ -260,6 +279,19 @@ static void build(Solver &s, const mwu_problem &p)
         s.n_user = C.cols;
         if (p.c) { cvec.assign(p.c, p.c + C.cols); check_rhs(p.c, C.cols, "bad c"); }
         check_rhs(p.b_C, C.rows, "bad b");
+        scale_rows_cols(C, p.b_C, cvec);
+    } else if (mixed_opt) {
+        check(p.c != nullptr, MWU_ERR_INVALID_ARG, "the mixed optimization forms need c");
+        P = to_csr(p.P, &elP);
+        C = to_csr(p.C, &elC);
+        check(P.cols == C.cols, MWU_ERR_INVALID_ARG, "P and C column counts differ");
+        s.n_user = P.cols;
+        check_rhs(p.b_P, P.rows, "bad b_P");
+        check_rhs(p.b_C, C.rows, "bad b_C");
+        check_rhs(p.c, P.cols, "bad c");
+        cvec.assign(p.c, p.c + P.cols);
+        // x' = c x: the objective row becomes (1/M) 1^T x'
+        scale_rows_cols(P, p.b_P, cvec);
         scale_rows_cols(C, p.b_C, cvec);
     } else {
         check(!p.c, MWU_ERR_INVALID_ARG, "c is not used by MWU_MIXED");
@@ -298,19 +330,71 @@ static void build(Solver &s, const mwu_problem &p)
             keep = true;
         } else if (p.form == MWU_COVERING) {
             keep = ccnt[i] > 0;
+        } else if (p.form == MWU_MIXED_MAX) {
+            // every column is in the objective row; the packing rows bound it
+            check(pcnt[i] > 0, MWU_ERR_UNBOUNDED, "column without packing entry: LP unbounded");
+            keep = true;
+        } else if (p.form == MWU_MIXED_MIN) {
+            // every column is in the objective row (a packing row); one without
+            // a covering entry never moves from its start (h = 0)
+            keep = true;
         } else {
             keep = ccnt[i] > 0;
             if (keep) check(pcnt[i] > 0, MWU_ERR_UNBOUNDED, "column with covering but no packing entry");
         }
         if (keep) { newid[i] = kept++; s.col_user.push_back(i); s.col_c.push_back(cvec.empty() ? 1.0 : cvec[i]); }
     }
-    if (!s.onesP) remap_cols(P, newid, kept);
+    if (!s.onesP) {
+        remap_cols(P, newid, kept);
+        // packing rows whose entries all sat in removed columns never bind
+        std::vector<char> keep(P.rows);
+        for (int64_t r = 0; r < P.rows; ++r) keep[r] = P.ptr[r + 1] > P.ptr[r];
+        P = drop_rows(P, keep);
+        check(P.rows >= 1, MWU_ERR_INVALID_ARG, "packing matrix has no nonzero in a kept column");
+    }
     if (!s.onesC) remap_cols(C, newid, kept);
     if (!P.val.empty() && all_ones(P)) P.val.clear();
     if (!C.val.empty() && all_ones(C)) C.val.clear();
+    int64_t obj_row = -1;
+    if (mixed_opt) {
+        check(C.rows >= 1, MWU_ERR_INVALID_ARG, "the mixed optimization forms need covering rows");
+        const double eps = s.opt.eps;
+        std::vector<double> cmax(kept, 0.0), colsum(kept, 0.0), xt(kept, 0.0);
+        for (int64_t k = 0; k < P.nnz(); ++k) cmax[P.idx[k]] = std::max(cmax[P.idx[k]], P.v(k));
+        for (int64_t r = 0; r < C.rows; ++r) {
+            const double nz = (double)(C.ptr[r + 1] - C.ptr[r]);
+            for (int64_t k = C.ptr[r]; k < C.ptr[r + 1]; ++k) {
+                colsum[C.idx[k]] += C.v(k);
+                xt[C.idx[k]] = std::max(xt[C.idx[k]], 1.0 / (C.v(k) * nz));
+            }
+        }
+        if (p.form == MWU_MIXED_MAX) {
+            double hi = 0.0;   // x'_i <= 1 / max_j P'_ji
+            for (int64_t i = 0; i < kept; ++i) hi += 1.0 / cmax[i];
+            s.hi0 = hi;
+            s.lo0 = 0.0;
+        } else {
+            // uniform dual weights on the covering rows; the covering-feasible
+            // point's value starts the search
+            s.lo0 = (double)C.rows / *std::max_element(colsum.begin(), colsum.end());
+            double v = 0.0;
+            for (double t : xt) v += t;
+            s.hi0 = std::max(v, 2.0 * s.lo0);
+        }
+        (void)eps;
+        // the objective row: every kept column, its values set before each probe
+        HostCSR &A = p.form == MWU_MIXED_MAX ? C : P;
+        if (A.val.empty()) A.val.assign(A.nnz(), 1.0);
+        for (int64_t i = 0; i < kept; ++i) { A.idx.push_back((int32_t)i); A.val.push_back(1.0); }
+        A.ptr.push_back(A.ptr.back() + kept);
+        A.rows += 1;
+        obj_row = p.form == MWU_MIXED_MAX ? P.rows + C.rows - 1 : P.rows - 1;
+    }
     // ---- outer-search starting bracket (same rules as the CPU reference)
     const double eps = s.opt.eps;
-    if (p.form == MWU_PACKING) {
+    if (mixed_opt) {
+        // set above
+    } else if (p.form == MWU_PACKING) {
         std::vector<double> cmin(kept, INFINITY), cmax(kept, 0.0);
         for (int64_t k = 0; k < P.nnz(); ++k) {
             const double v = P.v(k);
@@ -398,15 +482,19 @@ static void build(Solver &s, const mwu_problem &p)
         C = HostCSR();
         s.prog = make_densest_program(s, elP, vid, nv);
     } else {
-        s.prog = make_generic_program(s, s.onesP ? nullptr : &P, s.onesC ? nullptr : &C);
+        s.prog = make_generic_program(s, s.onesP ? nullptr : &P, s.onesC ? nullptr : &C, obj_row);
     }
 }
 
 // ------------------------------------------------------------ probes
 
+static bool mixed_opt_form(const Solver &s) { return s.form == MWU_MIXED_MAX || s.form == MWU_MIXED_MIN; }
+
+// Uniform scales of the two sides in a probe at param (the mixed optimization
+// forms scale their embedded objective row instead)
 static double probe_scale_P(const Solver &s, double param)
 {
-    return s.form == MWU_PACKING ? 1.0 : 1.0 / param;
+    return s.form == MWU_PACKING || mixed_opt_form(s) ? 1.0 : 1.0 / param;
 }
 static double probe_scale_C(const Solver &s, double param)
 {
@@ -467,6 +555,7 @@ static void begin_probe(Solver &s, double param, const double *x0, double eps_pr
     c.last_alpha = start_alpha;
     c.drop = (s.opt.flags & MWU_FLAG_DROP_SATISFIED) ? 1 : 0;
     push_ctl(s);
+    if (mixed_opt_form(s)) s.prog->set_objective_level(1.0 / param);   // the row (1/M) 1^T x'
     if (x0) s.prog->upload_x(x0);
     s.prog->probe_init(x0 != nullptr || device_x0);
     s.in_probe = true;
@@ -560,7 +649,7 @@ static SolveOut solve_impl(Solver &s)
     // probes after the first may start from their predecessor's point (R21):
     // its iterate scaled so that the largest packing row of the next probe is
     // eps (the level of the Algorithm 1 point), and its last step
-    const bool reuse = (s.opt.flags & MWU_FLAG_REUSE) != 0;
+    const bool reuse = (s.opt.flags & MWU_FLAG_REUSE) != 0 && !mixed_opt_form(s);
     double prev_pmax = 0.0, prev_sP = 0.0, prev_alpha = 0.0;   // max(P x) in the previous probe's scale
     auto probe_done = [&](double param) {
         const double sPn = probe_scale_P(s, param);
@@ -614,6 +703,52 @@ static SolveOut solve_impl(Solver &s)
     // An infeasible verdict proves OPT < param (packing) or OPT > param
     // (covering, densest) up to the direction threshold qmin.
     const double cf = s.fp32 ? 1.0 - kMixedQmin : 1.0;
+    if (mixed_opt_form(s)) {
+        // the objective embedded as a row at level M (reading of the last
+        // sentence of Section 2.2): the same search as the CPU reference
+        const bool maxi = s.form == MWU_MIXED_MAX;
+        double mlo = maxi ? 0.0 : s.lo0, mhi = maxi ? s.hi0 : INFINITY;
+        double slo = maxi ? s.hi0 / 1048576.0 : s.lo0, shi = s.hi0;
+        bool have = false;
+        o.status = MWU_INFEASIBLE;
+        while (o.probes < s.opt.max_probes && !(mhi <= (1.0 + eps) * mlo)) {
+            const bool grow = !maxi && !have;   // minimizing: probe the top until one is feasible
+            if (!grow && !(shi > (1.0 + eps / 16.0) * slo)) break;
+            const double M = grow ? shi : std::sqrt(slo * shi);
+            const Ctl c = probe_done(M);
+            finish_probe_stats(s);
+            const Ctl f = *s.ctl_host;
+            if (c.status == ST_NUMERIC) throw ApiError{MWU_ERR_DEVICE, "numerical failure in a probe"};
+            if (trace)
+                std::fprintf(stderr, "[mwu] probe %lld M %.10g status %d iters %d sumx %.10g ymax %.10g\n",
+                             (long long)o.probes, M, c.status, c.iter, f.sumx, f.ymax);
+            if (c.status == ST_FEASIBLE) {
+                if (!have || (maxi ? M > mlo : M < mhi)) {
+                    s.prog->save_best();
+                    o.have_best_dev = true;
+                    o.best_scale = 1.0;
+                    o.objective = f.sumx;   // 1^T x' = c^T x
+                    o.max_violation = std::max(0.0, f.ymax - 1.0);
+                    have = true;
+                }
+                if (maxi) { mlo = std::max(mlo, M); slo = M; }
+                else { mhi = std::min(mhi, M); shi = M; }
+            } else if (maxi) {
+                if (c.status == ST_INFEASIBLE) mhi = std::min(mhi, M / cf);
+                shi = M;
+            } else {
+                if (c.status == ST_INFEASIBLE) mlo = std::max(mlo, M * cf);
+                slo = M;
+                if (grow) shi = 4.0 * M;
+            }
+            slo = std::max(slo, mlo);
+            shi = std::min(shi, mhi);
+        }
+        o.lower = mlo;
+        o.upper = mhi;
+        if (have) o.status = mhi <= (1.0 + eps) * mlo ? MWU_CERTIFIED : MWU_FEASIBLE_UNCERTIFIED;
+        return o;
+    }
     // search bracket for the parameter: moves to every probed value, while
     // lo/hi (the certified bracket on OPT) move only with certificates
     double slo = lo, shi = hi;
