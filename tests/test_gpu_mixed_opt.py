@@ -170,3 +170,22 @@ def test_mixed_optimization_infeasible_lp(maximize, precision):
         ro, _ = oracle.solve_mixed_opt(_ocsr(Pn), _ocsr(Cn), c, maximize, max_probes=12)
         assert not ro.certified and ro.probes == r.probes and not np.any(ro.x)
         assert r.lower == pytest.approx(ro.lower, rel=1e-9) and r.upper == pytest.approx(ro.upper, rel=1e-9)
+
+
+def test_columns_without_covering_entries_leave_the_lp():
+    """The min-lambda mixed form keeps only the columns with a covering
+    entry; their packing entries leave the structure with them (they were
+    once renumbered to -1).  The LP then solves bit for bit as the LP with
+    those columns deleted, and they come back as 0."""
+    P, C, bP, bC, _ = _lp(0, rhs=False)
+    keep = np.asarray((C != 0).sum(axis=0)).ravel() > 0
+    gone = ~keep & (np.asarray((P != 0).sum(axis=0)).ravel() > 0)
+    assert gone.sum() >= 3
+    with _gpu(P, C, bP, bC, None, mwu.MIXED, precision=mwu.FP64) as s:
+        r = s.solve()
+    Pk, Ck = P[:, keep].tocsr(), C[:, keep].tocsr()
+    with _gpu(Pk, Ck, bP, bC, None, mwu.MIXED, precision=mwu.FP64) as s:
+        rk = s.solve()
+    print(f"{gone.sum()} packing-only columns: bracket [{r.lower:.9g}, {r.upper:.9g}], {r.probes} probes")
+    assert r.certified and (r.lower, r.upper, r.probes) == (rk.lower, rk.upper, rk.probes)
+    assert np.array_equal(r.x[keep], rk.x) and np.all(r.x[~keep] == 0.0)
