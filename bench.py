@@ -105,13 +105,9 @@ def pass_times(s, reps, param, warm_iters=0, last=0):
     return out
 
 
-def dominant(passes, r, kernels, names, tag, workload):
-    """The pass with the largest share of one iteration: one row pass, one
-    column pass, one forward pass, and the search passes (the combined first
-    pass, plus exponential-grid or bisection passes in the iterations the
-    combined pass does not settle).  Its roofline is reported for its common
-    launch (the combined pass for the search)."""
-    from paper_2307_03307_amd import profiling
+def _shares(passes, r, kernels):
+    """Each pass's time per iteration, the dominant one, and the pass index
+    whose held launches stand for it (the combined pass for the search)."""
     spi = r.search_passes / max(1, r.total_iterations)
     extra = max(0.0, spi - 1.0)
     fallback_us = 0.5 * (passes[3]["us"] + passes[4]["us"])
@@ -119,7 +115,17 @@ def dominant(passes, r, kernels, names, tag, workload):
     share = {k: passes[k]["us"] for k in (0, 1, 2) if k in passes and k in kernels}
     share[3] = spi * search_us
     dom = max(share, key=share.get)
-    dom_pass = 5 if dom == 3 else dom
+    return share, dom, 5 if dom == 3 else dom
+
+
+def dominant(passes, r, kernels, names, tag, workload):
+    """The pass with the largest share of one iteration: one row pass, one
+    column pass, one forward pass, and the search passes (the combined first
+    pass, plus exponential-grid or bisection passes in the iterations the
+    combined pass does not settle).  Its roofline is reported for its common
+    launch (the combined pass for the search)."""
+    from paper_2307_03307_amd import profiling
+    share, dom, dom_pass = _shares(passes, r, kernels)
     kernel = kernels[dom]
     tname = "float" if tag == "f32" else "double"
     full = f"{kernel}<{tname}, false>" if kernel.endswith("_fwd_v") else f"{kernel}<{tname}>"
@@ -332,6 +338,140 @@ def run_vcover(args, steps, warmup, scale=20, with_cpu=False):
     }
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline_vcover(g, r32.total_iterations, r32.evaluations,
+                                                  0.5 * (r32.lower + r32.upper))
+    return out
+
+
+GEN_KERNELS = {0: "k_row", 1: "k_col", 2: "k_fwd", 3: "k_search"}
+
+
+def run_small(args, steps, warmup):
+    """The small bipartite matching LP (2000 + 2000 vertices, 20,000 distinct
+    uniform edges, seed 1; packing, max 1^T x s.t. M x <= 1): a solve here is
+    bound by launch and finisher latency, not by HBM, so the figure is the
+    time per MWU iteration next to the whole solve, in both forms, with the
+    plain FP64 oracle's whole solve of the same LP timed beside it (the full
+    workload: it finishes in seconds on one host core)."""
+    import torch
+    import graphgen as gg
+    import paper_2307_03307_amd as mwu
+    assert torch.cuda.is_available(), "needs an MI355X"
+    g = gg.bipartite_uniform(2000, 2000, 20000, seed=1)
+    out = {"workload": "bipartite matching LP, 2000 + 2000 vertices, 20,000 uniform edges, seed 1, eps=0.1",
+           "vertices": g.num_vertices, "edges": g.num_edges}
+    for tag, prec in (("", mwu.MIXED_FP32_FP64), ("fp64_", mwu.FP64)):
+        with mwu.bmatch(g.num_vertices, g.u, g.v, precision=prec, step_rule=step_rule_of(mwu, args)) as s:
+            walls, r = timed_solves(s, steps, warmup, f"small precision={prec}")
+        t = statistics.mean(walls)
+        out.update({f"{tag}s": t, f"{tag}certified": r.certified, f"{tag}bracket": [r.lower, r.upper],
+                    f"{tag}iterations": r.total_iterations, f"{tag}probes": r.probes,
+                    f"{tag}search_passes": r.search_passes,
+                    f"{tag}us_per_iteration": 1e6 * t / max(1, r.total_iterations)})
+    out["value"] = out.pop("s")
+    out["unit"] = "s"
+    out["steps"] = steps
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        M = oracle.incidence(g)
+        rule = {"bin": oracle.STEP_BIN, "warm": oracle.STEP_BIN_WARM, "newton": oracle.STEP_NEWTON}[args.step_rule]
+        reps, t = 0, time.perf_counter()
+        while reps < 3 or time.perf_counter() - t < 2.0:
+            ro = oracle.solve_packing(M, step_rule=rule)
+            reps += 1
+        wall = (time.perf_counter() - t) / reps
+        out["cpu_baseline"] = {
+            "value": wall, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"the whole workload, mean of {reps} runs: the oracle's outer search on the same LP "
+                       f"({ro.probes} probes, {ro.total_iterations} iterations, bracket "
+                       f"[{ro.lower:.6g}, {ro.upper:.6g}])"),
+            "us_per_iteration": 1e6 * wall / max(1, ro.total_iterations), "cpu_model": cpu_model()}
+    return out
+
+
+def cpu_baseline_domset(g, gpu_iters, gpu_evals, param):
+    """As cpu_baseline_vcover, for the dominating-set LP (I + A)x >= 1."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    C = oracle.dominating_set_matrix(g)
+    n = C.cols
+    ones = oracle.CSR(1, n, np.array([0, n]), np.arange(n), np.ones(n))
+
+    def run(rule, iters):
+        t = time.perf_counter()
+        r = oracle.probe(ones, 1.0 / param, C, 1.0, 0.1, max_iter=iters, step_rule=rule)
+        return time.perf_counter() - t, r
+
+    t1, _ = run(oracle.STEP_STD, 1)
+    t2, _ = run(oracle.STEP_STD, 3)
+    tb, rb = run(oracle.STEP_BIN, 1)
+    per_iter = max(t2 - t1, 1e-9) / 2
+    per_eval = max(tb - t1, 0.0) / max(1, rb.evaluations)
+    return {"value": per_iter * gpu_iters + per_eval * gpu_evals, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle on the same graph at M = {param:.6g}: 1 and 3 standard-step iterations, one "
+                       f"Algorithm 3 iteration ({rb.evaluations} evaluations); {per_iter:.3f} s per iteration x "
+                       f"{gpu_iters} + {per_eval:.3f} s per evaluation x {gpu_evals}"),
+            "per_iteration_s": per_iter, "per_evaluation_s": per_eval, "cpu_model": cpu_model()}
+
+
+def run_domset(args, steps, warmup):
+    """Dominating set LP ((I + A)x >= 1) on a Chung-Lu power-law graph (2M
+    vertices, exponent 2.3, mean degree 10, seed 4; 21.6M nonzeros): the
+    generic CSR engine with its LDS-staged long rows, whole solves in both
+    forms, without and with probe reuse, the held pass timings 600 iterations
+    into a probe and the roofline of the dominant kernel."""
+    import torch
+    import graphgen as gg
+    import paper_2307_03307_amd as mwu
+    assert torch.cuda.is_available(), "needs an MI355X"
+    t = time.perf_counter()
+    g = gg.cached("chunglu2m_g23_d10_s4", lambda: gg.chung_lu(2_000_000, 2.3, 10.0, seed=4))
+    ptr, col = gg.adjacency_csr(g, with_identity=True)
+    log(f"graph: {g.num_vertices} vertices, {g.num_edges} edges, {len(col)} nonzeros "
+        f"({time.perf_counter() - t:.1f}s)")
+
+    def run(precision, flags, steps, warmup, passes=False):
+        t = time.perf_counter()
+        s = mwu.dominating_set(ptr, col, g.num_vertices, precision=precision, flags=flags,
+                               step_rule=step_rule_of(mwu, args))
+        create = time.perf_counter() - t
+        walls, r = timed_solves(s, steps, warmup, f"domset precision={precision} flags={flags}")
+        p = None
+        if passes:
+            # timed twice: the dominant pass goes last the second time, so that
+            # its held launches are the last ones of its kernel
+            param = 0.5 * (r.lower + r.upper)
+            p = pass_times(s, args.pass_reps, param, warm_iters=600, last=1)
+            dom_pass = _shares(p, r, GEN_KERNELS)[2]
+            p = pass_times(s, args.pass_reps, param, warm_iters=600, last=dom_pass)
+        s.close()
+        return create, statistics.mean(walls), r, p
+
+    # the reuse run first: the chosen form's held launches are then the last
+    # of their kernels in the process
+    _, tr32, rr32, _ = run(mwu.MIXED_FP32_FP64, mwu._lib.FLAG_REUSE, 2, 1)
+    c32, t32, r32, p32 = run(mwu.MIXED_FP32_FP64, 0, steps, warmup, passes=True)
+    _, t64, r64, p64 = run(mwu.FP64, 0, 1, 0, passes=True)
+    out = {
+        "workload": "dominating set LP (I + A)x >= 1, Chung-Lu power law, 2M vertices, exponent 2.3, "
+                    "mean degree 10, seed 4, eps=0.1",
+        "vertices": g.num_vertices, "edges": g.num_edges, "nonzeros": int(len(col)),
+        "value": t32, "unit": "s", "steps": steps, "certified": r32.certified, "objective": r32.objective,
+        "bracket": [r32.lower, r32.upper], "iterations": r32.total_iterations, "probes": r32.probes,
+        "search_passes": r32.search_passes, "evaluations": r32.evaluations, "create_s": c32,
+        "fp64_plain_s": t64, "fp64_certified": r64.certified, "fp64_iterations": r64.total_iterations,
+        "speedup_vs_fp64": t64 / t32,
+        "reuse_s": tr32, "reuse_certified": rr32.certified, "reuse_iterations": rr32.total_iterations,
+        "reuse_probes": rr32.probes,
+        "passes": {PASS_NAMES[k]: v for k, v in p32.items()},
+        "passes_fp64": {PASS_NAMES[k]: v for k, v in p64.items()},
+        "roofline": dominant(p32, r32, GEN_KERNELS, PASS_NAMES, "f32", "chunglu2m"),
+        "roofline_fp64": dominant(p64, r64, GEN_KERNELS, PASS_NAMES, "f64", "chunglu2m"),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample) ...")
+        out["cpu_baseline"] = cpu_baseline_domset(g, r32.total_iterations, r32.evaluations,
                                                   0.5 * (r32.lower + r32.upper))
     return out
 
@@ -554,11 +694,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch", "steprules"],
+    ap.add_argument("--workload", choices=["densest", "vcover", "batched", "genmatch", "steprules", "small",
+                                           "domset"],
                     default="densest",
                     help="densest: the headline R-MAT scale 22 densest subgraph (default); vcover: R-MAT "
                          "vertex cover; batched: 512 matching LPs; genmatch: generalized matching; "
-                         "steprules: step rules and probe reuse compared on three workloads")
+                         "steprules: step rules and probe reuse compared on three workloads; small: the "
+                         "2000 + 2000 matching LP (time per iteration); domset: dominating set on a 2M-vertex "
+                         "power-law graph (generic engine)")
     ap.add_argument("--scale", type=int, default=None, help="R-MAT scale (default 22 densest, 20 vcover)")
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -605,6 +748,12 @@ def main():
         out = headline(args, d, d["workload"])
     elif args.workload == "steprules":
         out = run_steprules(args)
+    elif args.workload == "small":
+        d = run_small(args, args.steps, args.warmup)
+        out = headline(args, d, d["workload"])
+    elif args.workload == "domset":
+        d = run_domset(args, args.steps, args.warmup)
+        out = headline(args, d, d["workload"])
     else:
         out = run_genmatch(args)
     if args.copy_calib_mib:

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
                 if (!row_met(ctl, dd.z[e])) v[0] = fmin(v[0], dd.z[e] + a * dd.dz[e]);
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
-            store_record(s_rec, 2, part);
+            store_record_qmajor(s_rec, 2, part);
         } else {                     // [sum over packing rows | over covering rows | their derivative sums]
             const double pm = ctl->rfPm, zm = ctl->rfZmin;
             double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
             }
             const Red red{4, 0, 0};
             block_combine<4>(v, red, 0, s_wave, s_rec);
-            store_record(s_rec, 4, part);
+            store_record_qmajor(s_rec, 4, part);
         }
         return;
     }
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(BLOCK) void dn_search(DnDev<T> dd, Ctl *ctl, double
     case SK_COMBO: dn_search_rows<T, SK_COMBO>(dd, ctl, s_wave, s_rec); break;
     default: dn_search_rows<T, SK_LIST>(dd, ctl, s_wave, s_rec); break;
     }
-    store_record(s_rec, 4 * KC, part);
+    store_record_qmajor(s_rec, 4 * KC, part);
 }
 
 __global__ __launch_bounds__(BLOCK) void dn_search_fin(Ctl *ctl, const double *part, int G)
@@ -399,12 +399,13 @@ __global__ __launch_bounds__(BLOCK) void dn_search_fin(Ctl *ctl, const double *p
     __shared__ double s_wave[4 * 4 * KC];
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_SEARCH) return;
+    // the search records are stored entry-major (G is the search grid)
     if (ctl->skind == SK_REFINE) {
-        if (ctl->ref_valid == 0) fold_records<2>(part, G, Red{0, 1, 1}, 0, s_wave, s_rec);
-        else fold_records<4>(part, G, Red{4, 0, 0}, 0, s_wave, s_rec);
+        if (ctl->ref_valid == 0) fold_records_qmajor<2>(part, G, Red{0, 1, 1}, s_wave, s_rec);
+        else fold_records_qmajor<4>(part, G, Red{4, 0, 0}, s_wave, s_rec);
     } else {
         const Red red{3 * KC, KC, 0};
-        fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
+        fold_records_qmajor<4 * KC>(part, G, red, s_wave, s_rec);
     }
     // every candidate of a grid or list pass is evaluated at once, one per
     // lane, before the sequential replay

@@ -137,17 +137,50 @@ MWU_DEV void store_record_qmajor(const double *s_rec, int Q, double *partials)
     if ((int)threadIdx.x < Q) partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_rec[threadIdx.x];
 }
 
+// Fold of entry-major records: wave w owns entries w, w + 4, ...; each lane
+// folds records lane, lane + 64, ... of its entries (one coalesced row per
+// entry, every entry's load in flight at once), and a butterfly over the wave
+// finishes each entry.  A lane holds one value per owned entry, so records of
+// dozens of entries fold without the register pressure and the block-wide
+// exchanges of a fold that keeps every entry in every thread.  out (LDS) is
+// complete on return; s_wave is not used.
 template <int Q>
 MWU_DEV void fold_records_qmajor(const double *partials, int G, Red r, double *s_wave, double *out)
 {
-    double v[Q];
+    (void)s_wave;
+    constexpr int NW = BLOCK / 64;
+    constexpr int PER = (Q + NW - 1) / NW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v[PER];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = red_id(q, r);
-    for (int b = threadIdx.x; b < G; b += BLOCK) {
+    for (int i = 0; i < PER; ++i) v[i] = red_id(wv + i * NW, r);
+    for (int b = lane; b < G; b += 64) {
+        double t[PER];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = red_op(v[q], partials[(size_t)q * G + b], q, r);
+        for (int i = 0; i < PER; ++i) {
+            const int q = wv + i * NW;
+            t[i] = q < Q ? partials[(size_t)q * G + b] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = wv + i * NW;
+            if (q < Q) v[i] = red_op(v[i], t[i], q, r);
+        }
     }
-    block_combine<Q>(v, r, 0, s_wave, out);
+    // lanes at or above G hold identities: with fewer than 64 records the
+    // butterfly stops once it spans them (same values, fewer exchanges)
+    int span = 64;
+    if (G < 64) { span = 1; while (span < G) span <<= 1; }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = wv + i * NW;
+        double x = v[i];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1)
+            if (m < span) x = red_op(x, __shfl_xor(x, m), q, r);
+        if (lane == 0 && q < Q) out[q] = x;
+    }
+    __syncthreads();
 }
 
 // Fold the G records of a pass (finisher kernel, one workgroup): thread t

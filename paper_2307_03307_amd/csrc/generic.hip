@@ -393,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             }
             const Red red{0, 1, 1};
             block_combine<2>(v, red, 0, s_wave, s_rec);
-            store_record(s_rec, 2, part);
+            store_record_qmajor(s_rec, 2, part);
         } else {                  // [sumP | sumC | sumP' | sumC']
             const double pm = ctl->rfPm, zm = ctl->rfZmin;
             double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
             }
             const Red red{4, 0, 0};
             block_combine<4>(v, red, 0, s_wave, s_rec);
-            store_record(s_rec, 4, part);
+            store_record_qmajor(s_rec, 4, part);
         }
         return;
     }
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(BLOCK) void k_search(GenericDev<T> gd, Ctl *ctl, do
     case SK_COMBO: search_rows<T, SK_COMBO>(gd, ctl, s_wave, s_rec); break;
     default: search_rows<T, SK_LIST>(gd, ctl, s_wave, s_rec); break;
     }
-    store_record(s_rec, 4 * KC, part);
+    store_record_qmajor(s_rec, 4 * KC, part);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_search_fin(Ctl *ctl, const double *part, int G)
@@ -430,12 +430,13 @@ __global__ __launch_bounds__(BLOCK) void k_search_fin(Ctl *ctl, const double *pa
     __shared__ double s_wave[4 * 4 * KC];
     __shared__ double s_rec[QMAX];
     if (ctl->phase != PH_SEARCH) return;
+    // the search records are stored entry-major (G is the search grid)
     if (ctl->skind == SK_REFINE) {
-        if (ctl->ref_valid == 0) fold_records<2>(part, G, Red{0, 1, 1}, 0, s_wave, s_rec);
-        else fold_records<4>(part, G, Red{4, 0, 0}, 0, s_wave, s_rec);
+        if (ctl->ref_valid == 0) fold_records_qmajor<2>(part, G, Red{0, 1, 1}, s_wave, s_rec);
+        else fold_records_qmajor<4>(part, G, Red{4, 0, 0}, s_wave, s_rec);
     } else {
         const Red red{3 * KC, KC, 0};
-        fold_records<4 * KC>(part, G, red, 0, s_wave, s_rec);
+        fold_records_qmajor<4 * KC>(part, G, red, s_wave, s_rec);
     }
     // every candidate of a grid or list pass is evaluated at once, one per
     // lane, before the sequential replay

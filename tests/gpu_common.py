@@ -16,6 +16,32 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / scale) if b.size else 0.0
 
 
+# the chosen form moves a coordinate only when q = 1 - g/h exceeds 2^-16
+MIXED_QMIN = 2.0 ** -16
+
+
+def direction_err(d, ref, qmin, margin=0.25):
+    """Error of a direction d against the oracle's (exact rule q > 0), with
+    the chosen form's threshold q > qmin taken apart.  Returns (far, near):
+    far is the infinity-relative error over the coordinates whose oracle q
+    lies outside (0, (1 + margin) qmin] (the GPU's q carries FP32 rounding
+    of g and h, well inside the margin at qmin); near is, over the others,
+    the largest distance of the GPU's d_i from the nearer of 0 (dropped by
+    the threshold) and the oracle's d_i, relative to max |d|.  The dropped
+    coordinates alone can differ by qmin x_i (s / eta), which relative to
+    max |d| grows with x_i / max (q x) and has no fixed bound."""
+    d = np.asarray(d, dtype=np.float64)
+    rd = np.asarray(ref["d"], dtype=np.float64)
+    h = np.asarray(ref["h"], dtype=np.float64)
+    g = np.asarray(ref["g"], dtype=np.float64)
+    q = np.where(h > 0, 1.0 - g / np.where(h > 0, h, 1.0), 0.0)
+    near = (q > 0) & (q <= qmin * (1 + margin)) if qmin > 0 else np.zeros(d.shape, bool)
+    scale = max(np.max(np.abs(rd)), 1e-300)
+    far = float(np.max(np.abs(d[~near] - rd[~near])) / scale) if (~near).any() else 0.0
+    nb = float(np.max(np.minimum(np.abs(d[near]), np.abs(d[near] - rd[near]))) / scale) if near.any() else 0.0
+    return far, nb
+
+
 def _merge_flags(kw, flags):
     """Keyword arguments of a solver factory with `flags` or-ed into any the
     caller passes."""
