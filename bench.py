@@ -128,7 +128,7 @@ def dominant(passes, r, kernels, names, tag, workload):
     share, dom, dom_pass = _shares(passes, r, kernels)
     kernel = kernels[dom]
     tname = "float" if tag == "f32" else "double"
-    full = f"{kernel}<{tname}, false>" if kernel.endswith("_fwd_v") else f"{kernel}<{tname}>"
+    full = f"{kernel}<{tname}, false>" if kernel.endswith(("_fwd_v", "k_fwd")) else f"{kernel}<{tname}>"
     us, by = passes[dom_pass]["us"], passes[dom_pass]["bytes"]
     achieved = by / us / 1e3
     traffic = profiling.load_traffic(os.path.join(PROFILES, f"{kernel}_{workload}_{tag}_traffic.txt"), full)
@@ -280,6 +280,13 @@ def run_passes_only(args):
         g = rmat_graph(args.scale, args.edge_factor, 3)
         s = mwu.densest_subgraph(g.num_vertices, g.u, g.v, precision=prec, step_rule=step_rule_of(mwu, args))
         passes = pass_times(s, args.pass_reps, args.pass_only, warm_iters=args.pass_warm_iters, last=1)
+        names = PASS_NAMES
+    elif args.workload == "domset":
+        import graphgen as gg
+        g = gg.cached("chunglu2m_g23_d10_s4", lambda: gg.chung_lu(2_000_000, 2.3, 10.0, seed=4))
+        ptr, col = gg.adjacency_csr(g, with_identity=True)
+        s = mwu.dominating_set(ptr, col, g.num_vertices, precision=prec, step_rule=step_rule_of(mwu, args))
+        passes = pass_times(s, args.pass_reps, args.pass_only, warm_iters=600, last=1)
         names = PASS_NAMES
     else:
         g = rmat_graph(args.scale, args.edge_factor, 2)
@@ -717,7 +724,8 @@ def main():
     ap.add_argument("--gm-items", type=int, default=20000)
     ap.add_argument("--loop-sample", type=int, default=16)
     ap.add_argument("--pass-only", type=float, default=None,
-                    help="counter runs: time the passes of a probe at this parameter (densest D, vcover M) "
+                    help="counter runs: time the passes of a probe at this parameter (densest D, vcover or "
+                         "domset M) "
                          "and solve nothing")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed", help="with --pass-only")
     ap.add_argument("--copy-calib-mib", type=int, default=0,

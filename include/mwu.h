@@ -176,6 +176,16 @@ typedef struct {
  * that of the full row count.  Single-problem handles; the batched program
  * (no explicit covering rows) ignores it. */
 #define MWU_FLAG_DROP_SATISFIED 16u
+/* Generic CSR engine: its internal order of the variables and of the rows
+ * (no effect on any result's order, which stays the caller's).  By default
+ * the engine sorts the columns by their number of nonzeros and the rows of
+ * each side by theirs, both descending, when the column lengths are heavy-
+ * tailed (at least 4096 columns, the longest at least 32 times the mean):
+ * the random gathers of the two products then fall mostly on a compact
+ * prefix of hub entries.  KEEP_ORDER never reorders (inputs already laid
+ * out for locality, such as banded matrices); LOCALITY_ORDER always does. */
+#define MWU_FLAG_KEEP_ORDER     32u
+#define MWU_FLAG_LOCALITY_ORDER 64u
 
 typedef struct {
     double eps;                 /* accuracy, default 0.1 (Section 6.2) */

@@ -157,6 +157,8 @@ struct GenericDev {
     double *grad;                       // nullable: grad_scale (g - h) per column
     double grad_scale;
     const double *forced;               // forced steps (host-provided), nullable
+    const int32_t *cmap;                // nullable: internal column -> the caller's column, for
+                                        // vectors in the caller's order (a given x, the gradient)
 };
 
 // Fused vertex-cover program: C = M^T read from the edge list, P = the
@@ -326,8 +328,9 @@ template <class T> void generic_search(const GenericDev<T> &g, Ctl *ctl, const L
 template <class T> void generic_load_x(const GenericDev<T> &g, Ctl *ctl, const Launch &L,
                                        hipStream_t st, const double *x_dev);
 // out[i] = scale * (g_dbg[i] - h_dbg[i]); val (nullable) = LP - LC.
+// out[map[i]] = scale (g_i - h_i) (map nullable: the identity); val = LP - LC
 void potential_finish(const double *g_dbg, const double *h_dbg, int n, double scale, double *out,
-                      const Ctl *ctl, double *val, hipStream_t st);
+                      const int32_t *map, const Ctl *ctl, double *val, hipStream_t st);
 // Copy a device vector of T to a double device vector.
 template <class T> void widen(const T *src, double *dst, int64_t n, hipStream_t st);
 template <class T> void narrow(const double *src, T *dst, int64_t n, hipStream_t st);

@@ -51,7 +51,7 @@ struct ColEpi {
         v[2] = fmax(v[2], (double)dt);
         v[3] = fmax(v[3], h);
         if (gd.g_dbg) { gd.g_dbg[i] = g; gd.h_dbg[i] = h; }
-        if (gd.grad) gd.grad[i] = gd.grad_scale * (g - h);
+        if (gd.grad) gd.grad[gd.cmap ? gd.cmap[i] : i] = gd.grad_scale * (g - h);
     }
 };
 
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_x(GenericDev<T> gd, Ctl *ctl, in
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < gd.n; i += stride) {
         T x;
         if (src) {
-            x = (T)src[i];
+            x = (T)src[gd.cmap ? gd.cmap[i] : i];
             gd.x[i] = x;
         } else if (!have_x0) {
             // Algorithm 1: x_i = eps / (n max_j P_ji)
@@ -487,10 +487,10 @@ __global__ void k_resume_search(Ctl *c, const double *forced)
 }
 
 __global__ void k_potential_finish(const double *g, const double *h, int n, double scale,
-                                   double *out, const Ctl *ctl, double *val)
+                                   double *out, const int32_t *map, const Ctl *ctl, double *val)
 {
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK)
-        out[i] = scale * (g[i] - h[i]);
+        out[map ? map[i] : i] = scale * (g[i] - h[i]);
     if (val && blockIdx.x == 0 && threadIdx.x == 0) *val = ctl->LP - ctl->LC;
 }
 
@@ -587,9 +587,9 @@ void generic_iteration(const GenericDev<T> &g, Ctl *ctl, const Launch &L, hipStr
 }
 
 void potential_finish(const double *g_dbg, const double *h_dbg, int n, double scale, double *out,
-                      const Ctl *ctl, double *val, hipStream_t st)
+                      const int32_t *map, const Ctl *ctl, double *val, hipStream_t st)
 {
-    LAUNCH(k_potential_finish, grid_for(n), g_dbg, h_dbg, n, scale, out, ctl, val);
+    LAUNCH(k_potential_finish, grid_for(n), g_dbg, h_dbg, n, scale, out, map, ctl, val);
 }
 
 template <class T>

@@ -218,7 +218,7 @@ class DensestProgram : public Program {
         dn_init<T>(g, ctl(), L_, st, true, x_dev);
         dn_row_pass<T>(g, ctl(), L_, st);
         dn_col_pass<T>(g, ctl(), L_, st);
-        if (val_dev) potential_finish(nullptr, nullptr, 0, scale, nullptr, ctl(), val_dev, st);
+        if (val_dev) potential_finish(nullptr, nullptr, 0, scale, nullptr, nullptr, ctl(), val_dev, st);
     }
 
     bool potential_static(const double *x_dev, double grad_scale, double *grad_dev, void *scr, size_t bytes,

@@ -45,6 +45,19 @@ TilePlan build_tiles(const std::vector<int32_t> &ptr, int64_t nseg)
     return tp;
 }
 
+// Whether the generic engine lays out its columns and rows by length: the
+// flags decide when set; otherwise heavy-tailed column lengths (at least
+// 4096 columns, the longest at least 32 times the mean) do.
+static bool locality_order(uint64_t flags, const std::vector<int64_t> &clen, int64_t nnz)
+{
+    if (flags & MWU_FLAG_KEEP_ORDER) return false;
+    if (flags & MWU_FLAG_LOCALITY_ORDER) return true;
+    const int64_t n = (int64_t)clen.size();
+    if (n < 4096 || nnz == 0) return false;
+    const int64_t longest = *std::max_element(clen.begin(), clen.end());
+    return (double)longest >= 32.0 * (double)nnz / (double)n;
+}
+
 template <class T>
 class GenericProgram : public Program {
   public:
@@ -60,21 +73,55 @@ class GenericProgram : public Program {
         const int64_t nnz = (s.onesP ? 0 : P->nnz()) + (s.onesC ? 0 : C->nnz());
         if (nnz >= INT32_MAX || mR_ >= INT32_MAX || n_ >= INT32_MAX)
             throw ApiError{MWU_ERR_TOO_LARGE, "structure exceeds 32-bit device indices"};
-        // concatenated row structure
+        // concatenated row r < mPc is row r of P, else row r - mPc of C
+        auto side = [&](int64_t r) -> const HostCSR & { return r < mPc ? *P : *C; };
+        auto local = [&](int64_t r) { return r < mPc ? r : r - mPc; };
+        // ---- internal order: columns by length, rows of each side by length
+        // (descending, stable) when the column lengths are heavy-tailed
+        std::vector<int64_t> clen(n_, 0);
+        if (!s.onesP) for (auto c : P->idx) clen[c]++;
+        if (!s.onesC) for (auto c : C->idx) clen[c]++;
+        reorder_ = locality_order(s.opt.flags, clen, nnz);
+        cperm_.resize(n_);
+        rperm_.resize(mR_);
+        for (int64_t i = 0; i < n_; ++i) cperm_[i] = (int32_t)i;
+        for (int64_t r = 0; r < mR_; ++r) rperm_[r] = (int32_t)r;
+        if (reorder_) {
+            std::stable_sort(cperm_.begin(), cperm_.end(), [&](int32_t a, int32_t b) { return clen[a] > clen[b]; });
+            auto rlen = [&](int32_t r) { const HostCSR &A = side(r); return A.ptr[local(r) + 1] - A.ptr[local(r)]; };
+            auto longer = [&](int32_t a, int32_t b) { return rlen(a) > rlen(b); };
+            std::stable_sort(rperm_.begin(), rperm_.begin() + mPc, longer);
+            std::stable_sort(rperm_.begin() + mPc, rperm_.end(), longer);
+        }
+        std::vector<int32_t> cinv(n_), rinv(mR_);
+        for (int64_t i = 0; i < n_; ++i) cinv[cperm_[i]] = (int32_t)i;
+        for (int64_t r = 0; r < mR_; ++r) rinv[rperm_[r]] = (int32_t)r;
+        const int64_t obj_int = obj_row >= 0 ? rinv[obj_row] : -1;
+        // concatenated row structure in the internal order, its exact FP64
+        // coefficients (certificate statistics) and max_j P_ji per column
+        // (Algorithm 1 initial point; an objective row in P enters at each
+        // probe, since its level changes)
         std::vector<int32_t> rptr(mR_ + 1), rcol(nnz);
         std::vector<T> rval(vals ? nnz : 0);
-        int64_t k = 0, r = 0;
-        auto add_side = [&](const HostCSR &A) {
-            for (int64_t i = 0; i < A.rows; ++i, ++r) {
-                rptr[r] = (int32_t)k;
-                for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q, ++k) {
-                    rcol[k] = A.idx[q];
-                    if (vals) rval[k] = (T)A.v(q);
-                }
+        std::vector<double> r64(vals ? nnz : 0);
+        std::vector<double> colmax(s.onesP ? 0 : n_, 0.0);
+        std::vector<std::pair<int32_t, double>> row;
+        int64_t k = 0;
+        for (int64_t r = 0; r < mR_; ++r) {
+            rptr[r] = (int32_t)k;
+            const int64_t kr = rperm_[r];
+            const HostCSR &A = side(kr);
+            const int64_t li = local(kr);
+            row.clear();
+            for (int64_t q = A.ptr[li]; q < A.ptr[li + 1]; ++q) row.emplace_back(cinv[A.idx[q]], A.v(q));
+            if (reorder_) std::sort(row.begin(), row.end());
+            for (const auto &e : row) {
+                rcol[k] = e.first;
+                if (vals) { rval[k] = (T)e.second; r64[k] = e.second; }
+                if (r < mPc && r != obj_int) colmax[e.first] = std::max(colmax[e.first], e.second);
+                ++k;
             }
-        };
-        if (!s.onesP) add_side(*P);
-        if (!s.onesC) add_side(*C);
+        }
         rptr[mR_] = (int32_t)k;
         // column structure (transpose); rows visited in order keep each column sorted
         std::vector<int32_t> cptr(n_ + 1, 0), crow(nnz);
@@ -89,22 +136,14 @@ class GenericProgram : public Program {
                     const int32_t pos = fill[rcol[q]]++;
                     crow[pos] = (int32_t)rr;
                     if (vals) cval[pos] = rval[q];
-                    if (rr == obj_row) opos.push_back(pos);
+                    if (rr == obj_int) opos.push_back(pos);
                 }
         }
         if (obj_row >= 0) {
-            obj_k0_ = rptr[obj_row];
-            obj_n_ = rptr[obj_row + 1] - rptr[obj_row];
-            obj_in_P_ = obj_row < mPc;
-        }
-        // max_j P_ji per column (Algorithm 1 initial point); an objective row
-        // in P enters at each probe (its level changes)
-        std::vector<double> colmax;
-        if (!s.onesP) {
-            colmax.assign(n_, 0.0);
-            const int64_t lastq = (obj_row >= 0 && obj_row < mPc) ? rptr[obj_row] : P->nnz();
-            for (int64_t q = 0; q < lastq; ++q)
-                colmax[P->idx[q]] = std::max(colmax[P->idx[q]], P->v(q));
+            // the row covers every column, its entries in internal column order
+            obj_k0_ = rptr[obj_int];
+            obj_n_ = rptr[obj_int + 1] - rptr[obj_int];
+            obj_in_P_ = obj_int < mPc;
         }
         nnz_ = nnz;
         vals_ = vals;
@@ -136,13 +175,8 @@ class GenericProgram : public Program {
         up(clcount_, ct.lcount.data(), ct.lcount.size() * 4);
         rlpart_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(T));
         rlpart64_.alloc(std::max<int32_t>(rt.nslots, 1) * sizeof(double));
-        if (vals) {   // exact coefficients for the FP64 certificate statistics
-            std::vector<double> r64(nnz);
-            int64_t q = 0;
-            for (const HostCSR *A : {s.onesP ? nullptr : P, s.onesC ? nullptr : C})
-                if (A) for (int64_t kk = 0; kk < A->nnz(); ++kk) r64[q++] = A->v(kk);
-            up(rval64_, r64.data(), r64.size() * 8);
-        }
+        if (vals) up(rval64_, r64.data(), r64.size() * 8);   // exact coefficients, FP64 statistics
+        if (reorder_) up(cmap_, cperm_.data(), cperm_.size() * 4);
         clpart_.alloc(std::max<int32_t>(ct.nslots, 1) * 2 * sizeof(T));
         x_.alloc(n_ * sizeof(T));
         d_.alloc(n_ * sizeof(T));
@@ -170,6 +204,7 @@ class GenericProgram : public Program {
         gd_.wu = wu_.as<T>();
         gd_.g_dbg = nullptr; gd_.h_dbg = nullptr; gd_.forced = nullptr;
         gd_.grad = nullptr; gd_.grad_scale = 0.0;
+        gd_.cmap = reorder_ ? cmap_.as<int32_t>() : nullptr;
         rslots_ = rt.nslots;
         cslots_ = ct.nslots;
 
@@ -201,6 +236,12 @@ class GenericProgram : public Program {
 
     void upload_x(const double *host_x) override
     {
+        std::vector<double> hx;
+        if (reorder_) {
+            hx.resize(n_);
+            for (int64_t i = 0; i < n_; ++i) hx[i] = host_x[cperm_[i]];
+            host_x = hx.data();
+        }
         DevBuf tmp;
         tmp.alloc(n_ * 8);
         HIP_OK(hipMemcpyAsync(tmp.p, host_x, n_ * 8, hipMemcpyHostToDevice, s_.stream));
@@ -232,33 +273,38 @@ class GenericProgram : public Program {
         HIP_OK(hipMemcpyAsync(xbest_.p, x_.p, n_ * sizeof(T), hipMemcpyDeviceToDevice, s_.stream));
     }
 
-    void best_to_host(double *out) override { to_host(xbest_.as<T>(), n_, out); }
+    void best_to_host(double *out) override { to_host(xbest_.as<T>(), n_, out, cols_out()); }
 
+    // Every vector leaves in the caller's order: column i of the internal
+    // order is the caller's cperm_[i], row r is the caller's rperm_[r].
     void read(int which, double *out, int64_t len) override
     {
         const int64_t mCc = mR_ - mPc_;
         switch (which) {
-        case 0: need(len, n_); to_host(gd_.x, n_, out); return;
-        case 1: need(len, n_); to_host(gd_.d, n_, out); return;
+        case 0: need(len, n_); to_host(gd_.x, n_, out, cols_out()); return;
+        case 1: need(len, n_); to_host(gd_.d, n_, out, cols_out()); return;
         case 2:
-        case 3:
+        case 3: {
             need(len, n_);
             if (!dbg_g_.p) throw ApiError{MWU_ERR_STATE, "g/h are recorded by mwu_probe_direction"};
-            HIP_OK(hipMemcpyAsync(out, which == 2 ? dbg_g_.p : dbg_h_.p, n_ * 8, hipMemcpyDeviceToHost,
+            std::vector<double> tmp(n_);
+            HIP_OK(hipMemcpyAsync(tmp.data(), which == 2 ? dbg_g_.p : dbg_h_.p, n_ * 8, hipMemcpyDeviceToHost,
                                   s_.stream));
             HIP_OK(hipStreamSynchronize(s_.stream));
+            for (int64_t i = 0; i < n_; ++i) out[reorder_ ? cperm_[i] : i] = tmp[i];
             return;
+        }
         case 4:
         case 6:
             if (s_.onesP) { need(len, 1); out[0] = scalar(which == 4 ? 0 : 2); return; }
             need(len, mPc_);
-            to_host((which == 4 ? gd_.yz : gd_.dyz), mPc_, out);
+            to_host((which == 4 ? gd_.yz : gd_.dyz), mPc_, out, rows_out(0));
             return;
         case 5:
         case 7:
             if (s_.onesC) { need(len, 1); out[0] = scalar(which == 5 ? 1 : 3); return; }
             need(len, mCc);
-            to_host((which == 5 ? gd_.yz : gd_.dyz) + mPc_, mCc, out);
+            to_host((which == 5 ? gd_.yz : gd_.dyz) + mPc_, mCc, out, rows_out(mPc_));
             return;
         }
         throw ApiError{MWU_ERR_INVALID_ARG, "unknown vector"};
@@ -300,7 +346,7 @@ class GenericProgram : public Program {
         generic_col<T>(g, ctl(), L_, st);
         if (grad_dev || val_dev)
             potential_finish(dbg_g_.as<double>(), dbg_h_.as<double>(), grad_dev ? (int)n_ : 0, scale,
-                             grad_dev, ctl(), val_dev, st);
+                             grad_dev, gd_.cmap, ctl(), val_dev, st);
     }
 
     bool potential_static(const double *x_dev, double grad_scale, double *grad_dev, void *scr, size_t bytes,
@@ -359,14 +405,22 @@ class GenericProgram : public Program {
         HIP_OK(hipStreamSynchronize(s_.stream));
         return which == 0 ? c.y1 : which == 1 ? c.z1 : which == 2 ? c.dy1 : c.dz1;
     }
-    void to_host(const T *src, int64_t len, double *out)
+    // map (nullable): internal index i goes to out[map[i] - base]
+    struct OutMap { const int32_t *map; int64_t base; };
+    OutMap cols_out() const { return {reorder_ ? cperm_.data() : nullptr, 0}; }
+    OutMap rows_out(int64_t base) const { return {reorder_ ? rperm_.data() + base : nullptr, base}; }
+    void to_host(const T *src, int64_t len, double *out, OutMap m = {nullptr, 0})
     {
         if (len == 0) return;
         DevBuf tmp;
         tmp.alloc(len * 8);
         widen<T>(src, tmp.as<double>(), len, s_.stream);
-        HIP_OK(hipMemcpyAsync(out, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
+        std::vector<double> h;
+        double *dst = out;
+        if (m.map) { h.resize(len); dst = h.data(); }
+        HIP_OK(hipMemcpyAsync(dst, tmp.p, len * 8, hipMemcpyDeviceToHost, s_.stream));
         HIP_OK(hipStreamSynchronize(s_.stream));
+        if (m.map) for (int64_t i = 0; i < len; ++i) out[m.map[i] - m.base] = h[i];
     }
 
     Solver &s_;
@@ -380,6 +434,9 @@ class GenericProgram : public Program {
     DevBuf x_, d_, xbest_, yz_, dyz_, wu_, partials_, forced_, dbg_g_, dbg_h_;
     int32_t rslots_ = 0, cslots_ = 0;   // chunk partial slots of the long rows and columns
     DevBuf opos_, colmax_base_;         // embedded objective row: its column positions, colmax without it
+    bool reorder_ = false;              // internal order by length (locality_order)
+    std::vector<int32_t> cperm_, rperm_;   // internal column / row -> the caller's
+    DevBuf cmap_;                       // cperm_ on the device (potential x and gradient)
     int64_t obj_k0_ = 0, obj_n_ = 0;
     bool obj_in_P_ = false;
 };
