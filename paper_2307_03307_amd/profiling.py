@@ -29,11 +29,12 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# sources whose text defines each kernel family (shared helpers + the program)
-KERNEL_SOURCES = {"vc_": ["device_common.h", "vcover.hip"],
-                  "k_": ["device_common.h", "generic.hip"],
-                  "kb_": ["device_common.h", "batch.hip"],
-                  "dn_": ["device_common.h", "densest.hip"]}
+# sources whose text defines each kernel family and its data layout (shared
+# helpers, the kernels, and the host program that lays out the device arrays)
+KERNEL_SOURCES = {"vc_": ["device_common.h", "vcover.hip", "program_vcover.cpp"],
+                  "k_": ["device_common.h", "generic.hip", "program_generic.cpp"],
+                  "kb_": ["device_common.h", "batch.hip", "program_batch.cpp"],
+                  "dn_": ["device_common.h", "densest.hip", "program_densest.cpp"]}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
