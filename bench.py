@@ -485,9 +485,10 @@ def run_domset(args, steps, warmup):
 
 def run_batched(args, steps, warmup):
     """Batched bipartite matching: 512 uneven instances (sides uniform in
-    [1024, 65536], mean degree uniform in [4, 16]) solved together, against
-    the plain FP64 form of the same batch and a host loop of single-instance
-    FP64 solves (timed on a sample of instances, scaled by edge count)."""
+    [1024, 65536], mean degree uniform in [4, 16]) solved together with the
+    built-in layout, against the plain FP64 form of the same batch, a host
+    loop of single-instance FP64 solves (timed on a sample of instances,
+    scaled by edge count) and the layout a timed sweep picks."""
     import numpy as np
     import scipy.sparse as sp
     from scipy.sparse.csgraph import maximum_bipartite_matching
@@ -502,7 +503,7 @@ def run_batched(args, steps, warmup):
     log(f"batch: {len(gs)} instances, {V} vertices, {E} edges ({time.perf_counter() - t:.1f}s)")
     spec = [(g.num_vertices, g.u, g.v) for g in gs]
 
-    def run(precision, steps, warmup, tune=True):
+    def run(precision, steps, warmup, tune=False):
         t = time.perf_counter()
         b = mwu.BatchSolver(spec, precision=precision, tune=tune, step_rule=step_rule_of(mwu, args))
         create = time.perf_counter() - t
@@ -525,7 +526,7 @@ def run_batched(args, steps, warmup):
 
     c32, w32, r32, lay32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
     c64, w64, r64, lay64 = run(mwu.FP64, 1, 0)
-    _, wdef, _, _ = run(mwu.MIXED_FP32_FP64, 1, 0, tune=False)
+    ctun, wtun, _, laytun = run(mwu.MIXED_FP32_FP64, 1, 0, tune=True)
     # exact optima of a sample (Hopcroft-Karp; the bipartite matching LP is integral)
     sample = list(range(0, len(gs), max(1, len(gs) // 8)))
     ok = 0
@@ -554,7 +555,9 @@ def run_batched(args, steps, warmup):
         "iterations": sum(r.total_iterations for r in r32), "create_s": c32,
         "layout": {k: lay32[k] for k in ("tile_edges", "tile_vertices", "workgroups_per_cu",
                                          "search_launches", "source", "candidates_timed")},
-        "default_layout_s": wdef[0],
+        "tuned_layout_s": wtun[0], "tuned_layout_create_s": ctun,
+        "tuned_layout": {k: laytun[k] for k in ("tile_edges", "tile_vertices", "workgroups_per_cu",
+                                                "search_launches", "source", "candidates_timed")},
         "fp64_batched_s": statistics.mean(w64), "fp64_batched_certified": sum(r.certified for r in r64),
         "fp64_loop_s": loop_s,
         "fp64_loop_sample": f"{loop_n} instances ({e_loop} edges) timed, scaled by total edges",

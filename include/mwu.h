@@ -162,7 +162,9 @@ typedef struct {
 
 #define MWU_FLAG_NO_FACTOR2   1u  /* do not double the step when one side is a single row */
 #define MWU_FLAG_GENERIC      2u  /* force the generic CSR engine (no fused graph program) */
-#define MWU_FLAG_NO_TUNE      4u  /* batched: take the default layout, time nothing */
+#define MWU_FLAG_NO_TUNE      4u  /* batched: take the default layout, time nothing (the default;
+                                     overrides MWU_FLAG_TUNE) */
+#define MWU_FLAG_TUNE         128u /* batched: choose the layout by a timed sweep (or a known record) */
 /* Outer search: every probe after the first starts from the previous probe's
  * iterate, scaled so that its largest packing row (in the new probe's scale)
  * is eps -- the level the Algorithm 1 point starts from -- and, with
@@ -238,14 +240,16 @@ mwu_status mwu_create_batch(const mwu_problem *probs, int32_t count, const mwu_o
  * Layout of a batched handle and its autotuner.  The batched passes visit
  * edge tiles (start, column and statistics passes), element tiles of vertex
  * rows (row and search passes) and nnz-balanced vertex tiles (forward
- * product, fixed at BLOCK x 8 nonzeros) with persistent grids.  At
- * mwu_create_batch the layout is chosen by timed sweeps over the batch itself
- * (one coordinate-descent pass over the four fields below; each candidate
- * runs the whole batched solve from its start for 0.4 s, host polling and
- * probe turnovers included, and is rated by the edge-iterations completed per
- * second), unless MWU_FLAG_NO_TUNE is set or a layout for the same device,
- * precision and batch shape is listed in opt->tune_cache or already known to
- * the process.  A sweep costs about 8 such windows at create.
+ * product, fixed at BLOCK x 8 nonzeros) with persistent grids.  By default
+ * mwu_create_batch takes the built-in layout and times nothing.  With
+ * MWU_FLAG_TUNE it takes a layout for the same device, precision and batch
+ * shape listed in opt->tune_cache or already known to the process, else one
+ * chosen by timed sweeps over the batch itself (one coordinate-descent pass
+ * over the four fields below; each candidate runs the whole batched solve
+ * from its start for 0.4 s, host polling and probe turnovers included, and is
+ * rated by the edge-iterations completed per second; about 8 such windows at
+ * create).  On the 512-instance workload the tuned and the built-in layouts
+ * solve within a few percent of each other, so the sweep is opt-in.
  * ------------------------------------------------------------------------- */
 
 #define MWU_LAYOUT_DEFAULT 0   /* built-in layout, nothing timed */

@@ -266,7 +266,7 @@ class BatchSolver:
 
     def __init__(self, graphs, eps: float = 0.1, max_iter: int = 5000, max_probes: int = 64,
                  step_rule: int = STEP_BIN, precision: int = MIXED_FP32_FP64, device: int = 0,
-                 flags: int = 0, iters_per_launch: int = 0, tune: bool = True,
+                 flags: int = 0, iters_per_launch: int = 0, tune: bool = False,
                  tune_cache: Optional[str] = None):
         L = _lib.load()
         self._L = L
@@ -281,7 +281,7 @@ class BatchSolver:
         L.mwu_default_options(ctypes.byref(opt))
         opt.eps, opt.max_iter, opt.max_probes = eps, max_iter, max_probes
         opt.step_rule, opt.precision, opt.device = step_rule, precision, device
-        opt.flags = flags | (0 if tune else _lib.FLAG_NO_TUNE)
+        opt.flags = flags | (_lib.FLAG_TUNE if tune else 0)
         opt.iters_per_launch = iters_per_launch
         self._cache = tune_cache.encode() if tune_cache else None   # kept alive for the call
         opt.tune_cache = self._cache

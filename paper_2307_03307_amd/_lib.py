@@ -22,7 +22,7 @@ MAT_CSR, MAT_INCIDENCE, MAT_INCIDENCE_T, MAT_EDGE_PAIR, MAT_INTERWEAVE = 0, 1, 2
 STEP_STD, STEP_BIN, STEP_BIN_WARM, STEP_NEWTON = 0, 1, 2, 3
 FP64, MIXED_FP32_FP64 = 0, 1
 FLAG_NO_FACTOR2, FLAG_GENERIC, FLAG_NO_TUNE, FLAG_REUSE, FLAG_DROP_SATISFIED = 1, 2, 4, 8, 16
-FLAG_KEEP_ORDER, FLAG_LOCALITY_ORDER = 32, 64
+FLAG_KEEP_ORDER, FLAG_LOCALITY_ORDER, FLAG_TUNE = 32, 64, 128
 LAYOUT_DEFAULT, LAYOUT_TUNED, LAYOUT_CACHED, LAYOUT_SET = 0, 1, 2, 3
 
 EXPORTED = [

@@ -489,12 +489,12 @@ class BatchMatching : public BatchProgram {
         return secs > 0.0 ? work / secs : 0.0;
     }
 
-    // Layout at create: the process's or the cache file's record for this
-    // device and batch shape, else a sweep (MWU_FLAG_NO_TUNE: the default).
+    // Layout at create: the built-in one, or with MWU_FLAG_TUNE the process's
+    // or the cache file's record for this device and batch shape, else a sweep.
     void choose_layout()
     {
         mwu_batch_layout L = default_layout();
-        if (s_.opt.flags & MWU_FLAG_NO_TUNE) {
+        if (!(s_.opt.flags & MWU_FLAG_TUNE) || (s_.opt.flags & MWU_FLAG_NO_TUNE)) {
             relayout(L);
             return;
         }

@@ -92,8 +92,8 @@ def test_batch_solve_twice_is_identical():
 
 def test_batch_full_c5():
     """The full C5 batch (512 instances, sides uniform in [1024, 65536], mean
-    degree uniform in [4, 16], 164M edges) in the chosen form with the layout
-    the autotuner picks, as bench.py runs it: every instance certified, and
+    degree uniform in [4, 16], 164M edges) in the chosen form with the
+    built-in layout, as bench.py runs it: every instance certified, and
     for every 16th instance the exact optimum in the bracket with a feasible
     x (per-vertex loads at most 1)."""
     import paper_2307_03307_amd as mwu
@@ -121,7 +121,7 @@ def test_autotuner_sweeps_then_reuses(tmp_path):
     gs = gg.batch_bipartite(64, scale_div=8)
     spec = [(g.num_vertices, g.u, g.v) for g in gs]
     cache = tmp_path / "layouts.txt"
-    with mwu.BatchSolver(spec, tune_cache=str(cache)) as b:
+    with mwu.BatchSolver(spec, tune=True, tune_cache=str(cache)) as b:
         lay = b.layout()
         print("tuned layout", lay)
         assert lay["source"] in (_lib.LAYOUT_TUNED, _lib.LAYOUT_CACHED)
@@ -134,7 +134,7 @@ def test_autotuner_sweeps_then_reuses(tmp_path):
         _check(g, r, _nu(g))
     lines = [ln for ln in cache.read_text().split("\n") if ln.strip()]
     assert len(lines) == 1   # a sweep's record, or the process's record for the same shape
-    with mwu.BatchSolver(spec, tune_cache=str(cache)) as b:
+    with mwu.BatchSolver(spec, tune=True, tune_cache=str(cache)) as b:
         again = b.layout()
     assert again["source"] == _lib.LAYOUT_CACHED
     assert all(again[f] == lay[f] for f in ("tile_edges", "tile_vertices", "workgroups_per_cu",
@@ -142,7 +142,7 @@ def test_autotuner_sweeps_then_reuses(tmp_path):
     key = lines[-1].split()[0]
     hand = tmp_path / "hand.txt"
     hand.write_text("garbage line\n" + f"{key} 1024 8192 4 1 1.0e9\n")
-    with mwu.BatchSolver(spec, tune_cache=str(hand)) as b:
+    with mwu.BatchSolver(spec, tune=True, tune_cache=str(hand)) as b:
         got = b.layout()
         res = b.solve()
     assert (got["tile_edges"], got["tile_vertices"], got["workgroups_per_cu"],
@@ -152,11 +152,18 @@ def test_autotuner_sweeps_then_reuses(tmp_path):
 
 
 def test_untuned_layout_is_the_default():
+    """Without MWU_FLAG_TUNE nothing is timed and the built-in layout is
+    taken, even where a cache file lists one; MWU_FLAG_NO_TUNE overrides the
+    request."""
     import paper_2307_03307_amd as mwu
     from paper_2307_03307_amd import _lib
     gs = _instances()[:4]
-    with mwu.BatchSolver([(g.num_vertices, g.u, g.v) for g in gs], tune=False) as b:
+    spec = [(g.num_vertices, g.u, g.v) for g in gs]
+    with mwu.BatchSolver(spec) as b:
         lay = b.layout()
+    with mwu.BatchSolver(spec, tune=True, flags=_lib.FLAG_NO_TUNE) as b:
+        lay2 = b.layout()
+    assert lay2["source"] == _lib.LAYOUT_DEFAULT and lay2["candidates_timed"] == 0
     assert lay["source"] == _lib.LAYOUT_DEFAULT and lay["candidates_timed"] == 0
     assert (lay["tile_edges"], lay["tile_vertices"], lay["workgroups_per_cu"],
             lay["search_launches"]) == (2048, 4096, 8, 2)
