@@ -325,12 +325,17 @@ def run_vcover(args, steps, warmup, scale=20, with_cpu=False):
         s = mwu.vertex_cover(g.num_vertices, g.u, g.v, precision=precision, step_rule=step_rule_of(mwu, args))
         create = time.perf_counter() - t
         walls, r = timed_solves(s, steps, warmup, f"vcover precision={precision}")
+        # one iteration in, before any active list exists (full lists), then
+        # 600 iterations in (the sparse phase, where most of a solve runs)
+        full = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=1, last=0)
         passes = pass_times(s, args.pass_reps, param=0.5 * (r.lower + r.upper), warm_iters=600, last=0)
         s.close()
+        passes["full_list"] = full
         return create, walls, r, passes
 
     c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
     c64, w64, r64, p64 = run(mwu.FP64, max(1, steps // 2), 1)
+    f32, f64 = p32.pop("full_list"), p64.pop("full_list")
     t32, t64 = statistics.mean(w32), statistics.mean(w64)
     out = {
         "workload": f"vertex cover LP, R-MAT scale {scale}, edge factor {args.edge_factor}, seed 2, eps=0.1",
@@ -341,6 +346,8 @@ def run_vcover(args, steps, warmup, scale=20, with_cpu=False):
         "fp64_iterations": r64.total_iterations, "speedup_vs_fp64": t64 / t32,
         "passes": {VC_PASS_NAMES[k]: v for k, v in p32.items()},
         "passes_fp64": {VC_PASS_NAMES[k]: v for k, v in p64.items()},
+        "passes_full_list": {VC_PASS_NAMES[k]: v for k, v in f32.items()},
+        "passes_full_list_fp64": {VC_PASS_NAMES[k]: v for k, v in f64.items()},
         "roofline": dominant(p32, r32, VC_KERNELS, VC_PASS_NAMES, "f32", f"rmat{scale}"),
     }
     if with_cpu:

@@ -115,7 +115,7 @@ def load_traffic(path: str, kernel: str):
 
 BENCH_KEYS = ("value", "unit", "fp64_plain_s", "speedup_vs_fp64", "iterations", "fp64_iterations",
               "certified", "roofline", "passes", "fp64_batched_s", "fp64_loop_s", "speedup_vs_fp64_loop",
-              "speedup_vs_fp64_batched", "exact_optimum_in_bracket", "layout", "tuned_layout_s")
+              "speedup_vs_fp64_batched", "exact_optimum_in_bracket", "layout", "tuned_layout_s", "passes_full_list")
 
 
 def trace_summary(trace_dir: str, title: str, command: str, out: str, bench_json: str, last: int,
