@@ -123,3 +123,26 @@ def _has_gpu():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def test_mixed_optimization_arguments_rejected():
+    """The mixed optimization forms (objective embedded as one more row)
+    check their inputs before any device work: a cost vector is required and
+    positive, the sides share their columns, there are covering rows, and
+    when maximizing every column has a packing entry (else the LP is
+    unbounded); a valid problem reaches the device."""
+    P = mwu.csr_matrix(np.array([0, 2, 3], np.int64), np.array([0, 1, 1], np.int32), [1.0, 2.0, 1.0],
+                       shape=(2, 2))
+    C = mwu.csr_matrix(np.array([0, 2], np.int64), np.array([0, 1], np.int32), [1.0, 1.0], shape=(1, 2))
+    C3 = mwu.csr_matrix(np.array([0, 1], np.int64), np.array([2], np.int32), [1.0], shape=(1, 3))
+    P_gap = mwu.csr_matrix(np.array([0, 1], np.int64), np.array([0], np.int32), [1.0], shape=(1, 2))
+    c = np.ones(2)
+    for form in (mwu.MIXED_MAX, mwu.MIXED_MIN):
+        assert _code(lambda: mwu.Solver(form, P=P, C=C)) == -1                     # no c
+        assert _code(lambda: mwu.Solver(form, P=P, C=C, c=[1.0, 0.0])) == -4      # c must be positive
+        assert _code(lambda: mwu.Solver(form, P=P, C=C3, c=c)) == -1              # column counts differ
+        assert _code(lambda: mwu.Solver(form, P=P, C=C, c=c, b_C=[-1.0])) == -4   # bad right-hand side
+    assert _code(lambda: mwu.Solver(mwu.MIXED_MAX, P=P_gap, C=C, c=c)) == -9      # column 1 unbounded
+    if not _has_gpu():
+        assert _code(lambda: mwu.Solver(mwu.MIXED_MAX, P=P, C=C, c=c)) == -8
+        assert _code(lambda: mwu.Solver(mwu.MIXED_MIN, P=P_gap, C=C, c=c)) == -8   # minimizing keeps it
