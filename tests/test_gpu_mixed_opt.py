@@ -189,3 +189,26 @@ def test_columns_without_covering_entries_leave_the_lp():
     print(f"{gone.sum()} packing-only columns: bracket [{r.lower:.9g}, {r.upper:.9g}], {r.probes} probes")
     assert r.certified and (r.lower, r.upper, r.probes) == (rk.lower, rk.upper, rk.probes)
     assert np.array_equal(r.x[keep], rk.x) and np.all(r.x[~keep] == 0.0)
+
+
+@pytest.mark.parametrize("rule,drop", [(mwu.STEP_BIN_WARM, False), (mwu.STEP_NEWTON, False),
+                                       (mwu.STEP_BIN, True), (mwu.STEP_BIN_WARM, True)])
+@pytest.mark.parametrize("maximize", [True, False])
+def test_mixed_optimization_step_rules_and_drop(maximize, rule, drop):
+    """The embedded objective row with the warm-started and the Newton step
+    searches and with met covering rows dropped (the objective row among
+    them when maximizing): in FP64 the probe count and the bracket equal the
+    oracle's run with the same rule and flag; the point is feasible."""
+    P, C, bP, bC, c = _lp(0)
+    form = mwu.MIXED_MAX if maximize else mwu.MIXED_MIN
+    flags = mwu._lib.FLAG_DROP_SATISFIED if drop else 0
+    with _gpu(P, C, bP, bC, c, form, precision=mwu.FP64, max_iter=MAX_ITER, step_rule=rule, flags=flags) as s:
+        r = s.solve()
+    Pn, Cn = _normalized(P, C, bP, bC)
+    ro, _ = oracle.solve_mixed_opt(_ocsr(Pn), _ocsr(Cn), c, maximize, max_iter=MAX_ITER, step_rule=rule, drop=drop)
+    print(f"{'max' if maximize else 'min'} rule {rule} drop {drop}: bracket [{r.lower:.6g}, {r.upper:.6g}] "
+          f"(oracle [{ro.lower:.6g}, {ro.upper:.6g}]), {r.probes} probes, {r.total_iterations} iterations "
+          f"(oracle {ro.total_iterations})")
+    assert r.certified and ro.certified and r.probes == ro.probes
+    assert r.lower == pytest.approx(ro.lower, rel=1e-9) and r.upper == pytest.approx(ro.upper, rel=1e-9)
+    assert (C @ r.x / bC).min() >= 1 - 1e-9 and (P @ r.x / bP).max() <= 1 + r.max_violation + 1e-9
