@@ -331,8 +331,17 @@ __device__ void dn_search_rows(const DnDev<T> &dd, const Ctl *ctl, double *s_wav
         double s1[KC];
 #pragma unroll
         for (int k = 0; k < KC; ++k) s1[k] = 0.0;
-        for (int r = r0; r < dd.nv; r += stride)
-            pack_terms<T, KIND>(nc, cand, a0, ga0, gdel, eta, dd.w[r], (T)dd.dy[r], dymax, shm, s1, deriv);
+        // In FP32 storage the max-shifted packing terms are formed from y in
+        // FP64 (lw = eta (y - L) for the L the stored w was formed with: the
+        // row pass has since moved L by log(sum w) / eta).
+        constexpr bool SH64 = sizeof(T) == 4;
+        const double LP = ctl->LP, lsw = -log(ctl->invSw);
+        for (int r = r0; r < dd.nv; r += stride) {
+            const double dy64 = dd.dy[r];
+            const double lw = SH64 && shm ? eta * (dd.y[r] - LP) + lsw : 0.0;
+            pack_terms<T, KIND, SH64>(nc, cand, a0, ga0, gdel, eta, dd.w[r], (T)dy64, dymax, shm, s1, deriv, lw,
+                                      dy64);
+        }
         const Red redp{KC, 0, 0};
         block_combine<KC>(s1, redp, 0, s_wave, s_rec);
     }

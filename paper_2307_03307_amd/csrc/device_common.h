@@ -503,12 +503,21 @@ MWU_DEV uint32_t shifted_mask(const Ctl *c)
 // / eta.  The shifted terms follow the same recurrences (squaring on the
 // exponential grid, float re-seeded every 4 steps; products on the bisection
 // grid).
-template <class T, int KIND>
+//
+// With SH64 the shifted terms are formed in double from the row's FP64 state
+// instead: lw = eta (y - L) for the L the stored weight w = e^{lw} was formed
+// with, and dy64 the FP64 direction.  A float w underflows once lw < -103,
+// and the rows that set dymax can be such rows; a shifted sum of float terms
+// is then 0 at large steps even though its exact value is far inside the
+// double range.  The unshifted terms still use w and dy.
+template <class T, int KIND, bool SH64 = false>
 MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, double gdel, double eta, T w, T dy,
-                        double dymax, uint32_t shmask, double *s1, bool deriv = false)
+                        double dymax, uint32_t shmask, double *s1, bool deriv = false, double lw = 0.0,
+                        double dy64 = 0.0)
 {
     const double dyd = (double)dy;
-    const double dsh = dyd - dymax;   // <= 0
+    const double dsh = (SH64 ? dy64 : dyd) - dymax;   // <= 0
+    const double w64 = SH64 && shmask ? exp(lw) : 0.0;
     auto doubling = [&](double b0, double c0, double *o) {
         T m = expm1_t((T)b0);
         if (!shmask) {
@@ -516,6 +525,16 @@ MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, doubl
             for (int k = 0; k < KE; ++k) {
                 o[k] += (double)(w * m);
                 m = m * (m + T(2));                  // expm1(2x) = expm1(x)(expm1(x)+2)
+            }
+            return;
+        }
+        if constexpr (SH64) {
+            double t = exp(c0);
+#pragma unroll
+            for (int k = 0; k < KE; ++k) {
+                o[k] += ((shmask >> k) & 1u) ? w64 * t : (double)(w * m);
+                m = m * (m + T(2));
+                t = t * t;
             }
             return;
         }
@@ -539,6 +558,17 @@ MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, doubl
             }
             return;
         }
+        if constexpr (SH64) {
+            double t = exp(c0);
+            const double tr = exp(cd);
+#pragma unroll
+            for (int k = 0; k < KG; ++k) {
+                o[k] += ((shmask >> (k0 + k)) & 1u) ? w64 * t : (double)(w * m);
+                m = m + mr + m * mr;
+                t = t * tr;
+            }
+            return;
+        }
         T t = exp_arg(c0, T(0));
         const T tr = exp_arg(cd, T(0));
 #pragma unroll
@@ -552,6 +582,10 @@ MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, doubl
 #pragma unroll
         for (int k = 0; k < KL; ++k)
             if (k < nc) {
+                if (SH64 && ((shmask >> k) & 1u)) {
+                    s1[k] += w64 * exp(eta * cand[k] * dsh);
+                    continue;
+                }
                 const T v = ((shmask >> k) & 1u) ? exp_arg(eta * cand[k] * dsh, T(0))
                                                  : expm1_t((T)(eta * cand[k] * dyd));
                 s1[k] += (double)(w * v);
@@ -559,8 +593,12 @@ MWU_DEV void pack_terms(int nc, const double *cand, double a0, double ga0, doubl
         // Newton pass: the sum of Psi' at cand[0], w dy e^{eta a_0 dy}, max-shifted as
         // cand[0]'s own sum is (slot KN, past its values)
         if (deriv) {
-            const T v0 = (shmask & 1u) ? exp_arg(eta * cand[0] * dsh, T(0)) : exp_arg(eta * cand[0] * dyd, T(0));
-            s1[KN] += (double)(w * dy * v0);
+            if (SH64 && (shmask & 1u)) {
+                s1[KN] += w64 * dy64 * exp(eta * cand[0] * dsh);
+            } else {
+                const T v0 = (shmask & 1u) ? exp_arg(eta * cand[0] * dsh, T(0)) : exp_arg(eta * cand[0] * dyd, T(0));
+                s1[KN] += (double)(w * dy * v0);
+            }
         }
     } else {
         if constexpr (KIND == SK_EXP || KIND == SK_COMBO) doubling(eta * a0 * dyd, eta * a0 * dsh, s1);
