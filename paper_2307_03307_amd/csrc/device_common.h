@@ -696,7 +696,7 @@ MWU_DEV void fold_cov_compact(const double *part, int G, double *s_wave, double 
 // values; when the sequential algorithm needs a value that the pass did not
 // produce, the next pass is set up and the replay resumes from its state.
 
-struct Eval { double psi, phi, zmin; int ok; };
+struct Eval { double psi, phi, zmin; int ok, pok; };   // pok: the packing side is resolved
 
 // eta (z - L) beyond which a covering row is left out of the sparse passes.
 // Double: exp(-746) is exactly zero (below half the smallest subnormal), so
@@ -803,6 +803,7 @@ MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
 {
     Eval e;
     e.ok = 1;
+    e.pok = 1;
     if (c->onesP) {
         e.psi = alpha * c->dy1;
     } else {
@@ -814,6 +815,7 @@ MWU_DEV Eval eval_cand(const Ctl *c, int k, double alpha)
             else { e.ok = 0; e.psi = 0; }
         } else if (!isfinite(s1)) { e.ok = 0; e.psi = 0; }
         else e.psi = log1p(s1) / c->eta;
+        e.pok = e.ok;
     }
     if (c->onesC) {
         e.phi = alpha * c->dz1;
@@ -946,11 +948,30 @@ MWU_DEV void setup_ladder(Ctl *c, double a, int kind, int nmax)
     c->gdelta = 0.0;
 }
 
+// The two-pass refinement of step a: pass 1 forms the shifts (max eta y',
+// min z'), pass 2 the shifted sums.  When a is a candidate of the pass just
+// made, that pass resolved its packing side and formed its min z' (the
+// exponential-grid and list passes do, over the full list), only the
+// covering sum fell out of range: pass 2 then starts at once, shifted by
+// eta (L_P + Psi(a)) (the exact log of the packing sum at a, so that sum is
+// about 1) and by that minimum.
 MWU_DEV void setup_refine(Ctl *c, double a)
 {
     c->skind = SK_REFINE;
     c->ref_alpha = a;
     c->ref_valid = 0;
+    c->ref_short = 0;
+    if (c->pass_sparse || c->onesC) return;
+    int k = -1;
+    for (int j = 0; j < c->ncand && j < KC; ++j)
+        if (c->cand[j] == a) { k = j; break; }
+    if (k < 0 || !isfinite(c->rZmin[k])) return;
+    const Eval e = eval_cand(c, k, a);
+    if (!e.pok) return;
+    c->rfZmin = c->rZmin[k];
+    c->rfPm = c->onesP ? 0.0 : c->eta * (c->LP + e.psi);
+    c->ref_valid = -1;
+    c->ref_short = 1;
 }
 
 MWU_DEV void accept_step(Ctl *c, double a, double psi, double phi)
@@ -1273,6 +1294,13 @@ MWU_DEV void finish_search(Ctl *c, const double *rec, bool pre_evaluated = false
             c->rfZmin = rec[0];
             c->rfPm = rec[1];
             c->ref_valid = -1;          // pass 2 pending
+            return;
+        }
+        // shifts taken from the grid pass that leave a sum out of range:
+        // form them exactly, in the two-pass way
+        if (c->ref_short && !((c->onesP || (rec[0] > 0.0 && isfinite(rec[0]))) && rec[1] > 0.0 && isfinite(rec[1]))) {
+            c->ref_short = 0;
+            c->ref_valid = 0;
             return;
         }
         const double a = c->ref_alpha;

@@ -112,6 +112,7 @@ struct Ctl {
     double exp_next, cur_alpha, cur_psi, cur_phi;
     double lb, ub, lb_psi, lb_phi;
     int32_t ref_valid, nw_evals;       // nw_evals: Newton evaluations of this search
+    int32_t ref_short, ref_pad;        // ref_short: the pending refinement took its shifts from the grid pass
     double ref_alpha, ref_psi, ref_phi, ref_zmin;
     double ref_dpsi, ref_dphi;          // Psi', Phi' at ref_alpha (refine pass 2)
     double ev_dpsi, ev_dphi;            // evaluation mode: Psi', Phi' at cand[0] of a Newton pass
