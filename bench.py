@@ -236,11 +236,9 @@ def run_densest(args, steps, warmup, with_cpu=True):
         passes["x_to_host_s"] = x_host
         return create, walls, r, passes
 
-    c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
-    c64, w64, r64, p64 = run(mwu.FP64, args.fp64_steps, 1 if args.fp64_steps > 1 else 0)
-    t32, t64 = statistics.mean(w32), statistics.mean(w64)
-    x_host32, x_host64 = p32.pop("x_to_host_s"), p64.pop("x_to_host_s")
-    # the fastest measured setting beside the default one: the warm-started
+    # the fastest measured setting beside the default one (solved first, so
+    # that each form's held pass repetitions are the last launches of its
+    # kernels in a profiled run): the warm-started
     # search (R19), probe-to-probe reuse (R21) and dropping met covering rows
     # (R22), in both forms (with it FP64 needs far fewer refinement passes)
     fast_flags = mwu._lib.FLAG_REUSE | mwu._lib.FLAG_DROP_SATISFIED
@@ -252,6 +250,10 @@ def run_densest(args, steps, warmup, with_cpu=True):
         fastest[key] = {"s": statistics.mean(wf), "certified": rf.certified, "bracket": [rf.lower, rf.upper],
                         "iterations": rf.total_iterations, "probes": rf.probes,
                         "search_passes": rf.search_passes, "evaluations": rf.evaluations}
+    c32, w32, r32, p32 = run(mwu.MIXED_FP32_FP64, steps, warmup)
+    c64, w64, r64, p64 = run(mwu.FP64, args.fp64_steps, 1 if args.fp64_steps > 1 else 0)
+    t32, t64 = statistics.mean(w32), statistics.mean(w64)
+    x_host32, x_host64 = p32.pop("x_to_host_s"), p64.pop("x_to_host_s")
     workload = f"rmat{args.scale}"
     out = {
         "metric": METRIC, "value": t32, "unit": "s", "n_gpus": 1, "steps": steps, "warmup": warmup,
